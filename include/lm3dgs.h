@@ -1,0 +1,184 @@
+/*
+ * lm3dgs.h - C ABI of the MI355X (gfx950) hot path of the Levenberg-Marquardt
+ * optimiser for 3D Gaussian Splatting ("3DGS-LM", arXiv 2409.12892).
+ *
+ * The library solves the damped normal equations of one LM iteration,
+ *     (J^T J + lambda diag(J^T J)) delta = -J^T F          (paper eq. norm-eq)
+ * with matrix-free Jacobi-preconditioned conjugate gradients (Algorithm 1),
+ * where J is the Jacobian of the rendered pixel colours with respect to all
+ * Gaussian parameters and F the per-pixel, per-channel residuals
+ * F = rendered - target (least-squares colour residuals; supplement A.5 notes
+ * dr/dc = 1 for L2).  J p and J^T u are evaluated from a per-pixel,
+ * per-splat gradient cache filled once per LM iteration (section 3.3,
+ * "Cache-driven parallelization").
+ *
+ * Conventions
+ *   - Every call returns an lm_status: 0 = LM_OK, < 0 error, > 0 warning.
+ *     lm_last_error() returns a thread-local message for the last failure.
+ *     No C++ exception crosses this boundary.
+ *   - "dev" pointers are device (HBM) pointers owned by the caller; "host"
+ *     pointers are ordinary host memory.  The library never frees caller
+ *     memory.  Cache memory is allocated by the library (hipMalloc) and
+ *     released by lm_cache_destroy().
+ *   - `stream` is a hipStream_t passed as void*; NULL means the default
+ *     stream.  Work is enqueued on it and returns asynchronously unless a
+ *     call says it synchronises.
+ *   - Parameter vectors (x, p, g, b, M, delta) use the per-attribute
+ *     structure-of-arrays layout x[P][N] (paper supplement A.4, vector "q"),
+ *     float32, with P = 11 + 3 (deg+1)^2 parameters per Gaussian in the order
+ *     mean(3), log-scale(3), quaternion w,x,y,z (4), opacity logit (1),
+ *     SH coefficients (index 11 + 3k + channel).
+ *   - Images and residual vectors are float32 [V][3][H][W] (view-major,
+ *     channel, row, column), all views of one subset back to back.
+ */
+#ifndef LM3DGS_H
+#define LM3DGS_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t lm_status;
+
+enum {
+    LM_OK = 0,
+    LM_ERR_INVALID_ARG = -1,   /* a pointer, size or option is out of range   */
+    LM_ERR_HIP = -2,           /* a HIP runtime call failed (message has it)  */
+    LM_ERR_CAPACITY = -3,      /* a size exceeds an index range of the layout */
+    LM_ERR_NOT_BUILT = -4,     /* the cache handle is empty                   */
+    LM_ERR_UNSUPPORTED = -5,   /* option combination not implemented          */
+    LM_WARN_BREAKDOWN = 1      /* PCG stopped early on p^T A p <= 0 / NaN     */
+};
+
+enum { LM_CACHE_F32 = 0, LM_CACHE_BF16 = 1, LM_CACHE_F16 = 2 };
+
+/* PCG stopping rule.  PAPER_SQUARED is Algorithm 1 as printed:
+ * stop when ||r||^2 < tol ||b||^2 (tol = 0.01 in the paper).  RELATIVE stops
+ * when ||r|| < tol ||b||.  NONE runs exactly n_iters iterations. */
+enum { LM_TOL_NONE = 0, LM_TOL_PAPER_SQUARED = 1, LM_TOL_RELATIVE = 2 };
+
+/* Pinhole camera, world -> camera: X_cam = R X + t (R row-major).  Camera
+ * axes x right, y down, z forward; pixel u = fx X/Z + cx, v = fy Y/Z + cy,
+ * pixel (i, j) has its centre at (i + 0.5, j + 0.5). */
+typedef struct lm_camera {
+    float R[9];
+    float t[3];
+    float fx, fy, cx, cy;
+    int32_t W, H;
+} lm_camera;
+
+/* The Gaussians: x is a device pointer to float32 [P][N] (see above). */
+typedef struct lm_scene {
+    int64_t N;
+    int32_t sh_degree;    /* 0..3 */
+    int32_t reserved;
+    const float* x;       /* dev */
+} lm_scene;
+
+typedef struct lm_options {
+    int32_t tile_w, tile_h;  /* tile shape in pixels; tile_w*tile_h <= 256 (0,0 = 16x16) */
+    int32_t cache_dtype;     /* LM_CACHE_F32 / _BF16 / _F16 storage of the cache      */
+    int32_t flags;           /* reserved, 0                                            */
+} lm_options;
+
+typedef struct lm_cache lm_cache;   /* opaque, library-owned */
+
+typedef struct lm_cache_info {
+    int64_t N, n_keys, n_pairs, n_segments, n_gv, n_pixels, n_tiles;
+    int64_t cache_bytes;     /* pair + segment arrays read by the products   */
+    int64_t device_bytes;    /* all device memory held by the cache          */
+    int32_t V, P, tile_w, tile_h, cache_dtype, sh_degree;
+} lm_cache_info;
+
+#define LM_PCG_MAX_HISTORY 257
+typedef struct lm_pcg_stats {
+    int32_t iters;           /* completed loop iterations                        */
+    int32_t status;          /* LM_OK or LM_WARN_BREAKDOWN                       */
+    double b_sqnorm;         /* ||b||^2                                          */
+    double history[LM_PCG_MAX_HISTORY];  /* ||r_i||^2 / ||b||^2, i = 0..iters      */
+} lm_pcg_stats;
+
+/* Message for the last error on this thread ("" if none). */
+const char* lm_last_error(void);
+
+/* Build the per-pixel, per-splat gradient cache of one image subset
+ * (Algorithm 1, buildCache; section 3.3 "Mapping of PCG to CUDA kernels").
+ * Projects every Gaussian into the V views, bins and depth-sorts the splats
+ * per tile, alpha-blends every pixel (eq. alpha-blending), writes the cache
+ * and forms b = -J^T F.
+ *   scene, cams (host, V entries), target (dev float32 [V][3][H][W]).
+ *   *inout: NULL to create a new cache, or an existing cache whose device
+ *           memory is reused (grown when needed).
+ *   b (dev float32 [P][N], may be NULL), F_sqnorm (dev double, may be NULL).
+ * Synchronises the stream twice (to size the key and pair arrays). */
+lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V,
+                         const float* target, const lm_options* opts, void* stream,
+                         lm_cache** inout, float* b, double* F_sqnorm);
+
+lm_status lm_cache_destroy(lm_cache* cache);
+lm_status lm_cache_get_info(const lm_cache* cache, lm_cache_info* info);
+
+/* M = diag(J^T J) (paper eq. diag-jtj, kernel diagJTJ), dev float32 [P][N]. */
+lm_status lm_jacobi_diag(const lm_cache* cache, float* M, void* stream);
+
+/* g = J^T J p + lambda M p (Algorithm 1, the applyJ / applyJT pair plus the
+ * damping term).  M may be NULL (then lambda is ignored).  If Jp_sqnorm is
+ * not NULL, ||J p||^2 (double, dev) is written too.  p, g dev [P][N]. */
+lm_status lm_apply_JtJ(const lm_cache* cache, const float* p, float lambda, const float* M,
+                       float* g, double* Jp_sqnorm, void* stream);
+
+/* u = J p (eq. apply-j), u dev float32 [V][3][H][W]. */
+lm_status lm_apply_J(const lm_cache* cache, const float* p, float* u, void* stream);
+
+/* g = J^T u (eq. apply-jt), u dev float32 [V][3][H][W], g dev [P][N]. */
+lm_status lm_apply_JT(const lm_cache* cache, const float* u, float* g, void* stream);
+
+/* Algorithm 1 for n_b image subsets (section 3.3 "Image Subsampling
+ * Scheme": each subset solves its own normal equations).  All arrays are
+ * host arrays of n_b device pointers; precond_scale may be NULL (plain
+ * Jacobi) or hold per-subset NULL / dev float32 [P][N] factors multiplying
+ * M^-1.  Dots, alpha and beta are float64 and stay on the device; the
+ * stopping test runs on the device.  stats (host, n_b entries) is filled
+ * after one synchronisation at the end. */
+lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b,
+                       const float* const* M, float lambda, int32_t n_iters, double tol,
+                       int32_t tol_mode, const float* const* precond_scale,
+                       float* const* delta, lm_pcg_stats* stats, void* stream);
+
+/* Weighted mean of subset directions (paper eq. combine-pcg):
+ * out = sum_i M_i delta_i / sum_k M_k element-wise; 0 where sum_k M_k = 0.
+ * delta, M: host arrays of n_b dev float32 pointers of n elements each. */
+lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float* const* M,
+                             int64_t n, float* out, void* stream);
+
+/* Forward render only (eq. alpha-blending), image dev float32 [V][3][H][W]. */
+lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V,
+                    const lm_options* opts, float* image, void* stream);
+
+/* Copy an internal array of a built cache to host memory (inspection and
+ * tests).  Synchronises the stream.  `what` selects the array; `bytes` must
+ * equal the array's size (lm_cache_export_size()). */
+enum {
+    LM_EXPORT_RECORDS_F32 = 0,   /* float [V][N][4]: mean x, mean y, depth, radius (as float) */
+    LM_EXPORT_SORTED_VALUES = 1, /* uint32 [n_keys]: Gaussian id, tile-major depth order       */
+    LM_EXPORT_TILE_RANGES = 2,   /* int64 [n_tiles+1]: start of each tile's list              */
+    LM_EXPORT_IMAGE = 3,         /* float [V][3][H][W]: rendered colour                       */
+    LM_EXPORT_NCONTRIB = 4,      /* int32 [V][H][W]: contributing splats per pixel            */
+    LM_EXPORT_PAIR_T = 5,        /* float [n_pairs]: cached transmittance (flags removed)     */
+    LM_EXPORT_PAIR_D = 6,        /* float [3][n_pairs]: cached dC/dalpha                      */
+    LM_EXPORT_PAIR_PIX = 7,      /* int32 [n_pairs]: global pixel index v*H*W + y*W + x       */
+    LM_EXPORT_PAIR_GAUSS = 8,    /* int32 [n_pairs]: Gaussian id of the pair's splat          */
+    LM_EXPORT_RESIDUAL = 9,      /* float [V][3][H][W]: F = rendered - target                 */
+    LM_EXPORT_PAIR_FLAGS = 10    /* int32 [n_pairs]: bit0 segment head, bit1 alpha clamped    */
+};
+int64_t lm_cache_export_size(const lm_cache* cache, int32_t what);
+lm_status lm_cache_export(const lm_cache* cache, int32_t what, void* host_dst, int64_t bytes,
+                          void* stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LM3DGS_H */

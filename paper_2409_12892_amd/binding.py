@@ -1,0 +1,258 @@
+"""ctypes binding of liblm3dgs.so (include/lm3dgs.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Device buffers are torch tensors on the current HIP device; the
+work is enqueued on torch's current stream.  Importing this module does not
+load the library; the first call does, and raises if it is missing (there is
+no CPU fallback).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, byref, c_double, c_float, c_int32, c_int64, c_void_p
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "liblm3dgs.so")
+
+LM_OK = 0
+LM_WARN_BREAKDOWN = 1
+CACHE_DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
+TOL_NONE, TOL_PAPER_SQUARED, TOL_RELATIVE = 0, 1, 2
+PCG_MAX_HISTORY = 257
+
+EXPORT = dict(records=0, sorted_values=1, tile_ranges=2, image=3, ncontrib=4, pair_T=5, pair_D=6,
+              pair_pix=7, pair_gauss=8, residual=9, pair_flags=10)
+_EXPORT_DTYPE = dict(records=np.float32, sorted_values=np.uint32, tile_ranges=np.int64, image=np.float32,
+                     ncontrib=np.int32, pair_T=np.float32, pair_D=np.float32, pair_pix=np.int32,
+                     pair_gauss=np.int32, residual=np.float32, pair_flags=np.int32)
+
+EXPORTED_SYMBOLS = (
+    "lm_last_error", "lm_build_cache", "lm_cache_destroy", "lm_cache_get_info", "lm_jacobi_diag",
+    "lm_apply_JtJ", "lm_apply_J", "lm_apply_JT", "lm_pcg_solve", "lm_combine_subsets", "lm_render",
+    "lm_cache_export_size", "lm_cache_export",
+)
+
+
+class LmCamera(ctypes.Structure):
+    _fields_ = [("R", c_float * 9), ("t", c_float * 3), ("fx", c_float), ("fy", c_float),
+                ("cx", c_float), ("cy", c_float), ("W", c_int32), ("H", c_int32)]
+
+
+class LmScene(ctypes.Structure):
+    _fields_ = [("N", c_int64), ("sh_degree", c_int32), ("reserved", c_int32), ("x", c_void_p)]
+
+
+class LmOptions(ctypes.Structure):
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("cache_dtype", c_int32), ("flags", c_int32)]
+
+
+class LmCacheInfo(ctypes.Structure):
+    _fields_ = [("N", c_int64), ("n_keys", c_int64), ("n_pairs", c_int64), ("n_segments", c_int64),
+                ("n_gv", c_int64), ("n_pixels", c_int64), ("n_tiles", c_int64), ("cache_bytes", c_int64),
+                ("device_bytes", c_int64), ("V", c_int32), ("P", c_int32), ("tile_w", c_int32),
+                ("tile_h", c_int32), ("cache_dtype", c_int32), ("sh_degree", c_int32)]
+
+
+class LmPcgStats(ctypes.Structure):
+    _fields_ = [("iters", c_int32), ("status", c_int32), ("b_sqnorm", c_double),
+                ("history", c_double * PCG_MAX_HISTORY)]
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the HIP library (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} not found: build it with `python -m paper_2409_12892_amd.build_lib` "
+                          "(there is no CPU fallback)")
+    lib = ctypes.CDLL(path)
+    lib.lm_last_error.restype = ctypes.c_char_p
+    lib.lm_cache_export_size.restype = c_int64
+    for name in EXPORTED_SYMBOLS:
+        if name not in ("lm_last_error", "lm_cache_export_size"):
+            getattr(lib, name).restype = c_int32
+    _lib = lib
+    return lib
+
+
+def _check(status: int, what: str) -> int:
+    if status < 0:
+        msg = load().lm_last_error().decode(errors="replace")
+        raise RuntimeError(f"{what} failed with status {status}: {msg}")
+    return status
+
+
+def _stream():
+    import torch
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _ptr(t) -> c_void_p:
+    return c_void_p(0 if t is None else t.data_ptr())
+
+
+def _dev_f32(t, name):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+        raise TypeError(f"{name} must be a contiguous float32 tensor on the GPU")
+    return t
+
+
+def camera_array(cams) -> ctypes.Array:
+    """ctypes array of lm_camera from a Cameras-like object (R, t, fx, fy, cx, cy, W, H arrays)."""
+    V = int(cams.R.shape[0])
+    arr = (LmCamera * V)()
+    for v in range(V):
+        c = arr[v]
+        c.R[:] = [float(a) for a in np.asarray(cams.R[v], np.float32).reshape(9)]
+        c.t[:] = [float(a) for a in np.asarray(cams.t[v], np.float32).reshape(3)]
+        c.fx, c.fy = float(cams.fx[v]), float(cams.fy[v])
+        c.cx, c.cy = float(cams.cx[v]), float(cams.cy[v])
+        c.W, c.H = int(cams.W[v]), int(cams.H[v])
+    return arr
+
+
+class Cache:
+    """Owner of one lm_cache handle (one image subset)."""
+
+    def __init__(self):
+        self.handle = c_void_p(0)
+        self.N = self.P = self.V = 0
+
+    def info(self) -> dict:
+        inf = LmCacheInfo()
+        _check(load().lm_cache_get_info(self.handle, byref(inf)), "lm_cache_get_info")
+        return {f: getattr(inf, f) for f, _ in LmCacheInfo._fields_}
+
+    def export(self, what: str) -> np.ndarray:
+        lib = load()
+        code = EXPORT[what]
+        n = lib.lm_cache_export_size(self.handle, code)
+        if n < 0:
+            raise RuntimeError(f"lm_cache_export_size({what}) failed")
+        out = np.empty(n // np.dtype(_EXPORT_DTYPE[what]).itemsize, _EXPORT_DTYPE[what])
+        _check(lib.lm_cache_export(self.handle, code, out.ctypes.data_as(c_void_p), c_int64(n), _stream()),
+               "lm_cache_export")
+        return out
+
+    def destroy(self):
+        if self.handle and self.handle.value:
+            load().lm_cache_destroy(self.handle)
+            self.handle = c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.destroy()
+        except Exception:
+            pass
+
+
+def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtype: str = "f32",
+                   cache: Cache | None = None, want_b: bool = True):
+    """Build the gradient cache of one subset.  Returns (cache, b, F_sqnorm)
+    with b = -J^T F as a [P, N] tensor and ||F||^2 as a 1-element float64
+    tensor (both None when want_b is False)."""
+    import torch
+    lib = load()
+    x = _dev_f32(x, "x")
+    target = _dev_f32(target, "target")
+    P, N = x.shape
+    scene = LmScene(N, sh_degree, 0, x.data_ptr())
+    opts = LmOptions(tile[0], tile[1], CACHE_DTYPES[cache_dtype], 0)
+    carr = camera_array(cams)
+    cache = Cache() if cache is None else cache
+    b = torch.empty((P, N), device=x.device, dtype=torch.float32) if want_b else None
+    fsq = torch.empty(1, device=x.device, dtype=torch.float64) if want_b else None
+    h = cache.handle
+    _check(lib.lm_build_cache(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), _stream(),
+                              byref(h), _ptr(b), _ptr(fsq)), "lm_build_cache")
+    cache.handle = h
+    cache.N, cache.P, cache.V = N, P, len(carr)
+    return cache, b, fsq
+
+
+def lm_jacobi_diag(cache: Cache, out=None):
+    import torch
+    out = torch.empty((cache.P, cache.N), device="cuda", dtype=torch.float32) if out is None else out
+    _check(load().lm_jacobi_diag(cache.handle, _ptr(out), _stream()), "lm_jacobi_diag")
+    return out
+
+
+def lm_apply_JtJ(cache: Cache, p, lam: float = 0.0, M=None, out=None, want_jp_sqnorm: bool = False):
+    import torch
+    p = _dev_f32(p, "p")
+    out = torch.empty_like(p) if out is None else out
+    jp = torch.empty(1, device=p.device, dtype=torch.float64) if want_jp_sqnorm else None
+    _check(load().lm_apply_JtJ(cache.handle, _ptr(p), c_float(lam), _ptr(M), _ptr(out), _ptr(jp), _stream()),
+           "lm_apply_JtJ")
+    return (out, jp) if want_jp_sqnorm else out
+
+
+def lm_apply_J(cache: Cache, p, out=None, n_residuals: int | None = None):
+    import torch
+    p = _dev_f32(p, "p")
+    if out is None:
+        n = n_residuals if n_residuals is not None else 3 * cache.info()["n_pixels"]
+        out = torch.empty(n, device=p.device, dtype=torch.float32)
+    _check(load().lm_apply_J(cache.handle, _ptr(p), _ptr(out), _stream()), "lm_apply_J")
+    return out
+
+
+def lm_apply_JT(cache: Cache, u, out=None):
+    import torch
+    u = _dev_f32(u, "u")
+    out = torch.empty((cache.P, cache.N), device=u.device, dtype=torch.float32) if out is None else out
+    _check(load().lm_apply_JT(cache.handle, _ptr(u), _ptr(out), _stream()), "lm_apply_JT")
+    return out
+
+
+def lm_pcg_solve(caches, bs, Ms, lam: float, n_iters: int, tol: float = 0.0, tol_mode: int = TOL_NONE,
+                 scales=None, deltas=None):
+    """Algorithm 1 for each subset; returns (deltas, stats dicts)."""
+    import torch
+    nb = len(caches)
+    deltas = [torch.empty_like(b) for b in bs] if deltas is None else deltas
+    H = (c_void_p * nb)(*[c.handle for c in caches])
+    B = (c_void_p * nb)(*[b.data_ptr() for b in bs])
+    Mm = (c_void_p * nb)(*[m.data_ptr() for m in Ms])
+    D = (c_void_p * nb)(*[d.data_ptr() for d in deltas])
+    Sc = None if scales is None else (c_void_p * nb)(*[0 if s is None else s.data_ptr() for s in scales])
+    stats = (LmPcgStats * nb)()
+    _check(load().lm_pcg_solve(H, c_int32(nb), B, Mm, c_float(lam), c_int32(n_iters), c_double(tol),
+                               c_int32(tol_mode), Sc, D, stats, _stream()), "lm_pcg_solve")
+    out = [dict(iters=s.iters, status=s.status, b_sqnorm=s.b_sqnorm,
+                history=np.array(s.history[:s.iters + 1])) for s in stats]
+    return deltas, out
+
+
+def lm_combine_subsets(deltas, Ms, out=None):
+    import torch
+    nb = len(deltas)
+    out = torch.empty_like(deltas[0]) if out is None else out
+    D = (c_void_p * nb)(*[d.data_ptr() for d in deltas])
+    Mm = (c_void_p * nb)(*[m.data_ptr() for m in Ms])
+    _check(load().lm_combine_subsets(c_int32(nb), D, Mm, c_int64(deltas[0].numel()), _ptr(out), _stream()),
+           "lm_combine_subsets")
+    return out
+
+
+def lm_render(x, sh_degree: int, cams, *, tile=(16, 16), out=None):
+    """Forward render of every view into a flat float32 [V][3][H][W] tensor."""
+    import torch
+    x = _dev_f32(x, "x")
+    P, N = x.shape
+    carr = camera_array(cams)
+    n = sum(3 * int(cams.W[v]) * int(cams.H[v]) for v in range(len(carr)))
+    out = torch.empty(n, device=x.device, dtype=torch.float32) if out is None else out
+    scene = LmScene(N, sh_degree, 0, x.data_ptr())
+    opts = LmOptions(tile[0], tile[1], 0, 0)
+    _check(load().lm_render(byref(scene), carr, c_int32(len(carr)), byref(opts), _ptr(out), _stream()),
+           "lm_render")
+    return out

@@ -1,0 +1,745 @@
+// Host side of the C ABI declared in include/lm3dgs.h: cache construction
+// and the orchestration of the kernels on the caller's stream.
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+#include <vector>
+
+#include "lm_internal.h"
+
+namespace lm {
+
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+namespace {
+
+// Device buffer that only grows; reused across rebuilds of one cache.
+struct DevBuf {
+    void* p = nullptr;
+    size_t cap = 0;
+    hipError_t ensure(size_t bytes) {
+        if (bytes <= cap && p) return hipSuccess;
+        if (p) {
+            hipError_t e = hipFree(p);
+            p = nullptr;
+            cap = 0;
+            if (e != hipSuccess) return e;
+        }
+        size_t want = bytes + bytes / 16 + 256;
+        hipError_t e = hipMalloc(&p, want);
+        if (e != hipSuccess) {
+            p = nullptr;
+            return e;
+        }
+        cap = want;
+        return hipSuccess;
+    }
+    void release() {
+        if (p) (void)hipFree(p);
+        p = nullptr;
+        cap = 0;
+    }
+    template <class T> T* as() const { return (T*)p; }
+};
+
+inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
+
+}  // namespace
+}  // namespace lm
+
+using lm::DevBuf;
+
+struct lm_cache {
+    int64_t N = 0;
+    int P = 0, deg = 0, V = 0, TW = 16, TH = 16, dtype = LM_CACHE_F32;
+    int64_t n_tiles = 0, n_pix = 0, n_keys = 0, n_pairs = 0, n_seg = 0, n_gv = 0;
+    int64_t pair_stride = 8, seg_stride = 8;
+    bool vals_in_alt = false;
+    bool built = false;
+    std::vector<lm::CamDev> cams_h;
+    std::vector<int> viewW, viewH;
+    DevBuf cams, tile_view, x;
+    DevBuf rec64, recf, rad, keycnt, keyoff;
+    DevBuf keys, vals, keys_alt, vals_alt, sort_tmp, scan_tmp;
+    DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
+    DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs;
+    DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
+    DevBuf dyc, gmom, jp_part, gram, pg_part, scalar;
+    DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
+
+    const uint32_t* sorted_vals() const { return vals_in_alt ? vals_alt.as<uint32_t>() : vals.as<uint32_t>(); }
+
+    lm::CacheView view() const {
+        lm::CacheView c{};
+        c.N = N; c.P = P; c.deg = deg; c.V = V; c.TW = TW; c.TH = TH; c.dtype = dtype;
+        c.n_tiles = n_tiles; c.n_pix = n_pix; c.n_seg = n_seg; c.n_gv = n_gv;
+        c.cams = cams.as<lm::CamDev>();
+        c.tile_view = tile_view.as<int32_t>();
+        c.tile_pair_off = tile_pair_off.as<int64_t>();
+        c.tile_seg_off = tile_seg_off.as<int64_t>();
+        c.pT = pT.p; c.pD = pD.p; c.ppix = ppix.as<uint8_t>();
+        c.n_pairs = n_pairs; c.pair_stride = pair_stride;
+        c.seg_gv = seg_gv.as<uint32_t>(); c.seg_loc = seg_loc.as<uint32_t>(); c.seg_f = seg_f.as<float>();
+        c.seg_stride = seg_stride;
+        c.gv_rec = gv_rec.as<uint32_t>(); c.gv_first = gv_first.as<uint32_t>();
+        c.gv_seg_off = gv_seg_off.as<uint32_t>(); c.gv_segs = gv_segs.as<uint32_t>();
+        return c;
+    }
+
+    lm::ApplyArgs apply_args() const {
+        lm::ApplyArgs a{};
+        a.c = view();
+        a.x = x.as<float>();
+        a.dyc = dyc.as<float>();
+        a.gmom = gmom.as<float>();
+        a.jp_part = jp_part.as<double>();
+        return a;
+    }
+
+    size_t device_bytes() const {
+        const DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt,
+                               &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
+                               &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &gv_cnt, &gv_flag,
+                               &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
+                               &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar,
+                               &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
+        size_t s = 0;
+        for (auto* b : all) s += b->cap;
+        return s;
+    }
+
+    void release_all() {
+        DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt,
+                         &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
+                         &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &gv_cnt, &gv_flag,
+                         &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
+                         &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar,
+                         &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
+        for (auto* b : all) b->release();
+    }
+};
+
+namespace {
+
+#define LM_CHECK(cond, code, msg)        \
+    do {                                 \
+        if (!(cond)) {                   \
+            ::lm::set_error(msg);        \
+            return code;                 \
+        }                                \
+    } while (0)
+
+inline hipStream_t S(void* s) { return (hipStream_t)s; }
+
+// Build the cache up to and including the count pass (projection, binning,
+// sort, forward render, residuals).  render_only stops there.
+lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                        const lm_options* opts, hipStream_t s) {
+    using namespace lm;
+    LM_CHECK(scene && cams && V > 0 && V <= kMaxViews, LM_ERR_INVALID_ARG, "lm_build_cache: bad scene/cameras");
+    LM_CHECK(scene->x && scene->N > 0, LM_ERR_INVALID_ARG, "lm_build_cache: empty scene");
+    LM_CHECK(scene->sh_degree >= 0 && scene->sh_degree <= 3, LM_ERR_INVALID_ARG, "sh_degree must be 0..3");
+    int TW = 16, TH = 16, dtype = LM_CACHE_F32;
+    if (opts) {
+        if (opts->tile_w > 0) TW = opts->tile_w;
+        if (opts->tile_h > 0) TH = opts->tile_h;
+        dtype = opts->cache_dtype;
+    }
+    LM_CHECK(TW * TH <= kMaxTilePix && TW > 0 && TH > 0, LM_ERR_INVALID_ARG, "tile_w * tile_h must be 1..256");
+    LM_CHECK(dtype == LM_CACHE_F32 || dtype == LM_CACHE_BF16 || dtype == LM_CACHE_F16, LM_ERR_INVALID_ARG,
+             "cache_dtype must be LM_CACHE_F32, _BF16 or _F16");
+    LM_CHECK(scene->N * (int64_t)V < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY, "N * V must fit in 32 bits");
+    c->built = false;
+    c->N = scene->N;
+    c->deg = scene->sh_degree;
+    c->P = 11 + 3 * (c->deg + 1) * (c->deg + 1);
+    c->V = V;
+    c->TW = TW;
+    c->TH = TH;
+    c->dtype = dtype;
+    c->cams_h.resize(V);
+    int64_t tile_base = 0, pix_base = 0;
+    std::vector<int32_t> tv;
+    for (int v = 0; v < V; ++v) {
+        const lm_camera& in = cams[v];
+        LM_CHECK(in.W > 0 && in.H > 0, LM_ERR_INVALID_ARG, "camera with empty image");
+        CamDev& d = c->cams_h[v];
+        for (int i = 0; i < 9; ++i) d.R[i] = in.R[i];
+        for (int i = 0; i < 3; ++i) d.t[i] = in.t[i];
+        d.fx = in.fx; d.fy = in.fy; d.cx = in.cx; d.cy = in.cy;
+        for (int i = 0; i < 3; ++i) d.C[i] = -(d.R[i] * d.t[0] + d.R[3 + i] * d.t[1] + d.R[6 + i] * d.t[2]);
+        d.W = in.W; d.H = in.H;
+        d.TX = (in.W + TW - 1) / TW;
+        d.TY = (in.H + TH - 1) / TH;
+        d.tile_base = tile_base;
+        d.pix_base = pix_base;
+        tv.insert(tv.end(), (size_t)d.TX * d.TY, v);
+        tile_base += (int64_t)d.TX * d.TY;
+        pix_base += (int64_t)in.W * in.H;
+    }
+    c->n_tiles = tile_base;
+    c->n_pix = pix_base;
+    LM_CHECK(c->n_tiles < ((int64_t)1 << 32), LM_ERR_CAPACITY, "too many tiles");
+    const int64_t N = c->N, R = N * (int64_t)V, P = c->P;
+    LM_HIP(c->cams.ensure(sizeof(CamDev) * V));
+    LM_HIP(hipMemcpyAsync(c->cams.p, c->cams_h.data(), sizeof(CamDev) * V, hipMemcpyHostToDevice, s));
+    LM_HIP(c->tile_view.ensure(sizeof(int32_t) * c->n_tiles));
+    LM_HIP(hipMemcpyAsync(c->tile_view.p, tv.data(), sizeof(int32_t) * c->n_tiles, hipMemcpyHostToDevice, s));
+    LM_HIP(c->x.ensure(sizeof(float) * P * N));
+    LM_HIP(hipMemcpyAsync(c->x.p, scene->x, sizeof(float) * P * N, hipMemcpyDeviceToDevice, s));
+
+    // projection and key counts
+    LM_HIP(c->rec64.ensure(sizeof(double) * 10 * R));
+    LM_HIP(c->recf.ensure(sizeof(float) * 3 * R));
+    LM_HIP(c->rad.ensure(sizeof(int32_t) * R));
+    LM_HIP(c->keycnt.ensure(sizeof(uint32_t) * R));
+    LM_HIP(c->keyoff.ensure(sizeof(uint64_t) * (R + 1)));
+    LM_HIP(c->scan_tmp.ensure(std::max(scan_tmp_bytes(R), scan_tmp_bytes(N * (int64_t)V + 1)) + 1024));
+    LM_HIP(launch_project(c->cams.as<CamDev>(), c->x.as<float>(), N, V, c->deg, TW, TH, c->rec64.as<double>(),
+                          c->recf.as<float>(), c->rad.as<int32_t>(), c->keycnt.as<uint32_t>(), s));
+    LM_HIP(exclusive_scan_u32_to_u64(c->keycnt.as<uint32_t>(), c->keyoff.as<uint64_t>(), R, c->scan_tmp.p,
+                                     c->scan_tmp.cap, s));
+    uint64_t K = 0;
+    LM_HIP(hipMemcpyAsync(&K, c->keyoff.as<uint64_t>() + R, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    LM_HIP(hipStreamSynchronize(s));
+    c->n_keys = (int64_t)K;
+
+    // binning and depth sort
+    const int64_t Ka = std::max<int64_t>(c->n_keys, 1);
+    LM_HIP(c->keys.ensure(sizeof(uint64_t) * Ka));
+    LM_HIP(c->vals.ensure(sizeof(uint32_t) * Ka));
+    LM_HIP(c->keys_alt.ensure(sizeof(uint64_t) * Ka));
+    LM_HIP(c->vals_alt.ensure(sizeof(uint32_t) * Ka));
+    LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(Ka)));
+    LM_HIP(launch_bin_emit(c->cams.as<CamDev>(), N, V, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(),
+                           c->keycnt.as<uint32_t>(), c->keyoff.as<uint64_t>(), c->keys.as<uint64_t>(),
+                           c->vals.as<uint32_t>(), s));
+    int tile_bits = 1;
+    while (((int64_t)1 << tile_bits) < c->n_tiles) ++tile_bits;
+    bool alt = false;
+    LM_HIP(radix_sort_pairs(c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), c->keys_alt.as<uint64_t>(),
+                            c->vals_alt.as<uint32_t>(), c->n_keys, 0, 31 + tile_bits, c->sort_tmp.p,
+                            c->sort_tmp.cap, &alt, s));
+    c->vals_in_alt = alt;
+    const uint64_t* skeys = alt ? c->keys_alt.as<uint64_t>() : c->keys.as<uint64_t>();
+    LM_HIP(c->tile_start.ensure(sizeof(int64_t) * (c->n_tiles + 1)));
+    LM_HIP(launch_tile_ranges(skeys, c->n_keys, c->n_tiles, c->tile_start.as<int64_t>(), s));
+
+    // forward render and per-entry counts
+    LM_HIP(c->entry_cnt.ensure(sizeof(uint32_t) * Ka));
+    LM_HIP(c->pixC.ensure(sizeof(double) * 3 * c->n_pix));
+    LM_HIP(c->ncontrib.ensure(sizeof(int32_t) * c->n_pix));
+    LM_HIP(c->resid.ensure(sizeof(float) * 3 * c->n_pix));
+    LM_HIP(c->fsq_part.ensure(sizeof(double) * c->n_tiles));
+    LM_HIP(c->tile_pairs.ensure(sizeof(uint32_t) * c->n_tiles));
+    LM_HIP(c->tile_segs.ensure(sizeof(uint32_t) * c->n_tiles));
+    LM_HIP(c->gv_cnt.ensure(sizeof(uint32_t) * (R + 1)));
+    LM_HIP(hipMemsetAsync(c->gv_cnt.p, 0, sizeof(uint32_t) * (R + 1), s));
+    RasterArgs ra{};
+    ra.cams = c->cams.as<CamDev>();
+    ra.tile_view = c->tile_view.as<int32_t>();
+    ra.tile_start = c->tile_start.as<int64_t>();
+    ra.vals = c->sorted_vals();
+    ra.rec64 = c->rec64.as<double>();
+    ra.N = N; ra.V = V; ra.TW = TW; ra.TH = TH;
+    ra.target = target;
+    ra.entry_cnt = c->entry_cnt.as<uint32_t>();
+    ra.pixC = c->pixC.as<double>();
+    ra.ncontrib = c->ncontrib.as<int32_t>();
+    ra.resid = c->resid.as<float>();
+    ra.fsq_part = c->fsq_part.as<double>();
+    ra.tile_pairs = c->tile_pairs.as<uint32_t>();
+    ra.tile_segs = c->tile_segs.as<uint32_t>();
+    ra.gv_cnt = c->gv_cnt.as<uint32_t>();
+    ra.n_pix = c->n_pix;
+    LM_HIP(launch_raster(false, dtype, c->n_tiles, ra, s));
+    return LM_OK;
+}
+
+lm_status build_fill(lm_cache* c, hipStream_t s) {
+    using namespace lm;
+    const int64_t N = c->N, V = c->V, NV = N * V;
+    LM_HIP(c->tile_pair_off.ensure(sizeof(uint64_t) * (c->n_tiles + 1)));
+    LM_HIP(c->tile_seg_off.ensure(sizeof(uint64_t) * (c->n_tiles + 1)));
+    LM_HIP(c->scan_tmp.ensure(std::max(scan_tmp_bytes(c->n_tiles), scan_tmp_bytes(NV)) + 1024));
+    LM_HIP(exclusive_scan_u32_to_u64(c->tile_pairs.as<uint32_t>(), c->tile_pair_off.as<uint64_t>(), c->n_tiles,
+                                     c->scan_tmp.p, c->scan_tmp.cap, s));
+    LM_HIP(exclusive_scan_u32_to_u64(c->tile_segs.as<uint32_t>(), c->tile_seg_off.as<uint64_t>(), c->n_tiles,
+                                     c->scan_tmp.p, c->scan_tmp.cap, s));
+    LM_HIP(c->gv_flag.ensure(sizeof(uint32_t) * NV));
+    LM_HIP(c->gv_idx.ensure(sizeof(uint64_t) * (NV + 1)));
+    LM_HIP(c->gv_segoff.ensure(sizeof(uint64_t) * (NV + 1)));
+    LM_HIP(launch_flag_nonzero(c->gv_cnt.as<uint32_t>(), NV, c->gv_flag.as<uint32_t>(), s));
+    LM_HIP(exclusive_scan_u32_to_u64(c->gv_flag.as<uint32_t>(), c->gv_idx.as<uint64_t>(), NV, c->scan_tmp.p,
+                                     c->scan_tmp.cap, s));
+    LM_HIP(exclusive_scan_u32_to_u64(c->gv_cnt.as<uint32_t>(), c->gv_segoff.as<uint64_t>(), NV, c->scan_tmp.p,
+                                     c->scan_tmp.cap, s));
+    uint64_t host3[3] = {0, 0, 0};
+    LM_HIP(hipMemcpyAsync(&host3[0], c->tile_pair_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
+    LM_HIP(hipMemcpyAsync(&host3[1], c->tile_seg_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
+    LM_HIP(hipMemcpyAsync(&host3[2], c->gv_idx.as<uint64_t>() + NV, 8, hipMemcpyDeviceToHost, s));
+    LM_HIP(hipStreamSynchronize(s));
+    c->n_pairs = (int64_t)host3[0];
+    c->n_seg = (int64_t)host3[1];
+    c->n_gv = (int64_t)host3[2];
+    LM_CHECK(c->n_seg < (int64_t)0xFFFFFFFFu && c->n_gv < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY,
+             "segment or (Gaussian, view) count exceeds 32 bits");
+    const int64_t nseg_a = std::max<int64_t>(c->n_seg, 1), ngv_a = std::max<int64_t>(c->n_gv, 1);
+    LM_HIP(c->gv_rec.ensure(sizeof(uint32_t) * ngv_a));
+    LM_HIP(c->gv_seg_off.ensure(sizeof(uint32_t) * (ngv_a + 1)));
+    LM_HIP(c->gv_first.ensure(sizeof(uint32_t) * (N + 1)));
+    LM_HIP(c->gv_cursor.ensure(sizeof(uint32_t) * ngv_a));
+    LM_HIP(hipMemsetAsync(c->gv_cursor.p, 0, sizeof(uint32_t) * ngv_a, s));
+    LM_HIP(c->gv_segs.ensure(sizeof(uint32_t) * nseg_a));
+    LM_HIP(launch_gv_compact(c->gv_cnt.as<uint32_t>(), c->gv_idx.as<uint64_t>(), c->gv_segoff.as<uint64_t>(), N,
+                             (int)V, c->gv_rec.as<uint32_t>(), c->gv_seg_off.as<uint32_t>(),
+                             c->gv_first.as<uint32_t>(), s));
+    // pair and segment arrays (planes padded so 8-wide vector loads stay inside)
+    c->pair_stride = round_up(c->n_pairs, 8) + 8;
+    c->seg_stride = round_up(nseg_a, 8);
+    const size_t wb = dtype_bytes(c->dtype);
+    LM_HIP(c->pT.ensure(wb * c->pair_stride));
+    LM_HIP(c->pD.ensure(wb * 3 * c->pair_stride));
+    LM_HIP(c->ppix.ensure(c->pair_stride));
+    LM_HIP(hipMemsetAsync(c->pT.p, 0, wb * c->pair_stride, s));
+    LM_HIP(hipMemsetAsync(c->pD.p, 0, wb * 3 * c->pair_stride, s));
+    LM_HIP(hipMemsetAsync(c->ppix.p, 0, c->pair_stride, s));
+    LM_HIP(c->seg_gv.ensure(sizeof(uint32_t) * nseg_a));
+    LM_HIP(c->seg_loc.ensure(sizeof(uint32_t) * nseg_a));
+    LM_HIP(c->seg_f.ensure(sizeof(float) * 6 * c->seg_stride));
+    RasterArgs ra{};
+    ra.cams = c->cams.as<CamDev>();
+    ra.tile_view = c->tile_view.as<int32_t>();
+    ra.tile_start = c->tile_start.as<int64_t>();
+    ra.vals = c->sorted_vals();
+    ra.rec64 = c->rec64.as<double>();
+    ra.N = N; ra.V = (int)V; ra.TW = c->TW; ra.TH = c->TH;
+    ra.entry_cnt = c->entry_cnt.as<uint32_t>();
+    ra.pixC = c->pixC.as<double>();
+    ra.n_pix = c->n_pix;
+    ra.tile_pair_off = c->tile_pair_off.as<int64_t>();
+    ra.tile_seg_off = c->tile_seg_off.as<int64_t>();
+    ra.gv_idx = c->gv_idx.as<uint64_t>();
+    ra.gv_segoff = c->gv_segoff.as<uint64_t>();
+    ra.gv_cursor = c->gv_cursor.as<uint32_t>();
+    ra.gv_segs = c->gv_segs.as<uint32_t>();
+    ra.pT = c->pT.p;
+    ra.pD = c->pD.p;
+    ra.pair_stride = c->pair_stride;
+    ra.ppix = c->ppix.as<uint8_t>();
+    ra.seg_gv = c->seg_gv.as<uint32_t>();
+    ra.seg_loc = c->seg_loc.as<uint32_t>();
+    ra.seg_f = c->seg_f.as<float>();
+    ra.seg_stride = c->seg_stride;
+    LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s));
+    LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s));
+    // product workspaces
+    LM_HIP(c->dyc.ensure(sizeof(float) * 9 * ngv_a));
+    LM_HIP(c->gmom.ensure(sizeof(float) * 9 * nseg_a));
+    LM_HIP(c->jp_part.ensure(sizeof(double) * c->n_tiles));
+    LM_HIP(c->pg_part.ensure(sizeof(double) * (chain_blocks(N) + 1)));
+    LM_HIP(c->scalar.ensure(sizeof(double) * 4));
+    c->built = true;
+    return LM_OK;
+}
+
+lm_status apply_JT_internal(const lm_cache* c, const float* u, float scale, float* g, hipStream_t s) {
+    lm::ApplyArgs a = c->apply_args();
+    a.uin = u;
+    LM_HIP(lm::launch_apply_tile(2, a, s));
+    LM_HIP(lm::launch_chain(a, scale, 0.0f, nullptr, g, nullptr, s));
+    return LM_OK;
+}
+
+lm_status apply_JtJ_internal(lm_cache* c, const float* p, float lambda, const float* M, float* g, double* pg_part,
+                             const int32_t* stop, hipStream_t s) {
+    lm::ApplyArgs a = c->apply_args();
+    a.p = p;
+    a.stop = stop;
+    LM_HIP(lm::launch_tangent(a, s));
+    LM_HIP(lm::launch_apply_tile(3, a, s));
+    LM_HIP(lm::launch_chain(a, 1.0f, lambda, M, g, pg_part, s));
+    return LM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lm_last_error(void) { return lm::g_last_error.c_str(); }
+
+lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                         const lm_options* opts, void* stream, lm_cache** inout, float* b, double* F_sqnorm) {
+    LM_CHECK(inout, LM_ERR_INVALID_ARG, "lm_build_cache: inout is NULL");
+    LM_CHECK(target, LM_ERR_INVALID_ARG, "lm_build_cache: target is NULL");
+    lm::set_error("");
+    lm_cache* c = *inout;
+    bool created = false;
+    if (!c) {
+        c = new (std::nothrow) lm_cache();
+        LM_CHECK(c, LM_ERR_HIP, "out of host memory");
+        created = true;
+    }
+    hipStream_t s = S(stream);
+    lm_status st = build_forward(c, scene, cams, V, target, opts, s);
+    if (st == LM_OK) st = build_fill(c, s);
+    if (st == LM_OK && F_sqnorm) {
+        hipError_t e = lm::reduce_f64(c->fsq_part.as<double>(), c->n_tiles, F_sqnorm, s);
+        if (e != hipSuccess) {
+            lm::set_error(std::string("reduce: ") + hipGetErrorString(e));
+            st = LM_ERR_HIP;
+        }
+    }
+    if (st == LM_OK && b) st = apply_JT_internal(c, c->resid.as<float>(), -1.0f, b, s);
+    if (st != LM_OK) {
+        if (created) {
+            c->release_all();
+            delete c;
+        }
+        return st;
+    }
+    *inout = c;
+    return LM_OK;
+}
+
+lm_status lm_cache_destroy(lm_cache* cache) {
+    if (!cache) return LM_OK;
+    (void)hipDeviceSynchronize();
+    cache->release_all();
+    delete cache;
+    return LM_OK;
+}
+
+lm_status lm_cache_get_info(const lm_cache* c, lm_cache_info* info) {
+    LM_CHECK(c && info, LM_ERR_INVALID_ARG, "lm_cache_get_info: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    memset(info, 0, sizeof(*info));
+    info->N = c->N;
+    info->n_keys = c->n_keys;
+    info->n_pairs = c->n_pairs;
+    info->n_segments = c->n_seg;
+    info->n_gv = c->n_gv;
+    info->n_pixels = c->n_pix;
+    info->n_tiles = c->n_tiles;
+    const int64_t wb = (int64_t)lm::dtype_bytes(c->dtype);
+    info->cache_bytes = c->n_pairs * (4 * wb + 1) + c->n_seg * (4 + 4 + 24);
+    info->device_bytes = (int64_t)c->device_bytes();
+    info->V = c->V;
+    info->P = c->P;
+    info->tile_w = c->TW;
+    info->tile_h = c->TH;
+    info->cache_dtype = c->dtype;
+    info->sh_degree = c->deg;
+    return LM_OK;
+}
+
+lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
+    LM_CHECK(c && M, LM_ERR_INVALID_ARG, "lm_jacobi_diag: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    LM_HIP(cm->gram.ensure(sizeof(float) * 40 * std::max<int64_t>(c->n_seg, 1)));
+    LM_HIP(lm::launch_jacobi_diag(c->view(), c->x.as<float>(), cm->gram.as<float>(), M, S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const float* M, float* g,
+                       double* Jp_sqnorm, void* stream) {
+    LM_CHECK(c && p && g, LM_ERR_INVALID_ARG, "lm_apply_JtJ: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    lm_status st = apply_JtJ_internal(cm, p, M ? lambda : 0.0f, M, g, nullptr, nullptr, S(stream));
+    if (st != LM_OK) return st;
+    if (Jp_sqnorm) LM_HIP(lm::reduce_f64(c->jp_part.as<double>(), c->n_tiles, Jp_sqnorm, S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) {
+    LM_CHECK(c && p && u, LM_ERR_INVALID_ARG, "lm_apply_J: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm::ApplyArgs a = c->apply_args();
+    a.p = p;
+    a.uout = u;
+    LM_HIP(lm::launch_tangent(a, S(stream)));
+    LM_HIP(lm::launch_apply_tile(1, a, S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream) {
+    LM_CHECK(c && u && g, LM_ERR_INVALID_ARG, "lm_apply_JT: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    return apply_JT_internal(c, u, 1.0f, g, S(stream));
+}
+
+lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
+                       float lambda, int32_t n_iters, double tol, int32_t tol_mode,
+                       const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
+    LM_CHECK(caches && b && M && delta && n_b > 0, LM_ERR_INVALID_ARG, "lm_pcg_solve: NULL argument");
+    LM_CHECK(n_iters >= 0 && n_iters < LM_PCG_MAX_HISTORY, LM_ERR_INVALID_ARG, "n_iters out of range");
+    LM_CHECK(tol_mode >= LM_TOL_NONE && tol_mode <= LM_TOL_RELATIVE, LM_ERR_INVALID_ARG, "bad tol_mode");
+    hipStream_t s = S(stream);
+    for (int i = 0; i < n_b; ++i) {
+        lm_cache* c = caches[i];
+        LM_CHECK(c && c->built && b[i] && M[i] && delta[i], LM_ERR_INVALID_ARG, "lm_pcg_solve: bad subset entry");
+        const int64_t n = c->N * (int64_t)c->P;
+        const float* sc = precond_scale ? precond_scale[i] : nullptr;
+        LM_HIP(c->pcg_r.ensure(sizeof(float) * n));
+        LM_HIP(c->pcg_z.ensure(sizeof(float) * n));
+        LM_HIP(c->pcg_p.ensure(sizeof(float) * n));
+        LM_HIP(c->pcg_g.ensure(sizeof(float) * n));
+        const int64_t np = lm::pcg_partial_count(n);
+        LM_HIP(c->pcg_part.ensure(sizeof(double) * 3 * np));
+        LM_HIP(c->pcg_state.ensure(sizeof(lm::PcgState)));
+        lm::PcgState* st = c->pcg_state.as<lm::PcgState>();
+        float* x = delta[i];
+        float *r = c->pcg_r.as<float>(), *z = c->pcg_z.as<float>(), *p = c->pcg_p.as<float>(),
+              *g = c->pcg_g.as<float>();
+        double* part = c->pcg_part.as<double>();
+        const int32_t* stop = &st->stop;
+        LM_HIP(lm::pcg_init(n, b[i], M[i], sc, x, s));
+        LM_HIP(hipMemsetAsync(st, 0, sizeof(lm::PcgState), s));
+        lm_status e = apply_JtJ_internal(c, x, lambda, M[i], g, nullptr, nullptr, s);
+        if (e != LM_OK) return e;
+        LM_HIP(lm::pcg_init_r(n, b[i], g, M[i], sc, r, z, p, part, st, s));
+        const int64_t nbc = lm::chain_blocks(c->N);
+        for (int it = 0; it < n_iters; ++it) {
+            e = apply_JtJ_internal(c, p, lambda, M[i], g, c->pg_part.as<double>(), stop, s);
+            if (e != LM_OK) return e;
+            LM_HIP(lm::pcg_alpha(c->pg_part.as<double>(), nbc, st, s));
+            LM_HIP(lm::pcg_update(n, st, p, g, M[i], sc, x, r, z, part, tol, tol_mode, s));
+        }
+        if (stats) {
+            lm::PcgState hs;
+            LM_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+            LM_HIP(hipStreamSynchronize(s));
+            stats[i].iters = hs.iters;
+            stats[i].status = hs.status;
+            stats[i].b_sqnorm = hs.bb;
+            for (int k = 0; k < LM_PCG_MAX_HISTORY; ++k) stats[i].history[k] = k <= hs.iters ? hs.hist[k] : 0.0;
+        }
+    }
+    if (!stats) LM_HIP(hipStreamSynchronize(s));
+    return LM_OK;
+}
+
+lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float* const* M, int64_t n, float* out,
+                             void* stream) {
+    LM_CHECK(delta && M && out && n_b > 0 && n_b <= 16 && n >= 0, LM_ERR_INVALID_ARG,
+             "lm_combine_subsets: bad arguments (1 <= n_b <= 16)");
+    for (int i = 0; i < n_b; ++i) LM_CHECK(delta[i] && M[i], LM_ERR_INVALID_ARG, "lm_combine_subsets: NULL entry");
+    if (n == 0) return LM_OK;
+    LM_HIP(lm::launch_combine(n_b, delta, M, n, out, S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, const lm_options* opts, float* image,
+                    void* stream) {
+    LM_CHECK(image, LM_ERR_INVALID_ARG, "lm_render: image is NULL");
+    lm_cache* c = new (std::nothrow) lm_cache();
+    LM_CHECK(c, LM_ERR_HIP, "out of host memory");
+    hipStream_t s = S(stream);
+    lm_status st = build_forward(c, scene, cams, V, nullptr, opts, s);
+    if (st == LM_OK) {
+        hipError_t e = hipMemcpyAsync(image, c->resid.p, sizeof(float) * 3 * c->n_pix, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            lm::set_error(std::string("lm_render: ") + hipGetErrorString(e));
+            st = LM_ERR_HIP;
+        }
+    }
+    (void)hipStreamSynchronize(s);
+    c->release_all();
+    delete c;
+    return st;
+}
+
+int64_t lm_cache_export_size(const lm_cache* c, int32_t what) {
+    if (!c || !c->built) return -1;
+    switch (what) {
+        case LM_EXPORT_RECORDS_F32: return 4 * 4 * c->N * (int64_t)c->V;
+        case LM_EXPORT_SORTED_VALUES: return 4 * c->n_keys;
+        case LM_EXPORT_TILE_RANGES: return 8 * (c->n_tiles + 1);
+        case LM_EXPORT_IMAGE: return 4 * 3 * c->n_pix;
+        case LM_EXPORT_NCONTRIB: return 4 * c->n_pix;
+        case LM_EXPORT_PAIR_T: return 4 * c->n_pairs;
+        case LM_EXPORT_PAIR_D: return 4 * 3 * c->n_pairs;
+        case LM_EXPORT_PAIR_PIX: return 4 * c->n_pairs;
+        case LM_EXPORT_PAIR_GAUSS: return 4 * c->n_pairs;
+        case LM_EXPORT_RESIDUAL: return 4 * 3 * c->n_pix;
+        case LM_EXPORT_PAIR_FLAGS: return 4 * c->n_pairs;
+        default: return -1;
+    }
+}
+
+}  // extern "C"
+
+namespace {
+
+float decode_word(const uint8_t* base, int dtype, int64_t i, uint32_t* flags) {
+    if (dtype == LM_CACHE_F32) {
+        uint32_t w;
+        memcpy(&w, base + 4 * i, 4);
+        if (flags) *flags = ((w >> 31) & 1u) | (((w >> 30) & 1u) << 1);
+        if (flags) w &= 0x3FFFFFFFu;
+        float f;
+        memcpy(&f, &w, 4);
+        return f;
+    }
+    uint16_t h;
+    memcpy(&h, base + 2 * i, 2);
+    if (flags) {
+        *flags = ((h >> 15) & 1u) | (((h >> 14) & 1u) << 1);
+        h &= 0x3FFF;
+    }
+    if (dtype == LM_CACHE_BF16) {
+        uint32_t w = (uint32_t)h << 16;
+        float f;
+        memcpy(&f, &w, 4);
+        return f;
+    }
+    // binary16 -> float
+    const uint32_t sign = (h >> 15) & 1u, ex = (h >> 10) & 0x1Fu, man = h & 0x3FFu;
+    float mag;
+    if (ex == 0) mag = ldexpf((float)man, -24);
+    else if (ex == 31) mag = man ? NAN : INFINITY;
+    else mag = ldexpf((float)(man | 0x400u), (int)ex - 25);
+    return sign ? -mag : mag;
+}
+
+template <class T>
+hipError_t fetch(std::vector<T>& out, const void* dev, int64_t n, hipStream_t s) {
+    out.resize((size_t)std::max<int64_t>(n, 0));
+    if (n <= 0) return hipSuccess;
+    hipError_t e = hipMemcpyAsync(out.data(), dev, sizeof(T) * n, hipMemcpyDeviceToHost, s);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(s);
+}
+
+}  // namespace
+
+extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host_dst, int64_t bytes, void* stream) {
+    LM_CHECK(c && host_dst, LM_ERR_INVALID_ARG, "lm_cache_export: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    const int64_t need = lm_cache_export_size(c, what);
+    LM_CHECK(need >= 0, LM_ERR_INVALID_ARG, "lm_cache_export: unknown array");
+    LM_CHECK(bytes == need, LM_ERR_INVALID_ARG, "lm_cache_export: size mismatch");
+    hipStream_t s = S(stream);
+    const int64_t R = c->N * (int64_t)c->V;
+    switch (what) {
+        case LM_EXPORT_RECORDS_F32: {
+            std::vector<float> rf;
+            std::vector<int32_t> rd;
+            LM_HIP(fetch(rf, c->recf.p, 3 * R, s));
+            LM_HIP(fetch(rd, c->rad.p, R, s));
+            float* o = (float*)host_dst;
+            for (int64_t r = 0; r < R; ++r) {
+                o[4 * r] = rf[r];
+                o[4 * r + 1] = rf[R + r];
+                o[4 * r + 2] = rf[2 * R + r];
+                o[4 * r + 3] = (float)rd[r];
+            }
+            return LM_OK;
+        }
+        case LM_EXPORT_SORTED_VALUES:
+            if (c->n_keys) {
+                LM_HIP(hipMemcpyAsync(host_dst, c->sorted_vals(), bytes, hipMemcpyDeviceToHost, s));
+                LM_HIP(hipStreamSynchronize(s));
+            }
+            return LM_OK;
+        case LM_EXPORT_TILE_RANGES:
+            LM_HIP(hipMemcpyAsync(host_dst, c->tile_start.p, bytes, hipMemcpyDeviceToHost, s));
+            LM_HIP(hipStreamSynchronize(s));
+            return LM_OK;
+        case LM_EXPORT_IMAGE: {
+            // rendered colour = residual + target is not stored; the float64
+            // colour per pixel is, in [3][n_pix] order
+            std::vector<double> pc;
+            LM_HIP(fetch(pc, c->pixC.p, 3 * c->n_pix, s));
+            float* o = (float*)host_dst;
+            for (int v = 0; v < c->V; ++v) {
+                const lm::CamDev& cam = c->cams_h[v];
+                const int64_t HW = (int64_t)cam.W * cam.H;
+                for (int ch = 0; ch < 3; ++ch)
+                    for (int64_t i = 0; i < HW; ++i)
+                        o[3 * cam.pix_base + ch * HW + i] = (float)pc[ch * c->n_pix + cam.pix_base + i];
+            }
+            return LM_OK;
+        }
+        case LM_EXPORT_NCONTRIB:
+            LM_HIP(hipMemcpyAsync(host_dst, c->ncontrib.p, bytes, hipMemcpyDeviceToHost, s));
+            LM_HIP(hipStreamSynchronize(s));
+            return LM_OK;
+        case LM_EXPORT_RESIDUAL:
+            LM_HIP(hipMemcpyAsync(host_dst, c->resid.p, bytes, hipMemcpyDeviceToHost, s));
+            LM_HIP(hipStreamSynchronize(s));
+            return LM_OK;
+        case LM_EXPORT_PAIR_T:
+        case LM_EXPORT_PAIR_FLAGS: {
+            const size_t wb = lm::dtype_bytes(c->dtype);
+            std::vector<uint8_t> raw;
+            LM_HIP(fetch(raw, c->pT.p, (int64_t)wb * c->n_pairs, s));
+            for (int64_t i = 0; i < c->n_pairs; ++i) {
+                uint32_t fl = 0;
+                const float v = decode_word(raw.data(), c->dtype, i, &fl);
+                if (what == LM_EXPORT_PAIR_T) ((float*)host_dst)[i] = v;
+                else ((int32_t*)host_dst)[i] = (int32_t)fl;
+            }
+            return LM_OK;
+        }
+        case LM_EXPORT_PAIR_D: {
+            const size_t wb = lm::dtype_bytes(c->dtype);
+            std::vector<uint8_t> raw;
+            LM_HIP(fetch(raw, c->pD.p, (int64_t)wb * 3 * c->pair_stride, s));
+            for (int ch = 0; ch < 3; ++ch)
+                for (int64_t i = 0; i < c->n_pairs; ++i)
+                    ((float*)host_dst)[ch * c->n_pairs + i] =
+                        decode_word(raw.data(), c->dtype, ch * c->pair_stride + i, nullptr);
+            return LM_OK;
+        }
+        case LM_EXPORT_PAIR_PIX:
+        case LM_EXPORT_PAIR_GAUSS: {
+            std::vector<uint64_t> tpo, tso;
+            std::vector<uint32_t> sloc, sgv, gvrec;
+            std::vector<uint8_t> pix;
+            LM_HIP(fetch(tpo, c->tile_pair_off.p, c->n_tiles + 1, s));
+            LM_HIP(fetch(tso, c->tile_seg_off.p, c->n_tiles + 1, s));
+            LM_HIP(fetch(sloc, c->seg_loc.p, c->n_seg, s));
+            LM_HIP(fetch(sgv, c->seg_gv.p, c->n_seg, s));
+            LM_HIP(fetch(gvrec, c->gv_rec.p, c->n_gv, s));
+            LM_HIP(fetch(pix, c->ppix.p, c->n_pairs, s));
+            int32_t* o = (int32_t*)host_dst;
+            int64_t t = 0;
+            std::vector<int32_t> tview;
+            for (int v = 0; v < c->V; ++v) {
+                const lm::CamDev& cam = c->cams_h[v];
+                tview.insert(tview.end(), (size_t)cam.TX * cam.TY, v);
+            }
+            for (t = 0; t < c->n_tiles; ++t) {
+                const lm::CamDev& cam = c->cams_h[tview[t]];
+                const int64_t lt = t - cam.tile_base;
+                const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
+                for (uint64_t sI = tso[t]; sI < tso[t + 1]; ++sI) {
+                    const uint64_t q0 = tpo[t] + sloc[sI];
+                    const uint64_t q1 = sI + 1 < tso[t + 1] ? tpo[t] + sloc[sI + 1] : tpo[t + 1];
+                    const int32_t gid = (int32_t)(gvrec[sgv[sI]] % (uint64_t)c->N);
+                    for (uint64_t q = q0; q < q1; ++q) {
+                        if (what == LM_EXPORT_PAIR_GAUSS) {
+                            o[q] = gid;
+                        } else {
+                            const int pl = pix[q];
+                            const int px = tx * c->TW + pl % c->TW, py = ty * c->TH + pl / c->TW;
+                            o[q] = (int32_t)(cam.pix_base + (int64_t)py * cam.W + px);
+                        }
+                    }
+                }
+            }
+            return LM_OK;
+        }
+        default:
+            break;
+    }
+    lm::set_error("lm_cache_export: unknown array");
+    return LM_ERR_INVALID_ARG;
+}

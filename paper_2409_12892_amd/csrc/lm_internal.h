@@ -1,0 +1,237 @@
+// Internal definitions shared by the HIP translation units of liblm3dgs.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lm3dgs.h"
+
+namespace lm {
+
+constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
+constexpr int kWave = 64;
+constexpr int kMaxTilePix = 256;   // pixels per tile (pixel-in-tile index is one byte)
+constexpr int kMaxViews = 4096;
+
+// Blending constants (paper section 3.1 defers them to the original 3DGS
+// rasteriser): alpha threshold, alpha clamp, transmittance cut-off, near
+// plane, screen-space dilation.
+constexpr double kAlphaMin = 1.0 / 255.0;
+constexpr double kAlphaMax = 0.99;
+constexpr double kTMin = 1e-4;
+constexpr double kNear = 0.2;
+constexpr double kDilation = 0.3;
+
+// Flag bits stored in the cached transmittance word (T in [1e-4, 1], so the
+// sign bit and the top exponent bit of its float32/bf16/fp16 encoding are
+// always zero and carry per-pair flags instead).
+constexpr uint32_t kHeadBit32 = 0x80000000u, kClampBit32 = 0x40000000u;
+constexpr uint16_t kHeadBit16 = 0x8000u, kClampBit16 = 0x4000u;
+
+// Camera in float64 plus its place in the subset's pixel and tile arrays.
+struct CamDev {
+    double R[9];
+    double t[3];
+    double fx, fy, cx, cy;
+    double C[3];          // camera centre in world coordinates, -R^T t
+    int32_t W, H, TX, TY;
+    int64_t tile_base;    // first global tile index of this view
+    int64_t pix_base;     // first global pixel index (v-major, then row, column)
+};
+
+// Everything a kernel needs to read the cache of one subset.
+struct CacheView {
+    int64_t N;
+    int32_t P, deg, V, TW, TH, dtype;
+    int64_t n_tiles, n_pix, n_seg, n_gv;
+    const CamDev* cams;          // dev [V]
+    const int32_t* tile_view;    // dev [n_tiles] view of each tile
+    const int64_t* tile_pair_off;// dev [n_tiles+1]
+    const int64_t* tile_seg_off; // dev [n_tiles+1]
+    const void* pT;              // dev [n_pairs] cache words (float or 16-bit)
+    const void* pD;              // dev [3][pair_stride]
+    const uint8_t* ppix;         // dev [n_pairs] pixel-in-tile index
+    int64_t n_pairs;
+    int64_t pair_stride;         // plane stride of pT/pD/ppix (>= n_pairs + 8, multiple of 8)
+    const uint32_t* seg_gv;      // dev [n_seg] active (Gaussian, view) index
+    const uint32_t* seg_loc;     // dev [n_seg] first pair, relative to the tile
+    const float* seg_f;          // dev [6][seg_stride]: mean-in-tile x, y, A, B, C, opacity
+    int64_t seg_stride;
+    const uint32_t* gv_rec;      // dev [n_gv] record index v*N + g
+    const uint32_t* gv_first;    // dev [N+1] first gv of each Gaussian
+    const uint32_t* gv_seg_off;  // dev [n_gv+1]
+    const uint32_t* gv_segs;     // dev [n_seg] segment ids grouped by gv, ascending
+};
+
+// Thread-local error message plumbing.
+void set_error(const std::string& msg);
+#define LM_HIP(call)                                                                   \
+    do {                                                                               \
+        hipError_t e_ = (call);                                                        \
+        if (e_ != hipSuccess) {                                                        \
+            ::lm::set_error(std::string(#call) + ": " + hipGetErrorString(e_));       \
+            return LM_ERR_HIP;                                                         \
+        }                                                                              \
+    } while (0)
+
+inline unsigned grid_for(int64_t n, int block = kBlock) {
+    int64_t g = (n + block - 1) / block;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---- cache element storage -------------------------------------------------
+__device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
+    uint32_t u = __float_as_uint(f);
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7FFFu + lsb;
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
+__device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
+    _Float16 h = (_Float16)f;   // round-to-nearest-even conversion
+    return __builtin_bit_cast(uint16_t, h);
+}
+__device__ __forceinline__ float f16_to_f32(uint16_t h) { return (float)__builtin_bit_cast(_Float16, h); }
+
+// Encode / decode one cached value for storage type DT.
+template <int DT> struct Store;
+template <> struct Store<LM_CACHE_F32> {
+    using word = uint32_t;
+    __device__ static word enc(float v) { return __float_as_uint(v); }
+    __device__ static float dec(word w) { return __uint_as_float(w); }
+    __device__ static word enc_T(float T, bool head, bool clamp) {
+        return __float_as_uint(T) | (head ? kHeadBit32 : 0u) | (clamp ? kClampBit32 : 0u);
+    }
+    __device__ static float dec_T(word w) { return __uint_as_float(w & 0x3FFFFFFFu); }
+    __device__ static bool head(word w) { return (w & kHeadBit32) != 0; }
+    __device__ static bool clamp(word w) { return (w & kClampBit32) != 0; }
+};
+template <> struct Store<LM_CACHE_BF16> {
+    using word = uint16_t;
+    __device__ static word enc(float v) { return f32_to_bf16_rne(v); }
+    __device__ static float dec(word w) { return bf16_to_f32(w); }
+    __device__ static word enc_T(float T, bool head, bool clamp) {
+        return (word)(f32_to_bf16_rne(T) | (head ? kHeadBit16 : 0) | (clamp ? kClampBit16 : 0));
+    }
+    __device__ static float dec_T(word w) { return bf16_to_f32((uint16_t)(w & 0x3FFFu)); }
+    __device__ static bool head(word w) { return (w & kHeadBit16) != 0; }
+    __device__ static bool clamp(word w) { return (w & kClampBit16) != 0; }
+};
+template <> struct Store<LM_CACHE_F16> {
+    using word = uint16_t;
+    __device__ static word enc(float v) { return f32_to_f16_rne(v); }
+    __device__ static float dec(word w) { return f16_to_f32(w); }
+    __device__ static word enc_T(float T, bool head, bool clamp) {
+        return (word)(f32_to_f16_rne(T) | (head ? kHeadBit16 : 0) | (clamp ? kClampBit16 : 0));
+    }
+    __device__ static float dec_T(word w) { return f16_to_f32((uint16_t)(w & 0x3FFFu)); }
+    __device__ static bool head(word w) { return (w & kHeadBit16) != 0; }
+    __device__ static bool clamp(word w) { return (w & kClampBit16) != 0; }
+};
+
+inline size_t dtype_bytes(int dt) { return dt == LM_CACHE_F32 ? 4 : 2; }
+
+// ---- launchers implemented in the .hip files --------------------------------
+// scan.hip
+hipError_t exclusive_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* tmp,
+                                     size_t tmp_bytes, hipStream_t s);   // out has n+1 entries
+size_t scan_tmp_bytes(int64_t n);
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                            int64_t n, int begin_bit, int end_bit, void* tmp, size_t tmp_bytes,
+                            bool* result_in_alt, hipStream_t s);
+size_t radix_tmp_bytes(int64_t n);
+hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s);
+
+
+// Arguments of the raster passes (raster.hip).
+struct RasterArgs {
+    const CamDev* cams;
+    const int32_t* tile_view;
+    const int64_t* tile_start;
+    const uint32_t* vals;
+    const double* rec64;       // [10][V*N]
+    int64_t N;
+    int32_t V, TW, TH;
+    // count pass
+    const float* target;       // [V][3][H][W] or nullptr (render only)
+    uint32_t* entry_cnt;       // [K]
+    double* pixC;              // [3][n_pix]
+    int32_t* ncontrib;         // [n_pix]
+    float* resid;              // image layout
+    double* fsq_part;          // [n_tiles]
+    uint32_t* tile_pairs;      // [n_tiles]
+    uint32_t* tile_segs;       // [n_tiles]
+    uint32_t* gv_cnt;          // [N*V] segments per (g, v), index g*V + v
+    int64_t n_pix;
+    // fill pass
+    const int64_t* tile_pair_off;
+    const int64_t* tile_seg_off;
+    const uint64_t* gv_idx;    // [N*V+1] exclusive scan of (gv_cnt > 0)
+    const uint64_t* gv_segoff; // [N*V+1] exclusive scan of gv_cnt
+    uint32_t* gv_cursor;       // [n_gv]
+    uint32_t* gv_segs;         // [n_seg]
+    void* pT;
+    void* pD;                  // [3][pair_stride]
+    int64_t pair_stride;
+    uint8_t* ppix;
+    uint32_t* seg_gv;
+    uint32_t* seg_loc;
+    float* seg_f;              // [6][seg_stride]
+    int64_t seg_stride;
+};
+
+// Arguments of the product kernels (apply.hip).
+struct ApplyArgs {
+    CacheView c;
+    const float* x;          // [P][N] parameters the cache was built at
+    const float* p;          // [P][N] direction (J modes)
+    const float* uin;        // image layout (J^T only)
+    float* uout;             // image layout (J only)
+    float* dyc;              // [n_gv][9] power coefficients of J_y p
+    float* gmom;             // [n_seg][9] moments of J^T u per segment
+    double* jp_part;         // [n_tiles] ||J p||^2 per tile
+    const int32_t* stop;     // optional device flag: skip when non-zero
+};
+
+// Device-resident PCG scalars of one subset (pcg.hip).
+struct PcgState {
+    double rz, rr, bb, pg, alpha, beta;
+    int32_t stop, iters, status, pad;
+    double hist[LM_PCG_MAX_HISTORY];
+};
+
+// project_bin.hip
+hipError_t launch_project(const CamDev* cams, const float* x, int64_t N, int V, int deg, int TW, int TH,
+                          double* rec64, float* recf, int32_t* rad, uint32_t* keycnt, hipStream_t s);
+hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int V, int TW, int TH, const float* recf,
+                           const int32_t* rad, const uint32_t* keycnt, const uint64_t* keyoff, uint64_t* keys,
+                           uint32_t* vals, hipStream_t s);
+hipError_t launch_tile_ranges(const uint64_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
+                              hipStream_t s);
+// raster.hip
+hipError_t launch_raster(bool fill, int dtype, int64_t n_tiles, const RasterArgs& a, hipStream_t s);
+hipError_t launch_flag_nonzero(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s);
+hipError_t launch_gv_compact(const uint32_t* gv_cnt, const uint64_t* gv_idx, const uint64_t* gv_segoff, int64_t N,
+                             int V, uint32_t* gv_rec, uint32_t* gv_seg_off, uint32_t* gv_first, hipStream_t s);
+hipError_t launch_gv_sort(const uint32_t* gv_seg_off, int64_t n_gv, uint32_t* gv_segs, hipStream_t s);
+// apply.hip (mode 1 = J, 2 = J^T, 3 = fused J^T J)
+hipError_t launch_tangent(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s);
+hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float* out, double* pg_part,
+                        hipStream_t s);
+unsigned chain_blocks(int64_t N);
+hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, float* M, hipStream_t s);
+// pcg.hip
+int64_t pcg_partial_count(int64_t n);
+hipError_t pcg_init(int64_t n, const float* b, const float* M, const float* scale, float* x, hipStream_t s);
+hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, const float* scale, float* r,
+                      float* z, float* p, double* part, PcgState* st, hipStream_t s);
+hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_t s);
+hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, const float* scale,
+                      float* x, float* r, float* z, double* part, double tol, int tol_mode, hipStream_t s);
+hipError_t launch_combine(int n_b, const float* const* d, const float* const* m, int64_t n, float* out,
+                          hipStream_t s);
+
+}  // namespace lm

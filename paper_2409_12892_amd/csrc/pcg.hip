@@ -1,0 +1,228 @@
+// Vector half of Algorithm 1 (PCG) with float64 dot products and scalars
+// kept on the device, and the subset combination (eq. combine-pcg).
+//
+// Every kernel of an iteration reads the device `stop` flag first and
+// returns when it is set, so the host enqueues n_iters iterations without
+// synchronising and the loop still ends where Algorithm 1 breaks.
+#include "lm_internal.h"
+
+namespace lm {
+
+
+
+namespace {
+
+constexpr int kVecBlocks = 2048;   // fixed grid: partial sums in a fixed order
+
+__device__ __forceinline__ float jacobi_inv(float M, const float* scale, int64_t i) {
+    if (!(M > 0.0f)) return 0.0f;
+    const float s = scale ? scale[i] : 1.0f;
+    return s / M;
+}
+
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* part, int64_t stride) {
+    __shared__ double sh[NV][kBlock / kWave];
+    const int lane = __lane_id(), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double x = v[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) x += __shfl_xor(x, off, kWave);
+        if (lane == 0) sh[k][wid] = x;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = 0.0;
+            for (int w = 0; w < kBlock / kWave; ++w) s += sh[k][w];
+            part[k * stride + blockIdx.x] = s;
+        }
+    }
+}
+
+__device__ double block_sum(const double* part, int64_t n) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) acc += part[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    const double r = sh[0];
+    __syncthreads();
+    return r;
+}
+
+// x0 = M^-1 b
+__global__ void k_init_x(int64_t n, const float* __restrict__ b, const float* __restrict__ M,
+                         const float* __restrict__ scale, float* __restrict__ x) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = jacobi_inv(M[i], scale, i) * b[i];
+}
+
+// r0 = b - g, z0 = M^-1 r0, p0 = z0; partials of r.z, r.r, b.b
+__global__ void k_init_r(int64_t n, const float* __restrict__ b, const float* __restrict__ g,
+                         const float* __restrict__ M, const float* __restrict__ scale, float* __restrict__ r,
+                         float* __restrict__ z, float* __restrict__ p, double* __restrict__ part) {
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        const float ri = b[i] - g[i];
+        const float zi = jacobi_inv(M[i], scale, i) * ri;
+        r[i] = ri;
+        z[i] = zi;
+        p[i] = zi;
+        acc[0] += (double)ri * zi;
+        acc[1] += (double)ri * ri;
+        acc[2] += (double)b[i] * b[i];
+    }
+    block_partials<3>(acc, part, gridDim.x);
+}
+
+__global__ void k_init_scalars(const double* __restrict__ part, int64_t nb, PcgState* st) {
+    const double rz = block_sum(part, nb);
+    const double rr = block_sum(part + nb, nb);
+    const double bb = block_sum(part + 2 * nb, nb);
+    if (threadIdx.x == 0) {
+        st->rz = rz;
+        st->rr = rr;
+        st->bb = bb;
+        st->iters = 0;
+        st->status = 0;
+        st->stop = 0;
+        st->hist[0] = bb > 0.0 ? rr / bb : 0.0;
+    }
+}
+
+// alpha = r.z / p.g, with a breakdown stop when p.g is not positive and finite
+__global__ void k_alpha(const double* __restrict__ pg_part, int64_t nb, PcgState* st) {
+    if (st->stop) return;
+    const double pg = block_sum(pg_part, nb);
+    if (threadIdx.x == 0) {
+        st->pg = pg;
+        if (!(pg > 0.0) || !isfinite(pg)) {
+            st->stop = 1;
+            st->status = LM_WARN_BREAKDOWN;
+        } else {
+            st->alpha = st->rz / pg;
+        }
+    }
+}
+
+// x += alpha p, r -= alpha g, z = M^-1 r; partials of r.z and r.r
+__global__ void k_update_xrz(int64_t n, const PcgState* __restrict__ st, const float* __restrict__ p,
+                             const float* __restrict__ g, const float* __restrict__ M,
+                             const float* __restrict__ scale, float* __restrict__ x, float* __restrict__ r,
+                             float* __restrict__ z, double* __restrict__ part) {
+    if (st->stop) return;
+    const float alpha = (float)st->alpha;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        x[i] = x[i] + alpha * p[i];
+        const float ri = r[i] - alpha * g[i];
+        const float zi = jacobi_inv(M[i], scale, i) * ri;
+        r[i] = ri;
+        z[i] = zi;
+        acc[0] += (double)ri * zi;
+        acc[1] += (double)ri * ri;
+    }
+    block_partials<2>(acc, part, gridDim.x);
+}
+
+// beta = r_new.z_new / r.z; history; stopping rule of Algorithm 1
+__global__ void k_beta(const double* __restrict__ part, int64_t nb, PcgState* st, double tol, int tol_mode) {
+    if (st->stop) return;
+    const double rz_new = block_sum(part, nb);
+    const double rr = block_sum(part + nb, nb);
+    if (threadIdx.x == 0) {
+        st->beta = st->rz != 0.0 ? rz_new / st->rz : 0.0;
+        st->rz = rz_new;
+        st->rr = rr;
+        const int it = st->iters + 1;
+        st->iters = it;
+        if (it < LM_PCG_MAX_HISTORY) st->hist[it] = st->bb > 0.0 ? rr / st->bb : 0.0;
+        if (tol_mode == LM_TOL_PAPER_SQUARED && rr < tol * st->bb) st->stop = 1;
+        if (tol_mode == LM_TOL_RELATIVE && sqrt(rr) < tol * sqrt(st->bb)) st->stop = 1;
+    }
+}
+
+// p = z + beta p
+__global__ void k_update_p(int64_t n, const PcgState* __restrict__ st, const float* __restrict__ z,
+                           float* __restrict__ p) {
+    if (st->stop) return;
+    const float beta = (float)st->beta;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = z[i] + beta * p[i];
+}
+
+struct CombineArgs {
+    const float* d[16];
+    const float* m[16];
+    int nb;
+};
+
+__global__ void k_combine(CombineArgs a, int64_t n, float* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+        double num = 0.0, den = 0.0;
+        for (int k = 0; k < a.nb; ++k) {
+            const double w = a.m[k][i];
+            num += w * (double)a.d[k][i];
+            den += w;
+        }
+        out[i] = den > 0.0 ? (float)(num / den) : 0.0f;
+    }
+}
+
+unsigned vec_grid(int64_t n) {
+    int64_t g = (n + kBlock - 1) / kBlock;
+    if (g > kVecBlocks) g = kVecBlocks;
+    return (unsigned)(g < 1 ? 1 : g);
+}
+
+}  // namespace
+
+int64_t pcg_partial_count(int64_t n) { return vec_grid(n); }
+
+hipError_t pcg_init(int64_t n, const float* b, const float* M, const float* scale, float* x, hipStream_t s) {
+    hipLaunchKernelGGL(k_init_x, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, b, M, scale, x);
+    return hipGetLastError();
+}
+
+hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, const float* scale, float* r,
+                      float* z, float* p, double* part, PcgState* st, hipStream_t s) {
+    const unsigned nb = vec_grid(n);
+    hipLaunchKernelGGL(k_init_r, dim3(nb), dim3(kBlock), 0, s, n, b, g, M, scale, r, z, p, part);
+    hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, part, (int64_t)nb, st);
+    return hipGetLastError();
+}
+
+hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_t s) {
+    hipLaunchKernelGGL(k_alpha, dim3(1), dim3(kBlock), 0, s, pg_part, nb, st);
+    return hipGetLastError();
+}
+
+hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, const float* scale,
+                      float* x, float* r, float* z, double* part, double tol, int tol_mode, hipStream_t s) {
+    const unsigned nb = vec_grid(n);
+    hipLaunchKernelGGL(k_update_xrz, dim3(nb), dim3(kBlock), 0, s, n, st, p, g, M, scale, x, r, z, part);
+    hipLaunchKernelGGL(k_beta, dim3(1), dim3(kBlock), 0, s, part, (int64_t)nb, st, tol, tol_mode);
+    hipLaunchKernelGGL(k_update_p, dim3(nb), dim3(kBlock), 0, s, n, st, z, p);
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(int n_b, const float* const* d, const float* const* m, int64_t n, float* out,
+                          hipStream_t s) {
+    CombineArgs a{};
+    a.nb = n_b;
+    for (int i = 0; i < n_b; ++i) {
+        a.d[i] = d[i];
+        a.m[i] = m[i];
+    }
+    hipLaunchKernelGGL(k_combine, dim3(vec_grid(n)), dim3(kBlock), 0, s, a, n, out);
+    return hipGetLastError();
+}
+
+}  // namespace lm

@@ -1,0 +1,334 @@
+// Forward rasterisation and gradient-cache construction (Algorithm 1,
+// buildCache; section 3.3 "Cache-driven parallelization").
+//
+// One workgroup per tile, one thread per pixel.  Each batch of up to 256
+// entries of the tile's depth-sorted list is staged in LDS (float64 splat
+// data) and every pixel walks it front to back (eq. alpha-blending):
+//     power = -0.5 (A dx^2 + C dy^2) - B dx dy   (skip if > 0)
+//     alpha = min(0.99, o exp(power))            (skip if < 1/255)
+//     stop (without this splat) if T (1 - alpha) < 1e-4
+//     C += c alpha T,  T *= 1 - alpha.
+// Blending state and every decision are float64, so the contributing set is
+// the float64 one.
+//
+// Two passes walk identically:
+//   count: per entry, contributing pixels per wave (packed 4 x u8); per pixel
+//          the rendered colour (float64), residual and contributor count;
+//          per tile the number of pairs and of active splats (segments).
+//   fill:  writes the cache in its final layout - per tile, active splats in
+//          depth order (segments), each segment's pairs in pixel order:
+//          T (with head/clamp flag bits), dC/dalpha (3 planes), pixel byte -
+//          plus the per-segment splat data and the (Gaussian,view) links.
+// dC_ch/dalpha = T c_ch - S_ch/(1 - alpha) with S_ch the colour blended by
+// later splats, S_ch = C_ch(final) - (colour blended up to and including
+// this splat), all in float64.
+#include "lm_internal.h"
+
+namespace lm {
+namespace {
+
+constexpr int NW = kBlock / kWave;
+
+
+
+__device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+
+template <bool FILL, int DT>
+__global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
+    using S = Store<DT>;
+    __shared__ double s_rec[10][kBlock];
+    __shared__ uint32_t s_g[kBlock];
+    __shared__ uint8_t s_wc[kBlock][NW];       // count pass: contributing pixels per wave
+    __shared__ uint32_t s_eoff[kBlock];        // fill pass: entry pair offset in tile
+    __shared__ uint32_t s_wpre[kBlock];        // fill pass: packed per-wave prefixes
+    __shared__ uint32_t s_run[2];              // running pairs, running segments
+    __shared__ double s_red[kBlock / kWave];
+    __shared__ uint32_t s_scan[NW];
+
+    const int64_t t = blockIdx.x;
+    const int v = a.tile_view[t];
+    const CamDev& cam = a.cams[v];
+    const int64_t lt = t - cam.tile_base;
+    const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
+    const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
+    const int lx = tid % a.TW, ly = tid / a.TW;
+    const int px = tx * a.TW + lx, py = ty * a.TH + ly;
+    const bool valid = tid < a.TW * a.TH && px < cam.W && py < cam.H;
+    const double pxc = px + 0.5, pyc = py + 0.5;
+    const int64_t pg = cam.pix_base + (int64_t)py * cam.W + px;   // global pixel index
+    const int64_t HW = (int64_t)cam.W * cam.H;
+    const int64_t R = a.N * (int64_t)a.V;
+
+    double T = 1.0, acc0 = 0.0, acc1 = 0.0, acc2 = 0.0;
+    double Ch0 = 0.0, Ch1 = 0.0, Ch2 = 0.0;
+    int cnt = 0;
+    bool done = !valid;
+    if (FILL && valid) {
+        Ch0 = a.pixC[pg];
+        Ch1 = a.pixC[a.n_pix + pg];
+        Ch2 = a.pixC[2 * a.n_pix + pg];
+    }
+    if (tid < 2) s_run[tid] = 0;
+    int64_t pair_base = 0, seg_base = 0, pair_end = 0, seg_end = 0;
+    if (FILL) {
+        pair_base = a.tile_pair_off[t];
+        seg_base = a.tile_seg_off[t];
+        pair_end = a.tile_pair_off[t + 1];
+        seg_end = a.tile_seg_off[t + 1];
+    }
+    const int64_t ks = a.tile_start[t], ke = a.tile_start[t + 1];
+    const double lmargin = 1e-9;
+
+    for (int64_t b0 = ks; b0 < ke; b0 += kBlock) {
+        if (__syncthreads_and(done ? 1 : 0)) break;
+        const int nb = (int)(ke - b0 < kBlock ? ke - b0 : kBlock);
+        if (tid < nb) {
+            const uint32_t gi = a.vals[b0 + tid];
+            const int64_t r = (int64_t)v * a.N + gi;
+            s_g[tid] = gi;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[(int64_t)i * R + r];
+        }
+        if (FILL) {
+            // per-entry totals, block-wide exclusive scan of (pairs, active) and
+            // segment records for the active entries
+            uint32_t c = tid < nb ? a.entry_cnt[b0 + tid] : 0u;
+            uint32_t tot = (c & 0xFF) + ((c >> 8) & 0xFF) + ((c >> 16) & 0xFF) + (c >> 24);
+            uint32_t packed = (tot << 10) | (tot > 0 ? 1u : 0u);
+            // wave inclusive scan
+            uint32_t inc = packed;
+#pragma unroll
+            for (int off = 1; off < kWave; off <<= 1) {
+                uint32_t o = __shfl_up(inc, off, kWave);
+                if (lane >= off) inc += o;
+            }
+            if (lane == kWave - 1) s_scan[wid] = inc;
+            __syncthreads();
+            uint32_t wbase = 0, btot = 0;
+#pragma unroll
+            for (int w = 0; w < NW; ++w) {
+                if (w < wid) wbase += s_scan[w];
+                btot += s_scan[w];
+            }
+            const uint32_t ex = wbase + inc - packed;
+            const uint32_t run_p = s_run[0], run_s = s_run[1];
+            const uint32_t eoff = run_p + (ex >> 10);
+            const uint32_t eseg = run_s + (ex & 0x3FF);
+            if (tid < nb) {
+                s_eoff[tid] = eoff;
+                s_wpre[tid] = ((c & 0xFF) << 8) | ((((c & 0xFF) + ((c >> 8) & 0xFF))) << 16) |
+                              ((((c & 0xFF) + ((c >> 8) & 0xFF) + ((c >> 16) & 0xFF))) << 24);
+                // note: prefix of wave 0 is 0; the packed bytes hold waves 1..3 (each <= 192 fits a byte)
+                if (tot > 0 && seg_base + eseg < seg_end) {
+                    const int64_t s = seg_base + eseg;
+                    const uint32_t gi = s_g[tid];
+                    const int64_t gvkey = (int64_t)gi * a.V + v;
+                    const uint32_t gv = (uint32_t)a.gv_idx[gvkey];
+                    a.seg_gv[s] = gv;
+                    a.seg_loc[s] = eoff;
+                    a.seg_f[0 * a.seg_stride + s] = (float)(s_rec[0][tid] - (double)(tx * a.TW));
+                    a.seg_f[1 * a.seg_stride + s] = (float)(s_rec[1][tid] - (double)(ty * a.TH));
+                    a.seg_f[2 * a.seg_stride + s] = (float)s_rec[2][tid];
+                    a.seg_f[3 * a.seg_stride + s] = (float)s_rec[3][tid];
+                    a.seg_f[4 * a.seg_stride + s] = (float)s_rec[4][tid];
+                    a.seg_f[5 * a.seg_stride + s] = (float)s_rec[5][tid];
+                    const uint32_t slot = atomicAdd(&a.gv_cursor[gv], 1u);
+                    if (a.gv_segoff[gvkey] + slot < a.gv_segoff[gvkey + 1]) a.gv_segs[a.gv_segoff[gvkey] + slot] = (uint32_t)s;
+                }
+            }
+            __syncthreads();
+            if (tid == 0) {
+                s_run[0] = run_p + (btot >> 10);
+                s_run[1] = run_s + (btot & 0x3FF);
+            }
+        }
+        __syncthreads();
+
+        for (int j = 0; j < nb; ++j) {
+            bool contrib = false;
+            double alpha = 0.0, a_raw = 0.0, Tn = T;
+            if (!done) {
+                const double dx = pxc - s_rec[0][j], dy = pyc - s_rec[1][j];
+                const double A = s_rec[2][j], B = s_rec[3][j], C = s_rec[4][j];
+                const double power = -0.5 * (A * dx * dx + C * dy * dy) - B * dx * dy;
+                if (power <= 0.0 && power >= s_rec[6][j] - lmargin) {
+                    a_raw = s_rec[5][j] * exp(power);
+                    alpha = a_raw < kAlphaMax ? a_raw : kAlphaMax;
+                    if (alpha >= kAlphaMin) {
+                        Tn = T * (1.0 - alpha);
+                        if (Tn < kTMin) done = true;
+                        else contrib = true;
+                    }
+                }
+            }
+            const uint64_t bal = __ballot(contrib);
+            if (!FILL) {
+                if (lane == 0) s_wc[j][wid] = (uint8_t)__popcll(bal);
+            }
+            if (contrib) {
+                const double w = alpha * T;
+                const double c0 = s_rec[7][j], c1 = s_rec[8][j], c2 = s_rec[9][j];
+                acc0 += c0 * w;
+                acc1 += c1 * w;
+                acc2 += c2 * w;
+                if (FILL) {
+                    const uint32_t rank = (uint32_t)__popcll(bal & lanemask_lt());
+                    const uint32_t wp = wid == 0 ? 0u : ((s_wpre[j] >> (8 * wid)) & 0xFFu);
+                    const uint32_t within = wp + rank;
+                    const int64_t slot = pair_base + s_eoff[j] + within;
+                    if (slot < pair_end) {   // always true when both passes agree
+                        const double inv = 1.0 / (1.0 - alpha);
+                        const float D0 = (float)(T * c0 - (Ch0 - acc0) * inv);
+                        const float D1 = (float)(T * c1 - (Ch1 - acc1) * inv);
+                        const float D2 = (float)(T * c2 - (Ch2 - acc2) * inv);
+                        typename S::word* pT = (typename S::word*)a.pT;
+                        typename S::word* pD = (typename S::word*)a.pD;
+                        pT[slot] = S::enc_T((float)T, within == 0, a_raw > kAlphaMax);
+                        pD[slot] = S::enc(D0);
+                        pD[a.pair_stride + slot] = S::enc(D1);
+                        pD[2 * a.pair_stride + slot] = S::enc(D2);
+                        a.ppix[slot] = (uint8_t)tid;
+                    }
+                }
+                T = Tn;
+                ++cnt;
+            }
+        }
+        __syncthreads();
+        if (!FILL) {
+            // per-entry counts, tile totals and the (Gaussian, view) segment counts
+            uint32_t tot = 0, packed = 0;
+            if (tid < nb) {
+                uint32_t c0 = s_wc[tid][0], c1 = s_wc[tid][1], c2 = s_wc[tid][2], c3 = s_wc[tid][3];
+                packed = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
+                tot = c0 + c1 + c2 + c3;
+                a.entry_cnt[b0 + tid] = packed;
+                if (tot > 0) atomicAdd(&a.gv_cnt[(int64_t)s_g[tid] * a.V + v], 1u);
+            }
+            // block reduction of (pairs, active entries)
+            uint32_t val = (tot << 10) | (tot > 0 ? 1u : 0u);
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) val += __shfl_xor(val, off, kWave);
+            if (lane == 0) s_scan[wid] = val;
+            __syncthreads();
+            if (tid == 0) {
+                uint32_t sum = 0;
+                for (int w = 0; w < NW; ++w) sum += s_scan[w];
+                s_run[0] += sum >> 10;
+                s_run[1] += sum & 0x3FF;
+            }
+            __syncthreads();
+        }
+    }
+    __syncthreads();
+    if (!FILL) {
+        double fsq = 0.0;
+        if (valid) {
+            a.pixC[pg] = acc0;
+            a.pixC[a.n_pix + pg] = acc1;
+            a.pixC[2 * a.n_pix + pg] = acc2;
+            a.ncontrib[pg] = cnt;
+            const int64_t ib = 3 * cam.pix_base + (int64_t)py * cam.W + px;
+            const double accs[3] = {acc0, acc1, acc2};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const double tgt = a.target ? (double)a.target[ib + ch * HW] : 0.0;
+                const double r = accs[ch] - tgt;
+                a.resid[ib + ch * HW] = (float)r;
+                fsq += r * r;
+            }
+        }
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) fsq += __shfl_xor(fsq, off, kWave);
+        if (lane == 0) s_red[wid] = fsq;
+        __syncthreads();
+        if (tid == 0) {
+            double s = 0.0;
+            for (int w = 0; w < NW; ++w) s += s_red[w];
+            a.fsq_part[t] = s;
+            a.tile_pairs[t] = s_run[0];
+            a.tile_segs[t] = s_run[1];
+        }
+    }
+}
+
+// gv compaction: for every (g, v) with segments, its record index and the
+// offset of its segment list; the first gv of each Gaussian.
+__global__ void k_gv_compact(const uint32_t* __restrict__ gv_cnt, const uint64_t* __restrict__ gv_idx,
+                             const uint64_t* __restrict__ gv_segoff, int64_t N, int V,
+                             uint32_t* __restrict__ gv_rec, uint32_t* __restrict__ gv_seg_off,
+                             uint32_t* __restrict__ gv_first) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t NV = N * (int64_t)V;
+    if (i > NV) return;
+    if (i == NV) {
+        gv_first[N] = (uint32_t)gv_idx[NV];
+        gv_seg_off[gv_idx[NV]] = (uint32_t)gv_segoff[NV];
+        return;
+    }
+    const int64_t g = i / V;
+    const int v = (int)(i - g * V);
+    if (v == 0) gv_first[g] = (uint32_t)gv_idx[i];
+    if (gv_cnt[i] > 0) {
+        const uint64_t k = gv_idx[i];
+        gv_rec[k] = (uint32_t)((int64_t)v * N + g);
+        gv_seg_off[k] = (uint32_t)gv_segoff[i];
+    }
+}
+
+__global__ void k_flag_nonzero(const uint32_t* __restrict__ in, int64_t n, uint32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) out[i] = in[i] > 0 ? 1u : 0u;
+}
+
+// Sort each gv's (short) segment list ascending so reductions run in a fixed order.
+__global__ void k_gv_sort(const uint32_t* __restrict__ gv_seg_off, int64_t n_gv, uint32_t* __restrict__ gv_segs) {
+    const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= n_gv) return;
+    const uint32_t b = gv_seg_off[k], e = gv_seg_off[k + 1];
+    for (uint32_t i = b + 1; i < e; ++i) {
+        const uint32_t key = gv_segs[i];
+        uint32_t j = i;
+        while (j > b && gv_segs[j - 1] > key) {
+            gv_segs[j] = gv_segs[j - 1];
+            --j;
+        }
+        gv_segs[j] = key;
+    }
+}
+
+}  // namespace
+
+hipError_t launch_raster(bool fill, int dtype, int64_t n_tiles, const RasterArgs& a, hipStream_t s) {
+    dim3 g((unsigned)n_tiles), b(kBlock);
+    if (!fill) {
+        hipLaunchKernelGGL((k_raster<false, LM_CACHE_F32>), g, b, 0, s, a);
+    } else if (dtype == LM_CACHE_F32) {
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F32>), g, b, 0, s, a);
+    } else if (dtype == LM_CACHE_BF16) {
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_BF16>), g, b, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F16>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_flag_nonzero(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_flag_nonzero, dim3(grid_for(n)), dim3(kBlock), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_gv_compact(const uint32_t* gv_cnt, const uint64_t* gv_idx, const uint64_t* gv_segoff, int64_t N,
+                             int V, uint32_t* gv_rec, uint32_t* gv_seg_off, uint32_t* gv_first, hipStream_t s) {
+    hipLaunchKernelGGL(k_gv_compact, dim3(grid_for(N * (int64_t)V + 1)), dim3(kBlock), 0, s, gv_cnt, gv_idx,
+                       gv_segoff, N, V, gv_rec, gv_seg_off, gv_first);
+    return hipGetLastError();
+}
+
+hipError_t launch_gv_sort(const uint32_t* gv_seg_off, int64_t n_gv, uint32_t* gv_segs, hipStream_t s) {
+    if (n_gv == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_gv_sort, dim3(grid_for(n_gv)), dim3(kBlock), 0, s, gv_seg_off, n_gv, gv_segs);
+    return hipGetLastError();
+}
+
+}  // namespace lm

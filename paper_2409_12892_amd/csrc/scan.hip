@@ -1,0 +1,251 @@
+// Device-wide exclusive scan, float64 reduction and a stable LSD radix sort
+// of (64-bit key, 32-bit value) pairs, written for wave64 / 256-thread
+// workgroups.  Used by tile binning (depth sort per tile), the cache build
+// (pair and segment offsets) and the PCG dot products.
+#include "lm_internal.h"
+
+namespace lm {
+namespace {
+
+constexpr int kScanItems = 16;                       // items per thread
+constexpr int kScanTile = kBlock * kScanItems;       // 4096 items per workgroup
+constexpr int kRadixItems = 16;
+constexpr int kRadixTile = kBlock * kRadixItems;
+
+__device__ __forceinline__ uint64_t lanemask_lt() {
+    return (1ull << __lane_id()) - 1ull;
+}
+
+// Inclusive wave scan (wave64) of a 64-bit value.
+__device__ __forceinline__ uint64_t wave_incl_scan(uint64_t v) {
+    const int lane = __lane_id();
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        uint64_t o = __shfl_up(v, off, kWave);
+        if (lane >= off) v += o;
+    }
+    return v;
+}
+
+// Exclusive scan across the 256 threads of a block; returns the exclusive
+// prefix of `v`, and the block total in *total (same for all threads).
+__device__ uint64_t block_excl_scan(uint64_t v, uint64_t* total) {
+    __shared__ uint64_t wsum[kBlock / kWave];
+    const int lane = __lane_id();
+    const int wid = threadIdx.x / kWave;
+    uint64_t inc = wave_incl_scan(v);
+    if (lane == kWave - 1) wsum[wid] = inc;
+    __syncthreads();
+    uint64_t base = 0, tot = 0;
+#pragma unroll
+    for (int w = 0; w < kBlock / kWave; ++w) {
+        uint64_t s = wsum[w];
+        if (w < wid) base += s;
+        tot += s;
+    }
+    __syncthreads();
+    *total = tot;
+    return base + inc - v;
+}
+
+__global__ void k_scan_tile_sums(const uint32_t* __restrict__ in, int64_t n, uint64_t* __restrict__ sums) {
+    const int64_t base = (int64_t)blockIdx.x * kScanTile;
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+        if (idx < n) acc += in[idx];
+    }
+    uint64_t tot;
+    block_excl_scan(acc, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+// Single-workgroup exclusive scan of the tile sums (any length).
+__global__ void k_scan_sums(uint64_t* __restrict__ sums, int64_t nb) {
+    const int64_t per = (nb + kBlock - 1) / kBlock;
+    const int64_t b0 = (int64_t)threadIdx.x * per;
+    uint64_t acc = 0;
+    for (int64_t i = 0; i < per; ++i) {
+        int64_t idx = b0 + i;
+        if (idx < nb) acc += sums[idx];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan(acc, &tot);
+    for (int64_t i = 0; i < per; ++i) {
+        int64_t idx = b0 + i;
+        if (idx < nb) {
+            uint64_t s = sums[idx];
+            sums[idx] = run;
+            run += s;
+        }
+    }
+    if (threadIdx.x == 0) sums[nb] = tot;
+}
+
+__global__ void k_scan_apply(const uint32_t* __restrict__ in, int64_t n, const uint64_t* __restrict__ sums,
+                             uint64_t* __restrict__ out, int64_t nb) {
+    // each thread scans kScanItems consecutive items (blocked arrangement)
+    const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+    uint32_t v[kScanItems];
+    uint64_t acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        v[i] = idx < n ? in[idx] : 0u;
+        acc += v[i];
+    }
+    uint64_t tot;
+    uint64_t run = block_excl_scan(acc, &tot) + sums[blockIdx.x];
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+        int64_t idx = base + i;
+        if (idx < n) out[idx] = run;
+        run += v[i];
+    }
+    if (blockIdx.x == nb - 1 && threadIdx.x == 0) out[n] = sums[nb];
+}
+
+__global__ void k_reduce_f64(const double* __restrict__ in, int64_t n, double* __restrict__ out) {
+    __shared__ double sh[kBlock];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) acc += in[i];
+    sh[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = kBlock / 2; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) sh[threadIdx.x] += sh[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *out = sh[0];
+}
+
+// ---- radix sort ---------------------------------------------------------------
+__global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, int64_t nb,
+                             uint32_t* __restrict__ hist) {
+    __shared__ uint32_t h[256];
+    h[threadIdx.x] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+#pragma unroll 4
+    for (int i = 0; i < kRadixItems; ++i) {
+        int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xFF], 1u);
+    }
+    __syncthreads();
+    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];   // digit-major
+}
+
+__global__ void k_radix_scatter(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+                                int64_t n, int shift, int64_t nb, const uint64_t* __restrict__ offs,
+                                uint64_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
+    constexpr int NW = kBlock / kWave;
+    __shared__ uint32_t wcnt[NW][256];
+    __shared__ uint64_t running[256];
+    const int tid = threadIdx.x;
+    const int wid = tid / kWave;
+    running[tid] = offs[(int64_t)tid * nb + blockIdx.x];
+    for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+    __syncthreads();
+    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    for (int r = 0; r < kRadixItems; ++r) {
+        const int64_t idx = base + (int64_t)r * kBlock + tid;
+        const bool live = idx < n;
+        uint64_t k = live ? keys[idx] : 0ull;
+        uint32_t v = live ? vals[idx] : 0u;
+        const uint32_t d = (uint32_t)((k >> shift) & 0xFF);
+        uint64_t peers = __ballot(live);
+#pragma unroll
+        for (int b = 0; b < 8; ++b) {
+            uint64_t m = __ballot((d >> b) & 1u);
+            peers &= ((d >> b) & 1u) ? m : ~m;
+        }
+        const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
+        if (live && rank == 0) wcnt[wid][d] = (uint32_t)__popcll(peers);
+        __syncthreads();
+        // thread `tid` owns digit `tid`: replace its per-wave counts by their
+        // exclusive prefix over the waves
+        uint32_t c[NW];
+        uint32_t tot = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) c[w] = wcnt[w][tid];
+#pragma unroll
+        for (int w = 0; w < NW; ++w) { wcnt[w][tid] = tot; tot += c[w]; }
+        __syncthreads();
+        if (live) {
+            uint64_t pos = running[d] + wcnt[wid][d] + rank;
+            okeys[pos] = k;
+            ovals[pos] = v;
+        }
+        __syncthreads();
+        running[tid] += tot;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+        __syncthreads();
+    }
+}
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) {
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    return (size_t)(nb + 1) * sizeof(uint64_t);
+}
+
+hipError_t exclusive_scan_u32_to_u64(const uint32_t* in, uint64_t* out, int64_t n, void* tmp,
+                                     size_t tmp_bytes, hipStream_t s) {
+    if (n <= 0) return hipMemsetAsync(out, 0, sizeof(uint64_t), s);
+    int64_t nb = (n + kScanTile - 1) / kScanTile;
+    if ((size_t)(nb + 1) * sizeof(uint64_t) > tmp_bytes) return hipErrorInvalidValue;
+    uint64_t* sums = (uint64_t*)tmp;
+    hipLaunchKernelGGL(k_scan_tile_sums, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, sums);
+    hipLaunchKernelGGL(k_scan_sums, dim3(1), dim3(kBlock), 0, s, sums, nb);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nb), dim3(kBlock), 0, s, in, n, sums, out, nb);
+    return hipGetLastError();
+}
+
+hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_reduce_f64, dim3(1), dim3(kBlock), 0, s, in, n, out);
+    return hipGetLastError();
+}
+
+size_t radix_tmp_bytes(int64_t n) {
+    int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    size_t hist = (size_t)256 * nb * sizeof(uint32_t);
+    size_t offs = (size_t)(256 * nb + 1) * sizeof(uint64_t);
+    size_t scan = scan_tmp_bytes(256 * nb);
+    return hist + offs + scan + 256;
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
+                            int64_t n, int begin_bit, int end_bit, void* tmp, size_t tmp_bytes,
+                            bool* result_in_alt, hipStream_t s) {
+    *result_in_alt = false;
+    if (n <= 1) return hipSuccess;
+    int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    if (radix_tmp_bytes(n) > tmp_bytes) return hipErrorInvalidValue;
+    char* t = (char*)tmp;
+    uint32_t* hist = (uint32_t*)t;
+    t += (size_t)256 * nb * sizeof(uint32_t);
+    t = (char*)(((uintptr_t)t + 7) & ~(uintptr_t)7);
+    uint64_t* offs = (uint64_t*)t;
+    t += (size_t)(256 * nb + 1) * sizeof(uint64_t);
+    void* stmp = t;
+    size_t stmp_bytes = scan_tmp_bytes(256 * nb);
+    uint64_t* ki = keys; uint32_t* vi = vals;
+    uint64_t* ko = keys_alt; uint32_t* vo = vals_alt;
+    bool alt = false;
+    for (int shift = begin_bit; shift < end_bit; shift += 8) {
+        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
+        hipError_t e = exclusive_scan_u32_to_u64(hist, offs, 256 * nb, stmp, stmp_bytes, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, n, shift, nb,
+                           offs, ko, vo);
+        std::swap(ki, ko);
+        std::swap(vi, vo);
+        alt = !alt;
+    }
+    *result_in_alt = alt;
+    return hipGetLastError();
+}
+
+}  // namespace lm

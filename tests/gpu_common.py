@@ -1,0 +1,50 @@
+"""Shared helpers for the GPU parity tests: seeded problems, oracle runs and
+error metrics.  Inputs come from the scene generator; expected values come
+from the oracle only."""
+from __future__ import annotations
+
+import numpy as np
+
+from oracle import forward, jacobian, solve
+from paper_2409_12892_amd import scenegen as sg
+
+BLOCKS = {"mean": slice(0, 3), "scale": slice(3, 6), "quat": slice(6, 10), "opacity": slice(10, 11),
+          "sh": slice(11, None)}
+
+
+def rel(a, b) -> float:
+    """Norm-wise relative error ||a - b|| / ||b||."""
+    a = np.asarray(a, np.float64).ravel()
+    b = np.asarray(b, np.float64).ravel()
+    nb = np.linalg.norm(b)
+    return float(np.linalg.norm(a - b) / nb) if nb > 0 else float(np.linalg.norm(a))
+
+
+def make_problem(name="tiny", N=None, subsets=None, seed=None, deg=None, tile=(16, 16), with_J=True):
+    """Scene, cameras and targets (oracle render of the perturbed scene plus
+    pixel noise, float32) for one subset, plus the oracle Jacobian at x."""
+    d = sg.config_scene(name, N=N, subsets=subsets, seed=seed, deg=deg)
+    sc = d["scene"]
+    cams = d["cams"][0]
+    tw, th = tile
+    imgs = forward.render_images(d["x_star"], cams, sc.sh_degree, tw, th)
+    target = np.stack([(im + nz).astype(np.float32) for im, nz in zip(imgs, d["noise"][0])])
+    J = jacobian.Jacobian(sc.x, cams, sc.sh_degree, tw, th) if with_J else None
+    return dict(scene=sc, cams=cams, target=target, J=J, cfg=d["cfg"], tile=tile)
+
+
+def random_direction(P, N, seed, block=None):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, 1.0, size=(P, N)).astype(np.float32)
+    if block is not None:
+        mask = np.zeros(P, bool)
+        mask[BLOCKS[block]] = True
+        p[~mask] = 0.0
+    return p
+
+
+def oracle_pcg(J, target, lam, n_iters, tol=0.0, tol_mode=0):
+    b = J.b(list(target))
+    M = J.diag_JtJ()
+    out = solve.pcg(J.apply_JtJ, b, M, lam, n_iters, tol, tol_mode)
+    return b, M, out

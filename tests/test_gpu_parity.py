@@ -1,0 +1,201 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle on the
+tiny plain-method scene: 2,048 Gaussians, SH degree 0, 4 views of 64x64,
+16x16 tiles, float32 cache.
+
+Bars: tile binning and sort bit-exact; active pair set exact; J p, J^T u,
+b = -J^T F and diag(J^T J) within a norm-wise relative error of 1e-5;
+the PCG direction after 10 fixed iterations within 1e-4."""
+import numpy as np
+import pytest
+
+from gpu_common import BLOCKS, make_problem, oracle_pcg, random_direction, rel
+from oracle import forward, solve
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def prob():
+    return make_problem("tiny")
+
+
+@pytest.fixture(scope="module")
+def gpu(prob):
+    from paper_2409_12892_amd import binding as B
+    x = torch.from_numpy(prob["scene"].x).cuda()
+    tgt = torch.from_numpy(prob["target"].ravel()).cuda()
+    cache, b, fsq = B.lm_build_cache(x, prob["scene"].sh_degree, prob["cams"], tgt)
+    torch.cuda.synchronize()
+    return dict(B=B, x=x, target=tgt, cache=cache, b=b, fsq=fsq)
+
+
+def test_library_loaded_is_in_tree(gpu):
+    import os
+    from paper_2409_12892_amd import binding
+    assert os.path.dirname(binding.LIB_PATH).endswith("paper_2409_12892_amd")
+
+
+def test_projection_records(prob, gpu):
+    rec = gpu["cache"].export("records").reshape(prob["cams"].V, -1, 4)
+    x64 = prob["scene"].x.astype(np.float64)
+    for v in range(prob["cams"].V):
+        pr = forward.project(x64, prob["cams"].view(v), prob["scene"].sh_degree)
+        vis = pr["visible"]
+        np.testing.assert_array_equal(rec[v, vis, 0], pr["y"][0][vis].astype(np.float32))
+        np.testing.assert_array_equal(rec[v, vis, 1], pr["y"][1][vis].astype(np.float32))
+        np.testing.assert_array_equal(rec[v, vis, 2], pr["z"][vis].astype(np.float32))
+        np.testing.assert_array_equal(rec[v, vis, 3].astype(np.int64), pr["radius"][vis])
+
+
+def test_binning_and_sort_bit_exact(prob, gpu):
+    vals = gpu["cache"].export("sorted_values")
+    rng = gpu["cache"].export("tile_ranges")
+    J = prob["J"]
+    t0 = 0
+    for v, vw in enumerate(J.views):
+        lists = vw["bins"]["lists"]
+        for t, lst in enumerate(lists):
+            got = vals[rng[t0 + t]:rng[t0 + t + 1]]
+            np.testing.assert_array_equal(got.astype(np.int64), lst, err_msg=f"view {v} tile {t}")
+        t0 += len(lists)
+    assert rng[-1] == len(vals)
+
+
+def test_render_and_contributors(prob, gpu):
+    img = gpu["cache"].export("image").reshape(prob["cams"].V, 3, 64, 64)
+    nc = gpu["cache"].export("ncontrib").reshape(prob["cams"].V, 64, 64)
+    for v, vw in enumerate(prob["J"].views):
+        np.testing.assert_allclose(img[v], vw["raster"]["image"], rtol=0, atol=2e-7)
+        np.testing.assert_array_equal(nc[v], vw["raster"]["n_contrib"])
+    res = gpu["cache"].export("residual")
+    F = prob["J"].residual(list(prob["target"]))
+    np.testing.assert_allclose(res, F, rtol=0, atol=2e-7)
+    assert float(gpu["fsq"].item()) == pytest.approx(float(F @ F), rel=1e-12)
+
+
+def test_cache_pairs_match_oracle(prob, gpu):
+    c = gpu["cache"]
+    pix = c.export("pair_pix").astype(np.int64)
+    gid = c.export("pair_gauss").astype(np.int64)
+    T = c.export("pair_T")
+    D = c.export("pair_D").reshape(3, -1)
+    HW = 64 * 64
+    o_pix, o_g, o_T, o_D = [], [], [], []
+    for v, vw in enumerate(prob["J"].views):
+        p = vw["raster"]["pairs"]
+        o_pix.append(p["pixel"] + v * HW)
+        o_g.append(p["g"])
+        o_T.append(p["T"])
+        o_D.append(p["D"])
+    o_pix, o_g = np.concatenate(o_pix), np.concatenate(o_g)
+    o_T, o_D = np.concatenate(o_T), np.concatenate(o_D)
+    assert len(pix) == len(o_pix)
+    key_gpu = pix * 10_000_000 + gid
+    key_or = o_pix * 10_000_000 + o_g
+    ig, io = np.argsort(key_gpu), np.argsort(key_or)
+    np.testing.assert_array_equal(key_gpu[ig], key_or[io])
+    np.testing.assert_allclose(T[ig], o_T[io], rtol=1e-7, atol=0)
+    np.testing.assert_allclose(D[:, ig].T, o_D[io], rtol=0, atol=1e-6)
+
+
+@pytest.mark.parametrize("block", [None, *BLOCKS.keys()])
+def test_apply_J(prob, gpu, block):
+    sc = prob["scene"]
+    p = random_direction(sc.P, sc.N, seed=10, block=block)
+    u = gpu["B"].lm_apply_J(gpu["cache"], torch.from_numpy(p).cuda())
+    ref = prob["J"].apply_J(p.astype(np.float64))
+    assert rel(u.cpu().numpy(), ref) < 1e-5
+
+
+@pytest.mark.parametrize("block", [None, *BLOCKS.keys()])
+def test_apply_JT(prob, gpu, block):
+    rng = np.random.default_rng(20)
+    u = rng.normal(size=prob["J"].n_res).astype(np.float32)
+    g = gpu["B"].lm_apply_JT(gpu["cache"], torch.from_numpy(u).cuda()).cpu().numpy()
+    ref = prob["J"].apply_JT(u.astype(np.float64)).reshape(g.shape)
+    sl = slice(None) if block is None else BLOCKS[block]
+    assert rel(g[sl], ref[sl]) < 1e-5
+
+
+def test_b_is_minus_JT_F(prob, gpu):
+    ref = prob["J"].b(list(prob["target"])).reshape(prob["scene"].P, -1)
+    b = gpu["b"].cpu().numpy()
+    for name, sl in BLOCKS.items():
+        assert rel(b[sl], ref[sl]) < 1e-5, name
+
+
+def test_jacobi_diag(prob, gpu):
+    M = gpu["B"].lm_jacobi_diag(gpu["cache"]).cpu().numpy()
+    ref = prob["J"].diag_JtJ().reshape(M.shape)
+    for name, sl in BLOCKS.items():
+        assert rel(M[sl], ref[sl]) < 1e-5, name
+
+
+def test_apply_JtJ_fused_with_damping(prob, gpu):
+    sc = prob["scene"]
+    p = random_direction(sc.P, sc.N, seed=30)
+    Mref = prob["J"].diag_JtJ()
+    M = torch.from_numpy(Mref.astype(np.float32).reshape(sc.P, sc.N)).cuda()
+    g, jp = gpu["B"].lm_apply_JtJ(gpu["cache"], torch.from_numpy(p).cuda(), 0.3, M, want_jp_sqnorm=True)
+    ref = prob["J"].apply_JtJ(p.astype(np.float64), 0.3, Mref.astype(np.float32).astype(np.float64))
+    assert rel(g.cpu().numpy(), ref) < 1e-5
+    Jp = prob["J"].apply_J(p.astype(np.float64))
+    assert float(jp.item()) == pytest.approx(float(Jp @ Jp), rel=1e-5)
+
+
+def test_pcg_direction(prob, gpu):
+    cfg = prob["cfg"]
+    J = prob["J"]
+    b_ref, M_ref, out = oracle_pcg(J, prob["target"], cfg["lam"], cfg["n_iters"])
+    B = gpu["B"]
+    M = B.lm_jacobi_diag(gpu["cache"])
+    deltas, stats = B.lm_pcg_solve([gpu["cache"]], [gpu["b"]], [M], cfg["lam"], cfg["n_iters"])
+    d = deltas[0].cpu().numpy().ravel()
+    assert stats[0]["iters"] == cfg["n_iters"] and stats[0]["status"] == 0
+    assert rel(d, out["x"]) < 1e-4
+    np.testing.assert_allclose(stats[0]["history"], out["history"], rtol=1e-3)
+
+
+def test_pcg_paper_stopping_rule(prob, gpu):
+    """Algorithm 1's break: ||r||^2 < 0.01 ||b||^2 ends the loop on the device."""
+    J = prob["J"]
+    _, _, out = oracle_pcg(J, prob["target"], 1e-2, 50, tol=0.01, tol_mode=solve.TOL_PAPER_SQUARED)
+    B = gpu["B"]
+    M = B.lm_jacobi_diag(gpu["cache"])
+    deltas, stats = B.lm_pcg_solve([gpu["cache"]], [gpu["b"]], [M], 1e-2, 50, tol=0.01,
+                                   tol_mode=B.TOL_PAPER_SQUARED)
+    assert stats[0]["iters"] == out["iters"]
+    assert stats[0]["history"][-1] < 0.01
+    assert rel(deltas[0].cpu().numpy().ravel(), out["x"]) < 1e-4
+
+
+def test_combine_subsets(gpu):
+    B = gpu["B"]
+    rng = np.random.default_rng(5)
+    ds = [rng.normal(size=1000).astype(np.float32) for _ in range(3)]
+    Ms = [np.abs(rng.normal(size=1000)).astype(np.float32) for _ in range(3)]
+    for m in Ms:
+        m[rng.integers(0, 1000, 100)] = 0.0
+    Ms[0][:5] = Ms[1][:5] = Ms[2][:5] = 0.0
+    out = B.lm_combine_subsets([torch.from_numpy(d).cuda() for d in ds], [torch.from_numpy(m).cuda() for m in Ms])
+    ref = solve.combine_subsets(ds, Ms)
+    np.testing.assert_allclose(out.cpu().numpy(), ref, rtol=1e-6, atol=1e-7)
+    assert np.all(out.cpu().numpy()[:5] == 0)
+
+
+def test_render_entry_point(prob, gpu):
+    img = gpu["B"].lm_render(gpu["x"], prob["scene"].sh_degree, prob["cams"]).cpu().numpy()
+    ref = np.concatenate([vw["raster"]["image"].ravel() for vw in prob["J"].views])
+    np.testing.assert_allclose(img, ref, rtol=0, atol=2e-7)
+
+
+def test_rebuild_reuses_cache_and_is_deterministic(prob, gpu):
+    B = gpu["B"]
+    c2, b2, _ = B.lm_build_cache(gpu["x"], prob["scene"].sh_degree, prob["cams"], gpu["target"])
+    assert np.array_equal(c2.export("sorted_values"), gpu["cache"].export("sorted_values"))
+    assert torch.equal(b2, gpu["b"]) or rel(b2.cpu().numpy(), gpu["b"].cpu().numpy()) < 1e-6
+    c3, b3, _ = B.lm_build_cache(gpu["x"], prob["scene"].sh_degree, prob["cams"], gpu["target"], cache=c2)
+    assert np.array_equal(c3.export("pair_T"), gpu["cache"].export("pair_T"))
+    c2.destroy()
