@@ -1,0 +1,257 @@
+#!/usr/bin/env python3
+"""Benchmark of the LM/PCG hot path on one MI355X.
+
+One step = one Levenberg-Marquardt iteration on one image subset: build the
+gradient cache (projection, binning, depth sort, forward render, cache fill,
+b = -J^T F), the Jacobi diagonal, Algorithm 1 with n_iters PCG iterations
+(n_iters + 1 applications of J^T J), the subset combination, one more
+application for ||J delta||^2, the line search on 30% of the views, the
+trust-region ratio and the update (paper section 3.2).  Inputs (scene,
+cameras, targets) are resident in HBM before the timed region.
+
+Default workload: 1,000,000 Gaussians, SH degree 3 (59 parameters each), 32
+views at 1024x640 in one subset, float32 cache, 8 Jacobi-PCG iterations per
+LM step, lambda = 1e-2.  Targets are renders of the perturbed scene plus
+pixel noise (synthetic stand-ins for the paper's captured images).
+
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "J^TJ·p applies/s + HBM GB/s; LM-iter ms, bf16/batched/learned vs plain"
+HBM_PEAK_GBPS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_tile_JtJ_paper_traffic.txt")
+APPLY_SRC = os.path.join(ROOT, "paper_2409_12892_amd", "csrc", "apply.hip")
+
+
+def log(msg: str) -> None:
+    print(f"[bench {time.strftime('%H:%M:%S')}] {msg}", file=sys.stderr, flush=True)
+
+
+class OneCam:
+    """Cameras-like wrapper of a single camera dict (for the oracle)."""
+
+    def __init__(self, cam):
+        self.cam = cam
+        self.V = 1
+
+    def view(self, v):
+        return self.cam
+
+
+def apply_tile_alg_bytes(info: dict) -> int:
+    """Algorithmic HBM bytes of one fused J^T J tile-pass launch: every cached
+    pair once (T, dC/dalpha x3 in the cache dtype + the pixel byte), per
+    segment its staged splat (6 floats), pair offset and gv index (2 x 4 B),
+    its tangent coefficients (9 floats, read) and moments (9 floats,
+    written), per tile its offsets, view and ||Jp||^2 partial."""
+    wb = 4 if info["cache_dtype"] == 0 else 2
+    return int(info["n_pairs"] * (4 * wb + 1) + info["n_segments"] * (24 + 8 + 36 + 36) + info["n_tiles"] * 28)
+
+
+def read_traffic(alg_bytes: int):
+    """HBM traffic per launch from the committed rocprofv3 counter summary, or
+    None when it is absent or was taken on a different kernel source."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    kv = {}
+    for line in open(TRAFFIC_FILE):
+        if "=" in line and not line.lstrip().startswith("#"):
+            k, v = line.split("=", 1)
+            kv[k.strip()] = v.strip()
+    src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
+    if kv.get("apply_src_sha256") != src:
+        return None
+    try:
+        return int(float(kv["traffic_bytes_per_launch"]))
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(scene, cams, n_pairs_per_apply: int, tile: int = 16, crop: int = 64, reps: int = 3) -> dict:
+    """The FP64 oracle, as it stands, on a bounded sample of the same
+    workload: a crop x crop pixel window at the centre of view 0 (all
+    Gaussians whose tile rectangle touches it).  Times the oracle's explicit
+    Jacobian build and its J^T J p (SciPy CSR, float64, one thread), and
+    scales the pair rate to applies/s of the full workload."""
+    from oracle import forward, jacobian
+    cam = dict(cams.view(0))
+    x0 = (cam["W"] // 2 - crop // 2) // tile * tile
+    y0 = (cam["H"] // 2 - crop // 2) // tile * tile
+    cc = dict(cam, cx=np.float32(cam["cx"] - x0), cy=np.float32(cam["cy"] - y0), W=crop, H=crop)
+    x64 = scene.x.astype(np.float64)
+    t0 = time.perf_counter()
+    pr = forward.project(x64, cc, scene.sh_degree)
+    bn = forward.bin_view(pr["y"], pr["z"], pr["radius"], pr["visible"], crop, crop, tile, tile)
+    sel = np.unique(bn["values"])
+    J = jacobian.Jacobian(x64[:, sel], OneCam(cc), scene.sh_degree, tile, tile)
+    t_build = time.perf_counter() - t0
+    p = np.random.default_rng(0).normal(size=J.P * J.N)
+    J.apply_JtJ(p)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        J.apply_JtJ(p)
+    t_apply = (time.perf_counter() - t1) / reps
+    pairs = J.n_pairs
+    rate = pairs / t_apply
+    return dict(value=rate / n_pairs_per_apply, unit="applies/s", cores=1, kind="oracle",
+                sample=(f"view 0, {crop}x{crop} centre crop ({(crop // tile) ** 2} tiles), {len(sel)} Gaussians, "
+                        f"{pairs} pairs; J^T J p with the explicit float64 J (SciPy CSR, single thread) "
+                        f"= {t_apply * 1e3:.1f} ms, i.e. {rate / 1e6:.2f} M pairs/s, scaled to the "
+                        f"{n_pairs_per_apply} pairs of one full apply; oracle build of the sample "
+                        f"{t_build:.1f} s"),
+                pairs_per_s=rate, sample_build_s=t_build, sample_apply_ms=t_apply * 1e3)
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--config", default="paper")
+    ap.add_argument("--cache-dtype", default="f32", choices=["f32", "bf16", "f16"])
+    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--N", type=int, default=None, help="override the number of Gaussians")
+    ap.add_argument("--views", type=int, default=None, help="override the views of the subset")
+    ap.add_argument("--cpu-baseline", type=int, default=1)
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
+              "the multi-GPU layout (one image subset per GPU, one all-reduce of the weighted "
+              "mean) is described in DESIGN.md and not run.", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_2409_12892_amd import binding as B
+    from paper_2409_12892_amd import scenegen as sg
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 3
+    B.load()
+    tw, th = (int(v) for v in args.tile.split("x"))
+    cfg = dict(sg.CONFIGS[args.config])
+    subsets = cfg["subsets"][:1]
+    if args.views is not None:
+        subsets = [(args.views, subsets[0][1], subsets[0][2])]
+    log(f"generating scene: config={args.config} N={args.N or cfg['N']} subsets={subsets}")
+    d = sg.config_scene(args.config, N=args.N, subsets=subsets)
+    scene, cams = d["scene"], d["cams"][0]
+    V, W, H = subsets[0]
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(scene.x).to(dev)
+    x_star = torch.from_numpy(d["x_star"]).to(dev)
+    noise = torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev)
+    target = B.lm_render(x_star, scene.sh_degree, cams, tile=(tw, th))
+    target.add_(noise)
+    del x_star, noise
+    torch.cuda.synchronize()
+    lam, n_iters = float(cfg["lam"]), int(cfg["n_iters"])
+    log(f"inputs resident: N={scene.N} P={scene.P} views={V} {W}x{H}")
+
+    from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
+    solver = LMSolver(x, scene.sh_degree, cams, target,
+                      LMConfig(lam=lam, n_iters=n_iters, tile=(tw, th), cache_dtype=args.cache_dtype))
+
+    def show(tag, rec):
+        log(f"{tag}: E {rec['E0']:.4g} -> {rec['E1']:.4g} gamma {rec['gamma']:g} rho {rec['rho']:.3g} "
+            f"{'accepted' if rec['accepted'] else 'rejected'} lambda {rec['lam']:.3g} -> {rec['lam_next']:.3g}")
+
+    for i in range(args.warmup):
+        show(f"warmup step {i + 1}/{args.warmup}", solver.iteration())
+    torch.cuda.synchronize()
+    B.lm_profile_read()
+    B.lm_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        show(f"timed step {i + 1}/{args.steps}", solver.iteration())
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    B.lm_profile_enable(False)
+    prof = B.lm_profile_read()
+    info = solver.cache.info()
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    applies = (n_iters + 2) * args.steps
+    value = applies / (t1 - t0)
+
+    launches, tot_ms = prof.get("apply_tile_JtJ", (0, 0.0))
+    apply_ms = tot_ms / max(launches, 1)
+    alg = apply_tile_alg_bytes(info)
+    achieved = alg / (apply_ms * 1e-3) / 1e9
+    traffic = read_traffic(alg)
+    full_apply_ms = sum(prof.get(k, (0, 0.0))[1] for k in ("tangent", "apply_tile_JtJ", "chain", "pcg_vector")) \
+        / max(launches, 1)
+    log(f"steps done: {ms_per_step:.1f} ms/step, apply tile pass {apply_ms:.3f} ms, {achieved:.0f} GB/s")
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 3),
+        "unit": "applies/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.cache_dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"LM iteration, plain method: {scene.N} Gaussians SH{scene.sh_degree}, {V} views "
+                         f"{W}x{H} in one subset, {args.cache_dtype} cache, {n_iters} Jacobi-PCG iterations"),
+            "N": scene.N, "P": scene.P, "views": V, "width": W, "height": H, "tile": args.tile,
+            "cache_dtype": args.cache_dtype, "pcg_iters": n_iters, "lambda": lam,
+            "diag_floor": solver.cfg.diag_floor, "line_search_views": int(len(solver.ls_idx)),
+        },
+        "roofline": {
+            "kernel": "k_apply_tile<J^T J fused>",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBPS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBPS, 4),
+            "traffic": traffic,
+            "alg_bytes_per_launch": alg,
+            "avg_launch_ms": round(apply_ms, 4),
+        },
+        "lm_iter_ms": round(ms_per_step, 3),
+        "apply_JtJ_ms": round(full_apply_ms, 4),
+        "apply_JtJ_per_s": round(1e3 / full_apply_ms, 2) if full_apply_ms > 0 else None,
+        "kernels_ms_per_step": {k: round(v[1] / args.steps, 3) for k, v in sorted(prof.items())},
+        "kernel_launches": {k: v[0] for k, v in sorted(prof.items())},
+        "cache": {k: info[k] for k in ("n_keys", "n_pairs", "n_segments", "n_gv", "n_tiles", "cache_bytes",
+                                        "device_bytes")},
+        "lm_steps": [{k: (round(v, 6) if isinstance(v, float) else v) for k, v in r.items()}
+                     for r in solver.history],
+    }
+    if args.cpu_baseline:
+        log("cpu baseline: oracle on a bounded crop of view 0")
+        try:
+            out["cpu_baseline"] = cpu_baseline(scene, cams, info["n_pairs"], tile=tw)
+        except Exception as e:  # the GPU result stands even if the CPU sample fails
+            out["cpu_baseline"] = {"value": None, "error": repr(e)}
+        log("cpu baseline done")
+    print(json.dumps(out), flush=True)
+    solver.close()
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

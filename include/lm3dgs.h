@@ -139,12 +139,16 @@ lm_status lm_apply_JT(const lm_cache* cache, const float* u, float* g, void* str
  * Scheme": each subset solves its own normal equations).  All arrays are
  * host arrays of n_b device pointers; precond_scale may be NULL (plain
  * Jacobi) or hold per-subset NULL / dev float32 [P][N] factors multiplying
- * M^-1.  Dots, alpha and beta are float64 and stay on the device; the
- * stopping test runs on the device.  stats (host, n_b entries) is filled
- * after one synchronisation at the end. */
+ * M^-1.  diag_floor: 0 runs Algorithm 1 exactly; > 0 replaces every
+ * positive diagonal entry below it by the floor in both the damping term
+ * and the Jacobi preconditioner (a minimum LM diagonal, as in CERES, whose
+ * LM variant the paper follows); unobserved parameters (M = 0) keep a zero
+ * update either way.  Dots, alpha and beta are float64 and stay on the
+ * device; the stopping test runs on the device.  stats (host, n_b entries)
+ * is filled after one synchronisation at the end. */
 lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b,
-                       const float* const* M, float lambda, int32_t n_iters, double tol,
-                       int32_t tol_mode, const float* const* precond_scale,
+                       const float* const* M, float lambda, float diag_floor, int32_t n_iters,
+                       double tol, int32_t tol_mode, const float* const* precond_scale,
                        float* const* delta, lm_pcg_stats* stats, void* stream);
 
 /* Weighted mean of subset directions (paper eq. combine-pcg):
@@ -156,6 +160,16 @@ lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float
 /* Forward render only (eq. alpha-blending), image dev float32 [V][3][H][W]. */
 lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V,
                     const lm_options* opts, float* image, void* stream);
+
+/* ||F(x)||^2 = ||render(x) - target||^2 summed over the given views, float64
+ * on the device (forward pass only: projection, binning, depth sort and
+ * alpha-blending; no cache fill).  Serves the line search (eq. line-search)
+ * and the trust-region ratio (eq. tr-update) of the LM outer loop.
+ * *workspace: NULL or a handle whose device memory is reused; after the call
+ * it holds no usable cache (products on it return LM_ERR_NOT_BUILT). */
+lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32_t V,
+                             const float* target, const lm_options* opts, void* stream,
+                             lm_cache** workspace, double* F_sqnorm);
 
 /* Copy an internal array of a built cache to host memory (inspection and
  * tests).  Synchronises the stream.  `what` selects the array; `bytes` must
@@ -176,6 +190,22 @@ enum {
 int64_t lm_cache_export_size(const lm_cache* cache, int32_t what);
 lm_status lm_cache_export(const lm_cache* cache, int32_t what, void* host_dst, int64_t bytes,
                           void* stream);
+
+/* Opt-in timing of the library's own kernels with HIP events recorded on
+ * the stream each kernel is launched on.  lm_profile_enable(1) starts
+ * recording (one start/stop event pair around every kernel group the
+ * library launches), lm_profile_enable(0) stops.  lm_profile_read()
+ * synchronises on the recorded events, returns per-group totals (at most
+ * max_entries, sorted by name) and clears the record.  Not thread-safe:
+ * meant for a single driver thread. */
+typedef struct lm_profile_entry {
+    char name[40];
+    int32_t launches;
+    int32_t reserved;
+    double total_ms;
+} lm_profile_entry;
+lm_status lm_profile_enable(int32_t on);
+int32_t lm_profile_read(lm_profile_entry* out, int32_t max_entries);
 
 #ifdef __cplusplus
 }

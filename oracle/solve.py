@@ -23,7 +23,8 @@ def jacobi_inverse(M: np.ndarray) -> np.ndarray:
 
 
 def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
-        tol: float = 0.0, tol_mode: int = TOL_NONE, precond_scale: np.ndarray | None = None) -> dict:
+        tol: float = 0.0, tol_mode: int = TOL_NONE, precond_scale: np.ndarray | None = None,
+        diag_floor: float = 0.0) -> dict:
     """Algorithm 1, in the order printed:
 
         x0 = M^-1 b;  r0 = b - (J^T J x0 + lam M x0);  z0 = M^-1 r0;  p0 = z0
@@ -37,10 +38,16 @@ def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
     runs n_iters times (n_iters + 1 products in total: with n_iters = 8 the
     paper's "up to 9" applications).  ``precond_scale`` multiplies M^-1
     element-wise (a learned diagonal rescaling); None means plain Jacobi.
+    ``diag_floor`` > 0 (not in the paper's text; the minimum LM diagonal of
+    CERES, whose LM variant the paper follows) replaces every positive
+    diagonal entry below the floor by the floor, in the damping term and in
+    M^-1 alike; 0 runs Algorithm 1 as printed.
     Returns x and the per-iteration ||r||^2 / ||b||^2 history.
     """
     b = np.asarray(b, np.float64).ravel()
     M = np.asarray(M, np.float64).ravel()
+    if diag_floor > 0.0:
+        M = np.where(M > 0.0, np.maximum(M, diag_floor), 0.0)
     Minv = jacobi_inverse(M)
     if precond_scale is not None:
         Minv = Minv * np.asarray(precond_scale, np.float64).ravel()
@@ -81,14 +88,16 @@ def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
     return dict(x=x, iters=it, history=np.asarray(hist), status=status)
 
 
-def dense_solve(JtJ: np.ndarray, b: np.ndarray, lam: float) -> np.ndarray:
-    """Solve (J^T J + lam diag(J^T J)) delta = b on the observed parameters
-    (eq. norm-eq); unobserved parameters (zero diagonal) get 0."""
+def dense_solve(JtJ: np.ndarray, b: np.ndarray, lam: float, diag_floor: float = 0.0) -> np.ndarray:
+    """Solve (J^T J + lam D) delta = b on the observed parameters (eq. norm-eq,
+    D = diag(J^T J), raised to diag_floor where it is positive and smaller);
+    unobserved parameters (zero diagonal) get 0."""
     A = np.asarray(JtJ.toarray() if hasattr(JtJ, "toarray") else JtJ, np.float64)
     d = np.diag(A).copy()
     obs = d > 0
     out = np.zeros(A.shape[0])
-    As = A[np.ix_(obs, obs)] + lam * np.diag(d[obs])
+    D = np.maximum(d[obs], diag_floor)
+    As = A[np.ix_(obs, obs)] + lam * np.diag(D)
     out[obs] = np.linalg.solve(As, np.asarray(b, np.float64).ravel()[obs])
     return out
 

@@ -32,7 +32,7 @@ _EXPORT_DTYPE = dict(records=np.float32, sorted_values=np.uint32, tile_ranges=np
 EXPORTED_SYMBOLS = (
     "lm_last_error", "lm_build_cache", "lm_cache_destroy", "lm_cache_get_info", "lm_jacobi_diag",
     "lm_apply_JtJ", "lm_apply_J", "lm_apply_JT", "lm_pcg_solve", "lm_combine_subsets", "lm_render",
-    "lm_cache_export_size", "lm_cache_export",
+    "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
 )
 
 
@@ -54,6 +54,11 @@ class LmCacheInfo(ctypes.Structure):
                 ("n_gv", c_int64), ("n_pixels", c_int64), ("n_tiles", c_int64), ("cache_bytes", c_int64),
                 ("device_bytes", c_int64), ("V", c_int32), ("P", c_int32), ("tile_w", c_int32),
                 ("tile_h", c_int32), ("cache_dtype", c_int32), ("sh_degree", c_int32)]
+
+
+class LmProfileEntry(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 40), ("launches", c_int32), ("reserved", c_int32),
+                ("total_ms", c_double)]
 
 
 class LmPcgStats(ctypes.Structure):
@@ -214,8 +219,9 @@ def lm_apply_JT(cache: Cache, u, out=None):
 
 
 def lm_pcg_solve(caches, bs, Ms, lam: float, n_iters: int, tol: float = 0.0, tol_mode: int = TOL_NONE,
-                 scales=None, deltas=None):
-    """Algorithm 1 for each subset; returns (deltas, stats dicts)."""
+                 scales=None, deltas=None, diag_floor: float = 0.0):
+    """Algorithm 1 for each subset; returns (deltas, stats dicts).  diag_floor
+    = 0 is Algorithm 1 exactly (see lm_pcg_solve in include/lm3dgs.h)."""
     import torch
     nb = len(caches)
     deltas = [torch.empty_like(b) for b in bs] if deltas is None else deltas
@@ -225,7 +231,8 @@ def lm_pcg_solve(caches, bs, Ms, lam: float, n_iters: int, tol: float = 0.0, tol
     D = (c_void_p * nb)(*[d.data_ptr() for d in deltas])
     Sc = None if scales is None else (c_void_p * nb)(*[0 if s is None else s.data_ptr() for s in scales])
     stats = (LmPcgStats * nb)()
-    _check(load().lm_pcg_solve(H, c_int32(nb), B, Mm, c_float(lam), c_int32(n_iters), c_double(tol),
+    _check(load().lm_pcg_solve(H, c_int32(nb), B, Mm, c_float(lam), c_float(diag_floor), c_int32(n_iters),
+                               c_double(tol),
                                c_int32(tol_mode), Sc, D, stats, _stream()), "lm_pcg_solve")
     out = [dict(iters=s.iters, status=s.status, b_sqnorm=s.b_sqnorm,
                 history=np.array(s.history[:s.iters + 1])) for s in stats]
@@ -241,6 +248,37 @@ def lm_combine_subsets(deltas, Ms, out=None):
     _check(load().lm_combine_subsets(c_int32(nb), D, Mm, c_int64(deltas[0].numel()), _ptr(out), _stream()),
            "lm_combine_subsets")
     return out
+
+
+def lm_residual_sqnorm(x, sh_degree: int, cams, target, *, tile=(16, 16), workspace: Cache | None = None,
+                       out=None):
+    """||render(x) - target||^2 over the views of `cams` (forward pass only).
+    Returns (value as a 1-element float64 device tensor, workspace)."""
+    import torch
+    x = _dev_f32(x, "x")
+    target = _dev_f32(target, "target")
+    P, N = x.shape
+    scene = LmScene(N, sh_degree, 0, x.data_ptr())
+    opts = LmOptions(tile[0], tile[1], 0, 0)
+    carr = camera_array(cams)
+    ws = Cache() if workspace is None else workspace
+    out = torch.empty(1, device=x.device, dtype=torch.float64) if out is None else out
+    h = ws.handle
+    _check(load().lm_residual_sqnorm(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), _stream(),
+                                     byref(h), _ptr(out)), "lm_residual_sqnorm")
+    ws.handle = h
+    return out, ws
+
+
+def lm_profile_enable(on: bool = True) -> None:
+    _check(load().lm_profile_enable(c_int32(1 if on else 0)), "lm_profile_enable")
+
+
+def lm_profile_read() -> dict:
+    """{kernel group: (launches, total ms)} recorded since the last read."""
+    arr = (LmProfileEntry * 64)()
+    n = load().lm_profile_read(arr, c_int32(64))
+    return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n)}
 
 
 def lm_render(x, sh_degree: int, cams, *, tile=(16, 16), out=None):

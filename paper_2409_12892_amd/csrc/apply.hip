@@ -292,7 +292,8 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
 // ---- chain: per-(Gaussian, view) moments -> parameters ---------------------------
 // out = scale * J^T u (+ lambda M p); partial dot products p . out per block.
 __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, float lambda, const float* __restrict__ M,
-                                                 float* __restrict__ out, double* __restrict__ pg_part) {
+                                                 float diag_floor, float* __restrict__ out,
+                                                 double* __restrict__ pg_part) {
     if (a.stop && *a.stop) return;
     const CacheView& c = a.c;
     __shared__ double s_red[kBlock / kWave];
@@ -328,7 +329,11 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, floa
             double val = j < 11 ? geo[j] : gsh[j - 11];
             val *= scale;
             const int64_t idx = (int64_t)j * c.N + g;
-            if (M) val += (double)lambda * (double)M[idx] * (double)a.p[idx];
+            if (M) {
+                const float m = M[idx];
+                const float md = m > 0.0f ? fmaxf(m, diag_floor) : 0.0f;
+                val += (double)lambda * (double)md * (double)a.p[idx];
+            }
             out[idx] = (float)val;
             if (pg_part) pg += (double)a.p[idx] * (double)(float)val;
         }
@@ -503,9 +508,10 @@ hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float* out, double* pg_part,
-                        hipStream_t s) {
-    hipLaunchKernelGGL(k_chain, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, out, pg_part);
+hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
+                        double* pg_part, hipStream_t s) {
+    hipLaunchKernelGGL(k_chain, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, diag_floor, out,
+                       pg_part);
     return hipGetLastError();
 }
 

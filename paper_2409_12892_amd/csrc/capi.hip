@@ -14,6 +14,50 @@ namespace lm {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+namespace prof {
+// Event pairs recorded around kernel groups while profiling is enabled.
+struct Rec {
+    const char* name;
+    hipEvent_t a, b;
+};
+static bool g_enabled = false;
+static std::vector<hipEvent_t> g_pool;
+static size_t g_used = 0;
+static std::vector<Rec> g_recs;
+
+static hipEvent_t take() {
+    if (g_used < g_pool.size()) return g_pool[g_used++];
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    g_pool.push_back(e);
+    ++g_used;
+    return e;
+}
+
+struct Scope {
+    const char* name;
+    hipStream_t s;
+    hipEvent_t a = nullptr;
+    Scope(const char* n, hipStream_t st) : name(n), s(st) {
+        if (g_enabled) {
+            a = take();
+            if (a) (void)hipEventRecord(a, s);
+        }
+    }
+    ~Scope() {
+        if (g_enabled && a) {
+            hipEvent_t b = take();
+            if (b) {
+                (void)hipEventRecord(b, s);
+                g_recs.push_back({name, a, b});
+            }
+        }
+    }
+};
+}  // namespace prof
+
+#define LM_PROF(name, stream) ::lm::prof::Scope lm_prof_scope_##__LINE__(name, stream)
+
 namespace {
 
 // Device buffer that only grows; reused across rebuilds of one cache.
@@ -198,10 +242,11 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->keycnt.ensure(sizeof(uint32_t) * R));
     LM_HIP(c->keyoff.ensure(sizeof(uint64_t) * (R + 1)));
     LM_HIP(c->scan_tmp.ensure(std::max(scan_tmp_bytes(R), scan_tmp_bytes(N * (int64_t)V + 1)) + 1024));
+    { LM_PROF("project", s);
     LM_HIP(launch_project(c->cams.as<CamDev>(), c->x.as<float>(), N, V, c->deg, TW, TH, c->rec64.as<double>(),
                           c->recf.as<float>(), c->rad.as<int32_t>(), c->keycnt.as<uint32_t>(), s));
     LM_HIP(exclusive_scan_u32_to_u64(c->keycnt.as<uint32_t>(), c->keyoff.as<uint64_t>(), R, c->scan_tmp.p,
-                                     c->scan_tmp.cap, s));
+                                     c->scan_tmp.cap, s)); }
     uint64_t K = 0;
     LM_HIP(hipMemcpyAsync(&K, c->keyoff.as<uint64_t>() + R, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     LM_HIP(hipStreamSynchronize(s));
@@ -214,19 +259,21 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->keys_alt.ensure(sizeof(uint64_t) * Ka));
     LM_HIP(c->vals_alt.ensure(sizeof(uint32_t) * Ka));
     LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(Ka)));
+    { LM_PROF("bin_emit", s);
     LM_HIP(launch_bin_emit(c->cams.as<CamDev>(), N, V, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(),
                            c->keycnt.as<uint32_t>(), c->keyoff.as<uint64_t>(), c->keys.as<uint64_t>(),
-                           c->vals.as<uint32_t>(), s));
+                           c->vals.as<uint32_t>(), s)); }
     int tile_bits = 1;
     while (((int64_t)1 << tile_bits) < c->n_tiles) ++tile_bits;
     bool alt = false;
+    { LM_PROF("depth_sort", s);
     LM_HIP(radix_sort_pairs(c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), c->keys_alt.as<uint64_t>(),
                             c->vals_alt.as<uint32_t>(), c->n_keys, 0, 31 + tile_bits, c->sort_tmp.p,
-                            c->sort_tmp.cap, &alt, s));
+                            c->sort_tmp.cap, &alt, s)); }
     c->vals_in_alt = alt;
     const uint64_t* skeys = alt ? c->keys_alt.as<uint64_t>() : c->keys.as<uint64_t>();
     LM_HIP(c->tile_start.ensure(sizeof(int64_t) * (c->n_tiles + 1)));
-    LM_HIP(launch_tile_ranges(skeys, c->n_keys, c->n_tiles, c->tile_start.as<int64_t>(), s));
+    { LM_PROF("tile_ranges", s); LM_HIP(launch_tile_ranges(skeys, c->n_keys, c->n_tiles, c->tile_start.as<int64_t>(), s)); }
 
     // forward render and per-entry counts
     LM_HIP(c->entry_cnt.ensure(sizeof(uint32_t) * Ka));
@@ -255,7 +302,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     ra.tile_segs = c->tile_segs.as<uint32_t>();
     ra.gv_cnt = c->gv_cnt.as<uint32_t>();
     ra.n_pix = c->n_pix;
-    LM_HIP(launch_raster(false, dtype, c->n_tiles, ra, s));
+    { LM_PROF("raster_count", s); LM_HIP(launch_raster(false, dtype, c->n_tiles, ra, s)); }
     return LM_OK;
 }
 
@@ -334,8 +381,8 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.seg_loc = c->seg_loc.as<uint32_t>();
     ra.seg_f = c->seg_f.as<float>();
     ra.seg_stride = c->seg_stride;
-    LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s));
-    LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s));
+    { LM_PROF("raster_fill", s); LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s)); }
+    { LM_PROF("gv_sort", s); LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s)); }
     // product workspaces
     LM_HIP(c->dyc.ensure(sizeof(float) * 9 * ngv_a));
     LM_HIP(c->gmom.ensure(sizeof(float) * 9 * nseg_a));
@@ -349,19 +396,19 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
 lm_status apply_JT_internal(const lm_cache* c, const float* u, float scale, float* g, hipStream_t s) {
     lm::ApplyArgs a = c->apply_args();
     a.uin = u;
-    LM_HIP(lm::launch_apply_tile(2, a, s));
-    LM_HIP(lm::launch_chain(a, scale, 0.0f, nullptr, g, nullptr, s));
+    { LM_PROF("apply_tile_JT", s); LM_HIP(lm::launch_apply_tile(2, a, s)); }
+    { LM_PROF("chain", s); LM_HIP(lm::launch_chain(a, scale, 0.0f, nullptr, 0.0f, g, nullptr, s)); }
     return LM_OK;
 }
 
-lm_status apply_JtJ_internal(lm_cache* c, const float* p, float lambda, const float* M, float* g, double* pg_part,
-                             const int32_t* stop, hipStream_t s) {
+lm_status apply_JtJ_internal(lm_cache* c, const float* p, float lambda, const float* M, float diag_floor, float* g,
+                             double* pg_part, const int32_t* stop, hipStream_t s) {
     lm::ApplyArgs a = c->apply_args();
     a.p = p;
     a.stop = stop;
-    LM_HIP(lm::launch_tangent(a, s));
-    LM_HIP(lm::launch_apply_tile(3, a, s));
-    LM_HIP(lm::launch_chain(a, 1.0f, lambda, M, g, pg_part, s));
+    { LM_PROF("tangent", s); LM_HIP(lm::launch_tangent(a, s)); }
+    { LM_PROF("apply_tile_JtJ", s); LM_HIP(lm::launch_apply_tile(3, a, s)); }
+    { LM_PROF("chain", s); LM_HIP(lm::launch_chain(a, 1.0f, lambda, M, diag_floor, g, pg_part, s)); }
     return LM_OK;
 }
 
@@ -441,7 +488,7 @@ lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
     LM_HIP(cm->gram.ensure(sizeof(float) * 40 * std::max<int64_t>(c->n_seg, 1)));
-    LM_HIP(lm::launch_jacobi_diag(c->view(), c->x.as<float>(), cm->gram.as<float>(), M, S(stream)));
+    { LM_PROF("jacobi_diag", S(stream)); LM_HIP(lm::launch_jacobi_diag(c->view(), c->x.as<float>(), cm->gram.as<float>(), M, S(stream))); }
     return LM_OK;
 }
 
@@ -450,7 +497,7 @@ lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const fl
     LM_CHECK(c && p && g, LM_ERR_INVALID_ARG, "lm_apply_JtJ: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
-    lm_status st = apply_JtJ_internal(cm, p, M ? lambda : 0.0f, M, g, nullptr, nullptr, S(stream));
+    lm_status st = apply_JtJ_internal(cm, p, M ? lambda : 0.0f, M, 0.0f, g, nullptr, nullptr, S(stream));
     if (st != LM_OK) return st;
     if (Jp_sqnorm) LM_HIP(lm::reduce_f64(c->jp_part.as<double>(), c->n_tiles, Jp_sqnorm, S(stream)));
     return LM_OK;
@@ -474,11 +521,12 @@ lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream)
 }
 
 lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
-                       float lambda, int32_t n_iters, double tol, int32_t tol_mode,
+                       float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
                        const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
     LM_CHECK(caches && b && M && delta && n_b > 0, LM_ERR_INVALID_ARG, "lm_pcg_solve: NULL argument");
     LM_CHECK(n_iters >= 0 && n_iters < LM_PCG_MAX_HISTORY, LM_ERR_INVALID_ARG, "n_iters out of range");
     LM_CHECK(tol_mode >= LM_TOL_NONE && tol_mode <= LM_TOL_RELATIVE, LM_ERR_INVALID_ARG, "bad tol_mode");
+    LM_CHECK(diag_floor >= 0.0f && lambda >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
     hipStream_t s = S(stream);
     for (int i = 0; i < n_b; ++i) {
         lm_cache* c = caches[i];
@@ -498,17 +546,18 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
               *g = c->pcg_g.as<float>();
         double* part = c->pcg_part.as<double>();
         const int32_t* stop = &st->stop;
-        LM_HIP(lm::pcg_init(n, b[i], M[i], sc, x, s));
+        LM_HIP(lm::pcg_init(n, b[i], M[i], diag_floor, sc, x, s));
         LM_HIP(hipMemsetAsync(st, 0, sizeof(lm::PcgState), s));
-        lm_status e = apply_JtJ_internal(c, x, lambda, M[i], g, nullptr, nullptr, s);
+        lm_status e = apply_JtJ_internal(c, x, lambda, M[i], diag_floor, g, nullptr, nullptr, s);
         if (e != LM_OK) return e;
-        LM_HIP(lm::pcg_init_r(n, b[i], g, M[i], sc, r, z, p, part, st, s));
+        LM_HIP(lm::pcg_init_r(n, b[i], g, M[i], diag_floor, sc, r, z, p, part, st, s));
         const int64_t nbc = lm::chain_blocks(c->N);
         for (int it = 0; it < n_iters; ++it) {
-            e = apply_JtJ_internal(c, p, lambda, M[i], g, c->pg_part.as<double>(), stop, s);
+            e = apply_JtJ_internal(c, p, lambda, M[i], diag_floor, g, c->pg_part.as<double>(), stop, s);
             if (e != LM_OK) return e;
+            { LM_PROF("pcg_vector", s);
             LM_HIP(lm::pcg_alpha(c->pg_part.as<double>(), nbc, st, s));
-            LM_HIP(lm::pcg_update(n, st, p, g, M[i], sc, x, r, z, part, tol, tol_mode, s));
+            LM_HIP(lm::pcg_update(n, st, p, g, M[i], diag_floor, sc, x, r, z, part, tol, tol_mode, s)); }
         }
         if (stats) {
             lm::PcgState hs;
@@ -524,13 +573,52 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
     return LM_OK;
 }
 
+lm_status lm_profile_enable(int32_t on) {
+    lm::prof::g_enabled = on != 0;
+    return LM_OK;
+}
+
+int32_t lm_profile_read(lm_profile_entry* out, int32_t max_entries) {
+    using namespace lm::prof;
+    struct Agg {
+        std::string name;
+        int32_t n = 0;
+        double ms = 0.0;
+    };
+    std::vector<Agg> agg;
+    for (const Rec& r : g_recs) {
+        float ms = 0.0f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.0f;
+        auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg& x) { return x.name == r.name; });
+        if (it == agg.end()) {
+            agg.push_back({r.name, 0, 0.0});
+            it = agg.end() - 1;
+        }
+        it->n += 1;
+        it->ms += ms;
+    }
+    g_recs.clear();
+    g_used = 0;
+    std::sort(agg.begin(), agg.end(), [](const Agg& a, const Agg& b) { return a.name < b.name; });
+    int32_t k = 0;
+    for (const Agg& a : agg) {
+        if (!out || k >= max_entries) break;
+        memset(&out[k], 0, sizeof(out[k]));
+        strncpy(out[k].name, a.name.c_str(), sizeof(out[k].name) - 1);
+        out[k].launches = a.n;
+        out[k].total_ms = a.ms;
+        ++k;
+    }
+    return k;
+}
+
 lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float* const* M, int64_t n, float* out,
                              void* stream) {
     LM_CHECK(delta && M && out && n_b > 0 && n_b <= 16 && n >= 0, LM_ERR_INVALID_ARG,
              "lm_combine_subsets: bad arguments (1 <= n_b <= 16)");
     for (int i = 0; i < n_b; ++i) LM_CHECK(delta[i] && M[i], LM_ERR_INVALID_ARG, "lm_combine_subsets: NULL entry");
     if (n == 0) return LM_OK;
-    LM_HIP(lm::launch_combine(n_b, delta, M, n, out, S(stream)));
+    { LM_PROF("combine", S(stream)); LM_HIP(lm::launch_combine(n_b, delta, M, n, out, S(stream))); }
     return LM_OK;
 }
 
@@ -552,6 +640,35 @@ lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, con
     (void)hipStreamSynchronize(s);
     c->release_all();
     delete c;
+    return st;
+}
+
+lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                             const lm_options* opts, void* stream, lm_cache** workspace, double* F_sqnorm) {
+    LM_CHECK(workspace && target && F_sqnorm, LM_ERR_INVALID_ARG, "lm_residual_sqnorm: NULL argument");
+    lm_cache* c = *workspace;
+    bool created = false;
+    if (!c) {
+        c = new (std::nothrow) lm_cache();
+        LM_CHECK(c, LM_ERR_HIP, "out of host memory");
+        created = true;
+    }
+    hipStream_t s = S(stream);
+    lm_status st = build_forward(c, scene, cams, V, target, opts, s);
+    if (st == LM_OK) {
+        hipError_t e = lm::reduce_f64(c->fsq_part.as<double>(), c->n_tiles, F_sqnorm, s);
+        if (e != hipSuccess) {
+            lm::set_error(std::string("lm_residual_sqnorm: ") + hipGetErrorString(e));
+            st = LM_ERR_HIP;
+        }
+    }
+    c->built = false;
+    if (st != LM_OK && created) {
+        c->release_all();
+        delete c;
+        return st;
+    }
+    *workspace = c;
     return st;
 }
 

@@ -219,18 +219,20 @@ hipError_t launch_gv_sort(const uint32_t* gv_seg_off, int64_t n_gv, uint32_t* gv
 // apply.hip (mode 1 = J, 2 = J^T, 3 = fused J^T J)
 hipError_t launch_tangent(const ApplyArgs& a, hipStream_t s);
 hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s);
-hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float* out, double* pg_part,
-                        hipStream_t s);
+hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
+                        double* pg_part, hipStream_t s);
 unsigned chain_blocks(int64_t N);
 hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, float* M, hipStream_t s);
 // pcg.hip
 int64_t pcg_partial_count(int64_t n);
-hipError_t pcg_init(int64_t n, const float* b, const float* M, const float* scale, float* x, hipStream_t s);
-hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, const float* scale, float* r,
-                      float* z, float* p, double* part, PcgState* st, hipStream_t s);
+hipError_t pcg_init(int64_t n, const float* b, const float* M, float floor_, const float* scale, float* x,
+                    hipStream_t s);
+hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, float floor_, const float* scale,
+                      float* r, float* z, float* p, double* part, PcgState* st, hipStream_t s);
 hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_t s);
-hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, const float* scale,
-                      float* x, float* r, float* z, double* part, double tol, int tol_mode, hipStream_t s);
+hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, float floor_,
+                      const float* scale, float* x, float* r, float* z, double* part, double tol, int tol_mode,
+                      hipStream_t s);
 hipError_t launch_combine(int n_b, const float* const* d, const float* const* m, int64_t n, float* out,
                           hipStream_t s);
 

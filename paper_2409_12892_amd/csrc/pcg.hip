@@ -14,10 +14,11 @@ namespace {
 
 constexpr int kVecBlocks = 2048;   // fixed grid: partial sums in a fixed order
 
-__device__ __forceinline__ float jacobi_inv(float M, const float* scale, int64_t i) {
+// M^-1 of Algorithm 1 with the optional minimum diagonal (0 where M = 0).
+__device__ __forceinline__ float jacobi_inv(float M, float floor_, const float* scale, int64_t i) {
     if (!(M > 0.0f)) return 0.0f;
     const float s = scale ? scale[i] : 1.0f;
-    return s / M;
+    return s / fmaxf(M, floor_);
 }
 
 template <int NV>
@@ -58,20 +59,20 @@ __device__ double block_sum(const double* part, int64_t n) {
 }
 
 // x0 = M^-1 b
-__global__ void k_init_x(int64_t n, const float* __restrict__ b, const float* __restrict__ M,
+__global__ void k_init_x(int64_t n, const float* __restrict__ b, const float* __restrict__ M, float floor_,
                          const float* __restrict__ scale, float* __restrict__ x) {
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
-        x[i] = jacobi_inv(M[i], scale, i) * b[i];
+        x[i] = jacobi_inv(M[i], floor_, scale, i) * b[i];
 }
 
 // r0 = b - g, z0 = M^-1 r0, p0 = z0; partials of r.z, r.r, b.b
 __global__ void k_init_r(int64_t n, const float* __restrict__ b, const float* __restrict__ g,
-                         const float* __restrict__ M, const float* __restrict__ scale, float* __restrict__ r,
+                         const float* __restrict__ M, float floor_, const float* __restrict__ scale, float* __restrict__ r,
                          float* __restrict__ z, float* __restrict__ p, double* __restrict__ part) {
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         const float ri = b[i] - g[i];
-        const float zi = jacobi_inv(M[i], scale, i) * ri;
+        const float zi = jacobi_inv(M[i], floor_, scale, i) * ri;
         r[i] = ri;
         z[i] = zi;
         p[i] = zi;
@@ -114,7 +115,7 @@ __global__ void k_alpha(const double* __restrict__ pg_part, int64_t nb, PcgState
 
 // x += alpha p, r -= alpha g, z = M^-1 r; partials of r.z and r.r
 __global__ void k_update_xrz(int64_t n, const PcgState* __restrict__ st, const float* __restrict__ p,
-                             const float* __restrict__ g, const float* __restrict__ M,
+                             const float* __restrict__ g, const float* __restrict__ M, float floor_,
                              const float* __restrict__ scale, float* __restrict__ x, float* __restrict__ r,
                              float* __restrict__ z, double* __restrict__ part) {
     if (st->stop) return;
@@ -123,7 +124,7 @@ __global__ void k_update_xrz(int64_t n, const PcgState* __restrict__ st, const f
     for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
         x[i] = x[i] + alpha * p[i];
         const float ri = r[i] - alpha * g[i];
-        const float zi = jacobi_inv(M[i], scale, i) * ri;
+        const float zi = jacobi_inv(M[i], floor_, scale, i) * ri;
         r[i] = ri;
         z[i] = zi;
         acc[0] += (double)ri * zi;
@@ -186,15 +187,16 @@ unsigned vec_grid(int64_t n) {
 
 int64_t pcg_partial_count(int64_t n) { return vec_grid(n); }
 
-hipError_t pcg_init(int64_t n, const float* b, const float* M, const float* scale, float* x, hipStream_t s) {
-    hipLaunchKernelGGL(k_init_x, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, b, M, scale, x);
+hipError_t pcg_init(int64_t n, const float* b, const float* M, float floor_, const float* scale, float* x,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_init_x, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, b, M, floor_, scale, x);
     return hipGetLastError();
 }
 
-hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, const float* scale, float* r,
-                      float* z, float* p, double* part, PcgState* st, hipStream_t s) {
+hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, float floor_, const float* scale,
+                      float* r, float* z, float* p, double* part, PcgState* st, hipStream_t s) {
     const unsigned nb = vec_grid(n);
-    hipLaunchKernelGGL(k_init_r, dim3(nb), dim3(kBlock), 0, s, n, b, g, M, scale, r, z, p, part);
+    hipLaunchKernelGGL(k_init_r, dim3(nb), dim3(kBlock), 0, s, n, b, g, M, floor_, scale, r, z, p, part);
     hipLaunchKernelGGL(k_init_scalars, dim3(1), dim3(kBlock), 0, s, part, (int64_t)nb, st);
     return hipGetLastError();
 }
@@ -204,10 +206,11 @@ hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_
     return hipGetLastError();
 }
 
-hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, const float* scale,
-                      float* x, float* r, float* z, double* part, double tol, int tol_mode, hipStream_t s) {
+hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, float floor_,
+                      const float* scale, float* x, float* r, float* z, double* part, double tol, int tol_mode,
+                      hipStream_t s) {
     const unsigned nb = vec_grid(n);
-    hipLaunchKernelGGL(k_update_xrz, dim3(nb), dim3(kBlock), 0, s, n, st, p, g, M, scale, x, r, z, part);
+    hipLaunchKernelGGL(k_update_xrz, dim3(nb), dim3(kBlock), 0, s, n, st, p, g, M, floor_, scale, x, r, z, part);
     hipLaunchKernelGGL(k_beta, dim3(1), dim3(kBlock), 0, s, part, (int64_t)nb, st, tol, tol_mode);
     hipLaunchKernelGGL(k_update_p, dim3(nb), dim3(kBlock), 0, s, n, st, z, p);
     return hipGetLastError();

@@ -1,0 +1,130 @@
+"""Levenberg-Marquardt outer loop around the HIP hot path (paper section 3.2).
+
+One iteration: build the gradient cache at x (b = -J^T F, ||F||^2), the
+Jacobi diagonal M, Algorithm 1 for delta, the subset combination, then
+
+* line search  min_gamma E(x + gamma delta) on a subset of the views
+  (eq. line-search; the paper uses 30% of the images and does not name the
+  method - here: gamma = 1, 1/2, 1/4, ... down to 2^-12; keep the best value
+  and stop once the error has dropped below E(x) on the subset and then
+  rises again);
+* trust-region ratio (eq. tr-update)
+      rho = (||F(x)||^2 - ||F(x + g d)||^2) / (||F(x)||^2 - ||J g d + F(x)||^2)
+  with the model decrease 2 g d^T b - g^2 ||J d||^2; keep the step when
+  rho > 1e-5 and scale lambda by 1 - (2 rho - 1)^3, otherwise revert and
+  double lambda; lambda is clamped to [lam_min, lam_max].
+
+The solve uses a minimum LM diagonal (diag_floor, CERES's safeguard; the
+paper follows CERES for the lambda schedule): on scenes with deeply occluded
+Gaussians, diag(J^T J) reaches 1e-25 and plain Jacobi PCG returns steps of
+order |F| / sqrt(diag) ~ 1e10 that no line search can rescue.
+
+Every product, render and reduction runs in the library; this module only
+sequences calls and does scalar bookkeeping (and the vector update
+x += gamma delta).
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import binding as B
+
+
+@dataclasses.dataclass
+class LMConfig:
+    lam: float = 1e-2
+    lam_min: float = 1e-4
+    lam_max: float = 1e4
+    n_iters: int = 8
+    tol: float = 0.0
+    tol_mode: int = B.TOL_NONE
+    rho_min: float = 1e-5
+    # minimum LM diagonal (see lm_pcg_solve); 0 reproduces Algorithm 1 exactly
+    diag_floor: float = 1e-2
+    line_search_fraction: float = 0.3
+    gammas: tuple = tuple(2.0 ** -k for k in range(13))
+    tile: tuple = (16, 16)
+    cache_dtype: str = "f32"
+
+
+class LMSolver:
+    """Holds the caches, workspaces and damping state of one problem
+    (one image subset)."""
+
+    def __init__(self, x, sh_degree: int, cams, target, cfg: LMConfig, ls_views=None):
+        import torch
+        self.x = x
+        self.deg = sh_degree
+        self.cams = cams
+        self.target = target
+        self.cfg = cfg
+        self.lam = cfg.lam
+        V = cams.V
+        k = max(1, int(round(cfg.line_search_fraction * V)))
+        self.ls_idx = np.asarray(ls_views if ls_views is not None else np.linspace(0, V - 1, k).round().astype(int))
+        self.ls_cams = cams.subset(self.ls_idx)
+        sizes = [3 * int(cams.W[v]) * int(cams.H[v]) for v in range(V)]
+        offs = np.concatenate([[0], np.cumsum(sizes)])
+        self.ls_target = torch.cat([target[offs[v]:offs[v + 1]] for v in self.ls_idx]).contiguous()
+        self.cache = None
+        self.ws = None
+        self.M = None
+        self.delta = None
+        self.comb = None
+        self.x_try = torch.empty_like(x)
+        self.history = []
+
+    def _E(self, x, cams, target) -> float:
+        val, self.ws = B.lm_residual_sqnorm(x, self.deg, cams, target, tile=self.cfg.tile, workspace=self.ws)
+        return float(val.item())
+
+    def iteration(self) -> dict:
+        import torch
+        cfg = self.cfg
+        self.cache, b, fsq = B.lm_build_cache(self.x, self.deg, self.cams, self.target, tile=cfg.tile,
+                                              cache_dtype=cfg.cache_dtype, cache=self.cache)
+        self.M = B.lm_jacobi_diag(self.cache, out=self.M)
+        deltas, stats = B.lm_pcg_solve([self.cache], [b], [self.M], self.lam, cfg.n_iters, cfg.tol, cfg.tol_mode,
+                                       deltas=None if self.delta is None else [self.delta],
+                                       diag_floor=cfg.diag_floor)
+        self.delta = deltas[0]
+        self.comb = B.lm_combine_subsets([self.delta], [self.M], out=self.comb)
+        d = self.comb
+        _, jd = B.lm_apply_JtJ(self.cache, d, want_jp_sqnorm=True)
+        E0 = float(fsq.item())
+        dTb = float(torch.dot(d.reshape(-1).double(), b.reshape(-1).double()).item())
+        Jd2 = float(jd.item())
+        # line search on the view subset
+        E_ref = self._E(self.x, self.ls_cams, self.ls_target)
+        best_g, best_E = cfg.gammas[-1], np.inf
+        for g in cfg.gammas:
+            torch.add(self.x, d, alpha=g, out=self.x_try)
+            E = self._E(self.x_try, self.ls_cams, self.ls_target)
+            if E < best_E:
+                best_g, best_E = g, E
+            elif best_E < E_ref:
+                break
+        g = best_g
+        torch.add(self.x, d, alpha=g, out=self.x_try)
+        E1 = self._E(self.x_try, self.cams, self.target)
+        pred = 2.0 * g * dTb - g * g * Jd2
+        rho = (E0 - E1) / pred if pred > 0 else -np.inf
+        accepted = bool(rho > cfg.rho_min and np.isfinite(E1))
+        lam_old = self.lam
+        if accepted:
+            self.x.copy_(self.x_try)
+            self.lam = self.lam * (1.0 - (2.0 * rho - 1.0) ** 3)
+        else:
+            self.lam = self.lam * 2.0
+        self.lam = float(min(max(self.lam, cfg.lam_min), cfg.lam_max))
+        rec = dict(E0=E0, E1=E1, gamma=g, rho=rho, accepted=accepted, lam=lam_old, lam_next=self.lam,
+                   pcg_iters=stats[0]["iters"], pcg_rel_res_sq=float(stats[0]["history"][-1]))
+        self.history.append(rec)
+        return rec
+
+    def close(self):
+        for h in (self.cache, self.ws):
+            if h is not None:
+                h.destroy()

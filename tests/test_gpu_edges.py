@@ -1,0 +1,101 @@
+"""Edge cases of the HIP path against the oracle: a view that sees nothing,
+a scene with no visible Gaussian (no keys, no pairs), a single Gaussian, and
+option validation."""
+import numpy as np
+import pytest
+
+from gpu_common import random_direction, rel
+from oracle import forward, jacobian, solve
+from paper_2409_12892_amd import scenegen as sg
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+def away_camera(cams: sg.Cameras, v: int) -> sg.Cameras:
+    """Copy of camera v turned to look away from the scene (x and z axes
+    flipped keep a proper rotation)."""
+    R = cams.R[v].astype(np.float64)
+    C = -R.T @ cams.t[v].astype(np.float64)
+    R2 = np.diag([-1.0, 1.0, -1.0]) @ R
+    t2 = -R2 @ C
+    out = cams.subset([v])
+    out.R = R2[None].astype(np.float32)
+    out.t = t2[None].astype(np.float32)
+    return out
+
+
+def _run(scene, cams, target, tile=(16, 16)):
+    from paper_2409_12892_amd import binding as B
+    x = torch.from_numpy(scene.x).cuda()
+    tgt = torch.from_numpy(np.ascontiguousarray(target).ravel()).cuda()
+    cache, b, fsq = B.lm_build_cache(x, scene.sh_degree, cams, tgt, tile=tile)
+    return B, x, cache, b, fsq
+
+
+def test_view_facing_away_has_no_splats():
+    d = sg.config_scene("tiny", N=600, subsets=[(3, 48, 48)], seed=21)
+    sc = d["scene"]
+    cams = sg.Cameras.concat([d["cams"][0].subset([0]), away_camera(d["cams"][0], 1), d["cams"][0].subset([2])])
+    rng = np.random.default_rng(1)
+    target = rng.uniform(0, 1, size=(3, 3, 48, 48)).astype(np.float32)
+    J = jacobian.Jacobian(sc.x, cams, sc.sh_degree)
+    assert len(J.views[1]["bins"]["values"]) == 0
+    B, x, cache, b, fsq = _run(sc, cams, target)
+    rngs = cache.export("tile_ranges")
+    nt = 9
+    assert rngs[nt] == rngs[2 * nt]                     # view 1: every tile list empty
+    np.testing.assert_allclose(cache.export("residual").reshape(3, 3, 48, 48)[1], -target[1], atol=0)
+    ref_b = J.b(list(target)).reshape(sc.P, -1)
+    assert rel(b.cpu().numpy(), ref_b) < 1e-5
+    p = random_direction(sc.P, sc.N, seed=3)
+    u = B.lm_apply_J(cache, torch.from_numpy(p).cuda()).cpu().numpy()
+    assert rel(u, J.apply_J(p.astype(np.float64))) < 1e-5
+    assert np.all(u.reshape(3, 3, 48, 48)[1] == 0)
+
+
+def test_no_visible_gaussian():
+    d = sg.config_scene("tiny", N=64, subsets=[(2, 32, 32)], seed=22)
+    sc = d["scene"]
+    cams = sg.Cameras.concat([away_camera(d["cams"][0], 0), away_camera(d["cams"][0], 1)])
+    target = np.full((2, 3, 32, 32), 0.25, np.float32)
+    B, x, cache, b, fsq = _run(sc, cams, target)
+    info = cache.info()
+    assert info["n_keys"] == 0 and info["n_pairs"] == 0 and info["n_segments"] == 0
+    assert float(fsq.item()) == pytest.approx(2 * 3 * 32 * 32 * 0.0625)
+    assert torch.count_nonzero(b).item() == 0
+    M = B.lm_jacobi_diag(cache)
+    assert torch.count_nonzero(M).item() == 0
+    deltas, stats = B.lm_pcg_solve([cache], [b], [M], 1e-2, 5)
+    assert torch.count_nonzero(deltas[0]).item() == 0
+    assert stats[0]["status"] == B.LM_WARN_BREAKDOWN and stats[0]["iters"] == 0
+    ref = solve.pcg(lambda v: 0 * v, np.zeros(sc.P * sc.N), np.zeros(sc.P * sc.N), 1e-2, 5)
+    assert ref["status"] == 1 and ref["iters"] == 0
+
+
+def test_single_gaussian_sh3():
+    sc, _ = sg.make_scene(1, 3, 23, mean_lo=-0.1, mean_hi=0.1, logscale_mu=-2.0)
+    cams = sg.fibonacci_cameras(2, 32, 32)
+    imgs = forward.render_images(sc.x, cams, 3)
+    target = (np.stack(imgs) * 0.9).astype(np.float32)
+    J = jacobian.Jacobian(sc.x, cams, 3)
+    assert J.n_pairs > 0
+    B, x, cache, b, fsq = _run(sc, cams, target)
+    assert cache.info()["n_pairs"] == J.n_pairs
+    assert rel(b.cpu().numpy().ravel(), J.b(list(target))) < 1e-5
+    M = B.lm_jacobi_diag(cache).cpu().numpy().ravel()
+    assert rel(M, J.diag_JtJ()) < 1e-5
+    p = random_direction(sc.P, sc.N, seed=4)
+    g = B.lm_apply_JtJ(cache, torch.from_numpy(p).cuda()).cpu().numpy().ravel()
+    assert rel(g, J.apply_JtJ(p.astype(np.float64))) < 1e-5
+
+
+def test_invalid_options_are_rejected():
+    from paper_2409_12892_amd import binding as B
+    d = sg.config_scene("tiny", N=16, subsets=[(1, 16, 16)], seed=24)
+    x = torch.from_numpy(d["scene"].x).cuda()
+    tgt = torch.zeros(3 * 16 * 16, device="cuda")
+    with pytest.raises(RuntimeError, match="tile_w"):
+        B.lm_build_cache(x, 0, d["cams"][0], tgt, tile=(32, 16))
+    with pytest.raises(RuntimeError, match="sh_degree"):
+        B.lm_build_cache(x, 4, d["cams"][0], tgt)

@@ -336,6 +336,26 @@ def test_pcg_matches_dense_solve():
     assert np.linalg.norm(out["x"] - ref) / np.linalg.norm(ref) < 1e-8
 
 
+def test_pcg_with_diag_floor_matches_dense_solve():
+    """The minimum-diagonal variant solves (J^T J + lam max(diag, floor)) d = b."""
+    sc, cams, J = _tiny_problem(seed=8)
+    rng = np.random.default_rng(4)
+    targets = [im + rng.normal(0, 0.05, size=im.shape) for im in J.images()]
+    b = J.b(targets)
+    M = J.diag_JtJ()
+    floor = float(np.quantile(M[M > 0], 0.3))
+    ref = solve.dense_solve(J.JtJ(), b, 0.1, diag_floor=floor)
+    out = solve.pcg(J.apply_JtJ, b, M, 0.1, n_iters=2000, tol=1e-13, tol_mode=solve.TOL_RELATIVE,
+                    diag_floor=floor)
+    assert np.linalg.norm(out["x"] - ref) / np.linalg.norm(ref) < 1e-8
+    plain = solve.dense_solve(J.JtJ(), b, 0.1)
+    assert np.linalg.norm(plain - ref) / np.linalg.norm(ref) > 1e-3     # the floor matters here
+    # x0 of Algorithm 1 uses the floored diagonal
+    one = solve.pcg(J.apply_JtJ, b, M, 0.1, n_iters=0, diag_floor=floor)
+    Mf = np.where(M > 0, np.maximum(M, floor), 0.0)
+    np.testing.assert_allclose(one["x"], solve.jacobi_inverse(Mf) * b, rtol=1e-15)
+
+
 def test_pcg_applies_count_and_history():
     sc, cams, J = _tiny_problem(seed=9)
     b = J.b([np.zeros_like(im) for im in J.images()])
