@@ -78,7 +78,8 @@ typedef struct lm_scene {
 } lm_scene;
 
 typedef struct lm_options {
-    int32_t tile_w, tile_h;  /* tile shape in pixels; tile_w*tile_h <= 256 (0,0 = 16x16) */
+    int32_t tile_w, tile_h;  /* tile shape in pixels: tile_w a power of two, tile_w*tile_h
+                                <= 256 (0 selects 16)                                     */
     int32_t cache_dtype;     /* LM_CACHE_F32 / _BF16 / _F16 storage of the cache      */
     int32_t flags;           /* reserved, 0                                            */
 } lm_options;
@@ -87,6 +88,8 @@ typedef struct lm_cache lm_cache;   /* opaque, library-owned */
 
 typedef struct lm_cache_info {
     int64_t N, n_keys, n_pairs, n_segments, n_gv, n_pixels, n_tiles;
+    int64_t n_pair_slots;    /* pair storage incl. the zero padding of each segment
+                                to a multiple of 8 pairs                        */
     int64_t cache_bytes;     /* pair + segment arrays read by the products   */
     int64_t device_bytes;    /* all device memory held by the cache          */
     int32_t V, P, tile_w, tile_h, cache_dtype, sh_degree;

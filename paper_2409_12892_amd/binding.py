@@ -51,7 +51,8 @@ class LmOptions(ctypes.Structure):
 
 class LmCacheInfo(ctypes.Structure):
     _fields_ = [("N", c_int64), ("n_keys", c_int64), ("n_pairs", c_int64), ("n_segments", c_int64),
-                ("n_gv", c_int64), ("n_pixels", c_int64), ("n_tiles", c_int64), ("cache_bytes", c_int64),
+                ("n_gv", c_int64), ("n_pixels", c_int64), ("n_tiles", c_int64), ("n_pair_slots", c_int64),
+                ("cache_bytes", c_int64),
                 ("device_bytes", c_int64), ("V", c_int32), ("P", c_int32), ("tile_w", c_int32),
                 ("tile_h", c_int32), ("cache_dtype", c_int32), ("sh_degree", c_int32)]
 

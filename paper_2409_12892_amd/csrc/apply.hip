@@ -12,35 +12,37 @@
 // pair pass, the chain kernel maps per-(Gaussian,view) moments back to the
 // parameters after it (supplement A.2 splits applyJT the same way).
 //
-// Pair pass: one workgroup per tile.  Each lane takes an aligned run of 8
-// consecutive pairs (vector loads of every cache plane), walks it serially
-// and
-//   J  : adds its colour derivative to the pixel's accumulator in LDS,
-//   J^T: accumulates the 9 moments of the pair's segment in registers and
-//        flushes them to the segment's LDS accumulator when the segment ends.
+// Pair pass: one workgroup per tile.  Every segment (the pairs of one splat
+// in one tile, in pixel order) starts on a multiple of 8 pairs and is padded
+// with zero words, so each aligned run of 8 pairs belongs to exactly one
+// segment, named by the run -> segment table.  A lane takes one run (vector
+// loads of every cache plane, the next run prefetched while the current one
+// is processed), reads its segment's splat data once from LDS and
+//   J  : adds each pair's colour derivative to the pixel's LDS accumulator
+//        (pixel accumulators are padded by one word per 8 pixels, so the
+//        8-pair stride between neighbouring lanes does not hit one bank),
+//   J^T: sums the 9 moments of its 8 pairs in registers; a segmented scan over
+//        the wave (keyed by segment, runs ascending across lanes) leaves one
+//        LDS add per segment and wave.
 // The fused J^T J pass keeps u in LDS between the two halves (every pixel's
 // splats live in its own tile), so u never reaches HBM.
 #include "proj_math.h"
 
 namespace lm {
-
-
-
 namespace {
 
+constexpr int kThreads = 512;  // threads per tile workgroup (8 wave64)
 constexpr int kChunk = 256;    // segments staged per LDS chunk
-constexpr int kRun = 8;        // consecutive pairs per lane
+constexpr int kRun = 8;        // pairs per run (segments are padded to runs)
+// pixel accumulators: padded pixel slots [0, 287), a zero slot that is never
+// written (read by padding pairs in J^T) and one sink slot per lane (written
+// by padding pairs in J), so the per-pair code has no branches
+constexpr int kUZero = kMaxTilePix + kMaxTilePix / 8 - 1;
+constexpr int kUSink = kUZero + 1;
+constexpr int kUTot = kUSink + kWave;
 constexpr int MODE_J = 1, MODE_JT = 2, MODE_JTJ = 3;
 
-__device__ __forceinline__ int find_seg(const uint32_t* s_loc, int cn, uint32_t local) {
-    int lo = 0, hi = cn - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (s_loc[mid] <= local) lo = mid;
-        else hi = mid - 1;
-    }
-    return lo;
-}
+__device__ __forceinline__ int upad(int pl) { return pl + (pl >> 3); }
 
 template <int DT>
 struct RunLoad {
@@ -49,7 +51,10 @@ struct RunLoad {
     W t[kRun];
     W d[3][kRun];
     uint8_t pix[kRun];
-    __device__ __forceinline__ void load(const CacheView& c, int64_t qr) {
+    uint32_t seg;
+    __device__ __forceinline__ void load(const CacheView& c, int64_t run) {
+        const int64_t qr = run * kRun;
+        seg = c.run_seg[run];
         if constexpr (sizeof(W) == 4) {
             const uint4* pt = (const uint4*)((const uint32_t*)c.pT + qr);
             uint4 a = pt[0], b = pt[1];
@@ -81,6 +86,7 @@ struct RunLoad {
 };
 
 // ---- tangent: p -> per-(Gaussian, view) power coefficients -------------------
+template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
     if (a.stop && *a.stop) return;
     const CacheView& c = a.c;
@@ -95,9 +101,9 @@ __global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
         const int v = (int)(c.gv_rec[gv] / c.N);
         const CamDev& cam = c.cams[v];
         ProjFwd f;
-        proj_forward(cam, a.x, c.N, g, c.deg, f);
+        proj_forward<DEG>(cam, a.x, c.N, g, f);
         double out[9];
-        proj_tangent(cam, f, dgeo, a.x, a.p, c.N, g, c.deg, out);
+        proj_tangent<DEG>(cam, f, dgeo, a.x, a.p, c.N, g, out);
 #pragma unroll
         for (int k = 0; k < 9; ++k) a.dyc[(int64_t)gv * 9 + k] = (float)out[k];
     }
@@ -105,17 +111,15 @@ __global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
 
 // ---- pair pass ---------------------------------------------------------------
 template <int MODE, int DT>
-__global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
+__global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     if (a.stop && *a.stop) return;
     using S = Store<DT>;
     const CacheView& c = a.c;
-    __shared__ float s_u[3][kMaxTilePix];
-    __shared__ float s_pc[2][kMaxTilePix];
+    __shared__ float s_u[3][kUTot];
     __shared__ float s_seg[6][kChunk];
     __shared__ float s_tan[9][kChunk];
     __shared__ float s_mom[9][kChunk];
-    __shared__ uint32_t s_loc[kChunk + 1];
-    __shared__ double s_red[kBlock / kWave];
+    __shared__ double s_red[kThreads / kWave];
 
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
@@ -123,7 +127,8 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
     const CamDev& cam = c.cams[v];
     const int64_t lt = t - cam.tile_base;
     const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
-    const int lx = tid % c.TW, ly = tid / c.TW;
+    const int tw_mask = c.TW - 1, tw_shift = c.tw_shift;
+    const int lx = tid & tw_mask, ly = tid >> tw_shift;
     const int px = tx * c.TW + lx, py = ty * c.TH + ly;
     const bool valid = tid < c.TW * c.TH && px < cam.W && py < cam.H;
     const int64_t HW = (int64_t)cam.W * cam.H;
@@ -131,80 +136,79 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
-    s_pc[0][tid] = (float)lx + 0.5f;
-    s_pc[1][tid] = (float)ly + 0.5f;
-    if (MODE == MODE_JT) {
+    for (int i = tid; i < kUTot; i += kThreads)
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) s_u[ch][tid] = valid ? a.uin[ib + ch * HW] : 0.0f;
-    } else {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) s_u[ch][tid] = 0.0f;
-    }
+        for (int ch = 0; ch < 3; ++ch) s_u[ch][i] = 0.0f;
     __syncthreads();
+    if (MODE == MODE_JT && tid < kMaxTilePix && valid) {
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) s_u[ch][upad(tid)] = a.uin[ib + ch * HW];
+    }
 
-    auto stage = [&](int c0, int cn, bool tangents) {
-        for (int i = tid; i < cn; i += kBlock) {
+    // segments [c0, c0 + cn) of the tile: splat data (and tangents) into LDS;
+    // returns their runs [r0, r1) (segment offsets are multiples of kRun)
+    auto stage = [&](int c0, int cn, bool tangents, int64_t& r0, int64_t& r1) {
+        for (int i = tid; i < cn; i += kThreads) {
             const int64_t s = sb + c0 + i;
 #pragma unroll
             for (int k = 0; k < 6; ++k) s_seg[k][i] = c.seg_f[(int64_t)k * c.seg_stride + s];
-            s_loc[i] = c.seg_loc[s];
             if (tangents) {
                 const int64_t gv = c.seg_gv[s];
 #pragma unroll
                 for (int k = 0; k < 9; ++k) s_tan[k][i] = a.dyc[gv * 9 + k];
             }
         }
-        if (tid == 0) s_loc[cn] = (c0 + cn < nseg) ? c.seg_loc[sb + c0 + cn] : (uint32_t)(pe - pb);
+        r0 = (pb + c.seg_loc[sb + c0]) / kRun;
+        r1 = (c0 + cn < nseg ? pb + c.seg_loc[sb + c0 + cn] : pe) / kRun;
     };
 
     // ---------------- J p ----------------
     if (MODE & MODE_J) {
         for (int c0 = 0; c0 < nseg; c0 += kChunk) {
             const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
-            stage(c0, cn, true);
+            int64_t r0, r1;
             __syncthreads();
-            const int64_t qb = pb + s_loc[0], qe = pb + s_loc[cn];
-            const int64_t q0 = qb & ~(int64_t)(kRun - 1);
-            const int64_t nruns = (qe - q0 + kRun - 1) / kRun;
-            for (int64_t run = tid; run < nruns; run += kBlock) {
-                const int64_t qr = q0 + run * kRun;
-                RunLoad<DT> L;
-                L.load(c, qr);
-                const int64_t qf = qr > qb ? qr : qb;
-                int s = find_seg(s_loc, cn, (uint32_t)(qf - pb));
+            stage(c0, cn, true, r0, r1);
+            __syncthreads();
+            RunLoad<DT> nxt;
+            if (r0 + tid < r1) nxt.load(c, r0 + tid);
+            for (int64_t run = r0 + tid; run < r1; run += kThreads) {
+                const RunLoad<DT> L = nxt;
+                if (run + kThreads < r1) nxt.load(c, run + kThreads);
+                const int s = (int)L.seg - c0;
+                if ((unsigned)s >= (unsigned)cn) continue;   // never, for a consistent cache
+                const float mx = s_seg[0][s], my = s_seg[1][s], A = s_seg[2][s], B = s_seg[3][s];
+                const float C = s_seg[4][s], o = s_seg[5][s];
+                const float P1 = s_tan[0][s], P2 = s_tan[1][s], Q1 = s_tan[2][s], Q2 = s_tan[3][s];
+                const float Q3 = s_tan[4][s], dop = s_tan[5][s];
+                const float dc0 = s_tan[6][s], dc1 = s_tan[7][s], dc2 = s_tan[8][s];
 #pragma unroll
                 for (int k = 0; k < kRun; ++k) {
-                    const int64_t q = qr + k;
-                    if (q < qb || q >= qe) continue;
-                    if (q > qf && S::head(L.t[k])) ++s;
                     const float T = S::dec_T(L.t[k]);
                     const bool clamped = S::clamp(L.t[k]);
                     const int pl = L.pix[k];
-                    const float dx = s_pc[0][pl] - s_seg[0][s], dy = s_pc[1][pl] - s_seg[1][s];
-                    const float A = s_seg[2][s], B = s_seg[3][s], C = s_seg[4][s];
+                    const float dx = (float)(pl & tw_mask) + 0.5f - mx;
+                    const float dy = (float)(pl >> tw_shift) + 0.5f - my;
                     const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
                     const float G = __expf(power);
-                    const float alpha = clamped ? 0.99f : s_seg[5][s] * G;
+                    const float alpha = clamped ? 0.99f : o * G;
                     const float aT = alpha * T;
-                    float dal = 0.0f;
-                    if (!clamped) {
-                        const float poly = dx * (s_tan[0][s] + s_tan[2][s] * dx + s_tan[3][s] * dy) +
-                                           dy * (s_tan[1][s] + s_tan[4][s] * dy);
-                        dal = alpha * poly + G * s_tan[5][s];
-                    }
-#pragma unroll
-                    for (int ch = 0; ch < 3; ++ch)
-                        atomicAdd(&s_u[ch][pl], S::dec(L.d[ch][k]) * dal + aT * s_tan[6 + ch][s]);
+                    const float dal_f = alpha * (dx * (P1 + Q1 * dx + Q2 * dy) + dy * (P2 + Q3 * dy)) + G * dop;
+                    const float dal = clamped ? 0.0f : dal_f;
+                    const int ui = L.t[k] != 0 ? upad(pl) : kUSink + lane;   // padding -> sink
+                    atomicAdd(&s_u[0][ui], S::dec(L.d[0][k]) * dal + aT * dc0);
+                    atomicAdd(&s_u[1][ui], S::dec(L.d[1][k]) * dal + aT * dc1);
+                    atomicAdd(&s_u[2][ui], S::dec(L.d[2][k]) * dal + aT * dc2);
                 }
             }
-            __syncthreads();
         }
+        __syncthreads();
         // ||J p||^2 of the tile, and u itself for the J-only product
         double sq = 0.0;
-        if (valid) {
+        if (tid < kMaxTilePix && valid) {
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const float u = s_u[ch][tid];
+                const float u = s_u[ch][upad(tid)];
                 sq += (double)u * (double)u;
                 if (MODE == MODE_J) a.uout[ib + ch * HW] = u;
             }
@@ -215,7 +219,7 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
         __syncthreads();
         if (tid == 0) {
             double tot = 0.0;
-            for (int w = 0; w < kBlock / kWave; ++w) tot += s_red[w];
+            for (int w = 0; w < kThreads / kWave; ++w) tot += s_red[w];
             a.jp_part[t] = tot;
         }
         if (MODE == MODE_J) return;
@@ -224,65 +228,79 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
     // ---------------- J^T u ----------------
     for (int c0 = 0; c0 < nseg; c0 += kChunk) {
         const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
+        int64_t r0, r1;
         __syncthreads();
-        stage(c0, cn, false);
-        for (int i = tid; i < cn; i += kBlock)
+        stage(c0, cn, false, r0, r1);
+        for (int i = tid; i < cn; i += kThreads)
 #pragma unroll
             for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
         __syncthreads();
-        const int64_t qb = pb + s_loc[0], qe = pb + s_loc[cn];
-        const int64_t q0 = qb & ~(int64_t)(kRun - 1);
-        const int64_t nruns = (qe - q0 + kRun - 1) / kRun;
-        for (int64_t run = tid; run < nruns; run += kBlock) {
-            const int64_t qr = q0 + run * kRun;
-            RunLoad<DT> L;
-            L.load(c, qr);
-            const int64_t qf = qr > qb ? qr : qb;
-            int s = find_seg(s_loc, cn, (uint32_t)(qf - pb));
+        RunLoad<DT> nxt;
+        if (r0 + tid < r1) nxt.load(c, r0 + tid);
+        // every lane runs every round (converged for the wave scan); lanes
+        // without a run carry zeros under a key of their own
+        for (int64_t base = r0; base < r1; base += kThreads) {
+            const int64_t run = base + tid;
+            const bool has = run < r1;
+            const RunLoad<DT> L = nxt;
+            if (run + kThreads < r1) nxt.load(c, run + kThreads);
+            int s = has ? (int)L.seg - c0 : kChunk;
+            if ((unsigned)s >= (unsigned)cn) s = kChunk;    // no run, or an inconsistent cache
             float m[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) m[k] = 0.0f;
-            bool any = false;
+            if (s < kChunk) {
+                const float mx = s_seg[0][s], my = s_seg[1][s], A = s_seg[2][s], B = s_seg[3][s];
+                const float C = s_seg[4][s], o = s_seg[5][s];
 #pragma unroll
-            for (int k = 0; k < kRun; ++k) {
-                const int64_t q = qr + k;
-                if (q < qb || q >= qe) continue;
-                if (q > qf && S::head(L.t[k])) {
-#pragma unroll
-                    for (int i = 0; i < 9; ++i) { atomicAdd(&s_mom[i][s], m[i]); m[i] = 0.0f; }
-                    ++s;
+                for (int k = 0; k < kRun; ++k) {
+                    const float T = S::dec_T(L.t[k]);
+                    const bool clamped = S::clamp(L.t[k]);
+                    const int pl = L.pix[k];
+                    const float dx = (float)(pl & tw_mask) + 0.5f - mx;
+                    const float dy = (float)(pl >> tw_shift) + 0.5f - my;
+                    const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
+                    const float G = __expf(power);
+                    const float alpha = clamped ? 0.99f : o * G;
+                    const float aT = alpha * T;                               // 0 for padding
+                    const int ui = L.t[k] != 0 ? upad(pl) : kUZero;           // padding reads u = 0
+                    const float u0 = s_u[0][ui], u1 = s_u[1][ui], u2 = s_u[2][ui];
+                    const float w = S::dec(L.d[0][k]) * u0 + S::dec(L.d[1][k]) * u1 + S::dec(L.d[2][k]) * u2;
+                    const float aw = clamped ? 0.0f : alpha * w;
+                    const float awx = aw * dx, awy = aw * dy;
+                    m[0] += awx;
+                    m[1] += awy;
+                    m[2] += awx * dx;
+                    m[3] += awx * dy;
+                    m[4] += awy * dy;
+                    m[5] += clamped ? 0.0f : G * w;
+                    m[6] += aT * u0;
+                    m[7] += aT * u1;
+                    m[8] += aT * u2;
                 }
-                any = true;
-                const float T = S::dec_T(L.t[k]);
-                const bool clamped = S::clamp(L.t[k]);
-                const int pl = L.pix[k];
-                const float dx = s_pc[0][pl] - s_seg[0][s], dy = s_pc[1][pl] - s_seg[1][s];
-                const float A = s_seg[2][s], B = s_seg[3][s], C = s_seg[4][s];
-                const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
-                const float G = __expf(power);
-                const float alpha = clamped ? 0.99f : s_seg[5][s] * G;
-                const float aT = alpha * T;
-                const float u0 = s_u[0][pl], u1 = s_u[1][pl], u2 = s_u[2][pl];
-                const float w = S::dec(L.d[0][k]) * u0 + S::dec(L.d[1][k]) * u1 + S::dec(L.d[2][k]) * u2;
-                const float aw = clamped ? 0.0f : alpha * w;
-                const float awx = aw * dx, awy = aw * dy;
-                m[0] += awx;
-                m[1] += awy;
-                m[2] += awx * dx;
-                m[3] += awx * dy;
-                m[4] += awy * dy;
-                m[5] += clamped ? 0.0f : G * w;
-                m[6] += aT * u0;
-                m[7] += aT * u1;
-                m[8] += aT * u2;
             }
-            if (any) {
+            // segmented inclusive scan over the wave: runs ascend with the
+            // lane, so each segment is a contiguous lane range [head, tail]
+            const int prev = __shfl_up(s, 1, kWave);
+            const int next = __shfl_down(s, 1, kWave);
+            const uint64_t heads = __ballot(lane == 0 || prev != s);
+            const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+            const int head = kWave - 1 - __clzll(heads & upto);
 #pragma unroll
-                for (int i = 0; i < 9; ++i) atomicAdd(&s_mom[i][s], m[i]);
+            for (int off = 1; off < kWave; off <<= 1) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) {
+                    const float o = __shfl_up(m[k], off, kWave);
+                    if (lane - off >= head) m[k] += o;
+                }
+            }
+            if (s < kChunk && (lane == kWave - 1 || next != s)) {
+#pragma unroll
+                for (int k = 0; k < 9; ++k) atomicAdd(&s_mom[k][s], m[k]);
             }
         }
         __syncthreads();
-        for (int i = tid; i < cn * 9; i += kBlock) {
+        for (int i = tid; i < cn * 9; i += kThreads) {
             const int si = i / 9, k = i - si * 9;
             a.gmom[(sb + c0 + si) * 9 + k] = s_mom[k][si];
         }
@@ -291,10 +309,13 @@ __global__ void __launch_bounds__(kBlock) k_apply_tile(ApplyArgs a) {
 
 // ---- chain: per-(Gaussian, view) moments -> parameters ---------------------------
 // out = scale * J^T u (+ lambda M p); partial dot products p . out per block.
+template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, float lambda, const float* __restrict__ M,
                                                  float diag_floor, float* __restrict__ out,
                                                  double* __restrict__ pg_part) {
     if (a.stop && *a.stop) return;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int P = 11 + 3 * K;
     const CacheView& c = a.c;
     __shared__ double s_red[kBlock / kWave];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -304,9 +325,9 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, floa
         double geo[11];
 #pragma unroll
         for (int j = 0; j < 11; ++j) geo[j] = 0.0;
-        double gsh[48];
-        const int nsh = c.P - 11;
-        for (int j = 0; j < 48; ++j) gsh[j] = 0.0;
+        double gsh[3 * K];
+#pragma unroll
+        for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0;
         const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
         for (uint32_t gv = b; gv < e; ++gv) {
             double S9[9];
@@ -320,14 +341,14 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, floa
             const int v = (int)(c.gv_rec[gv] / c.N);
             const CamDev& cam = c.cams[v];
             ProjFwd f;
-            proj_forward(cam, a.x, c.N, g, c.deg, f);
+            proj_forward<DEG>(cam, a.x, c.N, g, f);
             double Gy[9];
             moments_to_Gy(f, S9, Gy);
-            proj_adjoint(cam, f, Gy, a.x, c.N, g, c.deg, geo, gsh);
+            proj_adjoint<DEG>(cam, f, Gy, a.x, c.N, g, geo, gsh);
         }
-        for (int j = 0; j < c.P; ++j) {
-            double val = j < 11 ? geo[j] : gsh[j - 11];
-            val *= scale;
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            double val = (j < 11 ? geo[j < 11 ? j : 0] : gsh[j >= 11 ? j - 11 : 0]) * scale;
             const int64_t idx = (int64_t)j * c.N + g;
             if (M) {
                 const float m = M[idx];
@@ -337,7 +358,6 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, floa
             out[idx] = (float)val;
             if (pg_part) pg += (double)a.p[idx] * (double)(float)val;
         }
-        (void)nsh;
     }
     if (pg_part) {
         const int lane = __lane_id(), wid = threadIdx.x / kWave;
@@ -361,7 +381,7 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, floa
 //   Bbb = sum (D.D) b b^T (21), Ebd = sum e b D^T (18), E2 = sum e^2 (1).
 constexpr int kGram = 40;
 
-__device__ __forceinline__ int tri6(int i, int k) { return i * 6 - (i * (i - 1)) / 2 + (k - i); }
+__device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i * (i - 1)) / 2 + (k - i); }
 
 template <int DT>
 __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __restrict__ gram) {
@@ -369,10 +389,9 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
     using W = typename S::word;
     const int64_t t = blockIdx.x;
     const int lane = __lane_id(), wid = threadIdx.x / kWave;
-    const int v = c.tile_view[t];
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
-    (void)v;
+    const int tw_mask = c.TW - 1, tw_shift = c.tw_shift;
     for (int64_t s = sb + wid; s < se; s += kBlock / kWave) {
         const int64_t ss = c.seg_stride;
         const float mlx = c.seg_f[s], mly = c.seg_f[ss + s];
@@ -385,13 +404,14 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
         for (int k = 0; k < kGram; ++k) acc[k] = 0.0f;
         for (int64_t q = q0 + lane; q < q1; q += kWave) {
             const W tw = ((const W*)c.pT)[q];
+            if (tw == 0) continue;                   // padding
             const float T = S::dec_T(tw);
             const bool clamped = S::clamp(tw);
             const float D0 = S::dec(((const W*)c.pD)[q]);
             const float D1 = S::dec(((const W*)c.pD)[c.pair_stride + q]);
             const float D2 = S::dec(((const W*)c.pD)[2 * c.pair_stride + q]);
             const int pl = c.ppix[q];
-            const float dx = (float)(pl % c.TW) + 0.5f - mlx, dy = (float)(pl / c.TW) + 0.5f - mly;
+            const float dx = (float)(pl & tw_mask) + 0.5f - mlx, dy = (float)(pl >> tw_shift) + 0.5f - mly;
             const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
             const float G = __expf(power);
             const float alpha = clamped ? 0.99f : o * G;
@@ -432,16 +452,19 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
     }
 }
 
+template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float* __restrict__ x,
                                                       const float* __restrict__ gram, float* __restrict__ M) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int P = 11 + 3 * K;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= c.N) return;
     double dgeo_acc[11];
 #pragma unroll
     for (int j = 0; j < 11; ++j) dgeo_acc[j] = 0.0;
-    double dsh[48];
-    for (int j = 0; j < 48; ++j) dsh[j] = 0.0;
-    const int K = (c.deg + 1) * (c.deg + 1);
+    double dsh[3 * K];
+#pragma unroll
+    for (int j = 0; j < 3 * K; ++j) dsh[j] = 0.0;
     const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
     for (uint32_t gv = b; gv < e; ++gv) {
         double H[kGram];
@@ -455,13 +478,14 @@ __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float*
         const int v = (int)(c.gv_rec[gv] / c.N);
         const CamDev& cam = c.cams[v];
         ProjFwd f;
-        proj_forward(cam, x, c.N, g, c.deg, f);
+        proj_forward<DEG>(cam, x, c.N, g, f);
+#pragma unroll
         for (int j = 0; j < 11; ++j) {
             double unit[11];
 #pragma unroll
             for (int i = 0; i < 11; ++i) unit[i] = i == j ? 1.0 : 0.0;
             double co[9];
-            proj_tangent(cam, f, unit, x, nullptr, c.N, g, c.deg, co);
+            proj_tangent<DEG>(cam, f, unit, x, nullptr, c.N, g, co);
             double q = 0.0;
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
@@ -473,23 +497,36 @@ __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float*
             q += H[39] * (co[6] * co[6] + co[7] * co[7] + co[8] * co[8]);
             dgeo_acc[j] += q;
         }
+#pragma unroll
         for (int k = 0; k < K; ++k)
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch)
-                if (!f.clamp[ch]) dsh[3 * k + ch] += f.Y[k] * f.Y[k] * H[39];
+                dsh[3 * k + ch] += f.clamp[ch] ? 0.0 : f.Y[k] * f.Y[k] * H[39];
     }
-    for (int j = 0; j < c.P; ++j) M[(int64_t)j * c.N + g] = (float)(j < 11 ? dgeo_acc[j] : dsh[j - 11]);
+#pragma unroll
+    for (int j = 0; j < P; ++j)
+        M[(int64_t)j * c.N + g] = (float)(j < 11 ? dgeo_acc[j < 11 ? j : 0] : dsh[j >= 11 ? j - 11 : 0]);
 }
 
 }  // namespace
 
+#define LM_DEG_SWITCH(deg, CALL) \
+    switch (deg) {               \
+        case 0: CALL(0); break;  \
+        case 1: CALL(1); break;  \
+        case 2: CALL(2); break;  \
+        default: CALL(3); break; \
+    }
+
 hipError_t launch_tangent(const ApplyArgs& a, hipStream_t s) {
-    hipLaunchKernelGGL(k_tangent, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a);
+#define LM_T(D) hipLaunchKernelGGL(k_tangent<D>, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a)
+    LM_DEG_SWITCH(a.c.deg, LM_T)
+#undef LM_T
     return hipGetLastError();
 }
 
 hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s) {
-    dim3 g((unsigned)a.c.n_tiles), b(kBlock);
+    dim3 g((unsigned)a.c.n_tiles), b(kThreads);
 #define LM_APPLY_CASE(MODE, DT) hipLaunchKernelGGL((k_apply_tile<MODE, DT>), g, b, 0, s, a)
     if (a.c.dtype == LM_CACHE_F32) {
         if (mode == MODE_J) LM_APPLY_CASE(MODE_J, LM_CACHE_F32);
@@ -510,8 +547,11 @@ hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s) {
 
 hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
                         double* pg_part, hipStream_t s) {
-    hipLaunchKernelGGL(k_chain, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, diag_floor, out,
-                       pg_part);
+#define LM_C(D)                                                                                                  \
+    hipLaunchKernelGGL(k_chain<D>, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, diag_floor, out, \
+                       pg_part)
+    LM_DEG_SWITCH(a.c.deg, LM_C)
+#undef LM_C
     return hipGetLastError();
 }
 
@@ -525,7 +565,9 @@ hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, f
         hipLaunchKernelGGL((k_gram_tile<LM_CACHE_BF16>), dim3((unsigned)c.n_tiles), b, 0, s, c, gram);
     else
         hipLaunchKernelGGL((k_gram_tile<LM_CACHE_F16>), dim3((unsigned)c.n_tiles), b, 0, s, c, gram);
-    hipLaunchKernelGGL(k_diag_gauss, dim3(grid_for(c.N)), b, 0, s, c, x, gram, M);
+#define LM_D(D) hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, x, gram, M)
+    LM_DEG_SWITCH(c.deg, LM_D)
+#undef LM_D
     return hipGetLastError();
 }
 

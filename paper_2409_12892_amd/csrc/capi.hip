@@ -99,7 +99,7 @@ using lm::DevBuf;
 struct lm_cache {
     int64_t N = 0;
     int P = 0, deg = 0, V = 0, TW = 16, TH = 16, dtype = LM_CACHE_F32;
-    int64_t n_tiles = 0, n_pix = 0, n_keys = 0, n_pairs = 0, n_seg = 0, n_gv = 0;
+    int64_t n_tiles = 0, n_pix = 0, n_keys = 0, n_pairs = 0, n_slots = 0, n_seg = 0, n_gv = 0;
     int64_t pair_stride = 8, seg_stride = 8;
     bool vals_in_alt = false;
     bool built = false;
@@ -109,6 +109,7 @@ struct lm_cache {
     DevBuf rec64, recf, rad, keycnt, keyoff;
     DevBuf keys, vals, keys_alt, vals_alt, sort_tmp, scan_tmp;
     DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
+    DevBuf tile_real, tile_real_off, run_seg;
     DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs;
     DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar;
@@ -119,13 +120,16 @@ struct lm_cache {
     lm::CacheView view() const {
         lm::CacheView c{};
         c.N = N; c.P = P; c.deg = deg; c.V = V; c.TW = TW; c.TH = TH; c.dtype = dtype;
+        c.tw_shift = 0;
+        while ((1 << c.tw_shift) < TW) ++c.tw_shift;
         c.n_tiles = n_tiles; c.n_pix = n_pix; c.n_seg = n_seg; c.n_gv = n_gv;
         c.cams = cams.as<lm::CamDev>();
         c.tile_view = tile_view.as<int32_t>();
         c.tile_pair_off = tile_pair_off.as<int64_t>();
         c.tile_seg_off = tile_seg_off.as<int64_t>();
         c.pT = pT.p; c.pD = pD.p; c.ppix = ppix.as<uint8_t>();
-        c.n_pairs = n_pairs; c.pair_stride = pair_stride;
+        c.n_pairs = n_slots; c.pair_stride = pair_stride;
+        c.run_seg = run_seg.as<uint32_t>();
         c.seg_gv = seg_gv.as<uint32_t>(); c.seg_loc = seg_loc.as<uint32_t>(); c.seg_f = seg_f.as<float>();
         c.seg_stride = seg_stride;
         c.gv_rec = gv_rec.as<uint32_t>(); c.gv_first = gv_first.as<uint32_t>();
@@ -146,7 +150,8 @@ struct lm_cache {
     size_t device_bytes() const {
         const DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt,
                                &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
-                               &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &gv_cnt, &gv_flag,
+                               &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
+                               &run_seg, &gv_cnt, &gv_flag,
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
@@ -158,7 +163,8 @@ struct lm_cache {
     void release_all() {
         DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt,
                          &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
-                         &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &gv_cnt, &gv_flag,
+                         &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
+                               &run_seg, &gv_cnt, &gv_flag,
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
@@ -193,6 +199,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
         dtype = opts->cache_dtype;
     }
     LM_CHECK(TW * TH <= kMaxTilePix && TW > 0 && TH > 0, LM_ERR_INVALID_ARG, "tile_w * tile_h must be 1..256");
+    LM_CHECK((TW & (TW - 1)) == 0, LM_ERR_INVALID_ARG, "tile_w must be a power of two");
     LM_CHECK(dtype == LM_CACHE_F32 || dtype == LM_CACHE_BF16 || dtype == LM_CACHE_F16, LM_ERR_INVALID_ARG,
              "cache_dtype must be LM_CACHE_F32, _BF16 or _F16");
     LM_CHECK(scene->N * (int64_t)V < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY, "N * V must fit in 32 bits");
@@ -283,6 +290,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->fsq_part.ensure(sizeof(double) * c->n_tiles));
     LM_HIP(c->tile_pairs.ensure(sizeof(uint32_t) * c->n_tiles));
     LM_HIP(c->tile_segs.ensure(sizeof(uint32_t) * c->n_tiles));
+    LM_HIP(c->tile_real.ensure(sizeof(uint32_t) * c->n_tiles));
     LM_HIP(c->gv_cnt.ensure(sizeof(uint32_t) * (R + 1)));
     LM_HIP(hipMemsetAsync(c->gv_cnt.p, 0, sizeof(uint32_t) * (R + 1), s));
     RasterArgs ra{};
@@ -300,6 +308,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     ra.fsq_part = c->fsq_part.as<double>();
     ra.tile_pairs = c->tile_pairs.as<uint32_t>();
     ra.tile_segs = c->tile_segs.as<uint32_t>();
+    ra.tile_real = c->tile_real.as<uint32_t>();
     ra.gv_cnt = c->gv_cnt.as<uint32_t>();
     ra.n_pix = c->n_pix;
     { LM_PROF("raster_count", s); LM_HIP(launch_raster(false, dtype, c->n_tiles, ra, s)); }
@@ -311,10 +320,13 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     const int64_t N = c->N, V = c->V, NV = N * V;
     LM_HIP(c->tile_pair_off.ensure(sizeof(uint64_t) * (c->n_tiles + 1)));
     LM_HIP(c->tile_seg_off.ensure(sizeof(uint64_t) * (c->n_tiles + 1)));
+    LM_HIP(c->tile_real_off.ensure(sizeof(uint64_t) * (c->n_tiles + 1)));
     LM_HIP(c->scan_tmp.ensure(std::max(scan_tmp_bytes(c->n_tiles), scan_tmp_bytes(NV)) + 1024));
     LM_HIP(exclusive_scan_u32_to_u64(c->tile_pairs.as<uint32_t>(), c->tile_pair_off.as<uint64_t>(), c->n_tiles,
                                      c->scan_tmp.p, c->scan_tmp.cap, s));
     LM_HIP(exclusive_scan_u32_to_u64(c->tile_segs.as<uint32_t>(), c->tile_seg_off.as<uint64_t>(), c->n_tiles,
+                                     c->scan_tmp.p, c->scan_tmp.cap, s));
+    LM_HIP(exclusive_scan_u32_to_u64(c->tile_real.as<uint32_t>(), c->tile_real_off.as<uint64_t>(), c->n_tiles,
                                      c->scan_tmp.p, c->scan_tmp.cap, s));
     LM_HIP(c->gv_flag.ensure(sizeof(uint32_t) * NV));
     LM_HIP(c->gv_idx.ensure(sizeof(uint64_t) * (NV + 1)));
@@ -324,12 +336,14 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
                                      c->scan_tmp.cap, s));
     LM_HIP(exclusive_scan_u32_to_u64(c->gv_cnt.as<uint32_t>(), c->gv_segoff.as<uint64_t>(), NV, c->scan_tmp.p,
                                      c->scan_tmp.cap, s));
-    uint64_t host3[3] = {0, 0, 0};
+    uint64_t host3[4] = {0, 0, 0, 0};
     LM_HIP(hipMemcpyAsync(&host3[0], c->tile_pair_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
     LM_HIP(hipMemcpyAsync(&host3[1], c->tile_seg_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
     LM_HIP(hipMemcpyAsync(&host3[2], c->gv_idx.as<uint64_t>() + NV, 8, hipMemcpyDeviceToHost, s));
+    LM_HIP(hipMemcpyAsync(&host3[3], c->tile_real_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
     LM_HIP(hipStreamSynchronize(s));
-    c->n_pairs = (int64_t)host3[0];
+    c->n_slots = (int64_t)host3[0];
+    c->n_pairs = (int64_t)host3[3];
     c->n_seg = (int64_t)host3[1];
     c->n_gv = (int64_t)host3[2];
     LM_CHECK(c->n_seg < (int64_t)0xFFFFFFFFu && c->n_gv < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY,
@@ -344,8 +358,9 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(launch_gv_compact(c->gv_cnt.as<uint32_t>(), c->gv_idx.as<uint64_t>(), c->gv_segoff.as<uint64_t>(), N,
                              (int)V, c->gv_rec.as<uint32_t>(), c->gv_seg_off.as<uint32_t>(),
                              c->gv_first.as<uint32_t>(), s));
-    // pair and segment arrays (planes padded so 8-wide vector loads stay inside)
-    c->pair_stride = round_up(c->n_pairs, 8) + 8;
+    // pair and segment arrays (planes padded so 8-wide vector loads stay inside);
+    // the zero fill doubles as the padding of every segment to a multiple of 8
+    c->pair_stride = round_up(c->n_slots, 8) + 8;
     c->seg_stride = round_up(nseg_a, 8);
     const size_t wb = dtype_bytes(c->dtype);
     LM_HIP(c->pT.ensure(wb * c->pair_stride));
@@ -354,6 +369,7 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(hipMemsetAsync(c->pT.p, 0, wb * c->pair_stride, s));
     LM_HIP(hipMemsetAsync(c->pD.p, 0, wb * 3 * c->pair_stride, s));
     LM_HIP(hipMemsetAsync(c->ppix.p, 0, c->pair_stride, s));
+    LM_HIP(c->run_seg.ensure(sizeof(uint32_t) * (c->pair_stride / 8)));
     LM_HIP(c->seg_gv.ensure(sizeof(uint32_t) * nseg_a));
     LM_HIP(c->seg_loc.ensure(sizeof(uint32_t) * nseg_a));
     LM_HIP(c->seg_f.ensure(sizeof(float) * 6 * c->seg_stride));
@@ -381,6 +397,7 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.seg_loc = c->seg_loc.as<uint32_t>();
     ra.seg_f = c->seg_f.as<float>();
     ra.seg_stride = c->seg_stride;
+    ra.run_seg = c->run_seg.as<uint32_t>();
     { LM_PROF("raster_fill", s); LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s)); }
     { LM_PROF("gv_sort", s); LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s)); }
     // product workspaces
@@ -467,12 +484,13 @@ lm_status lm_cache_get_info(const lm_cache* c, lm_cache_info* info) {
     info->N = c->N;
     info->n_keys = c->n_keys;
     info->n_pairs = c->n_pairs;
+    info->n_pair_slots = c->n_slots;
     info->n_segments = c->n_seg;
     info->n_gv = c->n_gv;
     info->n_pixels = c->n_pix;
     info->n_tiles = c->n_tiles;
     const int64_t wb = (int64_t)lm::dtype_bytes(c->dtype);
-    info->cache_bytes = c->n_pairs * (4 * wb + 1) + c->n_seg * (4 + 4 + 24);
+    info->cache_bytes = c->n_slots * (4 * wb + 1) + (c->n_slots / 8) * 4 + c->n_seg * (4 + 4 + 24);
     info->device_bytes = (int64_t)c->device_bytes();
     info->V = c->V;
     info->P = c->P;
@@ -509,8 +527,8 @@ lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) 
     lm::ApplyArgs a = c->apply_args();
     a.p = p;
     a.uout = u;
-    LM_HIP(lm::launch_tangent(a, S(stream)));
-    LM_HIP(lm::launch_apply_tile(1, a, S(stream)));
+    { LM_PROF("tangent", S(stream)); LM_HIP(lm::launch_tangent(a, S(stream))); }
+    { LM_PROF("apply_tile_J", S(stream)); LM_HIP(lm::launch_apply_tile(1, a, S(stream))); }
     return LM_OK;
 }
 
@@ -734,6 +752,23 @@ hipError_t fetch(std::vector<T>& out, const void* dev, int64_t n, hipStream_t s)
     return hipStreamSynchronize(s);
 }
 
+// Pair slots holding a pair, in slot order (the zero slots pad each segment
+// to a multiple of 8; a stored T is >= 1e-4, so its word is never zero).
+hipError_t live_slots(const lm_cache* c, std::vector<int64_t>& live, hipStream_t s) {
+    const size_t wb = lm::dtype_bytes(c->dtype);
+    std::vector<uint8_t> raw;
+    hipError_t e = fetch(raw, c->pT.p, (int64_t)wb * c->n_slots, s);
+    if (e != hipSuccess) return e;
+    live.clear();
+    live.reserve((size_t)c->n_pairs);
+    for (int64_t i = 0; i < c->n_slots; ++i) {
+        bool nz = false;
+        for (size_t b = 0; b < wb; ++b) nz |= raw[(size_t)i * wb + b] != 0;
+        if (nz) live.push_back(i);
+    }
+    return hipSuccess;
+}
+
 }  // namespace
 
 extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host_dst, int64_t bytes, void* stream) {
@@ -796,10 +831,12 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
         case LM_EXPORT_PAIR_FLAGS: {
             const size_t wb = lm::dtype_bytes(c->dtype);
             std::vector<uint8_t> raw;
-            LM_HIP(fetch(raw, c->pT.p, (int64_t)wb * c->n_pairs, s));
-            for (int64_t i = 0; i < c->n_pairs; ++i) {
+            std::vector<int64_t> live;
+            LM_HIP(live_slots(c, live, s));
+            LM_HIP(fetch(raw, c->pT.p, (int64_t)wb * c->n_slots, s));
+            for (size_t i = 0; i < live.size(); ++i) {
                 uint32_t fl = 0;
-                const float v = decode_word(raw.data(), c->dtype, i, &fl);
+                const float v = decode_word(raw.data(), c->dtype, live[i], &fl);
                 if (what == LM_EXPORT_PAIR_T) ((float*)host_dst)[i] = v;
                 else ((int32_t*)host_dst)[i] = (int32_t)fl;
             }
@@ -808,11 +845,13 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
         case LM_EXPORT_PAIR_D: {
             const size_t wb = lm::dtype_bytes(c->dtype);
             std::vector<uint8_t> raw;
+            std::vector<int64_t> live;
+            LM_HIP(live_slots(c, live, s));
             LM_HIP(fetch(raw, c->pD.p, (int64_t)wb * 3 * c->pair_stride, s));
             for (int ch = 0; ch < 3; ++ch)
-                for (int64_t i = 0; i < c->n_pairs; ++i)
-                    ((float*)host_dst)[ch * c->n_pairs + i] =
-                        decode_word(raw.data(), c->dtype, ch * c->pair_stride + i, nullptr);
+                for (size_t i = 0; i < live.size(); ++i)
+                    ((float*)host_dst)[ch * c->n_pairs + (int64_t)i] =
+                        decode_word(raw.data(), c->dtype, ch * c->pair_stride + live[i], nullptr);
             return LM_OK;
         }
         case LM_EXPORT_PAIR_PIX:
@@ -825,8 +864,13 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
             LM_HIP(fetch(sloc, c->seg_loc.p, c->n_seg, s));
             LM_HIP(fetch(sgv, c->seg_gv.p, c->n_seg, s));
             LM_HIP(fetch(gvrec, c->gv_rec.p, c->n_gv, s));
-            LM_HIP(fetch(pix, c->ppix.p, c->n_pairs, s));
+            LM_HIP(fetch(pix, c->ppix.p, c->n_slots, s));
+            std::vector<int64_t> live;
+            LM_HIP(live_slots(c, live, s));
+            std::vector<uint8_t> is_live((size_t)c->n_slots, 0);
+            for (int64_t q : live) is_live[(size_t)q] = 1;
             int32_t* o = (int32_t*)host_dst;
+            int64_t k = 0;
             int64_t t = 0;
             std::vector<int32_t> tview;
             for (int v = 0; v < c->V; ++v) {
@@ -842,12 +886,13 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
                     const uint64_t q1 = sI + 1 < tso[t + 1] ? tpo[t] + sloc[sI + 1] : tpo[t + 1];
                     const int32_t gid = (int32_t)(gvrec[sgv[sI]] % (uint64_t)c->N);
                     for (uint64_t q = q0; q < q1; ++q) {
+                        if (!is_live[q]) continue;
                         if (what == LM_EXPORT_PAIR_GAUSS) {
-                            o[q] = gid;
+                            o[k++] = gid;
                         } else {
                             const int pl = pix[q];
                             const int px = tx * c->TW + pl % c->TW, py = ty * c->TH + pl / c->TW;
-                            o[q] = (int32_t)(cam.pix_base + (int64_t)py * cam.W + px);
+                            o[k++] = (int32_t)(cam.pix_base + (int64_t)py * cam.W + px);
                         }
                     }
                 }

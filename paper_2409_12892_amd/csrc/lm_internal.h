@@ -45,6 +45,7 @@ struct CamDev {
 struct CacheView {
     int64_t N;
     int32_t P, deg, V, TW, TH, dtype;
+    int32_t tw_shift;            // log2(TW); tile widths are powers of two
     int64_t n_tiles, n_pix, n_seg, n_gv;
     const CamDev* cams;          // dev [V]
     const int32_t* tile_view;    // dev [n_tiles] view of each tile
@@ -53,12 +54,13 @@ struct CacheView {
     const void* pT;              // dev [n_pairs] cache words (float or 16-bit)
     const void* pD;              // dev [3][pair_stride]
     const uint8_t* ppix;         // dev [n_pairs] pixel-in-tile index
-    int64_t n_pairs;
+    int64_t n_pairs;             // pair slots including the zero padding of each segment to 8
     int64_t pair_stride;         // plane stride of pT/pD/ppix (>= n_pairs + 8, multiple of 8)
     const uint32_t* seg_gv;      // dev [n_seg] active (Gaussian, view) index
     const uint32_t* seg_loc;     // dev [n_seg] first pair, relative to the tile
     const float* seg_f;          // dev [6][seg_stride]: mean-in-tile x, y, A, B, C, opacity
     int64_t seg_stride;
+    const uint32_t* run_seg;     // dev [pair_stride / 8]: tile-local segment of each 8-pair run
     const uint32_t* gv_rec;      // dev [n_gv] record index v*N + g
     const uint32_t* gv_first;    // dev [N+1] first gv of each Gaussian
     const uint32_t* gv_seg_off;  // dev [n_gv+1]
@@ -161,8 +163,9 @@ struct RasterArgs {
     int32_t* ncontrib;         // [n_pix]
     float* resid;              // image layout
     double* fsq_part;          // [n_tiles]
-    uint32_t* tile_pairs;      // [n_tiles]
+    uint32_t* tile_pairs;      // [n_tiles] padded pair count
     uint32_t* tile_segs;       // [n_tiles]
+    uint32_t* tile_real;       // [n_tiles] real pair count
     uint32_t* gv_cnt;          // [N*V] segments per (g, v), index g*V + v
     int64_t n_pix;
     // fill pass
@@ -180,6 +183,7 @@ struct RasterArgs {
     uint32_t* seg_loc;
     float* seg_f;              // [6][seg_stride]
     int64_t seg_stride;
+    uint32_t* run_seg;         // [pair_stride / 8] tile-local segment of each aligned run
 };
 
 // Arguments of the product kernels (apply.hip).

@@ -31,20 +31,21 @@ constexpr double C3a = 0.5900435899266435, C3b = 2.890611442640554, C3c = 0.4570
 constexpr double C3d = 0.3731763325901154, C3e = 1.445305721320277;
 }  // namespace shc
 
-__device__ __forceinline__ void sh_eval(int deg, const double d[3], double Y[16]) {
+template <int deg>
+__device__ __forceinline__ void sh_eval(const double d[3], double Y[16]) {
     using namespace shc;
     const double x = d[0], y = d[1], z = d[2];
     Y[0] = C0;
-    if (deg < 1) return;
+    if constexpr (deg < 1) return;
     Y[1] = C1 * y; Y[2] = C1 * z; Y[3] = C1 * x;
-    if (deg < 2) return;
+    if constexpr (deg < 2) return;
     const double xx = x * x, yy = y * y, zz = z * z;
     Y[4] = C2a * x * y;
     Y[5] = C2a * y * z;
     Y[6] = C2b * (2.0 * zz - xx - yy);
     Y[7] = C2a * x * z;
     Y[8] = C2c * (xx - yy);
-    if (deg < 3) return;
+    if constexpr (deg < 3) return;
     Y[9] = C3a * y * (3.0 * xx - yy);
     Y[10] = C3b * x * y * z;
     Y[11] = C3c * y * (4.0 * zz - xx - yy);
@@ -55,21 +56,22 @@ __device__ __forceinline__ void sh_eval(int deg, const double d[3], double Y[16]
 }
 
 // dY[k] = grad Y_k(d) . v  (gradients of the polynomials above in R^3)
-__device__ __forceinline__ void sh_grad_dot(int deg, const double d[3], const double v[3], double dY[16]) {
+template <int deg>
+__device__ __forceinline__ void sh_grad_dot(const double d[3], const double v[3], double dY[16]) {
     using namespace shc;
     const double x = d[0], y = d[1], z = d[2];
     const double vx = v[0], vy = v[1], vz = v[2];
     dY[0] = 0.0;
-    if (deg < 1) return;
+    if constexpr (deg < 1) return;
     dY[1] = C1 * vy; dY[2] = C1 * vz; dY[3] = C1 * vx;
-    if (deg < 2) return;
+    if constexpr (deg < 2) return;
     const double xx = x * x, yy = y * y, zz = z * z;
     dY[4] = C2a * (y * vx + x * vy);
     dY[5] = C2a * (z * vy + y * vz);
     dY[6] = C2b * (-2.0 * x * vx - 2.0 * y * vy + 4.0 * z * vz);
     dY[7] = C2a * (z * vx + x * vz);
     dY[8] = C2c * (2.0 * x * vx - 2.0 * y * vy);
-    if (deg < 3) return;
+    if constexpr (deg < 3) return;
     dY[9] = C3a * (6.0 * x * y * vx + (3.0 * xx - 3.0 * yy) * vy);
     dY[10] = C3b * (y * z * vx + x * z * vy + x * y * vz);
     dY[11] = C3c * (-2.0 * x * y * vx + (4.0 * zz - xx - 3.0 * yy) * vy + 8.0 * y * z * vz);
@@ -80,20 +82,21 @@ __device__ __forceinline__ void sh_grad_dot(int deg, const double d[3], const do
 }
 
 // g = sum_k w[k] grad Y_k(d)
-__device__ __forceinline__ void sh_grad_weighted(int deg, const double d[3], const double w[16], double g[3]) {
+template <int deg>
+__device__ __forceinline__ void sh_grad_weighted(const double d[3], const double w[16], double g[3]) {
     using namespace shc;
     const double x = d[0], y = d[1], z = d[2];
     g[0] = g[1] = g[2] = 0.0;
-    if (deg < 1) return;
+    if constexpr (deg < 1) return;
     g[0] += C1 * w[3]; g[1] += C1 * w[1]; g[2] += C1 * w[2];
-    if (deg < 2) return;
+    if constexpr (deg < 2) return;
     const double xx = x * x, yy = y * y, zz = z * z;
     g[0] += C2a * y * w[4];                 g[1] += C2a * x * w[4];
     g[1] += C2a * z * w[5];                 g[2] += C2a * y * w[5];
     g[0] += -2.0 * C2b * x * w[6];          g[1] += -2.0 * C2b * y * w[6];   g[2] += 4.0 * C2b * z * w[6];
     g[0] += C2a * z * w[7];                 g[2] += C2a * x * w[7];
     g[0] += 2.0 * C2c * x * w[8];           g[1] += -2.0 * C2c * y * w[8];
-    if (deg < 3) return;
+    if constexpr (deg < 3) return;
     g[0] += C3a * 6.0 * x * y * w[9];       g[1] += C3a * (3.0 * xx - 3.0 * yy) * w[9];
     g[0] += C3b * y * z * w[10];            g[1] += C3b * x * z * w[10];     g[2] += C3b * x * y * w[10];
     g[0] += C3c * -2.0 * x * y * w[11];     g[1] += C3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
@@ -134,8 +137,9 @@ struct ProjFwd {
 };
 
 // x is the SoA parameter array [P][N]; g the Gaussian index.
+template <int deg>
 __device__ inline void proj_forward(const CamDev& cam, const float* __restrict__ x, int64_t N, int64_t g,
-                                    int deg, ProjFwd& f) {
+                                    ProjFwd& f) {
     double mu[3], s[3], q[4];
 #pragma unroll
     for (int i = 0; i < 3; ++i) mu[i] = (double)x[(int64_t)i * N + g];
@@ -210,11 +214,12 @@ __device__ inline void proj_forward(const CamDev& cam, const float* __restrict__
     f.dn = sqrt(dv[0] * dv[0] + dv[1] * dv[1] + dv[2] * dv[2]);
 #pragma unroll
     for (int i = 0; i < 3; ++i) f.d[i] = dv[i] / f.dn;
-    sh_eval(deg, f.d, f.Y);
-    const int K = (deg + 1) * (deg + 1);
+    sh_eval<deg>(f.d, f.Y);
+    constexpr int K = (deg + 1) * (deg + 1);
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         double acc = 0.5;
+#pragma unroll
         for (int k = 0; k < K; ++k) acc += f.Y[k] * (double)x[(int64_t)(11 + 3 * k + ch) * N + g];
         f.clamp[ch] = acc < 0.0;
         f.col[ch] = f.clamp[ch] ? 0.0 : acc;
@@ -224,9 +229,10 @@ __device__ inline void proj_forward(const CamDev& cam, const float* __restrict__
 // Forward-mode derivative of y along the parameter tangent (dgeo = d mean,
 // d log-scale, d quaternion, d opacity logit; dsh = tangent SoA array or
 // nullptr).  Writes the power-coefficient form described at the top.
+template <int deg>
 __device__ inline void proj_tangent(const CamDev& cam, const ProjFwd& f, const double dgeo[11],
                                     const float* __restrict__ x, const float* __restrict__ dsh, int64_t N,
-                                    int64_t g, int deg, double out[9]) {
+                                    int64_t g, double out[9]) {
     const double* R = cam.R;
     const double fx = cam.fx, fy = cam.fy, tz = f.t[2];
     double dt[3];
@@ -319,12 +325,13 @@ __device__ inline void proj_tangent(const CamDev& cam, const ProjFwd& f, const d
         dd[2] = (dm2 - f.d[2] * pr) / f.dn;
     }
     double dY[16];
-    sh_grad_dot(deg, f.d, dd, dY);
-    const int Kc = (deg + 1) * (deg + 1);
+    sh_grad_dot<deg>(f.d, dd, dY);
+    constexpr int Kc = (deg + 1) * (deg + 1);
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
         double v = 0.0;
         if (!f.clamp[ch]) {
+#pragma unroll
             for (int k = 0; k < Kc; ++k) {
                 const int64_t row = (int64_t)(11 + 3 * k + ch) * N + g;
                 v += dY[k] * (double)x[row];
@@ -337,27 +344,30 @@ __device__ inline void proj_tangent(const CamDev& cam, const ProjFwd& f, const d
 
 // Reverse mode: Gy = (G_mx, G_my, G_A, G_B, G_C, G_o, G_r, G_g, G_b) ->
 // accumulate into ggeo[11] and gsh[3K] (index 3k + ch).
+template <int deg>
 __device__ inline void proj_adjoint(const CamDev& cam, const ProjFwd& f, const double Gy[9],
-                                    const float* __restrict__ x, int64_t N, int64_t g, int deg,
+                                    const float* __restrict__ x, int64_t N, int64_t g,
                                     double ggeo[11], double* gsh) {
     const double* R = cam.R;
     const double fx = cam.fx, fy = cam.fy, tz = f.t[2];
     const double iz2 = 1.0 / (tz * tz);
     ggeo[10] += Gy[5] * f.o * (1.0 - f.o);
     // colour
-    const int Kc = (deg + 1) * (deg + 1);
+    constexpr int Kc = (deg + 1) * (deg + 1);
     double w[16];
+#pragma unroll
     for (int k = 0; k < 16; ++k) w[k] = 0.0;
 #pragma unroll
     for (int ch = 0; ch < 3; ++ch) {
-        if (f.clamp[ch]) continue;
+        const double gc = f.clamp[ch] ? 0.0 : Gy[6 + ch];
+#pragma unroll
         for (int k = 0; k < Kc; ++k) {
-            gsh[3 * k + ch] += Gy[6 + ch] * f.Y[k];
-            w[k] += Gy[6 + ch] * (double)x[(int64_t)(11 + 3 * k + ch) * N + g];
+            gsh[3 * k + ch] += gc * f.Y[k];
+            w[k] += gc * (double)x[(int64_t)(11 + 3 * k + ch) * N + g];
         }
     }
     double Gd[3];
-    sh_grad_weighted(deg, f.d, w, Gd);
+    sh_grad_weighted<deg>(f.d, w, Gd);
     {
         const double pr = f.d[0] * Gd[0] + f.d[1] * Gd[1] + f.d[2] * Gd[2];
 #pragma unroll

@@ -25,7 +25,8 @@ __device__ __forceinline__ void tile_rect(float mx, float my, int32_t radius, in
 }
 
 // rec64 layout [10][V*N]: mx, my, A, B, C, o, log threshold, r, g, b (float64)
-__global__ void k_project(const CamDev* __restrict__ cams, const float* __restrict__ x, int64_t N, int V, int deg,
+template <int deg>
+__global__ void k_project(const CamDev* __restrict__ cams, const float* __restrict__ x, int64_t N, int V,
                           int TW, int TH, double* __restrict__ rec64, float* __restrict__ recf,
                           int32_t* __restrict__ rad, uint32_t* __restrict__ keycnt) {
     const int64_t R = N * (int64_t)V;
@@ -35,7 +36,7 @@ __global__ void k_project(const CamDev* __restrict__ cams, const float* __restri
     const int64_t g = r - (int64_t)v * N;
     const CamDev& cam = cams[v];
     ProjFwd f;
-    proj_forward(cam, x, N, g, deg, f);
+    proj_forward<deg>(cam, x, N, g, f);
     uint32_t cnt = 0;
     const float mx32 = (float)f.mx, my32 = (float)f.my, z32 = (float)f.z;
     if (f.vis) {
@@ -99,8 +100,16 @@ __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
 hipError_t launch_project(const CamDev* cams, const float* x, int64_t N, int V, int deg, int TW, int TH,
                           double* rec64, float* recf, int32_t* rad, uint32_t* keycnt, hipStream_t s) {
     const int64_t R = N * (int64_t)V;
-    hipLaunchKernelGGL(k_project, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, x, N, V, deg, TW, TH, rec64, recf,
-                       rad, keycnt);
+    switch (deg) {
+        case 0: hipLaunchKernelGGL(k_project<0>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, x, N, V, TW, TH, rec64,
+                                   recf, rad, keycnt); break;
+        case 1: hipLaunchKernelGGL(k_project<1>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, x, N, V, TW, TH, rec64,
+                                   recf, rad, keycnt); break;
+        case 2: hipLaunchKernelGGL(k_project<2>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, x, N, V, TW, TH, rec64,
+                                   recf, rad, keycnt); break;
+        default: hipLaunchKernelGGL(k_project<3>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, x, N, V, TW, TH, rec64,
+                                    recf, rad, keycnt); break;
+    }
     return hipGetLastError();
 }
 

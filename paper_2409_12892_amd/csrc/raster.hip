@@ -18,7 +18,10 @@
 //   fill:  writes the cache in its final layout - per tile, active splats in
 //          depth order (segments), each segment's pairs in pixel order:
 //          T (with head/clamp flag bits), dC/dalpha (3 planes), pixel byte -
-//          plus the per-segment splat data and the (Gaussian,view) links.
+//          plus the per-segment splat data, the (Gaussian,view) links and
+//          the run -> segment table.  Every
+//          segment starts on a multiple of 8 pairs (zero padding), so each
+//          aligned run of 8 pairs belongs to one segment.
 // dC_ch/dalpha = T c_ch - S_ch/(1 - alpha) with S_ch the colour blended by
 // later splats, S_ch = C_ch(final) - (colour blended up to and including
 // this splat), all in float64.
@@ -41,9 +44,10 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     __shared__ uint8_t s_wc[kBlock][NW];       // count pass: contributing pixels per wave
     __shared__ uint32_t s_eoff[kBlock];        // fill pass: entry pair offset in tile
     __shared__ uint32_t s_wpre[kBlock];        // fill pass: packed per-wave prefixes
-    __shared__ uint32_t s_run[2];              // running pairs, running segments
+    __shared__ uint32_t s_run[3];              // running padded pairs, segments, real pairs
     __shared__ double s_red[kBlock / kWave];
     __shared__ uint32_t s_scan[NW];
+    __shared__ uint32_t s_real[NW];
 
     const int64_t t = blockIdx.x;
     const int v = a.tile_view[t];
@@ -68,7 +72,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         Ch1 = a.pixC[a.n_pix + pg];
         Ch2 = a.pixC[2 * a.n_pix + pg];
     }
-    if (tid < 2) s_run[tid] = 0;
+    if (tid < 3) s_run[tid] = 0;
     int64_t pair_base = 0, seg_base = 0, pair_end = 0, seg_end = 0;
     if (FILL) {
         pair_base = a.tile_pair_off[t];
@@ -94,7 +98,8 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             // segment records for the active entries
             uint32_t c = tid < nb ? a.entry_cnt[b0 + tid] : 0u;
             uint32_t tot = (c & 0xFF) + ((c >> 8) & 0xFF) + ((c >> 16) & 0xFF) + (c >> 24);
-            uint32_t packed = (tot << 10) | (tot > 0 ? 1u : 0u);
+            const uint32_t padded = (tot + 7u) & ~7u;
+            uint32_t packed = (padded << 10) | (tot > 0 ? 1u : 0u);
             // wave inclusive scan
             uint32_t inc = packed;
 #pragma unroll
@@ -134,6 +139,10 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     a.seg_f[5 * a.seg_stride + s] = (float)s_rec[5][tid];
                     const uint32_t slot = atomicAdd(&a.gv_cursor[gv], 1u);
                     if (a.gv_segoff[gvkey] + slot < a.gv_segoff[gvkey + 1]) a.gv_segs[a.gv_segoff[gvkey] + slot] = (uint32_t)s;
+                    // aligned runs of this segment -> its tile-local index
+                    const int64_t r0 = (pair_base + eoff) >> 3;
+                    const int64_t r1 = min((int64_t)(pair_base + eoff + padded), pair_end) >> 3;
+                    for (int64_t r = r0; r < r1; ++r) a.run_seg[r] = eseg;
                 }
             }
             __syncthreads();
@@ -205,17 +214,28 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 a.entry_cnt[b0 + tid] = packed;
                 if (tot > 0) atomicAdd(&a.gv_cnt[(int64_t)s_g[tid] * a.V + v], 1u);
             }
-            // block reduction of (pairs, active entries)
-            uint32_t val = (tot << 10) | (tot > 0 ? 1u : 0u);
+            // block reduction of (padded pairs, active entries) and of real pairs
+            uint32_t val = (((tot + 7u) & ~7u) << 10) | (tot > 0 ? 1u : 0u);
+            uint32_t real = tot;
 #pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) val += __shfl_xor(val, off, kWave);
-            if (lane == 0) s_scan[wid] = val;
+            for (int off = kWave / 2; off > 0; off >>= 1) {
+                val += __shfl_xor(val, off, kWave);
+                real += __shfl_xor(real, off, kWave);
+            }
+            if (lane == 0) {
+                s_scan[wid] = val;
+                s_real[wid] = real;
+            }
             __syncthreads();
             if (tid == 0) {
-                uint32_t sum = 0;
-                for (int w = 0; w < NW; ++w) sum += s_scan[w];
+                uint32_t sum = 0, rsum = 0;
+                for (int w = 0; w < NW; ++w) {
+                    sum += s_scan[w];
+                    rsum += s_real[w];
+                }
                 s_run[0] += sum >> 10;
                 s_run[1] += sum & 0x3FF;
+                s_run[2] += rsum;
             }
             __syncthreads();
         }
@@ -248,6 +268,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             a.fsq_part[t] = s;
             a.tile_pairs[t] = s_run[0];
             a.tile_segs[t] = s_run[1];
+            a.tile_real[t] = s_run[2];
         }
     }
 }
