@@ -15,15 +15,15 @@
 // Pair pass: one workgroup per tile.  Every segment (the pairs of one splat
 // in one tile, in pixel order) starts on a multiple of 8 pairs and is padded
 // with zero words, so each aligned run of 8 pairs belongs to exactly one
-// segment, named by the run -> segment table.  A lane takes one run (vector
-// loads of every cache plane, the next run prefetched while the current one
-// is processed), reads its segment's splat data once from LDS and
-//   J  : adds each pair's colour derivative to the pixel's LDS accumulator
-//        (pixel accumulators are padded by one word per 8 pixels, so the
-//        8-pair stride between neighbouring lanes does not hit one bank),
-//   J^T: sums the 9 moments of its 8 pairs in registers; a segmented scan over
-//        the wave (keyed by segment, runs ascending across lanes) leaves one
-//        LDS add per segment and wave.
+// segment, named by the run -> segment table.
+//   J  : a wave takes one segment at a time, one pair per lane; the pixels of
+//        a segment are distinct, so each wave adds the colour derivatives
+//        into private per-pixel LDS accumulators without atomics, and the
+//        waves' accumulators are summed at the end.
+//   J^T: a lane takes one 8-pair run (vector loads of every cache plane, the
+//        next run prefetched), sums the 9 moments of its run in registers; a
+//        segmented scan over the wave (keyed by segment, runs ascending
+//        across lanes) leaves one LDS add per segment and wave.
 // The fused J^T J pass keeps u in LDS between the two halves (every pixel's
 // splats live in its own tile), so u never reaches HBM.
 #include "proj_math.h"
@@ -31,7 +31,7 @@
 namespace lm {
 namespace {
 
-constexpr int kThreads = 512;  // threads per tile workgroup (8 wave64)
+constexpr int kThreads = 256;  // threads per tile workgroup (4 wave64)
 constexpr int kChunk = 256;    // segments staged per LDS chunk
 constexpr int kRun = 8;        // pairs per run (segments are padded to runs)
 // pixel accumulators: padded pixel slots [0, 287), a zero slot that is never
@@ -43,6 +43,45 @@ constexpr int kUTot = kUSink + kWave;
 constexpr int MODE_J = 1, MODE_JT = 2, MODE_JTJ = 3;
 
 __device__ __forceinline__ int upad(int pl) { return pl + (pl >> 3); }
+
+// Data-parallel-primitive lane moves (VALU, no LDS): lanes whose source is
+// outside the row or in a row not selected by ROWMASK read 0.
+template <int CTRL, int ROWMASK>
+__device__ __forceinline__ float dpp_mov(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
+}
+
+// Segmented inclusive sum across the wave: segments are contiguous lane
+// ranges and head is the first lane of this lane's segment; afterwards lane
+// l holds the sum over lanes [head, l].  Row shifts 1, 2, 4, 8 scan the rows
+// of 16; broadcasts of lane 15 (to rows 1, 3) and lane 31 (to rows 2, 3)
+// join the rows.
+template <int NV>
+__device__ __forceinline__ void wave_segmented_scan(float (&m)[NV], int lane, int head) {
+    const bool c1 = lane - 1 >= head, c2 = lane - 2 >= head, c4 = lane - 4 >= head, c8 = lane - 8 >= head;
+    const bool c16 = (lane & ~15) - 1 >= head, c32 = 31 >= head;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x111, 0xF>(m[k]); m[k] += c1 ? o : 0.0f; }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x112, 0xF>(m[k]); m[k] += c2 ? o : 0.0f; }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x114, 0xF>(m[k]); m[k] += c4 ? o : 0.0f; }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x118, 0xF>(m[k]); m[k] += c8 ? o : 0.0f; }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x142, 0xA>(m[k]); m[k] += c16 ? o : 0.0f; }
+#pragma unroll
+    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x143, 0xC>(m[k]); m[k] += c32 ? o : 0.0f; }
+}
+
+// First lane of this lane's segment, given per-lane segment keys that are
+// ascending across the wave.
+__device__ __forceinline__ int segment_head(uint32_t key, int lane) {
+    const uint32_t prev = __shfl_up(key, 1, kWave);
+    const uint64_t heads = __ballot(lane == 0 || prev != key);
+    const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
+    return kWave - 1 - __clzll(heads & upto);
+}
 
 template <int DT>
 struct RunLoad {
@@ -110,16 +149,39 @@ __global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
 }
 
 // ---- pair pass ---------------------------------------------------------------
+// Per pair, with the splat staged in LDS: alpha and dalpha/dy are recomputed
+// from the pixel position and the cached T, dC/dalpha give
+//   J row block . dy = D (dalpha/dy_geo . a) + alpha T dc      (a: power coefficients)
+template <int DT>
+struct PairLoad {
+    using W = typename Store<DT>::word;
+    W t, d0, d1, d2;
+    uint8_t pix;
+    __device__ __forceinline__ void load(const CacheView& c, int64_t q, bool live) {
+        t = 0; d0 = 0; d1 = 0; d2 = 0; pix = 0;
+        if (live) {
+            t = ((const W*)c.pT)[q];
+            d0 = ((const W*)c.pD)[q];
+            d1 = ((const W*)c.pD)[c.pair_stride + q];
+            d2 = ((const W*)c.pD)[2 * c.pair_stride + q];
+            pix = c.ppix[q];
+        }
+    }
+};
+
 template <int MODE, int DT>
 __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     if (a.stop && *a.stop) return;
     using S = Store<DT>;
+    constexpr int NW = kThreads / kWave;
     const CacheView& c = a.c;
-    __shared__ float s_u[3][kUTot];
-    __shared__ float s_seg[6][kChunk];
-    __shared__ float s_tan[9][kChunk];
+    // s_up[w]: wave w's private pixel accumulators in the J half; after the
+    // J half s_up[0] holds u (read by the J^T half)
+    __shared__ float s_up[NW][3][kUTot];
+    __shared__ float4 s_sg[kChunk][4];   // mx, my, A, B | C, o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
+    __shared__ uint32_t s_loc[kChunk + 1];
     __shared__ float s_mom[9][kChunk];
-    __shared__ double s_red[kThreads / kWave];
+    __shared__ double s_red[NW];
 
     const int64_t t = blockIdx.x;
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
@@ -136,81 +198,95 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
-    for (int i = tid; i < kUTot; i += kThreads)
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) s_u[ch][i] = 0.0f;
+    {
+        float* all = &s_up[0][0][0];
+        for (int i = tid; i < NW * 3 * kUTot; i += kThreads) all[i] = 0.0f;
+    }
     __syncthreads();
     if (MODE == MODE_JT && tid < kMaxTilePix && valid) {
 #pragma unroll
-        for (int ch = 0; ch < 3; ++ch) s_u[ch][upad(tid)] = a.uin[ib + ch * HW];
+        for (int ch = 0; ch < 3; ++ch) s_up[0][ch][upad(tid)] = a.uin[ib + ch * HW];
     }
 
-    // segments [c0, c0 + cn) of the tile: splat data (and tangents) into LDS;
-    // returns their runs [r0, r1) (segment offsets are multiples of kRun)
-    auto stage = [&](int c0, int cn, bool tangents, int64_t& r0, int64_t& r1) {
+    // segments [c0, c0 + cn) of the tile: splat data (and tangents) and pair
+    // ranges into LDS
+    auto stage = [&](int c0, int cn, bool tangents) {
         for (int i = tid; i < cn; i += kThreads) {
             const int64_t s = sb + c0 + i;
-#pragma unroll
-            for (int k = 0; k < 6; ++k) s_seg[k][i] = c.seg_f[(int64_t)k * c.seg_stride + s];
+            const int64_t ss = c.seg_stride;
+            s_sg[i][0] = make_float4(c.seg_f[s], c.seg_f[ss + s], c.seg_f[2 * ss + s], c.seg_f[3 * ss + s]);
+            float4 w1 = make_float4(c.seg_f[4 * ss + s], c.seg_f[5 * ss + s], 0.0f, 0.0f);
             if (tangents) {
-                const int64_t gv = c.seg_gv[s];
-#pragma unroll
-                for (int k = 0; k < 9; ++k) s_tan[k][i] = a.dyc[gv * 9 + k];
+                const float* dy = a.dyc + (int64_t)c.seg_gv[s] * 9;
+                w1.z = dy[0];
+                w1.w = dy[1];
+                s_sg[i][2] = make_float4(dy[2], dy[3], dy[4], dy[5]);
+                s_sg[i][3] = make_float4(dy[6], dy[7], dy[8], 0.0f);
             }
+            s_sg[i][1] = w1;
+            s_loc[i] = c.seg_loc[s];
         }
-        r0 = (pb + c.seg_loc[sb + c0]) / kRun;
-        r1 = (c0 + cn < nseg ? pb + c.seg_loc[sb + c0 + cn] : pe) / kRun;
+        if (tid == 0) s_loc[cn] = c0 + cn < nseg ? c.seg_loc[sb + c0 + cn] : (uint32_t)(pe - pb);
     };
 
     // ---------------- J p ----------------
+    // Wave w takes segments w, w + NW, ... of each chunk, 64 consecutive pairs
+    // (one per lane) at a time: the pixels of one segment are distinct, so
+    // the wave adds into its private accumulators without atomics.
     if (MODE & MODE_J) {
+        float* up = &s_up[wid][0][0];
         for (int c0 = 0; c0 < nseg; c0 += kChunk) {
             const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
-            int64_t r0, r1;
             __syncthreads();
-            stage(c0, cn, true, r0, r1);
+            stage(c0, cn, true);
             __syncthreads();
-            RunLoad<DT> nxt;
-            if (r0 + tid < r1) nxt.load(c, r0 + tid);
-            for (int64_t run = r0 + tid; run < r1; run += kThreads) {
-                const RunLoad<DT> L = nxt;
-                if (run + kThreads < r1) nxt.load(c, run + kThreads);
-                const int s = (int)L.seg - c0;
-                if ((unsigned)s >= (unsigned)cn) continue;   // never, for a consistent cache
-                const float mx = s_seg[0][s], my = s_seg[1][s], A = s_seg[2][s], B = s_seg[3][s];
-                const float C = s_seg[4][s], o = s_seg[5][s];
-                const float P1 = s_tan[0][s], P2 = s_tan[1][s], Q1 = s_tan[2][s], Q2 = s_tan[3][s];
-                const float Q3 = s_tan[4][s], dop = s_tan[5][s];
-                const float dc0 = s_tan[6][s], dc1 = s_tan[7][s], dc2 = s_tan[8][s];
-#pragma unroll
-                for (int k = 0; k < kRun; ++k) {
-                    const float T = S::dec_T(L.t[k]);
-                    const bool clamped = S::clamp(L.t[k]);
-                    const int pl = L.pix[k];
-                    const float dx = (float)(pl & tw_mask) + 0.5f - mx;
-                    const float dy = (float)(pl >> tw_shift) + 0.5f - my;
-                    const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
-                    const float G = __expf(power);
-                    const float alpha = clamped ? 0.99f : o * G;
-                    const float aT = alpha * T;
-                    const float dal_f = alpha * (dx * (P1 + Q1 * dx + Q2 * dy) + dy * (P2 + Q3 * dy)) + G * dop;
-                    const float dal = clamped ? 0.0f : dal_f;
-                    const int ui = L.t[k] != 0 ? upad(pl) : kUSink + lane;   // padding -> sink
-                    atomicAdd(&s_u[0][ui], S::dec(L.d[0][k]) * dal + aT * dc0);
-                    atomicAdd(&s_u[1][ui], S::dec(L.d[1][k]) * dal + aT * dc1);
-                    atomicAdd(&s_u[2][ui], S::dec(L.d[2][k]) * dal + aT * dc2);
+            int i = wid;
+            uint32_t off = 0;
+            PairLoad<DT> nxt;
+            if (i < cn) nxt.load(c, pb + s_loc[i] + lane, (uint32_t)lane < s_loc[i + 1] - s_loc[i]);
+            while (i < cn) {
+                const PairLoad<DT> L = nxt;
+                const int si = i;
+                if (off + kWave < s_loc[i + 1] - s_loc[i]) {
+                    off += kWave;
+                } else {
+                    i += NW;
+                    off = 0;
                 }
+                if (i < cn) nxt.load(c, pb + s_loc[i] + off + lane, off + lane < s_loc[i + 1] - s_loc[i]);
+                const float4 g0 = s_sg[si][0], g1 = s_sg[si][1], g2 = s_sg[si][2], g3 = s_sg[si][3];
+                const float T = S::dec_T(L.t);
+                const bool clamped = S::clamp(L.t);
+                const int pl = L.pix;
+                const float dx = (float)(pl & tw_mask) + 0.5f - g0.x;
+                const float dy = (float)(pl >> tw_shift) + 0.5f - g0.y;
+                const float power = -0.5f * (g0.z * dx * dx + g1.x * dy * dy) - g0.w * dx * dy;
+                const float G = __expf(power);
+                const float alpha = clamped ? 0.99f : g1.y * G;
+                const float aT = alpha * T;
+                const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
+                const float dal = clamped ? 0.0f : dal_f;
+                const int ui = L.t != 0 ? upad(pl) : kUSink + lane;   // padding or no pair -> sink
+                up[ui] += S::dec(L.d0) * dal + aT * g3.x;
+                up[kUTot + ui] += S::dec(L.d1) * dal + aT * g3.y;
+                up[2 * kUTot + ui] += S::dec(L.d2) * dal + aT * g3.z;
             }
         }
         __syncthreads();
-        // ||J p||^2 of the tile, and u itself for the J-only product
+        // u = sum of the waves' accumulators; ||J p||^2 of the tile
         double sq = 0.0;
-        if (tid < kMaxTilePix && valid) {
+        if (tid < kMaxTilePix) {
+            const int ui = upad(tid);
 #pragma unroll
             for (int ch = 0; ch < 3; ++ch) {
-                const float u = s_u[ch][upad(tid)];
-                sq += (double)u * (double)u;
-                if (MODE == MODE_J) a.uout[ib + ch * HW] = u;
+                float u = 0.0f;
+#pragma unroll
+                for (int w = 0; w < NW; ++w) u += s_up[w][ch][ui];
+                s_up[0][ch][ui] = u;
+                if (valid) {
+                    sq += (double)u * (double)u;
+                    if (MODE == MODE_J) a.uout[ib + ch * HW] = u;
+                }
             }
         }
 #pragma unroll
@@ -219,7 +295,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
         __syncthreads();
         if (tid == 0) {
             double tot = 0.0;
-            for (int w = 0; w < kThreads / kWave; ++w) tot += s_red[w];
+            for (int w = 0; w < NW; ++w) tot += s_red[w];
             a.jp_part[t] = tot;
         }
         if (MODE == MODE_J) return;
@@ -228,13 +304,13 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     // ---------------- J^T u ----------------
     for (int c0 = 0; c0 < nseg; c0 += kChunk) {
         const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
-        int64_t r0, r1;
         __syncthreads();
-        stage(c0, cn, false, r0, r1);
+        stage(c0, cn, false);
         for (int i = tid; i < cn; i += kThreads)
 #pragma unroll
             for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
         __syncthreads();
+        const int64_t r0 = (pb + s_loc[0]) / kRun, r1 = (pb + s_loc[cn]) / kRun;
         RunLoad<DT> nxt;
         if (r0 + tid < r1) nxt.load(c, r0 + tid);
         // every lane runs every round (converged for the wave scan); lanes
@@ -244,14 +320,14 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
             const bool has = run < r1;
             const RunLoad<DT> L = nxt;
             if (run + kThreads < r1) nxt.load(c, run + kThreads);
-            int s = has ? (int)L.seg - c0 : kChunk;
-            if ((unsigned)s >= (unsigned)cn) s = kChunk;    // no run, or an inconsistent cache
+            const int64_t sl = (int64_t)L.seg - (sb + c0);
+            const int s = (has && sl >= 0 && sl < cn) ? (int)sl : kChunk;   // kChunk: no run (or an inconsistent cache)
             float m[9];
 #pragma unroll
             for (int k = 0; k < 9; ++k) m[k] = 0.0f;
             if (s < kChunk) {
-                const float mx = s_seg[0][s], my = s_seg[1][s], A = s_seg[2][s], B = s_seg[3][s];
-                const float C = s_seg[4][s], o = s_seg[5][s];
+                const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
+                const float mx = g0.x, my = g0.y, A = g0.z, B = g0.w, C = g1.x, o = g1.y;
 #pragma unroll
                 for (int k = 0; k < kRun; ++k) {
                     const float T = S::dec_T(L.t[k]);
@@ -264,7 +340,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
                     const float alpha = clamped ? 0.99f : o * G;
                     const float aT = alpha * T;                               // 0 for padding
                     const int ui = L.t[k] != 0 ? upad(pl) : kUZero;           // padding reads u = 0
-                    const float u0 = s_u[0][ui], u1 = s_u[1][ui], u2 = s_u[2][ui];
+                    const float u0 = s_up[0][0][ui], u1 = s_up[0][1][ui], u2 = s_up[0][2][ui];
                     const float w = S::dec(L.d[0][k]) * u0 + S::dec(L.d[1][k]) * u1 + S::dec(L.d[2][k]) * u2;
                     const float aw = clamped ? 0.0f : alpha * w;
                     const float awx = aw * dx, awy = aw * dy;
@@ -279,21 +355,10 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
                     m[8] += aT * u2;
                 }
             }
-            // segmented inclusive scan over the wave: runs ascend with the
-            // lane, so each segment is a contiguous lane range [head, tail]
-            const int prev = __shfl_up(s, 1, kWave);
+            // segmented scan over the wave: runs ascend with the lane, so each
+            // segment is a contiguous lane range; its last lane adds the sum
             const int next = __shfl_down(s, 1, kWave);
-            const uint64_t heads = __ballot(lane == 0 || prev != s);
-            const uint64_t upto = lane == kWave - 1 ? ~0ull : ((2ull << lane) - 1ull);
-            const int head = kWave - 1 - __clzll(heads & upto);
-#pragma unroll
-            for (int off = 1; off < kWave; off <<= 1) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) {
-                    const float o = __shfl_up(m[k], off, kWave);
-                    if (lane - off >= head) m[k] += o;
-                }
-            }
+            wave_segmented_scan<9>(m, lane, segment_head((uint32_t)s, lane));
             if (s < kChunk && (lane == kWave - 1 || next != s)) {
 #pragma unroll
                 for (int k = 0; k < 9; ++k) atomicAdd(&s_mom[k][s], m[k]);
@@ -383,52 +448,51 @@ constexpr int kGram = 40;
 
 __device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i * (i - 1)) / 2 + (k - i); }
 
+// One lane per aligned 8-pair run of the whole cache.  A segment's runs
+// are adjacent, so after a segmented scan across the wave the last lane of
+// each segment piece holds the piece's sums: a piece that is a whole segment
+// is stored, a piece of a segment that spans waves is added atomically
+// (gram is zero-filled before).
 template <int DT>
-__global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __restrict__ gram) {
+__global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_runs, float* __restrict__ gram) {
     using S = Store<DT>;
-    using W = typename S::word;
-    const int64_t t = blockIdx.x;
-    const int lane = __lane_id(), wid = threadIdx.x / kWave;
-    const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
-    const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
+    const int64_t run = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int lane = __lane_id();
     const int tw_mask = c.TW - 1, tw_shift = c.tw_shift;
-    for (int64_t s = sb + wid; s < se; s += kBlock / kWave) {
-        const int64_t ss = c.seg_stride;
-        const float mlx = c.seg_f[s], mly = c.seg_f[ss + s];
-        const float A = c.seg_f[2 * ss + s], B = c.seg_f[3 * ss + s], C = c.seg_f[4 * ss + s];
-        const float o = c.seg_f[5 * ss + s];
-        const int64_t q0 = pb + c.seg_loc[s];
-        const int64_t q1 = (s + 1 < se) ? pb + c.seg_loc[s + 1] : pe;
-        float acc[kGram];
+    const bool has = run < n_runs;
+    float acc[kGram];
 #pragma unroll
-        for (int k = 0; k < kGram; ++k) acc[k] = 0.0f;
-        for (int64_t q = q0 + lane; q < q1; q += kWave) {
-            const W tw = ((const W*)c.pT)[q];
-            if (tw == 0) continue;                   // padding
-            const float T = S::dec_T(tw);
-            const bool clamped = S::clamp(tw);
-            const float D0 = S::dec(((const W*)c.pD)[q]);
-            const float D1 = S::dec(((const W*)c.pD)[c.pair_stride + q]);
-            const float D2 = S::dec(((const W*)c.pD)[2 * c.pair_stride + q]);
-            const int pl = c.ppix[q];
+    for (int k = 0; k < kGram; ++k) acc[k] = 0.0f;
+    uint32_t key = 0xFFFFFFFFu;
+    if (has) {
+        RunLoad<DT> L;
+        L.load(c, run);
+        key = L.seg;
+        const int64_t ss = c.seg_stride, sg = L.seg;
+        const float mlx = c.seg_f[sg], mly = c.seg_f[ss + sg];
+        const float A = c.seg_f[2 * ss + sg], B = c.seg_f[3 * ss + sg], C = c.seg_f[4 * ss + sg];
+        const float o = c.seg_f[5 * ss + sg];
+#pragma unroll
+        for (int k = 0; k < kRun; ++k) {
+            const bool live = L.t[k] != 0;                  // padding contributes nothing
+            const float T = S::dec_T(L.t[k]);
+            const bool clamped = S::clamp(L.t[k]);
+            const float D0 = S::dec(L.d[0][k]), D1 = S::dec(L.d[1][k]), D2 = S::dec(L.d[2][k]);
+            const int pl = L.pix[k];
             const float dx = (float)(pl & tw_mask) + 0.5f - mlx, dy = (float)(pl >> tw_shift) + 0.5f - mly;
             const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
             const float G = __expf(power);
             const float alpha = clamped ? 0.99f : o * G;
-            const float e = alpha * T;
+            const float e = live ? alpha * T : 0.0f;
+            const float ag = (clamped || !live) ? 0.0f : alpha;
             float bb[6];
-            if (clamped) {
-#pragma unroll
-                for (int i = 0; i < 6; ++i) bb[i] = 0.0f;
-            } else {
-                bb[0] = alpha * dx; bb[1] = alpha * dy; bb[2] = alpha * dx * dx;
-                bb[3] = alpha * dx * dy; bb[4] = alpha * dy * dy; bb[5] = G;
-            }
+            bb[0] = ag * dx; bb[1] = ag * dy; bb[2] = ag * dx * dx;
+            bb[3] = ag * dx * dy; bb[4] = ag * dy * dy; bb[5] = (clamped || !live) ? 0.0f : G;
             const float DD = D0 * D0 + D1 * D1 + D2 * D2;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
 #pragma unroll
-                for (int k = i; k < 6; ++k) acc[tri6(i, k)] += DD * bb[i] * bb[k];
+                for (int j = i; j < 6; ++j) acc[tri6(i, j)] += DD * bb[i] * bb[j];
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
                 const float eb = e * bb[i];
@@ -438,18 +502,28 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
             }
             acc[39] += e * e;
         }
+    }
+    const uint32_t next = __shfl_down(key, 1, kWave);
+    const int head = segment_head(key, lane);
+    wave_segmented_scan<kGram>(acc, lane, head);
+    if (has && (lane == kWave - 1 || next != key)) {
+        const int64_t first = run - (lane - head);
+        const bool starts = head > 0 || first == 0 || c.run_seg[first - 1] != key;
+        const bool ends = lane < kWave - 1 || run + 1 >= n_runs || c.run_seg[run + 1] != key;
+        float* out = gram + (int64_t)key * kGram;
+        if (starts && ends) {
 #pragma unroll
-        for (int k = 0; k < kGram; ++k) {
-            float vsum = acc[k];
+            for (int k = 0; k < kGram; ++k) out[k] = acc[k];
+        } else {
 #pragma unroll
-            for (int off = kWave / 2; off > 0; off >>= 1) vsum += __shfl_xor(vsum, off, kWave);
-            acc[k] = vsum;
-        }
-        if (lane == 0) {
-#pragma unroll
-            for (int k = 0; k < kGram; ++k) gram[s * kGram + k] = acc[k];
+            for (int k = 0; k < kGram; ++k) unsafeAtomicAdd(out + k, acc[k]);
         }
     }
+}
+
+__global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
 }
 
 template <int DEG>
@@ -559,12 +633,18 @@ unsigned chain_blocks(int64_t N) { return grid_for(N); }
 
 hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, float* M, hipStream_t s) {
     dim3 b(kBlock);
-    if (c.dtype == LM_CACHE_F32)
-        hipLaunchKernelGGL((k_gram_tile<LM_CACHE_F32>), dim3((unsigned)c.n_tiles), b, 0, s, c, gram);
-    else if (c.dtype == LM_CACHE_BF16)
-        hipLaunchKernelGGL((k_gram_tile<LM_CACHE_BF16>), dim3((unsigned)c.n_tiles), b, 0, s, c, gram);
-    else
-        hipLaunchKernelGGL((k_gram_tile<LM_CACHE_F16>), dim3((unsigned)c.n_tiles), b, 0, s, c, gram);
+    const int64_t n_runs = c.n_pairs / kRun;
+    const int64_t ng = (int64_t)kGram * (c.n_seg > 0 ? c.n_seg : 1);
+    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(ng)), b, 0, s, gram, ng, 0.0f);
+    if (n_runs > 0) {
+        const dim3 g(grid_for(n_runs));
+        if (c.dtype == LM_CACHE_F32)
+            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F32>), g, b, 0, s, c, n_runs, gram);
+        else if (c.dtype == LM_CACHE_BF16)
+            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_BF16>), g, b, 0, s, c, n_runs, gram);
+        else
+            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram);
+    }
 #define LM_D(D) hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, x, gram, M)
     LM_DEG_SWITCH(c.deg, LM_D)
 #undef LM_D

@@ -60,7 +60,7 @@ struct CacheView {
     const uint32_t* seg_loc;     // dev [n_seg] first pair, relative to the tile
     const float* seg_f;          // dev [6][seg_stride]: mean-in-tile x, y, A, B, C, opacity
     int64_t seg_stride;
-    const uint32_t* run_seg;     // dev [pair_stride / 8]: tile-local segment of each 8-pair run
+    const uint32_t* run_seg;     // dev [pair_stride / 8]: segment of each aligned 8-pair run
     const uint32_t* gv_rec;      // dev [n_gv] record index v*N + g
     const uint32_t* gv_first;    // dev [N+1] first gv of each Gaussian
     const uint32_t* gv_seg_off;  // dev [n_gv+1]
@@ -183,7 +183,7 @@ struct RasterArgs {
     uint32_t* seg_loc;
     float* seg_f;              // [6][seg_stride]
     int64_t seg_stride;
-    uint32_t* run_seg;         // [pair_stride / 8] tile-local segment of each aligned run
+    uint32_t* run_seg;         // [pair_stride / 8] segment of each aligned 8-pair run
 };
 
 // Arguments of the product kernels (apply.hip).

@@ -139,10 +139,10 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     a.seg_f[5 * a.seg_stride + s] = (float)s_rec[5][tid];
                     const uint32_t slot = atomicAdd(&a.gv_cursor[gv], 1u);
                     if (a.gv_segoff[gvkey] + slot < a.gv_segoff[gvkey + 1]) a.gv_segs[a.gv_segoff[gvkey] + slot] = (uint32_t)s;
-                    // aligned runs of this segment -> its tile-local index
+                    // aligned runs of this segment -> its index
                     const int64_t r0 = (pair_base + eoff) >> 3;
                     const int64_t r1 = min((int64_t)(pair_base + eoff + padded), pair_end) >> 3;
-                    for (int64_t r = r0; r < r1; ++r) a.run_seg[r] = eseg;
+                    for (int64_t r = r0; r < r1; ++r) a.run_seg[r] = (uint32_t)s;
                 }
             }
             __syncthreads();
