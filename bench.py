@@ -81,6 +81,61 @@ def read_traffic(alg_bytes: int):
         return None
 
 
+COPY_BYTES = 256 * 1024 * 1024
+
+
+def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str) -> dict:
+    """HBM traffic of the fused J^T J tile pass from two rocprofv3 --pmc runs
+    of `bench.py --copy-calibration` (one with FETCH_SIZE, one with
+    WRITE_SIZE).  Each counter is summed over its instances per dispatch and
+    averaged over the dispatches of the kernel; the plain 256 MiB device copy
+    of the same run gives the scale of each counter (true bytes / counted
+    bytes).  Writes the summary read by read_traffic()."""
+    import csv
+    import glob
+
+    def per_dispatch(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            rows += list(csv.DictReader(open(f)))
+        disp = {}
+        for r in rows:
+            if r["Counter_Name"] != counter:
+                continue
+            key = (int(r["Dispatch_Id"]), r["Kernel_Name"])
+            disp[key] = disp.get(key, 0.0) + float(r["Counter_Value"])
+        return sorted(disp.items())
+
+    def mean(vals):
+        return (sum(vals) / len(vals), len(vals)) if vals else (None, 0)
+
+    res = {}
+    for tag, d, ctr in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        disp = per_dispatch(d, ctr)
+        a, na = mean([v for (_, name), v in disp if "k_apply_tile<3," in name])
+        # the calibration copies are the run's last three device copies
+        cp, nc = mean([v for (_, name), v in disp if "copyBuffer" in name][-3:])
+        if a is None or cp is None:
+            raise SystemExit(f"{ctr}: apply dispatches {na}, copy dispatches {nc} in {d}")
+        scale = COPY_BYTES / (cp * 1024.0)
+        res[tag] = dict(kib_per_launch=a, launches=na, copy_kib=cp, copy_launches=nc, scale=scale,
+                        bytes_per_launch=a * 1024.0 * scale)
+    total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
+    src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
+    with open(out_path, "w") as f:
+        f.write("# HBM traffic of k_apply_tile<J^T J fused, float32 cache> at the paper workload\n")
+        f.write(f"# command: {command}\n")
+        for tag in ("fetch", "write"):
+            r = res[tag]
+            f.write(f"# {tag}: {r['kib_per_launch']:.1f} KiB counted per launch over {r['launches']} launches; "
+                    f"256 MiB copy counted {r['copy_kib']:.1f} KiB -> scale {r['scale']:.3f}\n")
+        f.write(f"apply_src_sha256={src}\n")
+        f.write(f"fetch_bytes_per_launch={res['fetch']['bytes_per_launch']:.0f}\n")
+        f.write(f"write_bytes_per_launch={res['write']['bytes_per_launch']:.0f}\n")
+        f.write(f"traffic_bytes_per_launch={total:.0f}\n")
+    return res
+
+
 def cpu_baseline(scene, cams, n_pairs_per_apply: int, tile: int = 16, crop: int = 64, reps: int = 3) -> dict:
     """The FP64 oracle, as it stands, on a bounded sample of the same
     workload: a crop x crop pixel window at the centre of view 0 (all
@@ -127,7 +182,17 @@ def main() -> int:
     ap.add_argument("--N", type=int, default=None, help="override the number of Gaussians")
     ap.add_argument("--views", type=int, default=None, help="override the views of the subset")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="after the timed steps, copy 256 MiB device to device three times (the "
+                         "reference kernel for rocprofv3 byte counters)")
+    ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
+    ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
     args = ap.parse_args()
+    if args.summarize_pmc:
+        res = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_FILE, args.pmc_command)
+        print(json.dumps(res))
+        return 0
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -186,6 +251,13 @@ def main() -> int:
     t1 = time.perf_counter()
     B.lm_profile_enable(False)
     prof = B.lm_profile_read()
+    if args.copy_calibration:
+        src_buf = torch.empty(COPY_BYTES // 4, device=dev)
+        dst_buf = torch.empty_like(src_buf)
+        for _ in range(3):
+            dst_buf.copy_(src_buf)
+        torch.cuda.synchronize()
+        del src_buf, dst_buf
     info = solver.cache.info()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
     applies = (n_iters + 2) * args.steps
