@@ -8,9 +8,11 @@
 // with D = dC/dalpha and T read from the cache and alpha, dalpha/dy_geo
 // recomputed from the staged splat (mean, conic, opacity) and the pixel.
 // The splat-to-parameter factor dy/dx is applied per (Gaussian, view): the
-// tangent kernel maps p to per-(Gaussian,view) power coefficients before the
-// pair pass, the chain kernel maps per-(Gaussian,view) moments back to the
-// parameters after it (supplement A.2 splits applyJT the same way).
+// projection is linearised once per cache (float64, stored as float32), the
+// tangent kernel maps p through it to per-(Gaussian,view) power coefficients
+// before the pair pass, and the chain kernel applies its transpose to the
+// per-(Gaussian,view) moments after it (supplement A.2 splits applyJT the
+// same way).
 //
 // Pair pass: one workgroup per tile.  Every segment (the pairs of one splat
 // in one tile, in pixel order) starts on a multiple of 8 pairs and is padded
@@ -124,28 +126,75 @@ struct RunLoad {
     }
 };
 
+// ---- linearisation: the projection of every (Gaussian, view) at x ----------
+// Columns of the tangent map (unit tangents of the 11 geometric parameters)
+// in float64, stored as float32; the SH part is the basis itself.
+template <int DEG>
+__global__ void __launch_bounds__(kBlock) k_linearize(CacheView c, const float* __restrict__ x,
+                                                     float* __restrict__ lin) {
+    const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gv >= c.n_gv) return;
+    const uint32_t rec = c.gv_rec[gv];
+    const int v = (int)(rec / c.N);
+    const int64_t g = rec - (int64_t)v * c.N;
+    const CamDev& cam = c.cams[v];
+    ProjFwd f;
+    proj_forward<DEG>(cam, x, c.N, g, f);
+    const int64_t ls = c.lin_stride;
+#pragma unroll 1
+    for (int j = 0; j < 11; ++j) {
+        double unit[11];
+#pragma unroll
+        for (int i = 0; i < 11; ++i) unit[i] = i == j ? 1.0 : 0.0;
+        double co[9];
+        proj_tangent<DEG>(cam, f, unit, x, nullptr, c.N, g, co);
+#pragma unroll
+        for (int i = 0; i < 6; ++i) lin[(int64_t)(kLinL + 11 * i + j) * ls + gv] = (float)co[i];
+        if (j < 3) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) lin[(int64_t)(kLinJdir + 3 * ch + j) * ls + gv] = (float)co[6 + ch];
+        }
+    }
+#pragma unroll
+    for (int k = 0; k < 16; ++k) lin[(int64_t)(kLinY + k) * ls + gv] = k < (DEG + 1) * (DEG + 1) ? (float)f.Y[k] : 0.0f;
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) lin[(int64_t)(kLinMask + ch) * ls + gv] = f.clamp[ch] ? 0.0f : 1.0f;
+}
+
 // ---- tangent: p -> per-(Gaussian, view) power coefficients -------------------
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
     if (a.stop && *a.stop) return;
+    constexpr int K = (DEG + 1) * (DEG + 1);
     const CacheView& c = a.c;
-    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (g >= c.N) return;
-    const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
-    if (b == e) return;
-    double dgeo[11];
+    const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gv >= c.n_gv) return;
+    const int64_t g = c.gv_rec[gv] % (uint32_t)c.N;
+    const int64_t ls = c.lin_stride, N = c.N;
+    float dgeo[11];
 #pragma unroll
-    for (int j = 0; j < 11; ++j) dgeo[j] = (double)a.p[(int64_t)j * c.N + g];
-    for (uint32_t gv = b; gv < e; ++gv) {
-        const int v = (int)(c.gv_rec[gv] / c.N);
-        const CamDev& cam = c.cams[v];
-        ProjFwd f;
-        proj_forward<DEG>(cam, a.x, c.N, g, f);
-        double out[9];
-        proj_tangent<DEG>(cam, f, dgeo, a.x, a.p, c.N, g, out);
+    for (int j = 0; j < 11; ++j) dgeo[j] = a.p[(int64_t)j * N + g];
+    float out[9];
 #pragma unroll
-        for (int k = 0; k < 9; ++k) a.dyc[(int64_t)gv * 9 + k] = (float)out[k];
+    for (int i = 0; i < 6; ++i) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < 11; ++j) acc += (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv] * (double)dgeo[j];
+        out[i] = (float)acc;
     }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        double acc = 0.0;
+#pragma unroll
+        for (int m = 0; m < 3; ++m) acc += (double)c.lin[(int64_t)(kLinJdir + 3 * ch + m) * ls + gv] * (double)dgeo[m];
+        double sh = 0.0;
+#pragma unroll
+        for (int k = 0; k < K; ++k)
+            sh += (double)c.lin[(int64_t)(kLinY + k) * ls + gv] * (double)a.p[(int64_t)(11 + 3 * k + ch) * N + g];
+        out[6 + ch] = (float)(acc + (double)c.lin[(int64_t)(kLinMask + ch) * ls + gv] * sh);
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) a.dyc[gv * 9 + k] = out[k];
 }
 
 // ---- pair pass ---------------------------------------------------------------
@@ -372,8 +421,82 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     }
 }
 
+// ---- per-(Gaussian, view) sums of per-segment values ---------------------------
+// The segment list grouped by (Gaussian, view) (gv_segs, ascending gv) is
+// reduced with one lane per list entry and a segmented scan across each
+// wave.  A group that lies inside one wave is written directly; a gv whose
+// list crosses waves leaves a piece in each wave (the wave's last group, or
+// its first group), and k_gv_reduce_join adds the pieces in wave order.  The
+// result does not depend on scheduling.
+constexpr uint32_t kNoGv = 0xFFFFFFFFu;
+
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gv_reduce(CacheView c, const float* __restrict__ src,
+                                                     float* __restrict__ dst, float* __restrict__ edge,
+                                                     uint32_t* __restrict__ edge_key) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    const int64_t w = i / kWave;
+    const int lane = __lane_id();
+    const bool has = i < c.n_seg;
+    float v[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0f;
+    uint32_t key = kNoGv;
+    if (has) {
+        const int64_t sg = c.gv_segs[i];
+        key = c.seg_gv[sg];
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = src[sg * NV + k];
+    }
+    const uint32_t next = __shfl_down(key, 1, kWave);
+    const int head = segment_head(key, lane);
+    wave_segmented_scan<NV>(v, lane, head);
+    const bool tail = lane == kWave - 1 || next != key;
+    bool opens = false;
+    if (has && tail) {
+        const int64_t first = i - (lane - head);
+        const bool starts = first == (int64_t)c.gv_seg_off[key];
+        const bool ends = i + 1 == (int64_t)c.gv_seg_off[key + 1];
+        if (starts && ends) {
+#pragma unroll
+            for (int k = 0; k < NV; ++k) dst[(int64_t)key * NV + k] = v[k];
+        } else if (!starts) {   // continues from the previous wave: the wave's first group
+#pragma unroll
+            for (int k = 0; k < NV; ++k) edge[(2 * w) * NV + k] = v[k];
+        } else {                // starts here and continues: the wave's last group
+#pragma unroll
+            for (int k = 0; k < NV; ++k) edge[(2 * w + 1) * NV + k] = v[k];
+            opens = true;
+        }
+    }
+    if (lane == kWave - 1) edge_key[w] = opens ? key : kNoGv;
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gv_reduce_join(CacheView c, int64_t n_waves, const float* __restrict__ edge,
+                                                          const uint32_t* __restrict__ edge_key,
+                                                          float* __restrict__ dst) {
+    const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (w >= n_waves) return;
+    const uint32_t key = edge_key[w];
+    if (key == kNoGv) return;
+    float acc[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) acc[k] = edge[(2 * w + 1) * NV + k];
+    const int64_t end = c.gv_seg_off[key + 1];
+    for (int64_t u = w + 1; u * kWave < end && u < n_waves; ++u)
+#pragma unroll
+        for (int k = 0; k < NV; ++k) acc[k] += edge[(2 * u) * NV + k];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) dst[(int64_t)key * NV + k] = acc[k];
+}
+
 // ---- chain: per-(Gaussian, view) moments -> parameters ---------------------------
-// out = scale * J^T u (+ lambda M p); partial dot products p . out per block.
+// The adjoint of the tangent map: g_geo = sum_v L_v^T S[0:6] + Jdir_v^T S[6:9],
+// g_sh[k][ch] = sum_v mask_ch Y_k S[6 + ch], with S the (Gaussian, view)'s
+// moments (summed over its segments by k_gv_reduce).  One thread per
+// Gaussian.  out = scale * J^T u (+ lambda M p); partial dot products
+// p . out per block.
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, float lambda, const float* __restrict__ M,
                                                  float diag_floor, float* __restrict__ out,
@@ -385,35 +508,38 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, floa
     __shared__ double s_red[kBlock / kWave];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = g < c.N;
+    const int64_t ls = c.lin_stride;
     double pg = 0.0;
     if (live) {
         double geo[11];
 #pragma unroll
         for (int j = 0; j < 11; ++j) geo[j] = 0.0;
-        double gsh[3 * K];
+        float gsh[3 * K];
 #pragma unroll
-        for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0;
+        for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0f;
         const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
         for (uint32_t gv = b; gv < e; ++gv) {
-            double S9[9];
+            float S9[9];
 #pragma unroll
-            for (int k = 0; k < 9; ++k) S9[k] = 0.0;
-            for (uint32_t i = c.gv_seg_off[gv]; i < c.gv_seg_off[gv + 1]; ++i) {
-                const int64_t s = c.gv_segs[i];
+            for (int k = 0; k < 9; ++k) S9[k] = a.gvsum[(int64_t)gv * 9 + k];
 #pragma unroll
-                for (int k = 0; k < 9; ++k) S9[k] += (double)a.gmom[s * 9 + k];
+            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                for (int j = 0; j < 11; ++j)
+                    geo[j] += (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv] * (double)S9[i];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+#pragma unroll
+                for (int m = 0; m < 3; ++m)
+                    geo[m] += (double)c.lin[(int64_t)(kLinJdir + 3 * ch + m) * ls + gv] * (double)S9[6 + ch];
+                const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * S9[6 + ch];
+#pragma unroll
+                for (int k = 0; k < K; ++k) gsh[3 * k + ch] += c.lin[(int64_t)(kLinY + k) * ls + gv] * w;
             }
-            const int v = (int)(c.gv_rec[gv] / c.N);
-            const CamDev& cam = c.cams[v];
-            ProjFwd f;
-            proj_forward<DEG>(cam, a.x, c.N, g, f);
-            double Gy[9];
-            moments_to_Gy(f, S9, Gy);
-            proj_adjoint<DEG>(cam, f, Gy, a.x, c.N, g, geo, gsh);
         }
 #pragma unroll
         for (int j = 0; j < P; ++j) {
-            double val = (j < 11 ? geo[j < 11 ? j : 0] : gsh[j >= 11 ? j - 11 : 0]) * scale;
+            double val = (j < 11 ? geo[j < 11 ? j : 0] : (double)gsh[j >= 11 ? j - 11 : 0]) * scale;
             const int64_t idx = (int64_t)j * c.N + g;
             if (M) {
                 const float m = M[idx];
@@ -526,60 +652,61 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
     if (i < n) p[i] = v;
 }
 
+// diag(J^T J) per parameter: for each (Gaussian, view) the tangent of unit
+// parameter j has power coefficients co = (L[.][j], Jdir[.][j]) and its
+// squared Jacobian column norm is the quadratic form of the (Gaussian,
+// view)'s Gram values; an SH coefficient (k, ch) has co = Y_k e_ch on the
+// colour slots.  One thread per Gaussian.
 template <int DEG>
-__global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float* __restrict__ x,
-                                                      const float* __restrict__ gram, float* __restrict__ M) {
+__global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float* __restrict__ gvgram,
+                                                      float* __restrict__ M) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int P = 11 + 3 * K;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= c.N) return;
+    const int64_t ls = c.lin_stride;
     double dgeo_acc[11];
 #pragma unroll
     for (int j = 0; j < 11; ++j) dgeo_acc[j] = 0.0;
-    double dsh[3 * K];
+    float dsh[3 * K];
 #pragma unroll
-    for (int j = 0; j < 3 * K; ++j) dsh[j] = 0.0;
+    for (int j = 0; j < 3 * K; ++j) dsh[j] = 0.0f;
     const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
     for (uint32_t gv = b; gv < e; ++gv) {
-        double H[kGram];
-#pragma unroll
-        for (int k = 0; k < kGram; ++k) H[k] = 0.0;
-        for (uint32_t i = c.gv_seg_off[gv]; i < c.gv_seg_off[gv + 1]; ++i) {
-            const int64_t s = c.gv_segs[i];
-#pragma unroll
-            for (int k = 0; k < kGram; ++k) H[k] += (double)gram[s * kGram + k];
-        }
-        const int v = (int)(c.gv_rec[gv] / c.N);
-        const CamDev& cam = c.cams[v];
-        ProjFwd f;
-        proj_forward<DEG>(cam, x, c.N, g, f);
+        const float* H = gvgram + (int64_t)gv * kGram;
 #pragma unroll
         for (int j = 0; j < 11; ++j) {
-            double unit[11];
-#pragma unroll
-            for (int i = 0; i < 11; ++i) unit[i] = i == j ? 1.0 : 0.0;
             double co[9];
-            proj_tangent<DEG>(cam, f, unit, x, nullptr, c.N, g, co);
+#pragma unroll
+            for (int i = 0; i < 6; ++i) co[i] = (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv];
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) co[6 + ch] = j < 3 ? (double)c.lin[(int64_t)(kLinJdir + 3 * ch + j) * ls + gv] : 0.0;
             double q = 0.0;
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
-                q += co[i] * co[i] * H[tri6(i, i)];
+                q += co[i] * co[i] * (double)H[tri6(i, i)];
 #pragma unroll
-                for (int k = i + 1; k < 6; ++k) q += 2.0 * co[i] * co[k] * H[tri6(i, k)];
-                q += 2.0 * co[i] * (H[21 + 3 * i] * co[6] + H[22 + 3 * i] * co[7] + H[23 + 3 * i] * co[8]);
+                for (int k = i + 1; k < 6; ++k) q += 2.0 * co[i] * co[k] * (double)H[tri6(i, k)];
+                q += 2.0 * co[i] * ((double)H[21 + 3 * i] * co[6] + (double)H[22 + 3 * i] * co[7] +
+                                    (double)H[23 + 3 * i] * co[8]);
             }
-            q += H[39] * (co[6] * co[6] + co[7] * co[7] + co[8] * co[8]);
+            q += (double)H[39] * (co[6] * co[6] + co[7] * co[7] + co[8] * co[8]);
             dgeo_acc[j] += q;
         }
+        const float h39 = H[39];
 #pragma unroll
-        for (int k = 0; k < K; ++k)
+        for (int ch = 0; ch < 3; ++ch) {
+            const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * h39;
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch)
-                dsh[3 * k + ch] += f.clamp[ch] ? 0.0 : f.Y[k] * f.Y[k] * H[39];
+            for (int k = 0; k < K; ++k) {
+                const float y = c.lin[(int64_t)(kLinY + k) * ls + gv];
+                dsh[3 * k + ch] += y * y * w;
+            }
+        }
     }
 #pragma unroll
     for (int j = 0; j < P; ++j)
-        M[(int64_t)j * c.N + g] = (float)(j < 11 ? dgeo_acc[j < 11 ? j : 0] : dsh[j >= 11 ? j - 11 : 0]);
+        M[(int64_t)j * c.N + g] = j < 11 ? (float)dgeo_acc[j < 11 ? j : 0] : dsh[j >= 11 ? j - 11 : 0];
 }
 
 }  // namespace
@@ -592,8 +719,17 @@ __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float*
         default: CALL(3); break; \
     }
 
+hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipStream_t s) {
+    if (c.n_gv == 0) return hipSuccess;
+#define LM_L(D) hipLaunchKernelGGL(k_linearize<D>, dim3(grid_for(c.n_gv)), dim3(kBlock), 0, s, c, x, lin)
+    LM_DEG_SWITCH(c.deg, LM_L)
+#undef LM_L
+    return hipGetLastError();
+}
+
 hipError_t launch_tangent(const ApplyArgs& a, hipStream_t s) {
-#define LM_T(D) hipLaunchKernelGGL(k_tangent<D>, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a)
+    if (a.c.n_gv == 0) return hipSuccess;
+#define LM_T(D) hipLaunchKernelGGL(k_tangent<D>, dim3(grid_for(a.c.n_gv)), dim3(kBlock), 0, s, a)
     LM_DEG_SWITCH(a.c.deg, LM_T)
 #undef LM_T
     return hipGetLastError();
@@ -622,8 +758,8 @@ hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s) {
 hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
                         double* pg_part, hipStream_t s) {
 #define LM_C(D)                                                                                                  \
-    hipLaunchKernelGGL(k_chain<D>, dim3(grid_for(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, diag_floor, out, \
-                       pg_part)
+    hipLaunchKernelGGL(k_chain<D>, dim3(chain_blocks(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, diag_floor, \
+                       out, pg_part)
     LM_DEG_SWITCH(a.c.deg, LM_C)
 #undef LM_C
     return hipGetLastError();
@@ -631,7 +767,25 @@ hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const flo
 
 unsigned chain_blocks(int64_t N) { return grid_for(N); }
 
-hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, float* M, hipStream_t s) {
+int64_t gv_reduce_waves(int64_t n_seg) { return (n_seg + kWave - 1) / kWave; }
+
+template <int NV>
+hipError_t gv_reduce(const CacheView& c, const float* src, float* dst, float* edge, uint32_t* edge_key,
+                     hipStream_t s) {
+    if (c.n_seg == 0) return hipSuccess;
+    const int64_t nw = gv_reduce_waves(c.n_seg);
+    hipLaunchKernelGGL(k_gv_reduce<NV>, dim3(grid_for(nw * kWave)), dim3(kBlock), 0, s, c, src, dst, edge, edge_key);
+    hipLaunchKernelGGL(k_gv_reduce_join<NV>, dim3(grid_for(nw)), dim3(kBlock), 0, s, c, nw, edge, edge_key, dst);
+    return hipGetLastError();
+}
+
+hipError_t launch_gv_reduce_moments(const ApplyArgs& a, hipStream_t s) {
+    return gv_reduce<9>(a.c, a.gmom, a.gvsum, a.edge, a.edge_key, s);
+}
+
+
+hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
+                              float* M, hipStream_t s) {
     dim3 b(kBlock);
     const int64_t n_runs = c.n_pairs / kRun;
     const int64_t ng = (int64_t)kGram * (c.n_seg > 0 ? c.n_seg : 1);
@@ -645,7 +799,9 @@ hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, f
         else
             hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram);
     }
-#define LM_D(D) hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, x, gram, M)
+    hipError_t e = gv_reduce<kGram>(c, gram, gvgram, edge, edge_key, s);
+    if (e != hipSuccess) return e;
+#define LM_D(D) hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, gvgram, M)
     LM_DEG_SWITCH(c.deg, LM_D)
 #undef LM_D
     return hipGetLastError();

@@ -100,7 +100,7 @@ struct lm_cache {
     int64_t N = 0;
     int P = 0, deg = 0, V = 0, TW = 16, TH = 16, dtype = LM_CACHE_F32;
     int64_t n_tiles = 0, n_pix = 0, n_keys = 0, n_pairs = 0, n_slots = 0, n_seg = 0, n_gv = 0;
-    int64_t pair_stride = 8, seg_stride = 8;
+    int64_t pair_stride = 8, seg_stride = 8, lin_stride = 8;
     bool vals_in_alt = false;
     bool built = false;
     std::vector<lm::CamDev> cams_h;
@@ -108,11 +108,13 @@ struct lm_cache {
     DevBuf cams, tile_view, x;
     DevBuf rec64, recf, rad, keycnt, keyoff;
     DevBuf keys, vals, keys_alt, vals_alt, sort_tmp, scan_tmp;
+    DevBuf rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted;
     DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
     DevBuf tile_real, tile_real_off, run_seg;
     DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs;
     DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
-    DevBuf dyc, gmom, jp_part, gram, pg_part, scalar;
+    DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
+    DevBuf gvsum, edge_m, ekey_m, gvgram, edge_g, ekey_g;
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
 
     const uint32_t* sorted_vals() const { return vals_in_alt ? vals_alt.as<uint32_t>() : vals.as<uint32_t>(); }
@@ -134,6 +136,7 @@ struct lm_cache {
         c.seg_stride = seg_stride;
         c.gv_rec = gv_rec.as<uint32_t>(); c.gv_first = gv_first.as<uint32_t>();
         c.gv_seg_off = gv_seg_off.as<uint32_t>(); c.gv_segs = gv_segs.as<uint32_t>();
+        c.lin = lin.as<float>(); c.lin_stride = lin_stride;
         return c;
     }
 
@@ -143,17 +146,22 @@ struct lm_cache {
         a.x = x.as<float>();
         a.dyc = dyc.as<float>();
         a.gmom = gmom.as<float>();
+        a.gvsum = gvsum.as<float>();
+        a.edge = edge_m.as<float>();
+        a.edge_key = ekey_m.as<uint32_t>();
         a.jp_part = jp_part.as<double>();
         return a;
     }
 
     size_t device_bytes() const {
-        const DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt,
+        const DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
+                               &rkeys_alt, &rvals_alt, &cnt_sorted,
                                &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
                                &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
-                               &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar,
+                               &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
+                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -161,12 +169,14 @@ struct lm_cache {
     }
 
     void release_all() {
-        DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt,
+        DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
+                               &rkeys_alt, &rvals_alt, &cnt_sorted,
                          &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
                          &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
-                         &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar,
+                         &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
+                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -251,34 +261,54 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->scan_tmp.ensure(std::max(scan_tmp_bytes(R), scan_tmp_bytes(N * (int64_t)V + 1)) + 1024));
     { LM_PROF("project", s);
     LM_HIP(launch_project(c->cams.as<CamDev>(), c->x.as<float>(), N, V, c->deg, TW, TH, c->rec64.as<double>(),
-                          c->recf.as<float>(), c->rad.as<int32_t>(), c->keycnt.as<uint32_t>(), s));
-    LM_HIP(exclusive_scan_u32_to_u64(c->keycnt.as<uint32_t>(), c->keyoff.as<uint64_t>(), R, c->scan_tmp.p,
+                          c->recf.as<float>(), c->rad.as<int32_t>(), c->keycnt.as<uint32_t>(), s)); }
+
+    // depth sort of the records of every view (stable: ties keep the id order)
+    int view_bits = 0;
+    while ((1 << view_bits) < V) ++view_bits;
+    LM_HIP(c->rkeys.ensure(sizeof(uint64_t) * R));
+    LM_HIP(c->rkeys_alt.ensure(sizeof(uint64_t) * R));
+    LM_HIP(c->rvals.ensure(sizeof(uint32_t) * R));
+    LM_HIP(c->rvals_alt.ensure(sizeof(uint32_t) * R));
+    LM_HIP(c->cnt_sorted.ensure(sizeof(uint32_t) * R));
+    LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(R)));
+    const uint32_t* order = nullptr;
+    { LM_PROF("depth_sort", s);
+    LM_HIP(launch_record_keys(c->recf.as<float>(), c->keycnt.as<uint32_t>(), N, V, c->rkeys.as<uint64_t>(),
+                              c->rvals.as<uint32_t>(), s));
+    bool ralt = false;
+    LM_HIP(radix_sort_pairs(c->rkeys.as<uint64_t>(), c->rvals.as<uint32_t>(), c->rkeys_alt.as<uint64_t>(),
+                            c->rvals_alt.as<uint32_t>(), R, 0, 31 + view_bits, c->sort_tmp.p, c->sort_tmp.cap,
+                            &ralt, s));
+    order = ralt ? c->rvals_alt.as<uint32_t>() : c->rvals.as<uint32_t>();
+    LM_HIP(launch_gather_counts(order, c->keycnt.as<uint32_t>(), R, c->cnt_sorted.as<uint32_t>(), s));
+    LM_HIP(exclusive_scan_u32_to_u64(c->cnt_sorted.as<uint32_t>(), c->keyoff.as<uint64_t>(), R, c->scan_tmp.p,
                                      c->scan_tmp.cap, s)); }
     uint64_t K = 0;
     LM_HIP(hipMemcpyAsync(&K, c->keyoff.as<uint64_t>() + R, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
     LM_HIP(hipStreamSynchronize(s));
     c->n_keys = (int64_t)K;
+    LM_CHECK(c->n_keys < ((int64_t)1 << 40), LM_ERR_CAPACITY, "too many tile keys");
 
-    // binning and depth sort
+    // binning in depth order, then a stable sort by tile
     const int64_t Ka = std::max<int64_t>(c->n_keys, 1);
-    LM_HIP(c->keys.ensure(sizeof(uint64_t) * Ka));
+    LM_HIP(c->keys.ensure(sizeof(uint32_t) * Ka));
     LM_HIP(c->vals.ensure(sizeof(uint32_t) * Ka));
-    LM_HIP(c->keys_alt.ensure(sizeof(uint64_t) * Ka));
+    LM_HIP(c->keys_alt.ensure(sizeof(uint32_t) * Ka));
     LM_HIP(c->vals_alt.ensure(sizeof(uint32_t) * Ka));
-    LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(Ka)));
+    LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(std::max<int64_t>(Ka, R))));
     { LM_PROF("bin_emit", s);
-    LM_HIP(launch_bin_emit(c->cams.as<CamDev>(), N, V, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(),
-                           c->keycnt.as<uint32_t>(), c->keyoff.as<uint64_t>(), c->keys.as<uint64_t>(),
-                           c->vals.as<uint32_t>(), s)); }
+    LM_HIP(launch_bin_emit(c->cams.as<CamDev>(), N, R, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(), order,
+                           c->keyoff.as<uint64_t>(), c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), s)); }
     int tile_bits = 1;
     while (((int64_t)1 << tile_bits) < c->n_tiles) ++tile_bits;
     bool alt = false;
-    { LM_PROF("depth_sort", s);
-    LM_HIP(radix_sort_pairs(c->keys.as<uint64_t>(), c->vals.as<uint32_t>(), c->keys_alt.as<uint64_t>(),
-                            c->vals_alt.as<uint32_t>(), c->n_keys, 0, 31 + tile_bits, c->sort_tmp.p,
-                            c->sort_tmp.cap, &alt, s)); }
+    { LM_PROF("tile_sort", s);
+    LM_HIP(radix_sort_pairs_u32(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_alt.as<uint32_t>(),
+                                c->vals_alt.as<uint32_t>(), c->n_keys, 0, tile_bits, c->sort_tmp.p,
+                                c->sort_tmp.cap, &alt, s)); }
     c->vals_in_alt = alt;
-    const uint64_t* skeys = alt ? c->keys_alt.as<uint64_t>() : c->keys.as<uint64_t>();
+    const uint32_t* skeys = alt ? c->keys_alt.as<uint32_t>() : c->keys.as<uint32_t>();
     LM_HIP(c->tile_start.ensure(sizeof(int64_t) * (c->n_tiles + 1)));
     { LM_PROF("tile_ranges", s); LM_HIP(launch_tile_ranges(skeys, c->n_keys, c->n_tiles, c->tile_start.as<int64_t>(), s)); }
 
@@ -400,9 +430,17 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.run_seg = c->run_seg.as<uint32_t>();
     { LM_PROF("raster_fill", s); LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s)); }
     { LM_PROF("gv_sort", s); LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s)); }
+    // linearised projection of every (Gaussian, view) at x
+    c->lin_stride = round_up(ngv_a, 8);
+    LM_HIP(c->lin.ensure(sizeof(float) * lm::kLin * c->lin_stride));
+    { LM_PROF("linearize", s); LM_HIP(launch_linearize(c->view(), c->x.as<float>(), c->lin.as<float>(), s)); }
     // product workspaces
     LM_HIP(c->dyc.ensure(sizeof(float) * 9 * ngv_a));
     LM_HIP(c->gmom.ensure(sizeof(float) * 9 * nseg_a));
+    const int64_t nwav = lm::gv_reduce_waves(nseg_a);
+    LM_HIP(c->gvsum.ensure(sizeof(float) * 9 * ngv_a));
+    LM_HIP(c->edge_m.ensure(sizeof(float) * 2 * 9 * nwav));
+    LM_HIP(c->ekey_m.ensure(sizeof(uint32_t) * nwav));
     LM_HIP(c->jp_part.ensure(sizeof(double) * c->n_tiles));
     LM_HIP(c->pg_part.ensure(sizeof(double) * (chain_blocks(N) + 1)));
     LM_HIP(c->scalar.ensure(sizeof(double) * 4));
@@ -414,6 +452,7 @@ lm_status apply_JT_internal(const lm_cache* c, const float* u, float scale, floa
     lm::ApplyArgs a = c->apply_args();
     a.uin = u;
     { LM_PROF("apply_tile_JT", s); LM_HIP(lm::launch_apply_tile(2, a, s)); }
+    { LM_PROF("gv_reduce", s); LM_HIP(lm::launch_gv_reduce_moments(a, s)); }
     { LM_PROF("chain", s); LM_HIP(lm::launch_chain(a, scale, 0.0f, nullptr, 0.0f, g, nullptr, s)); }
     return LM_OK;
 }
@@ -425,6 +464,7 @@ lm_status apply_JtJ_internal(lm_cache* c, const float* p, float lambda, const fl
     a.stop = stop;
     { LM_PROF("tangent", s); LM_HIP(lm::launch_tangent(a, s)); }
     { LM_PROF("apply_tile_JtJ", s); LM_HIP(lm::launch_apply_tile(3, a, s)); }
+    { LM_PROF("gv_reduce", s); LM_HIP(lm::launch_gv_reduce_moments(a, s)); }
     { LM_PROF("chain", s); LM_HIP(lm::launch_chain(a, 1.0f, lambda, M, diag_floor, g, pg_part, s)); }
     return LM_OK;
 }
@@ -505,8 +545,15 @@ lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
     LM_CHECK(c && M, LM_ERR_INVALID_ARG, "lm_jacobi_diag: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
-    LM_HIP(cm->gram.ensure(sizeof(float) * 40 * std::max<int64_t>(c->n_seg, 1)));
-    { LM_PROF("jacobi_diag", S(stream)); LM_HIP(lm::launch_jacobi_diag(c->view(), c->x.as<float>(), cm->gram.as<float>(), M, S(stream))); }
+    const int64_t nseg_a = std::max<int64_t>(c->n_seg, 1);
+    const int64_t nwav = lm::gv_reduce_waves(nseg_a);
+    LM_HIP(cm->gram.ensure(sizeof(float) * 40 * nseg_a));
+    LM_HIP(cm->gvgram.ensure(sizeof(float) * 40 * std::max<int64_t>(c->n_gv, 1)));
+    LM_HIP(cm->edge_g.ensure(sizeof(float) * 2 * 40 * nwav));
+    LM_HIP(cm->ekey_g.ensure(sizeof(uint32_t) * nwav));
+    { LM_PROF("jacobi_diag", S(stream));
+    LM_HIP(lm::launch_jacobi_diag(c->view(), cm->gram.as<float>(), cm->gvgram.as<float>(), cm->edge_g.as<float>(),
+                                  cm->ekey_g.as<uint32_t>(), M, S(stream))); }
     return LM_OK;
 }
 

@@ -65,7 +65,20 @@ struct CacheView {
     const uint32_t* gv_first;    // dev [N+1] first gv of each Gaussian
     const uint32_t* gv_seg_off;  // dev [n_gv+1]
     const uint32_t* gv_segs;     // dev [n_seg] segment ids grouped by gv, ascending
+    const float* lin;            // dev [kLin][lin_stride]: linearised projection per gv
+    int64_t lin_stride;
 };
+
+// Linearisation of the projection of one (Gaussian, view) at the cache's x,
+// stored per gv (float32, index k of lin[k * lin_stride + gv]):
+//   L[i][j]     k = i*11 + j        d a_i / d xgeo_j, a = (P1, P2, Q1, Q2, Q3, do)
+//                                   (power-coefficient form), xgeo = mean,
+//                                   log-scale, quaternion, opacity logit
+//   Jdir[ch][m] k = 66 + 3 ch + m   d colour_ch / d mean_m through the view
+//                                   direction (0 for a clamped channel)
+//   Y[k]        k = 75 + k          SH basis at the view direction
+//   mask[ch]    k = 91 + ch         1, or 0 for a clamped channel
+constexpr int kLinL = 0, kLinJdir = 66, kLinY = 75, kLinMask = 91, kLin = 94;
 
 // Thread-local error message plumbing.
 void set_error(const std::string& msg);
@@ -143,6 +156,9 @@ size_t scan_tmp_bytes(int64_t n);
 hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
                             int64_t n, int begin_bit, int end_bit, void* tmp, size_t tmp_bytes,
                             bool* result_in_alt, hipStream_t s);
+hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                                int begin_bit, int end_bit, void* tmp, size_t tmp_bytes, bool* result_in_alt,
+                                hipStream_t s);
 size_t radix_tmp_bytes(int64_t n);
 hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s);
 
@@ -195,6 +211,9 @@ struct ApplyArgs {
     float* uout;             // image layout (J only)
     float* dyc;              // [n_gv][9] power coefficients of J_y p
     float* gmom;             // [n_seg][9] moments of J^T u per segment
+    float* gvsum;            // [n_gv][9] moments per (Gaussian, view)
+    float* edge;             // [2 * waves][9] pieces of gv lists that cross waves
+    uint32_t* edge_key;      // [waves]
     double* jp_part;         // [n_tiles] ||J p||^2 per tile
     const int32_t* stop;     // optional device flag: skip when non-zero
 };
@@ -209,10 +228,14 @@ struct PcgState {
 // project_bin.hip
 hipError_t launch_project(const CamDev* cams, const float* x, int64_t N, int V, int deg, int TW, int TH,
                           double* rec64, float* recf, int32_t* rad, uint32_t* keycnt, hipStream_t s);
-hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int V, int TW, int TH, const float* recf,
-                           const int32_t* rad, const uint32_t* keycnt, const uint64_t* keyoff, uint64_t* keys,
+hipError_t launch_record_keys(const float* recf, const uint32_t* keycnt, int64_t N, int V, uint64_t* rkeys,
+                              uint32_t* rvals, hipStream_t s);
+hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, int64_t R, uint32_t* cnt_sorted,
+                                hipStream_t s);
+hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
+                           const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted, uint32_t* keys,
                            uint32_t* vals, hipStream_t s);
-hipError_t launch_tile_ranges(const uint64_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
+hipError_t launch_tile_ranges(const uint32_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
                               hipStream_t s);
 // raster.hip
 hipError_t launch_raster(bool fill, int dtype, int64_t n_tiles, const RasterArgs& a, hipStream_t s);
@@ -226,7 +249,11 @@ hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s);
 hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
                         double* pg_part, hipStream_t s);
 unsigned chain_blocks(int64_t N);
-hipError_t launch_jacobi_diag(const CacheView& c, const float* x, float* gram, float* M, hipStream_t s);
+hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
+                              float* M, hipStream_t s);
+hipError_t launch_gv_reduce_moments(const ApplyArgs& a, hipStream_t s);
+int64_t gv_reduce_waves(int64_t n_seg);
+hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipStream_t s);
 // pcg.hip
 int64_t pcg_partial_count(int64_t n);
 hipError_t pcg_init(int64_t n, const float* b, const float* M, float floor_, const float* scale, float* x,

@@ -1,6 +1,5 @@
 // Float64 projection of one Gaussian into one view (the "ds/dx" factor of
-// paper eq. backward-pass), with its forward-mode tangent and reverse-mode
-// adjoint.  The paper defers the projection to the original 3DGS rasteriser
+// paper eq. backward-pass) and its forward-mode tangent.  The paper defers the projection to the original 3DGS rasteriser
 // (EWA splatting); the conventions here are: quaternion (w,x,y,z) normalised
 // before use, Sigma = R diag(exp(2 s)) R^T, t = R_v mu + t_v, pinhole mean
 // m = f t_xy / t_z + c, screen covariance J W J^T + 0.3 I with the
@@ -15,7 +14,7 @@
 // (P1, P2, Q1, Q2, Q3, do, dr, dg, db): for a pixel offset d,
 //     d alpha = alpha (P1 dx + P2 dy + Q1 dx^2 + Q2 dx dy + Q3 dy^2) + G do
 // with P1 = A dm_x + B dm_y, P2 = B dm_x + C dm_y, Q1 = -dA/2, Q2 = -dB,
-// Q3 = -dC/2 (G = exp(power)).  The adjoint takes the matching moments.
+// Q3 = -dC/2 (G = exp(power)).
 #pragma once
 
 #include "lm_internal.h"
@@ -79,36 +78,6 @@ __device__ __forceinline__ void sh_grad_dot(const double d[3], const double v[3]
     dY[13] = C3c * ((4.0 * zz - 3.0 * xx - yy) * vx - 2.0 * x * y * vy + 8.0 * x * z * vz);
     dY[14] = C3e * (2.0 * x * z * vx - 2.0 * y * z * vy + (xx - yy) * vz);
     dY[15] = C3a * ((3.0 * xx - 3.0 * yy) * vx - 6.0 * x * y * vy);
-}
-
-// g = sum_k w[k] grad Y_k(d)
-template <int deg>
-__device__ __forceinline__ void sh_grad_weighted(const double d[3], const double w[16], double g[3]) {
-    using namespace shc;
-    const double x = d[0], y = d[1], z = d[2];
-    g[0] = g[1] = g[2] = 0.0;
-    if constexpr (deg < 1) return;
-    g[0] += C1 * w[3]; g[1] += C1 * w[1]; g[2] += C1 * w[2];
-    if constexpr (deg < 2) return;
-    const double xx = x * x, yy = y * y, zz = z * z;
-    g[0] += C2a * y * w[4];                 g[1] += C2a * x * w[4];
-    g[1] += C2a * z * w[5];                 g[2] += C2a * y * w[5];
-    g[0] += -2.0 * C2b * x * w[6];          g[1] += -2.0 * C2b * y * w[6];   g[2] += 4.0 * C2b * z * w[6];
-    g[0] += C2a * z * w[7];                 g[2] += C2a * x * w[7];
-    g[0] += 2.0 * C2c * x * w[8];           g[1] += -2.0 * C2c * y * w[8];
-    if constexpr (deg < 3) return;
-    g[0] += C3a * 6.0 * x * y * w[9];       g[1] += C3a * (3.0 * xx - 3.0 * yy) * w[9];
-    g[0] += C3b * y * z * w[10];            g[1] += C3b * x * z * w[10];     g[2] += C3b * x * y * w[10];
-    g[0] += C3c * -2.0 * x * y * w[11];     g[1] += C3c * (4.0 * zz - xx - 3.0 * yy) * w[11];
-    g[2] += C3c * 8.0 * y * z * w[11];
-    g[0] += C3d * -6.0 * x * z * w[12];     g[1] += C3d * -6.0 * y * z * w[12];
-    g[2] += C3d * (6.0 * zz - 3.0 * xx - 3.0 * yy) * w[12];
-    g[0] += C3c * (4.0 * zz - 3.0 * xx - yy) * w[13];
-    g[1] += C3c * -2.0 * x * y * w[13];     g[2] += C3c * 8.0 * x * z * w[13];
-    g[0] += C3e * 2.0 * x * z * w[14];      g[1] += C3e * -2.0 * y * z * w[14];
-    g[2] += C3e * (xx - yy) * w[14];
-    g[0] += C3a * (3.0 * xx - 3.0 * yy) * w[15];
-    g[1] += C3a * -6.0 * x * y * w[15];
 }
 
 // Partial derivatives of the rotation matrix (row-major) with respect to the
@@ -340,129 +309,6 @@ __device__ inline void proj_tangent(const CamDev& cam, const ProjFwd& f, const d
         }
         out[6 + ch] = v;
     }
-}
-
-// Reverse mode: Gy = (G_mx, G_my, G_A, G_B, G_C, G_o, G_r, G_g, G_b) ->
-// accumulate into ggeo[11] and gsh[3K] (index 3k + ch).
-template <int deg>
-__device__ inline void proj_adjoint(const CamDev& cam, const ProjFwd& f, const double Gy[9],
-                                    const float* __restrict__ x, int64_t N, int64_t g,
-                                    double ggeo[11], double* gsh) {
-    const double* R = cam.R;
-    const double fx = cam.fx, fy = cam.fy, tz = f.t[2];
-    const double iz2 = 1.0 / (tz * tz);
-    ggeo[10] += Gy[5] * f.o * (1.0 - f.o);
-    // colour
-    constexpr int Kc = (deg + 1) * (deg + 1);
-    double w[16];
-#pragma unroll
-    for (int k = 0; k < 16; ++k) w[k] = 0.0;
-#pragma unroll
-    for (int ch = 0; ch < 3; ++ch) {
-        const double gc = f.clamp[ch] ? 0.0 : Gy[6 + ch];
-#pragma unroll
-        for (int k = 0; k < Kc; ++k) {
-            gsh[3 * k + ch] += gc * f.Y[k];
-            w[k] += gc * (double)x[(int64_t)(11 + 3 * k + ch) * N + g];
-        }
-    }
-    double Gd[3];
-    sh_grad_weighted<deg>(f.d, w, Gd);
-    {
-        const double pr = f.d[0] * Gd[0] + f.d[1] * Gd[1] + f.d[2] * Gd[2];
-#pragma unroll
-        for (int i = 0; i < 3; ++i) ggeo[i] += (Gd[i] - f.d[i] * pr) / f.dn;
-    }
-    // conic -> screen covariance
-    const double K[4] = {f.A, f.B, f.B, f.C};
-    const double Gb[4] = {Gy[2], 0.5 * Gy[3], 0.5 * Gy[3], Gy[4]};
-    double X[4], Gc[4];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) X[2 * i + j] = K[2 * i] * Gb[j] + K[2 * i + 1] * Gb[2 + j];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 2; ++j) Gc[2 * i + j] = -(X[2 * i] * K[j] + X[2 * i + 1] * K[2 + j]);
-    // cov = J W J^T: G_J = 2 Gc T2, G_W = J^T Gc J
-    double GJ[6];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) GJ[3 * i + j] = 2.0 * (Gc[2 * i] * f.T2[j] + Gc[2 * i + 1] * f.T2[3 + j]);
-    double GcJ[6];
-#pragma unroll
-    for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) GcJ[3 * i + j] = Gc[2 * i] * f.J[j] + Gc[2 * i + 1] * f.J[3 + j];
-    double GW[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) GW[3 * i + j] = f.J[i] * GcJ[j] + f.J[3 + i] * GcJ[3 + j];
-    // perspective Jacobian and mean -> camera-space position
-    double Gt[3];
-    Gt[0] = GJ[2] * (-fx * iz2) + Gy[0] * fx / tz;
-    Gt[1] = GJ[5] * (-fy * iz2) + Gy[1] * fy / tz;
-    Gt[2] = GJ[0] * (-fx * iz2) + GJ[2] * (2.0 * fx * f.t[0] * iz2 / tz) + GJ[4] * (-fy * iz2) +
-            GJ[5] * (2.0 * fy * f.t[1] * iz2 / tz) - Gy[0] * fx * f.t[0] * iz2 - Gy[1] * fy * f.t[1] * iz2;
-#pragma unroll
-    for (int i = 0; i < 3; ++i) ggeo[i] += R[i] * Gt[0] + R[3 + i] * Gt[1] + R[6 + i] * Gt[2];
-    // camera-frame covariance -> world covariance: G_Sigma = R_v^T G_W R_v
-    double T[9], GS[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) T[3 * i + j] = R[i] * GW[j] + R[3 + i] * GW[3 + j] + R[6 + i] * GW[6 + j];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j) GS[3 * i + j] = T[3 * i] * R[j] + T[3 * i + 1] * R[3 + j] + T[3 * i + 2] * R[6 + j];
-    // Sigma = M M^T, M = Rq diag(S)
-    double GM[9];
-#pragma unroll
-    for (int i = 0; i < 3; ++i)
-#pragma unroll
-        for (int j = 0; j < 3; ++j)
-            GM[3 * i + j] = 2.0 * (GS[3 * i] * f.M[j] + GS[3 * i + 1] * f.M[3 + j] + GS[3 * i + 2] * f.M[6 + j]);
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        const double gsj = f.Rq[j] * GM[j] + f.Rq[3 + j] * GM[3 + j] + f.Rq[6 + j] * GM[6 + j];
-        ggeo[3 + j] += gsj * f.S[j];
-    }
-    double dRp[4][9];
-    rot_partials(f.qn, dRp);
-    double Gqn[4];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) {
-        double v = 0.0;
-#pragma unroll
-        for (int i = 0; i < 3; ++i)
-#pragma unroll
-            for (int j = 0; j < 3; ++j) v += GM[3 * i + j] * f.S[j] * dRp[c][3 * i + j];
-        Gqn[c] = v;
-    }
-    const double pr = f.qn[0] * Gqn[0] + f.qn[1] * Gqn[1] + f.qn[2] * Gqn[2] + f.qn[3] * Gqn[3];
-#pragma unroll
-    for (int c = 0; c < 4; ++c) ggeo[6 + c] += (Gqn[c] - f.qn[c] * pr) / f.qnorm;
-}
-
-// Moments accumulated over the pairs of one (Gaussian, view):
-// S1 = sum a w dx, S2 = sum a w dy, S3 = sum a w dx^2, S4 = sum a w dx dy,
-// S5 = sum a w dy^2, S6 = sum G w, S7..9 = sum alpha T u_ch, where a = alpha
-// (0 when clamped), w = sum_ch dC_ch/dalpha u_ch.  Converts them to the
-// attribute adjoint G_y.
-__device__ __forceinline__ void moments_to_Gy(const ProjFwd& f, const double S[9], double Gy[9]) {
-    Gy[0] = f.A * S[0] + f.B * S[1];
-    Gy[1] = f.B * S[0] + f.C * S[1];
-    Gy[2] = -0.5 * S[2];
-    Gy[3] = -S[3];
-    Gy[4] = -0.5 * S[4];
-    Gy[5] = S[5];
-    Gy[6] = S[6];
-    Gy[7] = S[7];
-    Gy[8] = S[8];
 }
 
 }  // namespace lm

@@ -3,9 +3,11 @@
 // Binning is an integer function of float32 records: mean and depth are the
 // float64 projection rounded to float32, the tile rectangle is
 // floor((m -/+ r) / tile) evaluated in float32 (IEEE division) with inclusive
-// bounds, and the sort key is (global tile index << 31) | float32 depth bits
-// (depth > 0.2, so its sign bit is zero).  Values are Gaussian ids emitted in
-// id order per view, so the stable radix sort breaks depth ties by id.
+// bounds, and each tile's list is ordered by (float32 depth bits, Gaussian
+// id).  The order is reached in two stable sorts: the binned records of all
+// views by (view, depth bits) (records start in (view, id) order, and depth
+// > 0.2 has a zero sign bit), then the keys - emitted record by record in
+// that order - by global tile index alone.
 #include "proj_math.h"
 
 namespace lm {
@@ -55,36 +57,57 @@ __global__ void k_project(const CamDev* __restrict__ cams, const float* __restri
     for (int i = 0; i < 10; ++i) rec64[(int64_t)i * R + r] = vals[i];
 }
 
-__global__ void k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int V, int TW, int TH,
-                           const float* __restrict__ recf, const int32_t* __restrict__ rad,
-                           const uint32_t* __restrict__ keycnt, const uint64_t* __restrict__ keyoff,
-                           uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+// Depth-sort key of every record: (view << 31) | float32 depth bits for a
+// binned record, (view << 31) | 0x7FFFFFFF for one that emits no key.
+__global__ void k_record_keys(const float* __restrict__ recf, const uint32_t* __restrict__ keycnt, int64_t N,
+                              int V, uint64_t* __restrict__ rkeys, uint32_t* __restrict__ rvals) {
     const int64_t R = N * (int64_t)V;
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R || keycnt[r] == 0) return;
+    if (r >= R) return;
+    const uint64_t v = (uint64_t)(r / N);
+    const uint32_t zb = keycnt[r] > 0 ? __float_as_uint(recf[2 * R + r]) : 0x7FFFFFFFu;
+    rkeys[r] = (v << 31) | zb;
+    rvals[r] = (uint32_t)r;
+}
+
+__global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32_t* __restrict__ keycnt, int64_t R,
+                                uint32_t* __restrict__ cnt_sorted) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < R) cnt_sorted[i] = keycnt[order[i]];
+}
+
+// Keys (global tile index) and values (Gaussian id) of the records in depth
+// order; record order[i] writes its tiles at off_sorted[i].
+__global__ void k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int64_t R, int TW, int TH,
+                           const float* __restrict__ recf, const int32_t* __restrict__ rad,
+                           const uint32_t* __restrict__ order, const uint64_t* __restrict__ off_sorted,
+                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= R) return;
+    const uint64_t o0 = off_sorted[i], o1 = off_sorted[i + 1];
+    if (o0 == o1) return;
+    const int64_t r = order[i];
     const int v = (int)(r / N);
     const uint32_t g = (uint32_t)(r - (int64_t)v * N);
     const CamDev& cam = cams[v];
     int x0, y0, x1, y1;
     tile_rect(recf[r], recf[R + r], rad[r], TW, TH, cam.TX, cam.TY, x0, y0, x1, y1);
-    const uint64_t zbits = (uint64_t)__float_as_uint(recf[2 * R + r]);
-    uint64_t o = keyoff[r];
-    for (int ty = y0; ty <= y1; ++ty)
-        for (int tx = x0; tx <= x1; ++tx) {
-            const uint64_t tile = (uint64_t)(cam.tile_base + (int64_t)ty * cam.TX + tx);
-            keys[o] = (tile << 31) | zbits;
+    uint64_t o = o0;
+    for (int ty = y0; ty <= y1 && o < o1; ++ty)
+        for (int tx = x0; tx <= x1 && o < o1; ++tx) {
+            keys[o] = (uint32_t)(cam.tile_base + (int64_t)ty * cam.TX + tx);
             vals[o] = g;
             ++o;
         }
 }
 
 // tile_start[t] = first key index of tile t (lists are [tile_start[t], tile_start[t+1])).
-__global__ void k_tile_ranges(const uint64_t* __restrict__ keys, int64_t K, int64_t n_tiles,
+__global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t K, int64_t n_tiles,
                               int64_t* __restrict__ tile_start) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= K) return;
-    const int64_t t = (int64_t)(keys[i] >> 31);
-    const int64_t tp = i == 0 ? -1 : (int64_t)(keys[i - 1] >> 31);
+    const int64_t t = (int64_t)keys[i];
+    const int64_t tp = i == 0 ? -1 : (int64_t)keys[i - 1];
     for (int64_t u = tp + 1; u <= t; ++u) tile_start[u] = i;
     if (i == K - 1)
         for (int64_t u = t + 1; u <= n_tiles; ++u) tile_start[u] = K;
@@ -113,16 +136,28 @@ hipError_t launch_project(const CamDev* cams, const float* x, int64_t N, int V, 
     return hipGetLastError();
 }
 
-hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int V, int TW, int TH, const float* recf,
-                           const int32_t* rad, const uint32_t* keycnt, const uint64_t* keyoff, uint64_t* keys,
-                           uint32_t* vals, hipStream_t s) {
+hipError_t launch_record_keys(const float* recf, const uint32_t* keycnt, int64_t N, int V, uint64_t* rkeys,
+                              uint32_t* rvals, hipStream_t s) {
     const int64_t R = N * (int64_t)V;
-    hipLaunchKernelGGL(k_bin_emit, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, V, TW, TH, recf, rad, keycnt,
-                       keyoff, keys, vals);
+    hipLaunchKernelGGL(k_record_keys, dim3(grid_for(R)), dim3(kBlock), 0, s, recf, keycnt, N, V, rkeys, rvals);
     return hipGetLastError();
 }
 
-hipError_t launch_tile_ranges(const uint64_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
+hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, int64_t R, uint32_t* cnt_sorted,
+                                hipStream_t s) {
+    hipLaunchKernelGGL(k_gather_counts, dim3(grid_for(R)), dim3(kBlock), 0, s, order, keycnt, R, cnt_sorted);
+    return hipGetLastError();
+}
+
+hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
+                           const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_emit, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
+                       off_sorted, keys, vals);
+    return hipGetLastError();
+}
+
+hipError_t launch_tile_ranges(const uint32_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
                               hipStream_t s) {
     if (K == 0) {
         hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_tiles + 1)), dim3(kBlock), 0, s, tile_start, n_tiles + 1,

@@ -1,7 +1,7 @@
 // Device-wide exclusive scan, float64 reduction and a stable LSD radix sort
-// of (64-bit key, 32-bit value) pairs, written for wave64 / 256-thread
-// workgroups.  Used by tile binning (depth sort per tile), the cache build
-// (pair and segment offsets) and the PCG dot products.
+// of (64- or 32-bit key, 32-bit value) pairs, written for wave64 / 256-thread
+// workgroups.  Used by tile binning (depth sort per view, then tile sort),
+// the cache build (pair and segment offsets) and the PCG dot products.
 #include "lm_internal.h"
 
 namespace lm {
@@ -120,7 +120,8 @@ __global__ void k_reduce_f64(const double* __restrict__ in, int64_t n, double* _
 }
 
 // ---- radix sort ---------------------------------------------------------------
-__global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int shift, int64_t nb,
+template <typename KeyT>
+__global__ void k_radix_hist(const KeyT* __restrict__ keys, int64_t n, int shift, int64_t nb,
                              uint32_t* __restrict__ hist) {
     __shared__ uint32_t h[256];
     h[threadIdx.x] = 0;
@@ -135,9 +136,10 @@ __global__ void k_radix_hist(const uint64_t* __restrict__ keys, int64_t n, int s
     hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];   // digit-major
 }
 
-__global__ void k_radix_scatter(const uint64_t* __restrict__ keys, const uint32_t* __restrict__ vals,
+template <typename KeyT>
+__global__ void k_radix_scatter(const KeyT* __restrict__ keys, const uint32_t* __restrict__ vals,
                                 int64_t n, int shift, int64_t nb, const uint64_t* __restrict__ offs,
-                                uint64_t* __restrict__ okeys, uint32_t* __restrict__ ovals) {
+                                KeyT* __restrict__ okeys, uint32_t* __restrict__ ovals) {
     constexpr int NW = kBlock / kWave;
     __shared__ uint32_t wcnt[NW][256];
     __shared__ uint64_t running[256];
@@ -150,7 +152,7 @@ __global__ void k_radix_scatter(const uint64_t* __restrict__ keys, const uint32_
     for (int r = 0; r < kRadixItems; ++r) {
         const int64_t idx = base + (int64_t)r * kBlock + tid;
         const bool live = idx < n;
-        uint64_t k = live ? keys[idx] : 0ull;
+        KeyT k = live ? keys[idx] : (KeyT)0;
         uint32_t v = live ? vals[idx] : 0u;
         const uint32_t d = (uint32_t)((k >> shift) & 0xFF);
         uint64_t peers = __ballot(live);
@@ -216,9 +218,10 @@ size_t radix_tmp_bytes(int64_t n) {
     return hist + offs + scan + 256;
 }
 
-hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt,
-                            int64_t n, int begin_bit, int end_bit, void* tmp, size_t tmp_bytes,
-                            bool* result_in_alt, hipStream_t s) {
+template <typename KeyT>
+hipError_t radix_sort_impl(KeyT* keys, uint32_t* vals, KeyT* keys_alt, uint32_t* vals_alt, int64_t n,
+                           int begin_bit, int end_bit, void* tmp, size_t tmp_bytes, bool* result_in_alt,
+                           hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1) return hipSuccess;
     int64_t nb = (n + kRadixTile - 1) / kRadixTile;
@@ -231,14 +234,14 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
     t += (size_t)(256 * nb + 1) * sizeof(uint64_t);
     void* stmp = t;
     size_t stmp_bytes = scan_tmp_bytes(256 * nb);
-    uint64_t* ki = keys; uint32_t* vi = vals;
-    uint64_t* ko = keys_alt; uint32_t* vo = vals_alt;
+    KeyT* ki = keys; uint32_t* vi = vals;
+    KeyT* ko = keys_alt; uint32_t* vo = vals_alt;
     bool alt = false;
     for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
+        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
         hipError_t e = exclusive_scan_u32_to_u64(hist, offs, 256 * nb, stmp, stmp_bytes, s);
         if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, n, shift, nb,
+        hipLaunchKernelGGL(k_radix_scatter<KeyT>, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, n, shift, nb,
                            offs, ko, vo);
         std::swap(ki, ko);
         std::swap(vi, vo);
@@ -246,6 +249,20 @@ hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, 
     }
     *result_in_alt = alt;
     return hipGetLastError();
+}
+
+hipError_t radix_sort_pairs(uint64_t* keys, uint32_t* vals, uint64_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                            int begin_bit, int end_bit, void* tmp, size_t tmp_bytes, bool* result_in_alt,
+                            hipStream_t s) {
+    return radix_sort_impl<uint64_t>(keys, vals, keys_alt, vals_alt, n, begin_bit, end_bit, tmp, tmp_bytes,
+                                      result_in_alt, s);
+}
+
+hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_alt, uint32_t* vals_alt, int64_t n,
+                                int begin_bit, int end_bit, void* tmp, size_t tmp_bytes, bool* result_in_alt,
+                                hipStream_t s) {
+    return radix_sort_impl<uint32_t>(keys, vals, keys_alt, vals_alt, n, begin_bit, end_bit, tmp, tmp_bytes,
+                                      result_in_alt, s);
 }
 
 }  // namespace lm

@@ -1,5 +1,6 @@
 """Edge cases of the HIP path against the oracle: a view that sees nothing,
-a scene with no visible Gaussian (no keys, no pairs), a single Gaussian, and
+a scene with no visible Gaussian (no keys, no pairs), a single Gaussian,
+splats so large that one (Gaussian, view) owns more than 128 segments, and
 option validation."""
 import numpy as np
 import pytest
@@ -88,6 +89,28 @@ def test_single_gaussian_sh3():
     p = random_direction(sc.P, sc.N, seed=4)
     g = B.lm_apply_JtJ(cache, torch.from_numpy(p).cuda()).cpu().numpy().ravel()
     assert rel(g, J.apply_JtJ(p.astype(np.float64))) < 1e-5
+
+
+def test_large_splats_span_many_tiles():
+    """A few splats covering a whole 192x192 view (144 tiles): the segment
+    list of one (Gaussian, view) crosses several 64-entry waves of the
+    per-(Gaussian, view) reductions behind J^T u and diag(J^T J)."""
+    sc, _ = sg.make_scene(6, 0, 25, mean_lo=-0.2, mean_hi=0.2, logscale_mu=0.0, logscale_sigma=0.1)
+    cams = sg.fibonacci_cameras(1, 192, 192)
+    imgs = forward.render_images(sc.x, cams, 0)
+    target = (np.stack(imgs) * 0.8 + 0.05).astype(np.float32)
+    J = jacobian.Jacobian(sc.x, cams, 0)
+    B, x, cache, b, fsq = _run(sc, cams, target)
+    info = cache.info()
+    assert info["n_pairs"] == J.n_pairs
+    assert info["n_segments"] > 3 * 64 and info["n_gv"] <= 6   # some gv owns > 128 segments
+    assert rel(b.cpu().numpy().ravel(), J.b(list(target))) < 1e-5
+    M = B.lm_jacobi_diag(cache).cpu().numpy().ravel()
+    assert rel(M, J.diag_JtJ()) < 1e-5
+    for seed in (5, 6):
+        p = random_direction(sc.P, sc.N, seed=seed)
+        g = B.lm_apply_JtJ(cache, torch.from_numpy(p).cuda()).cpu().numpy().ravel()
+        assert rel(g, J.apply_JtJ(p.astype(np.float64))) < 1e-5
 
 
 def test_invalid_options_are_rejected():
