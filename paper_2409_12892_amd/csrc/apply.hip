@@ -18,10 +18,11 @@
 // in one tile, in pixel order) starts on a multiple of 8 pairs and is padded
 // with zero words, so each aligned run of 8 pairs belongs to exactly one
 // segment, named by the run -> segment table.
-//   J  : a wave takes one segment at a time, one pair per lane; the pixels of
-//        a segment are distinct, so each wave adds the colour derivatives
-//        into private per-pixel LDS accumulators without atomics, and the
-//        waves' accumulators are summed at the end.
+//   J  : a wave takes 64 consecutive pairs at a time, one per lane, and adds
+//        the colour derivatives into private per-pixel LDS accumulators; the
+//        pixels of one segment are distinct, so the segment pieces of the
+//        window update one after another without atomics, and the waves'
+//        accumulators are summed at the end.
 //   J^T: a lane takes one 8-pair run (vector loads of every cache plane, the
 //        next run prefetched), sums the 9 moments of its run in registers; a
 //        segmented scan over the wave (keyed by segment, runs ascending
@@ -36,15 +37,8 @@ namespace {
 constexpr int kThreads = 256;  // threads per tile workgroup (4 wave64)
 constexpr int kChunk = 256;    // segments staged per LDS chunk
 constexpr int kRun = 8;        // pairs per run (segments are padded to runs)
-// pixel accumulators: padded pixel slots [0, 287), a zero slot that is never
-// written (read by padding pairs in J^T) and one sink slot per lane (written
-// by padding pairs in J), so the per-pair code has no branches
-constexpr int kUZero = kMaxTilePix + kMaxTilePix / 8 - 1;
-constexpr int kUSink = kUZero + 1;
-constexpr int kUTot = kUSink + kWave;
 constexpr int MODE_J = 1, MODE_JT = 2, MODE_JTJ = 3;
 
-__device__ __forceinline__ int upad(int pl) { return pl + (pl >> 3); }
 
 // Data-parallel-primitive lane moves (VALU, no LDS): lanes whose source is
 // outside the row or in a row not selected by ROWMASK read 0.
@@ -201,33 +195,41 @@ __global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
 // Per pair, with the splat staged in LDS: alpha and dalpha/dy are recomputed
 // from the pixel position and the cached T, dC/dalpha give
 //   J row block . dy = D (dalpha/dy_geo . a) + alpha T dc      (a: power coefficients)
+// The staged splat holds the mean shifted to pixel-centre coordinates and
+// the conic scaled by -log2(e)/2 (and -log2(e) for B), so exp(power) is one
+// exp2 of a quadratic form.
 template <int DT>
 struct PairLoad {
     using W = typename Store<DT>::word;
     W t, d0, d1, d2;
     uint8_t pix;
+    uint32_t seg;
     __device__ __forceinline__ void load(const CacheView& c, int64_t q, bool live) {
-        t = 0; d0 = 0; d1 = 0; d2 = 0; pix = 0;
+        t = 0; d0 = 0; d1 = 0; d2 = 0; pix = 0; seg = 0xFFFFFFFFu;
         if (live) {
             t = ((const W*)c.pT)[q];
             d0 = ((const W*)c.pD)[q];
             d1 = ((const W*)c.pD)[c.pair_stride + q];
             d2 = ((const W*)c.pD)[2 * c.pair_stride + q];
             pix = c.ppix[q];
+            seg = c.run_seg[q / kRun];
         }
     }
 };
+
+constexpr float kLog2e = 1.4426950408889634f;
 
 template <int MODE, int DT>
 __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     if (a.stop && *a.stop) return;
     using S = Store<DT>;
     constexpr int NW = kThreads / kWave;
+    constexpr int kZero = kMaxTilePix;           // pixel slot that stays 0 (read by padding)
     const CacheView& c = a.c;
-    // s_up[w]: wave w's private pixel accumulators in the J half; after the
-    // J half s_up[0] holds u (read by the J^T half)
-    __shared__ float s_up[NW][3][kUTot];
-    __shared__ float4 s_sg[kChunk][4];   // mx, my, A, B | C, o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
+    // s_u[w]: wave w's private accumulators (u0, u1, u2, -) per pixel in the
+    // J half; afterwards s_u[0] holds u, read by the J^T half
+    __shared__ float4 s_u[NW][kMaxTilePix + 1];
+    __shared__ float4 s_sg[kChunk][4];   // mx', my', A', B' | C', o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
     __shared__ uint32_t s_loc[kChunk + 1];
     __shared__ float s_mom[9][kChunk];
     __shared__ double s_red[NW];
@@ -247,15 +249,10 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
-    {
-        float* all = &s_up[0][0][0];
-        for (int i = tid; i < NW * 3 * kUTot; i += kThreads) all[i] = 0.0f;
-    }
+    for (int i = tid; i < NW * (kMaxTilePix + 1); i += kThreads) (&s_u[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
-    if (MODE == MODE_JT && tid < kMaxTilePix && valid) {
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) s_up[0][ch][upad(tid)] = a.uin[ib + ch * HW];
-    }
+    if (MODE == MODE_JT && tid < kMaxTilePix && valid)
+        s_u[0][tid] = make_float4(a.uin[ib], a.uin[ib + HW], a.uin[ib + 2 * HW], 0.0f);
 
     // segments [c0, c0 + cn) of the tile: splat data (and tangents) and pair
     // ranges into LDS
@@ -263,8 +260,9 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
         for (int i = tid; i < cn; i += kThreads) {
             const int64_t s = sb + c0 + i;
             const int64_t ss = c.seg_stride;
-            s_sg[i][0] = make_float4(c.seg_f[s], c.seg_f[ss + s], c.seg_f[2 * ss + s], c.seg_f[3 * ss + s]);
-            float4 w1 = make_float4(c.seg_f[4 * ss + s], c.seg_f[5 * ss + s], 0.0f, 0.0f);
+            s_sg[i][0] = make_float4(c.seg_f[s] - 0.5f, c.seg_f[ss + s] - 0.5f, -0.5f * kLog2e * c.seg_f[2 * ss + s],
+                                     -kLog2e * c.seg_f[3 * ss + s]);
+            float4 w1 = make_float4(-0.5f * kLog2e * c.seg_f[4 * ss + s], c.seg_f[5 * ss + s], 0.0f, 0.0f);
             if (tangents) {
                 const float* dy = a.dyc + (int64_t)c.seg_gv[s] * 9;
                 w1.z = dy[0];
@@ -279,62 +277,79 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     };
 
     // ---------------- J p ----------------
-    // Wave w takes segments w, w + NW, ... of each chunk, 64 consecutive pairs
-    // (one per lane) at a time: the pixels of one segment are distinct, so
-    // the wave adds into its private accumulators without atomics.
+    // Wave w takes the 64-pair windows w, w + NW, ... of each chunk's pairs,
+    // one pair per lane, and adds into its private accumulators.  Pixels are
+    // distinct within a segment, so the window's segment pieces (contiguous
+    // lane ranges) update the accumulators one after another and need no
+    // atomics.
     if (MODE & MODE_J) {
-        float* up = &s_up[wid][0][0];
+        float4* up = s_u[wid];
         for (int c0 = 0; c0 < nseg; c0 += kChunk) {
             const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
             __syncthreads();
             stage(c0, cn, true);
             __syncthreads();
-            int i = wid;
-            uint32_t off = 0;
+            const int64_t q0 = pb + s_loc[0], q1 = pb + s_loc[cn];
+            const int64_t nwin = (q1 - q0 + kWave - 1) / kWave;
+            const int64_t sbase = sb + c0;
             PairLoad<DT> nxt;
-            if (i < cn) nxt.load(c, pb + s_loc[i] + lane, (uint32_t)lane < s_loc[i + 1] - s_loc[i]);
-            while (i < cn) {
+            if (wid < nwin) nxt.load(c, q0 + wid * kWave + lane, q0 + wid * kWave + lane < q1);
+            for (int64_t win = wid; win < nwin; win += NW) {
                 const PairLoad<DT> L = nxt;
-                const int si = i;
-                if (off + kWave < s_loc[i + 1] - s_loc[i]) {
-                    off += kWave;
-                } else {
-                    i += NW;
-                    off = 0;
-                }
-                if (i < cn) nxt.load(c, pb + s_loc[i] + off + lane, off + lane < s_loc[i + 1] - s_loc[i]);
-                const float4 g0 = s_sg[si][0], g1 = s_sg[si][1], g2 = s_sg[si][2], g3 = s_sg[si][3];
+                const int64_t qn = q0 + (win + NW) * kWave + lane;
+                if (win + NW < nwin) nxt.load(c, qn, qn < q1);
+                const int64_t sl = (int64_t)L.seg - sbase;
+                const bool live = L.t != 0 && sl >= 0 && sl < cn;   // not padding, not past the chunk
+                const int s = live ? (int)sl : 0;
+                const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
                 const float T = S::dec_T(L.t);
                 const bool clamped = S::clamp(L.t);
                 const int pl = L.pix;
-                const float dx = (float)(pl & tw_mask) + 0.5f - g0.x;
-                const float dy = (float)(pl >> tw_shift) + 0.5f - g0.y;
-                const float power = -0.5f * (g0.z * dx * dx + g1.x * dy * dy) - g0.w * dx * dy;
-                const float G = __expf(power);
+                const float dx = (float)(pl & tw_mask) - g0.x;
+                const float dy = (float)(pl >> tw_shift) - g0.y;
+                const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
                 const float alpha = clamped ? 0.99f : g1.y * G;
                 const float aT = alpha * T;
                 const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
                 const float dal = clamped ? 0.0f : dal_f;
-                const int ui = L.t != 0 ? upad(pl) : kUSink + lane;   // padding or no pair -> sink
-                up[ui] += S::dec(L.d0) * dal + aT * g3.x;
-                up[kUTot + ui] += S::dec(L.d1) * dal + aT * g3.y;
-                up[2 * kUTot + ui] += S::dec(L.d2) * dal + aT * g3.z;
+                const float v0 = S::dec(L.d0) * dal + aT * g3.x;
+                const float v1 = S::dec(L.d1) * dal + aT * g3.y;
+                const float v2 = S::dec(L.d2) * dal + aT * g3.z;
+                uint64_t todo = __ballot(live);
+                while (todo) {
+                    const int first = __ffsll((unsigned long long)todo) - 1;
+                    const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)L.seg, first);
+                    const bool mine = live && L.seg == sk;
+                    todo &= ~__ballot(mine);
+                    if (mine) {
+                        float4 u = up[pl];
+                        u.x += v0;
+                        u.y += v1;
+                        u.z += v2;
+                        up[pl] = u;
+                    }
+                }
             }
         }
         __syncthreads();
         // u = sum of the waves' accumulators; ||J p||^2 of the tile
         double sq = 0.0;
         if (tid < kMaxTilePix) {
-            const int ui = upad(tid);
+            float4 u = s_u[0][tid];
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                float u = 0.0f;
-#pragma unroll
-                for (int w = 0; w < NW; ++w) u += s_up[w][ch][ui];
-                s_up[0][ch][ui] = u;
-                if (valid) {
-                    sq += (double)u * (double)u;
-                    if (MODE == MODE_J) a.uout[ib + ch * HW] = u;
+            for (int w = 1; w < NW; ++w) {
+                const float4 o = s_u[w][tid];
+                u.x += o.x;
+                u.y += o.y;
+                u.z += o.z;
+            }
+            s_u[0][tid] = u;
+            if (valid) {
+                sq = (double)u.x * (double)u.x + (double)u.y * (double)u.y + (double)u.z * (double)u.z;
+                if (MODE == MODE_J) {
+                    a.uout[ib] = u.x;
+                    a.uout[ib + HW] = u.y;
+                    a.uout[ib + 2 * HW] = u.z;
                 }
             }
         }
@@ -376,21 +391,18 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
             for (int k = 0; k < 9; ++k) m[k] = 0.0f;
             if (s < kChunk) {
                 const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
-                const float mx = g0.x, my = g0.y, A = g0.z, B = g0.w, C = g1.x, o = g1.y;
 #pragma unroll
                 for (int k = 0; k < kRun; ++k) {
                     const float T = S::dec_T(L.t[k]);
                     const bool clamped = S::clamp(L.t[k]);
                     const int pl = L.pix[k];
-                    const float dx = (float)(pl & tw_mask) + 0.5f - mx;
-                    const float dy = (float)(pl >> tw_shift) + 0.5f - my;
-                    const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
-                    const float G = __expf(power);
-                    const float alpha = clamped ? 0.99f : o * G;
+                    const float dx = (float)(pl & tw_mask) - g0.x;
+                    const float dy = (float)(pl >> tw_shift) - g0.y;
+                    const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
+                    const float alpha = clamped ? 0.99f : g1.y * G;
                     const float aT = alpha * T;                               // 0 for padding
-                    const int ui = L.t[k] != 0 ? upad(pl) : kUZero;           // padding reads u = 0
-                    const float u0 = s_up[0][0][ui], u1 = s_up[0][1][ui], u2 = s_up[0][2][ui];
-                    const float w = S::dec(L.d[0][k]) * u0 + S::dec(L.d[1][k]) * u1 + S::dec(L.d[2][k]) * u2;
+                    const float4 u = s_u[0][L.t[k] != 0 ? pl : kZero];       // padding reads u = 0
+                    const float w = S::dec(L.d[0][k]) * u.x + S::dec(L.d[1][k]) * u.y + S::dec(L.d[2][k]) * u.z;
                     const float aw = clamped ? 0.0f : alpha * w;
                     const float awx = aw * dx, awy = aw * dy;
                     m[0] += awx;
@@ -399,9 +411,9 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
                     m[3] += awx * dy;
                     m[4] += awy * dy;
                     m[5] += clamped ? 0.0f : G * w;
-                    m[6] += aT * u0;
-                    m[7] += aT * u1;
-                    m[8] += aT * u2;
+                    m[6] += aT * u.x;
+                    m[7] += aT * u.y;
+                    m[8] += aT * u.z;
                 }
             }
             // segmented scan over the wave: runs ascend with the lane, so each
