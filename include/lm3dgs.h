@@ -174,6 +174,12 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
                              const float* target, const lm_options* opts, void* stream,
                              lm_cache** workspace, double* F_sqnorm);
 
+/* Per-view ||F||^2 of a built cache (the residual at the x it was built at,
+ * split by view; their sum is the F_sqnorm of lm_build_cache).  Used by
+ * the line search of section 3.2 (eq. line-search), which compares errors on
+ * a subset of the views.  per_view: dev double [V], written in view order. */
+lm_status lm_cache_view_sqnorm(const lm_cache* cache, double* per_view, void* stream);
+
 /* Copy an internal array of a built cache to host memory (inspection and
  * tests).  Synchronises the stream.  `what` selects the array; `bytes` must
  * equal the array's size (lm_cache_export_size()). */

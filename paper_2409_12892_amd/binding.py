@@ -33,6 +33,7 @@ EXPORTED_SYMBOLS = (
     "lm_last_error", "lm_build_cache", "lm_cache_destroy", "lm_cache_get_info", "lm_jacobi_diag",
     "lm_apply_JtJ", "lm_apply_J", "lm_apply_JT", "lm_pcg_solve", "lm_combine_subsets", "lm_render",
     "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
+    "lm_cache_view_sqnorm",
 )
 
 
@@ -161,10 +162,10 @@ class Cache:
 
 
 def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtype: str = "f32",
-                   cache: Cache | None = None, want_b: bool = True):
+                   cache: Cache | None = None, want_b: bool = True, b=None):
     """Build the gradient cache of one subset.  Returns (cache, b, F_sqnorm)
-    with b = -J^T F as a [P, N] tensor and ||F||^2 as a 1-element float64
-    tensor (both None when want_b is False)."""
+    with b = -J^T F as a [P, N] tensor (written into `b` when given) and
+    ||F||^2 as a 1-element float64 tensor (both None when want_b is False)."""
     import torch
     lib = load()
     x = _dev_f32(x, "x")
@@ -174,7 +175,10 @@ def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtyp
     opts = LmOptions(tile[0], tile[1], CACHE_DTYPES[cache_dtype], 0)
     carr = camera_array(cams)
     cache = Cache() if cache is None else cache
-    b = torch.empty((P, N), device=x.device, dtype=torch.float32) if want_b else None
+    if want_b and b is None:
+        b = torch.empty((P, N), device=x.device, dtype=torch.float32)
+    elif not want_b:
+        b = None
     fsq = torch.empty(1, device=x.device, dtype=torch.float64) if want_b else None
     h = cache.handle
     _check(lib.lm_build_cache(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), _stream(),
@@ -269,6 +273,15 @@ def lm_residual_sqnorm(x, sh_degree: int, cams, target, *, tile=(16, 16), worksp
                                      byref(h), _ptr(out)), "lm_residual_sqnorm")
     ws.handle = h
     return out, ws
+
+
+def lm_cache_view_sqnorm(cache: Cache, out=None):
+    """Per-view ||F||^2 of a built cache (float64 device tensor [V])."""
+    import torch
+    V = cache.info()["V"]
+    out = torch.empty(V, device="cuda", dtype=torch.float64) if out is None else out
+    _check(load().lm_cache_view_sqnorm(cache.handle, _ptr(out), _stream()), "lm_cache_view_sqnorm")
+    return out
 
 
 def lm_profile_enable(on: bool = True) -> None:

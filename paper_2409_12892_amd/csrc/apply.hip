@@ -278,7 +278,8 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
 
     // ---------------- J p ----------------
     // Wave w takes the 64-pair windows w, w + NW, ... of each chunk's pairs,
-    // one pair per lane, and adds into its private accumulators.  Pixels are
+    // one pair per lane, two windows per round (the next two prefetched),
+    // and adds into its private accumulators.  Pixels are
     // distinct within a segment, so the window's segment pieces (contiguous
     // lane ranges) update the accumulators one after another and need no
     // atomics.
@@ -292,41 +293,47 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
             const int64_t q0 = pb + s_loc[0], q1 = pb + s_loc[cn];
             const int64_t nwin = (q1 - q0 + kWave - 1) / kWave;
             const int64_t sbase = sb + c0;
-            PairLoad<DT> nxt;
-            if (wid < nwin) nxt.load(c, q0 + wid * kWave + lane, q0 + wid * kWave + lane < q1);
-            for (int64_t win = wid; win < nwin; win += NW) {
-                const PairLoad<DT> L = nxt;
-                const int64_t qn = q0 + (win + NW) * kWave + lane;
-                if (win + NW < nwin) nxt.load(c, qn, qn < q1);
-                const int64_t sl = (int64_t)L.seg - sbase;
-                const bool live = L.t != 0 && sl >= 0 && sl < cn;   // not padding, not past the chunk
-                const int s = live ? (int)sl : 0;
-                const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
-                const float T = S::dec_T(L.t);
-                const bool clamped = S::clamp(L.t);
-                const int pl = L.pix;
-                const float dx = (float)(pl & tw_mask) - g0.x;
-                const float dy = (float)(pl >> tw_shift) - g0.y;
-                const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
-                const float alpha = clamped ? 0.99f : g1.y * G;
-                const float aT = alpha * T;
-                const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
-                const float dal = clamped ? 0.0f : dal_f;
-                const float v0 = S::dec(L.d0) * dal + aT * g3.x;
-                const float v1 = S::dec(L.d1) * dal + aT * g3.y;
-                const float v2 = S::dec(L.d2) * dal + aT * g3.z;
-                uint64_t todo = __ballot(live);
-                while (todo) {
-                    const int first = __ffsll((unsigned long long)todo) - 1;
-                    const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)L.seg, first);
-                    const bool mine = live && L.seg == sk;
-                    todo &= ~__ballot(mine);
-                    if (mine) {
-                        float4 u = up[pl];
-                        u.x += v0;
-                        u.y += v1;
-                        u.z += v2;
-                        up[pl] = u;
+            PairLoad<DT> na, nb;
+            auto q_of = [&](int64_t w) { return q0 + w * kWave + lane; };
+            if (wid < nwin) na.load(c, q_of(wid), q_of(wid) < q1);
+            if (wid + NW < nwin) nb.load(c, q_of(wid + NW), q_of(wid + NW) < q1);
+            for (int64_t win = wid; win < nwin; win += 2 * NW) {
+                PairLoad<DT> Ls[2] = {na, nb};
+                if (win + 2 * NW < nwin) na.load(c, q_of(win + 2 * NW), q_of(win + 2 * NW) < q1);
+                if (win + 3 * NW < nwin) nb.load(c, q_of(win + 3 * NW), q_of(win + 3 * NW) < q1);
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    const PairLoad<DT>& L = Ls[h];
+                    const int64_t sl = (int64_t)L.seg - sbase;
+                    const bool live = L.t != 0 && sl >= 0 && sl < cn;
+                    const int s = live ? (int)sl : 0;
+                    const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
+                    const float T = S::dec_T(L.t);
+                    const bool clamped = S::clamp(L.t);
+                    const int pl = L.pix;
+                    const float dx = (float)(pl & tw_mask) - g0.x;
+                    const float dy = (float)(pl >> tw_shift) - g0.y;
+                    const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
+                    const float alpha = clamped ? 0.99f : g1.y * G;
+                    const float aT = alpha * T;
+                    const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
+                    const float dal = clamped ? 0.0f : dal_f;
+                    const float v0 = S::dec(L.d0) * dal + aT * g3.x;
+                    const float v1 = S::dec(L.d1) * dal + aT * g3.y;
+                    const float v2 = S::dec(L.d2) * dal + aT * g3.z;
+                    uint64_t todo = __ballot(live);
+                    while (todo) {
+                        const int first = __ffsll((unsigned long long)todo) - 1;
+                        const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)L.seg, first);
+                        const bool mine = live && L.seg == sk;
+                        todo &= ~__ballot(mine);
+                        if (mine) {
+                            float4 u = up[pl];
+                            u.x += v0;
+                            u.y += v1;
+                            u.z += v2;
+                            up[pl] = u;
+                        }
                     }
                 }
             }

@@ -737,6 +737,13 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
     return st;
 }
 
+lm_status lm_cache_view_sqnorm(const lm_cache* c, double* per_view, void* stream) {
+    LM_CHECK(c && per_view, LM_ERR_INVALID_ARG, "lm_cache_view_sqnorm: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    LM_HIP(lm::view_sum_f64(c->cams.as<lm::CamDev>(), c->V, c->fsq_part.as<double>(), per_view, S(stream)));
+    return LM_OK;
+}
+
 int64_t lm_cache_export_size(const lm_cache* c, int32_t what) {
     if (!c || !c->built) return -1;
     switch (what) {

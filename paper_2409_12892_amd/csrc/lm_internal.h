@@ -160,6 +160,7 @@ hipError_t radix_sort_pairs_u32(uint32_t* keys, uint32_t* vals, uint32_t* keys_a
                                 int begin_bit, int end_bit, void* tmp, size_t tmp_bytes, bool* result_in_alt,
                                 hipStream_t s);
 size_t radix_tmp_bytes(int64_t n);
+hipError_t view_sum_f64(const CamDev* cams, int V, const double* in, double* out, hipStream_t s);
 hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s);
 
 

@@ -186,7 +186,32 @@ __global__ void k_radix_scatter(const KeyT* __restrict__ keys, const uint32_t* _
     }
 }
 
+// out[v] = sum of in[tile_base_v .. tile_base_v + TX TY), one workgroup per view.
+__global__ void k_view_sum_f64(const CamDev* __restrict__ cams, const double* __restrict__ in,
+                               double* __restrict__ out) {
+    __shared__ double red[kBlock / kWave];
+    const CamDev& cam = cams[blockIdx.x];
+    const int64_t n = (int64_t)cam.TX * cam.TY;
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += kBlock) acc += in[cam.tile_base + i];
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) acc += __shfl_xor(acc, off, kWave);
+    if (__lane_id() == 0) red[threadIdx.x / kWave] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double tot = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) tot += red[w];
+        out[blockIdx.x] = tot;
+    }
+}
+
 }  // namespace
+
+hipError_t view_sum_f64(const CamDev* cams, int V, const double* in, double* out, hipStream_t s) {
+    if (V <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_view_sum_f64, dim3((unsigned)V), dim3(kBlock), 0, s, cams, in, out);
+    return hipGetLastError();
+}
 
 size_t scan_tmp_bytes(int64_t n) {
     int64_t nb = (n + kScanTile - 1) / kScanTile;

@@ -1,18 +1,23 @@
 """Levenberg-Marquardt outer loop around the HIP hot path (paper section 3.2).
 
-One iteration: build the gradient cache at x (b = -J^T F, ||F||^2), the
-Jacobi diagonal M, Algorithm 1 for delta, the subset combination, then
+One iteration: the gradient cache at x (b = -J^T F, ||F||^2), the Jacobi
+diagonal M, Algorithm 1 for delta, the subset combination, then
 
 * line search  min_gamma E(x + gamma delta) on a subset of the views
   (eq. line-search; the paper uses 30% of the images and does not name the
-  method - here: gamma = 1, 1/2, 1/4, ... down to 2^-12; keep the best value
-  and stop once the error has dropped below E(x) on the subset and then
-  rises again);
+  method - here: gamma on the grid 1, 1/2, 1/4, ..., 2^-12, starting from the
+  previous iteration's gamma; larger steps are tried while they lower the
+  subset error, then smaller ones while they lower it or while no step has
+  yet beaten E(x) on the subset, whose value comes from the cache's per-view
+  residuals; the best evaluated gamma is taken);
 * trust-region ratio (eq. tr-update)
       rho = (||F(x)||^2 - ||F(x + g d)||^2) / (||F(x)||^2 - ||J g d + F(x)||^2)
   with the model decrease 2 g d^T b - g^2 ||J d||^2; keep the step when
   rho > 1e-5 and scale lambda by 1 - (2 rho - 1)^3, otherwise revert and
-  double lambda; lambda is clamped to [lam_min, lam_max].
+  double lambda; lambda is clamped to [lam_min, lam_max].  ||F(x + g d)||^2
+  comes from building the cache at the trial point, which is the next
+  iteration's cache when the step is accepted (a rejected step rebuilds at
+  x).
 
 The solve uses a minimum LM diagonal (diag_floor, CERES's safeguard; the
 paper follows CERES for the lambda schedule): on scenes with deeply occluded
@@ -69,6 +74,10 @@ class LMSolver:
         offs = np.concatenate([[0], np.cumsum(sizes)])
         self.ls_target = torch.cat([target[offs[v]:offs[v + 1]] for v in self.ls_idx]).contiguous()
         self.cache = None
+        self.b = None
+        self.fsq = None
+        self.built_at_x = False
+        self.k_prev = 0
         self.ws = None
         self.M = None
         self.delta = None
@@ -80,11 +89,17 @@ class LMSolver:
         val, self.ws = B.lm_residual_sqnorm(x, self.deg, cams, target, tile=self.cfg.tile, workspace=self.ws)
         return float(val.item())
 
+    def _build(self, x):
+        cfg = self.cfg
+        self.cache, self.b, self.fsq = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
+                                                        cache_dtype=cfg.cache_dtype, cache=self.cache, b=self.b)
+
     def iteration(self) -> dict:
         import torch
         cfg = self.cfg
-        self.cache, b, fsq = B.lm_build_cache(self.x, self.deg, self.cams, self.target, tile=cfg.tile,
-                                              cache_dtype=cfg.cache_dtype, cache=self.cache)
+        if not self.built_at_x:
+            self._build(self.x)
+        b, fsq = self.b, self.fsq
         self.M = B.lm_jacobi_diag(self.cache, out=self.M)
         deltas, stats = B.lm_pcg_solve([self.cache], [b], [self.M], self.lam, cfg.n_iters, cfg.tol, cfg.tol_mode,
                                        deltas=None if self.delta is None else [self.delta],
@@ -96,19 +111,33 @@ class LMSolver:
         E0 = float(fsq.item())
         dTb = float(torch.dot(d.reshape(-1).double(), b.reshape(-1).double()).item())
         Jd2 = float(jd.item())
-        # line search on the view subset
-        E_ref = self._E(self.x, self.ls_cams, self.ls_target)
-        best_g, best_E = cfg.gammas[-1], np.inf
-        for g in cfg.gammas:
-            torch.add(self.x, d, alpha=g, out=self.x_try)
-            E = self._E(self.x_try, self.ls_cams, self.ls_target)
-            if E < best_E:
-                best_g, best_E = g, E
-            elif best_E < E_ref:
-                break
-        g = best_g
+        per_view = B.lm_cache_view_sqnorm(self.cache)
+        E_ref = float(per_view[torch.as_tensor(self.ls_idx, device=per_view.device)].sum().item())
+        # line search on the view subset (grid 2^-k, warm start at the last k)
+        gammas = cfg.gammas
+        evals = {}
+
+        def E(k):
+            if k not in evals:
+                torch.add(self.x, d, alpha=gammas[k], out=self.x_try)
+                evals[k] = self._E(self.x_try, self.ls_cams, self.ls_target)
+            return evals[k]
+
+        k = min(self.k_prev, len(gammas) - 1)
+        k0 = k
+        while k > 0 and E(k - 1) < E(k):
+            k -= 1
+        if k == k0:
+            while k + 1 < len(gammas) and (E(k + 1) < E(k) or min(evals.values()) >= E_ref):
+                k += 1
+        k = min(evals, key=lambda kk: (evals[kk], kk))
+        self.k_prev = k
+        g = gammas[k]
         torch.add(self.x, d, alpha=g, out=self.x_try)
-        E1 = self._E(self.x_try, self.cams, self.target)
+        # the cache at the trial point gives ||F(x + g d)||^2 and serves the
+        # next iteration if the step is accepted
+        self._build(self.x_try)
+        E1 = float(self.fsq.item())
         pred = 2.0 * g * dTb - g * g * Jd2
         rho = (E0 - E1) / pred if pred > 0 else -np.inf
         accepted = bool(rho > cfg.rho_min and np.isfinite(E1))
@@ -118,9 +147,11 @@ class LMSolver:
             self.lam = self.lam * (1.0 - (2.0 * rho - 1.0) ** 3)
         else:
             self.lam = self.lam * 2.0
+        self.built_at_x = accepted
         self.lam = float(min(max(self.lam, cfg.lam_min), cfg.lam_max))
         rec = dict(E0=E0, E1=E1, gamma=g, rho=rho, accepted=accepted, lam=lam_old, lam_next=self.lam,
-                   pcg_iters=stats[0]["iters"], pcg_rel_res_sq=float(stats[0]["history"][-1]))
+                   pcg_iters=stats[0]["iters"], pcg_rel_res_sq=float(stats[0]["history"][-1]),
+                   line_search_evals=len(evals))
         self.history.append(rec)
         return rec
 

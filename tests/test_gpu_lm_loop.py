@@ -35,6 +35,22 @@ def test_lm_iterations_decrease_error():
     solver.close()
 
 
+def test_per_view_residuals_match_oracle():
+    from paper_2409_12892_amd import binding as B
+    from oracle import forward
+    pr = make_problem("tiny", with_J=False)
+    sc, cams, target = pr["scene"], pr["cams"], pr["target"]
+    x = torch.from_numpy(sc.x).cuda()
+    tgt = torch.from_numpy(target.ravel()).cuda()
+    cache, b, fsq = B.lm_build_cache(x, sc.sh_degree, cams, tgt)
+    pv = B.lm_cache_view_sqnorm(cache).cpu().numpy()
+    imgs = forward.render_images(sc.x, cams, sc.sh_degree)
+    ref = np.array([np.sum((im - t.astype(np.float64)) ** 2) for im, t in zip(imgs, target)])
+    np.testing.assert_allclose(pv, ref, rtol=1e-10)
+    assert float(pv.sum()) == pytest.approx(float(fsq.item()), rel=1e-13)
+    cache.destroy()
+
+
 def test_residual_sqnorm_matches_build():
     from paper_2409_12892_amd import binding as B
     pr = make_problem("tiny", with_J=False)
