@@ -22,6 +22,13 @@ The assembled J is a SciPy CSR matrix with rows indexed like the residual
 images [view][channel][row][col] and columns like the structure-of-arrays
 parameter vector x[P][N] flattened (j * N + g).
 
+Storing the cache in a 16-bit type (the low-precision cache of the hot
+path) rounds each pair's T and dC/dalpha: T and D enter every Jacobian
+entry linearly, J = D_ch * (dalpha/dy_geo . dy_geo/dx) + alpha T *
+dc_ch/dx, so ``Jacobian.rounded(dtype)`` re-evaluates J with T and D
+rounded as stored (float64 -> float32 -> bfloat16 or float16, round to
+nearest even) and everything else exact.
+
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
 from __future__ import annotations
@@ -32,6 +39,25 @@ import scipy.sparse as sp
 from .forward import project, render
 
 _CSTEP = 1e-30
+
+
+def round_bf16(v: np.ndarray) -> np.ndarray:
+    """float64 -> float32 -> bfloat16 (round to nearest, ties to even),
+    returned as float64."""
+    f = np.ascontiguousarray(np.asarray(v, np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def round_f16(v: np.ndarray) -> np.ndarray:
+    """float64 -> float32 -> IEEE binary16 (round to nearest even), returned
+    as float64."""
+    return np.asarray(v, np.float64).astype(np.float32).astype(np.float16).astype(np.float64)
+
+
+CACHE_ROUNDING = {"f32": lambda v: np.asarray(v, np.float64).astype(np.float32).astype(np.float64),
+                  "bf16": round_bf16, "f16": round_f16}
 
 
 def dydx_complex_step(x: np.ndarray, cam: dict, deg: int) -> np.ndarray:
@@ -47,10 +73,9 @@ def dydx_complex_step(x: np.ndarray, cam: dict, deg: int) -> np.ndarray:
     return out
 
 
-def dC_dy(pairs: dict, y: np.ndarray) -> np.ndarray:
-    """Per-pair 3 x 9 block of d(pixel colour) / d(splat attributes)."""
+def dalpha_dygeo(pairs: dict, y: np.ndarray) -> np.ndarray:
+    """Per-pair d alpha / d(m_x, m_y, A, B, C, o), zero for a clamped alpha."""
     a = pairs["alpha"]
-    T = pairs["T"]
     G = pairs["G"]
     dx = pairs["dx"]
     dy = pairs["dy"]
@@ -63,7 +88,14 @@ def dC_dy(pairs: dict, y: np.ndarray) -> np.ndarray:
     dadB = np.where(live, -a * dx * dy, 0.0)
     dadC = np.where(live, -0.5 * a * dy * dy, 0.0)
     dado = np.where(live, G, 0.0)
-    geo = np.stack([dadm_x, dadm_y, dadA, dadB, dadC, dado], axis=1)        # [n,6]
+    return np.stack([dadm_x, dadm_y, dadA, dadB, dadC, dado], axis=1)     # [n,6]
+
+
+def dC_dy(pairs: dict, y: np.ndarray) -> np.ndarray:
+    """Per-pair 3 x 9 block of d(pixel colour) / d(splat attributes)."""
+    a = pairs["alpha"]
+    T = pairs["T"]
+    geo = dalpha_dygeo(pairs, y)
     out = np.zeros((len(a), 3, 9))
     out[:, :, 0:6] = pairs["D"][:, :, None] * geo[:, None, :]
     for ch in range(3):
@@ -80,7 +112,8 @@ class Jacobian:
         self.P, self.N = x64.shape
         self.deg = deg
         self.views = render(x64, cams, deg, TW, TH) if views is None else views
-        rows, cols, vals = [], [], []
+        rows, cols = [], []
+        geo_part, col_part, Dn, Tn = [], [], [], []
         roff = 0
         self.row_offsets = []
         for vw in self.views:
@@ -91,27 +124,45 @@ class Jacobian:
             self.row_offsets.append(roff)
             if len(pairs["g"]):
                 dydx = dydx_complex_step(x64, cam, deg)                     # [9,P,N]
-                dcdy = dC_dy(pairs, pr["y"])                                # [n,3,9]
                 g = pairs["g"]
-                blk = np.einsum("nci,ijn->ncj", dcdy, dydx[:, :, g])        # [n,3,P]
                 n = len(g)
+                # the pair's block dC/dy @ dy/dx, entry (ch, j) = D_ch * geo_j +
+                # T * col_ch_j with geo = dalpha/dy_geo . dy_geo/dx_j and
+                # col_ch = alpha dc_ch/dx_j (the two factors the cache stores
+                # are kept apart)
+                geo = dalpha_dygeo(pairs, pr["y"])                          # [n,6]
+                gpart = np.einsum("nk,kjn->nj", geo, dydx[0:6][:, :, g])   # [n,P]
+                cpart = pairs["alpha"][:, None, None] * np.transpose(dydx[6:9][:, :, g], (2, 0, 1))  # [n,3,P]
                 r = roff + np.arange(3)[None, :, None] * (H * W) + pairs["pixel"][:, None, None]
                 c = np.arange(self.P)[None, None, :] * self.N + g[:, None, None]
                 rows.append(np.broadcast_to(r, (n, 3, self.P)).ravel())
                 cols.append(np.broadcast_to(c, (n, 3, self.P)).ravel())
-                vals.append(blk.ravel())
+                geo_part.append(np.broadcast_to(gpart[:, None, :], (n, 3, self.P)).ravel())
+                col_part.append(cpart.ravel())
+                Dn.append(np.broadcast_to(pairs["D"][:, :, None], (n, 3, self.P)).ravel())
+                Tn.append(np.broadcast_to(pairs["T"][:, None, None], (n, 3, self.P)).ravel())
             roff += 3 * H * W
         self.n_res = roff
-        if rows:
-            rows = np.concatenate(rows)
-            cols = np.concatenate(cols)
-            vals = np.concatenate(vals)
-        else:
-            rows = cols = np.zeros(0, dtype=np.int64)
-            vals = np.zeros(0)
-        self.J = sp.csr_matrix((vals, (rows, cols)), shape=(self.n_res, self.P * self.N))
+        cat = (lambda lst: np.concatenate(lst)) if rows else (lambda lst: np.zeros(0))
+        self._rows = cat(rows).astype(np.int64)
+        self._cols = cat(cols).astype(np.int64)
+        self._geo, self._col, self._D, self._T = cat(geo_part), cat(col_part), cat(Dn), cat(Tn)
+        self._set_values(self._D * self._geo + self._T * self._col)
+
+    def _set_values(self, vals: np.ndarray) -> None:
+        # every (row, column) comes from one pair: a pixel meets a Gaussian once
+        self.J = sp.csr_matrix((vals, (self._rows, self._cols)), shape=(self.n_res, self.P * self.N))
         self.J.sum_duplicates()
         self.JT = self.J.T.tocsr()
+
+    def rounded(self, dtype: str) -> "Jacobian":
+        """The Jacobian the products see when the cache stores T and
+        dC/dalpha in `dtype` ("f32", "bf16" or "f16")."""
+        out = object.__new__(Jacobian)
+        out.__dict__.update(self.__dict__)
+        rnd = CACHE_ROUNDING[dtype]
+        out._set_values(rnd(self._D) * self._geo + rnd(self._T) * self._col)
+        return out
 
     # ---- images and residuals ----
     def images(self) -> list[np.ndarray]:

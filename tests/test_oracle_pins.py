@@ -471,3 +471,63 @@ def test_combine_equals_joint_solve_when_diagonal():
     obs = np.diag(Aj) > 0
     joint[obs] = np.linalg.solve(Aj[np.ix_(obs, obs)], (bs[0] + bs[1])[obs])
     np.testing.assert_allclose(solve.combine_subsets(deltas, Ms), joint, rtol=1e-12, atol=1e-300)
+
+
+# ---- low-precision cache: rounding of the stored T and dC/dalpha ----
+
+def test_bf16_rounding_ties_to_even_and_error_bound():
+    from oracle.jacobian import round_bf16
+    one = 1.0
+    cases = {one: one, one + 2.0 ** -8: one,                       # tie -> even (1.0)
+             one + 3 * 2.0 ** -8: one + 2.0 ** -6,                 # tie between odd and even -> even
+             one + 2.0 ** -8 + 2.0 ** -20: one + 2.0 ** -7,        # above the tie
+             -2.5: -2.5, 0.0: 0.0}
+    for v, ref in cases.items():
+        assert round_bf16(np.array([v]))[0] == ref, v
+    rng = np.random.default_rng(7)
+    v = rng.uniform(-3, 3, 10000) * 10.0 ** rng.uniform(-4, 0, 10000)
+    r = round_bf16(v)
+    assert np.all(np.abs(r - v) <= 2.0 ** -8 * np.abs(v) * (1 + 1e-6))
+    bits = r.astype(np.float32).view(np.uint32)
+    assert np.all(bits & 0xFFFF == 0)
+
+
+def test_f16_rounding_ties_to_even_and_error_bound():
+    from oracle.jacobian import round_f16
+    one = 1.0
+    cases = {one + 2.0 ** -11: one, one + 3 * 2.0 ** -11: one + 2.0 ** -9, one + 2.0 ** -11 + 2.0 ** -20: one + 2.0 ** -10,
+             1e-4: 1.0001659393310547e-04}       # 1e-4 = 0x068E in binary16 (normal)
+    for v, ref in cases.items():
+        assert round_f16(np.array([v]))[0] == ref, v
+    rng = np.random.default_rng(8)
+    v = rng.uniform(-3, 3, 10000) * 10.0 ** rng.uniform(-4, 0, 10000)
+    v = v[np.abs(v) >= 2.0 ** -14]                    # normal range
+    assert np.all(np.abs(round_f16(v) - v) <= 2.0 ** -11 * np.abs(v) * (1 + 1e-6))
+
+
+def test_rounded_jacobian_within_storage_bound():
+    """J(dtype) differs from J entry by entry by at most the storage rounding
+    of T and D times their coefficients; the first splat of a pixel has
+    T = 1, which every type stores exactly."""
+    d = sg.config_scene("tiny", N=200, subsets=[(2, 32, 32)], seed=31)
+    sc, cams = d["scene"], d["cams"][0]
+    J = jacobian.Jacobian(sc.x, cams, sc.sh_degree)
+    # relative half-ulp of the type, plus (binary16) half the subnormal spacing
+    for dt, eps, tiny in (("f32", 2.0 ** -24, 0.0), ("bf16", 2.0 ** -8, 0.0), ("f16", 2.0 ** -11, 2.0 ** -25)):
+        Jr = J.rounded(dt)
+        assert Jr.J.nnz == J.J.nnz
+        bound = (eps * 1.0001 + 2.0 ** -24) * (np.abs(J._D * J._geo) + np.abs(J._T * J._col)) + tiny * (
+            np.abs(J._geo) + np.abs(J._col))
+        exact = J._D * J._geo + J._T * J._col
+        rnd = jacobian.CACHE_ROUNDING[dt]
+        approx = rnd(J._D) * J._geo + rnd(J._T) * J._col
+        assert np.all(np.abs(approx - exact) <= bound + 1e-300)
+        # the rounded matrix holds exactly these values
+        p = np.random.default_rng(3).normal(size=J.P * J.N)
+        ref = np.zeros(J.n_res)
+        np.add.at(ref, J._rows, approx * p[J._cols])
+        np.testing.assert_allclose(Jr.apply_J(p), ref, rtol=1e-12, atol=1e-15)
+    first = J._T == 1.0
+    assert first.any()
+    for dt in ("bf16", "f16"):
+        assert np.all(jacobian.CACHE_ROUNDING[dt](J._T[first]) == 1.0)
