@@ -293,14 +293,18 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
             const int64_t q0 = pb + s_loc[0], q1 = pb + s_loc[cn];
             const int64_t nwin = (q1 - q0 + kWave - 1) / kWave;
             const int64_t sbase = sb + c0;
+            // window w (empty when past the chunk: a zero T word is no pair)
+            auto ld = [&](PairLoad<DT>& L, int64_t w) {
+                const int64_t q = q0 + w * kWave + lane;
+                L.load(c, q, w < nwin && q < q1);
+            };
             PairLoad<DT> na, nb;
-            auto q_of = [&](int64_t w) { return q0 + w * kWave + lane; };
-            if (wid < nwin) na.load(c, q_of(wid), q_of(wid) < q1);
-            if (wid + NW < nwin) nb.load(c, q_of(wid + NW), q_of(wid + NW) < q1);
+            ld(na, wid);
+            ld(nb, wid + NW);
             for (int64_t win = wid; win < nwin; win += 2 * NW) {
-                PairLoad<DT> Ls[2] = {na, nb};
-                if (win + 2 * NW < nwin) na.load(c, q_of(win + 2 * NW), q_of(win + 2 * NW) < q1);
-                if (win + 3 * NW < nwin) nb.load(c, q_of(win + 3 * NW), q_of(win + 3 * NW) < q1);
+                const PairLoad<DT> Ls[2] = {na, nb};
+                ld(na, win + 2 * NW);
+                ld(nb, win + 3 * NW);
 #pragma unroll
                 for (int h = 0; h < 2; ++h) {
                     const PairLoad<DT>& L = Ls[h];

@@ -105,6 +105,11 @@ __device__ __forceinline__ uint16_t f32_to_bf16_rne(float f) {
 }
 __device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float(((uint32_t)h) << 16); }
 __device__ __forceinline__ uint16_t f32_to_f16_rne(float f) {
+    // The float32 value is rounded again to binary16 (two roundings, like
+    // the other storage types); the empty asm keeps the compiler from
+    // folding a preceding float64 -> float32 conversion into one
+    // float64 -> binary16 rounding.
+    asm volatile("" : "+v"(f));
     _Float16 h = (_Float16)f;   // round-to-nearest-even conversion
     return __builtin_bit_cast(uint16_t, h);
 }
