@@ -37,6 +37,7 @@ namespace {
 constexpr int kThreads = 256;  // threads per tile workgroup (4 wave64)
 constexpr int kChunk = 256;    // segments staged per LDS chunk
 constexpr int kRun = 8;        // pairs per run (segments are padded to runs)
+constexpr int kJWin = 4;       // 64-pair windows a wave of the J half has in flight
 constexpr int MODE_J = 1, MODE_JT = 2, MODE_JTJ = 3;
 
 
@@ -278,7 +279,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
 
     // ---------------- J p ----------------
     // Wave w takes the 64-pair windows w, w + NW, ... of each chunk's pairs,
-    // one pair per lane, two windows per round (the next two prefetched),
+    // one pair per lane, kJWin windows per round (the next kJWin loading),
     // and adds into its private accumulators.  Pixels are
     // distinct within a segment, so the window's segment pieces (contiguous
     // lane ranges) update the accumulators one after another and need no
@@ -298,15 +299,18 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
                 const int64_t q = q0 + w * kWave + lane;
                 L.load(c, q, w < nwin && q < q1);
             };
-            PairLoad<DT> na, nb;
-            ld(na, wid);
-            ld(nb, wid + NW);
-            for (int64_t win = wid; win < nwin; win += 2 * NW) {
-                const PairLoad<DT> Ls[2] = {na, nb};
-                ld(na, win + 2 * NW);
-                ld(nb, win + 3 * NW);
+            PairLoad<DT> nx[kJWin];
 #pragma unroll
-                for (int h = 0; h < 2; ++h) {
+            for (int h = 0; h < kJWin; ++h) ld(nx[h], wid + h * NW);
+            for (int64_t win = wid; win < nwin; win += kJWin * NW) {
+                PairLoad<DT> Ls[kJWin];
+#pragma unroll
+                for (int h = 0; h < kJWin; ++h) {
+                    Ls[h] = nx[h];
+                    ld(nx[h], win + (kJWin + h) * NW);
+                }
+#pragma unroll
+                for (int h = 0; h < kJWin; ++h) {
                     const PairLoad<DT>& L = Ls[h];
                     const int64_t sl = (int64_t)L.seg - sbase;
                     const bool live = L.t != 0 && sl >= 0 && sl < cn;
