@@ -148,11 +148,37 @@ lm_status lm_apply_JT(const lm_cache* cache, const float* u, float* g, void* str
  * LM variant the paper follows); unobserved parameters (M = 0) keep a zero
  * update either way.  Dots, alpha and beta are float64 and stay on the
  * device; the stopping test runs on the device.  stats (host, n_b entries)
- * is filled after one synchronisation at the end. */
+ * is filled after one synchronisation at the end.
+ * Batching: the subsets (at most 8 per call; same N, SH degree and cache
+ * type) share every product launch - the tile pass takes all subsets'
+ * tiles in one grid - and, with graph replay on (lm_pcg_use_graph), one
+ * iteration is captured once and replayed n_iters times. */
 lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b,
                        const float* const* M, float lambda, float diag_floor, int32_t n_iters,
                        double tol, int32_t tol_mode, const float* const* precond_scale,
                        float* const* delta, lm_pcg_stats* stats, void* stream);
+
+/* Tile shape for one image subset, measured: for each candidate shape
+ * (16x16, 32x8, 8x32, 16x8, 8x16, 8x8) the cache is built and two J^T J
+ * products (along b) are timed; the shape with the smallest
+ * build_ms + n_products * apply_ms is returned in tile_w/tile_h.  scores
+ * (host, may be NULL) receives up to max_scores per-candidate timings and
+ * n_scores their count.  Allocates and frees its own device memory and
+ * synchronises the stream. */
+typedef struct lm_tile_score {
+    int32_t tile_w, tile_h;
+    float build_ms, apply_ms;
+} lm_tile_score;
+lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                           int32_t cache_dtype, int32_t n_products, void* stream, int32_t* tile_w,
+                           int32_t* tile_h, lm_tile_score* scores, int32_t max_scores, int32_t* n_scores);
+
+/* Launch mode of the PCG iterations (library-wide): 0 launches every
+ * kernel of every iteration from the host; 1 captures one iteration into a
+ * graph (on a library-owned stream) and replays it on the caller's stream;
+ * 2 (default) uses the graph when a call solves more than one subset.
+ * Results are the same in every mode. */
+lm_status lm_pcg_use_graph(int32_t mode);
 
 /* Weighted mean of subset directions (paper eq. combine-pcg):
  * out = sum_i M_i delta_i / sum_k M_k element-wise; 0 where sum_k M_k = 0.

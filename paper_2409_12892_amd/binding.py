@@ -33,7 +33,7 @@ EXPORTED_SYMBOLS = (
     "lm_last_error", "lm_build_cache", "lm_cache_destroy", "lm_cache_get_info", "lm_jacobi_diag",
     "lm_apply_JtJ", "lm_apply_J", "lm_apply_JT", "lm_pcg_solve", "lm_combine_subsets", "lm_render",
     "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
-    "lm_cache_view_sqnorm",
+    "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile",
 )
 
 
@@ -56,6 +56,10 @@ class LmCacheInfo(ctypes.Structure):
                 ("cache_bytes", c_int64),
                 ("device_bytes", c_int64), ("V", c_int32), ("P", c_int32), ("tile_w", c_int32),
                 ("tile_h", c_int32), ("cache_dtype", c_int32), ("sh_degree", c_int32)]
+
+
+class LmTileScore(ctypes.Structure):
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("build_ms", c_float), ("apply_ms", c_float)]
 
 
 class LmProfileEntry(ctypes.Structure):
@@ -282,6 +286,28 @@ def lm_cache_view_sqnorm(cache: Cache, out=None):
     out = torch.empty(V, device="cuda", dtype=torch.float64) if out is None else out
     _check(load().lm_cache_view_sqnorm(cache.handle, _ptr(out), _stream()), "lm_cache_view_sqnorm")
     return out
+
+
+def lm_autotune_tile(x, sh_degree: int, cams, target, *, cache_dtype: str = "f32", n_products: int = 10):
+    """Measured tile shape for one subset: ((tile_w, tile_h), [per-candidate
+    dicts with build_ms and apply_ms])."""
+    x = _dev_f32(x, "x")
+    target = _dev_f32(target, "target")
+    P, N = x.shape
+    scene = LmScene(N, sh_degree, 0, x.data_ptr())
+    carr = camera_array(cams)
+    tw, th, ns = c_int32(0), c_int32(0), c_int32(0)
+    sc = (LmTileScore * 16)()
+    _check(load().lm_autotune_tile(byref(scene), carr, c_int32(len(carr)), _ptr(target),
+                                   c_int32(CACHE_DTYPES[cache_dtype]), c_int32(n_products), _stream(), byref(tw),
+                                   byref(th), sc, c_int32(16), byref(ns)), "lm_autotune_tile")
+    return (tw.value, th.value), [dict(tile=(sc[i].tile_w, sc[i].tile_h), build_ms=sc[i].build_ms,
+                                       apply_ms=sc[i].apply_ms) for i in range(ns.value)]
+
+
+def lm_pcg_use_graph(mode: int) -> None:
+    """0: eager iterations, 1: graph replay, 2: graph replay for batches (default)."""
+    _check(load().lm_pcg_use_graph(c_int32(mode)), "lm_pcg_use_graph")
 
 
 def lm_profile_enable(on: bool = True) -> None:

@@ -29,6 +29,8 @@
 //        across lanes) leaves one LDS add per segment and wave.
 // The fused J^T J pass keeps u in LDS between the two halves (every pixel's
 // splats live in its own tile), so u never reaches HBM.
+#include <algorithm>
+
 #include "proj_math.h"
 
 namespace lm {
@@ -158,7 +160,8 @@ __global__ void __launch_bounds__(kBlock) k_linearize(CacheView c, const float* 
 
 // ---- tangent: p -> per-(Gaussian, view) power coefficients -------------------
 template <int DEG>
-__global__ void __launch_bounds__(kBlock) k_tangent(ApplyArgs a) {
+__global__ void __launch_bounds__(kBlock) k_tangent(ApplyBatch Bt) {
+    const ApplyArgs& a = Bt.a[blockIdx.y];
     if (a.stop && *a.stop) return;
     constexpr int K = (DEG + 1) * (DEG + 1);
     const CacheView& c = a.c;
@@ -221,7 +224,10 @@ struct PairLoad {
 constexpr float kLog2e = 1.4426950408889634f;
 
 template <int MODE, int DT>
-__global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
+__global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
+    int bi = 0;
+    while (bi + 1 < Bt.n && (int64_t)blockIdx.x >= Bt.tile_off[bi + 1]) ++bi;
+    const ApplyArgs& a = Bt.a[bi];
     if (a.stop && *a.stop) return;
     using S = Store<DT>;
     constexpr int NW = kThreads / kWave;
@@ -235,7 +241,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
     __shared__ float s_mom[9][kChunk];
     __shared__ double s_red[NW];
 
-    const int64_t t = blockIdx.x;
+    const int64_t t = blockIdx.x - Bt.tile_off[bi];
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
     const int v = c.tile_view[t];
     const CamDev& cam = c.cams[v];
@@ -458,11 +464,12 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyArgs a) {
 constexpr uint32_t kNoGv = 0xFFFFFFFFu;
 
 template <int NV>
-__global__ void __launch_bounds__(kBlock) k_gv_reduce(CacheView c, const float* __restrict__ src,
-                                                     float* __restrict__ dst, float* __restrict__ edge,
-                                                     uint32_t* __restrict__ edge_key) {
+__device__ __forceinline__ void gv_reduce_body(const CacheView& c, const float* __restrict__ src,
+                                               float* __restrict__ dst, float* __restrict__ edge,
+                                               uint32_t* __restrict__ edge_key) {
     const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int64_t w = i / kWave;
+    if (w >= (c.n_seg + kWave - 1) / kWave) return;   // whole waves past the list
     const int lane = __lane_id();
     const bool has = i < c.n_seg;
     float v[NV];
@@ -500,9 +507,9 @@ __global__ void __launch_bounds__(kBlock) k_gv_reduce(CacheView c, const float* 
 }
 
 template <int NV>
-__global__ void __launch_bounds__(kBlock) k_gv_reduce_join(CacheView c, int64_t n_waves, const float* __restrict__ edge,
-                                                          const uint32_t* __restrict__ edge_key,
-                                                          float* __restrict__ dst) {
+__device__ __forceinline__ void gv_reduce_join_body(const CacheView& c, const float* __restrict__ edge,
+                                                    const uint32_t* __restrict__ edge_key, float* __restrict__ dst) {
+    const int64_t n_waves = (c.n_seg + kWave - 1) / kWave;
     const int64_t w = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (w >= n_waves) return;
     const uint32_t key = edge_key[w];
@@ -518,6 +525,31 @@ __global__ void __launch_bounds__(kBlock) k_gv_reduce_join(CacheView c, int64_t 
     for (int k = 0; k < NV; ++k) dst[(int64_t)key * NV + k] = acc[k];
 }
 
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gv_reduce(CacheView c, const float* __restrict__ src,
+                                                     float* __restrict__ dst, float* __restrict__ edge,
+                                                     uint32_t* __restrict__ edge_key) {
+    gv_reduce_body<NV>(c, src, dst, edge, edge_key);
+}
+
+template <int NV>
+__global__ void __launch_bounds__(kBlock) k_gv_reduce_join(CacheView c, const float* __restrict__ edge,
+                                                          const uint32_t* __restrict__ edge_key,
+                                                          float* __restrict__ dst) {
+    gv_reduce_join_body<NV>(c, edge, edge_key, dst);
+}
+
+// the moment sums of a batch of subsets (subset = blockIdx.y)
+__global__ void __launch_bounds__(kBlock) k_gv_reduce_moments(ApplyBatch Bt) {
+    const ApplyArgs& a = Bt.a[blockIdx.y];
+    gv_reduce_body<9>(a.c, a.gmom, a.gvsum, a.edge, a.edge_key);
+}
+
+__global__ void __launch_bounds__(kBlock) k_gv_reduce_moments_join(ApplyBatch Bt) {
+    const ApplyArgs& a = Bt.a[blockIdx.y];
+    gv_reduce_join_body<9>(a.c, a.edge, a.edge_key, a.gvsum);
+}
+
 // ---- chain: per-(Gaussian, view) moments -> parameters ---------------------------
 // The adjoint of the tangent map: g_geo = sum_v L_v^T S[0:6] + Jdir_v^T S[6:9],
 // g_sh[k][ch] = sum_v mask_ch Y_k S[6 + ch], with S the (Gaussian, view)'s
@@ -525,10 +557,13 @@ __global__ void __launch_bounds__(kBlock) k_gv_reduce_join(CacheView c, int64_t 
 // Gaussian.  out = scale * J^T u (+ lambda M p); partial dot products
 // p . out per block.
 template <int DEG>
-__global__ void __launch_bounds__(kBlock) k_chain(ApplyArgs a, float scale, float lambda, const float* __restrict__ M,
-                                                 float diag_floor, float* __restrict__ out,
-                                                 double* __restrict__ pg_part) {
+__global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
+    const ApplyArgs& a = Bt.a[blockIdx.y];
     if (a.stop && *a.stop) return;
+    const float scale = Bt.scale, lambda = Bt.lambda, diag_floor = Bt.diag_floor;
+    const float* __restrict__ M = a.M;
+    float* __restrict__ out = a.out;
+    double* __restrict__ pg_part = a.pg_part;
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int P = 11 + 3 * K;
     const CacheView& c = a.c;
@@ -754,22 +789,33 @@ hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipS
     return hipGetLastError();
 }
 
-hipError_t launch_tangent(const ApplyArgs& a, hipStream_t s) {
-    if (a.c.n_gv == 0) return hipSuccess;
-#define LM_T(D) hipLaunchKernelGGL(k_tangent<D>, dim3(grid_for(a.c.n_gv)), dim3(kBlock), 0, s, a)
-    LM_DEG_SWITCH(a.c.deg, LM_T)
+static int64_t batch_max(const ApplyBatch& B, int64_t (*f)(const ApplyArgs&)) {
+    int64_t m = 0;
+    for (int i = 0; i < B.n; ++i) m = std::max(m, f(B.a[i]));
+    return m;
+}
+
+hipError_t launch_tangent(const ApplyBatch& B, hipStream_t s) {
+    const int64_t n = batch_max(B, [](const ApplyArgs& a) { return a.c.n_gv; });
+    if (n == 0) return hipSuccess;
+    const dim3 g(grid_for(n), (unsigned)B.n);
+#define LM_T(D) hipLaunchKernelGGL(k_tangent<D>, g, dim3(kBlock), 0, s, B)
+    LM_DEG_SWITCH(B.a[0].c.deg, LM_T)
 #undef LM_T
     return hipGetLastError();
 }
 
-hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s) {
-    dim3 g((unsigned)a.c.n_tiles), b(kThreads);
-#define LM_APPLY_CASE(MODE, DT) hipLaunchKernelGGL((k_apply_tile<MODE, DT>), g, b, 0, s, a)
-    if (a.c.dtype == LM_CACHE_F32) {
+hipError_t launch_apply_tile(int mode, const ApplyBatch& B, hipStream_t s) {
+    const int64_t nt = B.tile_off[B.n];
+    if (nt == 0) return hipSuccess;
+    dim3 g((unsigned)nt), b(kThreads);
+#define LM_APPLY_CASE(MODE, DT) hipLaunchKernelGGL((k_apply_tile<MODE, DT>), g, b, 0, s, B)
+    const int dtype = B.a[0].c.dtype;
+    if (dtype == LM_CACHE_F32) {
         if (mode == MODE_J) LM_APPLY_CASE(MODE_J, LM_CACHE_F32);
         else if (mode == MODE_JT) LM_APPLY_CASE(MODE_JT, LM_CACHE_F32);
         else LM_APPLY_CASE(MODE_JTJ, LM_CACHE_F32);
-    } else if (a.c.dtype == LM_CACHE_BF16) {
+    } else if (dtype == LM_CACHE_BF16) {
         if (mode == MODE_J) LM_APPLY_CASE(MODE_J, LM_CACHE_BF16);
         else if (mode == MODE_JT) LM_APPLY_CASE(MODE_JT, LM_CACHE_BF16);
         else LM_APPLY_CASE(MODE_JTJ, LM_CACHE_BF16);
@@ -782,12 +828,10 @@ hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
-                        double* pg_part, hipStream_t s) {
-#define LM_C(D)                                                                                                  \
-    hipLaunchKernelGGL(k_chain<D>, dim3(chain_blocks(a.c.N)), dim3(kBlock), 0, s, a, scale, lambda, M, diag_floor, \
-                       out, pg_part)
-    LM_DEG_SWITCH(a.c.deg, LM_C)
+hipError_t launch_chain(const ApplyBatch& B, hipStream_t s) {
+    const dim3 g(chain_blocks(B.a[0].c.N), (unsigned)B.n);
+#define LM_C(D) hipLaunchKernelGGL(k_chain<D>, g, dim3(kBlock), 0, s, B)
+    LM_DEG_SWITCH(B.a[0].c.deg, LM_C)
 #undef LM_C
     return hipGetLastError();
 }
@@ -802,14 +846,18 @@ hipError_t gv_reduce(const CacheView& c, const float* src, float* dst, float* ed
     if (c.n_seg == 0) return hipSuccess;
     const int64_t nw = gv_reduce_waves(c.n_seg);
     hipLaunchKernelGGL(k_gv_reduce<NV>, dim3(grid_for(nw * kWave)), dim3(kBlock), 0, s, c, src, dst, edge, edge_key);
-    hipLaunchKernelGGL(k_gv_reduce_join<NV>, dim3(grid_for(nw)), dim3(kBlock), 0, s, c, nw, edge, edge_key, dst);
+    hipLaunchKernelGGL(k_gv_reduce_join<NV>, dim3(grid_for(nw)), dim3(kBlock), 0, s, c, edge, edge_key, dst);
     return hipGetLastError();
 }
 
-hipError_t launch_gv_reduce_moments(const ApplyArgs& a, hipStream_t s) {
-    return gv_reduce<9>(a.c, a.gmom, a.gvsum, a.edge, a.edge_key, s);
+hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s) {
+    const int64_t ns = batch_max(B, [](const ApplyArgs& a) { return a.c.n_seg; });
+    if (ns == 0) return hipSuccess;
+    const int64_t nw = gv_reduce_waves(ns);
+    hipLaunchKernelGGL(k_gv_reduce_moments, dim3(grid_for(nw * kWave), (unsigned)B.n), dim3(kBlock), 0, s, B);
+    hipLaunchKernelGGL(k_gv_reduce_moments_join, dim3(grid_for(nw), (unsigned)B.n), dim3(kBlock), 0, s, B);
+    return hipGetLastError();
 }
-
 
 hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
                               float* M, hipStream_t s) {

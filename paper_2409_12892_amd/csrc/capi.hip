@@ -21,6 +21,7 @@ struct Rec {
     hipEvent_t a, b;
 };
 static bool g_enabled = false;
+static bool g_capturing = false;   // no event records while a stream is captured
 static std::vector<hipEvent_t> g_pool;
 static size_t g_used = 0;
 static std::vector<Rec> g_recs;
@@ -39,13 +40,13 @@ struct Scope {
     hipStream_t s;
     hipEvent_t a = nullptr;
     Scope(const char* n, hipStream_t st) : name(n), s(st) {
-        if (g_enabled) {
+        if (g_enabled && !g_capturing) {
             a = take();
             if (a) (void)hipEventRecord(a, s);
         }
     }
     ~Scope() {
-        if (g_enabled && a) {
+        if (g_enabled && !g_capturing && a) {
             hipEvent_t b = take();
             if (b) {
                 (void)hipEventRecord(b, s);
@@ -448,25 +449,70 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     return LM_OK;
 }
 
+lm::ApplyBatch batch_of(lm_cache* const* cs, int n) {
+    lm::ApplyBatch B{};
+    B.n = n;
+    B.scale = 1.0f;
+    B.tile_off[0] = 0;
+    for (int i = 0; i < n; ++i) {
+        B.a[i] = cs[i]->apply_args();
+        B.tile_off[i + 1] = B.tile_off[i] + cs[i]->n_tiles;
+    }
+    return B;
+}
+
 lm_status apply_JT_internal(const lm_cache* c, const float* u, float scale, float* g, hipStream_t s) {
-    lm::ApplyArgs a = c->apply_args();
-    a.uin = u;
-    { LM_PROF("apply_tile_JT", s); LM_HIP(lm::launch_apply_tile(2, a, s)); }
-    { LM_PROF("gv_reduce", s); LM_HIP(lm::launch_gv_reduce_moments(a, s)); }
-    { LM_PROF("chain", s); LM_HIP(lm::launch_chain(a, scale, 0.0f, nullptr, 0.0f, g, nullptr, s)); }
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    lm::ApplyBatch B = batch_of(&cm, 1);
+    B.a[0].uin = u;
+    B.a[0].out = g;
+    B.scale = scale;
+    { LM_PROF("apply_tile_JT", s); LM_HIP(lm::launch_apply_tile(2, B, s)); }
+    { LM_PROF("gv_reduce", s); LM_HIP(lm::launch_gv_reduce_moments(B, s)); }
+    { LM_PROF("chain", s); LM_HIP(lm::launch_chain(B, s)); }
+    return LM_OK;
+}
+
+// g_i = J_i^T J_i p_i + lambda M_i p_i for every subset of the batch
+lm_status apply_JtJ_batch(const lm::ApplyBatch& B, hipStream_t s) {
+    { LM_PROF("tangent", s); LM_HIP(lm::launch_tangent(B, s)); }
+    { LM_PROF("apply_tile_JtJ", s); LM_HIP(lm::launch_apply_tile(3, B, s)); }
+    { LM_PROF("gv_reduce", s); LM_HIP(lm::launch_gv_reduce_moments(B, s)); }
+    { LM_PROF("chain", s); LM_HIP(lm::launch_chain(B, s)); }
     return LM_OK;
 }
 
 lm_status apply_JtJ_internal(lm_cache* c, const float* p, float lambda, const float* M, float diag_floor, float* g,
                              double* pg_part, const int32_t* stop, hipStream_t s) {
-    lm::ApplyArgs a = c->apply_args();
-    a.p = p;
-    a.stop = stop;
-    { LM_PROF("tangent", s); LM_HIP(lm::launch_tangent(a, s)); }
-    { LM_PROF("apply_tile_JtJ", s); LM_HIP(lm::launch_apply_tile(3, a, s)); }
-    { LM_PROF("gv_reduce", s); LM_HIP(lm::launch_gv_reduce_moments(a, s)); }
-    { LM_PROF("chain", s); LM_HIP(lm::launch_chain(a, 1.0f, lambda, M, diag_floor, g, pg_part, s)); }
-    return LM_OK;
+    lm::ApplyBatch B = batch_of(&c, 1);
+    B.a[0].p = p;
+    B.a[0].stop = stop;
+    B.a[0].M = M;
+    B.a[0].out = g;
+    B.a[0].pg_part = pg_part;
+    B.lambda = lambda;
+    B.diag_floor = diag_floor;
+    return apply_JtJ_batch(B, s);
+}
+
+// 0: iterations launched one by one; 1: captured once and replayed as a
+// graph; 2 (default): graph replay when a call solves more than one subset
+int g_pcg_graph = 2;
+
+// Non-blocking stream (default priority) that the iteration is captured
+// into; the graph itself is launched on the caller's stream.
+hipError_t capture_stream(hipStream_t* out) {
+    static hipStream_t cs[64] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (!cs[dev]) {
+        e = hipStreamCreateWithFlags(&cs[dev], hipStreamNonBlocking);
+        if (e != hipSuccess) return e;
+    }
+    *out = cs[dev];
+    return hipSuccess;
 }
 
 }  // namespace
@@ -571,11 +617,12 @@ lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const fl
 lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) {
     LM_CHECK(c && p && u, LM_ERR_INVALID_ARG, "lm_apply_J: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
-    lm::ApplyArgs a = c->apply_args();
-    a.p = p;
-    a.uout = u;
-    { LM_PROF("tangent", S(stream)); LM_HIP(lm::launch_tangent(a, S(stream))); }
-    { LM_PROF("apply_tile_J", S(stream)); LM_HIP(lm::launch_apply_tile(1, a, S(stream))); }
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    lm::ApplyBatch B = batch_of(&cm, 1);
+    B.a[0].p = p;
+    B.a[0].uout = u;
+    { LM_PROF("tangent", S(stream)); LM_HIP(lm::launch_tangent(B, S(stream))); }
+    { LM_PROF("apply_tile_J", S(stream)); LM_HIP(lm::launch_apply_tile(1, B, S(stream))); }
     return LM_OK;
 }
 
@@ -589,52 +636,189 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
                        float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
                        const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
     LM_CHECK(caches && b && M && delta && n_b > 0, LM_ERR_INVALID_ARG, "lm_pcg_solve: NULL argument");
+    LM_CHECK(n_b <= lm::kMaxBatch, LM_ERR_INVALID_ARG, "lm_pcg_solve: at most 8 subsets per call");
     LM_CHECK(n_iters >= 0 && n_iters < LM_PCG_MAX_HISTORY, LM_ERR_INVALID_ARG, "n_iters out of range");
     LM_CHECK(tol_mode >= LM_TOL_NONE && tol_mode <= LM_TOL_RELATIVE, LM_ERR_INVALID_ARG, "bad tol_mode");
     LM_CHECK(diag_floor >= 0.0f && lambda >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
     hipStream_t s = S(stream);
     for (int i = 0; i < n_b; ++i) {
-        lm_cache* c = caches[i];
+        const lm_cache* c = caches[i];
         LM_CHECK(c && c->built && b[i] && M[i] && delta[i], LM_ERR_INVALID_ARG, "lm_pcg_solve: bad subset entry");
-        const int64_t n = c->N * (int64_t)c->P;
+        LM_CHECK(c->N == caches[0]->N && c->deg == caches[0]->deg && c->dtype == caches[0]->dtype,
+                 LM_ERR_INVALID_ARG, "lm_pcg_solve: subsets must share N, SH degree and cache type");
+    }
+    const int64_t n = caches[0]->N * (int64_t)caches[0]->P;
+    const int64_t nbc = lm::chain_blocks(caches[0]->N);
+    // workspaces and x0 = M^-1 b
+    for (int i = 0; i < n_b; ++i) {
+        lm_cache* c = caches[i];
         const float* sc = precond_scale ? precond_scale[i] : nullptr;
         LM_HIP(c->pcg_r.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_z.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_p.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_g.ensure(sizeof(float) * n));
-        const int64_t np = lm::pcg_partial_count(n);
-        LM_HIP(c->pcg_part.ensure(sizeof(double) * 3 * np));
+        LM_HIP(c->pcg_part.ensure(sizeof(double) * 3 * lm::pcg_partial_count(n)));
         LM_HIP(c->pcg_state.ensure(sizeof(lm::PcgState)));
-        lm::PcgState* st = c->pcg_state.as<lm::PcgState>();
-        float* x = delta[i];
-        float *r = c->pcg_r.as<float>(), *z = c->pcg_z.as<float>(), *p = c->pcg_p.as<float>(),
-              *g = c->pcg_g.as<float>();
-        double* part = c->pcg_part.as<double>();
-        const int32_t* stop = &st->stop;
-        LM_HIP(lm::pcg_init(n, b[i], M[i], diag_floor, sc, x, s));
-        LM_HIP(hipMemsetAsync(st, 0, sizeof(lm::PcgState), s));
-        lm_status e = apply_JtJ_internal(c, x, lambda, M[i], diag_floor, g, nullptr, nullptr, s);
-        if (e != LM_OK) return e;
-        LM_HIP(lm::pcg_init_r(n, b[i], g, M[i], diag_floor, sc, r, z, p, part, st, s));
-        const int64_t nbc = lm::chain_blocks(c->N);
-        for (int it = 0; it < n_iters; ++it) {
-            e = apply_JtJ_internal(c, p, lambda, M[i], diag_floor, g, c->pg_part.as<double>(), stop, s);
-            if (e != LM_OK) return e;
-            { LM_PROF("pcg_vector", s);
-            LM_HIP(lm::pcg_alpha(c->pg_part.as<double>(), nbc, st, s));
-            LM_HIP(lm::pcg_update(n, st, p, g, M[i], diag_floor, sc, x, r, z, part, tol, tol_mode, s)); }
+        LM_HIP(lm::pcg_init(n, b[i], M[i], diag_floor, sc, delta[i], s));
+        LM_HIP(hipMemsetAsync(c->pcg_state.p, 0, sizeof(lm::PcgState), s));
+    }
+    // r0 = b - A x0 for all subsets in one batched product
+    lm::ApplyBatch B = batch_of(caches, n_b);
+    B.lambda = lambda;
+    B.diag_floor = diag_floor;
+    for (int i = 0; i < n_b; ++i) {
+        B.a[i].p = delta[i];
+        B.a[i].M = M[i];
+        B.a[i].out = caches[i]->pcg_g.as<float>();
+    }
+    lm_status e = apply_JtJ_batch(B, s);
+    if (e != LM_OK) return e;
+    for (int i = 0; i < n_b; ++i) {
+        lm_cache* c = caches[i];
+        const float* sc = precond_scale ? precond_scale[i] : nullptr;
+        LM_HIP(lm::pcg_init_r(n, b[i], c->pcg_g.as<float>(), M[i], diag_floor, sc, c->pcg_r.as<float>(),
+                              c->pcg_z.as<float>(), c->pcg_p.as<float>(), c->pcg_part.as<double>(),
+                              c->pcg_state.as<lm::PcgState>(), s));
+        B.a[i].p = c->pcg_p.as<float>();
+        B.a[i].pg_part = c->pg_part.as<double>();
+        B.a[i].stop = &c->pcg_state.as<lm::PcgState>()->stop;
+    }
+    // one iteration of Algorithm 1 for every subset; the kernels of a subset
+    // whose loop has ended return at once
+    auto body = [&](hipStream_t q) -> lm_status {
+        lm_status st = apply_JtJ_batch(B, q);
+        if (st != LM_OK) return st;
+        LM_PROF("pcg_vector", q);
+        for (int i = 0; i < n_b; ++i) {
+            lm_cache* c = caches[i];
+            const float* sc = precond_scale ? precond_scale[i] : nullptr;
+            lm::PcgState* pst = c->pcg_state.as<lm::PcgState>();
+            LM_HIP(lm::pcg_alpha(c->pg_part.as<double>(), nbc, pst, q));
+            LM_HIP(lm::pcg_update(n, pst, c->pcg_p.as<float>(), c->pcg_g.as<float>(), M[i], diag_floor, sc, delta[i],
+                                  c->pcg_r.as<float>(), c->pcg_z.as<float>(), c->pcg_part.as<double>(), tol, tol_mode,
+                                  q));
         }
-        if (stats) {
-            lm::PcgState hs;
-            LM_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-            LM_HIP(hipStreamSynchronize(s));
-            stats[i].iters = hs.iters;
-            stats[i].status = hs.status;
-            stats[i].b_sqnorm = hs.bb;
-            for (int k = 0; k < LM_PCG_MAX_HISTORY; ++k) stats[i].history[k] = k <= hs.iters ? hs.hist[k] : 0.0;
+        return LM_OK;
+    };
+    const bool use_graph = n_iters >= 2 && (g_pcg_graph == 1 || (g_pcg_graph == 2 && n_b > 1));
+    if (use_graph) {
+        // the iteration is captured once (nothing runs while capturing) and
+        // replayed on the caller's stream: no host launch work per iteration
+        hipStream_t cs = nullptr;
+        LM_HIP(capture_stream(&cs));
+        hipGraph_t graph = nullptr;
+        hipGraphExec_t exec = nullptr;
+        LM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
+        lm::prof::g_capturing = true;
+        lm_status st = body(cs);
+        lm::prof::g_capturing = false;
+        hipError_t ce = hipStreamEndCapture(cs, &graph);
+        if (st != LM_OK) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return st;
+        }
+        LM_HIP(ce);
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (ie != hipSuccess) {
+            (void)hipGraphDestroy(graph);
+            LM_HIP(ie);
+        }
+        hipError_t le = hipSuccess;
+        for (int it = 0; it < n_iters && le == hipSuccess; ++it) {
+            LM_PROF("pcg_iteration_graph", s);
+            le = hipGraphLaunch(exec, s);
+        }
+        (void)hipGraphExecDestroy(exec);
+        (void)hipGraphDestroy(graph);
+        LM_HIP(le);
+    } else {
+        for (int it = 0; it < n_iters; ++it) {
+            e = body(s);
+            if (e != LM_OK) return e;
         }
     }
+    for (int i = 0; i < n_b; ++i) {
+        if (!stats) continue;
+        lm::PcgState hs;
+        LM_HIP(hipMemcpyAsync(&hs, caches[i]->pcg_state.p, sizeof(hs), hipMemcpyDeviceToHost, s));
+        LM_HIP(hipStreamSynchronize(s));
+        stats[i].iters = hs.iters;
+        stats[i].status = hs.status;
+        stats[i].b_sqnorm = hs.bb;
+        for (int k = 0; k < LM_PCG_MAX_HISTORY; ++k) stats[i].history[k] = k <= hs.iters ? hs.hist[k] : 0.0;
+    }
     if (!stats) LM_HIP(hipStreamSynchronize(s));
+    return LM_OK;
+}
+
+lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                           int32_t cache_dtype, int32_t n_products, void* stream, int32_t* tile_w, int32_t* tile_h,
+                           lm_tile_score* scores, int32_t max_scores, int32_t* n_scores) {
+    LM_CHECK(scene && cams && target && tile_w && tile_h, LM_ERR_INVALID_ARG, "lm_autotune_tile: NULL argument");
+    LM_CHECK(n_products >= 0, LM_ERR_INVALID_ARG, "lm_autotune_tile: n_products must be >= 0");
+    static const int32_t cand[][2] = {{16, 16}, {32, 8}, {8, 32}, {16, 8}, {8, 16}, {8, 8}};
+    const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
+    hipStream_t s = S(stream);
+    lm_cache* c = nullptr;
+    float* b = nullptr;
+    float* g = nullptr;
+    hipEvent_t ev[4] = {};
+    for (auto& e : ev) LM_HIP(hipEventCreate(&e));
+    const int64_t n = scene->N * (int64_t)(11 + 3 * (scene->sh_degree + 1) * (scene->sh_degree + 1));
+    lm_status st = LM_OK;
+    hipError_t he = hipMalloc(&b, sizeof(float) * std::max<int64_t>(n, 1));
+    if (he == hipSuccess) he = hipMalloc(&g, sizeof(float) * std::max<int64_t>(n, 1));
+    double best = -1.0;
+    int found = 0;
+    for (int k = 0; k < nc && he == hipSuccess && st == LM_OK; ++k) {
+        lm_options o{cand[k][0], cand[k][1], cache_dtype, 0};
+        he = hipEventRecord(ev[0], s);
+        if (he != hipSuccess) break;
+        st = lm_build_cache(scene, cams, V, target, &o, stream, &c, b, nullptr);
+        if (st != LM_OK) break;
+        he = hipEventRecord(ev[1], s);
+        // one untimed product, then two timed ones, along b = -J^T F
+        if (he == hipSuccess) st = apply_JtJ_internal(c, b, 0.0f, nullptr, 0.0f, g, nullptr, nullptr, s);
+        if (st != LM_OK) break;
+        he = hipEventRecord(ev[2], s);
+        for (int r = 0; r < 2 && st == LM_OK && he == hipSuccess; ++r)
+            st = apply_JtJ_internal(c, b, 0.0f, nullptr, 0.0f, g, nullptr, nullptr, s);
+        if (st != LM_OK) break;
+        if (he == hipSuccess) he = hipEventRecord(ev[3], s);
+        if (he == hipSuccess) he = hipEventSynchronize(ev[3]);
+        float build_ms = 0.0f, apply_ms = 0.0f;
+        if (he == hipSuccess) he = hipEventElapsedTime(&build_ms, ev[0], ev[1]);
+        if (he == hipSuccess) he = hipEventElapsedTime(&apply_ms, ev[2], ev[3]);
+        if (he != hipSuccess) break;
+        apply_ms *= 0.5f;
+        const double score = build_ms + (double)n_products * apply_ms;
+        if (scores && found < max_scores) scores[found] = lm_tile_score{cand[k][0], cand[k][1], build_ms, apply_ms};
+        ++found;
+        if (best < 0.0 || score < best) {
+            best = score;
+            *tile_w = cand[k][0];
+            *tile_h = cand[k][1];
+        }
+    }
+    if (n_scores) *n_scores = std::min(found, max_scores);
+    if (c) {
+        (void)hipDeviceSynchronize();
+        c->release_all();
+        delete c;
+    }
+    if (b) (void)hipFree(b);
+    if (g) (void)hipFree(g);
+    for (auto& e : ev)
+        if (e) (void)hipEventDestroy(e);
+    if (st != LM_OK) return st;
+    LM_HIP(he);
+    LM_CHECK(best >= 0.0, LM_ERR_INVALID_ARG, "lm_autotune_tile: no candidate could be measured");
+    return LM_OK;
+}
+
+lm_status lm_pcg_use_graph(int32_t mode) {
+    LM_CHECK(mode >= 0 && mode <= 2, LM_ERR_INVALID_ARG, "lm_pcg_use_graph: mode must be 0, 1 or 2");
+    g_pcg_graph = mode;
     return LM_OK;
 }
 

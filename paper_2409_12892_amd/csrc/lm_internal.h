@@ -222,7 +222,23 @@ struct ApplyArgs {
     uint32_t* edge_key;      // [waves]
     double* jp_part;         // [n_tiles] ||J p||^2 per tile
     const int32_t* stop;     // optional device flag: skip when non-zero
+    const float* M;          // chain: damping diagonal (or null)
+    float* out;              // chain: [P][N] result
+    double* pg_part;         // chain: per-block p . out partials (or null)
 };
+
+// Product arguments of up to kMaxBatch image subsets of one scene (same
+// N, SH degree and cache type): one launch per kernel covers them all; the
+// tile pass takes the subsets' tiles one after another (tile_off), the
+// other kernels take the subset from blockIdx.y.
+constexpr int kMaxBatch = 8;
+struct ApplyBatch {
+    ApplyArgs a[kMaxBatch];
+    int64_t tile_off[kMaxBatch + 1];
+    int32_t n;
+    float scale, lambda, diag_floor;
+};
+static_assert(sizeof(ApplyBatch) <= 4000, "kernel argument block too large");
 
 // Device-resident PCG scalars of one subset (pcg.hip).
 struct PcgState {
@@ -250,14 +266,13 @@ hipError_t launch_gv_compact(const uint32_t* gv_cnt, const uint64_t* gv_idx, con
                              int V, uint32_t* gv_rec, uint32_t* gv_seg_off, uint32_t* gv_first, hipStream_t s);
 hipError_t launch_gv_sort(const uint32_t* gv_seg_off, int64_t n_gv, uint32_t* gv_segs, hipStream_t s);
 // apply.hip (mode 1 = J, 2 = J^T, 3 = fused J^T J)
-hipError_t launch_tangent(const ApplyArgs& a, hipStream_t s);
-hipError_t launch_apply_tile(int mode, const ApplyArgs& a, hipStream_t s);
-hipError_t launch_chain(const ApplyArgs& a, float scale, float lambda, const float* M, float diag_floor, float* out,
-                        double* pg_part, hipStream_t s);
+hipError_t launch_tangent(const ApplyBatch& B, hipStream_t s);
+hipError_t launch_apply_tile(int mode, const ApplyBatch& B, hipStream_t s);
+hipError_t launch_chain(const ApplyBatch& B, hipStream_t s);
 unsigned chain_blocks(int64_t N);
 hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
                               float* M, hipStream_t s);
-hipError_t launch_gv_reduce_moments(const ApplyArgs& a, hipStream_t s);
+hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s);
 int64_t gv_reduce_waves(int64_t n_seg);
 hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipStream_t s);
 // pcg.hip
