@@ -15,6 +15,8 @@ Contents (each function cites the passage of the paper it follows):
                 diag-jtj)
 * ``solve``     Algorithm 1 (PCG) exactly as printed, dense normal-equation
                 solve, and the subset combination (eq. combine-pcg)
+* ``precond``   per-Gaussian blocks of J^T J, targets and features of the
+                learned diagonal preconditioner, and its reference MLP
 
 Arithmetic is float64 throughout; the only float32 steps are the ones that
 decide integers (tile rectangles and depth-sort keys), taken in the same

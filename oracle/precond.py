@@ -1,0 +1,139 @@
+"""Learned diagonal preconditioner (an extension of the PCG of Algorithm 1;
+the paper itself uses Jacobi, section 3.3): exact per-Gaussian blocks of
+J^T J, the training targets derived from them, scale-free per-Gaussian
+features and the reference MLP, all in float64.
+
+Readings (the paper does not describe a learned preconditioner):
+
+* Block of Gaussian k: B_k = J_k^T J_k over its P parameter columns.  With
+  the damping of the normal equations (eq. norm-eq) and the minimum
+  diagonal of the LM loop, D = max(diag B_k, floor) on observed entries,
+  B~_k = B_k + lambda diag(D) restricted to observed parameters (diag > 0).
+* Target: t_kj = log(D_kj / sum_i |B~_k,ji|) - the diagonal scaling that
+  bounds the Gershgorin discs of the preconditioned damped block (absolute
+  row sums instead of the diagonal alone), relative to Jacobi: t = 0 is
+  plain Jacobi, a diagonal block gives t = -log(1 + lambda).  (The
+  diagonal of the block inverse was tried as a target and preconditions
+  worse than Jacobi on these scenes.)  The preconditioner applied is
+  M^-1 = exp(s) / D with s the (clamped) prediction.
+* Features (8 per Gaussian): log of the mean Jacobi diagonal over the
+  mean, log-scale, quaternion, opacity and SH parameter groups, and
+  log(1 + number of (pixel, splat) pairs of the Gaussian) - each minus its
+  average over the scene's observed Gaussians (a geometric-mean
+  normalisation, so features do not depend on image size or view count) -
+  then the opacity sigmoid(logit) and the mean log-scale.  Unobserved
+  Gaussians get zero features.
+* MLP: 8 -> 64 -> GELU -> 64 -> GELU -> P_out, GELU in its exact erf form;
+  loss: mean squared error over observed (k, j).
+
+TEST INFRASTRUCTURE ONLY (see the package docstring).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import scipy.special
+
+GROUPS = ((0, 3), (3, 6), (6, 10), (10, 11), (11, None))   # mean, log-scale, quaternion, opacity, SH
+N_FEAT = 8
+HIDDEN = 64
+
+
+def gaussian_blocks(J) -> np.ndarray:
+    """B_k = J_k^T J_k for every Gaussian k of an oracle Jacobian: [N, P, P]."""
+    P, N = J.P, J.N
+    Jc = J.J.tocsc()
+    out = np.zeros((N, P, P))
+    for k in range(N):
+        Jk = Jc[:, [j * N + k for j in range(P)]]
+        out[k] = (Jk.T @ Jk).toarray()
+    return out
+
+
+def targets(blocks: np.ndarray, lam: float, diag_floor: float = 0.0):
+    """t [P, N] and the observed mask [P, N] (see the module readings)."""
+    N, P, _ = blocks.shape
+    t = np.zeros((P, N))
+    mask = np.zeros((P, N), bool)
+    for k in range(N):
+        d = np.diag(blocks[k]).copy()
+        obs = d > 0
+        if not obs.any():
+            continue
+        D = np.maximum(d[obs], diag_floor)
+        Bt = blocks[k][np.ix_(obs, obs)] + lam * np.diag(D)
+        t[obs, k] = np.log(D / np.abs(Bt).sum(axis=1))
+        mask[obs, k] = True
+    return t, mask
+
+
+def features(M: np.ndarray, coverage: np.ndarray, x: np.ndarray) -> np.ndarray:
+    """[8, N] features from the Jacobi diagonal M [P, N], the pair count per
+    Gaussian and the parameters x [P, N]."""
+    M = np.asarray(M, np.float64)
+    P, N = M.shape
+    x = np.asarray(x, np.float64)
+    obs = M.sum(axis=0) > 0
+    f = np.zeros((N_FEAT, N))
+    for i, (a, b) in enumerate(GROUPS):
+        b = P if b is None else b
+        with np.errstate(divide="ignore"):
+            f[i] = np.log(M[a:b].mean(axis=0))
+    f[5] = np.log1p(np.asarray(coverage, np.float64))
+    for i in range(6):
+        ok = obs & np.isfinite(f[i])
+        ref = f[i][ok].mean() if ok.any() else 0.0
+        f[i] = np.where(ok, f[i] - ref, 0.0)
+    f[6] = 1.0 / (1.0 + np.exp(-x[10]))
+    f[7] = x[3:6].mean(axis=0)
+    f[:, ~obs] = 0.0
+    return f
+
+
+# ---- MLP ----------------------------------------------------------------------
+
+def gelu(z):
+    return 0.5 * z * (1.0 + scipy.special.erf(z / math.sqrt(2.0)))
+
+
+def gelu_grad(z):
+    return 0.5 * (1.0 + scipy.special.erf(z / math.sqrt(2.0))) + z * np.exp(-0.5 * z * z) / math.sqrt(2.0 * math.pi)
+
+
+def init_params(p_out: int, seed: int = 0) -> dict:
+    rng = np.random.default_rng(seed)
+    return dict(W1=rng.normal(0, 1 / math.sqrt(N_FEAT), (N_FEAT, HIDDEN)), b1=np.zeros(HIDDEN),
+                W2=rng.normal(0, 1 / math.sqrt(HIDDEN), (HIDDEN, HIDDEN)), b2=np.zeros(HIDDEN),
+                W3=rng.normal(0, 0.1 / math.sqrt(HIDDEN), (HIDDEN, p_out)), b3=np.zeros(p_out))
+
+
+def forward(params: dict, f: np.ndarray):
+    """f [8, n] -> s [p_out, n] and the cache of the backward pass."""
+    X = np.asarray(f, np.float64).T
+    z1 = X @ params["W1"] + params["b1"]
+    h1 = gelu(z1)
+    z2 = h1 @ params["W2"] + params["b2"]
+    h2 = gelu(z2)
+    s = h2 @ params["W3"] + params["b3"]
+    return s.T, (X, z1, h1, z2, h2)
+
+
+def loss_and_grad(params: dict, f: np.ndarray, t: np.ndarray, mask: np.ndarray):
+    """Masked mean squared error and its gradient with respect to params."""
+    s, (X, z1, h1, z2, h2) = forward(params, f)
+    m = np.asarray(mask, np.float64)
+    cnt = max(m.sum(), 1.0)
+    r = (s - t) * m
+    loss = float((r * r).sum() / cnt)
+    ds = (2.0 / cnt) * r.T                        # [n, p_out]
+    g = {}
+    g["W3"] = h2.T @ ds
+    g["b3"] = ds.sum(axis=0)
+    dz2 = (ds @ params["W3"].T) * gelu_grad(z2)
+    g["W2"] = h1.T @ dz2
+    g["b2"] = dz2.sum(axis=0)
+    dz1 = (dz2 @ params["W2"].T) * gelu_grad(z1)
+    g["W1"] = X.T @ dz1
+    g["b1"] = dz1.sum(axis=0)
+    return loss, g
