@@ -25,6 +25,8 @@ Readings (the paper does not describe a learned preconditioner):
   Gaussians get zero features.
 * MLP: 8 -> 64 -> GELU -> 64 -> GELU -> P_out, GELU in its exact erf form;
   loss: mean squared error over observed (k, j).
+* Optimiser: Adam (Kingma and Ba, 2015) with bias correction, beta1 0.9,
+  beta2 0.999, eps 1e-8.
 
 TEST INFRASTRUCTURE ONLY (see the package docstring).
 """
@@ -137,3 +139,18 @@ def loss_and_grad(params: dict, f: np.ndarray, t: np.ndarray, mask: np.ndarray):
     g["W1"] = X.T @ dz1
     g["b1"] = dz1.sum(axis=0)
     return loss, g
+
+
+def adam_step(params: dict, grads: dict, m: dict, v: dict, step: int, lr: float,
+              beta1: float = 0.9, beta2: float = 0.999, eps: float = 1e-8) -> dict:
+    """One Adam update (step is 1-based); updates m and v in place and
+    returns the new parameters."""
+    out = {}
+    for k in params:
+        m[k] = beta1 * m[k] + (1.0 - beta1) * grads[k]
+        v[k] = beta2 * v[k] + (1.0 - beta2) * grads[k] ** 2
+        mh = m[k] / (1.0 - beta1 ** step)
+        vh = v[k] / (1.0 - beta2 ** step)
+        out[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)
+    return out
+

@@ -119,3 +119,19 @@ def test_exact_target_preconditioner_beats_jacobi():
     it_t = solve.pcg(J.apply_JtJ, b, M, lam, 200, 1e-2, solve.TOL_RELATIVE, precond_scale=scale,
                      diag_floor=floor)["iters"]
     assert it_t < it_j
+
+
+def test_adam_moves_by_lr_times_sign_under_a_constant_gradient():
+    """With bias correction, a constant gradient g gives m_hat = g and
+    v_hat = g^2 at every step, so each step moves by lr g / (|g| + eps)."""
+    params = {"a": np.array([1.0, -2.0, 0.5, 3.0])}
+    g = {"a": np.array([0.3, -4.0, 1e-3, -2e-2])}
+    m = {"a": np.zeros(4)}
+    v = {"a": np.zeros(4)}
+    lr = 1e-2
+    p = params
+    for step in range(1, 6):
+        new = precond.adam_step(p, g, m, v, step, lr)
+        np.testing.assert_allclose(new["a"] - p["a"], -lr * g["a"] / (np.abs(g["a"]) + 1e-8), rtol=1e-9)
+        p = new
+
