@@ -12,10 +12,18 @@ Readings (the paper does not describe a learned preconditioner):
 * Target: t_kj = log(D_kj / sum_i |B~_k,ji|) - the diagonal scaling that
   bounds the Gershgorin discs of the preconditioned damped block (absolute
   row sums instead of the diagonal alone), relative to Jacobi: t = 0 is
-  plain Jacobi, a diagonal block gives t = -log(1 + lambda).  (The
-  diagonal of the block inverse was tried as a target and preconditions
-  worse than Jacobi on these scenes.)  The preconditioner applied is
-  M^-1 = exp(s) / D with s the (clamped) prediction.
+  plain Jacobi, a diagonal block gives t = -log(1 + lambda).
+* Shrinkage: the training target is t' = mu_j + beta (t - mu_j), with mu_j
+  the mean of t over the scene's observed Gaussians for parameter j and
+  beta = 1/2.  On synthetic SH-3 scenes the unshrunk row-sum scaling cuts
+  PCG iterations by 12-27 % against Jacobi, its per-parameter scene mean
+  alone (beta = 0) by 33-36 %, and beta = 1/2 by 30-39 %; at SH 0 the
+  unshrunk scaling loses to Jacobi and beta = 1/2 still wins.  The full
+  per-Gaussian variation of the Gershgorin bound over-corrects.  (The
+  diagonal of the block inverse, the symmetric row sums, the row 2-norms
+  and the Frobenius-optimal diagonal were tried as targets and do worse.)
+  The preconditioner applied is M^-1 = exp(s) / D with s the (clamped)
+  prediction.
 * Features (8 per Gaussian): log of the mean Jacobi diagonal over the
   mean, log-scale, quaternion, opacity and SH parameter groups, and
   log(1 + number of (pixel, splat) pairs of the Gaussian) - each minus its
@@ -53,7 +61,29 @@ def gaussian_blocks(J) -> np.ndarray:
     return out
 
 
-def targets(blocks: np.ndarray, lam: float, diag_floor: float = 0.0):
+SHRINK = 0.5
+
+
+def shrink_to_mean(t: np.ndarray, mask: np.ndarray, beta: float = SHRINK) -> np.ndarray:
+    """mu_j + beta (t - mu_j) on observed entries (0 elsewhere), mu_j the
+    mean of t[j] over the observed Gaussians (0 if there are none)."""
+    out = np.zeros_like(t, dtype=np.float64)
+    for j in range(t.shape[0]):
+        obs = mask[j]
+        if obs.any():
+            mu = t[j][obs].mean()
+            out[j][obs] = mu + beta * (t[j][obs] - mu)
+    return out
+
+
+def targets(blocks: np.ndarray, lam: float, diag_floor: float = 0.0, beta: float = SHRINK):
+    """Training targets t' [P, N] (row-sum scaling shrunk by beta towards its
+    per-parameter mean) and the observed mask [P, N]."""
+    t, mask = rowsum_scaling(blocks, lam, diag_floor)
+    return shrink_to_mean(t, mask, beta), mask
+
+
+def rowsum_scaling(blocks: np.ndarray, lam: float, diag_floor: float = 0.0):
     """t [P, N] and the observed mask [P, N] (see the module readings)."""
     N, P, _ = blocks.shape
     t = np.zeros((P, N))

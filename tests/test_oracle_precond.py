@@ -44,28 +44,28 @@ def test_mlp_gradient_matches_central_differences():
             assert abs(g[name].reshape(-1)[idx] - fd) <= 1e-7 * max(1.0, abs(fd)), (name, idx)
 
 
-def test_targets_closed_forms():
+def test_rowsum_scaling_closed_forms():
     lam = 0.1
     # diagonal block: row sum = (1 + lam) d_j  ->  t = -log(1 + lam)
     B = np.diag([2.0, 0.5, 3.0])[None]
-    t, m = precond.targets(B, lam)
+    t, m = precond.rowsum_scaling(B, lam)
     np.testing.assert_allclose(t[:, 0], -math.log(1 + lam), rtol=1e-14)
     assert m.all()
     # 2 x 2 block [[a, b], [b, c]]
     a, b, c = 2.0, 0.7, 1.5
-    t, m = precond.targets(np.array([[[a, b], [b, c]]]), lam)
+    t, m = precond.rowsum_scaling(np.array([[[a, b], [b, c]]]), lam)
     ref = [math.log(a / (a * (1 + lam) + b)), math.log(c / (c * (1 + lam) + b))]
     np.testing.assert_allclose(t[:, 0], ref, rtol=1e-13)
     # unobserved parameter: masked out, the rest as if it did not exist
-    t, m = precond.targets(np.array([[[a, 0, b], [0, 0, 0], [b, 0, c]]]), lam)
+    t, m = precond.rowsum_scaling(np.array([[[a, 0, b], [0, 0, 0], [b, 0, c]]]), lam)
     assert list(m[:, 0]) == [True, False, True]
     np.testing.assert_allclose(t[[0, 2], 0], ref, rtol=1e-13)
     # a negative coupling counts by its magnitude
-    t, _ = precond.targets(np.array([[[a, -b], [-b, c]]]), lam)
+    t, _ = precond.rowsum_scaling(np.array([[[a, -b], [-b, c]]]), lam)
     np.testing.assert_allclose(t[:, 0], ref, rtol=1e-13)
     # minimum diagonal: D = max(d, floor) in the damping and the reference
     floor = 1.0
-    t, _ = precond.targets(np.diag([0.25, 4.0])[None], lam, diag_floor=floor)
+    t, _ = precond.rowsum_scaling(np.diag([0.25, 4.0])[None], lam, diag_floor=floor)
     np.testing.assert_allclose(t[:, 0], [math.log(floor / (0.25 + lam * floor)), -math.log(1 + lam)], rtol=1e-14)
 
 
@@ -103,8 +103,8 @@ def test_features_are_scale_free(small):
 
 
 def test_exact_target_preconditioner_beats_jacobi():
-    """On an SH-degree-3 scene the exact row-sum scaling needs fewer PCG
-    iterations than Jacobi to reach a 1e-2 relative residual."""
+    """On an SH-degree-3 scene the exact (shrunk) row-sum scaling needs fewer
+    PCG iterations than Jacobi to reach a 1e-2 relative residual."""
     from oracle import forward
     d = sg.config_scene("tiny", N=300, subsets=[(2, 48, 48)], seed=34, deg=3)
     sc = d["scene"]
@@ -134,4 +134,25 @@ def test_adam_moves_by_lr_times_sign_under_a_constant_gradient():
         new = precond.adam_step(p, g, m, v, step, lr)
         np.testing.assert_allclose(new["a"] - p["a"], -lr * g["a"] / (np.abs(g["a"]) + 1e-8), rtol=1e-9)
         p = new
+
+
+def test_shrinkage_keeps_the_mean_and_scales_the_spread():
+    rng = np.random.default_rng(9)
+    t = rng.normal(size=(4, 50))
+    mask = rng.uniform(size=(4, 50)) > 0.3
+    mask[2] = False
+    for beta in (0.0, 0.5, 1.0):
+        s = precond.shrink_to_mean(t, mask, beta)
+        assert np.all(s[~mask] == 0)
+        for j in (0, 1, 3):
+            o = mask[j]
+            assert abs(s[j][o].mean() - t[j][o].mean()) < 1e-12
+            np.testing.assert_allclose(s[j][o] - s[j][o].mean(), beta * (t[j][o] - t[j][o].mean()), atol=1e-12)
+    np.testing.assert_allclose(precond.shrink_to_mean(t, mask, 1.0)[mask], t[mask], rtol=0, atol=1e-15)
+    # the default target is the row-sum scaling shrunk by one half
+    B = np.stack([np.diag([2.0, 0.5]), np.array([[2.0, 0.7], [0.7, 1.5]])])
+    raw, m = precond.rowsum_scaling(B, 0.1)
+    sh, m2 = precond.targets(B, 0.1)
+    np.testing.assert_array_equal(m, m2)
+    np.testing.assert_allclose(sh, precond.shrink_to_mean(raw, m, 0.5), rtol=1e-15)
 
