@@ -186,6 +186,80 @@ lm_status lm_pcg_use_graph(int32_t mode);
 lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float* const* M,
                              int64_t n, float* out, void* stream);
 
+/* ---- Learned diagonal preconditioner --------------------------------------
+ * An extension of the Jacobi preconditioner of Algorithm 1 (section 3.3):
+ * a perceptron predicts, per parameter, a log-scale s of the Jacobi inverse,
+ * M^-1 = exp(s) / diag(J^T J), passed to lm_pcg_solve as precond_scale.
+ * Training data come from the per-Gaussian blocks of J^T J, which the paper
+ * does not use; they are built from the same per-(Gaussian, view) Gram
+ * values as the Jacobi diagonal (its eq. diag-jtj computes their diagonal).
+ * Calls on one cache must be ordered on one stream (they share its Gram
+ * buffers, computed once per build). */
+
+/* Number of (pixel, splat) pairs of each Gaussian over all views of the
+ * cache, dev float32 [N] (an exact count up to 2^24 per Gaussian). */
+lm_status lm_pair_coverage(const lm_cache* cache, float* coverage, void* stream);
+
+/* Dense blocks B_k = J_k^T J_k (P x P, over the P parameters of Gaussian k)
+ * of the n Gaussians listed in gaussians (dev int64 [n], each in [0, N);
+ * not checked on the device), written to blocks (dev float32 [n][P][P],
+ * row-major, symmetric up to rounding). */
+lm_status lm_block_jacobi(const lm_cache* cache, const int64_t* gaussians, int64_t n, float* blocks,
+                          void* stream);
+
+/* Training targets of the learned preconditioner, dev float32 [P][N] each.
+ * For parameter j of Gaussian k with d = (B_k)_jj > 0 and D = max(d,
+ * diag_floor): r = log(D / (sum_i |(B_k)_ji| + lambda D)), the diagonal
+ * scaling that bounds the Gershgorin discs of the damped block
+ * B_k + lambda diag(D), relative to Jacobi; then t = mu_j + shrink
+ * (r - mu_j) with mu_j the mean of r over the observed Gaussians of
+ * parameter j (shrink in [0, 1]; 1 keeps r, 0.5 is the training target);
+ * mask = 1.  Where d = 0: t = 0, mask = 0.  The means are summed in a fixed
+ * order (deterministic). */
+lm_status lm_precond_targets(const lm_cache* cache, float lambda, float diag_floor, float shrink, float* t,
+                             float* mask, void* stream);
+
+/* Eight features per Gaussian, dev float32 [8][N], from the parameters x
+ * (dev [P][N]) and the Jacobi diagonal M (dev [P][N], from lm_jacobi_diag):
+ * 0-4: log of the mean of M over the mean (3), log-scale (3), quaternion
+ * (4), opacity (1) and SH (P - 11) parameters; 5: log(1 + pair count);
+ * each centred on its mean over the observed Gaussians (sum of M > 0) where
+ * it is finite, else 0; 6: sigmoid of the opacity logit; 7: the mean
+ * log-scale.  Unobserved Gaussians get eight zeros. */
+lm_status lm_precond_features(const lm_cache* cache, const float* x, const float* M, float* feat, void* stream);
+
+/* Weights: dev float32 [LM_MLP_PARAMS]: W1 [8][64] (input-major), b1 [64],
+ * W2 [64][64], b2 [64], W3 [64][64] (columns >= p_out unused), b3 [64].
+ * The products run on bfloat16 copies of the weights and activations with
+ * float32 accumulation. */
+#define LM_MLP_FEATURES 8
+#define LM_MLP_HIDDEN 64
+#define LM_MLP_MAX_OUT 64
+#define LM_MLP_PARAMS 8896
+
+/* s = W3^T gelu(W2^T gelu(W1^T f + b1) + b2) + b3 for n samples (columns
+ * of feat, dev [8][n]); 1 <= p_out <= 64.  s (dev [p_out][n]) and scale =
+ * exp(clamp(s, -4, 4)) (dev [p_out][n]) may each be NULL.  A non-finite s
+ * gives scale 1 (the Jacobi preconditioner) and is counted in n_fallback
+ * (dev uint32, may be NULL; set to the count of this call). */
+lm_status lm_mlp_forward(const float* w, const float* feat, int64_t n, int32_t p_out, float* s, float* scale,
+                         uint32_t* n_fallback, void* stream);
+
+/* Device workspace (bytes) lm_mlp_train_step needs, for any n. */
+size_t lm_mlp_workspace_bytes(void);
+
+/* One training step on the masked mean squared error
+ * L = sum mask (s - target)^2 / sum mask (target, mask dev [p_out][n]):
+ * grad (dev float32 [LM_MLP_PARAMS], may be NULL) and loss (dev double, may
+ * be NULL) are taken at the weights on entry; then, if lr > 0, one Adam
+ * step (beta1 0.9, beta2 0.999, eps 1e-8, bias correction with the 1-based
+ * step) updates w, adam_m and adam_v (dev [LM_MLP_PARAMS]; zero them before
+ * step 1).  The gradient is summed in a fixed order (deterministic).
+ * workspace: dev, at least lm_mlp_workspace_bytes(). */
+lm_status lm_mlp_train_step(float* w, float* adam_m, float* adam_v, int32_t step, float lr, const float* feat,
+                            const float* target, const float* mask, int64_t n, int32_t p_out, float* grad,
+                            double* loss, void* workspace, size_t workspace_bytes, void* stream);
+
 /* Forward render only (eq. alpha-blending), image dev float32 [V][3][H][W]. */
 lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V,
                     const lm_options* opts, float* image, void* stream);

@@ -33,8 +33,14 @@ EXPORTED_SYMBOLS = (
     "lm_last_error", "lm_build_cache", "lm_cache_destroy", "lm_cache_get_info", "lm_jacobi_diag",
     "lm_apply_JtJ", "lm_apply_J", "lm_apply_JT", "lm_pcg_solve", "lm_combine_subsets", "lm_render",
     "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
-    "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile",
+    "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile", "lm_pair_coverage", "lm_block_jacobi",
+    "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
 )
+
+MLP_FEATURES, MLP_HIDDEN, MLP_MAX_OUT, MLP_PARAMS = 8, 64, 64, 8896
+# offsets of the weight layout: W1 [8][64], b1, W2 [64][64], b2, W3 [64][64], b3
+MLP_OFFSETS = dict(W1=(0, (8, 64)), b1=(512, (64,)), W2=(576, (64, 64)), b2=(4672, (64,)),
+                   W3=(4736, (64, 64)), b3=(8832, (64,)))
 
 
 class LmCamera(ctypes.Structure):
@@ -86,8 +92,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     lib = ctypes.CDLL(path)
     lib.lm_last_error.restype = ctypes.c_char_p
     lib.lm_cache_export_size.restype = c_int64
+    lib.lm_mlp_workspace_bytes.restype = ctypes.c_size_t
     for name in EXPORTED_SYMBOLS:
-        if name not in ("lm_last_error", "lm_cache_export_size"):
+        if name not in ("lm_last_error", "lm_cache_export_size", "lm_mlp_workspace_bytes"):
             getattr(lib, name).restype = c_int32
     _lib = lib
     return lib
@@ -334,3 +341,121 @@ def lm_render(x, sh_degree: int, cams, *, tile=(16, 16), out=None):
     _check(load().lm_render(byref(scene), carr, c_int32(len(carr)), byref(opts), _ptr(out), _stream()),
            "lm_render")
     return out
+
+
+# ---- learned preconditioner -----------------------------------------------------
+
+def lm_pair_coverage(cache: Cache, out=None):
+    """Pairs per Gaussian over all views (float32 device tensor [N])."""
+    import torch
+    out = torch.empty(cache.N, device="cuda", dtype=torch.float32) if out is None else out
+    _check(load().lm_pair_coverage(cache.handle, _ptr(out), _stream()), "lm_pair_coverage")
+    return out
+
+
+def lm_block_jacobi(cache: Cache, gaussians):
+    """Dense J^T J blocks [n, P, P] of the listed Gaussians (int64 device tensor)."""
+    import torch
+    idx = gaussians
+    if not (isinstance(idx, torch.Tensor) and idx.is_cuda and idx.dtype == torch.int64 and idx.is_contiguous()):
+        raise TypeError("gaussians must be a contiguous int64 tensor on the GPU")
+    if idx.numel() and (int(idx.min()) < 0 or int(idx.max()) >= cache.N):
+        raise ValueError("gaussian index out of range")
+    out = torch.empty((idx.numel(), cache.P, cache.P), device="cuda", dtype=torch.float32)
+    _check(load().lm_block_jacobi(cache.handle, _ptr(idx), c_int64(idx.numel()), _ptr(out), _stream()),
+           "lm_block_jacobi")
+    return out
+
+
+PRECOND_SHRINK = 0.5
+
+
+def lm_precond_targets(cache: Cache, lam: float, diag_floor: float = 0.0, shrink: float = PRECOND_SHRINK):
+    """(t, mask) float32 device tensors [P, N] (see lm_precond_targets in include/lm3dgs.h)."""
+    import torch
+    t = torch.empty((cache.P, cache.N), device="cuda", dtype=torch.float32)
+    m = torch.empty_like(t)
+    _check(load().lm_precond_targets(cache.handle, c_float(lam), c_float(diag_floor), c_float(shrink), _ptr(t),
+                                     _ptr(m), _stream()), "lm_precond_targets")
+    return t, m
+
+
+def lm_precond_features(cache: Cache, x, M, out=None):
+    """Features [8, N] from the parameters and the Jacobi diagonal."""
+    import torch
+    x = _dev_f32(x, "x")
+    M = _dev_f32(M, "M")
+    out = torch.empty((MLP_FEATURES, cache.N), device="cuda", dtype=torch.float32) if out is None else out
+    _check(load().lm_precond_features(cache.handle, _ptr(x), _ptr(M), _ptr(out), _stream()), "lm_precond_features")
+    return out
+
+
+def mlp_init(p_out: int, seed: int = 0):
+    """Float32 device weights [MLP_PARAMS]: normal W1 (std 1/sqrt(8)), W2 (1/8),
+    W3 (0.1/8, columns >= p_out zero), zero biases."""
+    import torch
+    if not 1 <= p_out <= MLP_MAX_OUT:
+        raise ValueError("p_out must be 1..64")
+    gen = torch.Generator().manual_seed(seed)
+    w = torch.zeros(MLP_PARAMS, dtype=torch.float32)
+    for name, std in (("W1", MLP_FEATURES ** -0.5), ("W2", MLP_HIDDEN ** -0.5), ("W3", 0.1 * MLP_HIDDEN ** -0.5)):
+        off, shape = MLP_OFFSETS[name]
+        v = torch.randn(shape, generator=gen, dtype=torch.float32) * std
+        if name == "W3":
+            v[:, p_out:] = 0
+        w[off:off + v.numel()] = v.reshape(-1)
+    return w.cuda()
+
+
+def mlp_unpack(w) -> dict:
+    """Host float64 views of a weight vector by name (W1 [8, 64], ..., W3 [64, 64])."""
+    a = w.detach().double().cpu().numpy() if hasattr(w, "detach") else np.asarray(w, np.float64)
+    return {k: a[o:o + int(np.prod(sh))].reshape(sh) for k, (o, sh) in MLP_OFFSETS.items()}
+
+
+def lm_mlp_forward(w, feat, p_out: int, want_s: bool = True, want_scale: bool = True):
+    """(s, scale, n_fallback) for the columns of feat [8, n]."""
+    import torch
+    w = _dev_f32(w, "w")
+    feat = _dev_f32(feat, "feat")
+    n = feat.shape[1]
+    s = torch.empty((p_out, n), device="cuda", dtype=torch.float32) if want_s else None
+    sc = torch.empty((p_out, n), device="cuda", dtype=torch.float32) if want_scale else None
+    nf = torch.zeros(1, device="cuda", dtype=torch.int32)
+    _check(load().lm_mlp_forward(_ptr(w), _ptr(feat), c_int64(n), c_int32(p_out), _ptr(s), _ptr(sc), _ptr(nf),
+                                 _stream()), "lm_mlp_forward")
+    return s, sc, nf
+
+
+class MlpTrainer:
+    """Adam state and workspace for lm_mlp_train_step on one weight vector."""
+
+    def __init__(self, w, lr: float = 1e-3):
+        import torch
+        self.w = _dev_f32(w, "w")
+        self.m = torch.zeros_like(self.w)
+        self.v = torch.zeros_like(self.w)
+        self.lr = lr
+        self.step_count = 0
+        nbytes = int(load().lm_mlp_workspace_bytes())
+        self.ws = torch.empty(nbytes, device="cuda", dtype=torch.uint8)
+
+    def step(self, feat, target, mask, lr: float | None = None, want_grad: bool = False):
+        """One Adam step; returns (loss device tensor [1] float64, grad or None),
+        both taken at the weights before the step.  lr = 0 computes them only."""
+        import torch
+        feat = _dev_f32(feat, "feat")
+        target = _dev_f32(target, "target")
+        mask = _dev_f32(mask, "mask")
+        p_out, n = target.shape
+        lr = self.lr if lr is None else lr
+        if lr > 0:
+            self.step_count += 1
+        loss = torch.empty(1, device="cuda", dtype=torch.float64)
+        grad = torch.empty_like(self.w) if want_grad else None
+        _check(load().lm_mlp_train_step(_ptr(self.w), _ptr(self.m), _ptr(self.v), c_int32(max(self.step_count, 1)),
+                                        c_float(lr), _ptr(feat), _ptr(target), _ptr(mask), c_int64(n),
+                                        c_int32(p_out), _ptr(grad), _ptr(loss), _ptr(self.ws),
+                                        ctypes.c_size_t(self.ws.numel()), _stream()), "lm_mlp_train_step")
+        return loss, grad
+

@@ -631,8 +631,9 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
 // (zero when alpha is clamped), e = alpha T and D = dC/dalpha, the pair's
 // Jacobian row block applied to a tangent with power coefficients (a, dc) is
 // D (b . a) + e dc.  Its squared norm summed over pairs needs
-//   Bbb = sum (D.D) b b^T (21), Ebd = sum e b D^T (18), E2 = sum e^2 (1).
-constexpr int kGram = 40;
+//   Bbb = sum (D.D) b b^T (21), Ebd = sum e b D^T (18), E2 = sum e^2 (1),
+// and, for the preconditioner features, the number of pairs (1).
+constexpr int kGram = kGramValues;
 
 __device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i * (i - 1)) / 2 + (k - i); }
 
@@ -689,6 +690,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
                 acc[23 + 3 * i] += eb * D2;
             }
             acc[39] += e * e;
+            acc[40] += live ? 1.0f : 0.0f;
         }
     }
     const uint32_t next = __shfl_down(key, 1, kWave);
@@ -769,6 +771,278 @@ __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float*
 #pragma unroll
     for (int j = 0; j < P; ++j)
         M[(int64_t)j * c.N + g] = j < 11 ? (float)dgeo_acc[j < 11 ? j : 0] : dsh[j >= 11 ? j - 11 : 0];
+}
+
+// Number of (pixel, splat) pairs of each Gaussian over all views.
+__global__ void __launch_bounds__(kBlock) k_coverage(CacheView c, const float* __restrict__ gvgram,
+                                                    float* __restrict__ coverage) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= c.N) return;
+    double pairs = 0.0;
+    for (uint32_t gv = c.gv_first[g]; gv < c.gv_first[g + 1]; ++gv) pairs += (double)gvgram[(int64_t)gv * kGram + 40];
+    coverage[g] = (float)pairs;
+}
+
+
+// Row j of the block B_k = J_k^T J_k of one Gaussian over its P parameters.
+// In the 9 slots of a (Gaussian, view) (six power coefficients, three
+// colours) the unit tangent of parameter j has coefficients co_j, and the
+// slot Gram matrix is G = [[Bbb, Ebd], [Ebd^T, E2 I]], so
+// B_ji = sum over views of co_j^T G co_i.  One thread per (Gaussian, row),
+// rows of a Gaussian adjacent, so the view data is read once per wave.
+// OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P]);
+// OUT = 1 writes the preconditioner target of the row: with d = B_jj,
+// D = max(d, floor) and the damped block B + lambda diag(D), the row-sum
+// scaling t = log(D / (sum_i |B_ji| + lambda D)) and the observed flag d > 0.
+template <int DEG, int OUT>
+__global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float* __restrict__ gvgram,
+                                                      const int64_t* __restrict__ sel, int64_t n_rows, float lam,
+                                                      float floor_, float* __restrict__ o0, float* __restrict__ o1) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int P = 11 + 3 * K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows) return;
+    const int64_t s = t / P;
+    const int j = (int)(t - s * P);
+    const int64_t g = sel ? sel[s] : s;
+    const int64_t ls = c.lin_stride;
+    const bool jgeo = j < 11;
+    const int jg = jgeo ? j : 0;                      // in-range index for the geometric loads
+    const int jk = jgeo ? 0 : (j - 11) / 3, jch = jgeo ? -1 : (j - 11) % 3;
+    float r[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) r[i] = 0.0f;
+    const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
+    for (uint32_t gv = b; gv < e; ++gv) {
+        const float* H = gvgram + (int64_t)gv * kGram;
+        float co[9];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) co[i] = jgeo ? c.lin[(int64_t)(kLinL + 11 * i + jg) * ls + gv] : 0.0f;
+        const float yj = c.lin[(int64_t)(kLinY + jk) * ls + gv];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float jd = j < 3 ? c.lin[(int64_t)(kLinJdir + 3 * ch + jg) * ls + gv] : 0.0f;
+            const float sh = ch == jch ? c.lin[(int64_t)(kLinMask + ch) * ls + gv] * yj : 0.0f;
+            co[6 + ch] = jd + sh;
+        }
+        float w[9];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            float a = 0.0f;
+#pragma unroll
+            for (int k = 0; k < 6; ++k) a += H[k < i ? tri6(k, i) : tri6(i, k)] * co[k];
+            w[i] = a + H[21 + 3 * i] * co[6] + H[22 + 3 * i] * co[7] + H[23 + 3 * i] * co[8];
+        }
+        const float e2 = H[39];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            float a = e2 * co[6 + ch];
+#pragma unroll
+            for (int i = 0; i < 6; ++i) a += H[21 + 3 * i + ch] * co[i];
+            w[6 + ch] = a;
+        }
+#pragma unroll
+        for (int i = 0; i < 11; ++i) {
+            float a = 0.0f;
+#pragma unroll
+            for (int m = 0; m < 6; ++m) a += c.lin[(int64_t)(kLinL + 11 * m + i) * ls + gv] * w[m];
+            if (i < 3) {
+#pragma unroll
+                for (int ch = 0; ch < 3; ++ch) a += c.lin[(int64_t)(kLinJdir + 3 * ch + i) * ls + gv] * w[6 + ch];
+            }
+            r[i] += a;
+        }
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) {
+            const float wc = w[6 + ch] * c.lin[(int64_t)(kLinMask + ch) * ls + gv];
+#pragma unroll
+            for (int k = 0; k < K; ++k) r[11 + 3 * k + ch] += wc * c.lin[(int64_t)(kLinY + k) * ls + gv];
+        }
+    }
+    if (OUT == 0) {
+        float* row = o0 + (s * P + j) * P;
+#pragma unroll
+        for (int i = 0; i < P; ++i) row[i] = r[i];
+    } else {
+        float d = 0.0f, sum = 0.0f;
+#pragma unroll
+        for (int i = 0; i < P; ++i) {
+            d = i == j ? r[i] : d;
+            sum += fabsf(r[i]);
+        }
+        const bool obs = d > 0.0f;
+        const float D = fmaxf(d, floor_);
+        o0[(int64_t)j * c.N + g] = obs ? logf(D / (sum + lam * D)) : 0.0f;
+        o1[(int64_t)j * c.N + g] = obs ? 1.0f : 0.0f;
+    }
+}
+
+// Shrinkage of the targets towards their per-parameter mean over the
+// observed Gaussians: t' = mu_j + beta (t - mu_j).  Block partials over a
+// fixed number of blocks per parameter, summed in order by one workgroup
+// per parameter (deterministic).
+constexpr int kShrinkBlocks = 1024;
+
+__global__ void __launch_bounds__(kBlock) k_target_partials(const float* __restrict__ t, const float* __restrict__ m,
+                                                           int64_t N, double* __restrict__ part) {
+    const int j = blockIdx.y;
+    double a = 0.0, n = 0.0;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < N; g += (int64_t)gridDim.x * kBlock) {
+        const float mk = m[(int64_t)j * N + g];
+        a += mk != 0.0f ? (double)t[(int64_t)j * N + g] : 0.0;
+        n += mk != 0.0f ? 1.0 : 0.0;
+    }
+    __shared__ double sh[2][kBlock / kWave];
+    const int lane = __lane_id(), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int off = kWave / 2; off > 0; off >>= 1) {
+        a += __shfl_xor(a, off, kWave);
+        n += __shfl_xor(n, off, kWave);
+    }
+    if (lane == 0) {
+        sh[0][wid] = a;
+        sh[1][wid] = n;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double sa = 0.0, sn = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            sa += sh[0][w];
+            sn += sh[1][w];
+        }
+        double* o = part + ((int64_t)j * gridDim.x + blockIdx.x) * 2;
+        o[0] = sa;
+        o[1] = sn;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_target_mean(const double* __restrict__ part, int nb,
+                                                       double* __restrict__ mean) {
+    const int j = blockIdx.x;
+    __shared__ double sa[kBlock], sn[kBlock];
+    double a = 0.0, n = 0.0;
+    for (int b = threadIdx.x; b < nb; b += kBlock) {
+        a += part[((int64_t)j * nb + b) * 2];
+        n += part[((int64_t)j * nb + b) * 2 + 1];
+    }
+    sa[threadIdx.x] = a;
+    sn[threadIdx.x] = n;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double ta = 0.0, tn = 0.0;
+        for (int k = 0; k < kBlock; ++k) {
+            ta += sa[k];
+            tn += sn[k];
+        }
+        mean[j] = tn > 0.0 ? ta / tn : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_target_shrink(float* __restrict__ t, const float* __restrict__ m,
+                                                         int64_t N, const double* __restrict__ mean, float beta) {
+    const int j = blockIdx.y;
+    const int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (g >= N) return;
+    const int64_t i = (int64_t)j * N + g;
+    const double mu = mean[j];
+    t[i] = m[i] != 0.0f ? (float)(mu + (double)beta * ((double)t[i] - mu)) : 0.0f;
+}
+
+// ---- preconditioner features ----------------------------------------------
+// Eight per-Gaussian features: the log of the mean Jacobi diagonal over the
+// parameter groups (mean, log-scale, quaternion, opacity, SH) and
+// log(1 + pair count), each centred on its mean over the observed Gaussians
+// (those with a non-zero diagonal) where it is finite; the opacity
+// sigmoid(logit) and the mean log-scale.  Unobserved Gaussians get zeros.
+constexpr int kFeatRef = 6;   // centred features
+
+__device__ __forceinline__ bool feat_observed(const float* M, int64_t N, int P, int64_t g) {
+    float sum = 0.0f;
+    for (int j = 0; j < P; ++j) sum += M[(int64_t)j * N + g];
+    return sum > 0.0f;
+}
+
+__global__ void __launch_bounds__(kBlock) k_feat_raw(const float* __restrict__ M, const float* __restrict__ cov,
+                                                    const float* __restrict__ x, int64_t N, int P,
+                                                    float* __restrict__ feat, double* __restrict__ part) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    double v[2 * kFeatRef];
+#pragma unroll
+    for (int k = 0; k < 2 * kFeatRef; ++k) v[k] = 0.0;
+    if (g < N) {
+        const bool obs = feat_observed(M, N, P, g);
+        const int lo[5] = {0, 3, 6, 10, 11}, hi[5] = {3, 6, 10, 11, P};
+        float f[kFeatRef];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) {
+            float m = 0.0f;
+            for (int j = lo[q]; j < hi[q]; ++j) m += M[(int64_t)j * N + g];
+            f[q] = logf(m / (float)(hi[q] - lo[q]));
+        }
+        f[5] = log1pf(cov[g]);
+#pragma unroll
+        for (int q = 0; q < kFeatRef; ++q) {
+            const bool ok = obs && isfinite(f[q]);
+            feat[(int64_t)q * N + g] = f[q];           // centred (or zeroed) by k_feat_centre
+            v[q] = ok ? (double)f[q] : 0.0;
+            v[kFeatRef + q] = ok ? 1.0 : 0.0;
+        }
+        const float om = x[(int64_t)10 * N + g];
+        feat[(int64_t)6 * N + g] = obs ? 1.0f / (1.0f + expf(-om)) : 0.0f;
+        feat[(int64_t)7 * N + g] =
+            obs ? (x[(int64_t)3 * N + g] + x[(int64_t)4 * N + g] + x[(int64_t)5 * N + g]) / 3.0f : 0.0f;
+    }
+    __shared__ double sh[2 * kFeatRef][kBlock / kWave];
+    const int lane = __lane_id(), wid = threadIdx.x / kWave;
+#pragma unroll
+    for (int k = 0; k < 2 * kFeatRef; ++k) {
+        double a = v[k];
+#pragma unroll
+        for (int off = kWave / 2; off > 0; off >>= 1) a += __shfl_xor(a, off, kWave);
+        if (lane == 0) sh[k][wid] = a;
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * kFeatRef) {
+        double a = 0.0;
+        for (int w = 0; w < kBlock / kWave; ++w) a += sh[threadIdx.x][w];
+        part[(int64_t)blockIdx.x * (2 * kFeatRef) + threadIdx.x] = a;
+    }
+}
+
+// One workgroup: sums the block partials in a fixed order into the centres.
+__global__ void __launch_bounds__(kBlock) k_feat_ref(const double* __restrict__ part, int64_t n_part,
+                                                    double* __restrict__ ref) {
+    __shared__ double sh[2 * kFeatRef][kBlock];
+    double v[2 * kFeatRef];
+#pragma unroll
+    for (int k = 0; k < 2 * kFeatRef; ++k) v[k] = 0.0;
+    for (int64_t b = threadIdx.x; b < n_part; b += kBlock)
+#pragma unroll
+        for (int k = 0; k < 2 * kFeatRef; ++k) v[k] += part[b * (2 * kFeatRef) + k];
+#pragma unroll
+    for (int k = 0; k < 2 * kFeatRef; ++k) sh[k][threadIdx.x] = v[k];
+    __syncthreads();
+    if (threadIdx.x < kFeatRef) {
+        double a = 0.0, n = 0.0;
+        for (int w = 0; w < kBlock; ++w) {
+            a += sh[threadIdx.x][w];
+            n += sh[kFeatRef + threadIdx.x][w];
+        }
+        ref[threadIdx.x] = n > 0.0 ? a / n : 0.0;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_feat_centre(const float* __restrict__ M, int64_t N, int P,
+                                                       const double* __restrict__ ref, float* __restrict__ feat) {
+    const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (g >= N) return;
+    const bool obs = feat_observed(M, N, P, g);
+#pragma unroll
+    for (int q = 0; q < kFeatRef; ++q) {
+        float* f = feat + (int64_t)q * N + g;
+        const float raw = *f;
+        *f = obs && isfinite(raw) ? (float)((double)raw - ref[q]) : 0.0f;
+    }
 }
 
 }  // namespace
@@ -859,8 +1133,47 @@ hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
-                              float* M, hipStream_t s) {
+hipError_t launch_block_rows(const CacheView& c, const float* gvgram, const int64_t* sel, int64_t n_sel, int out,
+                             float lam, float floor_, float* o0, float* o1, hipStream_t s) {
+    const int64_t n_rows = (sel ? n_sel : c.N) * c.P;
+    if (n_rows == 0) return hipSuccess;
+    const dim3 g(grid_for(n_rows)), b(kBlock);
+#define LM_B(D)                                                                                               \
+    if (out == 0) hipLaunchKernelGGL((k_block_rows<D, 0>), g, b, 0, s, c, gvgram, sel, n_rows, lam, floor_, o0, o1); \
+    else hipLaunchKernelGGL((k_block_rows<D, 1>), g, b, 0, s, c, gvgram, sel, n_rows, lam, floor_, o0, o1)
+    LM_DEG_SWITCH(c.deg, LM_B)
+#undef LM_B
+    return hipGetLastError();
+}
+
+int64_t shrink_scratch_doubles(int P) { return (int64_t)P * (2 * kShrinkBlocks + 1); }
+
+hipError_t launch_target_shrink(float* t, const float* mask, int64_t N, int P, float beta, double* scratch,
+                                hipStream_t s) {
+    if (N == 0 || P == 0) return hipSuccess;
+    const int nb = (int)std::min<int64_t>(grid_for(N), kShrinkBlocks);
+    double* mean = scratch + (int64_t)P * 2 * nb;
+    hipLaunchKernelGGL(k_target_partials, dim3(nb, P), dim3(kBlock), 0, s, t, mask, N, scratch);
+    hipLaunchKernelGGL(k_target_mean, dim3(P), dim3(kBlock), 0, s, scratch, nb, mean);
+    hipLaunchKernelGGL(k_target_shrink, dim3(grid_for(N), P), dim3(kBlock), 0, s, t, mask, N, mean, beta);
+    return hipGetLastError();
+}
+
+int64_t feature_parts(int64_t N) { return grid_for(N); }
+
+hipError_t launch_precond_features(const float* M, const float* coverage, const float* x, int64_t N, int P,
+                                   float* feat, double* part, hipStream_t s) {
+    if (N == 0) return hipSuccess;
+    const int64_t nb = feature_parts(N);
+    double* ref = part + nb * (2 * kFeatRef);
+    hipLaunchKernelGGL(k_feat_raw, dim3((unsigned)nb), dim3(kBlock), 0, s, M, coverage, x, N, P, feat, part);
+    hipLaunchKernelGGL(k_feat_ref, dim3(1), dim3(kBlock), 0, s, part, nb, ref);
+    hipLaunchKernelGGL(k_feat_centre, dim3((unsigned)nb), dim3(kBlock), 0, s, M, N, P, ref, feat);
+    return hipGetLastError();
+}
+
+hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
+                       hipStream_t s) {
     dim3 b(kBlock);
     const int64_t n_runs = c.n_pairs / kRun;
     const int64_t ng = (int64_t)kGram * (c.n_seg > 0 ? c.n_seg : 1);
@@ -874,8 +1187,16 @@ hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, fl
         else
             hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram);
     }
-    hipError_t e = gv_reduce<kGram>(c, gram, gvgram, edge, edge_key, s);
-    if (e != hipSuccess) return e;
+    return gv_reduce<kGram>(c, gram, gvgram, edge, edge_key, s);
+}
+
+hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* coverage, hipStream_t s) {
+    hipLaunchKernelGGL(k_coverage, dim3(grid_for(c.N)), dim3(kBlock), 0, s, c, gvgram, coverage);
+    return hipGetLastError();
+}
+
+hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s) {
+    dim3 b(kBlock);
 #define LM_D(D) hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, gvgram, M)
     LM_DEG_SWITCH(c.deg, LM_D)
 #undef LM_D

@@ -115,7 +115,8 @@ struct lm_cache {
     DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs;
     DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
-    DevBuf gvsum, edge_m, ekey_m, gvgram, edge_g, ekey_g;
+    DevBuf gvsum, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
+    bool gram_valid = false;     // gvgram holds the Gram values of the current build
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
 
     const uint32_t* sorted_vals() const { return vals_in_alt ? vals_alt.as<uint32_t>() : vals.as<uint32_t>(); }
@@ -162,7 +163,7 @@ struct lm_cache {
                                &run_seg, &gv_cnt, &gv_flag,
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g,
+                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -177,7 +178,7 @@ struct lm_cache {
                                &run_seg, &gv_cnt, &gv_flag,
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g,
+                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -215,6 +216,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
              "cache_dtype must be LM_CACHE_F32, _BF16 or _F16");
     LM_CHECK(scene->N * (int64_t)V < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY, "N * V must fit in 32 bits");
     c->built = false;
+    c->gram_valid = false;
     c->N = scene->N;
     c->deg = scene->sh_degree;
     c->P = 11 + 3 * (c->deg + 1) * (c->deg + 1);
@@ -587,19 +589,88 @@ lm_status lm_cache_get_info(const lm_cache* c, lm_cache_info* info) {
     return LM_OK;
 }
 
+// The per-(Gaussian, view) Gram values of the current build, computed on
+// first use; every quantity derived from J^T J per Gaussian reads them.
+static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
+    if (cm->gram_valid) return LM_OK;
+    constexpr int64_t kG = lm::kGramValues;
+    const int64_t nseg_a = std::max<int64_t>(cm->n_seg, 1);
+    const int64_t nwav = lm::gv_reduce_waves(nseg_a);
+    LM_HIP(cm->gram.ensure(sizeof(float) * kG * nseg_a));
+    LM_HIP(cm->gvgram.ensure(sizeof(float) * kG * std::max<int64_t>(cm->n_gv, 1)));
+    LM_HIP(cm->edge_g.ensure(sizeof(float) * 2 * kG * nwav));
+    LM_HIP(cm->ekey_g.ensure(sizeof(uint32_t) * nwav));
+    LM_HIP(lm::launch_gram(cm->view(), cm->gram.as<float>(), cm->gvgram.as<float>(), cm->edge_g.as<float>(),
+                           cm->ekey_g.as<uint32_t>(), s));
+    cm->gram_valid = true;
+    return LM_OK;
+}
+
 lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
     LM_CHECK(c && M, LM_ERR_INVALID_ARG, "lm_jacobi_diag: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
-    const int64_t nseg_a = std::max<int64_t>(c->n_seg, 1);
-    const int64_t nwav = lm::gv_reduce_waves(nseg_a);
-    LM_HIP(cm->gram.ensure(sizeof(float) * 40 * nseg_a));
-    LM_HIP(cm->gvgram.ensure(sizeof(float) * 40 * std::max<int64_t>(c->n_gv, 1)));
-    LM_HIP(cm->edge_g.ensure(sizeof(float) * 2 * 40 * nwav));
-    LM_HIP(cm->ekey_g.ensure(sizeof(uint32_t) * nwav));
-    { LM_PROF("jacobi_diag", S(stream));
-    LM_HIP(lm::launch_jacobi_diag(c->view(), cm->gram.as<float>(), cm->gvgram.as<float>(), cm->edge_g.as<float>(),
-                                  cm->ekey_g.as<uint32_t>(), M, S(stream))); }
+    LM_PROF("jacobi_diag", S(stream));
+    lm_status st = ensure_gram(cm, S(stream));
+    if (st != LM_OK) return st;
+    LM_HIP(lm::launch_jacobi_diag(c->view(), cm->gvgram.as<float>(), M, S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_pair_coverage(const lm_cache* c, float* coverage, void* stream) {
+    LM_CHECK(c && coverage, LM_ERR_INVALID_ARG, "lm_pair_coverage: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    lm_status st = ensure_gram(cm, S(stream));
+    if (st != LM_OK) return st;
+    LM_HIP(lm::launch_coverage(c->view(), cm->gvgram.as<float>(), coverage, S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_block_jacobi(const lm_cache* c, const int64_t* gaussians, int64_t n, float* blocks, void* stream) {
+    LM_CHECK(c && (n == 0 || (gaussians && blocks)) && n >= 0, LM_ERR_INVALID_ARG, "lm_block_jacobi: bad argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    if (n == 0) return LM_OK;
+    lm_status st = ensure_gram(cm, S(stream));
+    if (st != LM_OK) return st;
+    LM_HIP(lm::launch_block_rows(c->view(), cm->gvgram.as<float>(), gaussians, n, 0, 0.0f, 0.0f, blocks, nullptr,
+                                 S(stream)));
+    return LM_OK;
+}
+
+lm_status lm_precond_targets(const lm_cache* c, float lambda, float diag_floor, float shrink, float* t, float* mask,
+                             void* stream) {
+    LM_CHECK(c && t && mask, LM_ERR_INVALID_ARG, "lm_precond_targets: NULL argument");
+    LM_CHECK(lambda >= 0.0f && diag_floor >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
+    LM_CHECK(shrink >= 0.0f && shrink <= 1.0f, LM_ERR_INVALID_ARG, "shrink must be in [0, 1]");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    LM_PROF("precond_targets", S(stream));
+    lm_status st = ensure_gram(cm, S(stream));
+    if (st != LM_OK) return st;
+    LM_HIP(lm::launch_block_rows(c->view(), cm->gvgram.as<float>(), nullptr, 0, 1, lambda, diag_floor, t, mask,
+                                 S(stream)));
+    if (shrink != 1.0f) {
+        LM_HIP(cm->tgt_red.ensure(sizeof(double) * lm::shrink_scratch_doubles(c->P)));
+        LM_HIP(lm::launch_target_shrink(t, mask, c->N, c->P, shrink, cm->tgt_red.as<double>(), S(stream)));
+    }
+    return LM_OK;
+}
+
+lm_status lm_precond_features(const lm_cache* c, const float* x, const float* M, float* feat, void* stream) {
+    LM_CHECK(c && x && M && feat, LM_ERR_INVALID_ARG, "lm_precond_features: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    LM_PROF("precond_features", S(stream));
+    lm_status st = ensure_gram(cm, S(stream));
+    if (st != LM_OK) return st;
+    const int64_t N = c->N;
+    LM_HIP(cm->coverage.ensure(sizeof(float) * N));
+    LM_HIP(cm->feat_red.ensure(sizeof(double) * (12 * lm::feature_parts(N) + 6)));
+    LM_HIP(lm::launch_coverage(c->view(), cm->gvgram.as<float>(), cm->coverage.as<float>(), S(stream)));
+    LM_HIP(lm::launch_precond_features(M, cm->coverage.as<float>(), x, N, c->P, feat, cm->feat_red.as<double>(),
+                                       S(stream)));
     return LM_OK;
 }
 
@@ -868,6 +939,43 @@ lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float
     for (int i = 0; i < n_b; ++i) LM_CHECK(delta[i] && M[i], LM_ERR_INVALID_ARG, "lm_combine_subsets: NULL entry");
     if (n == 0) return LM_OK;
     { LM_PROF("combine", S(stream)); LM_HIP(lm::launch_combine(n_b, delta, M, n, out, S(stream))); }
+    return LM_OK;
+}
+
+lm_status lm_mlp_forward(const float* w, const float* feat, int64_t n, int32_t p_out, float* s, float* scale,
+                         uint32_t* n_fallback, void* stream) {
+    LM_CHECK(w && (n == 0 || feat) && n >= 0, LM_ERR_INVALID_ARG, "lm_mlp_forward: bad argument");
+    LM_CHECK(p_out >= 1 && p_out <= LM_MLP_MAX_OUT, LM_ERR_INVALID_ARG, "lm_mlp_forward: p_out must be 1..64");
+    LM_CHECK(n < ((int64_t)1 << 40), LM_ERR_CAPACITY, "lm_mlp_forward: n too large");
+    if (n_fallback) LM_HIP(hipMemsetAsync(n_fallback, 0, sizeof(uint32_t), S(stream)));
+    LM_PROF("mlp_forward", S(stream));
+    LM_HIP(lm::launch_mlp_forward(w, feat, n, p_out, s, scale, n_fallback, S(stream)));
+    return LM_OK;
+}
+
+size_t lm_mlp_workspace_bytes(void) {
+    const size_t parts = (size_t)lm::mlp_grad_parts();
+    return parts * lm::kMlpParams * sizeof(float) + parts * 2 * sizeof(double);
+}
+
+lm_status lm_mlp_train_step(float* w, float* adam_m, float* adam_v, int32_t step, float lr, const float* feat,
+                            const float* target, const float* mask, int64_t n, int32_t p_out, float* grad,
+                            double* loss, void* workspace, size_t workspace_bytes, void* stream) {
+    LM_CHECK(w && (n == 0 || (feat && target && mask)) && n >= 0, LM_ERR_INVALID_ARG,
+             "lm_mlp_train_step: bad argument");
+    LM_CHECK(p_out >= 1 && p_out <= LM_MLP_MAX_OUT, LM_ERR_INVALID_ARG, "lm_mlp_train_step: p_out must be 1..64");
+    LM_CHECK(!(lr > 0.0f) || (adam_m && adam_v && step >= 1), LM_ERR_INVALID_ARG,
+             "lm_mlp_train_step: lr > 0 needs adam_m, adam_v and step >= 1");
+    LM_CHECK(lr >= 0.0f, LM_ERR_INVALID_ARG, "lm_mlp_train_step: lr must be >= 0");
+    LM_CHECK(workspace && workspace_bytes >= lm_mlp_workspace_bytes(), LM_ERR_INVALID_ARG,
+             "lm_mlp_train_step: workspace smaller than lm_mlp_workspace_bytes()");
+    LM_CHECK(n < ((int64_t)1 << 40), LM_ERR_CAPACITY, "lm_mlp_train_step: n too large");
+    const size_t parts = (size_t)lm::mlp_grad_parts();
+    float* gpart = static_cast<float*>(workspace);
+    double* lpart = reinterpret_cast<double*>(gpart + parts * lm::kMlpParams);
+    LM_PROF("mlp_train_step", S(stream));
+    LM_HIP(lm::launch_mlp_grad_step(w, adam_m, adam_v, step, lr, feat, target, mask, n, p_out, grad, loss, gpart,
+                                    lpart, S(stream)));
     return LM_OK;
 }
 

@@ -270,8 +270,31 @@ hipError_t launch_tangent(const ApplyBatch& B, hipStream_t s);
 hipError_t launch_apply_tile(int mode, const ApplyBatch& B, hipStream_t s);
 hipError_t launch_chain(const ApplyBatch& B, hipStream_t s);
 unsigned chain_blocks(int64_t N);
-hipError_t launch_jacobi_diag(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
-                              float* M, hipStream_t s);
+// Per-segment Gram values (41 floats) reduced per (Gaussian, view) into gvgram.
+constexpr int kGramValues = 41;
+hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
+                       hipStream_t s);
+hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s);
+hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* coverage, hipStream_t s);
+// out 0: dense blocks of the selected Gaussians; out 1: targets and mask [P][N]
+hipError_t launch_block_rows(const CacheView& c, const float* gvgram, const int64_t* sel, int64_t n_sel, int out,
+                             float lam, float floor_, float* o0, float* o1, hipStream_t s);
+// t <- mu_j + beta (t - mu_j) on observed entries; scratch: shrink_scratch_doubles(P)
+int64_t shrink_scratch_doubles(int P);
+hipError_t launch_target_shrink(float* t, const float* mask, int64_t N, int P, float beta, double* scratch,
+                                hipStream_t s);
+int64_t feature_parts(int64_t N);   // part holds 12 * feature_parts(N) + 6 doubles
+hipError_t launch_precond_features(const float* M, const float* coverage, const float* x, int64_t N, int P,
+                                   float* feat, double* part, hipStream_t s);
+// mlp.hip
+constexpr int kMlpParams = 8896;   // W1 [8][64], b1, W2 [64][64], b2, W3 [64][64], b3 (float32)
+hipError_t launch_mlp_forward(const float* w, const float* feat, int64_t n, int p_out, float* s_out, float* scale_out,
+                              uint32_t* n_fallback, hipStream_t s);
+// gpart holds mlp_grad_parts() * kMlpParams floats, lpart 2 * mlp_grad_parts() doubles
+hipError_t launch_mlp_grad_step(float* w, float* adam_m, float* adam_v, int step, float lr, const float* feat,
+                                const float* target, const float* mask, int64_t n, int p_out, float* grad_out,
+                                double* loss_out, float* gpart, double* lpart, hipStream_t s);
+int mlp_grad_parts();
 hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s);
 int64_t gv_reduce_waves(int64_t n_seg);
 hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipStream_t s);
