@@ -208,20 +208,83 @@ struct PairLoad {
     W t, d0, d1, d2;
     uint8_t pix;
     uint32_t seg;
-    __device__ __forceinline__ void load(const CacheView& c, int64_t q, bool live) {
-        t = 0; d0 = 0; d1 = 0; d2 = 0; pix = 0; seg = 0xFFFFFFFFu;
-        if (live) {
-            t = ((const W*)c.pT)[q];
-            d0 = ((const W*)c.pD)[q];
-            d1 = ((const W*)c.pD)[c.pair_stride + q];
-            d2 = ((const W*)c.pD)[2 * c.pair_stride + q];
-            pix = c.ppix[q];
-            seg = c.run_seg[q / kRun];
-        }
-    }
 };
 
 constexpr float kLog2e = 1.4426950408889634f;
+
+// Buffer resources over one tile's slots: every plane is addressed by a
+// 32-bit tile-local offset from a base held in scalar registers, and a read
+// past the tile's last slot returns 0 (a zero T word is no pair), so the
+// per-lane loads need neither 64-bit address arithmetic nor a bounds test.
+// A tile holds at most 256 pixels x ~2350 blended splats plus padding, far
+// below the 2 GB range of a resource.
+constexpr int kRsrcWord3 = 0x00020000;
+
+template <int DT>
+struct TilePlanes {
+    using W = typename Store<DT>::word;
+    __amdgpu_buffer_rsrc_t t, d0, d1, d2, pix, seg;
+    __device__ __forceinline__ TilePlanes(const CacheView& c, int64_t pb, int64_t pe) {
+        const int n = (int)(pe - pb);
+        const int nb = n * (int)sizeof(W);
+        const W* pt = (const W*)c.pT + pb;
+        const W* pd = (const W*)c.pD + pb;
+        t = __builtin_amdgcn_make_buffer_rsrc((void*)pt, (short)0, nb, kRsrcWord3);
+        d0 = __builtin_amdgcn_make_buffer_rsrc((void*)pd, (short)0, nb, kRsrcWord3);
+        d1 = __builtin_amdgcn_make_buffer_rsrc((void*)(pd + c.pair_stride), (short)0, nb, kRsrcWord3);
+        d2 = __builtin_amdgcn_make_buffer_rsrc((void*)(pd + 2 * c.pair_stride), (short)0, nb, kRsrcWord3);
+        pix = __builtin_amdgcn_make_buffer_rsrc((void*)(c.ppix + pb), (short)0, n, kRsrcWord3);
+        seg = __builtin_amdgcn_make_buffer_rsrc((void*)(c.run_seg + pb / kRun), (short)0, (n / kRun) * 4,
+                                                kRsrcWord3);
+    }
+    __device__ __forceinline__ W word(__amdgpu_buffer_rsrc_t r, int q) const {
+        if constexpr (sizeof(W) == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, q * 4, 0, 0);
+        else return __builtin_amdgcn_raw_buffer_load_b16(r, q * 2, 0, 0);
+    }
+    // slot q of the tile (the J half: one pair per lane)
+    __device__ __forceinline__ void pair(int q, PairLoad<DT>& L) const {
+        L.t = word(t, q);
+        L.d0 = word(d0, q);
+        L.d1 = word(d1, q);
+        L.d2 = word(d2, q);
+        L.pix = __builtin_amdgcn_raw_buffer_load_b8(pix, q, 0, 0);
+        L.seg = __builtin_amdgcn_raw_buffer_load_b32(seg, (q / kRun) * 4, 0, 0);
+    }
+    // aligned run r of the tile (the J^T half: eight pairs per lane)
+    __device__ __forceinline__ void run(int r, RunLoad<DT>& L) const {
+        L.seg = __builtin_amdgcn_raw_buffer_load_b32(seg, r * 4, 0, 0);
+        if constexpr (sizeof(W) == 4) {
+            const int o = r * kRun * 4;
+            const auto a = __builtin_amdgcn_raw_buffer_load_b128(t, o, 0, 0);
+            const auto b = __builtin_amdgcn_raw_buffer_load_b128(t, o + 16, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { L.t[i] = a[i]; L.t[4 + i] = b[i]; }
+            const __amdgpu_buffer_rsrc_t dr[3] = {d0, d1, d2};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const auto e = __builtin_amdgcn_raw_buffer_load_b128(dr[ch], o, 0, 0);
+                const auto f = __builtin_amdgcn_raw_buffer_load_b128(dr[ch], o + 16, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) { L.d[ch][i] = e[i]; L.d[ch][4 + i] = f[i]; }
+            }
+        } else {
+            const int o = r * kRun * 2;
+            const auto a = __builtin_amdgcn_raw_buffer_load_b128(t, o, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) { L.t[2 * i] = (W)(a[i] & 0xFFFF); L.t[2 * i + 1] = (W)(a[i] >> 16); }
+            const __amdgpu_buffer_rsrc_t dr[3] = {d0, d1, d2};
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch) {
+                const auto e = __builtin_amdgcn_raw_buffer_load_b128(dr[ch], o, 0, 0);
+#pragma unroll
+                for (int i = 0; i < 4; ++i) { L.d[ch][2 * i] = (W)(e[i] & 0xFFFF); L.d[ch][2 * i + 1] = (W)(e[i] >> 16); }
+            }
+        }
+        const auto px = __builtin_amdgcn_raw_buffer_load_b64(pix, r * kRun, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) { L.pix[i] = (px[0] >> (8 * i)) & 0xFF; L.pix[4 + i] = (px[1] >> (8 * i)) & 0xFF; }
+    }
+};
 
 template <int MODE, int DT>
 __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
@@ -234,12 +297,15 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
     constexpr int kZero = kMaxTilePix;           // pixel slot that stays 0 (read by padding)
     const CacheView& c = a.c;
     // s_u[w]: wave w's private accumulators (u0, u1, u2, -) per pixel in the
-    // J half; afterwards s_u[0] holds u, read by the J^T half
+    // J half; afterwards s_u[0] holds u, read by the J^T half, whose segment
+    // moments reuse the other accumulators' storage (LDS stays below a
+    // quarter of the CU's 160 KB: four tile workgroups per CU)
     __shared__ float4 s_u[NW][kMaxTilePix + 1];
     __shared__ float4 s_sg[kChunk][4];   // mx', my', A', B' | C', o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
     __shared__ uint32_t s_loc[kChunk + 1];
-    __shared__ float s_mom[9][kChunk];
     __shared__ double s_red[NW];
+    static_assert(sizeof(float) * 9 * kChunk <= sizeof(float4) * (NW - 1) * (kMaxTilePix + 1), "moments");
+    float (*s_mom)[kChunk] = reinterpret_cast<float (*)[kChunk]>(&s_u[1][0]);
 
     const int64_t t = blockIdx.x - Bt.tile_off[bi];
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
@@ -256,6 +322,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
+    const TilePlanes<DT> P(c, pb, pe);
     for (int i = tid; i < NW * (kMaxTilePix + 1); i += kThreads) (&s_u[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
     __syncthreads();
     if (MODE == MODE_JT && tid < kMaxTilePix && valid)
@@ -297,18 +364,16 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
             __syncthreads();
             stage(c0, cn, true);
             __syncthreads();
-            const int64_t q0 = pb + s_loc[0], q1 = pb + s_loc[cn];
-            const int64_t nwin = (q1 - q0 + kWave - 1) / kWave;
+            const int q0 = (int)s_loc[0], q1 = (int)s_loc[cn];
+            const int nwin = (q1 - q0 + kWave - 1) / kWave;
             const int64_t sbase = sb + c0;
-            // window w (empty when past the chunk: a zero T word is no pair)
-            auto ld = [&](PairLoad<DT>& L, int64_t w) {
-                const int64_t q = q0 + w * kWave + lane;
-                L.load(c, q, w < nwin && q < q1);
-            };
+            // window w; slots past the chunk belong to later segments (not
+            // live) or lie past the tile (read as 0)
+            auto ld = [&](PairLoad<DT>& L, int w) { P.pair(q0 + w * kWave + lane, L); };
             PairLoad<DT> nx[kJWin];
 #pragma unroll
             for (int h = 0; h < kJWin; ++h) ld(nx[h], wid + h * NW);
-            for (int64_t win = wid; win < nwin; win += kJWin * NW) {
+            for (int win = wid; win < nwin; win += kJWin * NW) {
                 PairLoad<DT> Ls[kJWin];
 #pragma unroll
                 for (int h = 0; h < kJWin; ++h) {
@@ -318,8 +383,8 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
 #pragma unroll
                 for (int h = 0; h < kJWin; ++h) {
                     const PairLoad<DT>& L = Ls[h];
-                    const int64_t sl = (int64_t)L.seg - sbase;
-                    const bool live = L.t != 0 && sl >= 0 && sl < cn;
+                    const uint32_t sl = L.seg - (uint32_t)sbase;      // segment ids fit 32 bits
+                    const bool live = L.t != 0 && sl < (uint32_t)cn;
                     const int s = live ? (int)sl : 0;
                     const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
                     const float T = S::dec_T(L.t);
@@ -395,16 +460,16 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
 #pragma unroll
             for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
         __syncthreads();
-        const int64_t r0 = (pb + s_loc[0]) / kRun, r1 = (pb + s_loc[cn]) / kRun;
+        const int r0 = (int)s_loc[0] / kRun, r1 = (int)s_loc[cn] / kRun;   // tile-local runs
         RunLoad<DT> nxt;
-        if (r0 + tid < r1) nxt.load(c, r0 + tid);
+        P.run(r0 + tid, nxt);
         // every lane runs every round (converged for the wave scan); lanes
         // without a run carry zeros under a key of their own
-        for (int64_t base = r0; base < r1; base += kThreads) {
-            const int64_t run = base + tid;
+        for (int base = r0; base < r1; base += kThreads) {
+            const int run = base + tid;
             const bool has = run < r1;
             const RunLoad<DT> L = nxt;
-            if (run + kThreads < r1) nxt.load(c, run + kThreads);
+            P.run(run + kThreads, nxt);
             const int64_t sl = (int64_t)L.seg - (sb + c0);
             const int s = (has && sl >= 0 && sl < cn) ? (int)sl : kChunk;   // kChunk: no run (or an inconsistent cache)
             float m[9];
