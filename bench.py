@@ -171,6 +171,119 @@ def cpu_baseline(scene, cams, n_pairs_per_apply: int, tile: int = 16, crop: int 
                 pairs_per_s=rate, sample_build_s=t_build, sample_apply_ms=t_apply * 1e3)
 
 
+def bench_batching(args, B, sg, torch) -> dict:
+    """The PCG phase of one LM iteration over the four uneven image subsets
+    of the batching workload (1.5M Gaussians, SH 3; 16 x 512x384, 24 x
+    800x600, 32 x 1024x640, 48 x 1280x720): every subset's cache resident
+    (compact builds), the tile shape of each autotuned, then Algorithm 1 with
+    n_iters iterations for all subsets plus eq. combine-pcg, timed once as one
+    batched call replaying a captured iteration and once as four sequential
+    calls launched iteration by iteration."""
+    cfg = dict(sg.CONFIGS["batching"])
+    d = sg.config_scene("batching", N=args.N)
+    scene = d["scene"]
+    dev = torch.device("cuda:0")
+    x = torch.from_numpy(scene.x).to(dev)
+    x_star = torch.from_numpy(d["x_star"]).to(dev)
+    lam, n_iters, floor = float(cfg["lam"]), int(cfg["n_iters"]), 1e-2
+    subs = []
+    for i, cams in enumerate(d["cams"]):
+        V, W, H = cfg["subsets"][i]
+        noise = torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][i]])).to(dev)
+        target = B.lm_render(x_star, scene.sh_degree, cams)
+        target.add_(noise)
+        del noise
+        t0 = time.perf_counter()
+        tile, scores = B.lm_autotune_tile(x, scene.sh_degree, cams, target, cache_dtype=args.cache_dtype,
+                                          n_products=n_iters + 2)
+        t1 = time.perf_counter()
+        cache, b, _ = B.lm_build_cache(x, scene.sh_degree, cams, target, tile=tile, cache_dtype=args.cache_dtype,
+                                       compact=True)
+        M = B.lm_jacobi_diag(cache)
+        torch.cuda.synchronize()
+        t2 = time.perf_counter()
+        del target
+        inf = cache.info()
+        log(f"subset {i}: {V} views {W}x{H}, tile {tile[0]}x{tile[1]} (autotune {t1 - t0:.1f} s), "
+            f"{inf['n_pairs']} pairs, build + diagonal {1e3 * (t2 - t1):.0f} ms")
+        subs.append(dict(cache=cache, b=b, M=M, tile=tile, scores=scores, info=inf, views=(V, W, H)))
+    del x_star
+    caches = [s_["cache"] for s_ in subs]
+    bs, Ms = [s_["b"] for s_ in subs], [s_["M"] for s_ in subs]
+
+    def batched():
+        B.lm_pcg_use_graph(1)
+        deltas, st = B.lm_pcg_solve(caches, bs, Ms, lam, n_iters, diag_floor=floor)
+        return B.lm_combine_subsets(deltas, Ms), deltas, st
+
+    def sequential():
+        B.lm_pcg_use_graph(0)
+        deltas, st = [], []
+        for c_, b_, M_ in zip(caches, bs, Ms):
+            dl, s1 = B.lm_pcg_solve([c_], [b_], [M_], lam, n_iters, diag_floor=floor)
+            deltas += dl
+            st += s1
+        return B.lm_combine_subsets(deltas, Ms), deltas, st
+
+    res = {}
+    for name, fn in (("sequential", sequential), ("batched", batched)):
+        fn()
+        torch.cuda.synchronize()
+        B.lm_profile_read()
+        B.lm_profile_enable(True)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            out, deltas, st = fn()
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        B.lm_profile_enable(False)
+        prof = B.lm_profile_read()
+        res[name] = dict(ms=(t1 - t0) * 1e3 / args.steps, out=out, deltas=deltas, iters=[s_["iters"] for s_ in st],
+                         kernels={k: round(v[1] / args.steps, 3) for k, v in sorted(prof.items())})
+        log(f"{name}: {res[name]['ms']:.1f} ms per PCG phase")
+    B.lm_pcg_use_graph(2)
+    diff = max(float((a_ - b_).norm() / max(b_.norm(), 1e-30))
+               for a_, b_ in zip(res["batched"]["deltas"], res["sequential"]["deltas"]))
+    comb = float((res["batched"]["out"] - res["sequential"]["out"]).norm() / max(res["sequential"]["out"].norm(), 1e-30))
+    pairs = sum(s_["info"]["n_pairs"] for s_ in subs)
+    out = {
+        "metric": "PCG phase ms, 4 uneven subsets: batched with graph replay vs sequential",
+        "value": round(res["batched"]["ms"], 3),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": round(res["batched"]["ms"], 3),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.cache_dtype,
+        "data": "synthetic",
+        "config": {
+            "workload": (f"batching: {scene.N} Gaussians SH{scene.sh_degree}, subsets "
+                         + ", ".join(f"{V}x{W}x{H}" for V, W, H in cfg["subsets"])
+                         + f", {args.cache_dtype} cache, {n_iters} PCG iterations + combine"),
+            "N": scene.N, "subsets": cfg["subsets"], "pcg_iters": n_iters, "lambda": lam, "diag_floor": floor,
+        },
+        "sequential_ms": round(res["sequential"]["ms"], 3),
+        "speedup": round(res["sequential"]["ms"] / res["batched"]["ms"], 3),
+        "rel_diff_batched_vs_sequential": {"deltas_max": diff, "combined": comb},
+        "pcg_iters": res["batched"]["iters"],
+        "subsets": [dict(views=s_["views"], tile=f"{s_['tile'][0]}x{s_['tile'][1]}", n_pairs=s_["info"]["n_pairs"],
+                         n_tiles=s_["info"]["n_tiles"], cache_bytes=s_["info"]["cache_bytes"],
+                         device_bytes=s_["info"]["device_bytes"],
+                         autotune=[dict(tile=f"{c['tile'][0]}x{c['tile'][1]}", build_ms=round(c["build_ms"], 2),
+                                        apply_ms=round(c["apply_ms"], 3)) for c in s_["scores"]])
+                    for s_ in subs],
+        "n_pairs_total": pairs,
+        "device_bytes_total": sum(s_["info"]["device_bytes"] for s_ in subs),
+        "kernels_ms_per_phase": {k: v["kernels"] for k, v in res.items()},
+    }
+    for s_ in subs:
+        s_["cache"].destroy()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -210,6 +323,9 @@ def main() -> int:
         print("bench.py needs a GPU", file=sys.stderr)
         return 3
     B.load()
+    if args.config == "batching":
+        print(json.dumps(bench_batching(args, B, sg, torch)), flush=True)
+        return 0
     tw, th = (int(v) for v in args.tile.split("x"))
     cfg = dict(sg.CONFIGS[args.config])
     subsets = cfg["subsets"][:1]

@@ -81,8 +81,18 @@ typedef struct lm_options {
     int32_t tile_w, tile_h;  /* tile shape in pixels: tile_w a power of two, tile_w*tile_h
                                 <= 256 (0 selects 16)                                     */
     int32_t cache_dtype;     /* LM_CACHE_F32 / _BF16 / _F16 storage of the cache      */
-    int32_t flags;           /* reserved, 0                                            */
+    int32_t flags;           /* 0 or LM_BUILD_COMPACT                                  */
 } lm_options;
+
+/* lm_options.flags: after a successful lm_build_cache, synchronise the stream
+ * and free the buffers only the build uses (projection records, binning keys
+ * and sort buffers, per-pixel counts, residual image), keeping what the
+ * products, the diagonal, PCG and the per-view residual norms read; for
+ * several subsets resident at once.  A later build on the same handle
+ * allocates them again.  lm_cache_export of the pair arrays still works;
+ * of the records, sorted values, tile ranges, image, contribution counts
+ * and residual it returns LM_ERR_INVALID_ARG. */
+#define LM_BUILD_COMPACT 1
 
 typedef struct lm_cache lm_cache;   /* opaque, library-owned */
 
@@ -159,7 +169,8 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
                        float* const* delta, lm_pcg_stats* stats, void* stream);
 
 /* Tile shape for one image subset, measured: for each candidate shape
- * (16x16, 32x8, 8x32, 16x8, 8x16, 8x8) the cache is built and two J^T J
+ * (16x16, 32x8, 8x32, 16x8, 8x16, 8x8) the cache is built twice (the
+ * first build absorbs buffer growth), the second build and two J^T J
  * products (along b) are timed; the shape with the smallest
  * build_ms + n_products * apply_ms is returned in tile_w/tile_h.  scores
  * (host, may be NULL) receives up to max_scores per-candidate timings and

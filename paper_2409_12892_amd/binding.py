@@ -172,8 +172,11 @@ class Cache:
             pass
 
 
+BUILD_COMPACT = 1
+
+
 def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtype: str = "f32",
-                   cache: Cache | None = None, want_b: bool = True, b=None):
+                   cache: Cache | None = None, want_b: bool = True, b=None, compact: bool = False):
     """Build the gradient cache of one subset.  Returns (cache, b, F_sqnorm)
     with b = -J^T F as a [P, N] tensor (written into `b` when given) and
     ||F||^2 as a 1-element float64 tensor (both None when want_b is False)."""
@@ -183,7 +186,7 @@ def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtyp
     target = _dev_f32(target, "target")
     P, N = x.shape
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
-    opts = LmOptions(tile[0], tile[1], CACHE_DTYPES[cache_dtype], 0)
+    opts = LmOptions(tile[0], tile[1], CACHE_DTYPES[cache_dtype], BUILD_COMPACT if compact else 0)
     carr = camera_array(cams)
     cache = Cache() if cache is None else cache
     if want_b and b is None:

@@ -117,6 +117,7 @@ struct lm_cache {
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
     DevBuf gvsum, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
     bool gram_valid = false;     // gvgram holds the Gram values of the current build
+    bool compact = false;        // the build-only buffers were released (LM_BUILD_COMPACT)
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
 
     const uint32_t* sorted_vals() const { return vals_in_alt ? vals_alt.as<uint32_t>() : vals.as<uint32_t>(); }
@@ -170,6 +171,16 @@ struct lm_cache {
         return s;
     }
 
+    // buffers read only while building (see LM_BUILD_COMPACT)
+    void release_build_buffers() {
+        DevBuf* build[] = {&x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &vals_alt, &sort_tmp,
+                           &scan_tmp, &rkeys, &rvals, &rkeys_alt, &rvals_alt, &cnt_sorted, &tile_start, &entry_cnt,
+                           &pixC, &ncontrib, &resid, &tile_pairs, &tile_segs, &tile_real, &tile_real_off, &gv_cnt,
+                           &gv_flag, &gv_idx, &gv_segoff, &gv_cursor};
+        for (auto* b : build) b->release();
+        compact = true;
+    }
+
     void release_all() {
         DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
                                &rkeys_alt, &rvals_alt, &cnt_sorted,
@@ -214,9 +225,12 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_CHECK((TW & (TW - 1)) == 0, LM_ERR_INVALID_ARG, "tile_w must be a power of two");
     LM_CHECK(dtype == LM_CACHE_F32 || dtype == LM_CACHE_BF16 || dtype == LM_CACHE_F16, LM_ERR_INVALID_ARG,
              "cache_dtype must be LM_CACHE_F32, _BF16 or _F16");
-    LM_CHECK(scene->N * (int64_t)V < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY, "N * V must fit in 32 bits");
+    // record ids are 32-bit, and one-thread-per-record launches must stay
+    // below 2^32 work-items after rounding up to whole workgroups
+    LM_CHECK(scene->N * (int64_t)V < ((int64_t)1 << 32) - 65536, LM_ERR_CAPACITY, "N * V must fit in 32 bits");
     c->built = false;
     c->gram_valid = false;
+    c->compact = false;
     c->N = scene->N;
     c->deg = scene->sh_degree;
     c->P = 11 + 3 * (c->deg + 1) * (c->deg + 1);
@@ -379,7 +393,7 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     c->n_pairs = (int64_t)host3[3];
     c->n_seg = (int64_t)host3[1];
     c->n_gv = (int64_t)host3[2];
-    LM_CHECK(c->n_seg < (int64_t)0xFFFFFFFFu && c->n_gv < (int64_t)0xFFFFFFFFu, LM_ERR_CAPACITY,
+    LM_CHECK(c->n_seg < ((int64_t)1 << 32) - 65536 && c->n_gv < ((int64_t)1 << 32) - 65536, LM_ERR_CAPACITY,
              "segment or (Gaussian, view) count exceeds 32 bits");
     const int64_t nseg_a = std::max<int64_t>(c->n_seg, 1), ngv_a = std::max<int64_t>(c->n_gv, 1);
     LM_HIP(c->gv_rec.ensure(sizeof(uint32_t) * ngv_a));
@@ -546,6 +560,15 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         }
     }
     if (st == LM_OK && b) st = apply_JT_internal(c, c->resid.as<float>(), -1.0f, b, s);
+    if (st == LM_OK && opts && (opts->flags & LM_BUILD_COMPACT)) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            lm::set_error(std::string("lm_build_cache: ") + hipGetErrorString(e));
+            st = LM_ERR_HIP;
+        } else {
+            c->release_build_buffers();
+        }
+    }
     if (st != LM_OK) {
         if (created) {
             c->release_all();
@@ -843,6 +866,10 @@ lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t
     int found = 0;
     for (int k = 0; k < nc && he == hipSuccess && st == LM_OK; ++k) {
         lm_options o{cand[k][0], cand[k][1], cache_dtype, 0};
+        // an untimed build first: buffer growth (device allocation) is not
+        // part of the shape's cost
+        st = lm_build_cache(scene, cams, V, target, &o, stream, &c, b, nullptr);
+        if (st != LM_OK) break;
         he = hipEventRecord(ev[0], s);
         if (he != hipSuccess) break;
         st = lm_build_cache(scene, cams, V, target, &o, stream, &c, b, nullptr);
@@ -1125,6 +1152,11 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
     LM_CHECK(bytes == need, LM_ERR_INVALID_ARG, "lm_cache_export: size mismatch");
     hipStream_t s = S(stream);
     const int64_t R = c->N * (int64_t)c->V;
+    const bool build_only = what == LM_EXPORT_RECORDS_F32 || what == LM_EXPORT_SORTED_VALUES ||
+                            what == LM_EXPORT_TILE_RANGES || what == LM_EXPORT_IMAGE ||
+                            what == LM_EXPORT_NCONTRIB || what == LM_EXPORT_RESIDUAL;
+    LM_CHECK(!(c->compact && build_only), LM_ERR_INVALID_ARG,
+             "lm_cache_export: the build buffers of this cache were released (LM_BUILD_COMPACT)");
     switch (what) {
         case LM_EXPORT_RECORDS_F32: {
             std::vector<float> rf;

@@ -91,6 +91,9 @@ void set_error(const std::string& msg);
         }                                                                              \
     } while (0)
 
+// Blocks of one thread per element.  A launch's work-item count is a 32-bit
+// number: kernels whose element count can reach 2^32 (the tile keys of a
+// large subset) loop grid-stride over a capped grid instead.
 inline unsigned grid_for(int64_t n, int block = kBlock) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : g);

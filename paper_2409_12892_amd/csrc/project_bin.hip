@@ -102,15 +102,17 @@ __global__ void k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int64_t R
 }
 
 // tile_start[t] = first key index of tile t (lists are [tile_start[t], tile_start[t+1])).
+// Grid-stride over the keys: a launch's work-item count is a 32-bit number,
+// and the key count of a large subset exceeds it.
 __global__ void k_tile_ranges(const uint32_t* __restrict__ keys, int64_t K, int64_t n_tiles,
                               int64_t* __restrict__ tile_start) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= K) return;
-    const int64_t t = (int64_t)keys[i];
-    const int64_t tp = i == 0 ? -1 : (int64_t)keys[i - 1];
-    for (int64_t u = tp + 1; u <= t; ++u) tile_start[u] = i;
-    if (i == K - 1)
-        for (int64_t u = t + 1; u <= n_tiles; ++u) tile_start[u] = K;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < K; i += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t t = (int64_t)keys[i];
+        const int64_t tp = i == 0 ? -1 : (int64_t)keys[i - 1];
+        for (int64_t u = tp + 1; u <= t; ++u) tile_start[u] = i;
+        if (i == K - 1)
+            for (int64_t u = t + 1; u <= n_tiles; ++u) tile_start[u] = K;
+    }
 }
 
 __global__ void k_fill_i64(int64_t* p, int64_t n, int64_t v) {
@@ -163,7 +165,8 @@ hipError_t launch_tile_ranges(const uint32_t* keys, int64_t K, int64_t n_tiles, 
         hipLaunchKernelGGL(k_fill_i64, dim3(grid_for(n_tiles + 1)), dim3(kBlock), 0, s, tile_start, n_tiles + 1,
                            (int64_t)0);
     } else {
-        hipLaunchKernelGGL(k_tile_ranges, dim3(grid_for(K)), dim3(kBlock), 0, s, keys, K, n_tiles, tile_start);
+        const unsigned grid = std::min<unsigned>(grid_for(K), 1u << 20);
+        hipLaunchKernelGGL(k_tile_ranges, dim3(grid), dim3(kBlock), 0, s, keys, K, n_tiles, tile_start);
     }
     return hipGetLastError();
 }

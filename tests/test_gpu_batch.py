@@ -30,7 +30,11 @@ def batch():
         J = jacobian.Jacobian(sc.x, cams, sc.sh_degree)
         cache, b, fsq = B.lm_build_cache(x, sc.sh_degree, cams, torch.from_numpy(target.ravel()).cuda())
         M = B.lm_jacobi_diag(cache)
-        subs.append(dict(J=J, target=target, cache=cache, b=b, M=M))
+        # the oracle's own right-hand side, diagonal and Algorithm 1 on this subset
+        b_o, M_o = J.b(list(target)), J.diag_JtJ()
+        out = solve.pcg(J.apply_JtJ, b_o, M_o, 1e-2, 8, diag_floor=1e-2)
+        bar = pcg_direction_bar(J, b_o, M_o, 1e-2, 8, diag_floor=1e-2)
+        subs.append(dict(J=J, target=target, cache=cache, b=b, M=M, M_o=M_o, out=out, bar=bar))
     yield dict(B=B, scene=sc, subs=subs)
     for s_ in subs:
         s_["cache"].destroy()
@@ -49,11 +53,7 @@ def _solve(batch, mode, iters=8, lam=1e-2, floor=1e-2):
 def test_batched_directions_match_oracle(batch, report):
     deltas, stats = _solve(batch, 1)
     for i, (s_, d) in enumerate(zip(batch["subs"], deltas)):
-        J = s_["J"]
-        b = s_["b"].cpu().numpy().ravel().astype(np.float64)
-        M = s_["M"].cpu().numpy().ravel().astype(np.float64)
-        out = solve.pcg(J.apply_JtJ, b, M, 1e-2, 8, diag_floor=1e-2)
-        bar = pcg_direction_bar(J, b, M, 1e-2, 8, diag_floor=1e-2)
+        out, bar = s_["out"], s_["bar"]
         report[("batch_pcg", i)] = dict(err=rel(d, out["x"]), bar=bar)
         assert rel(d, out["x"]) < bar, i
         np.testing.assert_allclose(stats[i]["history"], out["history"], rtol=1e-3)
@@ -74,13 +74,15 @@ def test_graph_replay_matches_eager_and_repeats(batch):
 
 
 def test_combine_matches_oracle(batch):
+    """eq. combine-pcg of the batch's directions against the oracle's combination
+    of its own directions and diagonals, within the largest direction bar."""
     B = batch["B"]
     deltas, _ = _solve(batch, 2)
     dt = [torch.from_numpy(d_.reshape(batch["scene"].P, -1)).cuda() for d_ in deltas]
     Ms = [s_["M"] for s_ in batch["subs"]]
     out = B.lm_combine_subsets(dt, Ms).cpu().numpy().ravel()
-    ref = solve.combine_subsets(deltas, [m.cpu().numpy().ravel() for m in Ms])
-    np.testing.assert_allclose(out, ref, rtol=1e-6, atol=1e-30)
+    ref = solve.combine_subsets([s_["out"]["x"] for s_ in batch["subs"]], [s_["M_o"] for s_ in batch["subs"]])
+    assert rel(out, ref) < max(s_["bar"] for s_ in batch["subs"])
 
 
 def test_autotune_returns_a_measured_candidate():

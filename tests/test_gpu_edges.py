@@ -122,3 +122,33 @@ def test_invalid_options_are_rejected():
         B.lm_build_cache(x, 0, d["cams"][0], tgt, tile=(32, 16))
     with pytest.raises(RuntimeError, match="sh_degree"):
         B.lm_build_cache(x, 4, d["cams"][0], tgt)
+
+
+def test_compact_build_keeps_the_products_and_refuses_build_exports():
+    """LM_BUILD_COMPACT frees the build-only buffers: products, diagonal and
+    per-view residuals are bit-identical to those of a full build, the pair
+    arrays still export, the residual image does not, and a rebuild on the
+    compacted handle works."""
+    from paper_2409_12892_amd import binding as B
+    d = sg.config_scene("tiny", N=700, subsets=[(3, 64, 48)], seed=23, deg=1)
+    sc, cams = d["scene"], d["cams"][0]
+    imgs = forward.render_images(d["x_star"], cams, sc.sh_degree)
+    tgt = torch.from_numpy(np.stack([(im + nz).astype(np.float32) for im, nz in zip(imgs, d["noise"][0])]).ravel()).cuda()
+    x = torch.from_numpy(sc.x).cuda()
+    full, b1, f1 = B.lm_build_cache(x, sc.sh_degree, cams, tgt)
+    comp, b2, f2 = B.lm_build_cache(x, sc.sh_degree, cams, tgt, compact=True)
+    assert torch.equal(b1, b2) and torch.equal(f1, f2)
+    assert comp.info()["device_bytes"] < full.info()["device_bytes"]
+    p = torch.from_numpy(random_direction(sc.P, sc.N, seed=5)).cuda()
+    M1, M2 = B.lm_jacobi_diag(full), B.lm_jacobi_diag(comp)
+    assert torch.equal(M1, M2)
+    assert torch.equal(B.lm_apply_JtJ(full, p, 1e-2, M1), B.lm_apply_JtJ(comp, p, 1e-2, M2))
+    assert torch.equal(B.lm_cache_view_sqnorm(full), B.lm_cache_view_sqnorm(comp))
+    np.testing.assert_array_equal(full.export("pair_T"), comp.export("pair_T"))
+    with pytest.raises(RuntimeError):
+        comp.export("residual")
+    comp2, b3, _ = B.lm_build_cache(x, sc.sh_degree, cams, tgt, cache=comp)
+    assert torch.equal(b3, b1)
+    assert comp2.export("residual").size == 3 * 3 * 64 * 48
+    full.destroy()
+    comp2.destroy()
