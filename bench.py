@@ -284,6 +284,114 @@ def bench_batching(args, B, sg, torch) -> dict:
     return out
 
 
+def bench_learned(args, B, sg, torch) -> dict:
+    """The learned diagonal preconditioner at the learned-preconditioner
+    workload, one subset at full size (3M Gaussians, SH 3, 40 views
+    1280x720, bfloat16 cache; the workload's four subsets would not leave
+    room for the build transients).  The perceptron is trained on the GPU on
+    a separate scene of the same generator (other seed, 300k Gaussians, 8
+    views 1280x720); then, on the workload subset, Algorithm 1 runs to a
+    relative residual of 1e-2 with the Jacobi, the learned and the exact-target
+    scaling."""
+    cfg = dict(sg.CONFIGS["learned"])
+    lam, floor, tol, max_it = float(cfg["lam"]), 1e-2, 1e-2, 200
+    dev = torch.device("cuda:0")
+
+    def subset(N, views, seed):
+        d = sg.config_scene("learned", N=N, subsets=[views], seed=seed)
+        sc, cams = d["scene"], d["cams"][0]
+        x = torch.from_numpy(sc.x).to(dev)
+        noise = torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev)
+        target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
+        target.add_(noise)
+        del noise
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        cache, b, _ = B.lm_build_cache(x, sc.sh_degree, cams, target, cache_dtype=args.cache_dtype, compact=True)
+        M = B.lm_jacobi_diag(cache)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        del target
+        return dict(scene=sc, x=x, cache=cache, b=b, M=M, build_ms=(t1 - t0) * 1e3)
+
+    log("training scene: 300000 Gaussians, 8 views 1280x720")
+    tr = subset(300_000, (8, 1280, 720), int(cfg["seed"]) + 100)
+    feat = B.lm_precond_features(tr["cache"], tr["x"], tr["M"])
+    t, mask = B.lm_precond_targets(tr["cache"], lam, floor)
+    P = t.shape[0]
+    trainer = B.MlpTrainer(B.mlp_init(P, seed=3), lr=3e-3)
+    loss0, _ = trainer.step(feat, t, mask, lr=0.0)
+    n_steps = 300
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        trainer.step(feat, t, mask)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3 / n_steps
+    loss1, _ = trainer.step(feat, t, mask, lr=0.0)
+    log(f"training: loss {loss0.item():.4f} -> {loss1.item():.4f}, {train_ms:.3f} ms per Adam step "
+        f"({feat.shape[1]} samples)")
+    tr["cache"].destroy()
+    del tr, feat, t, mask
+    torch.cuda.empty_cache()
+
+    V, W, H = cfg["subsets"][0]
+    log(f"workload subset: {cfg['N']} Gaussians, {V} views {W}x{H}")
+    ws = subset(int(cfg["N"]), (V, W, H), int(cfg["seed"]))
+    info = ws["cache"].info()
+    log(f"built: {info['n_pairs']} pairs, {ws['build_ms']:.0f} ms with the diagonal")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        f = B.lm_precond_features(ws["cache"], ws["x"], ws["M"])
+        _, scale, nf = B.lm_mlp_forward(trainer.w, f, P, want_s=False)
+    torch.cuda.synchronize()
+    pre_ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    tt, mm = B.lm_precond_targets(ws["cache"], lam, floor)
+    exact = torch.where(mm > 0, torch.exp(tt), torch.ones_like(tt))
+    del tt, mm
+    res = {}
+    for name, sc_ in (("jacobi", None), ("learned", scale), ("exact_target", exact)):
+        B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE,
+                       scales=None if sc_ is None else [sc_], diag_floor=floor)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, st = B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE,
+                               scales=None if sc_ is None else [sc_], diag_floor=floor)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        res[name] = dict(iters=int(st[0]["iters"]), ms=round(ms, 2),
+                         rel_res=float(np.sqrt(st[0]["history"][-1])))
+        log(f"{name}: {res[name]['iters']} iterations, {ms:.1f} ms")
+    ws["cache"].destroy()
+    j, l_ = res["jacobi"], res["learned"]
+    return {
+        "metric": "PCG to relative residual 1e-2: ms (iterations), learned vs Jacobi preconditioner",
+        "value": round(l_["ms"] + pre_ms, 2),
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": 1,
+        "ms_per_step": round(l_["ms"] + pre_ms, 2),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": args.cache_dtype,
+        "data": "synthetic",
+        "config": {"workload": (f"learned preconditioner: {cfg['N']} Gaussians SH3, one subset of {V} views "
+                                f"{W}x{H} (of the workload's four), {args.cache_dtype} cache"),
+                   "N": int(cfg["N"]), "views": V, "width": W, "height": H, "lambda": lam, "diag_floor": floor,
+                   "tol_relative": tol},
+        "jacobi": j, "learned": l_, "exact_target": res["exact_target"],
+        "features_and_forward_ms": round(pre_ms, 3),
+        "speedup_vs_jacobi": round(j["ms"] / (l_["ms"] + pre_ms), 3),
+        "training": {"samples": 300_000, "steps": n_steps, "ms_per_step": round(train_ms, 3),
+                     "loss_first": round(loss0.item(), 5), "loss_last": round(loss1.item(), 5)},
+        "n_pairs": info["n_pairs"], "build_and_diag_ms": round(ws["build_ms"], 1),
+        "n_fallback": int(nf.item()),
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -325,6 +433,9 @@ def main() -> int:
     B.load()
     if args.config == "batching":
         print(json.dumps(bench_batching(args, B, sg, torch)), flush=True)
+        return 0
+    if args.config == "learned":
+        print(json.dumps(bench_learned(args, B, sg, torch)), flush=True)
         return 0
     tw, th = (int(v) for v in args.tile.split("x"))
     cfg = dict(sg.CONFIGS[args.config])
