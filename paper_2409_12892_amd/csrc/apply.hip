@@ -461,15 +461,19 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
             for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
         __syncthreads();
         const int r0 = (int)s_loc[0] / kRun, r1 = (int)s_loc[cn] / kRun;   // tile-local runs
+        // rounds of kThreads runs, last first: the J half ended on the
+        // chunk's last pairs, which are the likeliest to be still cached
+        const int nround = (r1 - r0 + kThreads - 1) / kThreads;
         RunLoad<DT> nxt;
-        P.run(r0 + tid, nxt);
+        P.run(r0 + (nround > 0 ? nround - 1 : 0) * kThreads + tid, nxt);
         // every lane runs every round (converged for the wave scan); lanes
         // without a run carry zeros under a key of their own
-        for (int base = r0; base < r1; base += kThreads) {
+        for (int k = nround - 1; k >= 0; --k) {
+            const int base = r0 + k * kThreads;
             const int run = base + tid;
             const bool has = run < r1;
             const RunLoad<DT> L = nxt;
-            P.run(run + kThreads, nxt);
+            if (k > 0) P.run(base - kThreads + tid, nxt);
             const int64_t sl = (int64_t)L.seg - (sb + c0);
             const int s = (has && sl >= 0 && sl < cn) ? (int)sl : kChunk;   // kChunk: no run (or an inconsistent cache)
             float m[9];
@@ -618,9 +622,46 @@ __global__ void __launch_bounds__(kBlock) k_gv_reduce_moments_join(ApplyBatch Bt
 // ---- chain: per-(Gaussian, view) moments -> parameters ---------------------------
 // The adjoint of the tangent map: g_geo = sum_v L_v^T S[0:6] + Jdir_v^T S[6:9],
 // g_sh[k][ch] = sum_v mask_ch Y_k S[6 + ch], with S the (Gaussian, view)'s
-// moments (summed over its segments by k_gv_reduce).  One thread per
-// Gaussian.  out = scale * J^T u (+ lambda M p); partial dot products
-// p . out per block.
+// moments (summed over its segments by k_gv_reduce).  Two passes, both with
+// coalesced loads: one thread per (Gaussian, view) maps its moments to its
+// 11 geometric (float64) and 3K SH contributions, stored per row over the
+// (Gaussian, view) records; then one thread per Gaussian sums its records
+// row by row (in record order).  out = scale * J^T u (+ lambda M p);
+// partial dot products p . out per block.
+template <int DEG>
+__global__ void __launch_bounds__(kBlock) k_chain_gv(ApplyBatch Bt) {
+    const ApplyArgs& a = Bt.a[blockIdx.y];
+    if (a.stop && *a.stop) return;
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    const CacheView& c = a.c;
+    const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gv >= c.n_gv) return;
+    const int64_t ls = c.lin_stride;
+    double* __restrict__ geo_out = a.gvc;                           // [11][ls]
+    float* __restrict__ sh_out = (float*)(a.gvc + 11 * ls);         // [3K][ls]
+    float S9[9];
+#pragma unroll
+    for (int k = 0; k < 9; ++k) S9[k] = a.gvsum[gv * 9 + k];
+#pragma unroll
+    for (int j = 0; j < 11; ++j) {
+        double v = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) v += (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv] * (double)S9[i];
+        if (j < 3) {
+#pragma unroll
+            for (int ch = 0; ch < 3; ++ch)
+                v += (double)c.lin[(int64_t)(kLinJdir + 3 * ch + j) * ls + gv] * (double)S9[6 + ch];
+        }
+        geo_out[(int64_t)j * ls + gv] = v;
+    }
+#pragma unroll
+    for (int ch = 0; ch < 3; ++ch) {
+        const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * S9[6 + ch];
+#pragma unroll
+        for (int k = 0; k < K; ++k) sh_out[(int64_t)(3 * k + ch) * ls + gv] = c.lin[(int64_t)(kLinY + k) * ls + gv] * w;
+    }
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
     const ApplyArgs& a = Bt.a[blockIdx.y];
@@ -634,39 +675,22 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
     const CacheView& c = a.c;
     __shared__ double s_red[kBlock / kWave];
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool live = g < c.N;
     const int64_t ls = c.lin_stride;
+    const double* __restrict__ geo_in = a.gvc;
+    const float* __restrict__ sh_in = (const float*)(a.gvc + 11 * ls);
     double pg = 0.0;
-    if (live) {
-        double geo[11];
-#pragma unroll
-        for (int j = 0; j < 11; ++j) geo[j] = 0.0;
-        float gsh[3 * K];
-#pragma unroll
-        for (int j = 0; j < 3 * K; ++j) gsh[j] = 0.0f;
+    if (g < c.N) {
         const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
-        for (uint32_t gv = b; gv < e; ++gv) {
-            float S9[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) S9[k] = a.gvsum[(int64_t)gv * 9 + k];
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-#pragma unroll
-                for (int j = 0; j < 11; ++j)
-                    geo[j] += (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv] * (double)S9[i];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-#pragma unroll
-                for (int m = 0; m < 3; ++m)
-                    geo[m] += (double)c.lin[(int64_t)(kLinJdir + 3 * ch + m) * ls + gv] * (double)S9[6 + ch];
-                const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * S9[6 + ch];
-#pragma unroll
-                for (int k = 0; k < K; ++k) gsh[3 * k + ch] += c.lin[(int64_t)(kLinY + k) * ls + gv] * w;
-            }
-        }
-#pragma unroll
         for (int j = 0; j < P; ++j) {
-            double val = (j < 11 ? geo[j < 11 ? j : 0] : (double)gsh[j >= 11 ? j - 11 : 0]) * scale;
+            double v = 0.0;
+            if (j < 11) {
+                for (uint32_t gv = b; gv < e; ++gv) v += geo_in[(int64_t)j * ls + gv];
+            } else {
+                float f = 0.0f;
+                for (uint32_t gv = b; gv < e; ++gv) f += sh_in[(int64_t)(j - 11) * ls + gv];
+                v = (double)f;
+            }
+            double val = v * scale;
             const int64_t idx = (int64_t)j * c.N + g;
             if (M) {
                 const float m = M[idx];
@@ -1168,6 +1192,13 @@ hipError_t launch_apply_tile(int mode, const ApplyBatch& B, hipStream_t s) {
 }
 
 hipError_t launch_chain(const ApplyBatch& B, hipStream_t s) {
+    const int64_t ngv = batch_max(B, [](const ApplyArgs& a) { return a.c.n_gv; });
+    if (ngv > 0) {
+        const dim3 gg(grid_for(ngv), (unsigned)B.n);
+#define LM_CG(D) hipLaunchKernelGGL(k_chain_gv<D>, gg, dim3(kBlock), 0, s, B)
+        LM_DEG_SWITCH(B.a[0].c.deg, LM_CG)
+#undef LM_CG
+    }
     const dim3 g(chain_blocks(B.a[0].c.N), (unsigned)B.n);
 #define LM_C(D) hipLaunchKernelGGL(k_chain<D>, g, dim3(kBlock), 0, s, B)
     LM_DEG_SWITCH(B.a[0].c.deg, LM_C)

@@ -115,7 +115,7 @@ struct lm_cache {
     DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs;
     DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
-    DevBuf gvsum, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
+    DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
     bool gram_valid = false;     // gvgram holds the Gram values of the current build
     bool compact = false;        // the build-only buffers were released (LM_BUILD_COMPACT)
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
@@ -150,6 +150,7 @@ struct lm_cache {
         a.dyc = dyc.as<float>();
         a.gmom = gmom.as<float>();
         a.gvsum = gvsum.as<float>();
+        a.gvc = gvchain.as<double>();
         a.edge = edge_m.as<float>();
         a.edge_key = ekey_m.as<uint32_t>();
         a.jp_part = jp_part.as<double>();
@@ -164,7 +165,7 @@ struct lm_cache {
                                &run_seg, &gv_cnt, &gv_flag,
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -189,7 +190,7 @@ struct lm_cache {
                                &run_seg, &gv_cnt, &gv_flag,
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -456,6 +457,7 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(c->gmom.ensure(sizeof(float) * 9 * nseg_a));
     const int64_t nwav = lm::gv_reduce_waves(nseg_a);
     LM_HIP(c->gvsum.ensure(sizeof(float) * 9 * ngv_a));
+    LM_HIP(c->gvchain.ensure((sizeof(double) * 11 + sizeof(float) * 3 * (c->deg + 1) * (c->deg + 1)) * c->lin_stride));
     LM_HIP(c->edge_m.ensure(sizeof(float) * 2 * 9 * nwav));
     LM_HIP(c->ekey_m.ensure(sizeof(uint32_t) * nwav));
     LM_HIP(c->jp_part.ensure(sizeof(double) * c->n_tiles));

@@ -221,6 +221,7 @@ struct ApplyArgs {
     float* dyc;              // [n_gv][9] power coefficients of J_y p
     float* gmom;             // [n_seg][9] moments of J^T u per segment
     float* gvsum;            // [n_gv][9] moments per (Gaussian, view)
+    double* gvc;             // chain: [11][lin_stride] float64 + [3K][lin_stride] float32 per gv
     float* edge;             // [2 * waves][9] pieces of gv lists that cross waves
     uint32_t* edge_key;      // [waves]
     double* jp_part;         // [n_tiles] ||J p||^2 per tile
