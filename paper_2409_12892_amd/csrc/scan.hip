@@ -120,69 +120,132 @@ __global__ void k_reduce_f64(const double* __restrict__ in, int64_t n, double* _
 }
 
 // ---- radix sort ---------------------------------------------------------------
-template <typename KeyT>
+// One pass sorts by a digit of BITS bits (8 or 9; the pass widths of a key
+// are chosen so that the passes are as few as 9-bit digits allow), stable:
+// per-block digit histograms, one exclusive scan in digit-major order, then
+// a scatter that ranks equal digits within a wave by ballots and across the
+// block's waves by a prefix of their counts.
+template <typename KeyT, int BITS>
 __global__ void k_radix_hist(const KeyT* __restrict__ keys, int64_t n, int shift, int64_t nb,
                              uint32_t* __restrict__ hist) {
-    __shared__ uint32_t h[256];
-    h[threadIdx.x] = 0;
+    constexpr int NDIG = 1 << BITS;
+    __shared__ uint32_t h[NDIG];
+    for (int d = threadIdx.x; d < NDIG; d += kBlock) h[d] = 0;
     __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
 #pragma unroll 4
     for (int i = 0; i < kRadixItems; ++i) {
         int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
-        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & 0xFF], 1u);
+        if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (NDIG - 1)], 1u);
     }
     __syncthreads();
-    hist[(int64_t)threadIdx.x * nb + blockIdx.x] = h[threadIdx.x];   // digit-major
+    for (int d = threadIdx.x; d < NDIG; d += kBlock) hist[(int64_t)d * nb + blockIdx.x] = h[d];   // digit-major
 }
 
-template <typename KeyT>
-__global__ void k_radix_scatter(const KeyT* __restrict__ keys, const uint32_t* __restrict__ vals,
-                                int64_t n, int shift, int64_t nb, const uint64_t* __restrict__ offs,
-                                KeyT* __restrict__ okeys, uint32_t* __restrict__ ovals) {
+// The block's kRadixTile items are first ranked by digit in LDS (stable:
+// rounds in order, waves in order, lanes in order), then written out in that
+// order, so consecutive threads write consecutive addresses of a digit's run.
+template <typename KeyT, int BITS>
+__global__ void __launch_bounds__(kBlock) k_radix_scatter(const KeyT* __restrict__ keys,
+                                                         const uint32_t* __restrict__ vals, int64_t n, int shift,
+                                                         int64_t nb, const uint64_t* __restrict__ offs,
+                                                         KeyT* __restrict__ okeys, uint32_t* __restrict__ ovals) {
     constexpr int NW = kBlock / kWave;
-    __shared__ uint32_t wcnt[NW][256];
-    __shared__ uint64_t running[256];
+    constexpr int NDIG = 1 << BITS;
+    constexpr int DPT = NDIG / kBlock;   // digits owned per thread
+    __shared__ uint32_t wcnt[NW][NDIG];
+    __shared__ uint32_t lstart[NDIG];    // first local slot of each digit in the block
+    __shared__ uint32_t lrun[NDIG];      // items of each digit placed so far
+    __shared__ KeyT s_key[kRadixTile];
+    __shared__ uint32_t s_val[kRadixTile];
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
-    running[tid] = offs[(int64_t)tid * nb + blockIdx.x];
-    for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
-    __syncthreads();
     const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int nloc = (int)(n - base < kRadixTile ? n - base : kRadixTile);
+    // the block's count of digit d is the step of the digit-major exclusive
+    // scan at (d, block) (its entry past the end holds the total); the local
+    // starts are an exclusive scan of those counts over the digits
+    {
+        uint32_t cnt[DPT];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            const int64_t at = (int64_t)(tid * DPT + q) * nb + blockIdx.x;
+            cnt[q] = (uint32_t)(offs[at + 1] - offs[at]);
+            mine += cnt[q];
+            for (int w = 0; w < NW; ++w) wcnt[w][tid * DPT + q] = 0;
+        }
+        // exclusive scan of the per-thread sums over the block
+        uint32_t inc = mine;
+        const int lane = __lane_id();
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        __shared__ uint32_t wsum[NW];
+        if (lane == kWave - 1) wsum[wid] = inc;
+        __syncthreads();
+        uint32_t wbase = 0;
+        for (int w = 0; w < wid; ++w) wbase += wsum[w];
+        uint32_t run = wbase + inc - mine;
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            lstart[tid * DPT + q] = run;
+            run += cnt[q];
+            lrun[tid * DPT + q] = 0;
+        }
+        __syncthreads();
+    }
     for (int r = 0; r < kRadixItems; ++r) {
-        const int64_t idx = base + (int64_t)r * kBlock + tid;
-        const bool live = idx < n;
-        KeyT k = live ? keys[idx] : (KeyT)0;
-        uint32_t v = live ? vals[idx] : 0u;
-        const uint32_t d = (uint32_t)((k >> shift) & 0xFF);
+        const int li = r * kBlock + tid;
+        const bool live = li < nloc;
+        KeyT k = live ? keys[base + li] : (KeyT)0;
+        uint32_t v = live ? vals[base + li] : 0u;
+        const uint32_t d = (uint32_t)((k >> shift) & (NDIG - 1));
         uint64_t peers = __ballot(live);
 #pragma unroll
-        for (int b = 0; b < 8; ++b) {
+        for (int b = 0; b < BITS; ++b) {
             uint64_t m = __ballot((d >> b) & 1u);
             peers &= ((d >> b) & 1u) ? m : ~m;
         }
         const uint32_t rank = (uint32_t)__popcll(peers & lanemask_lt());
         if (live && rank == 0) wcnt[wid][d] = (uint32_t)__popcll(peers);
         __syncthreads();
-        // thread `tid` owns digit `tid`: replace its per-wave counts by their
-        // exclusive prefix over the waves
-        uint32_t c[NW];
-        uint32_t tot = 0;
+        uint32_t tot[DPT];
 #pragma unroll
-        for (int w = 0; w < NW; ++w) c[w] = wcnt[w][tid];
+        for (int q = 0; q < DPT; ++q) {
+            const int dg = tid * DPT + q;
+            uint32_t c[NW];
+            tot[q] = 0;
 #pragma unroll
-        for (int w = 0; w < NW; ++w) { wcnt[w][tid] = tot; tot += c[w]; }
-        __syncthreads();
-        if (live) {
-            uint64_t pos = running[d] + wcnt[wid][d] + rank;
-            okeys[pos] = k;
-            ovals[pos] = v;
+            for (int w = 0; w < NW; ++w) c[w] = wcnt[w][dg];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) { wcnt[w][dg] = tot[q]; tot[q] += c[w]; }
         }
         __syncthreads();
-        running[tid] += tot;
-#pragma unroll
-        for (int w = 0; w < NW; ++w) wcnt[w][tid] = 0;
+        if (live) {
+            const uint32_t slot = lstart[d] + lrun[d] + wcnt[wid][d] + rank;
+            s_key[slot] = k;
+            s_val[slot] = v;
+        }
         __syncthreads();
+#pragma unroll
+        for (int q = 0; q < DPT; ++q) {
+            const int dg = tid * DPT + q;
+            lrun[dg] += tot[q];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) wcnt[w][dg] = 0;
+        }
+        __syncthreads();
+    }
+    // write the block's items in local digit order
+    for (int i = tid; i < nloc; i += kBlock) {
+        const KeyT k = s_key[i];
+        const uint32_t d = (uint32_t)((k >> shift) & (NDIG - 1));
+        const uint64_t pos = offs[(int64_t)d * nb + blockIdx.x] + (uint64_t)(i - (int)lstart[d]);
+        okeys[pos] = k;
+        ovals[pos] = s_val[i];
     }
 }
 
@@ -235,11 +298,14 @@ hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s) {
     return hipGetLastError();
 }
 
+constexpr int kMaxDigitBits = 9;
+constexpr int kMaxDigits = 1 << kMaxDigitBits;
+
 size_t radix_tmp_bytes(int64_t n) {
     int64_t nb = (n + kRadixTile - 1) / kRadixTile;
-    size_t hist = (size_t)256 * nb * sizeof(uint32_t);
-    size_t offs = (size_t)(256 * nb + 1) * sizeof(uint64_t);
-    size_t scan = scan_tmp_bytes(256 * nb);
+    size_t hist = (size_t)kMaxDigits * nb * sizeof(uint32_t);
+    size_t offs = (size_t)(kMaxDigits * nb + 1) * sizeof(uint64_t);
+    size_t scan = scan_tmp_bytes(kMaxDigits * nb);
     return hist + offs + scan + 256;
 }
 
@@ -253,21 +319,39 @@ hipError_t radix_sort_impl(KeyT* keys, uint32_t* vals, KeyT* keys_alt, uint32_t*
     if (radix_tmp_bytes(n) > tmp_bytes) return hipErrorInvalidValue;
     char* t = (char*)tmp;
     uint32_t* hist = (uint32_t*)t;
-    t += (size_t)256 * nb * sizeof(uint32_t);
+    t += (size_t)kMaxDigits * nb * sizeof(uint32_t);
     t = (char*)(((uintptr_t)t + 7) & ~(uintptr_t)7);
     uint64_t* offs = (uint64_t*)t;
-    t += (size_t)(256 * nb + 1) * sizeof(uint64_t);
+    t += (size_t)(kMaxDigits * nb + 1) * sizeof(uint64_t);
     void* stmp = t;
-    size_t stmp_bytes = scan_tmp_bytes(256 * nb);
+    size_t stmp_bytes = scan_tmp_bytes(kMaxDigits * nb);
     KeyT* ki = keys; uint32_t* vi = vals;
     KeyT* ko = keys_alt; uint32_t* vo = vals_alt;
     bool alt = false;
-    for (int shift = begin_bit; shift < end_bit; shift += 8) {
-        hipLaunchKernelGGL(k_radix_hist<KeyT>, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
-        hipError_t e = exclusive_scan_u32_to_u64(hist, offs, 256 * nb, stmp, stmp_bytes, s);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k_radix_scatter<KeyT>, dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, n, shift, nb,
-                           offs, ko, vo);
+    // as few passes as 9-bit digits allow, the bits spread evenly over them.
+    // A pass narrower than its kernel's digit also sorts by a few bits of the
+    // next digit (harmless: every pass is a stable sort, and the next one
+    // orders those bits again) or by bits above end_bit (zero in every key).
+    const int bits = end_bit - begin_bit;
+    const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
+    int shift = begin_bit;
+    for (int pass = 0; pass < passes; ++pass) {
+        const int w = (bits - (shift - begin_bit) + (passes - pass) - 1) / (passes - pass);
+        hipError_t e;
+        if (w > 8) {
+            hipLaunchKernelGGL((k_radix_hist<KeyT, 9>), dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
+            e = exclusive_scan_u32_to_u64(hist, offs, 512 * nb, stmp, stmp_bytes, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, 9>), dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, n, shift,
+                               nb, offs, ko, vo);
+        } else {
+            hipLaunchKernelGGL((k_radix_hist<KeyT, 8>), dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
+            e = exclusive_scan_u32_to_u64(hist, offs, 256 * nb, stmp, stmp_bytes, s);
+            if (e != hipSuccess) return e;
+            hipLaunchKernelGGL((k_radix_scatter<KeyT, 8>), dim3((unsigned)nb), dim3(kBlock), 0, s, ki, vi, n, shift,
+                               nb, offs, ko, vo);
+        }
+        shift += w;
         std::swap(ki, ko);
         std::swap(vi, vo);
         alt = !alt;
