@@ -271,7 +271,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(hipMemcpyAsync(c->x.p, scene->x, sizeof(float) * P * N, hipMemcpyDeviceToDevice, s));
 
     // projection and key counts
-    LM_HIP(c->rec64.ensure(sizeof(double) * 10 * R));
+    LM_HIP(c->rec64.ensure(sizeof(double) * lm::kRecStride * R));
     LM_HIP(c->recf.ensure(sizeof(float) * 3 * R));
     LM_HIP(c->rad.ensure(sizeof(int32_t) * R));
     LM_HIP(c->keycnt.ensure(sizeof(uint32_t) * R));

@@ -172,13 +172,18 @@ hipError_t view_sum_f64(const CamDev* cams, int V, const double* in, double* out
 hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s);
 
 
+// Float64 projection record per (Gaussian, view): mx, my, A, B, C, o, log
+// threshold, r, g, b, padded to 16 doubles so that a record is one aligned
+// 128-byte line (the raster passes gather one record per tile key).
+constexpr int kRecStride = 16;
+
 // Arguments of the raster passes (raster.hip).
 struct RasterArgs {
     const CamDev* cams;
     const int32_t* tile_view;
     const int64_t* tile_start;
     const uint32_t* vals;
-    const double* rec64;       // [10][V*N]
+    const double* rec64;       // [V*N][kRecStride]
     int64_t N;
     int32_t V, TW, TH;
     // count pass

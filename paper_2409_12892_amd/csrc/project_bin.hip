@@ -26,14 +26,12 @@ __device__ __forceinline__ void tile_rect(float mx, float my, int32_t radius, in
     y1 = (int)fmaxf(fminf(fy1, (float)(TY - 1)), -1.0f);
 }
 
-// rec64 layout [10][V*N]: mx, my, A, B, C, o, log threshold, r, g, b (float64)
 template <int deg>
-__global__ void k_project(const CamDev* __restrict__ cams, const float* __restrict__ x, int64_t N, int V,
-                          int TW, int TH, double* __restrict__ rec64, float* __restrict__ recf,
-                          int32_t* __restrict__ rad, uint32_t* __restrict__ keycnt) {
+__device__ __forceinline__ void project_one(const CamDev* __restrict__ cams, const float* __restrict__ x, int64_t N,
+                                            int V, int TW, int TH, int64_t r, float* __restrict__ recf,
+                                            int32_t* __restrict__ rad, uint32_t* __restrict__ keycnt,
+                                            double* __restrict__ rec) {
     const int64_t R = N * (int64_t)V;
-    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
     const int v = (int)(r / N);
     const int64_t g = r - (int64_t)v * N;
     const CamDev& cam = cams[v];
@@ -54,8 +52,31 @@ __global__ void k_project(const CamDev* __restrict__ cams, const float* __restri
     const double o = f.o;
     const double vals[10] = {f.mx, f.my, f.A, f.B, f.C, o, -log(255.0 * o), f.col[0], f.col[1], f.col[2]};
 #pragma unroll
-    for (int i = 0; i < 10; ++i) rec64[(int64_t)i * R + r] = vals[i];
+    for (int i = 0; i < 10; ++i) rec[i] = vals[i];
+#pragma unroll
+    for (int i = 10; i < kRecStride; ++i) rec[i] = 0.0;
 }
+
+// rec64 layout [V*N][kRecStride]: mx, my, A, B, C, o, log threshold, r, g, b (float64)
+template <int deg>
+__global__ void k_project(const CamDev* __restrict__ cams, const float* __restrict__ x, int64_t N, int V,
+                          int TW, int TH, double* __restrict__ rec64, float* __restrict__ recf,
+                          int32_t* __restrict__ rad, uint32_t* __restrict__ keycnt) {
+    const int64_t R = N * (int64_t)V;
+    const int64_t r0 = (int64_t)blockIdx.x * blockDim.x;
+    const int64_t r = r0 + threadIdx.x;
+    // the block's records go through LDS (rows padded by one double against
+    // bank conflicts) and leave as one contiguous run
+    constexpr int kRow = kRecStride + 1;
+    __shared__ double s_rec[kBlock * kRow];
+    if (r < R) project_one<deg>(cams, x, N, V, TW, TH, r, recf, rad, keycnt, &s_rec[threadIdx.x * kRow]);
+    __syncthreads();
+    const int nrec = (int)(R - r0 < kBlock ? R - r0 : kBlock);
+    double* dst = rec64 + r0 * kRecStride;
+    for (int i = threadIdx.x; i < nrec * kRecStride; i += kBlock) dst[i] = s_rec[(i / kRecStride) * kRow + i % kRecStride];
+}
+
+
 
 // Depth-sort key of every record: (view << 31) | float32 depth bits for a
 // binned record, (view << 31) | 0x7FFFFFFF for one that emits no key.

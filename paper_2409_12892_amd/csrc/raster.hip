@@ -91,7 +91,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             const int64_t r = (int64_t)v * a.N + gi;
             s_g[tid] = gi;
 #pragma unroll
-            for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[(int64_t)i * R + r];
+            for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
         }
         if (FILL) {
             // per-entry totals, block-wide exclusive scan of (pairs, active) and
