@@ -98,28 +98,56 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32
 }
 
 // Keys (global tile index) and values (Gaussian id) of the records in depth
-// order; record order[i] writes its tiles at off_sorted[i].
-__global__ void k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int64_t R, int TW, int TH,
-                           const float* __restrict__ recf, const int32_t* __restrict__ rad,
-                           const uint32_t* __restrict__ order, const uint64_t* __restrict__ off_sorted,
-                           uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= R) return;
-    const uint64_t o0 = off_sorted[i], o1 = off_sorted[i + 1];
-    if (o0 == o1) return;
-    const int64_t r = order[i];
-    const int v = (int)(r / N);
-    const uint32_t g = (uint32_t)(r - (int64_t)v * N);
-    const CamDev& cam = cams[v];
-    int x0, y0, x1, y1;
-    tile_rect(recf[r], recf[R + r], rad[r], TW, TH, cam.TX, cam.TY, x0, y0, x1, y1);
-    uint64_t o = o0;
-    for (int ty = y0; ty <= y1 && o < o1; ++ty)
-        for (int tx = x0; tx <= x1 && o < o1; ++tx) {
-            keys[o] = (uint32_t)(cam.tile_base + (int64_t)ty * cam.TX + tx);
-            vals[o] = g;
-            ++o;
+// order; record order[i] writes its tiles (row by row) at off_sorted[i].
+// A block takes 256 consecutive records and writes their keys together:
+// each thread takes every 256th key of the block's range and finds its
+// record by a binary search over the block's offsets, so the stores of a
+// wave are consecutive.
+__global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int64_t R, int TW,
+                                                    int TH, const float* __restrict__ recf,
+                                                    const int32_t* __restrict__ rad,
+                                                    const uint32_t* __restrict__ order,
+                                                    const uint64_t* __restrict__ off_sorted,
+                                                    uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+    __shared__ uint32_t s_off[kBlock];    // first key of each record, relative to the block
+    __shared__ int32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock];
+    __shared__ uint32_t s_base[kBlock], s_g[kBlock], s_tx[kBlock];
+    const int64_t i0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t i = i0 + threadIdx.x;
+    const int64_t ie = i0 + kBlock < R ? i0 + kBlock : R;
+    const uint64_t b0 = off_sorted[i0], b1 = off_sorted[ie];
+    if (i < R) {
+        const int64_t r = order[i];
+        const int v = (int)(r / N);
+        const CamDev& cam = cams[v];
+        int x0, y0, x1, y1;
+        tile_rect(recf[r], recf[R + r], rad[r], TW, TH, cam.TX, cam.TY, x0, y0, x1, y1);
+        s_off[threadIdx.x] = (uint32_t)(off_sorted[i] - b0);
+        s_x0[threadIdx.x] = x0;
+        s_y0[threadIdx.x] = y0;
+        s_w[threadIdx.x] = x1 - x0 + 1;
+        s_base[threadIdx.x] = (uint32_t)cam.tile_base;
+        s_tx[threadIdx.x] = (uint32_t)cam.TX;
+        s_g[threadIdx.x] = (uint32_t)(r - (int64_t)v * N);
+    } else {
+        s_off[threadIdx.x] = (uint32_t)(b1 - b0);   // past the block's last key: never selected
+    }
+    __syncthreads();
+    const uint32_t nk = (uint32_t)(b1 - b0);
+    for (uint32_t k = threadIdx.x; k < nk; k += kBlock) {
+        // the last record whose first key is at or before k holds key k
+        int lo = 0, hi = kBlock - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (s_off[mid] <= k) lo = mid;
+            else hi = mid - 1;
         }
+        const uint32_t j = k - s_off[lo];
+        const int w = s_w[lo];
+        const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
+        keys[b0 + k] = s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+        vals[b0 + k] = s_g[lo];
+    }
 }
 
 // tile_start[t] = first key index of tile t (lists are [tile_start[t], tile_start[t+1])).
