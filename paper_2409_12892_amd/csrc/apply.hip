@@ -729,10 +729,13 @@ __device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i 
 // One lane per aligned 8-pair run of the whole cache.  A segment's runs
 // are adjacent, so after a segmented scan across the wave the last lane of
 // each segment piece holds the piece's sums: a piece that is a whole segment
-// is stored, a piece of a segment that spans waves is added atomically
-// (gram is zero-filled before).
+// is stored; a wave's piece that continues into the next wave (slot 1) or
+// comes from the previous one (slot 0) goes to the wave's edge slots, and
+// k_gram_join adds the pieces in wave order.
 template <int DT>
-__global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_runs, float* __restrict__ gram) {
+__global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_runs, float* __restrict__ gram,
+                                                     float* __restrict__ edge, uint32_t* __restrict__ ekey,
+                                                     uint32_t* __restrict__ eends) {
     using S = Store<DT>;
     const int64_t run = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     const int lane = __lane_id();
@@ -785,19 +788,54 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
     const uint32_t next = __shfl_down(key, 1, kWave);
     const int head = segment_head(key, lane);
     wave_segmented_scan<kGram>(acc, lane, head);
-    if (has && (lane == kWave - 1 || next != key)) {
-        const int64_t first = run - (lane - head);
-        const bool starts = head > 0 || first == 0 || c.run_seg[first - 1] != key;
-        const bool ends = lane < kWave - 1 || run + 1 >= n_runs || c.run_seg[run + 1] != key;
-        float* out = gram + (int64_t)key * kGram;
-        if (starts && ends) {
+    if (lane == kWave - 1 || next != key) {
+        const int64_t wave = run / kWave;
+        bool starts = true, ends = true;
+        if (has) {
+            const int64_t first = run - (lane - head);
+            starts = head > 0 || first == 0 || c.run_seg[first - 1] != key;
+            ends = lane < kWave - 1 || run + 1 >= n_runs || c.run_seg[run + 1] != key;
+        }
+        float* out = nullptr;
+        if (has && starts && ends) {
+            out = gram + (int64_t)key * kGram;
+        } else if (has && starts) {              // continues into the next wave (lane 63)
+            out = edge + (wave * 2 + 1) * kGram;
+            ekey[wave * 2 + 1] = key;
+        } else if (has) {                        // comes from the previous wave (the first piece)
+            out = edge + wave * 2 * kGram;
+            ekey[wave * 2] = key;
+            eends[wave] = ends ? 1u : 0u;
+        }
+        if (out) {
 #pragma unroll
             for (int k = 0; k < kGram; ++k) out[k] = acc[k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < kGram; ++k) unsafeAtomicAdd(out + k, acc[k]);
         }
+        if (lane == kWave - 1 && !(has && starts && !ends)) ekey[wave * 2 + 1] = kNoGv;
+        if (head == 0 && !(has && !starts)) ekey[wave * 2] = kNoGv;
     }
+}
+
+// Segments whose runs span waves: the wave where the segment starts adds
+// the pieces of the following waves in order and stores the sums.
+__global__ void __launch_bounds__(kBlock) k_gram_join(int64_t n_waves, const float* __restrict__ edge,
+                                                     const uint32_t* __restrict__ ekey,
+                                                     const uint32_t* __restrict__ eends, float* __restrict__ gram) {
+    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (w >= n_waves) return;
+    const uint32_t key = ekey[w * 2 + 1];
+    if (key == kNoGv) return;
+    float acc[kGram];
+#pragma unroll
+    for (int k = 0; k < kGram; ++k) acc[k] = edge[(w * 2 + 1) * kGram + k];
+    for (int64_t u = w + 1; u < n_waves && ekey[u * 2] == key; ++u) {
+#pragma unroll
+        for (int k = 0; k < kGram; ++k) acc[k] += edge[u * 2 * kGram + k];
+        if (eends[u]) break;
+    }
+    float* out = gram + (int64_t)key * kGram;
+#pragma unroll
+    for (int k = 0; k < kGram; ++k) out[k] = acc[k];
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
@@ -1268,20 +1306,22 @@ hipError_t launch_precond_features(const float* M, const float* coverage, const 
     return hipGetLastError();
 }
 
+int64_t gram_run_waves(int64_t n_pairs) { return (int64_t)grid_for(n_pairs / kRun) * (kBlock / kWave); }
+
 hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
-                       hipStream_t s) {
+                       float* run_edge, uint32_t* run_ekey, uint32_t* run_eends, hipStream_t s) {
     dim3 b(kBlock);
     const int64_t n_runs = c.n_pairs / kRun;
-    const int64_t ng = (int64_t)kGram * (c.n_seg > 0 ? c.n_seg : 1);
-    hipLaunchKernelGGL(k_fill_f32, dim3(grid_for(ng)), b, 0, s, gram, ng, 0.0f);
     if (n_runs > 0) {
         const dim3 g(grid_for(n_runs));
+        const int64_t nw = gram_run_waves(c.n_pairs);
         if (c.dtype == LM_CACHE_F32)
-            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F32>), g, b, 0, s, c, n_runs, gram);
+            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F32>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
         else if (c.dtype == LM_CACHE_BF16)
-            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_BF16>), g, b, 0, s, c, n_runs, gram);
+            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_BF16>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
         else
-            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram);
+            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
+        hipLaunchKernelGGL(k_gram_join, dim3(grid_for(nw)), b, 0, s, nw, run_edge, run_ekey, run_eends, gram);
     }
     return gv_reduce<kGram>(c, gram, gvgram, edge, edge_key, s);
 }

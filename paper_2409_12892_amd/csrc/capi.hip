@@ -116,6 +116,7 @@ struct lm_cache {
     DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
+    DevBuf gram_redge, gram_rkey, gram_rends;
     bool gram_valid = false;     // gvgram holds the Gram values of the current build
     bool compact = false;        // the build-only buffers were released (LM_BUILD_COMPACT)
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
@@ -165,7 +166,7 @@ struct lm_cache {
                                &run_seg, &gv_cnt, &gv_flag,
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -190,7 +191,7 @@ struct lm_cache {
                                &run_seg, &gv_cnt, &gv_flag,
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -625,8 +626,13 @@ static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
     LM_HIP(cm->gvgram.ensure(sizeof(float) * kG * std::max<int64_t>(cm->n_gv, 1)));
     LM_HIP(cm->edge_g.ensure(sizeof(float) * 2 * kG * nwav));
     LM_HIP(cm->ekey_g.ensure(sizeof(uint32_t) * nwav));
+    const int64_t nrw = std::max<int64_t>(lm::gram_run_waves(cm->n_slots), 1);
+    LM_HIP(cm->gram_redge.ensure(sizeof(float) * 2 * kG * nrw));
+    LM_HIP(cm->gram_rkey.ensure(sizeof(uint32_t) * 2 * nrw));
+    LM_HIP(cm->gram_rends.ensure(sizeof(uint32_t) * nrw));
     LM_HIP(lm::launch_gram(cm->view(), cm->gram.as<float>(), cm->gvgram.as<float>(), cm->edge_g.as<float>(),
-                           cm->ekey_g.as<uint32_t>(), s));
+                           cm->ekey_g.as<uint32_t>(), cm->gram_redge.as<float>(), cm->gram_rkey.as<uint32_t>(),
+                           cm->gram_rends.as<uint32_t>(), s));
     cm->gram_valid = true;
     return LM_OK;
 }

@@ -281,8 +281,10 @@ hipError_t launch_chain(const ApplyBatch& B, hipStream_t s);
 unsigned chain_blocks(int64_t N);
 // Per-segment Gram values (41 floats) reduced per (Gaussian, view) into gvgram.
 constexpr int kGramValues = 41;
+// run_edge: 2 * kGramValues floats, run_ekey: 2 u32, run_eends: 1 u32 per gram_run_waves(n_pairs)
+int64_t gram_run_waves(int64_t n_pairs);
 hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
-                       hipStream_t s);
+                       float* run_edge, uint32_t* run_ekey, uint32_t* run_eends, hipStream_t s);
 hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s);
 hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* coverage, hipStream_t s);
 // out 0: dense blocks of the selected Gaussians; out 1: targets and mask [P][N]
