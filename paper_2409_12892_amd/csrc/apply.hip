@@ -518,7 +518,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
         __syncthreads();
         for (int i = tid; i < cn * 9; i += kThreads) {
             const int si = i / 9, k = i - si * 9;
-            a.gmom[(sb + c0 + si) * 9 + k] = s_mom[k][si];
+            a.gmom[(int64_t)c.seg_pos[sb + c0 + si] * 9 + k] = s_mom[k][si];
         }
     }
 }
@@ -545,11 +545,10 @@ __device__ __forceinline__ void gv_reduce_body(const CacheView& c, const float* 
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0f;
     uint32_t key = kNoGv;
-    if (has) {
-        const int64_t sg = c.gv_segs[i];
-        key = c.seg_gv[sg];
+    if (has) {   // src holds the per-segment values at their list positions
+        key = c.list_gv[i];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = src[sg * NV + k];
+        for (int k = 0; k < NV; ++k) v[k] = src[i * NV + k];
     }
     const uint32_t next = __shfl_down(key, 1, kWave);
     const int head = segment_head(key, lane);
@@ -798,7 +797,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
         }
         float* out = nullptr;
         if (has && starts && ends) {
-            out = gram + (int64_t)key * kGram;
+            out = gram + (int64_t)c.seg_pos[key] * kGram;   // at the segment's list position
         } else if (has && starts) {              // continues into the next wave (lane 63)
             out = edge + (wave * 2 + 1) * kGram;
             ekey[wave * 2 + 1] = key;
@@ -820,7 +819,8 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
 // the pieces of the following waves in order and stores the sums.
 __global__ void __launch_bounds__(kBlock) k_gram_join(int64_t n_waves, const float* __restrict__ edge,
                                                      const uint32_t* __restrict__ ekey,
-                                                     const uint32_t* __restrict__ eends, float* __restrict__ gram) {
+                                                     const uint32_t* __restrict__ eends,
+                                                     const uint32_t* __restrict__ seg_pos, float* __restrict__ gram) {
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (w >= n_waves) return;
     const uint32_t key = ekey[w * 2 + 1];
@@ -833,7 +833,7 @@ __global__ void __launch_bounds__(kBlock) k_gram_join(int64_t n_waves, const flo
         for (int k = 0; k < kGram; ++k) acc[k] += edge[u * 2 * kGram + k];
         if (eends[u]) break;
     }
-    float* out = gram + (int64_t)key * kGram;
+    float* out = gram + (int64_t)seg_pos[key] * kGram;
 #pragma unroll
     for (int k = 0; k < kGram; ++k) out[k] = acc[k];
 }
@@ -1321,7 +1321,8 @@ hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* ed
             hipLaunchKernelGGL((k_gram_runs<LM_CACHE_BF16>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
         else
             hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
-        hipLaunchKernelGGL(k_gram_join, dim3(grid_for(nw)), b, 0, s, nw, run_edge, run_ekey, run_eends, gram);
+        hipLaunchKernelGGL(k_gram_join, dim3(grid_for(nw)), b, 0, s, nw, run_edge, run_ekey, run_eends, c.seg_pos,
+                           gram);
     }
     return gv_reduce<kGram>(c, gram, gvgram, edge, edge_key, s);
 }

@@ -112,7 +112,7 @@ struct lm_cache {
     DevBuf rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted;
     DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
     DevBuf tile_real, tile_real_off, run_seg;
-    DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs;
+    DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs, seg_pos, list_gv;
     DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
@@ -140,6 +140,7 @@ struct lm_cache {
         c.seg_stride = seg_stride;
         c.gv_rec = gv_rec.as<uint32_t>(); c.gv_first = gv_first.as<uint32_t>();
         c.gv_seg_off = gv_seg_off.as<uint32_t>(); c.gv_segs = gv_segs.as<uint32_t>();
+        c.seg_pos = seg_pos.as<uint32_t>(); c.list_gv = list_gv.as<uint32_t>();
         c.lin = lin.as<float>(); c.lin_stride = lin_stride;
         return c;
     }
@@ -164,7 +165,7 @@ struct lm_cache {
                                &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
                                &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
-                               &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
+                               &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
@@ -189,7 +190,7 @@ struct lm_cache {
                          &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
                          &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
-                         &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &pT, &pD,
+                         &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
@@ -404,6 +405,8 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(c->gv_cursor.ensure(sizeof(uint32_t) * ngv_a));
     LM_HIP(hipMemsetAsync(c->gv_cursor.p, 0, sizeof(uint32_t) * ngv_a, s));
     LM_HIP(c->gv_segs.ensure(sizeof(uint32_t) * nseg_a));
+    LM_HIP(c->seg_pos.ensure(sizeof(uint32_t) * nseg_a));
+    LM_HIP(c->list_gv.ensure(sizeof(uint32_t) * nseg_a));
     LM_HIP(launch_gv_compact(c->gv_cnt.as<uint32_t>(), c->gv_idx.as<uint64_t>(), c->gv_segoff.as<uint64_t>(), N,
                              (int)V, c->gv_rec.as<uint32_t>(), c->gv_seg_off.as<uint32_t>(),
                              c->gv_first.as<uint32_t>(), s));
@@ -448,7 +451,9 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.seg_stride = c->seg_stride;
     ra.run_seg = c->run_seg.as<uint32_t>();
     { LM_PROF("raster_fill", s); LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s)); }
-    { LM_PROF("gv_sort", s); LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s)); }
+    { LM_PROF("gv_sort", s); LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s));
+      LM_HIP(launch_seg_pos(c->gv_segs.as<uint32_t>(), c->seg_gv.as<uint32_t>(), c->n_seg, c->seg_pos.as<uint32_t>(),
+                            c->list_gv.as<uint32_t>(), s)); }
     // linearised projection of every (Gaussian, view) at x
     c->lin_stride = round_up(ngv_a, 8);
     LM_HIP(c->lin.ensure(sizeof(float) * lm::kLin * c->lin_stride));

@@ -65,6 +65,8 @@ struct CacheView {
     const uint32_t* gv_first;    // dev [N+1] first gv of each Gaussian
     const uint32_t* gv_seg_off;  // dev [n_gv+1]
     const uint32_t* gv_segs;     // dev [n_seg] segment ids grouped by gv, ascending
+    const uint32_t* seg_pos;     // dev [n_seg] position of each segment in gv_segs
+    const uint32_t* list_gv;     // dev [n_seg] gv of each gv_segs entry
     const float* lin;            // dev [kLin][lin_stride]: linearised projection per gv
     int64_t lin_stride;
 };
@@ -273,6 +275,8 @@ hipError_t launch_raster(bool fill, int dtype, int64_t n_tiles, const RasterArgs
 hipError_t launch_flag_nonzero(const uint32_t* in, int64_t n, uint32_t* out, hipStream_t s);
 hipError_t launch_gv_compact(const uint32_t* gv_cnt, const uint64_t* gv_idx, const uint64_t* gv_segoff, int64_t N,
                              int V, uint32_t* gv_rec, uint32_t* gv_seg_off, uint32_t* gv_first, hipStream_t s);
+hipError_t launch_seg_pos(const uint32_t* gv_segs, const uint32_t* seg_gv, int64_t n_seg, uint32_t* seg_pos,
+                          uint32_t* list_gv, hipStream_t s);
 hipError_t launch_gv_sort(const uint32_t* gv_seg_off, int64_t n_gv, uint32_t* gv_segs, hipStream_t s);
 // apply.hip (mode 1 = J, 2 = J^T, 3 = fused J^T J)
 hipError_t launch_tangent(const ApplyBatch& B, hipStream_t s);

@@ -303,6 +303,18 @@ __global__ void k_flag_nonzero(const uint32_t* __restrict__ in, int64_t n, uint3
 }
 
 // Sort each gv's (short) segment list ascending so reductions run in a fixed order.
+// Position of every segment in the (Gaussian, view)-grouped list, and the
+// gv of every list entry: per-segment sums are written at their list
+// position, so the per-gv reduction reads them in order.
+__global__ void k_seg_pos(const uint32_t* __restrict__ gv_segs, const uint32_t* __restrict__ seg_gv, int64_t n_seg,
+                          uint32_t* __restrict__ seg_pos, uint32_t* __restrict__ list_gv) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_seg) return;
+    const uint32_t sg = gv_segs[i];
+    seg_pos[sg] = (uint32_t)i;
+    list_gv[i] = seg_gv[sg];
+}
+
 __global__ void k_gv_sort(const uint32_t* __restrict__ gv_seg_off, int64_t n_gv, uint32_t* __restrict__ gv_segs) {
     const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= n_gv) return;
@@ -349,6 +361,13 @@ hipError_t launch_gv_compact(const uint32_t* gv_cnt, const uint64_t* gv_idx, con
 hipError_t launch_gv_sort(const uint32_t* gv_seg_off, int64_t n_gv, uint32_t* gv_segs, hipStream_t s) {
     if (n_gv == 0) return hipSuccess;
     hipLaunchKernelGGL(k_gv_sort, dim3(grid_for(n_gv)), dim3(kBlock), 0, s, gv_seg_off, n_gv, gv_segs);
+    return hipGetLastError();
+}
+
+hipError_t launch_seg_pos(const uint32_t* gv_segs, const uint32_t* seg_gv, int64_t n_seg, uint32_t* seg_pos,
+                          uint32_t* list_gv, hipStream_t s) {
+    if (n_seg == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_seg_pos, dim3(grid_for(n_seg)), dim3(kBlock), 0, s, gv_segs, seg_gv, n_seg, seg_pos, list_gv);
     return hipGetLastError();
 }
 
