@@ -145,6 +145,11 @@ lm_status lm_apply_JtJ(const lm_cache* cache, const float* p, float lambda, cons
 /* u = J p (eq. apply-j), u dev float32 [V][3][H][W]. */
 lm_status lm_apply_J(const lm_cache* cache, const float* p, float* u, void* stream);
 
+/* ||J p||^2 (float64, dev, one value): the J product alone, with the
+ * squared norm of each tile's u summed in a fixed order (the denominator of
+ * the trust-region ratio, eq. tr-update, needs no J^T half). */
+lm_status lm_jp_sqnorm(const lm_cache* cache, const float* p, double* out, void* stream);
+
 /* g = J^T u (eq. apply-jt), u dev float32 [V][3][H][W], g dev [P][N]. */
 lm_status lm_apply_JT(const lm_cache* cache, const float* u, float* g, void* stream);
 

@@ -35,6 +35,7 @@ EXPORTED_SYMBOLS = (
     "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
     "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile", "lm_pair_coverage", "lm_block_jacobi",
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
+    "lm_jp_sqnorm",
 )
 
 MLP_FEATURES, MLP_HIDDEN, MLP_MAX_OUT, MLP_PARAMS = 8, 64, 64, 8896
@@ -226,6 +227,15 @@ def lm_apply_J(cache: Cache, p, out=None, n_residuals: int | None = None):
         n = n_residuals if n_residuals is not None else 3 * cache.info()["n_pixels"]
         out = torch.empty(n, device=p.device, dtype=torch.float32)
     _check(load().lm_apply_J(cache.handle, _ptr(p), _ptr(out), _stream()), "lm_apply_J")
+    return out
+
+
+def lm_jp_sqnorm(cache: Cache, p):
+    """||J p||^2 as a 1-element float64 device tensor."""
+    import torch
+    p = _dev_f32(p, "p")
+    out = torch.empty(1, device=p.device, dtype=torch.float64)
+    _check(load().lm_jp_sqnorm(cache.handle, _ptr(p), _ptr(out), _stream()), "lm_jp_sqnorm")
     return out
 
 

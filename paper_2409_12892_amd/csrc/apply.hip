@@ -432,7 +432,7 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
             s_u[0][tid] = u;
             if (valid) {
                 sq = (double)u.x * (double)u.x + (double)u.y * (double)u.y + (double)u.z * (double)u.z;
-                if (MODE == MODE_J) {
+                if (MODE == MODE_J && a.uout) {
                     a.uout[ib] = u.x;
                     a.uout[ib + HW] = u.y;
                     a.uout[ib + 2 * HW] = u.z;

@@ -733,6 +733,19 @@ lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) 
     return LM_OK;
 }
 
+lm_status lm_jp_sqnorm(const lm_cache* c, const float* p, double* out, void* stream) {
+    LM_CHECK(c && p && out, LM_ERR_INVALID_ARG, "lm_jp_sqnorm: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    lm_cache* cm = const_cast<lm_cache*>(c);
+    lm::ApplyBatch B = batch_of(&cm, 1);
+    B.a[0].p = p;
+    B.a[0].uout = nullptr;   // the J half's per-tile squared norms only
+    { LM_PROF("tangent", S(stream)); LM_HIP(lm::launch_tangent(B, S(stream))); }
+    { LM_PROF("apply_tile_J", S(stream)); LM_HIP(lm::launch_apply_tile(1, B, S(stream))); }
+    LM_HIP(lm::reduce_f64(c->jp_part.as<double>(), c->n_tiles, out, S(stream)));
+    return LM_OK;
+}
+
 lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream) {
     LM_CHECK(c && u && g, LM_ERR_INVALID_ARG, "lm_apply_JT: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");

@@ -107,7 +107,7 @@ class LMSolver:
         self.delta = deltas[0]
         self.comb = B.lm_combine_subsets([self.delta], [self.M], out=self.comb)
         d = self.comb
-        _, jd = B.lm_apply_JtJ(self.cache, d, want_jp_sqnorm=True)
+        jd = B.lm_jp_sqnorm(self.cache, d)
         E0 = float(fsq.item())
         dTb = float(torch.dot(d.reshape(-1).double(), b.reshape(-1).double()).item())
         Jd2 = float(jd.item())

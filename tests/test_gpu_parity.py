@@ -177,6 +177,9 @@ def test_apply_JtJ_fused_with_damping(prob, gpu, report):
     assert rel(g.cpu().numpy(), ref) < 1e-5
     Jp = prob["J"].apply_J(p.astype(np.float64))
     assert float(jp.item()) == pytest.approx(float(Jp @ Jp), rel=1e-5)
+    # the J-only entry point gives the same norm (same tile partials, same order)
+    jp2 = gpu["B"].lm_jp_sqnorm(gpu["cache"], torch.from_numpy(p).cuda())
+    assert float(jp2.item()) == float(jp.item())
 
 
 def test_pcg_direction(prob, gpu, report):
