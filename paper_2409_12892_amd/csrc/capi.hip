@@ -418,9 +418,15 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(c->pT.ensure(wb * c->pair_stride));
     LM_HIP(c->pD.ensure(wb * 3 * c->pair_stride));
     LM_HIP(c->ppix.ensure(c->pair_stride));
-    LM_HIP(hipMemsetAsync(c->pT.p, 0, wb * c->pair_stride, s));
-    LM_HIP(hipMemsetAsync(c->pD.p, 0, wb * 3 * c->pair_stride, s));
-    LM_HIP(hipMemsetAsync(c->ppix.p, 0, c->pair_stride, s));
+    // the fill pass writes every slot of every segment (pairs and padding);
+    // only the slots past the last segment are cleared here
+    if (c->pair_stride > c->n_slots) {
+        const size_t tail = (size_t)(c->pair_stride - c->n_slots);
+        LM_HIP(hipMemsetAsync((char*)c->pT.p + wb * c->n_slots, 0, wb * tail, s));
+        for (int ch = 0; ch < 3; ++ch)
+            LM_HIP(hipMemsetAsync((char*)c->pD.p + wb * (ch * c->pair_stride + c->n_slots), 0, wb * tail, s));
+        LM_HIP(hipMemsetAsync(c->ppix.as<uint8_t>() + c->n_slots, 0, tail, s));
+    }
     LM_HIP(c->run_seg.ensure(sizeof(uint32_t) * (c->pair_stride / 8)));
     LM_HIP(c->seg_gv.ensure(sizeof(uint32_t) * nseg_a));
     LM_HIP(c->seg_loc.ensure(sizeof(uint32_t) * nseg_a));

@@ -143,6 +143,18 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     const int64_t r0 = (pair_base + eoff) >> 3;
                     const int64_t r1 = min((int64_t)(pair_base + eoff + padded), pair_end) >> 3;
                     for (int64_t r = r0; r < r1; ++r) a.run_seg[r] = (uint32_t)s;
+                    // the segment's padding slots: a zero T word marks no pair
+                    typename S::word* zT = (typename S::word*)a.pT;
+                    typename S::word* zD = (typename S::word*)a.pD;
+                    for (uint32_t q = tot; q < padded; ++q) {
+                        const int64_t slot = pair_base + eoff + q;
+                        if (slot >= pair_end) break;
+                        zT[slot] = 0;
+                        zD[slot] = 0;
+                        zD[a.pair_stride + slot] = 0;
+                        zD[2 * a.pair_stride + slot] = 0;
+                        a.ppix[slot] = 0;
+                    }
                 }
             }
             __syncthreads();
