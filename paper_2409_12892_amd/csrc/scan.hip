@@ -9,8 +9,12 @@ namespace {
 
 constexpr int kScanItems = 16;                       // items per thread
 constexpr int kScanTile = kBlock * kScanItems;       // 4096 items per workgroup
-constexpr int kRadixItems = 16;
-constexpr int kRadixTile = kBlock * kRadixItems;
+// Items per thread of a radix pass: a block ranks kBlock * items keys in LDS
+// (more items make longer digit runs but fewer resident blocks; 32 items per
+// thread measured slower for both key widths).
+template <typename KeyT> constexpr int radix_items() { return 16; }
+template <typename KeyT> constexpr int radix_tile() { return kBlock * radix_items<KeyT>(); }
+constexpr int kRadixTileMin = kBlock * 16;   // the smallest tile: sizes the scratch
 
 __device__ __forceinline__ uint64_t lanemask_lt() {
     return (1ull << __lane_id()) - 1ull;
@@ -132,9 +136,9 @@ __global__ void k_radix_hist(const KeyT* __restrict__ keys, int64_t n, int shift
     __shared__ uint32_t h[NDIG];
     for (int d = threadIdx.x; d < NDIG; d += kBlock) h[d] = 0;
     __syncthreads();
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
+    const int64_t base = (int64_t)blockIdx.x * radix_tile<KeyT>();
 #pragma unroll 4
-    for (int i = 0; i < kRadixItems; ++i) {
+    for (int i = 0; i < radix_items<KeyT>(); ++i) {
         int64_t idx = base + (int64_t)i * kBlock + threadIdx.x;
         if (idx < n) atomicAdd(&h[(keys[idx] >> shift) & (NDIG - 1)], 1u);
     }
@@ -142,7 +146,7 @@ __global__ void k_radix_hist(const KeyT* __restrict__ keys, int64_t n, int shift
     for (int d = threadIdx.x; d < NDIG; d += kBlock) hist[(int64_t)d * nb + blockIdx.x] = h[d];   // digit-major
 }
 
-// The block's kRadixTile items are first ranked by digit in LDS (stable:
+// The block's radix_tile items are first ranked by digit in LDS (stable:
 // rounds in order, waves in order, lanes in order), then written out in that
 // order, so consecutive threads write consecutive addresses of a digit's run.
 template <typename KeyT, int BITS>
@@ -156,12 +160,14 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const KeyT* __restrict
     __shared__ uint32_t wcnt[NW][NDIG];
     __shared__ uint32_t lstart[NDIG];    // first local slot of each digit in the block
     __shared__ uint32_t lrun[NDIG];      // items of each digit placed so far
-    __shared__ KeyT s_key[kRadixTile];
-    __shared__ uint32_t s_val[kRadixTile];
+    __shared__ uint64_t s_goff[NDIG];    // global position of the block's first item of each digit
+    constexpr int kTile = radix_tile<KeyT>();
+    __shared__ KeyT s_key[kTile];
+    __shared__ uint32_t s_val[kTile];
     const int tid = threadIdx.x;
     const int wid = tid / kWave;
-    const int64_t base = (int64_t)blockIdx.x * kRadixTile;
-    const int nloc = (int)(n - base < kRadixTile ? n - base : kRadixTile);
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int nloc = (int)(n - base < kTile ? n - base : kTile);
     // the block's count of digit d is the step of the digit-major exclusive
     // scan at (d, block) (its entry past the end holds the total); the local
     // starts are an exclusive scan of those counts over the digits
@@ -171,7 +177,9 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const KeyT* __restrict
 #pragma unroll
         for (int q = 0; q < DPT; ++q) {
             const int64_t at = (int64_t)(tid * DPT + q) * nb + blockIdx.x;
-            cnt[q] = (uint32_t)(offs[at + 1] - offs[at]);
+            const uint64_t o0 = offs[at];
+            s_goff[tid * DPT + q] = o0;
+            cnt[q] = (uint32_t)(offs[at + 1] - o0);
             mine += cnt[q];
             for (int w = 0; w < NW; ++w) wcnt[w][tid * DPT + q] = 0;
         }
@@ -197,7 +205,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const KeyT* __restrict
         }
         __syncthreads();
     }
-    for (int r = 0; r < kRadixItems; ++r) {
+    for (int r = 0; r < radix_items<KeyT>(); ++r) {
         const int li = r * kBlock + tid;
         const bool live = li < nloc;
         KeyT k = live ? keys[base + li] : (KeyT)0;
@@ -243,7 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const KeyT* __restrict
     for (int i = tid; i < nloc; i += kBlock) {
         const KeyT k = s_key[i];
         const uint32_t d = (uint32_t)((k >> shift) & (NDIG - 1));
-        const uint64_t pos = offs[(int64_t)d * nb + blockIdx.x] + (uint64_t)(i - (int)lstart[d]);
+        const uint64_t pos = s_goff[d] + (uint64_t)(i - (int)lstart[d]);
         okeys[pos] = k;
         ovals[pos] = s_val[i];
     }
@@ -302,7 +310,7 @@ constexpr int kMaxDigitBits = 9;
 constexpr int kMaxDigits = 1 << kMaxDigitBits;
 
 size_t radix_tmp_bytes(int64_t n) {
-    int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    int64_t nb = (n + kRadixTileMin - 1) / kRadixTileMin;
     size_t hist = (size_t)kMaxDigits * nb * sizeof(uint32_t);
     size_t offs = (size_t)(kMaxDigits * nb + 1) * sizeof(uint64_t);
     size_t scan = scan_tmp_bytes(kMaxDigits * nb);
@@ -315,7 +323,7 @@ hipError_t radix_sort_impl(KeyT* keys, uint32_t* vals, KeyT* keys_alt, uint32_t*
                            hipStream_t s) {
     *result_in_alt = false;
     if (n <= 1) return hipSuccess;
-    int64_t nb = (n + kRadixTile - 1) / kRadixTile;
+    int64_t nb = (n + radix_tile<KeyT>() - 1) / radix_tile<KeyT>();
     if (radix_tmp_bytes(n) > tmp_bytes) return hipErrorInvalidValue;
     char* t = (char*)tmp;
     uint32_t* hist = (uint32_t*)t;
