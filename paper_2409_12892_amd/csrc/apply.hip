@@ -680,13 +680,28 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
     double pg = 0.0;
     if (g < c.N) {
         const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
+        const uint32_t n = e - b;
         for (int j = 0; j < P; ++j) {
+            // the first four records' loads are issued together (most
+            // Gaussians have at most four); the sums keep record order
             double v = 0.0;
             if (j < 11) {
-                for (uint32_t gv = b; gv < e; ++gv) v += geo_in[(int64_t)j * ls + gv];
+                const double* row = geo_in + (int64_t)j * ls + b;
+                double r[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = (uint32_t)q < n ? row[q] : 0.0;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) v += r[q];
+                for (uint32_t q = 4; q < n; ++q) v += row[q];
             } else {
+                const float* row = sh_in + (int64_t)(j - 11) * ls + b;
+                float r[4];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) r[q] = (uint32_t)q < n ? row[q] : 0.0f;
                 float f = 0.0f;
-                for (uint32_t gv = b; gv < e; ++gv) f += sh_in[(int64_t)(j - 11) * ls + gv];
+#pragma unroll
+                for (int q = 0; q < 4; ++q) f += r[q];
+                for (uint32_t q = 4; q < n; ++q) f += row[q];
                 v = (double)f;
             }
             double val = v * scale;
