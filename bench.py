@@ -64,9 +64,10 @@ def apply_tile_alg_bytes(info: dict) -> int:
     return int(info["n_pairs"] * (4 * wb + 1) + info["n_segments"] * (24 + 8 + 36 + 36) + info["n_tiles"] * 28)
 
 
-def read_traffic(alg_bytes: int):
+def read_traffic(alg_bytes: int, tile: str):
     """HBM traffic per launch from the committed rocprofv3 counter summary, or
-    None when it is absent or was taken on a different kernel source."""
+    None when it is absent or was taken on a different kernel source or tile
+    shape."""
     if not os.path.exists(TRAFFIC_FILE):
         return None
     kv = {}
@@ -75,7 +76,7 @@ def read_traffic(alg_bytes: int):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
-    if kv.get("apply_src_sha256") != src:
+    if kv.get("apply_src_sha256") != src or kv.get("tile", tile) != tile:
         return None
     try:
         return int(float(kv["traffic_bytes_per_launch"]))
@@ -86,7 +87,7 @@ def read_traffic(alg_bytes: int):
 COPY_BYTES = 256 * 1024 * 1024
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str) -> dict:
+def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, tile: str = "") -> dict:
     """HBM traffic of the fused J^T J tile pass from two rocprofv3 --pmc runs
     of `bench.py --copy-calibration` (one with FETCH_SIZE, one with
     WRITE_SIZE).  Each counter is summed over its instances per dispatch and
@@ -132,6 +133,8 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str) -
             f.write(f"# {tag}: {r['kib_per_launch']:.1f} KiB counted per launch over {r['launches']} launches; "
                     f"256 MiB copy counted {r['copy_kib']:.1f} KiB -> scale {r['scale']:.3f}\n")
         f.write(f"apply_src_sha256={src}\n")
+        if tile:
+            f.write(f"tile={tile}\n")
         f.write(f"fetch_bytes_per_launch={res['fetch']['bytes_per_launch']:.0f}\n")
         f.write(f"write_bytes_per_launch={res['write']['bytes_per_launch']:.0f}\n")
         f.write(f"traffic_bytes_per_launch={total:.0f}\n")
@@ -401,7 +404,8 @@ def main() -> int:
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--config", default="paper")
     ap.add_argument("--cache-dtype", default="f32", choices=["f32", "bf16", "f16"])
-    ap.add_argument("--tile", default="16x16")
+    ap.add_argument("--tile", default="auto",
+                    help="tile shape WxH, or auto: lm_autotune_tile on the workload before the timed region")
     ap.add_argument("--N", type=int, default=None, help="override the number of Gaussians")
     ap.add_argument("--views", type=int, default=None, help="override the views of the subset")
     ap.add_argument("--cpu-baseline", type=int, default=1)
@@ -411,9 +415,11 @@ def main() -> int:
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
+    ap.add_argument("--pmc-tile", default="", help="tile shape of the counted runs, recorded in the summary")
     args = ap.parse_args()
     if args.summarize_pmc:
-        res = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_FILE, args.pmc_command)
+        res = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_FILE, args.pmc_command,
+                            args.pmc_tile)
         print(json.dumps(res))
         return 0
 
@@ -439,7 +445,6 @@ def main() -> int:
     if args.config == "learned":
         print(json.dumps(bench_learned(args, B, sg, torch)), flush=True)
         return 0
-    tw, th = (int(v) for v in args.tile.split("x"))
     cfg = dict(sg.CONFIGS[args.config])
     subsets = cfg["subsets"][:1]
     if args.views is not None:
@@ -452,12 +457,22 @@ def main() -> int:
     x = torch.from_numpy(scene.x).to(dev)
     x_star = torch.from_numpy(d["x_star"]).to(dev)
     noise = torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev)
-    target = B.lm_render(x_star, scene.sh_degree, cams, tile=(tw, th))
+    target = B.lm_render(x_star, scene.sh_degree, cams)      # targets: 16x16 binning whatever the tile
     target.add_(noise)
     del x_star, noise
     torch.cuda.synchronize()
     lam, n_iters = float(cfg["lam"]), int(cfg["n_iters"])
     log(f"inputs resident: N={scene.N} P={scene.P} views={V} {W}x{H}")
+    tile_scores = None
+    if args.tile == "auto":
+        (tw, th), sc_ = B.lm_autotune_tile(x, scene.sh_degree, cams, target, cache_dtype=args.cache_dtype,
+                                          n_products=n_iters + 2)
+        tile_scores = [dict(tile=f"{c['tile'][0]}x{c['tile'][1]}", build_ms=round(c["build_ms"], 2),
+                            apply_ms=round(c["apply_ms"], 3)) for c in sc_]
+        log(f"autotuned tile {tw}x{th}: " + ", ".join(f"{c['tile']} {c['build_ms']:.0f}/{c['apply_ms']:.1f} ms"
+                                                       for c in tile_scores))
+    else:
+        tw, th = (int(v) for v in args.tile.split("x"))
 
     from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
     solver = LMSolver(x, scene.sh_degree, cams, target,
@@ -496,7 +511,7 @@ def main() -> int:
     apply_ms = tot_ms / max(launches, 1)
     alg = apply_tile_alg_bytes(info)
     achieved = alg / (apply_ms * 1e-3) / 1e9
-    traffic = read_traffic(alg)
+    traffic = read_traffic(alg, f"{tw}x{th}")
     full_apply_ms = sum(prof.get(k, (0, 0.0))[1] for k in ("tangent", "apply_tile_JtJ", "chain", "pcg_vector")) \
         / max(launches, 1)
     log(f"steps done: {ms_per_step:.1f} ms/step, apply tile pass {apply_ms:.3f} ms, {achieved:.0f} GB/s")
@@ -517,7 +532,8 @@ def main() -> int:
         "config": {
             "workload": (f"LM iteration, plain method: {scene.N} Gaussians SH{scene.sh_degree}, {V} views "
                          f"{W}x{H} in one subset, {args.cache_dtype} cache, {n_iters} Jacobi-PCG iterations"),
-            "N": scene.N, "P": scene.P, "views": V, "width": W, "height": H, "tile": args.tile,
+            "N": scene.N, "P": scene.P, "views": V, "width": W, "height": H, "tile": f"{tw}x{th}",
+            "tile_autotune": tile_scores,
             "cache_dtype": args.cache_dtype, "pcg_iters": n_iters, "lambda": lam,
             "diag_floor": solver.cfg.diag_floor, "line_search_views": int(len(solver.ls_idx)),
         },
@@ -545,7 +561,7 @@ def main() -> int:
     if args.cpu_baseline:
         log("cpu baseline: oracle on a bounded crop of view 0")
         try:
-            out["cpu_baseline"] = cpu_baseline(scene, cams, info["n_pairs"], tile=tw)
+            out["cpu_baseline"] = cpu_baseline(scene, cams, info["n_pairs"], tile=16)
         except Exception as e:  # the GPU result stands even if the CPU sample fails
             out["cpu_baseline"] = {"value": None, "error": repr(e)}
         log("cpu baseline done")
