@@ -55,7 +55,17 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     const int64_t lt = t - cam.tile_base;
     const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
-    const int lx = tid % a.TW, ly = tid / a.TW;
+    // each wave takes an 8x8 block of the tile (when the tile is at least
+    // 8 pixels each way): compact waves share splats and saturate together
+    int lx, ly;
+    if (a.TW >= 8 && a.TH >= 8) {
+        const int blk = tid >> 6, bpr = a.TW >> 3;
+        lx = ((blk % bpr) << 3) + (tid & 7);
+        ly = ((blk / bpr) << 3) + ((tid >> 3) & 7);
+    } else {
+        lx = tid % a.TW;
+        ly = tid / a.TW;
+    }
     const int px = tx * a.TW + lx, py = ty * a.TH + ly;
     const bool valid = tid < a.TW * a.TH && px < cam.W && py < cam.H;
     const double pxc = px + 0.5, pyc = py + 0.5;
@@ -208,7 +218,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                         pD[slot] = S::enc(D0);
                         pD[a.pair_stride + slot] = S::enc(D1);
                         pD[2 * a.pair_stride + slot] = S::enc(D2);
-                        a.ppix[slot] = (uint8_t)tid;
+                        a.ppix[slot] = (uint8_t)(ly * a.TW + lx);   // tile-linear pixel index
                     }
                 }
                 T = Tn;
