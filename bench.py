@@ -87,7 +87,8 @@ def read_traffic(alg_bytes: int, tile: str):
 COPY_BYTES = 256 * 1024 * 1024
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, tile: str = "") -> dict:
+def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, tile: str = "",
+                  last: int = 9) -> dict:
     """HBM traffic of the fused J^T J tile pass from two rocprofv3 --pmc runs
     of `bench.py --copy-calibration` (one with FETCH_SIZE, one with
     WRITE_SIZE).  Each counter is summed over its instances per dispatch and
@@ -115,7 +116,9 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, t
     res = {}
     for tag, d, ctr in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
         disp = per_dispatch(d, ctr)
-        a, na = mean([v for (_, name), v in disp if "k_apply_tile<3," in name])
+        # the timed step's products: the kernel's last `last` dispatches (the
+        # autotuner's candidate shapes come before them)
+        a, na = mean([v for (_, name), v in disp if "k_apply_tile<3," in name][-last:])
         # the calibration copies are the run's last three device copies
         cp, nc = mean([v for (_, name), v in disp if "copyBuffer" in name][-3:])
         if a is None or cp is None:
