@@ -96,6 +96,25 @@ typedef struct lm_options {
 
 typedef struct lm_cache lm_cache;   /* opaque, library-owned */
 
+/* Device memory of caches and workspaces.  By default the library calls
+ * hipMalloc / hipFree.  With an allocator installed, every device buffer
+ * the library needs comes from alloc(user, bytes, stream) - stream being
+ * the hipStream_t of the call that needs it, on which the buffer's work is
+ * ordered - and goes back through free(user, ptr, stream) of the same
+ * allocator on the same stream, at the latest in lm_cache_destroy (after a
+ * device synchronisation).  alloc returns NULL on failure (the call then
+ * fails with LM_ERR_HIP).  The allocator is library-wide; a buffer is always
+ * returned to the allocator that supplied it, so it may be changed between
+ * calls.  (lm_autotune_tile's two scratch vectors use hipMalloc.) */
+typedef struct lm_allocator {
+    void* user;
+    void* (*alloc)(void* user, size_t bytes, void* stream);
+    void (*free)(void* user, void* ptr, void* stream);
+} lm_allocator;
+
+/* Installs a (copy of the) allocator; NULL restores hipMalloc / hipFree. */
+lm_status lm_set_allocator(const lm_allocator* allocator);
+
 typedef struct lm_cache_info {
     int64_t N, n_keys, n_pairs, n_segments, n_gv, n_pixels, n_tiles;
     int64_t n_pair_slots;    /* pair storage incl. the zero padding of each segment

@@ -35,7 +35,7 @@ EXPORTED_SYMBOLS = (
     "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
     "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile", "lm_pair_coverage", "lm_block_jacobi",
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
-    "lm_jp_sqnorm",
+    "lm_jp_sqnorm", "lm_set_allocator",
 )
 
 MLP_FEATURES, MLP_HIDDEN, MLP_MAX_OUT, MLP_PARAMS = 8, 64, 64, 8896
@@ -228,6 +228,42 @@ def lm_apply_J(cache: Cache, p, out=None, n_residuals: int | None = None):
         out = torch.empty(n, device=p.device, dtype=torch.float32)
     _check(load().lm_apply_J(cache.handle, _ptr(p), _ptr(out), _stream()), "lm_apply_J")
     return out
+
+
+class LmAllocator(ctypes.Structure):
+    _fields_ = [("user", c_void_p),
+                ("alloc", ctypes.CFUNCTYPE(c_void_p, c_void_p, ctypes.c_size_t, c_void_p)),
+                ("free", ctypes.CFUNCTYPE(None, c_void_p, c_void_p, c_void_p))]
+
+
+_torch_allocator = None
+
+
+def use_torch_allocator(on: bool = True) -> None:
+    """Route the library's device memory through PyTorch's caching allocator
+    (torch.cuda.caching_allocator_alloc / _delete on the call's stream), or
+    back to hipMalloc / hipFree."""
+    global _torch_allocator
+    if not on:
+        _check(load().lm_set_allocator(None), "lm_set_allocator")
+        return
+    import torch
+
+    def _alloc(user, nbytes, stream):
+        try:
+            return torch.cuda.caching_allocator_alloc(int(nbytes), torch.cuda.current_device(), stream or 0)
+        except Exception:   # an exception cannot cross the C boundary: report NULL
+            return None
+
+    def _free(user, ptr, stream):
+        try:
+            torch.cuda.caching_allocator_delete(ptr)
+        except Exception:
+            pass
+
+    a = LmAllocator(None, LmAllocator._fields_[1][1](_alloc), LmAllocator._fields_[2][1](_free))
+    _torch_allocator = a        # the callbacks must outlive every buffer they allocated
+    _check(load().lm_set_allocator(byref(a)), "lm_set_allocator")
 
 
 def lm_jp_sqnorm(cache: Cache, p):

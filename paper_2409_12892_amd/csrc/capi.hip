@@ -14,6 +14,18 @@ namespace lm {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
+// Device memory: hipMalloc/hipFree unless the caller installed an
+// allocator (lm_set_allocator).  Allocations are stream-ordered on the
+// stream of the entry point that made them, which each entry point binds for
+// the duration of the call.
+static lm_allocator g_alloc{};
+static thread_local hipStream_t g_alloc_stream = nullptr;
+struct StreamScope {
+    hipStream_t prev;
+    explicit StreamScope(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
+    ~StreamScope() { g_alloc_stream = prev; }
+};
+
 namespace prof {
 // Event pairs recorded around kernel groups while profiling is enabled.
 struct Rec {
@@ -61,29 +73,40 @@ struct Scope {
 
 namespace {
 
-// Device buffer that only grows; reused across rebuilds of one cache.
+// Device buffer that only grows; reused across rebuilds of one cache.  It
+// is returned through the allocator that supplied it, on the stream it was
+// allocated on.
 struct DevBuf {
     void* p = nullptr;
     size_t cap = 0;
+    lm_allocator al{};
+    hipStream_t st = nullptr;
     hipError_t ensure(size_t bytes) {
         if (bytes <= cap && p) return hipSuccess;
-        if (p) {
-            hipError_t e = hipFree(p);
-            p = nullptr;
-            cap = 0;
-            if (e != hipSuccess) return e;
+        release();
+        const size_t want = bytes + bytes / 16 + 256;
+        const lm_allocator g = lm::g_alloc;
+        const hipStream_t s = lm::g_alloc_stream;
+        if (g.alloc) {
+            p = g.alloc(g.user, want, (void*)s);
+            if (!p) return hipErrorOutOfMemory;
+        } else {
+            hipError_t e = hipMalloc(&p, want);
+            if (e != hipSuccess) {
+                p = nullptr;
+                return e;
+            }
         }
-        size_t want = bytes + bytes / 16 + 256;
-        hipError_t e = hipMalloc(&p, want);
-        if (e != hipSuccess) {
-            p = nullptr;
-            return e;
-        }
+        al = g;
+        st = s;
         cap = want;
         return hipSuccess;
     }
     void release() {
-        if (p) (void)hipFree(p);
+        if (p) {
+            if (al.alloc) al.free(al.user, p, (void*)st);
+            else (void)hipFree(p);
+        }
         p = nullptr;
         cap = 0;
     }
@@ -553,6 +576,7 @@ const char* lm_last_error(void) { return lm::g_last_error.c_str(); }
 
 lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
                          const lm_options* opts, void* stream, lm_cache** inout, float* b, double* F_sqnorm) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(inout, LM_ERR_INVALID_ARG, "lm_build_cache: inout is NULL");
     LM_CHECK(target, LM_ERR_INVALID_ARG, "lm_build_cache: target is NULL");
     lm::set_error("");
@@ -649,6 +673,7 @@ static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
 }
 
 lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && M, LM_ERR_INVALID_ARG, "lm_jacobi_diag: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -660,6 +685,7 @@ lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
 }
 
 lm_status lm_pair_coverage(const lm_cache* c, float* coverage, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && coverage, LM_ERR_INVALID_ARG, "lm_pair_coverage: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -670,6 +696,7 @@ lm_status lm_pair_coverage(const lm_cache* c, float* coverage, void* stream) {
 }
 
 lm_status lm_block_jacobi(const lm_cache* c, const int64_t* gaussians, int64_t n, float* blocks, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && (n == 0 || (gaussians && blocks)) && n >= 0, LM_ERR_INVALID_ARG, "lm_block_jacobi: bad argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -683,6 +710,7 @@ lm_status lm_block_jacobi(const lm_cache* c, const int64_t* gaussians, int64_t n
 
 lm_status lm_precond_targets(const lm_cache* c, float lambda, float diag_floor, float shrink, float* t, float* mask,
                              void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && t && mask, LM_ERR_INVALID_ARG, "lm_precond_targets: NULL argument");
     LM_CHECK(lambda >= 0.0f && diag_floor >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
     LM_CHECK(shrink >= 0.0f && shrink <= 1.0f, LM_ERR_INVALID_ARG, "shrink must be in [0, 1]");
@@ -701,6 +729,7 @@ lm_status lm_precond_targets(const lm_cache* c, float lambda, float diag_floor, 
 }
 
 lm_status lm_precond_features(const lm_cache* c, const float* x, const float* M, float* feat, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && x && M && feat, LM_ERR_INVALID_ARG, "lm_precond_features: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -718,6 +747,7 @@ lm_status lm_precond_features(const lm_cache* c, const float* x, const float* M,
 
 lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const float* M, float* g,
                        double* Jp_sqnorm, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && p && g, LM_ERR_INVALID_ARG, "lm_apply_JtJ: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -728,6 +758,7 @@ lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const fl
 }
 
 lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && p && u, LM_ERR_INVALID_ARG, "lm_apply_J: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -740,6 +771,7 @@ lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) 
 }
 
 lm_status lm_jp_sqnorm(const lm_cache* c, const float* p, double* out, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && p && out, LM_ERR_INVALID_ARG, "lm_jp_sqnorm: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -753,6 +785,7 @@ lm_status lm_jp_sqnorm(const lm_cache* c, const float* p, double* out, void* str
 }
 
 lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && u && g, LM_ERR_INVALID_ARG, "lm_apply_JT: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     return apply_JT_internal(c, u, 1.0f, g, S(stream));
@@ -761,6 +794,7 @@ lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream)
 lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
                        float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
                        const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(caches && b && M && delta && n_b > 0, LM_ERR_INVALID_ARG, "lm_pcg_solve: NULL argument");
     LM_CHECK(n_b <= lm::kMaxBatch, LM_ERR_INVALID_ARG, "lm_pcg_solve: at most 8 subsets per call");
     LM_CHECK(n_iters >= 0 && n_iters < LM_PCG_MAX_HISTORY, LM_ERR_INVALID_ARG, "n_iters out of range");
@@ -880,6 +914,7 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
 lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
                            int32_t cache_dtype, int32_t n_products, void* stream, int32_t* tile_w, int32_t* tile_h,
                            lm_tile_score* scores, int32_t max_scores, int32_t* n_scores) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(scene && cams && target && tile_w && tile_h, LM_ERR_INVALID_ARG, "lm_autotune_tile: NULL argument");
     LM_CHECK(n_products >= 0, LM_ERR_INVALID_ARG, "lm_autotune_tile: n_products must be >= 0");
     static const int32_t cand[][2] = {{16, 16}, {32, 8}, {8, 32}, {16, 8}, {8, 16}, {8, 8}};
@@ -946,6 +981,12 @@ lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t
     return LM_OK;
 }
 
+lm_status lm_set_allocator(const lm_allocator* a) {
+    LM_CHECK(!a || (a->alloc && a->free), LM_ERR_INVALID_ARG, "lm_set_allocator: alloc and free are both required");
+    lm::g_alloc = a ? *a : lm_allocator{};
+    return LM_OK;
+}
+
 lm_status lm_pcg_use_graph(int32_t mode) {
     LM_CHECK(mode >= 0 && mode <= 2, LM_ERR_INVALID_ARG, "lm_pcg_use_graph: mode must be 0, 1 or 2");
     g_pcg_graph = mode;
@@ -993,6 +1034,7 @@ int32_t lm_profile_read(lm_profile_entry* out, int32_t max_entries) {
 
 lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float* const* M, int64_t n, float* out,
                              void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(delta && M && out && n_b > 0 && n_b <= 16 && n >= 0, LM_ERR_INVALID_ARG,
              "lm_combine_subsets: bad arguments (1 <= n_b <= 16)");
     for (int i = 0; i < n_b; ++i) LM_CHECK(delta[i] && M[i], LM_ERR_INVALID_ARG, "lm_combine_subsets: NULL entry");
@@ -1003,6 +1045,7 @@ lm_status lm_combine_subsets(int32_t n_b, const float* const* delta, const float
 
 lm_status lm_mlp_forward(const float* w, const float* feat, int64_t n, int32_t p_out, float* s, float* scale,
                          uint32_t* n_fallback, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(w && (n == 0 || feat) && n >= 0, LM_ERR_INVALID_ARG, "lm_mlp_forward: bad argument");
     LM_CHECK(p_out >= 1 && p_out <= LM_MLP_MAX_OUT, LM_ERR_INVALID_ARG, "lm_mlp_forward: p_out must be 1..64");
     LM_CHECK(n < ((int64_t)1 << 40), LM_ERR_CAPACITY, "lm_mlp_forward: n too large");
@@ -1020,6 +1063,7 @@ size_t lm_mlp_workspace_bytes(void) {
 lm_status lm_mlp_train_step(float* w, float* adam_m, float* adam_v, int32_t step, float lr, const float* feat,
                             const float* target, const float* mask, int64_t n, int32_t p_out, float* grad,
                             double* loss, void* workspace, size_t workspace_bytes, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(w && (n == 0 || (feat && target && mask)) && n >= 0, LM_ERR_INVALID_ARG,
              "lm_mlp_train_step: bad argument");
     LM_CHECK(p_out >= 1 && p_out <= LM_MLP_MAX_OUT, LM_ERR_INVALID_ARG, "lm_mlp_train_step: p_out must be 1..64");
@@ -1040,6 +1084,7 @@ lm_status lm_mlp_train_step(float* w, float* adam_m, float* adam_v, int32_t step
 
 lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, const lm_options* opts, float* image,
                     void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(image, LM_ERR_INVALID_ARG, "lm_render: image is NULL");
     lm_cache* c = new (std::nothrow) lm_cache();
     LM_CHECK(c, LM_ERR_HIP, "out of host memory");
@@ -1061,6 +1106,7 @@ lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, con
 
 lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
                              const lm_options* opts, void* stream, lm_cache** workspace, double* F_sqnorm) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(workspace && target && F_sqnorm, LM_ERR_INVALID_ARG, "lm_residual_sqnorm: NULL argument");
     lm_cache* c = *workspace;
     bool created = false;
@@ -1089,6 +1135,7 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
 }
 
 lm_status lm_cache_view_sqnorm(const lm_cache* c, double* per_view, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && per_view, LM_ERR_INVALID_ARG, "lm_cache_view_sqnorm: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     LM_HIP(lm::view_sum_f64(c->cams.as<lm::CamDev>(), c->V, c->fsq_part.as<double>(), per_view, S(stream)));
@@ -1177,6 +1224,7 @@ hipError_t live_slots(const lm_cache* c, std::vector<int64_t>& live, hipStream_t
 }  // namespace
 
 extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host_dst, int64_t bytes, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && host_dst, LM_ERR_INVALID_ARG, "lm_cache_export: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     const int64_t need = lm_cache_export_size(c, what);
