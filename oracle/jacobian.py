@@ -180,15 +180,42 @@ class Jacobian:
     def apply_JT(self, u: np.ndarray) -> np.ndarray:
         return self.JT @ np.asarray(u, np.float64).ravel()
 
-    def apply_JtJ(self, p: np.ndarray, lam: float = 0.0, M: np.ndarray | None = None) -> np.ndarray:
+    def apply_JtJ(self, p: np.ndarray, lam: float = 0.0, M: np.ndarray | None = None,
+                  w: np.ndarray | None = None) -> np.ndarray:
+        """J^T J p (+ lam M p).  With per-residual weights w (supplement A.5,
+        eq. apply-jtj-simplified-vec-vec: w = (dr/dc)^2 of each pixel and
+        channel) the product is J^T (w . J p), J being the colour Jacobian."""
         p = np.asarray(p, np.float64).ravel()
-        g = self.apply_JT(self.apply_J(p))
+        u = self.apply_J(p)
+        if w is not None:
+            u = np.asarray(w, np.float64).ravel() * u
+        g = self.apply_JT(u)
         if M is not None:
             g = g + lam * np.asarray(M, np.float64).ravel() * p
         return g
 
-    def diag_JtJ(self) -> np.ndarray:
-        return np.asarray(self.J.multiply(self.J).sum(axis=0)).ravel()
+    def diag_JtJ(self, w: np.ndarray | None = None) -> np.ndarray:
+        """diag(J^T J), or diag(J^T W J) = sum_i w_i J_ij^2 with weights."""
+        sq = self.J.multiply(self.J)
+        if w is None:
+            return np.asarray(sq.sum(axis=0)).ravel()
+        return np.asarray(sq.T @ np.asarray(w, np.float64).ravel()).ravel()
+
+    def Jp_sqnorm(self, p: np.ndarray, w: np.ndarray | None = None) -> float:
+        """||J p||^2, or sum_i w_i (J p)_i^2 with weights."""
+        u = self.apply_J(p)
+        return float(u @ u) if w is None else float(u @ (np.asarray(w, np.float64).ravel() * u))
+
+    def weighted(self, w: np.ndarray) -> "Jacobian":
+        """The Jacobian of the residuals r whose rows are sqrt(w_i) times the
+        colour Jacobian's (eq. res-sq-root-weights with |dr/dc| = sqrt(w))."""
+        out = object.__new__(Jacobian)
+        out.__dict__.update(self.__dict__)
+        s = np.sqrt(np.asarray(w, np.float64).ravel())
+        out.J = sp.diags(s) @ self.J
+        out.J = out.J.tocsr()
+        out.JT = out.J.T.tocsr()
+        return out
 
     def b(self, targets: list[np.ndarray]) -> np.ndarray:
         return -self.apply_JT(self.residual(targets))
