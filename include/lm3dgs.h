@@ -152,7 +152,13 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
 lm_status lm_cache_destroy(lm_cache* cache);
 lm_status lm_cache_get_info(const lm_cache* cache, lm_cache_info* info);
 
-/* M = diag(J^T J) (paper eq. diag-jtj, kernel diagJTJ), dev float32 [P][N]. */
+/* M = diag(J^T J) (paper eq. diag-jtj, kernel diagJTJ), dev float32 [P][N].
+ * With residual weights set on the cache (lm_set_residual_weights,
+ * lm_cache_objective) every product below uses J^T W J in place of J^T J
+ * (supplement A.5, eq. apply-jtj-simplified-vec-vec): this diagonal, the
+ * J^T J half of lm_apply_JtJ and lm_pcg_solve, and the squared norms
+ * (sum w (J p)^2).  lm_apply_J and lm_apply_JT stay the plain colour
+ * Jacobian products. */
 lm_status lm_jacobi_diag(const lm_cache* cache, float* M, void* stream);
 
 /* g = J^T J p + lambda M p (Algorithm 1, the applyJ / applyJT pair plus the
@@ -171,6 +177,54 @@ lm_status lm_jp_sqnorm(const lm_cache* cache, const float* p, double* out, void*
 
 /* g = J^T u (eq. apply-jt), u dev float32 [V][3][H][W], g dev [P][N]. */
 lm_status lm_apply_JT(const lm_cache* cache, const float* u, float* g, void* stream);
+
+/* ---- the paper's objective (section 3.1 eq. sgd-loss, eq. gn-loss;
+ * supplement A.5) ----
+ * Per pixel and colour channel, residuals r1 = sqrt(lambda1 |c - C|) and
+ * r2 = sqrt(lambda2 (1 - SSIM(c, C))); E = sum r1^2 + r2^2.  SSIM per
+ * channel: 11 x 11 Gaussian window of standard deviation 1.5 (weights sum to
+ * 1, pixels outside the image are 0), C1 = 0.01^2, C2 = 0.03^2; its
+ * derivative goes to the window's centre pixel only (section 3.3).  The
+ * Gauss-Newton system needs two images: the colour-space gradient
+ * e = sum_t r_t dr_t/dc (b = -J^T e) and the residual weight
+ * w = sum_t (dr_t/dc)^2 = sum_t f_t'^2 / (4 max(f_t, eps)), f_t = r_t^2.
+ * LM_OBJ_L2 is the plain least-squares objective r = c - C (e = r, w = 1). */
+enum { LM_OBJ_L2 = 0, LM_OBJ_L1_SSIM = 1 };
+typedef struct lm_objective {
+    int32_t kind;            /* LM_OBJ_L2 or LM_OBJ_L1_SSIM                      */
+    float lambda1, lambda2;  /* 0.8 and 0.2 in the paper                         */
+    float eps;               /* floor of f_t in the weight's denominator, > 0    */
+} lm_objective;
+
+/* Terms of the objective for images already in device memory: image and
+ * target dev float32 [V][3][H][W] (view sizes from cams).  w and e (same
+ * layout) may be NULL; E (dev double, one value) is written.  Enqueued on
+ * the stream; *workspace as for lm_residual_sqnorm (NULL or a reusable
+ * handle; the call keeps its partial sums there).  Errors: NULL image,
+ * target, E or workspace, V < 1, an unknown kind, eps <= 0. */
+lm_status lm_objective_terms(const float* image, const float* target, const lm_camera* cams, int32_t V,
+                             const lm_objective* obj, float* w, float* e, double* E, void* stream,
+                             lm_cache** workspace);
+
+/* Set the cache's residual weights, dev float32 [V][3][H][W] of the cache's
+ * views (copied; the caller keeps ownership of w).  w == NULL returns to
+ * plain least squares (unit weights). */
+lm_status lm_set_residual_weights(lm_cache* cache, const float* w, void* stream);
+
+/* The objective at the point the cache was built at (its rendered image is
+ * the stored residual plus target, the same target as the build): sets the
+ * cache's residual weights (NULL weights for LM_OBJ_L2), writes
+ * b = -J^T e (dev float32 [P][N], may be NULL) and E (dev double, may be
+ * NULL).  With LM_OBJ_L2, b and E equal the build's b and ||F||^2. */
+lm_status lm_cache_objective(lm_cache* cache, const float* target, const lm_objective* obj, float* b,
+                             double* E, void* stream);
+
+/* The objective of a forward render (line search of the LM loop, eq.
+ * line-search): render the views at the scene's x and evaluate E against
+ * target (no cache fill).  *workspace as for lm_residual_sqnorm. */
+lm_status lm_objective_value(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                             const lm_options* opts, const lm_objective* obj, void* stream,
+                             lm_cache** workspace, double* E);
 
 /* Algorithm 1 for n_b image subsets (section 3.3 "Image Subsampling
  * Scheme": each subset solves its own normal equations).  All arrays are

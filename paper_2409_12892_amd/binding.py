@@ -35,13 +35,29 @@ EXPORTED_SYMBOLS = (
     "lm_cache_export_size", "lm_cache_export", "lm_profile_enable", "lm_profile_read", "lm_residual_sqnorm",
     "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile", "lm_pair_coverage", "lm_block_jacobi",
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
-    "lm_jp_sqnorm", "lm_set_allocator",
+    "lm_jp_sqnorm", "lm_set_allocator", "lm_objective_terms", "lm_set_residual_weights", "lm_cache_objective",
+    "lm_objective_value",
 )
+
+# objective kinds (include/lm3dgs.h): plain least squares, and the paper's
+# square-root L1 / SSIM residuals with lambda1 = 0.8, lambda2 = 0.2
+OBJ_L2, OBJ_L1_SSIM = 0, 1
+OBJ_LAMBDA1, OBJ_LAMBDA2, OBJ_EPS = 0.8, 0.2, 1e-4
 
 MLP_FEATURES, MLP_HIDDEN, MLP_MAX_OUT, MLP_PARAMS = 8, 64, 64, 8896
 # offsets of the weight layout: W1 [8][64], b1, W2 [64][64], b2, W3 [64][64], b3
 MLP_OFFSETS = dict(W1=(0, (8, 64)), b1=(512, (64,)), W2=(576, (64, 64)), b2=(4672, (64,)),
                    W3=(4736, (64, 64)), b3=(8832, (64,)))
+
+
+class LmObjective(ctypes.Structure):
+    _fields_ = [("kind", c_int32), ("lambda1", c_float), ("lambda2", c_float), ("eps", c_float)]
+
+
+def objective(kind=OBJ_L1_SSIM, lambda1=OBJ_LAMBDA1, lambda2=OBJ_LAMBDA2, eps=OBJ_EPS) -> LmObjective:
+    if isinstance(kind, str):
+        kind = {"l2": OBJ_L2, "l1_ssim": OBJ_L1_SSIM}[kind]
+    return LmObjective(int(kind), float(lambda1), float(lambda2), float(eps))
 
 
 class LmCamera(ctypes.Structure):
@@ -331,6 +347,65 @@ def lm_residual_sqnorm(x, sh_degree: int, cams, target, *, tile=(16, 16), worksp
     h = ws.handle
     _check(load().lm_residual_sqnorm(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), _stream(),
                                      byref(h), _ptr(out)), "lm_residual_sqnorm")
+    ws.handle = h
+    return out, ws
+
+
+def lm_objective_terms(image, target, cams, obj: LmObjective, *, w=True, e=True, workspace: Cache | None = None):
+    """Objective terms of device images [V][3][H][W] (flattened): returns
+    (w or None, e or None, E as a 1-element float64 device tensor, workspace)."""
+    import torch
+    image = _dev_f32(image, "image")
+    target = _dev_f32(target, "target")
+    carr = camera_array(cams)
+    ws = Cache() if workspace is None else workspace
+    wt = torch.empty_like(image) if w is True else (w if w is not False else None)
+    et = torch.empty_like(image) if e is True else (e if e is not False else None)
+    E = torch.empty(1, device=image.device, dtype=torch.float64)
+    h = ws.handle
+    _check(load().lm_objective_terms(_ptr(image), _ptr(target), carr, c_int32(len(carr)), byref(obj), _ptr(wt),
+                                     _ptr(et), _ptr(E), _stream(), byref(h)), "lm_objective_terms")
+    ws.handle = h
+    return wt, et, E, ws
+
+
+def lm_set_residual_weights(cache: Cache, w=None):
+    """Residual weights (image layout) for every later product of the cache;
+    None returns to plain least squares."""
+    _check(load().lm_set_residual_weights(cache.handle, _ptr(None if w is None else _dev_f32(w, "w")), _stream()),
+           "lm_set_residual_weights")
+
+
+def lm_cache_objective(cache: Cache, target, obj: LmObjective, *, b=None, want_b=True):
+    """Objective at the cache's point: sets the residual weights and returns
+    (b = -J^T e or None, per-view E as a float64 device tensor [V])."""
+    import torch
+    target = _dev_f32(target, "target")
+    info = cache.info()
+    if want_b and b is None:
+        b = torch.empty((info["P"], info["N"]), device=target.device, dtype=torch.float32)
+    E = torch.empty(info["V"], device=target.device, dtype=torch.float64)
+    _check(load().lm_cache_objective(cache.handle, _ptr(target), byref(obj), _ptr(b if want_b else None), _ptr(E),
+                                     _stream()), "lm_cache_objective")
+    return (b if want_b else None), E
+
+
+def lm_objective_value(x, sh_degree: int, cams, target, obj: LmObjective, *, tile=(16, 16),
+                       workspace: Cache | None = None, out=None):
+    """Objective of a forward render over the views of `cams`.  Returns
+    (value as a 1-element float64 device tensor, workspace)."""
+    import torch
+    x = _dev_f32(x, "x")
+    target = _dev_f32(target, "target")
+    P, N = x.shape
+    scene = LmScene(N, sh_degree, 0, x.data_ptr())
+    opts = LmOptions(tile[0], tile[1], 0, 0)
+    carr = camera_array(cams)
+    ws = Cache() if workspace is None else workspace
+    out = torch.empty(1, device=x.device, dtype=torch.float64) if out is None else out
+    h = ws.handle
+    _check(load().lm_objective_value(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), byref(obj),
+                                     _stream(), byref(h), _ptr(out)), "lm_objective_value")
     ws.handle = h
     return out, ws
 

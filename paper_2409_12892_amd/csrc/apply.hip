@@ -429,9 +429,17 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
                 u.y += o.y;
                 u.z += o.z;
             }
-            s_u[0][tid] = u;
+            // residual weights (w . u between the halves; ||J p||^2 becomes
+            // sum w u^2)
+            float4 wu = u;
+            if (valid && c.wres) {
+                wu.x = u.x * c.wres[ib];
+                wu.y = u.y * c.wres[ib + HW];
+                wu.z = u.z * c.wres[ib + 2 * HW];
+            }
+            s_u[0][tid] = wu;
             if (valid) {
-                sq = (double)u.x * (double)u.x + (double)u.y * (double)u.y + (double)u.z * (double)u.z;
+                sq = (double)u.x * (double)wu.x + (double)u.y * (double)wu.y + (double)u.z * (double)wu.z;
                 if (MODE == MODE_J && a.uout) {
                     a.uout[ib] = u.x;
                     a.uout[ib + HW] = u.y;
@@ -733,8 +741,10 @@ __global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
 // Per pair, with b = (alpha dx, alpha dy, alpha dx^2, alpha dx dy, alpha dy^2, G)
 // (zero when alpha is clamped), e = alpha T and D = dC/dalpha, the pair's
 // Jacobian row block applied to a tangent with power coefficients (a, dc) is
-// D (b . a) + e dc.  Its squared norm summed over pairs needs
-//   Bbb = sum (D.D) b b^T (21), Ebd = sum e b D^T (18), E2 = sum e^2 (1),
+// D (b . a) + e dc.  Its squared norm, weighted per channel by the pixel's
+// residual weights w (1 without weights), summed over pairs needs
+//   Bbb = sum (D.wD) b b^T (21), Ebd = sum e b (wD)^T (18),
+//   E2_ch = sum w_ch e^2 (3),
 // and, for the preconditioner features, the number of pairs (1).
 constexpr int kGram = kGramValues;
 
@@ -767,6 +777,25 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
         const float mlx = c.seg_f[sg], mly = c.seg_f[ss + sg];
         const float A = c.seg_f[2 * ss + sg], B = c.seg_f[3 * ss + sg], C = c.seg_f[4 * ss + sg];
         const float o = c.seg_f[5 * ss + sg];
+        // residual weights: the run's tile (binary search over the tiles'
+        // segment ranges) gives the view and the pixels' image positions
+        int64_t wb = 0, whw = 0;
+        int wtx = 0, wty = 0, wW = 0, wH = 0;
+        if (c.wres) {
+            int64_t lo = 0, hi = c.n_tiles - 1;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi + 1) >> 1;
+                if (c.tile_seg_off[mid] <= sg) lo = mid; else hi = mid - 1;
+            }
+            const CamDev& cam = c.cams[c.tile_view[lo]];
+            const int64_t lt = lo - cam.tile_base;
+            wtx = (int)(lt % cam.TX) * c.TW;
+            wty = (int)(lt / cam.TX) * c.TH;
+            wW = cam.W;
+            wH = cam.H;
+            whw = (int64_t)cam.W * cam.H;
+            wb = 3 * cam.pix_base;
+        }
 #pragma unroll
         for (int k = 0; k < kRun; ++k) {
             const bool live = L.t[k] != 0;                  // padding contributes nothing
@@ -783,7 +812,18 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
             float bb[6];
             bb[0] = ag * dx; bb[1] = ag * dy; bb[2] = ag * dx * dx;
             bb[3] = ag * dx * dy; bb[4] = ag * dy * dy; bb[5] = (clamped || !live) ? 0.0f : G;
-            const float DD = D0 * D0 + D1 * D1 + D2 * D2;
+            float w0 = 1.0f, w1 = 1.0f, w2 = 1.0f;
+            if (c.wres) {
+                const int gx = wtx + (pl & tw_mask), gy = wty + (pl >> tw_shift);
+                if (live && gx < wW && gy < wH) {
+                    const int64_t ib = wb + (int64_t)gy * wW + gx;
+                    w0 = c.wres[ib];
+                    w1 = c.wres[ib + whw];
+                    w2 = c.wres[ib + 2 * whw];
+                }
+            }
+            const float WD0 = w0 * D0, WD1 = w1 * D1, WD2 = w2 * D2;
+            const float DD = WD0 * D0 + WD1 * D1 + WD2 * D2;
 #pragma unroll
             for (int i = 0; i < 6; ++i)
 #pragma unroll
@@ -791,12 +831,15 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
 #pragma unroll
             for (int i = 0; i < 6; ++i) {
                 const float eb = e * bb[i];
-                acc[21 + 3 * i] += eb * D0;
-                acc[22 + 3 * i] += eb * D1;
-                acc[23 + 3 * i] += eb * D2;
+                acc[21 + 3 * i] += eb * WD0;
+                acc[22 + 3 * i] += eb * WD1;
+                acc[23 + 3 * i] += eb * WD2;
             }
-            acc[39] += e * e;
-            acc[40] += live ? 1.0f : 0.0f;
+            const float ee = e * e;
+            acc[39] += w0 * ee;
+            acc[40] += w1 * ee;
+            acc[41] += w2 * ee;
+            acc[42] += live ? 1.0f : 0.0f;
         }
     }
     const uint32_t next = __shfl_down(key, 1, kWave);
@@ -896,13 +939,12 @@ __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float*
                 q += 2.0 * co[i] * ((double)H[21 + 3 * i] * co[6] + (double)H[22 + 3 * i] * co[7] +
                                     (double)H[23 + 3 * i] * co[8]);
             }
-            q += (double)H[39] * (co[6] * co[6] + co[7] * co[7] + co[8] * co[8]);
+            q += (double)H[39] * co[6] * co[6] + (double)H[40] * co[7] * co[7] + (double)H[41] * co[8] * co[8];
             dgeo_acc[j] += q;
         }
-        const float h39 = H[39];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * h39;
+            const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * H[39 + ch];
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 const float y = c.lin[(int64_t)(kLinY + k) * ls + gv];
@@ -921,7 +963,7 @@ __global__ void __launch_bounds__(kBlock) k_coverage(CacheView c, const float* _
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= c.N) return;
     double pairs = 0.0;
-    for (uint32_t gv = c.gv_first[g]; gv < c.gv_first[g + 1]; ++gv) pairs += (double)gvgram[(int64_t)gv * kGram + 40];
+    for (uint32_t gv = c.gv_first[g]; gv < c.gv_first[g + 1]; ++gv) pairs += (double)gvgram[(int64_t)gv * kGram + 42];
     coverage[g] = (float)pairs;
 }
 
@@ -929,7 +971,7 @@ __global__ void __launch_bounds__(kBlock) k_coverage(CacheView c, const float* _
 // Row j of the block B_k = J_k^T J_k of one Gaussian over its P parameters.
 // In the 9 slots of a (Gaussian, view) (six power coefficients, three
 // colours) the unit tangent of parameter j has coefficients co_j, and the
-// slot Gram matrix is G = [[Bbb, Ebd], [Ebd^T, E2 I]], so
+// slot Gram matrix is G = [[Bbb, Ebd], [Ebd^T, diag(E2)]], so
 // B_ji = sum over views of co_j^T G co_i.  One thread per (Gaussian, row),
 // rows of a Gaussian adjacent, so the view data is read once per wave.
 // OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P]);
@@ -975,10 +1017,9 @@ __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float*
             for (int k = 0; k < 6; ++k) a += H[k < i ? tri6(k, i) : tri6(i, k)] * co[k];
             w[i] = a + H[21 + 3 * i] * co[6] + H[22 + 3 * i] * co[7] + H[23 + 3 * i] * co[8];
         }
-        const float e2 = H[39];
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
-            float a = e2 * co[6 + ch];
+            float a = H[39 + ch] * co[6 + ch];
 #pragma unroll
             for (int i = 0; i < 6; ++i) a += H[21 + 3 * i + ch] * co[i];
             w[6 + ch] = a;

@@ -140,6 +140,8 @@ struct lm_cache {
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
     DevBuf gram_redge, gram_rkey, gram_rends;
+    DevBuf wres, obj_e, obj_part;
+    bool weighted = false;       // wres holds residual weights for the products
     bool gram_valid = false;     // gvgram holds the Gram values of the current build
     bool compact = false;        // the build-only buffers were released (LM_BUILD_COMPACT)
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
@@ -165,6 +167,7 @@ struct lm_cache {
         c.gv_seg_off = gv_seg_off.as<uint32_t>(); c.gv_segs = gv_segs.as<uint32_t>();
         c.seg_pos = seg_pos.as<uint32_t>(); c.list_gv = list_gv.as<uint32_t>();
         c.lin = lin.as<float>(); c.lin_stride = lin_stride;
+        c.wres = weighted ? wres.as<float>() : nullptr;
         return c;
     }
 
@@ -191,6 +194,7 @@ struct lm_cache {
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &wres, &obj_e, &obj_part,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -216,6 +220,7 @@ struct lm_cache {
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &wres, &obj_e, &obj_part,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -257,6 +262,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     c->built = false;
     c->gram_valid = false;
     c->compact = false;
+    c->weighted = false;
     c->N = scene->N;
     c->deg = scene->sh_degree;
     c->P = 11 + 3 * (c->deg + 1) * (c->deg + 1);
@@ -566,6 +572,56 @@ hipError_t capture_stream(hipStream_t* out) {
     }
     *out = cs[dev];
     return hipSuccess;
+}
+
+// The objective's terms for the V views of an image-layout pair (a, t):
+// a is the image, or the residual image - t when add_target.  Partial sums
+// of E stay in ws->obj_part; E_total and E_view (dev, may be null) receive
+// the total and the per-view sums (E_view needs cams_dev).
+lm_status objective_check(const lm_objective* o) {
+    LM_CHECK(o, LM_ERR_INVALID_ARG, "objective is NULL");
+    LM_CHECK(o->kind == LM_OBJ_L2 || o->kind == LM_OBJ_L1_SSIM, LM_ERR_INVALID_ARG,
+             "objective kind must be LM_OBJ_L2 or LM_OBJ_L1_SSIM");
+    LM_CHECK(o->kind == LM_OBJ_L2 || (o->eps > 0.0f && o->lambda1 >= 0.0f && o->lambda2 >= 0.0f),
+             LM_ERR_INVALID_ARG, "objective needs eps > 0 and lambda1, lambda2 >= 0");
+    return LM_OK;
+}
+
+lm_status run_objective(lm_cache* ws, const float* a, const float* t, bool add_target, const std::vector<int>& Ws,
+                        const std::vector<int>& Hs, const lm_objective* o, float* w, float* e, double* E_total,
+                        const lm::CamDev* cams_dev, double* E_view, hipStream_t s) {
+    const int V = (int)Ws.size();
+    int64_t nparts = 0;
+    std::vector<int64_t> p0(V);
+    for (int v = 0; v < V; ++v) {
+        p0[v] = nparts;
+        nparts += lm::objective_blocks(Ws[v], Hs[v]);
+    }
+    LM_HIP(ws->obj_part.ensure(sizeof(double) * std::max<int64_t>(nparts, 1)));
+    lm::ObjectiveArgs A{};
+    A.a = a;
+    A.t = t;
+    A.w = w;
+    A.e = e;
+    A.part = ws->obj_part.as<double>();
+    A.kind = o->kind;
+    A.add_target = add_target ? 1 : 0;
+    A.lam1 = o->lambda1;
+    A.lam2 = o->lambda2;
+    A.eps = o->eps;
+    lm::objective_window(A.g);
+    int64_t off = 0;
+    for (int v = 0; v < V; ++v) {
+        A.off = off;
+        A.part0 = p0[v];
+        A.W = Ws[v];
+        A.H = Hs[v];
+        LM_HIP(lm::launch_objective(A, s));
+        off += 3 * (int64_t)Ws[v] * Hs[v];
+    }
+    if (E_total) LM_HIP(lm::reduce_f64(ws->obj_part.as<double>(), nparts, E_total, s));
+    if (E_view) LM_HIP(lm::launch_objective_view_sums(cams_dev, V, ws->obj_part.as<double>(), E_view, s));
+    return LM_OK;
 }
 
 }  // namespace
@@ -1140,6 +1196,130 @@ lm_status lm_cache_view_sqnorm(const lm_cache* c, double* per_view, void* stream
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     LM_HIP(lm::view_sum_f64(c->cams.as<lm::CamDev>(), c->V, c->fsq_part.as<double>(), per_view, S(stream)));
     return LM_OK;
+}
+
+lm_status lm_objective_terms(const float* image, const float* target, const lm_camera* cams, int32_t V,
+                             const lm_objective* obj, float* w, float* e, double* E, void* stream,
+                             lm_cache** workspace) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    LM_CHECK(image && target && cams && E && workspace, LM_ERR_INVALID_ARG, "lm_objective_terms: NULL argument");
+    LM_CHECK(V > 0 && V <= lm::kMaxViews, LM_ERR_INVALID_ARG, "lm_objective_terms: bad view count");
+    lm_status st = objective_check(obj);
+    if (st != LM_OK) return st;
+    std::vector<int> Ws(V), Hs(V);
+    for (int v = 0; v < V; ++v) {
+        LM_CHECK(cams[v].W > 0 && cams[v].H > 0, LM_ERR_INVALID_ARG, "camera with empty image");
+        Ws[v] = cams[v].W;
+        Hs[v] = cams[v].H;
+    }
+    lm_cache* c = *workspace;
+    bool created = false;
+    if (!c) {
+        c = new (std::nothrow) lm_cache();
+        LM_CHECK(c, LM_ERR_HIP, "out of host memory");
+        created = true;
+    }
+    st = run_objective(c, image, target, false, Ws, Hs, obj, w, e, E, nullptr, nullptr, S(stream));
+    if (st != LM_OK && created) {
+        c->release_all();
+        delete c;
+        return st;
+    }
+    *workspace = c;
+    return st;
+}
+
+lm_status lm_set_residual_weights(lm_cache* c, const float* w, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    LM_CHECK(c, LM_ERR_INVALID_ARG, "lm_set_residual_weights: NULL cache");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    c->gram_valid = false;
+    if (!w) {
+        c->weighted = false;
+        return LM_OK;
+    }
+    LM_HIP(c->wres.ensure(sizeof(float) * 3 * c->n_pix));
+    LM_HIP(hipMemcpyAsync(c->wres.p, w, sizeof(float) * 3 * c->n_pix, hipMemcpyDeviceToDevice, S(stream)));
+    c->weighted = true;
+    return LM_OK;
+}
+
+lm_status lm_cache_objective(lm_cache* c, const float* target, const lm_objective* obj, float* b, double* E,
+                             void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    LM_CHECK(c && target, LM_ERR_INVALID_ARG, "lm_cache_objective: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    LM_CHECK(!c->compact, LM_ERR_NOT_BUILT,
+             "lm_cache_objective: the residual image was released (LM_BUILD_COMPACT build)");
+    lm_status st = objective_check(obj);
+    if (st != LM_OK) return st;
+    hipStream_t s = S(stream);
+    c->gram_valid = false;
+    if (obj->kind == LM_OBJ_L2) {
+        c->weighted = false;
+        if (E) LM_HIP(lm::view_sum_f64(c->cams.as<lm::CamDev>(), c->V, c->fsq_part.as<double>(), E, s));
+        if (b) return apply_JT_internal(c, c->resid.as<float>(), -1.0f, b, s);
+        return LM_OK;
+    }
+    LM_HIP(c->wres.ensure(sizeof(float) * 3 * c->n_pix));
+    LM_HIP(c->obj_e.ensure(sizeof(float) * 3 * c->n_pix));
+    std::vector<int> Ws(c->V), Hs(c->V);
+    for (int v = 0; v < c->V; ++v) {
+        Ws[v] = c->cams_h[v].W;
+        Hs[v] = c->cams_h[v].H;
+    }
+    {
+        LM_PROF("objective", s);
+        st = run_objective(c, c->resid.as<float>(), target, true, Ws, Hs, obj, c->wres.as<float>(),
+                           c->obj_e.as<float>(), nullptr, c->cams.as<lm::CamDev>(), E, s);
+    }
+    if (st != LM_OK) return st;
+    c->weighted = true;
+    if (b) return apply_JT_internal(c, c->obj_e.as<float>(), -1.0f, b, s);
+    return LM_OK;
+}
+
+lm_status lm_objective_value(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
+                             const lm_options* opts, const lm_objective* obj, void* stream, lm_cache** workspace,
+                             double* E) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    LM_CHECK(workspace && target && E, LM_ERR_INVALID_ARG, "lm_objective_value: NULL argument");
+    lm_status st = objective_check(obj);
+    if (st != LM_OK) return st;
+    lm_cache* c = *workspace;
+    bool created = false;
+    if (!c) {
+        c = new (std::nothrow) lm_cache();
+        LM_CHECK(c, LM_ERR_HIP, "out of host memory");
+        created = true;
+    }
+    hipStream_t s = S(stream);
+    st = build_forward(c, scene, cams, V, target, opts, s);
+    if (st == LM_OK) {
+        if (obj->kind == LM_OBJ_L2) {
+            hipError_t e = lm::reduce_f64(c->fsq_part.as<double>(), c->n_tiles, E, s);
+            if (e != hipSuccess) {
+                lm::set_error(std::string("lm_objective_value: ") + hipGetErrorString(e));
+                st = LM_ERR_HIP;
+            }
+        } else {
+            std::vector<int> Ws(V), Hs(V);
+            for (int v = 0; v < V; ++v) {
+                Ws[v] = cams[v].W;
+                Hs[v] = cams[v].H;
+            }
+            st = run_objective(c, c->resid.as<float>(), target, true, Ws, Hs, obj, nullptr, nullptr, E, nullptr,
+                               nullptr, s);
+        }
+    }
+    c->built = false;
+    if (st != LM_OK && created) {
+        c->release_all();
+        delete c;
+        return st;
+    }
+    *workspace = c;
+    return st;
 }
 
 int64_t lm_cache_export_size(const lm_cache* c, int32_t what) {

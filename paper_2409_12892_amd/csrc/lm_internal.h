@@ -69,6 +69,7 @@ struct CacheView {
     const uint32_t* list_gv;     // dev [n_seg] gv of each gv_segs entry
     const float* lin;            // dev [kLin][lin_stride]: linearised projection per gv
     int64_t lin_stride;
+    const float* wres;           // dev [3 * n_pix] residual weights (image layout), or null: all 1
 };
 
 // Linearisation of the projection of one (Gaussian, view) at the cache's x,
@@ -283,8 +284,8 @@ hipError_t launch_tangent(const ApplyBatch& B, hipStream_t s);
 hipError_t launch_apply_tile(int mode, const ApplyBatch& B, hipStream_t s);
 hipError_t launch_chain(const ApplyBatch& B, hipStream_t s);
 unsigned chain_blocks(int64_t N);
-// Per-segment Gram values (41 floats) reduced per (Gaussian, view) into gvgram.
-constexpr int kGramValues = 41;
+// Per-segment Gram values (43 floats) reduced per (Gaussian, view) into gvgram.
+constexpr int kGramValues = 43;
 // run_edge: 2 * kGramValues floats, run_ekey: 2 u32, run_eends: 1 u32 per gram_run_waves(n_pairs)
 int64_t gram_run_waves(int64_t n_pairs);
 hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
@@ -313,6 +314,25 @@ int mlp_grad_parts();
 hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s);
 int64_t gv_reduce_waves(int64_t n_seg);
 hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipStream_t s);
+// objective.hip: residual terms of one view (w, e may be null); part[part0 ..
+// part0 + objective_blocks(W, H)) receives the workgroups' sums of E.
+struct ObjectiveArgs {
+    const float* a;          // image, or the residual image - target when add_target
+    const float* t;          // target
+    float* w;                // residual weights (or null)
+    float* e;                // colour-space residual gradient (or null)
+    double* part;
+    int64_t off;             // first element of the view ([3][H][W] from here)
+    int64_t part0;
+    int32_t W, H, kind, add_target;
+    double lam1, lam2, eps;
+    double g[11];            // 1-D window weights (objective_window)
+};
+int64_t objective_blocks(int W, int H);
+void objective_window(double* g);
+hipError_t launch_objective(const ObjectiveArgs& a, hipStream_t s);
+// out[v] = E of view v from the partials of launch_objective over views 0..V-1
+hipError_t launch_objective_view_sums(const CamDev* cams, int V, const double* part, double* out, hipStream_t s);
 // pcg.hip
 int64_t pcg_partial_count(int64_t n);
 hipError_t pcg_init(int64_t n, const float* b, const float* M, float floor_, const float* scale, float* x,

@@ -127,8 +127,8 @@ def test_invalid_options_are_rejected():
 def test_compact_build_keeps_the_products_and_refuses_build_exports():
     """LM_BUILD_COMPACT frees the build-only buffers: products, diagonal and
     per-view residuals are bit-identical to those of a full build, the pair
-    arrays still export, the residual image does not, and a rebuild on the
-    compacted handle works."""
+    arrays still export, the residual image does not (nor the objective,
+    which reads it), and a rebuild on the compacted handle works."""
     from paper_2409_12892_amd import binding as B
     d = sg.config_scene("tiny", N=700, subsets=[(3, 64, 48)], seed=23, deg=1)
     sc, cams = d["scene"], d["cams"][0]
@@ -147,6 +147,8 @@ def test_compact_build_keeps_the_products_and_refuses_build_exports():
     np.testing.assert_array_equal(full.export("pair_T"), comp.export("pair_T"))
     with pytest.raises(RuntimeError):
         comp.export("residual")
+    with pytest.raises(RuntimeError):       # the objective needs the residual image
+        B.lm_cache_objective(comp, tgt, B.objective())
     comp2, b3, _ = B.lm_build_cache(x, sc.sh_degree, cams, tgt, cache=comp)
     assert torch.equal(b3, b1)
     assert comp2.export("residual").size == 3 * 3 * 64 * 48
