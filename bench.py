@@ -54,14 +54,16 @@ class OneCam:
         return self.cam
 
 
-def apply_tile_alg_bytes(info: dict) -> int:
+def apply_tile_alg_bytes(info: dict, weighted: bool = False) -> int:
     """Algorithmic HBM bytes of one fused J^T J tile-pass launch: every cached
     pair once (T, dC/dalpha x3 in the cache dtype + the pixel byte), per
     segment its staged splat (6 floats), pair offset and gv index (2 x 4 B),
     its tangent coefficients (9 floats, read) and moments (9 floats,
-    written), per tile its offsets, view and ||Jp||^2 partial."""
+    written), per tile its offsets, view and ||Jp||^2 partial; with residual
+    weights, 3 floats per pixel."""
     wb = 4 if info["cache_dtype"] == 0 else 2
-    return int(info["n_pairs"] * (4 * wb + 1) + info["n_segments"] * (24 + 8 + 36 + 36) + info["n_tiles"] * 28)
+    return int(info["n_pairs"] * (4 * wb + 1) + info["n_segments"] * (24 + 8 + 36 + 36) + info["n_tiles"] * 28
+               + (12 * info["n_pixels"] if weighted else 0))
 
 
 def read_traffic(alg_bytes: int, tile: str):
@@ -412,6 +414,9 @@ def main() -> int:
     ap.add_argument("--N", type=int, default=None, help="override the number of Gaussians")
     ap.add_argument("--views", type=int, default=None, help="override the views of the subset")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--objective", default="l2", choices=["l2", "l1_ssim"],
+                    help="least-squares RGB residuals (the configured workload) or the paper's square-root "
+                         "L1 / SSIM residuals")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="after the timed steps, copy 256 MiB device to device three times (the "
                          "reference kernel for rocprofv3 byte counters)")
@@ -479,7 +484,8 @@ def main() -> int:
 
     from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
     solver = LMSolver(x, scene.sh_degree, cams, target,
-                      LMConfig(lam=lam, n_iters=n_iters, tile=(tw, th), cache_dtype=args.cache_dtype))
+                      LMConfig(lam=lam, n_iters=n_iters, tile=(tw, th), cache_dtype=args.cache_dtype,
+                               objective=args.objective))
 
     def show(tag, rec):
         log(f"{tag}: E {rec['E0']:.4g} -> {rec['E1']:.4g} gamma {rec['gamma']:g} rho {rec['rho']:.3g} "
@@ -512,9 +518,10 @@ def main() -> int:
 
     launches, tot_ms = prof.get("apply_tile_JtJ", (0, 0.0))
     apply_ms = tot_ms / max(launches, 1)
-    alg = apply_tile_alg_bytes(info)
+    alg = apply_tile_alg_bytes(info, weighted=args.objective != "l2")
     achieved = alg / (apply_ms * 1e-3) / 1e9
-    traffic = read_traffic(alg, f"{tw}x{th}")
+    # the counter summary covers the least-squares (unweighted) pass
+    traffic = read_traffic(alg, f"{tw}x{th}") if args.objective == "l2" else None
     full_apply_ms = sum(prof.get(k, (0, 0.0))[1] for k in ("tangent", "apply_tile_JtJ", "chain", "pcg_vector")) \
         / max(launches, 1)
     log(f"steps done: {ms_per_step:.1f} ms/step, apply tile pass {apply_ms:.3f} ms, {achieved:.0f} GB/s")
@@ -533,8 +540,10 @@ def main() -> int:
         "dtype": args.cache_dtype,
         "data": "synthetic",
         "config": {
-            "workload": (f"LM iteration, plain method: {scene.N} Gaussians SH{scene.sh_degree}, {V} views "
+            "workload": (f"LM iteration, {'plain method' if args.objective == 'l2' else 'square-root L1/SSIM objective'}: "
+                         f"{scene.N} Gaussians SH{scene.sh_degree}, {V} views "
                          f"{W}x{H} in one subset, {args.cache_dtype} cache, {n_iters} Jacobi-PCG iterations"),
+            "objective": args.objective,
             "N": scene.N, "P": scene.P, "views": V, "width": W, "height": H, "tile": f"{tw}x{th}",
             "tile_autotune": tile_scores,
             "cache_dtype": args.cache_dtype, "pcg_iters": n_iters, "lambda": lam,

@@ -24,6 +24,12 @@ paper follows CERES for the lambda schedule): on scenes with deeply occluded
 Gaussians, diag(J^T J) reaches 1e-25 and plain Jacobi PCG returns steps of
 order |F| / sqrt(diag) ~ 1e10 that no line search can rescue.
 
+The objective is plain least squares (objective="l2") or the paper's
+square-root L1 / SSIM residuals (objective="l1_ssim", eq. gn-loss): then the
+cache's residual weights and b come from lm_cache_objective after every
+build, every product is J^T W J, and the errors E compared by the line
+search and the trust-region ratio are the objective's values.
+
 Every product, render and reduction runs in the library; this module only
 sequences calls and does scalar bookkeeping (and the vector update
 x += gamma delta).
@@ -52,6 +58,8 @@ class LMConfig:
     gammas: tuple = tuple(2.0 ** -k for k in range(13))
     tile: tuple = (16, 16)
     cache_dtype: str = "f32"
+    objective: str = "l2"           # "l2" or "l1_ssim"
+    obj_eps: float = B.OBJ_EPS
 
 
 class LMSolver:
@@ -84,15 +92,27 @@ class LMSolver:
         self.comb = None
         self.x_try = torch.empty_like(x)
         self.history = []
+        self.obj = None if cfg.objective == "l2" else B.objective(cfg.objective, eps=cfg.obj_eps)
+        self.E_views = None
 
     def _E(self, x, cams, target) -> float:
-        val, self.ws = B.lm_residual_sqnorm(x, self.deg, cams, target, tile=self.cfg.tile, workspace=self.ws)
+        if self.obj is None:
+            val, self.ws = B.lm_residual_sqnorm(x, self.deg, cams, target, tile=self.cfg.tile, workspace=self.ws)
+        else:
+            val, self.ws = B.lm_objective_value(x, self.deg, cams, target, self.obj, tile=self.cfg.tile,
+                                                workspace=self.ws)
         return float(val.item())
 
     def _build(self, x):
+        """Cache at x; self.fsq holds the objective's value there (device),
+        self.E_views its per-view split (or None: taken from the cache)."""
         cfg = self.cfg
         self.cache, self.b, self.fsq = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
                                                         cache_dtype=cfg.cache_dtype, cache=self.cache, b=self.b)
+        self.E_views = None
+        if self.obj is not None:
+            self.b, self.E_views = B.lm_cache_objective(self.cache, self.target, self.obj, b=self.b)
+            self.fsq = self.E_views.sum().reshape(1)
 
     def iteration(self) -> dict:
         import torch
@@ -111,7 +131,7 @@ class LMSolver:
         E0 = float(fsq.item())
         dTb = float(torch.dot(d.reshape(-1).double(), b.reshape(-1).double()).item())
         Jd2 = float(jd.item())
-        per_view = B.lm_cache_view_sqnorm(self.cache)
+        per_view = B.lm_cache_view_sqnorm(self.cache) if self.E_views is None else self.E_views
         E_ref = float(per_view[torch.as_tensor(self.ls_idx, device=per_view.device)].sum().item())
         # line search on the view subset (grid 2^-k, warm start at the last k)
         gammas = cfg.gammas

@@ -64,3 +64,34 @@ def test_residual_sqnorm_matches_build():
         B.lm_jacobi_diag(ws)          # a workspace holds no usable cache
     ws.destroy()
     cache.destroy()
+
+
+def test_lm_iterations_on_the_paper_objective():
+    """The square-root L1 / SSIM objective (eq. gn-loss): accepted steps
+    lower E, the error of the next iteration's cache equals the accepted
+    trial value, and E agrees with the oracle's objective of its own render
+    at the starting point."""
+    from oracle import forward, objective as ob
+    from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
+    pr = make_problem("tiny", with_J=False)
+    sc = pr["scene"]
+    x = torch.from_numpy(sc.x).cuda()
+    tgt = torch.from_numpy(pr["target"].ravel()).cuda()
+    solver = LMSolver(x, sc.sh_degree, pr["cams"], tgt,
+                      LMConfig(lam=1e-2, n_iters=8, line_search_fraction=0.5, objective="l1_ssim"))
+    recs = [solver.iteration() for _ in range(4)]
+    imgs = forward.render_images(sc.x, pr["cams"], sc.sh_degree)
+    lam = [float(np.float32(v)) for v in (ob.LAMBDA1, ob.LAMBDA2, ob.EPS)]
+    E_ref = sum(ob.terms(im, t.astype(np.float64), ob.OBJ_L1_SSIM, *lam)["E"] for im, t in zip(imgs, pr["target"]))
+    assert recs[0]["E0"] == pytest.approx(E_ref, rel=1e-6)
+    for r in recs:
+        print(r)
+        if r["accepted"]:
+            assert r["E1"] < r["E0"] and r["rho"] > 1e-5
+        else:
+            assert r["lam_next"] == pytest.approx(min(2 * r["lam"], 1e4))
+    assert any(r["accepted"] for r in recs)
+    for a, b in zip(recs[:-1], recs[1:]):
+        if a["accepted"]:
+            assert b["E0"] == pytest.approx(a["E1"], rel=1e-9)
+    solver.close()
