@@ -777,16 +777,21 @@ __global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_run
         const float mlx = c.seg_f[sg], mly = c.seg_f[ss + sg];
         const float A = c.seg_f[2 * ss + sg], B = c.seg_f[3 * ss + sg], C = c.seg_f[4 * ss + sg];
         const float o = c.seg_f[5 * ss + sg];
-        // residual weights: the run's tile (binary search over the tiles'
-        // segment ranges) gives the view and the pixels' image positions
+        // residual weights: the run's tile gives the view and the pixels'
+        // image positions.  The wave's first active lane finds its tile by a
+        // binary search over the tiles' segment ranges; segments ascend with
+        // the lane, so the others step forward from there (a wave's 512
+        // pairs rarely span two tiles).
         int64_t wb = 0, whw = 0;
         int wtx = 0, wty = 0, wW = 0, wH = 0;
         if (c.wres) {
+            const int64_t s0 = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)L.seg);
             int64_t lo = 0, hi = c.n_tiles - 1;
             while (lo < hi) {
                 const int64_t mid = (lo + hi + 1) >> 1;
-                if (c.tile_seg_off[mid] <= sg) lo = mid; else hi = mid - 1;
+                if (c.tile_seg_off[mid] <= s0) lo = mid; else hi = mid - 1;
             }
+            while (lo + 1 < c.n_tiles && c.tile_seg_off[lo + 1] <= sg) ++lo;
             const CamDev& cam = c.cams[c.tile_view[lo]];
             const int64_t lt = lo - cam.tile_base;
             wtx = (int)(lt % cam.TX) * c.TW;
