@@ -107,10 +107,14 @@ class LMSolver:
         """Cache at x; self.fsq holds the objective's value there (device),
         self.E_views its per-view split (or None: taken from the cache)."""
         cfg = self.cfg
-        self.cache, self.b, self.fsq = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
-                                                        cache_dtype=cfg.cache_dtype, cache=self.cache, b=self.b)
         self.E_views = None
-        if self.obj is not None:
+        if self.obj is None:
+            self.cache, self.b, self.fsq = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
+                                                            cache_dtype=cfg.cache_dtype, cache=self.cache, b=self.b)
+        else:
+            # the build's own b = -J^T F belongs to the least-squares objective
+            self.cache, _, _ = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
+                                                cache_dtype=cfg.cache_dtype, cache=self.cache, want_b=False)
             self.b, self.E_views = B.lm_cache_objective(self.cache, self.target, self.obj, b=self.b)
             self.fsq = self.E_views.sum().reshape(1)
 
