@@ -24,7 +24,7 @@ def jacobi_inverse(M: np.ndarray) -> np.ndarray:
 
 def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
         tol: float = 0.0, tol_mode: int = TOL_NONE, precond_scale: np.ndarray | None = None,
-        diag_floor: float = 0.0) -> dict:
+        diag_floor: float = 0.0, precond=None) -> dict:
     """Algorithm 1, in the order printed:
 
         x0 = M^-1 b;  r0 = b - (J^T J x0 + lam M x0);  z0 = M^-1 r0;  p0 = z0
@@ -41,7 +41,9 @@ def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
     ``diag_floor`` > 0 (not in the paper's text; the minimum LM diagonal of
     CERES, whose LM variant the paper follows) replaces every positive
     diagonal entry below the floor by the floor, in the damping term and in
-    M^-1 alike; 0 runs Algorithm 1 as printed.
+    M^-1 alike; 0 runs Algorithm 1 as printed.  ``precond(v)``, when given,
+    replaces every application of M^-1 (a block preconditioner); the damping
+    term still uses M.
     Returns x and the per-iteration ||r||^2 / ||b||^2 history.
     """
     b = np.asarray(b, np.float64).ravel()
@@ -56,9 +58,10 @@ def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
     def A(v):
         return apply_JtJ(v) + lam * M * v
 
-    x = Minv * b
+    Pinv = (lambda v: Minv * v) if precond is None else precond
+    x = Pinv(b)
     r = b - A(x)
-    z = Minv * r
+    z = Pinv(r)
     p = z.copy()
     rz = float(r @ z)
     hist = [float(r @ r) / bb if bb > 0 else 0.0]
@@ -74,7 +77,7 @@ def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
         alpha = rz / pg
         x = x + alpha * p
         r = r - alpha * g
-        z = Minv * r
+        z = Pinv(r)
         rz_new = float(r @ z)
         beta = rz_new / rz if rz != 0.0 else 0.0
         p = z + beta * p
@@ -86,6 +89,34 @@ def pcg(apply_JtJ, b: np.ndarray, M: np.ndarray, lam: float, n_iters: int,
         if tol_mode == TOL_RELATIVE and np.sqrt(rr) < tol * np.sqrt(bb):
             break
     return dict(x=x, iters=it, history=np.asarray(hist), status=status)
+
+
+def block_jacobi(blocks: np.ndarray, lam: float, diag_floor: float = 0.0):
+    """Block-Jacobi preconditioner of the damped normal equations: per
+    Gaussian k the P x P block A_k = B_k + lam diag(D_k) of
+    J^T J + lam diag(D) (eq. norm-eq restricted to the Gaussian's own
+    parameters; B_k = J_k^T J_k, D = diag(J^T J) raised to diag_floor where
+    positive and smaller), inverted exactly.  A parameter with a zero
+    diagonal (no residual sees it) keeps a unit diagonal and no coupling, so
+    its entry passes through unchanged (its residual entry is 0).
+    ``blocks`` [N, P, P]; returns v -> A^-1 v on [P][N]-ordered vectors."""
+    blocks = np.asarray(blocks, np.float64)
+    N, P, _ = blocks.shape
+    A = blocks.copy()
+    for k in range(N):
+        d = np.diag(blocks[k]).copy()
+        obs = d > 0
+        A[k][~obs, :] = 0.0
+        A[k][:, ~obs] = 0.0
+        A[k][np.diag_indices(P)] = np.where(obs, d + lam * np.maximum(d, diag_floor), 1.0)
+
+    def apply(v):
+        V = np.asarray(v, np.float64).reshape(P, N)
+        out = np.empty_like(V)
+        for k in range(N):
+            out[:, k] = np.linalg.solve(A[k], V[:, k])
+        return out.ravel()
+    return apply
 
 
 def dense_solve(JtJ: np.ndarray, b: np.ndarray, lam: float, diag_floor: float = 0.0) -> np.ndarray:
