@@ -246,6 +246,29 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
                        double tol, int32_t tol_mode, const float* const* precond_scale,
                        float* const* delta, lm_pcg_stats* stats, void* stream);
 
+/* Block-Jacobi preconditioner (a stronger preconditioner than the paper's
+ * Jacobi choice of section 3.3): per Gaussian the damped block
+ * A_k = J_k^T J_k + lambda diag(max(d, diag_floor)) of eq. norm-eq
+ * restricted to the Gaussian's own P parameters (d = diag(J_k^T J_k); a
+ * parameter with d = 0 keeps a unit diagonal and no coupling), inverted
+ * exactly through a Cholesky factor, in place of M^-1 in Algorithm 1.  The
+ * factors (P (P + 1) / 2 floats per Gaussian) are computed on first use for
+ * (lambda, diag_floor) and kept in the cache until the next build or
+ * residual-weight change; with residual weights the blocks are those of
+ * J^T W J.  Same arguments and behaviour as lm_pcg_solve otherwise. */
+lm_status lm_pcg_solve_block(lm_cache* const* caches, int32_t n_b, const float* const* b,
+                             const float* const* M, float lambda, float diag_floor, int32_t n_iters,
+                             double tol, int32_t tol_mode, float* const* delta, lm_pcg_stats* stats,
+                             void* stream);
+
+/* z = A^-1 r with the block-Jacobi factors for (lambda, diag_floor) (r, z
+ * dev float32 [P][N]).  n_fallback (host, may be NULL): when given, the
+ * factors are recomputed and it receives the number of Gaussians whose
+ * damped block did not factor (those use their damped diagonal); the call
+ * then synchronises the stream. */
+lm_status lm_block_precond_apply(lm_cache* cache, float lambda, float diag_floor, const float* r, float* z,
+                                 int32_t* n_fallback, void* stream);
+
 /* Tile shape for one image subset, measured: for each candidate shape
  * (16x16, 32x8, 8x32, 16x8, 8x16, 8x8) the cache is built twice (the
  * first build absorbs buffer growth), the second build and two J^T J

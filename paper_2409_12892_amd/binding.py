@@ -36,7 +36,7 @@ EXPORTED_SYMBOLS = (
     "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile", "lm_pair_coverage", "lm_block_jacobi",
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
     "lm_jp_sqnorm", "lm_set_allocator", "lm_objective_terms", "lm_set_residual_weights", "lm_cache_objective",
-    "lm_objective_value",
+    "lm_objective_value", "lm_pcg_solve_block", "lm_block_precond_apply",
 )
 
 # objective kinds (include/lm3dgs.h): plain least squares, and the paper's
@@ -300,9 +300,10 @@ def lm_apply_JT(cache: Cache, u, out=None):
 
 
 def lm_pcg_solve(caches, bs, Ms, lam: float, n_iters: int, tol: float = 0.0, tol_mode: int = TOL_NONE,
-                 scales=None, deltas=None, diag_floor: float = 0.0):
+                 scales=None, deltas=None, diag_floor: float = 0.0, block: bool = False):
     """Algorithm 1 for each subset; returns (deltas, stats dicts).  diag_floor
-    = 0 is Algorithm 1 exactly (see lm_pcg_solve in include/lm3dgs.h)."""
+    = 0 is Algorithm 1 exactly (see lm_pcg_solve in include/lm3dgs.h);
+    block=True uses the block-Jacobi preconditioner (lm_pcg_solve_block)."""
     import torch
     nb = len(caches)
     deltas = [torch.empty_like(b) for b in bs] if deltas is None else deltas
@@ -312,12 +313,32 @@ def lm_pcg_solve(caches, bs, Ms, lam: float, n_iters: int, tol: float = 0.0, tol
     D = (c_void_p * nb)(*[d.data_ptr() for d in deltas])
     Sc = None if scales is None else (c_void_p * nb)(*[0 if s is None else s.data_ptr() for s in scales])
     stats = (LmPcgStats * nb)()
-    _check(load().lm_pcg_solve(H, c_int32(nb), B, Mm, c_float(lam), c_float(diag_floor), c_int32(n_iters),
-                               c_double(tol),
-                               c_int32(tol_mode), Sc, D, stats, _stream()), "lm_pcg_solve")
+    if block:
+        if scales is not None:
+            raise ValueError("the block-Jacobi solve takes no diagonal scaling")
+        _check(load().lm_pcg_solve_block(H, c_int32(nb), B, Mm, c_float(lam), c_float(diag_floor), c_int32(n_iters),
+                                         c_double(tol), c_int32(tol_mode), D, stats, _stream()), "lm_pcg_solve_block")
+    else:
+        _check(load().lm_pcg_solve(H, c_int32(nb), B, Mm, c_float(lam), c_float(diag_floor), c_int32(n_iters),
+                                   c_double(tol),
+                                   c_int32(tol_mode), Sc, D, stats, _stream()), "lm_pcg_solve")
     out = [dict(iters=s.iters, status=s.status, b_sqnorm=s.b_sqnorm,
                 history=np.array(s.history[:s.iters + 1])) for s in stats]
     return deltas, out
+
+
+def lm_block_precond_apply(cache: Cache, r, lam: float, diag_floor: float = 0.0, out=None,
+                           count_fallback: bool = False):
+    """z = A^-1 r with the cache's block-Jacobi factors for (lam, diag_floor);
+    returns z, or (z, number of Gaussians that fell back to their damped
+    diagonal) with count_fallback."""
+    import torch
+    r = _dev_f32(r, "r")
+    out = torch.empty_like(r) if out is None else out
+    nf = c_int32(0)
+    _check(load().lm_block_precond_apply(cache.handle, c_float(lam), c_float(diag_floor), _ptr(r), _ptr(out),
+                                         byref(nf) if count_fallback else None, _stream()), "lm_block_precond_apply")
+    return (out, int(nf.value)) if count_fallback else out
 
 
 def lm_combine_subsets(deltas, Ms, out=None):

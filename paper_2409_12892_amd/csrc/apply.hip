@@ -979,21 +979,23 @@ __global__ void __launch_bounds__(kBlock) k_coverage(CacheView c, const float* _
 // slot Gram matrix is G = [[Bbb, Ebd], [Ebd^T, diag(E2)]], so
 // B_ji = sum over views of co_j^T G co_i.  One thread per (Gaussian, row),
 // rows of a Gaussian adjacent, so the view data is read once per wave.
-// OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P]);
+// OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P];
+// without a selection, of the Gaussians g0, g0 + 1, ...);
 // OUT = 1 writes the preconditioner target of the row: with d = B_jj,
 // D = max(d, floor) and the damped block B + lambda diag(D), the row-sum
 // scaling t = log(D / (sum_i |B_ji| + lambda D)) and the observed flag d > 0.
 template <int DEG, int OUT>
 __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float* __restrict__ gvgram,
-                                                      const int64_t* __restrict__ sel, int64_t n_rows, float lam,
-                                                      float floor_, float* __restrict__ o0, float* __restrict__ o1) {
+                                                      const int64_t* __restrict__ sel, int64_t g0, int64_t n_rows,
+                                                      float lam, float floor_, float* __restrict__ o0,
+                                                      float* __restrict__ o1) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int P = 11 + 3 * K;
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= n_rows) return;
     const int64_t s = t / P;
     const int j = (int)(t - s * P);
-    const int64_t g = sel ? sel[s] : s;
+    const int64_t g = sel ? sel[s] : g0 + s;
     const int64_t ls = c.lin_stride;
     const bool jgeo = j < 11;
     const int jg = jgeo ? j : 0;                      // in-range index for the geometric loads
@@ -1329,13 +1331,14 @@ hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s) {
 }
 
 hipError_t launch_block_rows(const CacheView& c, const float* gvgram, const int64_t* sel, int64_t n_sel, int out,
-                             float lam, float floor_, float* o0, float* o1, hipStream_t s) {
-    const int64_t n_rows = (sel ? n_sel : c.N) * c.P;
-    if (n_rows == 0) return hipSuccess;
+                             float lam, float floor_, float* o0, float* o1, hipStream_t s, int64_t g0) {
+    const int64_t n_rows = (sel ? n_sel : (n_sel > 0 ? n_sel : c.N - g0)) * c.P;
+    if (n_rows <= 0) return hipSuccess;
     const dim3 g(grid_for(n_rows)), b(kBlock);
-#define LM_B(D)                                                                                               \
-    if (out == 0) hipLaunchKernelGGL((k_block_rows<D, 0>), g, b, 0, s, c, gvgram, sel, n_rows, lam, floor_, o0, o1); \
-    else hipLaunchKernelGGL((k_block_rows<D, 1>), g, b, 0, s, c, gvgram, sel, n_rows, lam, floor_, o0, o1)
+#define LM_B(D)                                                                                                     \
+    if (out == 0) hipLaunchKernelGGL((k_block_rows<D, 0>), g, b, 0, s, c, gvgram, sel, g0, n_rows, lam, floor_, o0, \
+                                     o1);                                                                           \
+    else hipLaunchKernelGGL((k_block_rows<D, 1>), g, b, 0, s, c, gvgram, sel, g0, n_rows, lam, floor_, o0, o1)
     LM_DEG_SWITCH(c.deg, LM_B)
 #undef LM_B
     return hipGetLastError();

@@ -141,7 +141,10 @@ struct lm_cache {
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
     DevBuf gram_redge, gram_rkey, gram_rends;
     DevBuf wres, obj_e, obj_part;
+    DevBuf bj_L, bj_tmp, bj_count;
     bool weighted = false;       // wres holds residual weights for the products
+    bool bj_valid = false;       // bj_L holds the block-Jacobi factors for (bj_lambda, bj_floor)
+    float bj_lambda = 0.0f, bj_floor = 0.0f;
     bool gram_valid = false;     // gvgram holds the Gram values of the current build
     bool compact = false;        // the build-only buffers were released (LM_BUILD_COMPACT)
     DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
@@ -194,7 +197,7 @@ struct lm_cache {
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
-                               &wres, &obj_e, &obj_part,
+                               &wres, &obj_e, &obj_part, &bj_L, &bj_tmp, &bj_count,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -220,7 +223,7 @@ struct lm_cache {
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
-                               &wres, &obj_e, &obj_part,
+                               &wres, &obj_e, &obj_part, &bj_L, &bj_tmp, &bj_count,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -261,6 +264,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_CHECK(scene->N * (int64_t)V < ((int64_t)1 << 32) - 65536, LM_ERR_CAPACITY, "N * V must fit in 32 bits");
     c->built = false;
     c->gram_valid = false;
+    c->bj_valid = false;
     c->compact = false;
     c->weighted = false;
     c->N = scene->N;
@@ -728,6 +732,47 @@ static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
     return LM_OK;
 }
 
+// Block-Jacobi factors of the current build for (lambda, floor), computed
+// on first use: dense blocks of a chunk of Gaussians, then one factorisation
+// per Gaussian.  *n_fallback (host, may be null) receives the number of
+// Gaussians whose block did not factor (Jacobi on those).
+static lm_status ensure_block_precond(lm_cache* cm, float lambda, float floor_, hipStream_t s,
+                                      int32_t* n_fallback) {
+    if (cm->bj_valid && cm->bj_lambda == lambda && cm->bj_floor == floor_ && !n_fallback) return LM_OK;
+    lm_status st = ensure_gram(cm, s);
+    if (st != LM_OK) return st;
+    const int64_t N = cm->N, P = cm->P, T = P * (P + 1) / 2;
+    const int64_t chunk = std::min<int64_t>(N, 131072);
+    LM_HIP(cm->bj_L.ensure(sizeof(float) * T * N));
+    LM_HIP(cm->bj_tmp.ensure(sizeof(float) * P * P * chunk));
+    LM_HIP(cm->bj_count.ensure(sizeof(uint32_t)));
+    LM_HIP(hipMemsetAsync(cm->bj_count.p, 0, sizeof(uint32_t), s));
+    {
+        LM_PROF("block_precond", s);
+        for (int64_t g0 = 0; g0 < N; g0 += chunk) {
+            const int64_t n = std::min(chunk, N - g0);
+            LM_HIP(lm::launch_block_rows(cm->view(), cm->gvgram.as<float>(), nullptr, n, 0, 0.0f, 0.0f,
+                                         cm->bj_tmp.as<float>(), nullptr, s, g0));
+            LM_HIP(lm::launch_bj_factor(cm->bj_tmp.as<float>(), (int)P, g0, n, lambda, floor_, cm->bj_L.as<float>(),
+                                        cm->bj_count.as<uint32_t>(), s));
+        }
+    }
+    cm->bj_valid = true;
+    cm->bj_lambda = lambda;
+    cm->bj_floor = floor_;
+    if (n_fallback) {
+        uint32_t h = 0;
+        LM_HIP(hipMemcpyAsync(&h, cm->bj_count.p, sizeof(h), hipMemcpyDeviceToHost, s));
+        LM_HIP(hipStreamSynchronize(s));
+        *n_fallback = (int32_t)h;
+    }
+    return LM_OK;
+}
+
+static lm::BlockPrecond block_precond_of(const lm_cache* c) {
+    return lm::BlockPrecond{c->bj_L.as<float>(), c->N, c->P};
+}
+
 lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
     lm::StreamScope lm_stream_scope_(S(stream));
     LM_CHECK(c && M, LM_ERR_INVALID_ARG, "lm_jacobi_diag: NULL argument");
@@ -847,10 +892,10 @@ lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream)
     return apply_JT_internal(c, u, 1.0f, g, S(stream));
 }
 
-lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
-                       float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
-                       const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
+                                float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
+                                const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats,
+                                void* stream, bool block) {
     LM_CHECK(caches && b && M && delta && n_b > 0, LM_ERR_INVALID_ARG, "lm_pcg_solve: NULL argument");
     LM_CHECK(n_b <= lm::kMaxBatch, LM_ERR_INVALID_ARG, "lm_pcg_solve: at most 8 subsets per call");
     LM_CHECK(n_iters >= 0 && n_iters < LM_PCG_MAX_HISTORY, LM_ERR_INVALID_ARG, "n_iters out of range");
@@ -865,17 +910,25 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
     }
     const int64_t n = caches[0]->N * (int64_t)caches[0]->P;
     const int64_t nbc = lm::chain_blocks(caches[0]->N);
+    // block-Jacobi factors of every subset (before any capture)
+    lm::BlockPrecond bjs[lm::kMaxBatch];
+    for (int i = 0; i < n_b && block; ++i) {
+        lm_status st = ensure_block_precond(caches[i], lambda, diag_floor, s, nullptr);
+        if (st != LM_OK) return st;
+        bjs[i] = block_precond_of(caches[i]);
+    }
     // workspaces and x0 = M^-1 b
     for (int i = 0; i < n_b; ++i) {
         lm_cache* c = caches[i];
         const float* sc = precond_scale ? precond_scale[i] : nullptr;
+        const lm::BlockPrecond* bj = block ? &bjs[i] : nullptr;
         LM_HIP(c->pcg_r.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_z.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_p.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_g.ensure(sizeof(float) * n));
         LM_HIP(c->pcg_part.ensure(sizeof(double) * 3 * lm::pcg_partial_count(n)));
         LM_HIP(c->pcg_state.ensure(sizeof(lm::PcgState)));
-        LM_HIP(lm::pcg_init(n, b[i], M[i], diag_floor, sc, delta[i], s));
+        LM_HIP(lm::pcg_init(n, b[i], M[i], diag_floor, sc, delta[i], s, bj));
         LM_HIP(hipMemsetAsync(c->pcg_state.p, 0, sizeof(lm::PcgState), s));
     }
     // r0 = b - A x0 for all subsets in one batched product
@@ -894,7 +947,7 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
         const float* sc = precond_scale ? precond_scale[i] : nullptr;
         LM_HIP(lm::pcg_init_r(n, b[i], c->pcg_g.as<float>(), M[i], diag_floor, sc, c->pcg_r.as<float>(),
                               c->pcg_z.as<float>(), c->pcg_p.as<float>(), c->pcg_part.as<double>(),
-                              c->pcg_state.as<lm::PcgState>(), s));
+                              c->pcg_state.as<lm::PcgState>(), s, block ? &bjs[i] : nullptr));
         B.a[i].p = c->pcg_p.as<float>();
         B.a[i].pg_part = c->pg_part.as<double>();
         B.a[i].stop = &c->pcg_state.as<lm::PcgState>()->stop;
@@ -912,7 +965,7 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
             LM_HIP(lm::pcg_alpha(c->pg_part.as<double>(), nbc, pst, q));
             LM_HIP(lm::pcg_update(n, pst, c->pcg_p.as<float>(), c->pcg_g.as<float>(), M[i], diag_floor, sc, delta[i],
                                   c->pcg_r.as<float>(), c->pcg_z.as<float>(), c->pcg_part.as<double>(), tol, tol_mode,
-                                  q));
+                                  q, block ? &bjs[i] : nullptr));
         }
         return LM_OK;
     };
@@ -964,6 +1017,34 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
         for (int k = 0; k < LM_PCG_MAX_HISTORY; ++k) stats[i].history[k] = k <= hs.iters ? hs.hist[k] : 0.0;
     }
     if (!stats) LM_HIP(hipStreamSynchronize(s));
+    return LM_OK;
+}
+
+lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
+                       float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
+                       const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    return pcg_solve_impl(caches, n_b, b, M, lambda, diag_floor, n_iters, tol, tol_mode, precond_scale, delta, stats,
+                          stream, false);
+}
+
+lm_status lm_pcg_solve_block(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
+                             float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
+                             float* const* delta, lm_pcg_stats* stats, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    return pcg_solve_impl(caches, n_b, b, M, lambda, diag_floor, n_iters, tol, tol_mode, nullptr, delta, stats,
+                          stream, true);
+}
+
+lm_status lm_block_precond_apply(lm_cache* c, float lambda, float diag_floor, const float* r, float* z,
+                                 int32_t* n_fallback, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream));
+    LM_CHECK(c && r && z, LM_ERR_INVALID_ARG, "lm_block_precond_apply: NULL argument");
+    LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
+    LM_CHECK(lambda >= 0.0f && diag_floor >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
+    lm_status st = ensure_block_precond(c, lambda, diag_floor, S(stream), n_fallback);
+    if (st != LM_OK) return st;
+    LM_HIP(lm::launch_bj_apply(block_precond_of(c), r, z, S(stream)));
     return LM_OK;
 }
 
@@ -1234,6 +1315,7 @@ lm_status lm_set_residual_weights(lm_cache* c, const float* w, void* stream) {
     LM_CHECK(c, LM_ERR_INVALID_ARG, "lm_set_residual_weights: NULL cache");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     c->gram_valid = false;
+    c->bj_valid = false;
     if (!w) {
         c->weighted = false;
         return LM_OK;
@@ -1255,6 +1337,7 @@ lm_status lm_cache_objective(lm_cache* c, const float* target, const lm_objectiv
     if (st != LM_OK) return st;
     hipStream_t s = S(stream);
     c->gram_valid = false;
+    c->bj_valid = false;
     if (obj->kind == LM_OBJ_L2) {
         c->weighted = false;
         if (E) LM_HIP(lm::view_sum_f64(c->cams.as<lm::CamDev>(), c->V, c->fsq_part.as<double>(), E, s));

@@ -292,9 +292,10 @@ hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* ed
                        float* run_edge, uint32_t* run_ekey, uint32_t* run_eends, hipStream_t s);
 hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s);
 hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* coverage, hipStream_t s);
-// out 0: dense blocks of the selected Gaussians; out 1: targets and mask [P][N]
+// out 0: dense blocks [n][P][P] of the selected Gaussians, or without a
+// selection of the n_sel Gaussians from g0 on; out 1: targets and mask [P][N]
 hipError_t launch_block_rows(const CacheView& c, const float* gvgram, const int64_t* sel, int64_t n_sel, int out,
-                             float lam, float floor_, float* o0, float* o1, hipStream_t s);
+                             float lam, float floor_, float* o0, float* o1, hipStream_t s, int64_t g0 = 0);
 // t <- mu_j + beta (t - mu_j) on observed entries; scratch: shrink_scratch_doubles(P)
 int64_t shrink_scratch_doubles(int P);
 hipError_t launch_target_shrink(float* t, const float* mask, int64_t N, int P, float beta, double* scratch,
@@ -334,15 +335,27 @@ hipError_t launch_objective(const ObjectiveArgs& a, hipStream_t s);
 // out[v] = E of view v from the partials of launch_objective over views 0..V-1
 hipError_t launch_objective_view_sums(const CamDev* cams, int V, const double* part, double* out, hipStream_t s);
 // pcg.hip
+// Block-Jacobi factors: packed lower Cholesky factors of the damped
+// per-Gaussian blocks, L[g][P (P + 1) / 2]; bj == null means Jacobi.
+struct BlockPrecond {
+    const float* L;
+    int64_t N;
+    int P;
+};
 int64_t pcg_partial_count(int64_t n);
 hipError_t pcg_init(int64_t n, const float* b, const float* M, float floor_, const float* scale, float* x,
-                    hipStream_t s);
+                    hipStream_t s, const BlockPrecond* bj = nullptr);
 hipError_t pcg_init_r(int64_t n, const float* b, const float* g, const float* M, float floor_, const float* scale,
-                      float* r, float* z, float* p, double* part, PcgState* st, hipStream_t s);
+                      float* r, float* z, float* p, double* part, PcgState* st, hipStream_t s,
+                      const BlockPrecond* bj = nullptr);
 hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_t s);
 hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, float floor_,
                       const float* scale, float* x, float* r, float* z, double* part, double tol, int tol_mode,
-                      hipStream_t s);
+                      hipStream_t s, const BlockPrecond* bj = nullptr);
+// factor the dense damped blocks [n][P][P] of Gaussians g0 .. g0 + n - 1 into L
+hipError_t launch_bj_factor(const float* blocks, int P, int64_t g0, int64_t n, float lam, float floor_, float* L,
+                            uint32_t* n_fallback, hipStream_t s);
+hipError_t launch_bj_apply(const BlockPrecond& bj, const float* r, float* z, hipStream_t s);
 hipError_t launch_combine(int n_b, const float* const* d, const float* const* m, int64_t n, float* out,
                           hipStream_t s);
 

@@ -43,14 +43,17 @@ def random_direction(P, N, seed, block=None):
     return p
 
 
-def pcg_direction_bar(J, b, M, lam, n_iters, eps=1e-6, trials=3, diag_floor=0.0, tol=0.0, tol_mode=0):
+def pcg_direction_bar(J, b, M, lam, n_iters, eps=1e-6, trials=3, diag_floor=0.0, tol=0.0, tol_mode=0,
+                      precond=None, precond_eps=0.0):
     """Tolerance for a float32 PCG direction, derived from the problem's own
     sensitivity: the oracle reruns Algorithm 1 with every J^T J product
     perturbed element-wise by relative noise of size eps (the float32 budget
     of one product: ~10 accumulated roundings of 2^-24), and the bar is the
     largest change of the direction over the trials, never below 1e-4: a
-    direction within it is indistinguishable from float32 product rounding."""
-    base = solve.pcg(J.apply_JtJ, b, M, lam, n_iters, tol, tol_mode, diag_floor=diag_floor)["x"]
+    direction within it is indistinguishable from float32 product rounding.
+    With a block preconditioner its output is perturbed by relative noise of
+    size precond_eps as well (the float32 factorisation's error)."""
+    base = solve.pcg(J.apply_JtJ, b, M, lam, n_iters, tol, tol_mode, diag_floor=diag_floor, precond=precond)["x"]
     worst = 0.0
     for t in range(trials):
         rng = np.random.default_rng(1000 + t)
@@ -58,7 +61,13 @@ def pcg_direction_bar(J, b, M, lam, n_iters, eps=1e-6, trials=3, diag_floor=0.0,
         def A(v):
             y = J.apply_JtJ(v)
             return y * (1.0 + eps * rng.standard_normal(y.shape))
-        x = solve.pcg(A, b, M, lam, n_iters, tol, tol_mode, diag_floor=diag_floor)["x"]
+
+        pre = None
+        if precond is not None:
+            def pre(v):
+                y = precond(v)
+                return y * (1.0 + precond_eps * rng.standard_normal(y.shape))
+        x = solve.pcg(A, b, M, lam, n_iters, tol, tol_mode, diag_floor=diag_floor, precond=pre)["x"]
         worst = max(worst, rel(x, base))
     return max(1e-4, worst)
 
