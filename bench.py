@@ -373,6 +373,24 @@ def bench_learned(args, B, sg, torch) -> dict:
         res[name] = dict(iters=int(st[0]["iters"]), ms=round(ms, 2),
                          rel_res=float(np.sqrt(st[0]["history"][-1])))
         log(f"{name}: {res[name]['iters']} iterations, {ms:.1f} ms")
+    # block-Jacobi (exact per-Gaussian damped blocks): factorisation timed on
+    # its own (a call that recomputes the factors and synchronises), then the
+    # solve with the factors kept
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, n_bj_fallback = B.lm_block_precond_apply(ws["cache"], ws["b"], lam, floor, count_fallback=True)
+    factor_ms = (time.perf_counter() - t0) * 1e3
+    B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE, diag_floor=floor,
+                   block=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    _, st = B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE,
+                           diag_floor=floor, block=True)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3
+    res["block_jacobi"] = dict(iters=int(st[0]["iters"]), ms=round(ms, 2), factor_ms=round(factor_ms, 2),
+                               rel_res=float(np.sqrt(st[0]["history"][-1])), n_fallback=n_bj_fallback)
+    log(f"block_jacobi: {res['block_jacobi']['iters']} iterations, {ms:.1f} ms + factors {factor_ms:.1f} ms")
     ws["cache"].destroy()
     j, l_ = res["jacobi"], res["learned"]
     return {
@@ -392,7 +410,7 @@ def bench_learned(args, B, sg, torch) -> dict:
                                 f"{W}x{H} (of the workload's four), {args.cache_dtype} cache"),
                    "N": int(cfg["N"]), "views": V, "width": W, "height": H, "lambda": lam, "diag_floor": floor,
                    "tol_relative": tol},
-        "jacobi": j, "learned": l_, "exact_target": res["exact_target"],
+        "jacobi": j, "learned": l_, "exact_target": res["exact_target"], "block_jacobi": res["block_jacobi"],
         "features_and_forward_ms": round(pre_ms, 3),
         "speedup_vs_jacobi": round(j["ms"] / (l_["ms"] + pre_ms), 3),
         "training": {"samples": 300_000, "steps": n_steps, "ms_per_step": round(train_ms, 3),
@@ -414,6 +432,8 @@ def main() -> int:
     ap.add_argument("--N", type=int, default=None, help="override the number of Gaussians")
     ap.add_argument("--views", type=int, default=None, help="override the views of the subset")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--precond", default="jacobi", choices=["jacobi", "block"],
+                    help="Jacobi (Algorithm 1) or the per-Gaussian block-Jacobi preconditioner")
     ap.add_argument("--objective", default="l2", choices=["l2", "l1_ssim"],
                     help="least-squares RGB residuals (the configured workload) or the paper's square-root "
                          "L1 / SSIM residuals")
@@ -485,7 +505,7 @@ def main() -> int:
     from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
     solver = LMSolver(x, scene.sh_degree, cams, target,
                       LMConfig(lam=lam, n_iters=n_iters, tile=(tw, th), cache_dtype=args.cache_dtype,
-                               objective=args.objective))
+                               objective=args.objective, precond=args.precond))
 
     def show(tag, rec):
         log(f"{tag}: E {rec['E0']:.4g} -> {rec['E1']:.4g} gamma {rec['gamma']:g} rho {rec['rho']:.3g} "
@@ -542,8 +562,8 @@ def main() -> int:
         "config": {
             "workload": (f"LM iteration, {'plain method' if args.objective == 'l2' else 'square-root L1/SSIM objective'}: "
                          f"{scene.N} Gaussians SH{scene.sh_degree}, {V} views "
-                         f"{W}x{H} in one subset, {args.cache_dtype} cache, {n_iters} Jacobi-PCG iterations"),
-            "objective": args.objective,
+                         f"{W}x{H} in one subset, {args.cache_dtype} cache, {n_iters} {'Jacobi' if args.precond == 'jacobi' else 'block-Jacobi'}-PCG iterations"),
+            "objective": args.objective, "precond": args.precond,
             "N": scene.N, "P": scene.P, "views": V, "width": W, "height": H, "tile": f"{tw}x{th}",
             "tile_autotune": tile_scores,
             "cache_dtype": args.cache_dtype, "pcg_iters": n_iters, "lambda": lam,

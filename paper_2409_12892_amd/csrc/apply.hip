@@ -973,34 +973,16 @@ __global__ void __launch_bounds__(kBlock) k_coverage(CacheView c, const float* _
 }
 
 
-// Row j of the block B_k = J_k^T J_k of one Gaussian over its P parameters.
-// In the 9 slots of a (Gaussian, view) (six power coefficients, three
-// colours) the unit tangent of parameter j has coefficients co_j, and the
-// slot Gram matrix is G = [[Bbb, Ebd], [Ebd^T, diag(E2)]], so
-// B_ji = sum over views of co_j^T G co_i.  One thread per (Gaussian, row),
-// rows of a Gaussian adjacent, so the view data is read once per wave.
-// OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P];
-// without a selection, of the Gaussians g0, g0 + 1, ...);
-// OUT = 1 writes the preconditioner target of the row: with d = B_jj,
-// D = max(d, floor) and the damped block B + lambda diag(D), the row-sum
-// scaling t = log(D / (sum_i |B_ji| + lambda D)) and the observed flag d > 0.
-template <int DEG, int OUT>
-__global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float* __restrict__ gvgram,
-                                                      const int64_t* __restrict__ sel, int64_t g0, int64_t n_rows,
-                                                      float lam, float floor_, float* __restrict__ o0,
-                                                      float* __restrict__ o1) {
+// Row j of the block B_g = J_g^T J_g of Gaussian g into r (see k_block_rows).
+template <int DEG>
+__device__ __forceinline__ void block_row(const CacheView& c, const float* __restrict__ gvgram, int64_t g, int j,
+                                          float (&r)[11 + 3 * (DEG + 1) * (DEG + 1)]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int P = 11 + 3 * K;
-    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= n_rows) return;
-    const int64_t s = t / P;
-    const int j = (int)(t - s * P);
-    const int64_t g = sel ? sel[s] : g0 + s;
     const int64_t ls = c.lin_stride;
     const bool jgeo = j < 11;
     const int jg = jgeo ? j : 0;                      // in-range index for the geometric loads
     const int jk = jgeo ? 0 : (j - 11) / 3, jch = jgeo ? -1 : (j - 11) % 3;
-    float r[P];
 #pragma unroll
     for (int i = 0; i < P; ++i) r[i] = 0.0f;
     const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
@@ -1049,6 +1031,33 @@ __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float*
             for (int k = 0; k < K; ++k) r[11 + 3 * k + ch] += wc * c.lin[(int64_t)(kLinY + k) * ls + gv];
         }
     }
+}
+
+// Row j of the block B_k = J_k^T J_k of one Gaussian over its P parameters.
+// In the 9 slots of a (Gaussian, view) (six power coefficients, three
+// colours) the unit tangent of parameter j has coefficients co_j, and the
+// slot Gram matrix is G = [[Bbb, Ebd], [Ebd^T, diag(E2)]], so
+// B_ji = sum over views of co_j^T G co_i.  One thread per (Gaussian, row),
+// rows of a Gaussian adjacent, so the view data is read once per wave.
+// OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P];
+// without a selection, of the Gaussians g0, g0 + 1, ...);
+// OUT = 1 writes the preconditioner target of the row: with d = B_jj,
+// D = max(d, floor) and the damped block B + lambda diag(D), the row-sum
+// scaling t = log(D / (sum_i |B_ji| + lambda D)) and the observed flag d > 0.
+template <int DEG, int OUT>
+__global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float* __restrict__ gvgram,
+                                                      const int64_t* __restrict__ sel, int64_t g0, int64_t n_rows,
+                                                      float lam, float floor_, float* __restrict__ o0,
+                                                      float* __restrict__ o1) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int P = 11 + 3 * K;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= n_rows) return;
+    const int64_t s = t / P;
+    const int j = (int)(t - s * P);
+    const int64_t g = sel ? sel[s] : g0 + s;
+    float r[P];
+    block_row<DEG>(c, gvgram, g, j, r);
     if (OUT == 0) {
         float* row = o0 + (s * P + j) * P;
 #pragma unroll
@@ -1065,6 +1074,70 @@ __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float*
         o0[(int64_t)j * c.N + g] = obs ? logf(D / (sum + lam * D)) : 0.0f;
         o1[(int64_t)j * c.N + g] = obs ? 1.0f : 0.0f;
     }
+}
+
+// Block-Jacobi factors.  Per Gaussian the damped block
+// A = B + lambda diag(max(d, floor)) of its own parameters (d = diag(B); a
+// parameter with d = 0 keeps a unit diagonal and no coupling) is factored
+// A = L L^T in registers: one wave per Gaussian, lane i computes row i of B
+// (block_row) and owns row i of the factor; each step broadcasts the pivot
+// and the new column with lane reads.  A non-positive pivot falls back to
+// the damped diagonal (Jacobi on this Gaussian).  L is stored packed lower,
+// structure-of-arrays L[i (i + 1) / 2 + j][N], with 1 / L_ii on the
+// diagonal; the 8 Gaussians of a workgroup are consecutive, so their stores
+// to a row of L fill 32-byte sectors together.
+constexpr int kBjWaves = 8;
+
+template <int DEG>
+__global__ void __launch_bounds__(kBjWaves * kWave) k_bj_factor(CacheView c, const float* __restrict__ gvgram,
+                                                                float lam, float floor_, float* __restrict__ L,
+                                                                uint32_t* __restrict__ n_fallback) {
+    constexpr int K = (DEG + 1) * (DEG + 1);
+    constexpr int P = 11 + 3 * K;
+    const int lane = __lane_id();
+    const int64_t g = (int64_t)blockIdx.x * kBjWaves + threadIdx.x / kWave;
+    if (g >= c.N) return;                              // whole waves
+    const int64_t N = c.N;
+    float a[P];
+    block_row<DEG>(c, gvgram, g, lane < P ? lane : P - 1, a);
+    float d = 0.0f;
+#pragma unroll
+    for (int i = 0; i < P; ++i) d = i == lane ? a[i] : d;
+    const uint64_t obs = __ballot(lane < P && d > 0.0f);
+    const bool mine = (obs >> lane) & 1ull;
+#pragma unroll
+    for (int i = 0; i < P; ++i)
+        if (!mine || !((obs >> i) & 1ull)) a[i] = 0.0f;
+    const float dd = mine ? d + lam * fmaxf(d, floor_) : 1.0f;
+#pragma unroll
+    for (int i = 0; i < P; ++i) a[i] = i == lane ? dd : a[i];
+    bool ok = true;
+#pragma unroll
+    for (int k = 0; k < P; ++k) {
+        const float akk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[k]), k));
+        ok = ok && akk > 0.0f && akk < INFINITY;
+        const float lkk = sqrtf(fmaxf(akk, 1e-30f));
+        const float inv = 1.0f / lkk;
+        a[k] = lane == k ? lkk : (lane > k ? a[k] * inv : a[k]);
+#pragma unroll
+        for (int j = k + 1; j < P; ++j) {
+            const float ljk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(a[k]), j));
+            if (lane >= j) a[j] -= a[k] * ljk;
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+    if (lane < P) {
+        const int64_t row = (int64_t)(lane * (lane + 1) / 2);
+#pragma unroll
+        for (int j = 0; j < P; ++j) {
+            if (j > lane) continue;
+            float v;
+            if (j == lane) v = ok ? 1.0f / a[j] : 1.0f / sqrtf(dd);
+            else v = ok ? a[j] : 0.0f;
+            L[(row + j) * N + g] = v;
+        }
+    }
+    if (!ok && lane == 0) atomicAdd(n_fallback, 1u);
 }
 
 // Shrinkage of the targets towards their per-parameter mean over the
@@ -1341,6 +1414,19 @@ hipError_t launch_block_rows(const CacheView& c, const float* gvgram, const int6
     else hipLaunchKernelGGL((k_block_rows<D, 1>), g, b, 0, s, c, gvgram, sel, g0, n_rows, lam, floor_, o0, o1)
     LM_DEG_SWITCH(c.deg, LM_B)
 #undef LM_B
+    return hipGetLastError();
+}
+
+hipError_t launch_bj_factor(const CacheView& c, const float* gvgram, float lam, float floor_, float* L,
+                            uint32_t* n_fallback, hipStream_t s) {
+    if (c.N == 0) return hipSuccess;
+    const dim3 g((unsigned)((c.N + kBjWaves - 1) / kBjWaves)), b(kBjWaves * kWave);
+    switch (c.deg) {
+        case 0: hipLaunchKernelGGL(k_bj_factor<0>, g, b, 0, s, c, gvgram, lam, floor_, L, n_fallback); break;
+        case 1: hipLaunchKernelGGL(k_bj_factor<1>, g, b, 0, s, c, gvgram, lam, floor_, L, n_fallback); break;
+        case 2: hipLaunchKernelGGL(k_bj_factor<2>, g, b, 0, s, c, gvgram, lam, floor_, L, n_fallback); break;
+        default: hipLaunchKernelGGL(k_bj_factor<3>, g, b, 0, s, c, gvgram, lam, floor_, L, n_fallback); break;
+    }
     return hipGetLastError();
 }
 

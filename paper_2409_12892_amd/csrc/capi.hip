@@ -141,7 +141,7 @@ struct lm_cache {
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
     DevBuf gram_redge, gram_rkey, gram_rends;
     DevBuf wres, obj_e, obj_part;
-    DevBuf bj_L, bj_tmp, bj_count;
+    DevBuf bj_L, bj_count;
     bool weighted = false;       // wres holds residual weights for the products
     bool bj_valid = false;       // bj_L holds the block-Jacobi factors for (bj_lambda, bj_floor)
     float bj_lambda = 0.0f, bj_floor = 0.0f;
@@ -197,7 +197,7 @@ struct lm_cache {
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                                &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
-                               &wres, &obj_e, &obj_part, &bj_L, &bj_tmp, &bj_count,
+                               &wres, &obj_e, &obj_part, &bj_L, &bj_count,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -223,7 +223,7 @@ struct lm_cache {
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
                          &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
-                               &wres, &obj_e, &obj_part, &bj_L, &bj_tmp, &bj_count,
+                               &wres, &obj_e, &obj_part, &bj_L, &bj_count,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -733,8 +733,7 @@ static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
 }
 
 // Block-Jacobi factors of the current build for (lambda, floor), computed
-// on first use: dense blocks of a chunk of Gaussians, then one factorisation
-// per Gaussian.  *n_fallback (host, may be null) receives the number of
+// on first use (one factorisation per Gaussian from the Gram values).  *n_fallback (host, may be null) receives the number of
 // Gaussians whose block did not factor (Jacobi on those).
 static lm_status ensure_block_precond(lm_cache* cm, float lambda, float floor_, hipStream_t s,
                                       int32_t* n_fallback) {
@@ -742,20 +741,13 @@ static lm_status ensure_block_precond(lm_cache* cm, float lambda, float floor_, 
     lm_status st = ensure_gram(cm, s);
     if (st != LM_OK) return st;
     const int64_t N = cm->N, P = cm->P, T = P * (P + 1) / 2;
-    const int64_t chunk = std::min<int64_t>(N, 131072);
     LM_HIP(cm->bj_L.ensure(sizeof(float) * T * N));
-    LM_HIP(cm->bj_tmp.ensure(sizeof(float) * P * P * chunk));
     LM_HIP(cm->bj_count.ensure(sizeof(uint32_t)));
     LM_HIP(hipMemsetAsync(cm->bj_count.p, 0, sizeof(uint32_t), s));
     {
         LM_PROF("block_precond", s);
-        for (int64_t g0 = 0; g0 < N; g0 += chunk) {
-            const int64_t n = std::min(chunk, N - g0);
-            LM_HIP(lm::launch_block_rows(cm->view(), cm->gvgram.as<float>(), nullptr, n, 0, 0.0f, 0.0f,
-                                         cm->bj_tmp.as<float>(), nullptr, s, g0));
-            LM_HIP(lm::launch_bj_factor(cm->bj_tmp.as<float>(), (int)P, g0, n, lambda, floor_, cm->bj_L.as<float>(),
-                                        cm->bj_count.as<uint32_t>(), s));
-        }
+        LM_HIP(lm::launch_bj_factor(cm->view(), cm->gvgram.as<float>(), lambda, floor_, cm->bj_L.as<float>(),
+                                    cm->bj_count.as<uint32_t>(), s));
     }
     cm->bj_valid = true;
     cm->bj_lambda = lambda;

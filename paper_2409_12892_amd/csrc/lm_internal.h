@@ -336,7 +336,8 @@ hipError_t launch_objective(const ObjectiveArgs& a, hipStream_t s);
 hipError_t launch_objective_view_sums(const CamDev* cams, int V, const double* part, double* out, hipStream_t s);
 // pcg.hip
 // Block-Jacobi factors: packed lower Cholesky factors of the damped
-// per-Gaussian blocks, L[g][P (P + 1) / 2]; bj == null means Jacobi.
+// per-Gaussian blocks, structure-of-arrays L[i (i + 1) / 2 + j][N] with
+// 1 / L_ii in the diagonal slots; bj == null means Jacobi.
 struct BlockPrecond {
     const float* L;
     int64_t N;
@@ -352,8 +353,8 @@ hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_
 hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, float floor_,
                       const float* scale, float* x, float* r, float* z, double* part, double tol, int tol_mode,
                       hipStream_t s, const BlockPrecond* bj = nullptr);
-// factor the dense damped blocks [n][P][P] of Gaussians g0 .. g0 + n - 1 into L
-hipError_t launch_bj_factor(const float* blocks, int P, int64_t g0, int64_t n, float lam, float floor_, float* L,
+// apply.hip: block-Jacobi factors of every Gaussian into L[P (P + 1) / 2][N]
+hipError_t launch_bj_factor(const CacheView& c, const float* gvgram, float lam, float floor_, float* L,
                             uint32_t* n_fallback, hipStream_t s);
 hipError_t launch_bj_apply(const BlockPrecond& bj, const float* r, float* z, hipStream_t s);
 hipError_t launch_combine(int n_b, const float* const* d, const float* const* m, int64_t n, float* out,

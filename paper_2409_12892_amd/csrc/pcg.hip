@@ -160,114 +160,58 @@ __global__ void k_update_p(int64_t n, const PcgState* __restrict__ st, const flo
 }
 
 // ---- block-Jacobi preconditioner ------------------------------------------
-// Per Gaussian the damped block A_k = B_k + lambda diag(max(d, floor)) of
-// the normal equations restricted to its own parameters (d = diag(B_k); a
-// parameter with d = 0 keeps a unit diagonal and no coupling), factored
-// A_k = L_k L_k^T and stored packed lower row-major, L[g][i (i + 1) / 2 + j].
+// Factors (apply.hip, k_bj_factor): per Gaussian the packed lower Cholesky
+// factor of its damped block, structure-of-arrays L[t][N] with
+// t = i (i + 1) / 2 + j, the diagonal slot holding 1 / L_ii.
 
-// One wave per Gaussian: the dense block of a chunk is staged in LDS as
-// float64, damped and factored (right-looking, lane i owns row i); a
-// non-positive pivot falls back to the block's damped diagonal.
-template <int P>
-__global__ void __launch_bounds__(kWave) k_bj_factor(const float* __restrict__ blocks, int64_t g0, int64_t n,
-                                                    float lam, float floor_, float* __restrict__ L,
-                                                    uint32_t* __restrict__ n_fallback) {
-    constexpr int T = P * (P + 1) / 2;
-    __shared__ double A[P][P + 1];
-    __shared__ double sdd[P];
-    const int64_t s = blockIdx.x;
-    const int lane = threadIdx.x;
-    const float* Bk = blocks + s * P * P;
-    for (int i = lane; i < P * P; i += kWave) A[i / P][i % P] = (double)Bk[i];
-    __syncthreads();
-    const double d = lane < P ? A[lane < P ? lane : 0][lane < P ? lane : 0] : 0.0;
-    const uint64_t obs = __ballot(lane < P && d > 0.0);
-    __syncthreads();
-    for (int i = lane; i < P * P; i += kWave) {
-        const int r = i / P, c = i % P;
-        if (!((obs >> r) & 1) || !((obs >> c) & 1)) A[r][c] = 0.0;
-    }
-    __syncthreads();
-    const double dd = lane < P ? (d > 0.0 ? d + (double)lam * fmax(d, (double)floor_) : 1.0) : 1.0;
-    if (lane < P) {
-        A[lane][lane] = dd;
-        sdd[lane] = dd;
-    }
-    __syncthreads();
-    bool ok = true;
-    for (int k = 0; k < P; ++k) {
-        const double akk = A[k][k];
-        if (!(akk > 0.0) || !isfinite(akk)) {
-            ok = false;
-            break;
-        }
-        const double lkk = sqrt(akk);
-        __syncthreads();
-        if (lane == k) A[k][k] = lkk;
-        if (lane > k && lane < P) A[lane][k] /= lkk;
-        __syncthreads();
-        if (lane > k && lane < P) {
-            const double lik = A[lane][k];
-            for (int j = k + 1; j <= lane; ++j) A[lane][j] -= lik * A[j][k];
-        }
-        __syncthreads();
-    }
-    float* Lg = L + (g0 + s) * T;
-    for (int t = lane; t < T; t += kWave) {
-        int i = (int)((sqrt(8.0 * t + 1.0) - 1.0) * 0.5);
-        while ((i + 1) * (i + 2) / 2 <= t) ++i;
-        while (i * (i + 1) / 2 > t) --i;
-        const int j = t - i * (i + 1) / 2;
-        // without a factorisation: the damped diagonal alone (Jacobi on
-        // this Gaussian)
-        Lg[t] = ok ? (float)A[i][j] : (i == j ? (float)sqrt(sdd[i]) : 0.0f);
-    }
-    if (!ok && lane == 0) atomicAdd(n_fallback, 1u);
-}
-
-// z = A^-1 r per Gaussian, one wave per Gaussian over a fixed grid (the PCG
-// partial grid): the factor goes to LDS, lane j holds entry j, and the
-// forward and backward substitutions broadcast each solved entry.  Writes
-// z (and a copy to z2 when given) and the block partials of r . z.
+// z = A^-1 r, one thread per Gaussian over a fixed grid (the PCG partial
+// grid): forward substitution L y = r, then backward L^T z = y, both
+// walking the factor row by row (coalesced across the wave's Gaussians;
+// the factor is read twice).  The thread's vector lives in LDS, one column
+// per thread (conflict-free).  Writes z (and a copy to z2 when given) and
+// the block partials of r . z.
 template <int P>
 __global__ void __launch_bounds__(kBlock) k_bj_solve(const float* __restrict__ L, int64_t N,
                                                    const float* __restrict__ r, float* __restrict__ z,
                                                    float* __restrict__ z2, double* __restrict__ part,
                                                    const PcgState* __restrict__ st) {
     if (st && st->stop) return;
-    constexpr int T = P * (P + 1) / 2;
-    constexpr int NW = kBlock / kWave;
-    __shared__ float sL[NW][T];
-    const int lane = __lane_id(), w = threadIdx.x / kWave;
+    __shared__ float sy[P][kBlock];
+    float* y = &sy[0][threadIdx.x];
     double acc[1] = {0.0};
-    for (int64_t g = (int64_t)blockIdx.x * NW + w; g < N; g += (int64_t)gridDim.x * NW) {
-        const float* Lg = L + g * T;
-        for (int t = lane; t < T; t += kWave) sL[w][t] = Lg[t];
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        const float rj = lane < P ? r[(int64_t)lane * N + g] : 0.0f;
-        float y = rj;
-        for (int k = 0; k < P; ++k) {
-            const float yk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), k)) /
-                             sL[w][k * (k + 1) / 2 + k];
-            if (lane == k) y = yk;
-            else if (lane > k && lane < P) y -= sL[w][lane * (lane + 1) / 2 + k] * yk;
+    for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < N; g += (int64_t)gridDim.x * kBlock) {
+#pragma unroll 1
+        for (int i = 0; i < P; ++i) y[i * kBlock] = r[(int64_t)i * N + g];
+        const float* Lp = L + g;
+#pragma unroll 1
+        for (int i = 0; i < P; ++i) {
+            float v = y[i * kBlock];
+#pragma unroll 16
+            for (int j = 0; j < i; ++j) {
+                v -= *Lp * y[j * kBlock];
+                Lp += N;
+            }
+            y[i * kBlock] = v * *Lp;
+            Lp += N;
         }
-        for (int k = P - 1; k >= 0; --k) {
-            const float zk = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(y), k)) /
-                             sL[w][k * (k + 1) / 2 + k];
-            if (lane == k) y = zk;
-            else if (lane < k) y -= sL[w][k * (k + 1) / 2 + lane] * zk;
+#pragma unroll 1
+        for (int i = P - 1; i >= 0; --i) {
+            const float* Lr = L + (int64_t)(i * (i + 1) / 2) * N + g;
+            const float zi = y[i * kBlock] * Lr[(int64_t)i * N];
+            y[i * kBlock] = zi;
+#pragma unroll 16
+            for (int j = 0; j < i; ++j) {
+                y[j * kBlock] -= *Lr * zi;
+                Lr += N;
+            }
         }
-        if (lane < P) {
-            z[(int64_t)lane * N + g] = y;
-            if (z2) z2[(int64_t)lane * N + g] = y;
-            acc[0] += (double)rj * y;
+#pragma unroll 1
+        for (int i = 0; i < P; ++i) {
+            const float zi = y[i * kBlock];
+            z[(int64_t)i * N + g] = zi;
+            if (z2) z2[(int64_t)i * N + g] = zi;
+            acc[0] += (double)r[(int64_t)i * N + g] * zi;
         }
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
     }
     if (part) block_partials<1>(acc, part, gridDim.x);
 }
@@ -317,20 +261,6 @@ unsigned vec_grid(int64_t n) {
 }  // namespace
 
 int64_t pcg_partial_count(int64_t n) { return vec_grid(n); }
-
-hipError_t launch_bj_factor(const float* blocks, int P, int64_t g0, int64_t n, float lam, float floor_, float* L,
-                            uint32_t* n_fallback, hipStream_t s) {
-    if (n <= 0) return hipSuccess;
-    const dim3 g((unsigned)n), b(kWave);
-    switch (P) {
-        case 14: hipLaunchKernelGGL(k_bj_factor<14>, g, b, 0, s, blocks, g0, n, lam, floor_, L, n_fallback); break;
-        case 23: hipLaunchKernelGGL(k_bj_factor<23>, g, b, 0, s, blocks, g0, n, lam, floor_, L, n_fallback); break;
-        case 38: hipLaunchKernelGGL(k_bj_factor<38>, g, b, 0, s, blocks, g0, n, lam, floor_, L, n_fallback); break;
-        case 59: hipLaunchKernelGGL(k_bj_factor<59>, g, b, 0, s, blocks, g0, n, lam, floor_, L, n_fallback); break;
-        default: return hipErrorInvalidValue;
-    }
-    return hipGetLastError();
-}
 
 hipError_t launch_bj_apply(const BlockPrecond& bj, const float* r, float* z, hipStream_t s) {
     return bj_solve(bj, r, z, nullptr, nullptr, nullptr, vec_grid(bj.N * bj.P), s);

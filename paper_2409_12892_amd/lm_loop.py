@@ -59,6 +59,7 @@ class LMConfig:
     tile: tuple = (16, 16)
     cache_dtype: str = "f32"
     objective: str = "l2"           # "l2" or "l1_ssim"
+    precond: str = "jacobi"         # "jacobi" (Algorithm 1) or "block" (per-Gaussian block-Jacobi)
     obj_eps: float = B.OBJ_EPS
 
 
@@ -127,7 +128,7 @@ class LMSolver:
         self.M = B.lm_jacobi_diag(self.cache, out=self.M)
         deltas, stats = B.lm_pcg_solve([self.cache], [b], [self.M], self.lam, cfg.n_iters, cfg.tol, cfg.tol_mode,
                                        deltas=None if self.delta is None else [self.delta],
-                                       diag_floor=cfg.diag_floor)
+                                       diag_floor=cfg.diag_floor, block=cfg.precond == "block")
         self.delta = deltas[0]
         self.comb = B.lm_combine_subsets([self.delta], [self.M], out=self.comb)
         d = self.comb
