@@ -1083,9 +1083,9 @@ __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float*
 // (block_row) and owns row i of the factor; each step broadcasts the pivot
 // and the new column with lane reads.  A non-positive pivot falls back to
 // the damped diagonal (Jacobi on this Gaussian).  L is stored packed lower,
-// structure-of-arrays L[i (i + 1) / 2 + j][N], with 1 / L_ii on the
-// diagonal; the 8 Gaussians of a workgroup are consecutive, so their stores
-// to a row of L fill 32-byte sectors together.
+// element t = i (i + 1) / 2 + j with 1 / L_ii on the diagonal, in tiles of
+// 64 Gaussians, L[g / 64][t][g % 64]; the 8 Gaussians of a workgroup are
+// consecutive, so their stores to an element fill a 32-byte sector together.
 constexpr int kBjWaves = 8;
 
 template <int DEG>
@@ -1127,14 +1127,15 @@ __global__ void __launch_bounds__(kBjWaves * kWave) k_bj_factor(CacheView c, con
         __builtin_amdgcn_sched_barrier(0);
     }
     if (lane < P) {
-        const int64_t row = (int64_t)(lane * (lane + 1) / 2);
+        constexpr int T = P * (P + 1) / 2;
+        float* Lrow = L + ((g >> 6) * (int64_t)T + lane * (lane + 1) / 2) * 64 + (g & 63);
 #pragma unroll
         for (int j = 0; j < P; ++j) {
             if (j > lane) continue;
             float v;
             if (j == lane) v = ok ? 1.0f / a[j] : 1.0f / sqrtf(dd);
             else v = ok ? a[j] : 0.0f;
-            L[(row + j) * N + g] = v;
+            Lrow[j * 64] = v;
         }
     }
     if (!ok && lane == 0) atomicAdd(n_fallback, 1u);

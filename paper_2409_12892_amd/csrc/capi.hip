@@ -741,7 +741,7 @@ static lm_status ensure_block_precond(lm_cache* cm, float lambda, float floor_, 
     lm_status st = ensure_gram(cm, s);
     if (st != LM_OK) return st;
     const int64_t N = cm->N, P = cm->P, T = P * (P + 1) / 2;
-    LM_HIP(cm->bj_L.ensure(sizeof(float) * T * N));
+    LM_HIP(cm->bj_L.ensure(sizeof(float) * T * ((N + 63) / 64) * 64));
     LM_HIP(cm->bj_count.ensure(sizeof(uint32_t)));
     LM_HIP(hipMemsetAsync(cm->bj_count.p, 0, sizeof(uint32_t), s));
     {

@@ -336,8 +336,9 @@ hipError_t launch_objective(const ObjectiveArgs& a, hipStream_t s);
 hipError_t launch_objective_view_sums(const CamDev* cams, int V, const double* part, double* out, hipStream_t s);
 // pcg.hip
 // Block-Jacobi factors: packed lower Cholesky factors of the damped
-// per-Gaussian blocks, structure-of-arrays L[i (i + 1) / 2 + j][N] with
-// 1 / L_ii in the diagonal slots; bj == null means Jacobi.
+// per-Gaussian blocks, element t = i (i + 1) / 2 + j (1 / L_ii in the
+// diagonal slots) in tiles of 64 Gaussians, L[g / 64][t][g % 64];
+// bj == null means Jacobi.
 struct BlockPrecond {
     const float* L;
     int64_t N;
@@ -353,7 +354,7 @@ hipError_t pcg_alpha(const double* pg_part, int64_t nb, PcgState* st, hipStream_
 hipError_t pcg_update(int64_t n, PcgState* st, float* p, const float* g, const float* M, float floor_,
                       const float* scale, float* x, float* r, float* z, double* part, double tol, int tol_mode,
                       hipStream_t s, const BlockPrecond* bj = nullptr);
-// apply.hip: block-Jacobi factors of every Gaussian into L[P (P + 1) / 2][N]
+// apply.hip: block-Jacobi factors of every Gaussian into L (64-Gaussian tiles)
 hipError_t launch_bj_factor(const CacheView& c, const float* gvgram, float lam, float floor_, float* L,
                             uint32_t* n_fallback, hipStream_t s);
 hipError_t launch_bj_apply(const BlockPrecond& bj, const float* r, float* z, hipStream_t s);

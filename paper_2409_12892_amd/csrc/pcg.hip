@@ -161,8 +161,9 @@ __global__ void k_update_p(int64_t n, const PcgState* __restrict__ st, const flo
 
 // ---- block-Jacobi preconditioner ------------------------------------------
 // Factors (apply.hip, k_bj_factor): per Gaussian the packed lower Cholesky
-// factor of its damped block, structure-of-arrays L[t][N] with
-// t = i (i + 1) / 2 + j, the diagonal slot holding 1 / L_ii.
+// factor of its damped block, element t = i (i + 1) / 2 + j (the diagonal
+// slot holding 1 / L_ii), stored in tiles of 64 Gaussians,
+// L[g / 64][t][g % 64]: a wave's 64 Gaussians read one contiguous tile.
 
 // z = A^-1 r, one thread per Gaussian over a fixed grid (the PCG partial
 // grid): forward substitution L y = r, then backward L^T z = y, both
@@ -182,27 +183,29 @@ __global__ void __launch_bounds__(kBlock) k_bj_solve(const float* __restrict__ L
     for (int64_t g = (int64_t)blockIdx.x * kBlock + threadIdx.x; g < N; g += (int64_t)gridDim.x * kBlock) {
 #pragma unroll 1
         for (int i = 0; i < P; ++i) y[i * kBlock] = r[(int64_t)i * N + g];
-        const float* Lp = L + g;
+        constexpr int T = P * (P + 1) / 2;
+        const float* Lt = L + (g >> 6) * (int64_t)T * 64 + (g & 63);
+        const float* Lp = Lt;
 #pragma unroll 1
         for (int i = 0; i < P; ++i) {
             float v = y[i * kBlock];
-#pragma unroll 16
+#pragma unroll 8
             for (int j = 0; j < i; ++j) {
                 v -= *Lp * y[j * kBlock];
-                Lp += N;
+                Lp += 64;
             }
             y[i * kBlock] = v * *Lp;
-            Lp += N;
+            Lp += 64;
         }
 #pragma unroll 1
         for (int i = P - 1; i >= 0; --i) {
-            const float* Lr = L + (int64_t)(i * (i + 1) / 2) * N + g;
-            const float zi = y[i * kBlock] * Lr[(int64_t)i * N];
+            const float* Lr = Lt + (int64_t)(i * (i + 1) / 2) * 64;
+            const float zi = y[i * kBlock] * Lr[i * 64];
             y[i * kBlock] = zi;
-#pragma unroll 16
+#pragma unroll 8
             for (int j = 0; j < i; ++j) {
                 y[j * kBlock] -= *Lr * zi;
-                Lr += N;
+                Lr += 64;
             }
         }
 #pragma unroll 1
