@@ -73,6 +73,35 @@ def test_graph_replay_matches_eager_and_repeats(batch):
             assert rel(d_g, d_e) < 1e-5, rep
 
 
+def test_batched_block_jacobi_graph_matches_single_solves_and_oracle(batch, report):
+    """Block-Jacobi through the batched, graph-replayed solve: every subset's
+    direction equals its own single-subset solve, and subset 0 matches the
+    oracle's Algorithm 1 with the block preconditioner."""
+    from oracle import precond
+    B = batch["B"]
+    subs = batch["subs"]
+    lam, floor = 1e-2, 1e-2
+    B.lm_pcg_use_graph(1)
+    deltas, stats = B.lm_pcg_solve([s_["cache"] for s_ in subs], [s_["b"] for s_ in subs],
+                                   [s_["M"] for s_ in subs], lam, 8, diag_floor=floor, block=True)
+    B.lm_pcg_use_graph(0)
+    for i, s_ in enumerate(subs):
+        single, st1 = B.lm_pcg_solve([s_["cache"]], [s_["b"]], [s_["M"]], lam, 8, diag_floor=floor, block=True)
+        assert rel(deltas[i].cpu().numpy(), single[0].cpu().numpy()) < 1e-5, i
+        assert st1[0]["iters"] == stats[i]["iters"]
+    B.lm_pcg_use_graph(2)
+    J = subs[0]["J"]
+    b_o, M_o = J.b(list(subs[0]["target"])), J.diag_JtJ()
+    pre = solve.block_jacobi(precond.gaussian_blocks(J), lam, floor)
+    out = solve.pcg(J.apply_JtJ, b_o, M_o, lam, 8, diag_floor=floor, precond=pre)
+    # the preconditioner's float32 error as in the block-Jacobi parity test,
+    # at a condition number bound of 1e3 for the damped scaled blocks
+    bar = pcg_direction_bar(J, b_o, M_o, lam, 8, diag_floor=floor, precond=pre, precond_eps=1e-2)
+    err = rel(deltas[0].cpu().numpy().ravel(), out["x"])
+    report[("batch_pcg_block", 0)] = dict(err=err, bar=bar)
+    assert err < bar
+
+
 def test_combine_matches_oracle(batch):
     """eq. combine-pcg of the batch's directions against the oracle's combination
     of its own directions and diagonals, within the largest direction bar."""

@@ -95,3 +95,22 @@ def test_lm_iterations_on_the_paper_objective():
         if a["accepted"]:
             assert b["E0"] == pytest.approx(a["E1"], rel=1e-9)
     solver.close()
+
+
+def test_lm_iterations_with_block_jacobi():
+    """The LM loop with the block-Jacobi preconditioner: accepted steps lower
+    the error and at least one step is accepted."""
+    from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
+    pr = make_problem("tiny", with_J=False)
+    sc = pr["scene"]
+    x = torch.from_numpy(sc.x).cuda()
+    tgt = torch.from_numpy(pr["target"].ravel()).cuda()
+    solver = LMSolver(x, sc.sh_degree, pr["cams"], tgt,
+                      LMConfig(lam=1e-2, n_iters=8, line_search_fraction=0.5, precond="block"))
+    recs = [solver.iteration() for _ in range(3)]
+    for r in recs:
+        print(r)
+        if r["accepted"]:
+            assert r["E1"] < r["E0"] and r["rho"] > 1e-5
+    assert any(r["accepted"] for r in recs)
+    solver.close()
