@@ -294,6 +294,33 @@ def bench_batching(args, B, sg, torch) -> dict:
     return out
 
 
+def train_learned_mlp(args, B, torch, subset, cfg, lam, floor):
+    """The perceptron of the learned preconditioner, trained on the GPU on a
+    separate scene of the same generator (other seed, 300k Gaussians, 8 views
+    1280x720) with the shrunk row-sum targets: 300 Adam steps."""
+    log("training scene: 300000 Gaussians, 8 views 1280x720")
+    tr = subset(300_000, (8, 1280, 720), int(cfg["seed"]) + 100)
+    feat = B.lm_precond_features(tr["cache"], tr["x"], tr["M"])
+    t, mask = B.lm_precond_targets(tr["cache"], lam, floor)
+    P = t.shape[0]
+    trainer = B.MlpTrainer(B.mlp_init(P, seed=3), lr=3e-3)
+    loss0, _ = trainer.step(feat, t, mask, lr=0.0)
+    n_steps = 300
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(n_steps):
+        trainer.step(feat, t, mask)
+    torch.cuda.synchronize()
+    train_ms = (time.perf_counter() - t0) * 1e3 / n_steps
+    loss1, _ = trainer.step(feat, t, mask, lr=0.0)
+    log(f"training: loss {loss0.item():.4f} -> {loss1.item():.4f}, {train_ms:.3f} ms per Adam step "
+        f"({feat.shape[1]} samples)")
+    tr["cache"].destroy()
+    del tr, feat, t, mask
+    torch.cuda.empty_cache()
+    return trainer, n_steps, train_ms, loss0, loss1
+
+
 def bench_learned(args, B, sg, torch) -> dict:
     """The learned diagonal preconditioner at the learned-preconditioner
     workload, one subset at full size (3M Gaussians, SH 3, 40 views
@@ -324,26 +351,8 @@ def bench_learned(args, B, sg, torch) -> dict:
         del target
         return dict(scene=sc, x=x, cache=cache, b=b, M=M, build_ms=(t1 - t0) * 1e3)
 
-    log("training scene: 300000 Gaussians, 8 views 1280x720")
-    tr = subset(300_000, (8, 1280, 720), int(cfg["seed"]) + 100)
-    feat = B.lm_precond_features(tr["cache"], tr["x"], tr["M"])
-    t, mask = B.lm_precond_targets(tr["cache"], lam, floor)
-    P = t.shape[0]
-    trainer = B.MlpTrainer(B.mlp_init(P, seed=3), lr=3e-3)
-    loss0, _ = trainer.step(feat, t, mask, lr=0.0)
-    n_steps = 300
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(n_steps):
-        trainer.step(feat, t, mask)
-    torch.cuda.synchronize()
-    train_ms = (time.perf_counter() - t0) * 1e3 / n_steps
-    loss1, _ = trainer.step(feat, t, mask, lr=0.0)
-    log(f"training: loss {loss0.item():.4f} -> {loss1.item():.4f}, {train_ms:.3f} ms per Adam step "
-        f"({feat.shape[1]} samples)")
-    tr["cache"].destroy()
-    del tr, feat, t, mask
-    torch.cuda.empty_cache()
+    trainer, n_steps, train_ms, loss0, loss1 = train_learned_mlp(args, B, torch, subset, cfg, lam, floor)
+    P = sg.n_params(int(cfg["deg"]))
 
     V, W, H = cfg["subsets"][0]
     log(f"workload subset: {cfg['N']} Gaussians, {V} views {W}x{H}")
@@ -420,6 +429,185 @@ def bench_learned(args, B, sg, torch) -> dict:
     }
 
 
+def bench_deploy(args, B, sg, torch) -> dict:
+    """One LM step's solve phase at the learned-preconditioner workload
+    (3M Gaussians, SH 3, four subsets of 40 views 1280x720), to a relative
+    residual of 1e-2 in each subset, in two forms:
+      plain: float32 caches, one subset at a time in one reused cache
+             (build, Jacobi diagonal, Algorithm 1 with Jacobi), then
+             eq. combine-pcg;
+      full:  bfloat16 compact caches sharing one scratch handle for the
+             build transients, subsets held together in groups of
+             --deploy-group (the four together plus the transients exceed
+             288 GB), the learned scaling, one batched graph-replayed
+             Algorithm 1 per group, then eq. combine-pcg;
+      bf16_learned_sequential: bfloat16 and the learned scaling, one subset
+             at a time in one reused cache.
+    The cache handles persist from the warm-up run into the timed run (as in
+    an LM loop), and the library's memory comes from PyTorch's caching
+    allocator (--deploy-alloc torch, the default), so the transients that a
+    compact build releases serve the next build; the perceptron is trained
+    first, outside the timed regions."""
+    cfg = dict(sg.CONFIGS["learned"])
+    lam, floor, tol, max_it = float(cfg["lam"]), 1e-2, 1e-2, 80
+    dev = torch.device("cuda:0")
+
+    def subset(N, views, seed):
+        d = sg.config_scene("learned", N=N, subsets=[views], seed=seed)
+        sc, cams = d["scene"], d["cams"][0]
+        x = torch.from_numpy(sc.x).to(dev)
+        noise = torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev)
+        target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
+        target.add_(noise)
+        cache, b, _ = B.lm_build_cache(x, sc.sh_degree, cams, target, cache_dtype="bf16", compact=True)
+        M = B.lm_jacobi_diag(cache)
+        return dict(scene=sc, x=x, cache=cache, b=b, M=M)
+
+    trainer, n_steps, train_ms, loss0, loss1 = train_learned_mlp(args, B, torch, subset, cfg, lam, floor)
+    if args.deploy_alloc == "torch":
+        B.use_torch_allocator()
+    log("workload: 3000000 Gaussians, 4 subsets of 40 views 1280x720")
+    d = sg.config_scene("learned")
+    sc = d["scene"]
+    P, N = sc.P, sc.N
+    x = torch.from_numpy(sc.x).to(dev)
+    x_star = torch.from_numpy(d["x_star"]).to(dev)
+    targets = []
+    for i, cams in enumerate(d["cams"]):
+        tg = B.lm_render(x_star, sc.sh_degree, cams)
+        tg.add_(torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][i]])).to(dev))
+        targets.append(tg)
+    del x_star, d["noise"]
+    torch.cuda.synchronize()
+    tile = tuple(int(v) for v in (args.tile if args.tile != "auto" else "8x32").split("x"))
+
+    group = max(1, min(4, int(args.deploy_group)))
+    phases = {}
+
+    def mark(name, t0):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        phases[name] = phases.get(name, 0.0) + (t1 - t0) * 1e3
+        return t1
+
+    # cache handles live across the warm-up and the timed run, as in an LM
+    # loop: the timed run allocates nothing new
+    plain_h = [None]
+    full_h = [None] * group + [B.Cache()]          # the last one: scratch of the compact builds
+
+    def sequential(dtype, learned, tag):
+        deltas, Ms, its = [], [], []
+        cache = plain_h[0]
+        for i, cams in enumerate(d["cams"]):
+            t0 = time.perf_counter()
+            cache, b, _ = B.lm_build_cache(x, sc.sh_degree, cams, targets[i], tile=tile, cache_dtype=dtype,
+                                           cache=cache)
+            M = B.lm_jacobi_diag(cache)
+            scales = None
+            if learned:
+                f = B.lm_precond_features(cache, x, M)
+                _, scale, _ = B.lm_mlp_forward(trainer.w, f, P, want_s=False)
+                scales = [scale]
+                del f
+            t0 = mark(f"{tag}_build_diag", t0)
+            dl, st = B.lm_pcg_solve([cache], [b], [M], lam, max_it, tol, B.TOL_RELATIVE, scales=scales,
+                                    diag_floor=floor)
+            mark(f"{tag}_pcg", t0)
+            deltas.append(dl[0])
+            Ms.append(M)
+            its.append(int(st[0]["iters"]))
+            del b
+        out = B.lm_combine_subsets(deltas, Ms)
+        torch.cuda.synchronize()
+        plain_h[0] = cache
+        return out, its, cache.info()["device_bytes"]
+
+    def full():
+        deltas, Ms_all, its, mem = [], [], [], 0
+        handles = full_h
+        for g0 in range(0, 4, group):
+            caches, bs, Ms, scales = [], [], [], []
+            t0 = time.perf_counter()
+            for k, i in enumerate(range(g0, min(4, g0 + group))):
+                cache, b, _ = B.lm_build_cache(x, sc.sh_degree, d["cams"][i], targets[i], tile=tile,
+                                               cache_dtype="bf16", compact=True, cache=handles[k],
+                                               scratch=handles[group])
+                handles[k] = cache
+                M = B.lm_jacobi_diag(cache)
+                f = B.lm_precond_features(cache, x, M)
+                _, scale, _ = B.lm_mlp_forward(trainer.w, f, P, want_s=False)
+                caches.append(cache)
+                bs.append(b)
+                Ms.append(M)
+                scales.append(scale)
+                del f
+            t0 = mark("full_build_diag_scale", t0)
+            dl, st = B.lm_pcg_solve(caches, bs, Ms, lam, max_it, tol, B.TOL_RELATIVE, scales=scales,
+                                    diag_floor=floor)
+            mark("full_pcg", t0)
+            deltas += dl
+            Ms_all += Ms
+            its += [int(s_["iters"]) for s_ in st]
+            mem = max(mem, sum(c.info()["device_bytes"] for c in caches))
+            del bs, scales
+        out = B.lm_combine_subsets(deltas, Ms_all)
+        torch.cuda.synchronize()
+        return out, its, mem
+
+    res = {}
+    forms = (("plain", lambda: sequential("f32", False, "plain")),
+             ("bf16_learned_sequential", lambda: sequential("bf16", True, "seq")),
+             ("full", full))
+    for name, fn in forms:
+        fn()                                    # warm-up: allocations and code objects
+        torch.cuda.empty_cache()
+        torch.cuda.synchronize()
+        phases.clear()
+        t0 = time.perf_counter()
+        r = fn()
+        ms = (time.perf_counter() - t0) * 1e3
+        res[name] = dict(ms=round(ms, 1), pcg_iters=r[1], cache_device_bytes=int(r[2]),
+                         phases_ms={k: round(v, 1) for k, v in phases.items()})
+        res[name]["delta"] = r[0]
+        log(f"{name}: {ms:.1f} ms, PCG iterations {r[1]}, phases {res[name]['phases_ms']}")
+        hl = full_h if name == "full" else plain_h
+        for k, h in enumerate(hl):
+            if h is not None:
+                h.destroy()
+            hl[k] = None
+        torch.cuda.empty_cache()
+    dp, df = res["plain"].pop("delta"), res["full"].pop("delta")
+    res["bf16_learned_sequential"].pop("delta")
+    if args.deploy_alloc == "torch":
+        B.use_torch_allocator(False)
+    diff = float(torch.linalg.vector_norm(df - dp) / torch.linalg.vector_norm(dp))
+    return {
+        "metric": "LM solve phase to relative residual 1e-2 in every subset: ms, full form vs plain",
+        "value": res["full"]["ms"],
+        "unit": "ms",
+        "n_gpus": 1,
+        "steps": 1,
+        "warmup": 1,
+        "ms_per_step": res["full"]["ms"],
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": (f"learned preconditioner deployment: {N} Gaussians SH3, 4 subsets of 40 views "
+                                f"1280x720; plain = float32, sequential subsets, Jacobi; full = bfloat16, subsets "
+                                f"resident in groups of {group}, batched graph-replayed PCG, learned scaling"),
+                   "N": N, "subsets": 4, "views": 40, "width": 1280, "height": 720, "lambda": lam,
+                   "diag_floor": floor, "tol_relative": tol, "tile": f"{tile[0]}x{tile[1]}", "group": group,
+                   "allocator": args.deploy_alloc},
+        "plain": res["plain"], "full": res["full"], "bf16_learned_sequential": res["bf16_learned_sequential"],
+        "speedup_full_vs_plain": round(res["plain"]["ms"] / res["full"]["ms"], 3),
+        "combined_direction_rel_diff": diff,
+        "training": {"samples": 300_000, "steps": n_steps, "ms_per_step": round(train_ms, 3),
+                     "loss_first": round(loss0.item(), 5), "loss_last": round(loss1.item(), 5)},
+    }
+
+
 def main() -> int:
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -432,6 +620,10 @@ def main() -> int:
     ap.add_argument("--N", type=int, default=None, help="override the number of Gaussians")
     ap.add_argument("--views", type=int, default=None, help="override the views of the subset")
     ap.add_argument("--cpu-baseline", type=int, default=1)
+    ap.add_argument("--deploy-alloc", default="torch", choices=["hip", "torch"],
+                    help="device memory of --config deploy: hipMalloc, or PyTorch's caching allocator")
+    ap.add_argument("--deploy-group", type=int, default=2,
+                    help="subsets held and solved together by the full form of --config deploy")
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "block"],
                     help="Jacobi (Algorithm 1) or the per-Gaussian block-Jacobi preconditioner")
     ap.add_argument("--objective", default="l2", choices=["l2", "l1_ssim"],
@@ -472,6 +664,9 @@ def main() -> int:
         return 0
     if args.config == "learned":
         print(json.dumps(bench_learned(args, B, sg, torch)), flush=True)
+        return 0
+    if args.config == "deploy":
+        print(json.dumps(bench_deploy(args, B, sg, torch)), flush=True)
         return 0
     cfg = dict(sg.CONFIGS[args.config])
     subsets = cfg["subsets"][:1]

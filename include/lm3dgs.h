@@ -82,6 +82,10 @@ typedef struct lm_options {
                                 <= 256 (0 selects 16)                                     */
     int32_t cache_dtype;     /* LM_CACHE_F32 / _BF16 / _F16 storage of the cache      */
     int32_t flags;           /* 0 or LM_BUILD_COMPACT                                  */
+    struct lm_cache** scratch; /* LM_BUILD_COMPACT only: NULL, or the address of a handle
+                                  that keeps the build-only buffers between compact builds
+                                  (created on first use when *scratch is NULL; release it
+                                  with lm_cache_destroy)                                 */
 } lm_options;
 
 /* lm_options.flags: after a successful lm_build_cache, synchronise the stream
@@ -91,7 +95,13 @@ typedef struct lm_options {
  * several subsets resident at once.  A later build on the same handle
  * allocates them again.  lm_cache_export of the pair arrays still works;
  * of the records, sorted values, tile ranges, image, contribution counts
- * and residual it returns LM_ERR_INVALID_ARG. */
+ * and residual it returns LM_ERR_INVALID_ARG.
+ * With opts->scratch set, the build borrows the build-only buffers held by
+ * *scratch and hands them back afterwards instead of freeing them, so that
+ * compact builds of several subsets (each cache then holding only what the
+ * products read) allocate their transients once.  Builds sharing one
+ * scratch handle must be ordered (one stream, or synchronised); *scratch
+ * is never a built cache (products on it return LM_ERR_NOT_BUILT). */
 #define LM_BUILD_COMPACT 1
 
 typedef struct lm_cache lm_cache;   /* opaque, library-owned */

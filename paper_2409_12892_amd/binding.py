@@ -70,7 +70,8 @@ class LmScene(ctypes.Structure):
 
 
 class LmOptions(ctypes.Structure):
-    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("cache_dtype", c_int32), ("flags", c_int32)]
+    _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("cache_dtype", c_int32), ("flags", c_int32),
+                ("scratch", c_void_p)]
 
 
 class LmCacheInfo(ctypes.Structure):
@@ -193,10 +194,13 @@ BUILD_COMPACT = 1
 
 
 def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtype: str = "f32",
-                   cache: Cache | None = None, want_b: bool = True, b=None, compact: bool = False):
+                   cache: Cache | None = None, want_b: bool = True, b=None, compact: bool = False,
+                   scratch: Cache | None = None):
     """Build the gradient cache of one subset.  Returns (cache, b, F_sqnorm)
     with b = -J^T F as a [P, N] tensor (written into `b` when given) and
-    ||F||^2 as a 1-element float64 tensor (both None when want_b is False)."""
+    ||F||^2 as a 1-element float64 tensor (both None when want_b is False).
+    With compact=True and a `scratch` Cache (possibly empty), the build's
+    transient buffers are kept in `scratch` for the next compact build."""
     import torch
     lib = load()
     x = _dev_f32(x, "x")
@@ -204,6 +208,12 @@ def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtyp
     P, N = x.shape
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
     opts = LmOptions(tile[0], tile[1], CACHE_DTYPES[cache_dtype], BUILD_COMPACT if compact else 0)
+    sh = None
+    if scratch is not None:
+        if not compact:
+            raise ValueError("a scratch handle serves compact builds only")
+        sh = c_void_p(scratch.handle.value)
+        opts.scratch = ctypes.cast(ctypes.pointer(sh), c_void_p)
     carr = camera_array(cams)
     cache = Cache() if cache is None else cache
     if want_b and b is None:
@@ -212,8 +222,12 @@ def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtyp
         b = None
     fsq = torch.empty(1, device=x.device, dtype=torch.float64) if want_b else None
     h = cache.handle
-    _check(lib.lm_build_cache(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), _stream(),
-                              byref(h), _ptr(b), _ptr(fsq)), "lm_build_cache")
+    try:
+        _check(lib.lm_build_cache(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts), _stream(),
+                                  byref(h), _ptr(b), _ptr(fsq)), "lm_build_cache")
+    finally:
+        if sh is not None:
+            scratch.handle = sh
     cache.handle = h
     cache.N, cache.P, cache.V = N, P, len(carr)
     return cache, b, fsq

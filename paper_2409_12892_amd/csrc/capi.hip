@@ -111,6 +111,12 @@ struct DevBuf {
         cap = 0;
     }
     template <class T> T* as() const { return (T*)p; }
+    void swap(DevBuf& o) {
+        std::swap(p, o.p);
+        std::swap(cap, o.cap);
+        std::swap(al, o.al);
+        std::swap(st, o.st);
+    }
 };
 
 inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
@@ -205,13 +211,28 @@ struct lm_cache {
     }
 
     // buffers read only while building (see LM_BUILD_COMPACT)
+    static constexpr int kBuildBufs = 31;
+    void build_buffers(DevBuf* (&out)[kBuildBufs]) {
+        DevBuf* build[kBuildBufs] = {&x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &vals_alt,
+                                     &sort_tmp, &scan_tmp, &rkeys, &rvals, &rkeys_alt, &rvals_alt, &cnt_sorted,
+                                     &tile_start, &entry_cnt, &pixC, &ncontrib, &resid, &tile_pairs, &tile_segs,
+                                     &tile_real, &tile_real_off, &gv_cnt, &gv_flag, &gv_idx, &gv_segoff, &gv_cursor};
+        for (int i = 0; i < kBuildBufs; ++i) out[i] = build[i];
+    }
     void release_build_buffers() {
-        DevBuf* build[] = {&x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &vals_alt, &sort_tmp,
-                           &scan_tmp, &rkeys, &rvals, &rkeys_alt, &rvals_alt, &cnt_sorted, &tile_start, &entry_cnt,
-                           &pixC, &ncontrib, &resid, &tile_pairs, &tile_segs, &tile_real, &tile_real_off, &gv_cnt,
-                           &gv_flag, &gv_idx, &gv_segoff, &gv_cursor};
+        DevBuf* build[kBuildBufs];
+        build_buffers(build);
         for (auto* b : build) b->release();
         compact = true;
+    }
+    // exchange the build-only buffers with another handle's (a scratch
+    // handle of LM_BUILD_COMPACT builds)
+    void swap_build_buffers(lm_cache& o) {
+        DevBuf* a[kBuildBufs];
+        DevBuf* b[kBuildBufs];
+        build_buffers(a);
+        o.build_buffers(b);
+        for (int i = 0; i < kBuildBufs; ++i) a[i]->swap(*b[i]);
     }
 
     void release_all() {
@@ -648,6 +669,20 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         created = true;
     }
     hipStream_t s = S(stream);
+    // a compact build with a scratch handle borrows its build-only buffers
+    lm_cache* scratch = nullptr;
+    if (opts && (opts->flags & LM_BUILD_COMPACT) && opts->scratch) {
+        if (!*opts->scratch) {
+            *opts->scratch = new (std::nothrow) lm_cache();
+            if (!*opts->scratch) {
+                if (created) delete c;
+                LM_CHECK(false, LM_ERR_HIP, "out of host memory");
+            }
+        }
+        scratch = *opts->scratch;
+        LM_CHECK(scratch != c, LM_ERR_INVALID_ARG, "lm_build_cache: the scratch handle is the cache itself");
+        c->swap_build_buffers(*scratch);
+    }
     lm_status st = build_forward(c, scene, cams, V, target, opts, s);
     if (st == LM_OK) st = build_fill(c, s);
     if (st == LM_OK && F_sqnorm) {
@@ -658,6 +693,11 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         }
     }
     if (st == LM_OK && b) st = apply_JT_internal(c, c->resid.as<float>(), -1.0f, b, s);
+    if (scratch) {
+        // the build is enqueued; the scratch handle takes its buffers back
+        // (later work on them is ordered on the stream)
+        c->swap_build_buffers(*scratch);
+    }
     if (st == LM_OK && opts && (opts->flags & LM_BUILD_COMPACT)) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) {

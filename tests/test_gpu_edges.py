@@ -154,3 +154,34 @@ def test_compact_build_keeps_the_products_and_refuses_build_exports():
     assert comp2.export("residual").size == 3 * 3 * 64 * 48
     full.destroy()
     comp2.destroy()
+
+
+def test_compact_builds_share_a_scratch_handle():
+    """Compact builds of two subsets through one scratch handle: products,
+    diagonal and b are bit-identical to those of full builds; the compacted
+    caches hold only what the products read, the scratch handle holds the
+    transients and is no built cache."""
+    from paper_2409_12892_amd import binding as B
+    d = sg.config_scene("tiny", N=700, subsets=[(3, 64, 48), (2, 80, 40)], seed=24, deg=1)
+    sc = d["scene"]
+    x = torch.from_numpy(sc.x).cuda()
+    scratch = B.Cache()
+    for i, cams in enumerate(d["cams"]):
+        print(f"[gpu edges] scratch-shared compact build, subset {i}", flush=True)
+        imgs = forward.render_images(d["x_star"], cams, sc.sh_degree)
+        tgt = torch.from_numpy(np.stack([(im + nz).astype(np.float32)
+                                         for im, nz in zip(imgs, d["noise"][i])]).ravel()).cuda()
+        full, b1, f1 = B.lm_build_cache(x, sc.sh_degree, cams, tgt)
+        comp, b2, f2 = B.lm_build_cache(x, sc.sh_degree, cams, tgt, compact=True, scratch=scratch)
+        assert torch.equal(b1, b2) and torch.equal(f1, f2)
+        p = torch.from_numpy(random_direction(sc.P, sc.N, seed=6 + i)).cuda()
+        M1, M2 = B.lm_jacobi_diag(full), B.lm_jacobi_diag(comp)
+        assert torch.equal(M1, M2)
+        assert torch.equal(B.lm_apply_JtJ(full, p, 1e-2, M1), B.lm_apply_JtJ(comp, p, 1e-2, M2))
+        assert comp.info()["device_bytes"] < full.info()["device_bytes"]
+        full.destroy()
+        comp.destroy()
+    assert scratch.handle.value
+    with pytest.raises(RuntimeError):
+        B.lm_jacobi_diag(scratch)
+    scratch.destroy()
