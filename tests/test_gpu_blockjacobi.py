@@ -108,3 +108,25 @@ def test_block_jacobi_reaches_tolerance_in_fewer_iterations(prob, gpu, report):
         res[blk] = st[0]["iters"]
     report[("pcg_iters_to_1e-2", prob["id"])] = dict(jacobi=res[False], block=res[True])
     assert res[True] <= res[False]
+
+
+def test_block_precond_with_residual_weights(prob, gpu, report):
+    """With residual weights on the cache the blocks are those of J^T W J
+    (supplement A.5): z = A^-1 r against the oracle's blocks of the
+    row-scaled Jacobian."""
+    B, cache, J = gpu["B"], gpu["cache"], prob["J"]
+    rng = np.random.default_rng(61)
+    w = rng.uniform(0.2, 3.0, size=J.n_res).astype(np.float32)
+    B.lm_set_residual_weights(cache, torch.from_numpy(w).cuda())
+    try:
+        r = rng.normal(size=(J.P, J.N)).astype(np.float32)
+        z, nf = B.lm_block_precond_apply(cache, torch.from_numpy(r).cuda(), LAM, FLOOR, count_fallback=True)
+        assert nf == 0
+        blocks = precond.gaussian_blocks(J.weighted(w.astype(np.float64)))
+        ref = solve.block_jacobi(blocks, LAM, FLOOR)(r.astype(np.float64).ravel())
+        kappa = _kappa_max(blocks, LAM, FLOOR)
+        err = rel(z.cpu().numpy(), ref)
+        report[("block_precond_z_weighted", prob["id"])] = dict(err=err, kappa=kappa)
+        assert err < 1e-5 * kappa + 1e-6
+    finally:
+        B.lm_set_residual_weights(cache, None)
