@@ -373,9 +373,11 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(std::max<int64_t>(Ka, R))));
     { LM_PROF("bin_emit", s);
     LM_HIP(launch_bin_emit(c->cams.as<CamDev>(), N, R, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(), order,
-                           c->keyoff.as<uint64_t>(), c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), s)); }
+                           c->keyoff.as<uint64_t>(), c->rec64.as<double>(), c->n_tiles, c->keys.as<uint32_t>(),
+                           c->vals.as<uint32_t>(), s)); }
+    // keys run up to n_tiles (left-out tiles), inclusive
     int tile_bits = 1;
-    while (((int64_t)1 << tile_bits) < c->n_tiles) ++tile_bits;
+    while (((int64_t)1 << tile_bits) <= c->n_tiles) ++tile_bits;
     bool alt = false;
     { LM_PROF("tile_sort", s);
     LM_HIP(radix_sort_pairs_u32(c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), c->keys_alt.as<uint32_t>(),

@@ -179,6 +179,9 @@ hipError_t reduce_f64(const double* in, int64_t n, double* out, hipStream_t s);
 // threshold, r, g, b, padded to 16 doubles so that a record is one aligned
 // 128-byte line (the raster passes gather one record per tile key).
 constexpr int kRecStride = 16;
+// A tile is left out of a splat's binning when the splat's exponent stays
+// below its alpha threshold by this margin at every pixel centre of the tile.
+constexpr double kCullMargin = 1e-3;
 
 // Arguments of the raster passes (raster.hip).
 struct RasterArgs {
@@ -266,9 +269,10 @@ hipError_t launch_record_keys(const float* recf, const uint32_t* keycnt, int64_t
                               uint32_t* rvals, hipStream_t s);
 hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, int64_t R, uint32_t* cnt_sorted,
                                 hipStream_t s);
+// keys of tiles where the splat stays below its alpha threshold get n_tiles
 hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
-                           const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s);
+                           const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
+                           const double* rec64, int64_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
                               hipStream_t s);
 // raster.hip

@@ -26,6 +26,31 @@ __device__ __forceinline__ void tile_rect(float mx, float my, int32_t radius, in
     y1 = (int)fmaxf(fminf(fy1, (float)(TY - 1)), -1.0f);
 }
 
+// Largest exponent -0.5 (A dx^2 + 2 B dx dy + C dy^2) of a splat over the
+// box [xa, xb] x [ya, yb] of offsets from its mean (the pixel centres of a
+// tile): 0 when the mean lies inside, else the best point of the four
+// edges (the exponent is concave).  Evaluated without contracted
+// multiply-adds, in a fixed order, so that it is a reproducible function of
+// its float64 inputs.
+__device__ __attribute__((noinline)) double tile_max_power(double A, double B, double C, double xa, double xb,
+                                                           double ya, double yb) {
+#pragma clang fp contract(off)
+    if (xa <= 0.0 && 0.0 <= xb && ya <= 0.0 && 0.0 <= yb) return 0.0;
+    double best = -INFINITY;
+    const double xe[2] = {xa, xb}, ye[2] = {ya, yb};
+    for (int k = 0; k < 2; ++k) {
+        const double xx = xe[k];
+        const double yy = fmin(fmax(-(B * xx) / C, ya), yb);
+        best = fmax(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy));
+    }
+    for (int k = 0; k < 2; ++k) {
+        const double yy = ye[k];
+        const double xx = fmin(fmax(-(B * yy) / A, xa), xb);
+        best = fmax(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy));
+    }
+    return best;
+}
+
 template <int deg>
 __device__ __forceinline__ void project_one(const CamDev* __restrict__ cams, const float* __restrict__ x, int64_t N,
                                             int V, int TW, int TH, int64_t r, float* __restrict__ recf,
@@ -99,6 +124,9 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32
 
 // Keys (global tile index) and values (Gaussian id) of the records in depth
 // order; record order[i] writes its tiles (row by row) at off_sorted[i].
+// A tile of the rectangle in which the splat's exponent stays below its
+// alpha threshold (alpha < 1/255) by a margin at every pixel centre gets the
+// key n_tiles instead: it sorts after every tile and is in no tile's list.
 // A block takes 256 consecutive records and writes their keys together:
 // each thread takes every 256th key of the block's range and finds its
 // record by a binary search over the block's offsets, so the stores of a
@@ -108,10 +136,11 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
                                                     const int32_t* __restrict__ rad,
                                                     const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ off_sorted,
+                                                    const double* __restrict__ rec64, uint32_t n_tiles,
                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_off[kBlock];    // first key of each record, relative to the block
     __shared__ int32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock];
-    __shared__ uint32_t s_base[kBlock], s_g[kBlock], s_tx[kBlock];
+    __shared__ uint32_t s_base[kBlock], s_g[kBlock], s_tx[kBlock], s_r[kBlock];
     const int64_t i0 = (int64_t)blockIdx.x * kBlock;
     const int64_t i = i0 + threadIdx.x;
     const int64_t ie = i0 + kBlock < R ? i0 + kBlock : R;
@@ -129,6 +158,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
         s_base[threadIdx.x] = (uint32_t)cam.tile_base;
         s_tx[threadIdx.x] = (uint32_t)cam.TX;
         s_g[threadIdx.x] = (uint32_t)(r - (int64_t)v * N);
+        s_r[threadIdx.x] = (uint32_t)r;
     } else {
         s_off[threadIdx.x] = (uint32_t)(b1 - b0);   // past the block's last key: never selected
     }
@@ -145,7 +175,12 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
         const uint32_t j = k - s_off[lo];
         const int w = s_w[lo];
         const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
-        keys[b0 + k] = s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+        const double* rc = rec64 + (int64_t)s_r[lo] * kRecStride;
+        const double xa = ((double)(tx * TW) + 0.5) - rc[0], ya = ((double)(ty * TH) + 0.5) - rc[1];
+        const double pmax = tile_max_power(rc[2], rc[3], rc[4], xa, xa + (double)(TW - 1), ya,
+                                           ya + (double)(TH - 1));
+        const bool culled = pmax < rc[6] - kCullMargin;
+        keys[b0 + k] = culled ? n_tiles : s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
         vals[b0 + k] = s_g[lo];
     }
 }
@@ -201,10 +236,10 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, i
 }
 
 hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
-                           const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s) {
+                           const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
+                           const double* rec64, int64_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_emit, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
-                       off_sorted, keys, vals);
+                       off_sorted, rec64, (uint32_t)n_tiles, keys, vals);
     return hipGetLastError();
 }
 

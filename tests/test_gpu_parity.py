@@ -7,7 +7,7 @@ cache, on several seeded scenes:
   tile8     1,000 Gaussians, SH 2, 2 views 48x48, 8x8 tiles
   wide      1,200 Gaussians, SH 3, 2 views 96x24, 32x8 tiles
 
-Bars: tile binning and sort bit-exact; active pair set exact; J p, J^T u,
+Bars: tile binning (tiles below a splat's alpha threshold left out) and sort bit-exact; active pair set exact; J p, J^T u,
 b = -J^T F and diag(J^T J) within a norm-wise relative error of 1e-5 (per
 parameter block); PCG directions within max(1e-4, the oracle's own
 sensitivity to float32-sized product perturbations)."""
@@ -85,7 +85,11 @@ def test_binning_and_sort_bit_exact(prob, gpu):
             got = vals[rng[t0 + t]:rng[t0 + t + 1]]
             np.testing.assert_array_equal(got.astype(np.int64), lst, err_msg=f"view {v} tile {t}")
         t0 += len(lists)
-    assert rng[-1] == len(vals)
+    # the keys of tiles left out (below the alpha threshold) follow every
+    # tile's list: the same (Gaussian) multiset as the oracle's
+    out_ref = np.concatenate([vw["bins"]["values"][vw["bins"]["ranges"][-1]:] for vw in J.views])
+    assert len(vals) - rng[-1] == len(out_ref) == sum(vw["bins"]["n_culled"] for vw in J.views)
+    np.testing.assert_array_equal(np.sort(vals[rng[-1]:].astype(np.int64)), np.sort(out_ref))
 
 
 def test_render_and_contributors(prob, gpu):

@@ -224,9 +224,37 @@ def test_suffix_sums_brute_force():
 
 
 # ---------------------------------------------------------------- binning brute force
+def _rect_members(pr, t, TX, TW, TH):
+    mx = pr["y"][0].astype(np.float32).astype(np.float64)
+    my = pr["y"][1].astype(np.float32).astype(np.float64)
+    r = pr["radius"].astype(np.float64)
+    zb = pr["z"].astype(np.float32).view(np.uint32)
+    tx, ty = t % TX, t // TX
+    # interval overlap of [m - r, m + r] with the half-open tile [x0, x0 + TW)
+    inside = (pr["visible"] & (mx + r >= tx * TW) & (mx - r < (tx + 1) * TW)
+              & (my + r >= ty * TH) & (my - r < (ty + 1) * TH))
+    members = np.nonzero(inside)[0]
+    return members[np.lexsort((members, zb[members]))]
+
+
+def _dense_max_power(pr, g, t, TX, TW, TH):
+    """Largest exponent of splat g over every pixel centre of tile t."""
+    y = np.real(pr["y"])
+    tx, ty = t % TX, t // TX
+    px = tx * TW + np.arange(TW) + 0.5
+    py = ty * TH + np.arange(TH) + 0.5
+    dx = px[None, :] - y[0, g]
+    dy = py[:, None] - y[1, g]
+    return float((-0.5 * (y[2, g] * dx * dx + y[4, g] * dy * dy) - y[3, g] * dx * dy).max())
+
+
 def test_binning_brute_force():
+    """Every tile list is the set of splats whose rectangle covers the tile,
+    in (depth, id) order, minus the splats left out because no pixel centre
+    of the tile reaches their alpha threshold (checked pixel by pixel)."""
     d = sg.config_scene("tiny", N=300)
     cams = d["cams"][0]
+    n_out = 0
     for v in range(cams.V):
         cam = cams.view(v)
         for TW, TH in ((16, 16), (8, 16), (16, 8), (32, 8)):
@@ -236,28 +264,56 @@ def test_binning_brute_force():
             my = pr["y"][1].astype(np.float32).astype(np.float64)
             r = pr["radius"].astype(np.float64)
             zb = pr["z"].astype(np.float32).view(np.uint32)
+            o = np.real(pr["y"][5])
             TX, TY = bn["TX"], bn["TY"]
             total_area = 0
             for t in range(TX * TY):
-                tx, ty = t % TX, t // TX
-                # interval overlap of [m - r, m + r] with the half-open tile [x0, x0 + TW)
-                inside = (pr["visible"] & (mx + r >= tx * TW) & (mx - r < (tx + 1) * TW)
-                          & (my + r >= ty * TH) & (my - r < (ty + 1) * TH))
-                members = np.nonzero(inside)[0]
-                members = members[np.lexsort((members, zb[members]))]
+                members = _rect_members(pr, t, TX, TW, TH)
                 got = bn["lists"][t]
-                if not np.array_equal(got, members):
+                extra = np.setdiff1d(got, members)
+                for g in extra:
                     # only acceptable at a float32 rounding margin of the quotient
-                    diff = np.setxor1d(got, members)
-                    for g in diff:
-                        qs = np.array([(mx[g] - r[g]) / TW, (mx[g] + r[g]) / TW,
-                                       (my[g] - r[g]) / TH, (my[g] + r[g]) / TH])
-                        assert np.min(np.abs(qs - np.round(qs))) < 1e-5, (t, g)
+                    qs = np.array([(mx[g] - r[g]) / TW, (mx[g] + r[g]) / TW,
+                                   (my[g] - r[g]) / TH, (my[g] + r[g]) / TH])
+                    assert np.min(np.abs(qs - np.round(qs))) < 1e-5, (t, g)
+                for g in np.setdiff1d(members, got):
+                    qs = np.array([(mx[g] - r[g]) / TW, (mx[g] + r[g]) / TW,
+                                   (my[g] - r[g]) / TH, (my[g] + r[g]) / TH])
+                    if np.min(np.abs(qs - np.round(qs))) < 1e-5:
+                        continue
+                    # left out: below the alpha threshold at every pixel centre
+                    thr = -np.log(255.0 * o[g])
+                    assert _dense_max_power(pr, g, t, TX, TW, TH) < thr - forward.CULL_MARGIN, (t, g)
+                    n_out += 1
                 total_area += len(got)
                 zs = zb[got]
                 assert np.all((zs[1:] > zs[:-1]) | ((zs[1:] == zs[:-1]) & (got[1:] > got[:-1])))
             rect = bn["rect"][:, bn["binned"]]
-            assert total_area == int(((rect[2] - rect[0] + 1) * (rect[3] - rect[1] + 1)).sum())
+            assert total_area + bn["n_culled"] == int(((rect[2] - rect[0] + 1) * (rect[3] - rect[1] + 1)).sum())
+    assert n_out > 0
+
+
+def test_left_out_tiles_do_not_change_the_blend():
+    """Blending the full rectangle lists (no tile left out) gives the same
+    image and the same contributing pairs, bit for bit."""
+    d = sg.config_scene("tiny", N=400)
+    cams = d["cams"][0]
+    for v in range(2):
+        cam = cams.view(v)
+        for TW, TH in ((16, 16), (8, 32)):
+            pr = forward.project(d["scene"].x.astype(np.float64), cam, 0)
+            bn = forward.bin_view(pr["y"], pr["z"], pr["radius"], pr["visible"], cam["W"], cam["H"], TW, TH)
+            assert bn["n_culled"] > 0
+            full = [_rect_members(pr, t, bn["TX"], TW, TH) for t in range(bn["TX"] * bn["TY"])]
+            a = forward.rasterize_view(pr["y"], bn["lists"], cam["W"], cam["H"], TW, TH)
+            b = forward.rasterize_view(pr["y"], full, cam["W"], cam["H"], TW, TH)
+            np.testing.assert_array_equal(a["image"], b["image"])
+            # the same (pixel, splat) pairs with the same state (enumeration order
+            # follows list positions, so compare in (pixel, splat) order)
+            sa = np.lexsort((a["pairs"]["g"], a["pairs"]["pixel"]))
+            sb = np.lexsort((b["pairs"]["g"], b["pairs"]["pixel"]))
+            for k in ("pixel", "g", "T", "alpha", "D"):
+                np.testing.assert_array_equal(a["pairs"][k][sa], b["pairs"][k][sb])
 
 
 # ---------------------------------------------------------------- whole-J finite differences
