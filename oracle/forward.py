@@ -233,11 +233,12 @@ def tile_max_power(A, B, C, xa, xb, ya, yb):
     concave, so its maximum over the box lies on the boundary)."""
     inside = (xa <= 0.0) & (0.0 <= xb) & (ya <= 0.0) & (0.0 <= yb)
     best = np.full(np.shape(xa), -np.inf)
+    iA, iC = 1.0 / A, 1.0 / C
     for xx in (xa, xb):
-        yy = np.minimum(np.maximum(-(B * xx) / C, ya), yb)
+        yy = np.minimum(np.maximum(-(B * xx) * iC, ya), yb)
         best = np.maximum(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy))
     for yy in (ya, yb):
-        xx = np.minimum(np.maximum(-(B * yy) / A, xa), xb)
+        xx = np.minimum(np.maximum(-(B * yy) * iA, xa), xb)
         best = np.maximum(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy))
     return np.where(inside, 0.0, best)
 

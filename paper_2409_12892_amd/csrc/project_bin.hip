@@ -29,23 +29,25 @@ __device__ __forceinline__ void tile_rect(float mx, float my, int32_t radius, in
 // Largest exponent -0.5 (A dx^2 + 2 B dx dy + C dy^2) of a splat over the
 // box [xa, xb] x [ya, yb] of offsets from its mean (the pixel centres of a
 // tile): 0 when the mean lies inside, else the best point of the four
-// edges (the exponent is concave).  Evaluated without contracted
-// multiply-adds, in a fixed order, so that it is a reproducible function of
-// its float64 inputs.
-__device__ __attribute__((noinline)) double tile_max_power(double A, double B, double C, double xa, double xb,
-                                                           double ya, double yb) {
+// edges (the exponent is concave; iA = 1 / A, iC = 1 / C).  Evaluated
+// without contracted multiply-adds, in a fixed order, so that it is a
+// reproducible function of its float64 inputs.
+__device__ __forceinline__ double tile_max_power(double A, double B, double C, double iA, double iC, double xa,
+                                                 double xb, double ya, double yb) {
 #pragma clang fp contract(off)
     if (xa <= 0.0 && 0.0 <= xb && ya <= 0.0 && 0.0 <= yb) return 0.0;
     double best = -INFINITY;
     const double xe[2] = {xa, xb}, ye[2] = {ya, yb};
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         const double xx = xe[k];
-        const double yy = fmin(fmax(-(B * xx) / C, ya), yb);
+        const double yy = fmin(fmax(-(B * xx) * iC, ya), yb);
         best = fmax(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy));
     }
+#pragma unroll
     for (int k = 0; k < 2; ++k) {
         const double yy = ye[k];
-        const double xx = fmin(fmax(-(B * yy) / A, xa), xb);
+        const double xx = fmin(fmax(-(B * yy) * iA, xa), xb);
         best = fmax(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy));
     }
     return best;
@@ -140,7 +142,8 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_off[kBlock];    // first key of each record, relative to the block
     __shared__ int32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock];
-    __shared__ uint32_t s_base[kBlock], s_g[kBlock], s_tx[kBlock], s_r[kBlock];
+    __shared__ uint32_t s_base[kBlock], s_g[kBlock], s_tx[kBlock];
+    __shared__ double s_iA[kBlock], s_iC[kBlock], s_q[6][kBlock];   // q: mx, my, A, B, C, log threshold
     const int64_t i0 = (int64_t)blockIdx.x * kBlock;
     const int64_t i = i0 + threadIdx.x;
     const int64_t ie = i0 + kBlock < R ? i0 + kBlock : R;
@@ -158,7 +161,12 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
         s_base[threadIdx.x] = (uint32_t)cam.tile_base;
         s_tx[threadIdx.x] = (uint32_t)cam.TX;
         s_g[threadIdx.x] = (uint32_t)(r - (int64_t)v * N);
-        s_r[threadIdx.x] = (uint32_t)r;
+        const double* rc = rec64 + r * kRecStride;
+#pragma unroll
+        for (int q = 0; q < 5; ++q) s_q[q][threadIdx.x] = rc[q];
+        s_q[5][threadIdx.x] = rc[6];
+        s_iA[threadIdx.x] = 1.0 / rc[2];
+        s_iC[threadIdx.x] = 1.0 / rc[4];
     } else {
         s_off[threadIdx.x] = (uint32_t)(b1 - b0);   // past the block's last key: never selected
     }
@@ -175,11 +183,10 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
         const uint32_t j = k - s_off[lo];
         const int w = s_w[lo];
         const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
-        const double* rc = rec64 + (int64_t)s_r[lo] * kRecStride;
-        const double xa = ((double)(tx * TW) + 0.5) - rc[0], ya = ((double)(ty * TH) + 0.5) - rc[1];
-        const double pmax = tile_max_power(rc[2], rc[3], rc[4], xa, xa + (double)(TW - 1), ya,
-                                           ya + (double)(TH - 1));
-        const bool culled = pmax < rc[6] - kCullMargin;
+        const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo], ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
+        const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
+                                           xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
+        const bool culled = pmax < s_q[5][lo] - kCullMargin;
         keys[b0 + k] = culled ? n_tiles : s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
         vals[b0 + k] = s_g[lo];
     }
