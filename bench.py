@@ -647,7 +647,7 @@ def main() -> int:
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}, WORLD_SIZE {world}); "
               "the multi-GPU layout (one image subset per GPU, one all-reduce of the weighted "
-              "mean) is described in DESIGN.md and not run.", file=sys.stderr)
+              "mean) is not run.", file=sys.stderr)
         return 2
 
     import torch
