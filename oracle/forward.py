@@ -254,9 +254,8 @@ def bin_view(y, z, radius, visible, W, H, TW, TH):
     CULL_MARGIN at every pixel centre (the tile's box of pixel centres, from
     the float64 mean and conic) is left out: no pixel there can have
     alpha >= 1/255 (eq. alpha-blending skips it), so the blend is unchanged.
-    Left-out keys sort after every tile (key = number of tiles).  Returns the
-    per-tile lists, all values in key order (left-out ones last) and the tile
-    ranges."""
+    Returns the per-tile lists, their concatenation in tile order, the tile
+    ranges and the number of left-out keys."""
     TX, TY = tile_grid(W, H, TW, TH)
     f32 = np.float32
     mx = np.real(y[0]).astype(f32)
@@ -288,11 +287,11 @@ def bin_view(y, z, radius, visible, W, H, TW, TH):
     ya = ((kt // TX) * TH).astype(np.float64) + 0.5 - yr[1][rep]
     pmax = tile_max_power(A, Bc, C, xa, xa + float(TW - 1), ya, ya + float(TH - 1))
     culled = pmax < -np.log(255.0 * o) - CULL_MARGIN
-    kt = np.where(culled, ntiles, kt)
+    kt, rep = kt[~culled], rep[~culled]
     kz = zb[rep]
     order = np.lexsort((rep, kz, kt))
     kt, kg = kt[order], rep[order]
-    counts = np.bincount(kt, minlength=ntiles + 1)[:ntiles]
+    counts = np.bincount(kt, minlength=ntiles)
     starts = np.concatenate([[0], np.cumsum(counts)])
     lists = [kg[starts[i]:starts[i + 1]] for i in range(ntiles)]
     return dict(lists=lists, values=kg, tile_of_key=kt, ranges=starts, TX=TX, TY=TY,

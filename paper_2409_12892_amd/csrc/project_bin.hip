@@ -127,23 +127,29 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32
 // Keys (global tile index) and values (Gaussian id) of the records in depth
 // order; record order[i] writes its tiles (row by row) at off_sorted[i].
 // A tile of the rectangle in which the splat's exponent stays below its
-// alpha threshold (alpha < 1/255) by a margin at every pixel centre gets the
-// key n_tiles instead: it sorts after every tile and is in no tile's list.
+// alpha threshold (alpha < 1/255) by a margin at every pixel centre is left
+// out.  Two launches: COUNT counts each block's kept keys; after a scan of
+// the counts the emitting launch writes the kept keys contiguously, in the
+// same order (each round of 256 keys ranked with wave ballots).
 // A block takes 256 consecutive records and writes their keys together:
 // each thread takes every 256th key of the block's range and finds its
 // record by a binary search over the block's offsets, so the stores of a
 // wave are consecutive.
+template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int64_t R, int TW,
                                                     int TH, const float* __restrict__ recf,
                                                     const int32_t* __restrict__ rad,
                                                     const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ off_sorted,
-                                                    const double* __restrict__ rec64, uint32_t n_tiles,
+                                                    const double* __restrict__ rec64,
+                                                    uint32_t* __restrict__ kept_blk,
+                                                    const uint64_t* __restrict__ kept_off, uint64_t n_kept,
                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
     __shared__ uint32_t s_off[kBlock];    // first key of each record, relative to the block
     __shared__ int32_t s_x0[kBlock], s_y0[kBlock], s_w[kBlock];
     __shared__ uint32_t s_base[kBlock], s_g[kBlock], s_tx[kBlock];
     __shared__ double s_iA[kBlock], s_iC[kBlock], s_q[6][kBlock];   // q: mx, my, A, B, C, log threshold
+    __shared__ uint32_t s_wsum[kBlock / kWave];
     const int64_t i0 = (int64_t)blockIdx.x * kBlock;
     const int64_t i = i0 + threadIdx.x;
     const int64_t ie = i0 + kBlock < R ? i0 + kBlock : R;
@@ -172,24 +178,54 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
     }
     __syncthreads();
     const uint32_t nk = (uint32_t)(b1 - b0);
-    for (uint32_t k = threadIdx.x; k < nk; k += kBlock) {
-        // the last record whose first key is at or before k holds key k
-        int lo = 0, hi = kBlock - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (s_off[mid] <= k) lo = mid;
-            else hi = mid - 1;
+    const int lane = __lane_id(), wid = threadIdx.x / kWave;
+    const uint64_t base = COUNT ? 0 : kept_off[blockIdx.x];
+    uint32_t running = 0;
+    // every thread runs every round (block-wide ranking)
+    for (uint32_t k0 = 0; k0 < nk; k0 += kBlock) {
+        const uint32_t k = k0 + threadIdx.x;
+        bool keep = false;
+        uint32_t key = 0, val = 0;
+        if (k < nk) {
+            // the last record whose first key is at or before k holds key k
+            int lo = 0, hi = kBlock - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (s_off[mid] <= k) lo = mid;
+                else hi = mid - 1;
+            }
+            const uint32_t j = k - s_off[lo];
+            const int w = s_w[lo];
+            const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
+            const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo], ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
+            const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
+                                               xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
+            keep = !(pmax < s_q[5][lo] - kCullMargin);
+            key = s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+            val = s_g[lo];
         }
-        const uint32_t j = k - s_off[lo];
-        const int w = s_w[lo];
-        const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
-        const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo], ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
-        const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
-                                           xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
-        const bool culled = pmax < s_q[5][lo] - kCullMargin;
-        keys[b0 + k] = culled ? n_tiles : s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
-        vals[b0 + k] = s_g[lo];
+        const uint64_t m = __ballot(keep);
+        const uint32_t wrank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+        if (lane == 0) s_wsum[wid] = (uint32_t)__popcll(m);
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+#pragma unroll
+        for (int w = 0; w < kBlock / kWave; ++w) {
+            const uint32_t c = s_wsum[w];
+            before += w < wid ? c : 0u;
+            total += c;
+        }
+        if (!COUNT && keep) {
+            const uint64_t pos = base + running + before + wrank;
+            if (pos < n_kept) {
+                keys[pos] = key;
+                vals[pos] = val;
+            }
+        }
+        running += total;
+        __syncthreads();
     }
+    if (COUNT && threadIdx.x == 0) kept_blk[blockIdx.x] = running;
 }
 
 // tile_start[t] = first key index of tile t (lists are [tile_start[t], tile_start[t+1])).
@@ -242,11 +278,22 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, i
     return hipGetLastError();
 }
 
+int64_t bin_emit_blocks(int64_t R) { return grid_for(R); }
+
+hipError_t launch_bin_count(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
+                            const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
+                            const double* rec64, uint32_t* kept_blk, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_emit<true>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
+                       off_sorted, rec64, kept_blk, nullptr, (uint64_t)0, nullptr, nullptr);
+    return hipGetLastError();
+}
+
 hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
                            const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
-                           const double* rec64, int64_t n_tiles, uint32_t* keys, uint32_t* vals, hipStream_t s) {
-    hipLaunchKernelGGL(k_bin_emit, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
-                       off_sorted, rec64, (uint32_t)n_tiles, keys, vals);
+                           const double* rec64, const uint64_t* kept_off, int64_t n_kept, uint32_t* keys,
+                           uint32_t* vals, hipStream_t s) {
+    hipLaunchKernelGGL(k_bin_emit<false>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
+                       off_sorted, rec64, nullptr, kept_off, (uint64_t)n_kept, keys, vals);
     return hipGetLastError();
 }
 

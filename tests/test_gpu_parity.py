@@ -85,11 +85,7 @@ def test_binning_and_sort_bit_exact(prob, gpu):
             got = vals[rng[t0 + t]:rng[t0 + t + 1]]
             np.testing.assert_array_equal(got.astype(np.int64), lst, err_msg=f"view {v} tile {t}")
         t0 += len(lists)
-    # the keys of tiles left out (below the alpha threshold) follow every
-    # tile's list: the same (Gaussian) multiset as the oracle's
-    out_ref = np.concatenate([vw["bins"]["values"][vw["bins"]["ranges"][-1]:] for vw in J.views])
-    assert len(vals) - rng[-1] == len(out_ref) == sum(vw["bins"]["n_culled"] for vw in J.views)
-    np.testing.assert_array_equal(np.sort(vals[rng[-1]:].astype(np.int64)), np.sort(out_ref))
+    assert rng[-1] == len(vals)
 
 
 def test_render_and_contributors(prob, gpu):

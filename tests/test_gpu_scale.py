@@ -1,6 +1,6 @@
-"""Index ranges at scale: the 48-view 1280x720 subset of the batching
-workload (1.5M Gaussians, SH 3) binned into 8x8 tiles has more than 2^32
-tile keys.  The cache must not depend on that: the pair count and
+"""Index ranges at scale: 64 views of 1280x720 over the batching workload's
+scene (1.5M Gaussians, SH 3) binned into 8x8 tiles keep more than 2^32
+tile keys (after the tiles below a splat's alpha threshold are left out).  The cache must not depend on that: the pair count and
 b = -J^T F match the 8x32-tile build up to the binning difference of the
 two tile shapes (a splat's pixels beyond its 3-sigma rectangle contribute
 only where the rectangle reaches their tile; about 1e-4 of the pairs,
@@ -16,9 +16,9 @@ torch = pytest.importorskip("torch")
 
 def test_more_than_2_32_tile_keys():
     from paper_2409_12892_amd import binding as B
-    print("[gpu scale] batching scene, 48 views 1280x720", flush=True)
-    d = sg.config_scene("batching")
-    sc, cams = d["scene"], d["cams"][3]
+    print("[gpu scale] batching scene, 64 views 1280x720", flush=True)
+    d = sg.config_scene("batching", subsets=[(64, 1280, 720)])
+    sc, cams = d["scene"], d["cams"][0]
     x = torch.from_numpy(sc.x).cuda()
     tgt = B.lm_render(torch.from_numpy(d["x_star"]).cuda(), sc.sh_degree, cams)
     out = {}
