@@ -138,7 +138,7 @@ struct lm_cache {
     DevBuf cams, tile_view, x;
     DevBuf rec64, recf, rad, keycnt, keyoff;
     DevBuf keys, vals, keys_alt, vals_alt, sort_tmp, scan_tmp;
-    DevBuf rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, kept_blk, kept_off;
+    DevBuf rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, kept_blk, kept_off, kept_mask;
     DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
     DevBuf tile_real, tile_real_off, run_seg;
     DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs, seg_pos, list_gv;
@@ -196,7 +196,7 @@ struct lm_cache {
 
     size_t device_bytes() const {
         const DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
-                               &rkeys_alt, &rvals_alt, &cnt_sorted, &kept_blk, &kept_off,
+                               &rkeys_alt, &rvals_alt, &cnt_sorted, &kept_blk, &kept_off, &kept_mask,
                                &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
                                &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
@@ -211,11 +211,11 @@ struct lm_cache {
     }
 
     // buffers read only while building (see LM_BUILD_COMPACT)
-    static constexpr int kBuildBufs = 33;
+    static constexpr int kBuildBufs = 34;
     void build_buffers(DevBuf* (&out)[kBuildBufs]) {
         DevBuf* build[kBuildBufs] = {&x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &vals_alt,
                                      &sort_tmp, &scan_tmp, &rkeys, &rvals, &rkeys_alt, &rvals_alt, &cnt_sorted,
-                                     &kept_blk, &kept_off,
+                                     &kept_blk, &kept_off, &kept_mask,
                                      &tile_start, &entry_cnt, &pixC, &ncontrib, &resid, &tile_pairs, &tile_segs,
                                      &tile_real, &tile_real_off, &gv_cnt, &gv_flag, &gv_idx, &gv_segoff, &gv_cursor};
         for (int i = 0; i < kBuildBufs; ++i) out[i] = build[i];
@@ -238,7 +238,7 @@ struct lm_cache {
 
     void release_all() {
         DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
-                               &rkeys_alt, &rvals_alt, &cnt_sorted, &kept_blk, &kept_off,
+                               &rkeys_alt, &rvals_alt, &cnt_sorted, &kept_blk, &kept_off, &kept_mask,
                          &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
                          &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
@@ -360,13 +360,19 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(exclusive_scan_u32_to_u64(c->cnt_sorted.as<uint32_t>(), c->keyoff.as<uint64_t>(), R, c->scan_tmp.p,
                                      c->scan_tmp.cap, s)); }
     // kept keys per block of records (tiles below a splat's alpha threshold
-    // are left out), their offsets, and the total
+    // are left out), their offsets, and the total; the tile test's ballots
+    // cover every rectangle key
+    uint64_t K_rect = 0;
+    LM_HIP(hipMemcpyAsync(&K_rect, c->keyoff.as<uint64_t>() + R, sizeof(uint64_t), hipMemcpyDeviceToHost, s));
+    LM_HIP(hipStreamSynchronize(s));
     const int64_t nbk = bin_emit_blocks(R);
     LM_HIP(c->kept_blk.ensure(sizeof(uint32_t) * nbk));
     LM_HIP(c->kept_off.ensure(sizeof(uint64_t) * (nbk + 1)));
+    LM_HIP(c->kept_mask.ensure(sizeof(uint64_t) * bin_mask_words((int64_t)K_rect, R)));
     { LM_PROF("bin_emit", s);
     LM_HIP(launch_bin_count(c->cams.as<CamDev>(), N, R, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(), order,
-                            c->keyoff.as<uint64_t>(), c->rec64.as<double>(), c->kept_blk.as<uint32_t>(), s));
+                            c->keyoff.as<uint64_t>(), c->rec64.as<double>(), c->kept_mask.as<uint64_t>(),
+                            c->kept_blk.as<uint32_t>(), s));
     LM_HIP(exclusive_scan_u32_to_u64(c->kept_blk.as<uint32_t>(), c->kept_off.as<uint64_t>(), nbk, c->scan_tmp.p,
                                      c->scan_tmp.cap, s)); }
     uint64_t K = 0;
@@ -384,7 +390,8 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->sort_tmp.ensure(radix_tmp_bytes(std::max<int64_t>(Ka, R))));
     { LM_PROF("bin_emit", s);
     LM_HIP(launch_bin_emit(c->cams.as<CamDev>(), N, R, TW, TH, c->recf.as<float>(), c->rad.as<int32_t>(), order,
-                           c->keyoff.as<uint64_t>(), c->rec64.as<double>(), c->kept_off.as<uint64_t>(), c->n_keys,
+                           c->keyoff.as<uint64_t>(), c->rec64.as<double>(), c->kept_mask.as<uint64_t>(),
+                           c->kept_off.as<uint64_t>(), c->n_keys,
                            c->keys.as<uint32_t>(), c->vals.as<uint32_t>(), s)); }
     int tile_bits = 1;
     while (((int64_t)1 << tile_bits) < c->n_tiles) ++tile_bits;

@@ -269,16 +269,19 @@ hipError_t launch_record_keys(const float* recf, const uint32_t* keycnt, int64_t
                               uint32_t* rvals, hipStream_t s);
 hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, int64_t R, uint32_t* cnt_sorted,
                                 hipStream_t s);
-// binning in two launches: kept keys per block of bin_emit_blocks(R), then
-// (after an exclusive scan of the counts into kept_off) the kept keys
+// binning in two launches: the tile test's ballots (kept_mask, of
+// bin_mask_words(K, R) words for K rectangle keys) and kept keys per block of
+// bin_emit_blocks(R), then (after an exclusive scan of the counts into
+// kept_off) the kept keys
 int64_t bin_emit_blocks(int64_t R);
+int64_t bin_mask_words(int64_t K, int64_t R);
 hipError_t launch_bin_count(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
                             const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
-                            const double* rec64, uint32_t* kept_blk, hipStream_t s);
+                            const double* rec64, uint64_t* kept_mask, uint32_t* kept_blk, hipStream_t s);
 hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
                            const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
-                           const double* rec64, const uint64_t* kept_off, int64_t n_kept, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s);
+                           const double* rec64, uint64_t* kept_mask, const uint64_t* kept_off, int64_t n_kept,
+                           uint32_t* keys, uint32_t* vals, hipStream_t s);
 hipError_t launch_tile_ranges(const uint32_t* keys, int64_t K, int64_t n_tiles, int64_t* tile_start,
                               hipStream_t s);
 // raster.hip

@@ -128,9 +128,13 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32
 // order; record order[i] writes its tiles (row by row) at off_sorted[i].
 // A tile of the rectangle in which the splat's exponent stays below its
 // alpha threshold (alpha < 1/255) by a margin at every pixel centre is left
-// out.  Two launches: COUNT counts each block's kept keys; after a scan of
-// the counts the emitting launch writes the kept keys contiguously, in the
-// same order (each round of 256 keys ranked with wave ballots).
+// out.  Two launches: COUNT evaluates the test, stores each wave's ballot of
+// kept keys in kept_mask and counts each block's kept keys; after a scan of
+// the counts the emitting launch reads the ballots back and writes the kept
+// keys contiguously, in the same order (each round of 256 keys ranked with
+// the ballots).  Block b's ballots start at word b0/64 + 5b (b0 its first
+// key), one word per wave and round: the regions of consecutive blocks do
+// not overlap, and all fit in bin_mask_words(K, R) words.
 // A block takes 256 consecutive records and writes their keys together:
 // each thread takes every 256th key of the block's range and finds its
 // record by a binary search over the block's offsets, so the stores of a
@@ -142,6 +146,7 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
                                                     const uint32_t* __restrict__ order,
                                                     const uint64_t* __restrict__ off_sorted,
                                                     const double* __restrict__ rec64,
+                                                    uint64_t* __restrict__ kept_mask,
                                                     uint32_t* __restrict__ kept_blk,
                                                     const uint64_t* __restrict__ kept_off, uint64_t n_kept,
                                                     uint32_t* __restrict__ keys, uint32_t* __restrict__ vals) {
@@ -167,12 +172,14 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
         s_base[threadIdx.x] = (uint32_t)cam.tile_base;
         s_tx[threadIdx.x] = (uint32_t)cam.TX;
         s_g[threadIdx.x] = (uint32_t)(r - (int64_t)v * N);
-        const double* rc = rec64 + r * kRecStride;
+        if (COUNT) {
+            const double* rc = rec64 + r * kRecStride;
 #pragma unroll
-        for (int q = 0; q < 5; ++q) s_q[q][threadIdx.x] = rc[q];
-        s_q[5][threadIdx.x] = rc[6];
-        s_iA[threadIdx.x] = 1.0 / rc[2];
-        s_iC[threadIdx.x] = 1.0 / rc[4];
+            for (int q = 0; q < 5; ++q) s_q[q][threadIdx.x] = rc[q];
+            s_q[5][threadIdx.x] = rc[6];
+            s_iA[threadIdx.x] = 1.0 / rc[2];
+            s_iC[threadIdx.x] = 1.0 / rc[4];
+        }
     } else {
         s_off[threadIdx.x] = (uint32_t)(b1 - b0);   // past the block's last key: never selected
     }
@@ -180,8 +187,9 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
     const uint32_t nk = (uint32_t)(b1 - b0);
     const int lane = __lane_id(), wid = threadIdx.x / kWave;
     const uint64_t base = COUNT ? 0 : kept_off[blockIdx.x];
+    uint64_t* const mask = kept_mask + (b0 / kWave + 5 * (uint64_t)blockIdx.x) + wid;
     uint32_t running = 0;
-    // every thread runs every round (block-wide ranking)
+    // every wave runs every round of the block
     for (uint32_t k0 = 0; k0 < nk; k0 += kBlock) {
         const uint32_t k = k0 + threadIdx.x;
         bool keep = false;
@@ -197,35 +205,55 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
             const uint32_t j = k - s_off[lo];
             const int w = s_w[lo];
             const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
-            const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo], ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
-            const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
-                                               xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
-            keep = !(pmax < s_q[5][lo] - kCullMargin);
+            if (COUNT) {
+                const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo];
+                const double ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
+                const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
+                                                   xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
+                keep = !(pmax < s_q[5][lo] - kCullMargin);
+            }
             key = s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
             val = s_g[lo];
         }
-        const uint64_t m = __ballot(keep);
-        const uint32_t wrank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-        if (lane == 0) s_wsum[wid] = (uint32_t)__popcll(m);
-        __syncthreads();
-        uint32_t before = 0, total = 0;
+        if (COUNT) {
+            const uint64_t m = (uint64_t)__ballot(keep);
+            if (lane == 0) mask[4 * (k0 / kBlock)] = m;
+            running += (uint32_t)__popcll(m);
+        } else {
+            // the round's four ballots: this wave's keys and the kept keys
+            // of the waves before it
+            const uint64_t* rw = mask - wid + 4 * (k0 / kBlock);
+            uint32_t before = 0, total = 0;
+            uint64_t m = 0;
 #pragma unroll
-        for (int w = 0; w < kBlock / kWave; ++w) {
-            const uint32_t c = s_wsum[w];
-            before += w < wid ? c : 0u;
-            total += c;
-        }
-        if (!COUNT && keep) {
-            const uint64_t pos = base + running + before + wrank;
-            if (pos < n_kept) {
-                keys[pos] = key;
-                vals[pos] = val;
+            for (int w = 0; w < kBlock / kWave; ++w) {
+                const uint64_t mw = rw[w];
+                const uint32_t c = (uint32_t)__popcll(mw);
+                before += w < wid ? c : 0u;
+                total += c;
+                m = w == wid ? mw : m;
             }
+            if ((m >> lane) & 1ull) {
+                const uint64_t pos = base + running + before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                if (pos < n_kept) {
+                    keys[pos] = key;
+                    vals[pos] = val;
+                }
+            }
+            running += total;
         }
-        running += total;
-        __syncthreads();
     }
-    if (COUNT && threadIdx.x == 0) kept_blk[blockIdx.x] = running;
+    if (COUNT) {
+        // the block's kept keys: the sum of its waves' counts
+        if (lane == 0) s_wsum[wid] = running;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            uint32_t t = 0;
+#pragma unroll
+            for (int w = 0; w < kBlock / kWave; ++w) t += s_wsum[w];
+            kept_blk[blockIdx.x] = t;
+        }
+    }
 }
 
 // tile_start[t] = first key index of tile t (lists are [tile_start[t], tile_start[t+1])).
@@ -280,20 +308,23 @@ hipError_t launch_gather_counts(const uint32_t* order, const uint32_t* keycnt, i
 
 int64_t bin_emit_blocks(int64_t R) { return grid_for(R); }
 
+// block b's last ballot word is below (b0 + nk)/64 + 5b + 4 <= K/64 + 5 nblocks
+int64_t bin_mask_words(int64_t K, int64_t R) { return K / kWave + 5 * bin_emit_blocks(R) + 8; }
+
 hipError_t launch_bin_count(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
                             const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
-                            const double* rec64, uint32_t* kept_blk, hipStream_t s) {
+                            const double* rec64, uint64_t* kept_mask, uint32_t* kept_blk, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_emit<true>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
-                       off_sorted, rec64, kept_blk, nullptr, (uint64_t)0, nullptr, nullptr);
+                       off_sorted, rec64, kept_mask, kept_blk, nullptr, (uint64_t)0, nullptr, nullptr);
     return hipGetLastError();
 }
 
 hipError_t launch_bin_emit(const CamDev* cams, int64_t N, int64_t R, int TW, int TH, const float* recf,
                            const int32_t* rad, const uint32_t* order, const uint64_t* off_sorted,
-                           const double* rec64, const uint64_t* kept_off, int64_t n_kept, uint32_t* keys,
-                           uint32_t* vals, hipStream_t s) {
+                           const double* rec64, uint64_t* kept_mask, const uint64_t* kept_off, int64_t n_kept,
+                           uint32_t* keys, uint32_t* vals, hipStream_t s) {
     hipLaunchKernelGGL(k_bin_emit<false>, dim3(grid_for(R)), dim3(kBlock), 0, s, cams, N, R, TW, TH, recf, rad, order,
-                       off_sorted, rec64, nullptr, kept_off, (uint64_t)n_kept, keys, vals);
+                       off_sorted, rec64, kept_mask, nullptr, kept_off, (uint64_t)n_kept, keys, vals);
     return hipGetLastError();
 }
 
