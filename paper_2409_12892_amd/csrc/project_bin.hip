@@ -159,6 +159,11 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
     const int64_t i = i0 + threadIdx.x;
     const int64_t ie = i0 + kBlock < R ? i0 + kBlock : R;
     const uint64_t b0 = off_sorted[i0], b1 = off_sorted[ie];
+    // records that emit no key sort last in their view: most blocks have none
+    if (b0 == b1) {
+        if (COUNT && threadIdx.x == 0) kept_blk[blockIdx.x] = 0;
+        return;
+    }
     if (i < R) {
         const int64_t r = order[i];
         const int v = (int)(r / N);
@@ -189,58 +194,69 @@ __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ 
     const uint64_t base = COUNT ? 0 : kept_off[blockIdx.x];
     uint64_t* const mask = kept_mask + (b0 / kWave + 5 * (uint64_t)blockIdx.x) + wid;
     uint32_t running = 0;
-    // every wave runs every round of the block
-    for (uint32_t k0 = 0; k0 < nk; k0 += kBlock) {
-        const uint32_t k = k0 + threadIdx.x;
-        bool keep = false;
-        uint32_t key = 0, val = 0;
-        if (k < nk) {
-            // the last record whose first key is at or before k holds key k
-            int lo = 0, hi = kBlock - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (s_off[mid] <= k) lo = mid;
-                else hi = mid - 1;
-            }
-            const uint32_t j = k - s_off[lo];
-            const int w = s_w[lo];
-            const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
-            if (COUNT) {
-                const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo];
-                const double ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
-                const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
-                                                   xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
-                keep = !(pmax < s_q[5][lo] - kCullMargin);
-            }
-            key = s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
-            val = s_g[lo];
-        }
-        if (COUNT) {
-            const uint64_t m = (uint64_t)__ballot(keep);
-            if (lane == 0) mask[4 * (k0 / kBlock)] = m;
-            running += (uint32_t)__popcll(m);
-        } else {
-            // the round's four ballots: this wave's keys and the kept keys
-            // of the waves before it
-            const uint64_t* rw = mask - wid + 4 * (k0 / kBlock);
-            uint32_t before = 0, total = 0;
-            uint64_t m = 0;
+    // key k's tile, Gaussian and (COUNT) tile test
+    auto key_at = [&](uint32_t k, uint32_t& key, uint32_t& val, bool& keep) {
+        keep = false;
+        key = val = 0;
+        if (k >= nk) return;
+        // the last record whose first key is at or before k holds key k
+        // (s_off ascends from s_off[0] = 0; fixed-step search)
+        int lo = 0;
 #pragma unroll
-            for (int w = 0; w < kBlock / kWave; ++w) {
-                const uint64_t mw = rw[w];
-                const uint32_t c = (uint32_t)__popcll(mw);
-                before += w < wid ? c : 0u;
-                total += c;
-                m = w == wid ? mw : m;
-            }
-            if ((m >> lane) & 1ull) {
-                const uint64_t pos = base + running + before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
-                if (pos < n_kept) {
-                    keys[pos] = key;
-                    vals[pos] = val;
+        for (int step = kBlock / 2; step > 0; step >>= 1) lo = s_off[lo + step] <= k ? lo + step : lo;
+        const uint32_t j = k - s_off[lo];
+        const int w = s_w[lo];
+        const int ty = s_y0[lo] + (int)(j / (uint32_t)w), tx = s_x0[lo] + (int)(j % (uint32_t)w);
+        if (COUNT) {
+            const double xa = ((double)(tx * TW) + 0.5) - s_q[0][lo];
+            const double ya = ((double)(ty * TH) + 0.5) - s_q[1][lo];
+            const double pmax = tile_max_power(s_q[2][lo], s_q[3][lo], s_q[4][lo], s_iA[lo], s_iC[lo], xa,
+                                               xa + (double)(TW - 1), ya, ya + (double)(TH - 1));
+            keep = !(pmax < s_q[5][lo] - kCullMargin);
+        }
+        key = s_base[lo] + (uint32_t)ty * s_tx[lo] + (uint32_t)tx;
+        val = s_g[lo];
+    };
+    // every wave runs every round of the block; a thread takes one key of
+    // each of kRounds rounds per iteration (independent searches in flight)
+    constexpr int kRounds = 2;
+    for (uint32_t k0 = 0; k0 < nk; k0 += kRounds * kBlock) {
+        uint32_t key[kRounds], val[kRounds];
+        bool keep[kRounds];
+#pragma unroll
+        for (int h = 0; h < kRounds; ++h) key_at(k0 + h * kBlock + threadIdx.x, key[h], val[h], keep[h]);
+#pragma unroll
+        for (int h = 0; h < kRounds; ++h) {
+            const uint32_t kr = k0 + h * kBlock;   // the round's first key
+            if (kr >= nk) break;
+            const uint32_t round = kr / kBlock;
+            if (COUNT) {
+                const uint64_t m = (uint64_t)__ballot(keep[h]);
+                if (lane == 0) mask[4 * round] = m;
+                running += (uint32_t)__popcll(m);
+            } else {
+                // the round's four ballots: this wave's keys and the kept
+                // keys of the waves before it
+                const uint64_t* rw = mask - wid + 4 * round;
+                uint32_t before = 0, total = 0;
+                uint64_t m = 0;
+#pragma unroll
+                for (int w = 0; w < kBlock / kWave; ++w) {
+                    const uint64_t mw = rw[w];
+                    const uint32_t c = (uint32_t)__popcll(mw);
+                    before += w < wid ? c : 0u;
+                    total += c;
+                    m = w == wid ? mw : m;
                 }
+                if ((m >> lane) & 1ull) {
+                    const uint64_t pos = base + running + before + (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+                    if (pos < n_kept) {
+                        keys[pos] = key[h];
+                        vals[pos] = val[h];
+                    }
+                }
+                running += total;
             }
-            running += total;
         }
     }
     if (COUNT) {
