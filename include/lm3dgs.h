@@ -127,6 +127,10 @@ lm_status lm_set_allocator(const lm_allocator* allocator);
 
 typedef struct lm_cache_info {
     int64_t N, n_keys, n_pairs, n_segments, n_gv, n_pixels, n_tiles;
+                             /* n_keys: (splat, tile) keys kept by the binning;
+                                a tile of a splat's rectangle where it stays
+                                below its alpha threshold (alpha < 1/255, the
+                                alpha-blending equation's skip) is not a key */
     int64_t n_pair_slots;    /* pair storage incl. the zero padding of each segment
                                 to a multiple of 8 pairs                        */
     int64_t cache_bytes;     /* pair + segment arrays read by the products   */
