@@ -344,7 +344,7 @@ hipError_t radix_sort_impl(KeyT* keys, uint32_t* vals, KeyT* keys_alt, uint32_t*
     const int passes = (bits + kMaxDigitBits - 1) / kMaxDigitBits;
     int shift = begin_bit;
     for (int pass = 0; pass < passes; ++pass) {
-        const int w = (bits - (shift - begin_bit) + (passes - pass) - 1) / (passes - pass);
+        const int w = (bits - (shift - begin_bit)) / (passes - pass);   // the wider digits last
         hipError_t e;
         if (w > 8) {
             hipLaunchKernelGGL((k_radix_hist<KeyT, 9>), dim3((unsigned)nb), dim3(kBlock), 0, s, ki, n, shift, nb, hist);
