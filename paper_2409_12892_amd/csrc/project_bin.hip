@@ -137,8 +137,8 @@ __global__ void k_gather_counts(const uint32_t* __restrict__ order, const uint32
 // not overlap, and all fit in bin_mask_words(K, R) words.
 // A block takes 256 consecutive records and writes their keys together:
 // each thread takes every 256th key of the block's range and finds its
-// record by a binary search over the block's offsets, so the stores of a
-// wave are consecutive.
+// record by a fixed-step search over the block's offsets, so the stores of
+// a wave are consecutive.
 template <bool COUNT>
 __global__ void __launch_bounds__(kBlock) k_bin_emit(const CamDev* __restrict__ cams, int64_t N, int64_t R, int TW,
                                                     int TH, const float* __restrict__ recf,
