@@ -223,39 +223,17 @@ def render_images(x: np.ndarray, cams, deg: int, TW: int = 16, TH: int = 16) -> 
     return [r["raster"]["image"] for r in render(x, cams, deg, TW, TH)]
 
 
-CULL_MARGIN = 1e-3
-
-
-def tile_max_power(A, B, C, xa, xb, ya, yb):
-    """Largest exponent -0.5 (A dx^2 + 2 B dx dy + C dy^2) over the box of
-    offsets [xa, xb] x [ya, yb] (element-wise over arrays): 0 when the box
-    holds the mean, else the best point of the four edges (the exponent is
-    concave, so its maximum over the box lies on the boundary)."""
-    inside = (xa <= 0.0) & (0.0 <= xb) & (ya <= 0.0) & (0.0 <= yb)
-    best = np.full(np.shape(xa), -np.inf)
-    iA, iC = 1.0 / A, 1.0 / C
-    for xx in (xa, xb):
-        yy = np.minimum(np.maximum(-(B * xx) * iC, ya), yb)
-        best = np.maximum(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy))
-    for yy in (ya, yb):
-        xx = np.minimum(np.maximum(-(B * yy) * iA, xa), xb)
-        best = np.maximum(best, -0.5 * (A * xx * xx + 2.0 * B * xx * yy + C * yy * yy))
-    return np.where(inside, 0.0, best)
-
-
 def bin_view(y, z, radius, visible, W, H, TW, TH):
-    """Tile binning and depth sort for one view.
+    """Tile binning and depth sort for one view (section 3.1: the
+    rasteriser of 3DGS duplicates each splat into every tile its 3-sigma
+    square touches and sorts the copies by tile and depth).
 
     Integer function of float32 records: the mean and depth are rounded to
     float32, the tile rectangle is floor((m -/+ r) / tile) evaluated in
-    float32 with inclusive bounds, and each tile's list is ordered by
-    (float32 depth bits, Gaussian id).  A tile of the rectangle in which the
-    splat's exponent stays below its alpha threshold log(1 / (255 o)) by
-    CULL_MARGIN at every pixel centre (the tile's box of pixel centres, from
-    the float64 mean and conic) is left out: no pixel there can have
-    alpha >= 1/255 (eq. alpha-blending skips it), so the blend is unchanged.
-    Returns the per-tile lists, their concatenation in tile order, the tile
-    ranges and the number of left-out keys."""
+    float32 (IEEE division) with inclusive bounds, and each tile's list is
+    every splat whose rectangle holds the tile, ordered by (float32 depth
+    bits, Gaussian id).  Returns the per-tile lists, their concatenation in
+    tile order and the tile ranges."""
     TX, TY = tile_grid(W, H, TW, TH)
     f32 = np.float32
     mx = np.real(y[0]).astype(f32)
@@ -281,13 +259,6 @@ def bin_view(y, z, radius, visible, W, H, TW, TH):
     ww = np.repeat(w, cnt)
     kt = (y0[rep] + local // ww) * TX + (x0[rep] + local % ww)
     ntiles = TX * TY
-    yr = np.real(y)
-    A, Bc, C, o = yr[2][rep], yr[3][rep], yr[4][rep], yr[5][rep]
-    xa = ((kt % TX) * TW).astype(np.float64) + 0.5 - yr[0][rep]
-    ya = ((kt // TX) * TH).astype(np.float64) + 0.5 - yr[1][rep]
-    pmax = tile_max_power(A, Bc, C, xa, xa + float(TW - 1), ya, ya + float(TH - 1))
-    culled = pmax < -np.log(255.0 * o) - CULL_MARGIN
-    kt, rep = kt[~culled], rep[~culled]
     kz = zb[rep]
     order = np.lexsort((rep, kz, kt))
     kt, kg = kt[order], rep[order]
@@ -295,4 +266,4 @@ def bin_view(y, z, radius, visible, W, H, TW, TH):
     starts = np.concatenate([[0], np.cumsum(counts)])
     lists = [kg[starts[i]:starts[i + 1]] for i in range(ntiles)]
     return dict(lists=lists, values=kg, tile_of_key=kt, ranges=starts, TX=TX, TY=TY,
-                rect=np.stack([x0, y0, x1, y1]), binned=ok, n_culled=int(culled.sum()))
+                rect=np.stack([x0, y0, x1, y1]), binned=ok)

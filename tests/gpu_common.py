@@ -77,3 +77,19 @@ def oracle_pcg(J, target, lam, n_iters, tol=0.0, tol_mode=0):
     M = J.diag_JtJ()
     out = solve.pcg(J.apply_JtJ, b, M, lam, n_iters, tol, tol_mode)
     return b, M, out
+
+
+def kappa_max(blocks, lam, floor):
+    """Largest condition number of the Jacobi-scaled damped blocks
+    B_k + lam diag(max(d, floor)) over the observed parameters."""
+    worst = 1.0
+    for Bk in blocks:
+        d = np.diag(Bk).copy()
+        obs = d > 0
+        if not obs.any():
+            continue
+        A = Bk[np.ix_(obs, obs)] + np.diag(lam * np.maximum(d[obs], floor))
+        s = 1.0 / np.sqrt(np.diag(A))
+        ev = np.linalg.eigvalsh(A * s[:, None] * s[None, :])
+        worst = max(worst, ev.max() / ev.min())
+    return worst

@@ -114,3 +114,38 @@ def test_lm_iterations_with_block_jacobi():
             assert r["E1"] < r["E0"] and r["rho"] > 1e-5
     assert any(r["accepted"] for r in recs)
     solver.close()
+
+
+def test_lm_step_matches_the_oracle_step():
+    """One LMSolver.iteration() against the oracle's LM step (section 3.2:
+    Algorithm 1, eq. line-search on the grid, eq. tr-update with the clamp)
+    on the tiny scene.  gamma is a discrete choice and must be equal (the
+    oracle's grid errors are unimodal here, so the solver's walk over the
+    grid and the oracle's full-grid minimum coincide); rho and lambda_next
+    within the effect of the direction's float32 error (relative 1e-3 on
+    rho, propagated through d lambda / d rho = -6 lambda (2 rho - 1)^2)."""
+    from oracle import lm
+    from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
+    pr = make_problem("tiny", with_J=True)
+    sc, cams = pr["scene"], pr["cams"]
+    x = torch.from_numpy(sc.x).cuda()
+    tgt = torch.from_numpy(pr["target"].ravel()).cuda()
+    cfg = LMConfig(lam=1e-2, n_iters=8, line_search_fraction=0.3)
+    solver = LMSolver(x, sc.sh_degree, cams, tgt, cfg)
+    rec = solver.iteration()
+    ref = lm.lm_step_3dgs(sc.x, cams, list(pr["target"]), sc.sh_degree, cfg.lam, cfg.n_iters, solver.ls_idx,
+                          diag_floor=cfg.diag_floor, gammas=cfg.gammas, rho_min=cfg.rho_min, lam_min=cfg.lam_min,
+                          lam_max=cfg.lam_max, J=pr["J"])
+    E = ref["E_ls"]
+    k = ref["k"]
+    assert np.all(np.diff(E[:k + 1]) <= 0) and np.all(np.diff(E[k:]) >= 0), "grid errors not unimodal"
+    print(dict(gpu=rec, oracle=dict(gamma=ref["gamma"], rho=ref["rho"], lam_next=ref["lam_next"],
+                                    E0=ref["E0"], E1=ref["E1"])))
+    assert rec["gamma"] == ref["gamma"]
+    assert rec["E0"] == pytest.approx(ref["E0"], rel=1e-6)
+    assert rec["accepted"] == ref["accepted"]
+    assert rec["rho"] == pytest.approx(ref["rho"], rel=1e-3)
+    lam = cfg.lam
+    bar = 6.0 * lam * (2.0 * ref["rho"] - 1.0) ** 2 * 1e-3 * abs(ref["rho"]) + 1e-12
+    assert abs(rec["lam_next"] - ref["lam_next"]) <= bar
+    solver.close()

@@ -108,6 +108,8 @@ PROBLEMS = {
     "tiny": dict(name="tiny"),
     "ragged": dict(name="tiny", N=1500, deg=1, subsets=[(3, 72, 40)], seed=11, tile=(16, 8)),
     "wide": dict(name="tiny", N=1200, deg=3, subsets=[(2, 96, 24)], seed=13, tile=(32, 8)),
+    "tall": dict(name="tiny", N=1500, deg=3, subsets=[(3, 60, 100)], seed=14, tile=(8, 32)),
+    "tall16": dict(name="tiny", N=1200, deg=3, subsets=[(3, 64, 96)], seed=15, tile=(8, 16)),
 }
 
 

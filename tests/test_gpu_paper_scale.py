@@ -1,0 +1,223 @@
+"""Checks at the measured sizes, where the explicit oracle Jacobian cannot be
+formed: the paper workload (1M Gaussians, SH 3, 32 views 1024x640, float32
+cache, the 8x32 tiles the autotuner picks; 1.3G pairs) and one subset of the
+learned-preconditioner workload (3M Gaussians, SH 3, 40 views 1280x720,
+bfloat16 cache, 16x16 tiles; 3.6G pairs, past 2^31).  Through the C ABI:
+
+* adjointness of the two products, |<J p, u> - <p, J^T u>| <= 1e-5 ||J p|| ||u||
+  (float64 dots of the float32 outputs);
+* p^T (J^T J p) = ||J p||^2 within 1e-5, with the fused pass's own norm and
+  with the norm of lm_apply_J's output;
+* 64 sampled entries of diag(J^T J) equal ||J e_j||^2 from lm_apply_J within
+  1e-5 (each e_j a unit vector of one parameter of one Gaussian);
+* the float32 projection records of two views equal the oracle's float64
+  projection rounded to float32, and on 192 sampled tiles of those views the
+  GPU tile lists are order-preserving subsequences of the oracle's
+  3-sigma-rectangle lists with every left-out key certified below the alpha
+  threshold pixel by pixel;
+* a rebuild gives bit-identical sorted values and pair arrays, and J^T u
+  from the two builds agrees within float32 rounding (the tile pass adds
+  per-segment moments in LDS in wave order, so the last bit may move).
+
+Targets are 0.5 plus the generator's pixel noise (any image serves: none of
+these checks depends on the residual)."""
+import numpy as np
+import pytest
+
+from oracle import forward
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+WORKLOADS = {
+    "paper_f32": dict(name="paper", subsets=None, dtype="f32", tile=(8, 32), views=(0, 31)),
+    "learned_subset_bf16": dict(name="learned", subsets=[(40, 1280, 720)], dtype="bf16", tile=(16, 16),
+                                views=(0, 39)),
+}
+N_TILES_SAMPLED = 96      # per view
+N_DIAG_SAMPLED = 64
+
+
+@pytest.fixture(scope="module", params=list(WORKLOADS))
+def big(request):
+    from paper_2409_12892_amd import binding as B
+    from paper_2409_12892_amd import scenegen as sg
+    w = WORKLOADS[request.param]
+    print(f"[paper scale] {request.param}: generating inputs", flush=True)
+    d = sg.config_scene(w["name"], subsets=w["subsets"])
+    sc, cams = d["scene"], d["cams"][0]
+    tgt = np.concatenate([(0.5 + n).astype(np.float32).ravel() for n in d["noise"][0]])
+    del d
+    x = torch.from_numpy(sc.x).cuda()
+    target = torch.from_numpy(tgt).cuda()
+    del tgt
+    print(f"[paper scale] {request.param}: building the cache", flush=True)
+    cache, b, fsq = B.lm_build_cache(x, sc.sh_degree, cams, target, tile=w["tile"], cache_dtype=w["dtype"])
+    torch.cuda.synchronize()
+    info = cache.info()
+    print(f"[paper scale] {request.param}: {info['n_pairs']} pairs, {info['n_keys']} keys", flush=True)
+    yield dict(B=B, id=request.param, w=w, scene=sc, cams=cams, x=x, target=target, cache=cache, info=info)
+    cache.destroy()
+    del x, target
+    torch.cuda.empty_cache()
+
+
+def _dot(a, b):
+    return float(torch.dot(a.reshape(-1).double(), b.reshape(-1).double()).item())
+
+
+def test_products_are_adjoint(big, report):
+    B, cache, sc = big["B"], big["cache"], big["scene"]
+    gen = torch.Generator(device="cuda").manual_seed(7)
+    p = torch.randn((sc.P, sc.N), device="cuda", generator=gen)
+    u = torch.randn(3 * big["info"]["n_pixels"], device="cuda", generator=gen)
+    Jp = B.lm_apply_J(cache, p)
+    JTu = B.lm_apply_JT(cache, u)
+    lhs, rhs = _dot(Jp, u), _dot(p, JTu)
+    scale = float(Jp.double().norm().item() * u.double().norm().item())
+    report[("adjoint", big["id"])] = abs(lhs - rhs) / scale
+    assert abs(lhs - rhs) <= 1e-5 * scale
+
+
+def test_quadratic_form_is_the_squared_norm(big, report):
+    B, cache, sc = big["B"], big["cache"], big["scene"]
+    gen = torch.Generator(device="cuda").manual_seed(8)
+    p = torch.randn((sc.P, sc.N), device="cuda", generator=gen)
+    g, jp = B.lm_apply_JtJ(cache, p, want_jp_sqnorm=True)
+    Jp = B.lm_apply_J(cache, p)
+    ptg = _dot(p, g)
+    n_fused = float(jp.item())
+    n_J = _dot(Jp, Jp)
+    report[("pTJTJp_vs_Jp2", big["id"])] = dict(fused=abs(ptg - n_fused) / n_fused, J=abs(ptg - n_J) / n_J)
+    assert abs(ptg - n_fused) <= 1e-5 * n_fused
+    assert abs(ptg - n_J) <= 1e-5 * n_J
+    assert float(B.lm_jp_sqnorm(cache, p).item()) == n_fused
+
+
+def test_sampled_diagonal_entries(big, report):
+    B, cache, sc = big["B"], big["cache"], big["scene"]
+    M = B.lm_jacobi_diag(cache)
+    Mh = M.cpu().numpy()
+    rng = np.random.default_rng(9)
+    # parameters of every group, among observed entries
+    rows = np.concatenate([rng.integers(0, 11, N_DIAG_SAMPLED // 2), rng.integers(11, sc.P, N_DIAG_SAMPLED // 2)])
+    worst = 0.0
+    e = torch.zeros((sc.P, sc.N), device="cuda")
+    u = None
+    for j in rows:
+        obs = np.flatnonzero(Mh[j] > 0)
+        k = int(obs[rng.integers(0, len(obs))])
+        e.zero_()
+        e[j, k] = 1.0
+        u = B.lm_apply_J(cache, e, out=u)
+        n2 = _dot(u, u)
+        err = abs(n2 - float(Mh[j, k])) / float(Mh[j, k])
+        worst = max(worst, err)
+        assert err <= 1e-5, (j, k, n2, float(Mh[j, k]))
+    report[("diag_sampled", big["id"])] = worst
+
+
+def _oracle_lists_for_tiles(pr, tiles, W, H, TW, TH):
+    """Oracle lists (full 3-sigma rectangles) of the given tiles: bin_view over
+    the Gaussians whose float64 rectangle comes within a tile of a sampled
+    tile (a superset of every list member, so the lists are complete)."""
+    TX, TY = forward.tile_grid(W, H, TW, TH)
+    mx, my = np.real(pr["y"][0]), np.real(pr["y"][1])
+    r = pr["radius"].astype(np.float64)
+    near = np.zeros(mx.shape, bool)
+    for t in tiles:
+        tx, ty = t % TX, t // TX
+        near |= ((mx + r >= (tx - 1) * TW) & (mx - r < (tx + 2) * TW)
+                 & (my + r >= (ty - 1) * TH) & (my - r < (ty + 2) * TH))
+    bn = forward.bin_view(pr["y"], pr["z"], pr["radius"], pr["visible"] & near, W, H, TW, TH)
+    return bn
+
+
+def test_records_and_sampled_tile_lists(big, report):
+    cache, sc, cams = big["cache"], big["scene"], big["cams"]
+    TW, TH = big["w"]["tile"]
+    rec = big["cache"].export("records").reshape(cams.V, sc.N, 4)
+    vals = cache.export("sorted_values")
+    rng_t = cache.export("tile_ranges")
+    x64 = sc.x.astype(np.float64)
+    rng = np.random.default_rng(10)
+    t0 = 0
+    n_keys = n_out = 0
+    tiles_per_view = []
+    for v in range(cams.V):
+        W, H = int(cams.W[v]), int(cams.H[v])
+        TX, TY = forward.tile_grid(W, H, TW, TH)
+        tiles_per_view.append(TX * TY)
+    for v in big["w"]["views"]:
+        print(f"[paper scale] {big['id']}: oracle projection and binning of view {v}", flush=True)
+        cam = cams.view(v)
+        W, H = cam["W"], cam["H"]
+        pr = forward.project(x64, cam, sc.sh_degree)
+        vis = pr["visible"]
+        np.testing.assert_array_equal(rec[v, vis, 0], pr["y"][0][vis].astype(np.float32))
+        np.testing.assert_array_equal(rec[v, vis, 1], pr["y"][1][vis].astype(np.float32))
+        np.testing.assert_array_equal(rec[v, vis, 2], pr["z"][vis].astype(np.float32))
+        rad = rec[v, vis, 3].astype(np.int64)
+        bad = np.flatnonzero(rad != pr["radius"][vis])
+        if len(bad):
+            # only where the float64 3 sqrt(lambda_max) lies within 1e-4 of an integer
+            yv = np.real(pr["y"])[:, vis][:, bad]
+            det = yv[2] * yv[4] - yv[3] * yv[3]
+            a, bb, c = yv[4] / det, -yv[3] / det, yv[2] / det      # the 2D covariance
+            lam = 0.5 * (a + c) + np.sqrt(0.25 * (a - c) ** 2 + bb * bb)
+            q = 3.0 * np.sqrt(lam)
+            assert np.all(np.abs(q - np.round(q)) < 1e-4), bad[:10]
+        report[("paper_scale_radius_boundary_cases", big["id"], v)] = int(len(bad))
+        nt = tiles_per_view[v]
+        tiles = rng.choice(nt, size=min(N_TILES_SAMPLED, nt), replace=False)
+        bn = _oracle_lists_for_tiles(pr, tiles, W, H, TW, TH)
+        y = np.real(pr["y"])
+        base = int(sum(tiles_per_view[:v]))
+        TX = bn["TX"]
+        for t in tiles:
+            lst = bn["lists"][t]
+            got = vals[rng_t[base + t]:rng_t[base + t + 1]].astype(np.int64)
+            keep = np.isin(lst, got)
+            np.testing.assert_array_equal(got, lst[keep], err_msg=f"view {v} tile {t}")
+            drop = lst[~keep]
+            if len(drop):
+                tx, ty = t % TX, t // TX
+                px = tx * TW + np.arange(TW)
+                py = ty * TH + np.arange(TH)
+                px, py = px[px < W] + 0.5, py[py < H] + 0.5
+                dx = px[None, None, :] - y[0, drop][:, None, None]
+                dy = py[None, :, None] - y[1, drop][:, None, None]
+                power = (-0.5 * (y[2, drop][:, None, None] * dx * dx + y[4, drop][:, None, None] * dy * dy)
+                         - y[3, drop][:, None, None] * dx * dy)
+                amax = (y[5, drop][:, None, None] * np.exp(power)).max(axis=(1, 2))
+                assert np.all(amax < forward.ALPHA_MIN), f"view {v} tile {t}"
+            n_keys += len(lst)
+            n_out += len(drop)
+    report[("paper_scale_binning", big["id"])] = dict(tiles=2 * N_TILES_SAMPLED, keys=n_keys, left_out=n_out)
+    assert n_keys > 0
+
+
+def test_rebuild_is_bit_identical(big, report):
+    """Runs last on the workload: rebuilds into the same handle (two
+    non-compact caches of the learned subset would not fit together)."""
+    B, cache, sc = big["B"], big["cache"], big["scene"]
+    w = big["w"]
+    gen = torch.Generator(device="cuda").manual_seed(11)
+    u = torch.randn(3 * big["info"]["n_pixels"], device="cuda", generator=gen)
+    g1 = B.lm_apply_JT(cache, u)
+    g1b = B.lm_apply_JT(cache, u)
+    vals1 = cache.export("sorted_values")
+    T1 = cache.export("pair_T")
+    print(f"[paper scale] {big['id']}: rebuilding", flush=True)
+    B.lm_build_cache(big["x"], sc.sh_degree, big["cams"], big["target"], tile=w["tile"], cache_dtype=w["dtype"],
+                     want_b=False, cache=cache)
+    assert np.array_equal(cache.export("sorted_values"), vals1)
+    del vals1
+    assert np.array_equal(cache.export("pair_T"), T1)
+    del T1
+    g2 = B.lm_apply_JT(cache, u)
+    d_same = float((g1 - g1b).double().norm().item() / g1.double().norm().item())
+    d_rebuilt = float((g1 - g2).double().norm().item() / g1.double().norm().item())
+    report[("JTu_repeat", big["id"])] = dict(same_cache=d_same, rebuilt=d_rebuilt,
+                                            bitwise=bool(torch.equal(g1, g2) and torch.equal(g1, g1b)))
+    assert d_same <= 1e-6 and d_rebuilt <= 1e-6

@@ -6,8 +6,14 @@ cache, on several seeded scenes:
   ragged    1,500 Gaussians, SH 1, 3 views 72x40, 16x8 tiles (partial tiles in x and y)
   tile8     1,000 Gaussians, SH 2, 2 views 48x48, 8x8 tiles
   wide      1,200 Gaussians, SH 3, 2 views 96x24, 32x8 tiles
+  tall      1,500 Gaussians, SH 3, 3 views 60x100, 8x32 tiles (the shape the
+            autotuner picks at the paper workload; partial tiles in x and y)
+  tall16    1,200 Gaussians, SH 3, 3 views 64x96, 8x16 tiles
 
-Bars: tile binning (tiles below a splat's alpha threshold left out) and sort bit-exact; active pair set exact; J p, J^T u,
+Bars: tile binning and depth order bit-exact (each GPU tile list an
+order-preserving subsequence of the oracle's 3-sigma-rectangle list, every
+left-out key certified below the alpha threshold pixel by pixel); active
+pair set exact; J p, J^T u,
 b = -J^T F and diag(J^T J) within a norm-wise relative error of 1e-5 (per
 parameter block); PCG directions within max(1e-4, the oracle's own
 sensitivity to float32-sized product perturbations)."""
@@ -28,6 +34,8 @@ PROBLEMS = {
     "ragged": dict(name="tiny", N=1500, deg=1, subsets=[(3, 72, 40)], seed=11, tile=(16, 8)),
     "tile8": dict(name="tiny", N=1000, deg=2, subsets=[(2, 48, 48)], seed=12, tile=(8, 8)),
     "wide": dict(name="tiny", N=1200, deg=3, subsets=[(2, 96, 24)], seed=13, tile=(32, 8)),
+    "tall": dict(name="tiny", N=1500, deg=3, subsets=[(3, 60, 100)], seed=14, tile=(8, 32)),
+    "tall16": dict(name="tiny", N=1200, deg=3, subsets=[(3, 64, 96)], seed=15, tile=(8, 16)),
 }
 
 
@@ -73,19 +81,56 @@ def test_projection_records(prob, gpu):
         np.testing.assert_array_equal(rec[v, vis, 3].astype(np.int64), pr["radius"][vis])
 
 
-def test_binning_and_sort_bit_exact(prob, gpu):
+def _below_threshold_everywhere(y, g, t, TX, TW, TH, W, H):
+    """alpha = o exp(power) < 1/255 at every pixel centre of tile t inside
+    the image, from the oracle's float64 projection (pixel by pixel)."""
+    tx, ty = t % TX, t // TX
+    px = tx * TW + np.arange(TW)
+    py = ty * TH + np.arange(TH)
+    px, py = px[px < W] + 0.5, py[py < H] + 0.5
+    dx = px[None, :] - y[0, g]
+    dy = py[:, None] - y[1, g]
+    power = -0.5 * (y[2, g] * dx * dx + y[4, g] * dy * dy) - y[3, g] * dx * dy
+    return bool((y[5, g] * np.exp(power) < forward.ALPHA_MIN).all())
+
+
+def check_tile_lists(vals, rng, J, tile):
+    """Each GPU tile list is an order-preserving subsequence of the oracle's
+    full 3-sigma-rectangle list (bit-exact integer binning and depth order),
+    and every key the GPU leaves out is certified non-contributing by the
+    oracle: the splat stays below the alpha threshold at every pixel centre
+    of the tile.  Returns (oracle keys, left-out keys)."""
+    t0 = 0
+    n_keys = n_out = 0
+    for v, vw in enumerate(J.views):
+        lists = vw["bins"]["lists"]
+        y = np.real(vw["proj"]["y"])
+        TX = vw["bins"]["TX"]
+        W, H = vw["cam"]["W"], vw["cam"]["H"]
+        TW, TH = tile
+        for t, lst in enumerate(lists):
+            got = vals[rng[t0 + t]:rng[t0 + t + 1]].astype(np.int64)
+            keep = np.isin(lst, got)
+            np.testing.assert_array_equal(got, lst[keep], err_msg=f"view {v} tile {t}: not a subsequence")
+            for g in lst[~keep]:
+                assert _below_threshold_everywhere(y, g, t, TX, TW, TH, W, H), f"view {v} tile {t}: dropped {g}"
+            n_keys += len(lst)
+            n_out += int((~keep).sum())
+        t0 += len(lists)
+    assert rng[-1] == len(vals)
+    return n_keys, n_out
+
+
+def test_binning_and_sort_bit_exact(prob, gpu, report):
+    """Integer binning and depth order against the oracle's 3-sigma-rectangle
+    lists; the keys the GPU leaves out (tiles where the splat cannot reach
+    the alpha threshold) are certified pixel by pixel."""
     assert gpu["cache"].info()["tile_w"] == prob["tile"][0]
     vals = gpu["cache"].export("sorted_values")
     rng = gpu["cache"].export("tile_ranges")
-    J = prob["J"]
-    t0 = 0
-    for v, vw in enumerate(J.views):
-        lists = vw["bins"]["lists"]
-        for t, lst in enumerate(lists):
-            got = vals[rng[t0 + t]:rng[t0 + t + 1]]
-            np.testing.assert_array_equal(got.astype(np.int64), lst, err_msg=f"view {v} tile {t}")
-        t0 += len(lists)
-    assert rng[-1] == len(vals)
+    n_keys, n_out = check_tile_lists(vals, rng, prob["J"], prob["tile"])
+    assert gpu["cache"].info()["n_keys"] == n_keys - n_out
+    report[("binning_left_out_fraction", prob["id"])] = n_out / max(n_keys, 1)
 
 
 def test_render_and_contributors(prob, gpu):

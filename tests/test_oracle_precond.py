@@ -156,3 +156,81 @@ def test_shrinkage_keeps_the_mean_and_scales_the_spread():
     np.testing.assert_array_equal(m, m2)
     np.testing.assert_allclose(sh, precond.shrink_to_mean(raw, m, 0.5), rtol=1e-15)
 
+
+
+def _parameter_groups_from_the_projection(deg=1):
+    """Name the parameter rows by what they change in the projected splat
+    (section 3.1 forward model), independently of any slice table: the
+    mean rows move the 2D mean; the covariance rows change the conic but not
+    the mean, and among them the quaternion rows are the ones whose radial
+    direction changes nothing (the quaternion is normalised); the opacity
+    row changes only the opacity; the SH rows change only the colour."""
+    from oracle import forward
+    d = sg.config_scene("tiny", N=6, subsets=[(1, 32, 32)], seed=41, deg=deg)
+    cam = d["cams"][0].view(0)
+    x = d["scene"].x.astype(np.float64)
+    P = x.shape[0]
+    base = forward.project(x, cam, deg)["y"]
+    moved = {}
+    for j in range(P):
+        xc = x.astype(np.complex128)
+        xc[j] += 1e-30j
+        dy = np.abs(np.imag(forward.project(xc, cam, deg)["y"])) / 1e-30
+        moved[j] = dict(mean=dy[0:2].max() > 0, conic=dy[2:5].max() > 0, opac=dy[5].max() > 0,
+                        colour=dy[6:9].max() > 0, size=dy.max())
+    mean_rows = [j for j in range(P) if moved[j]["mean"]]
+    cov_rows = [j for j in range(P) if moved[j]["conic"] and not moved[j]["mean"]]
+    # radial direction of the quaternion: x[q] += eps x[q] leaves y unchanged
+    # (zero up to rounding: below 1e-9 of the rows' own derivatives)
+    quat_rows = []
+    for a in range(len(cov_rows) - 3):
+        rows = cov_rows[a:a + 4]
+        xc = x.astype(np.complex128)
+        xc[rows] += 1e-30j * x[rows]
+        radial = np.abs(np.imag(forward.project(xc, cam, deg)["y"])).max() / 1e-30
+        if radial < 1e-9 * max(moved[j]["size"] for j in rows):
+            quat_rows = rows
+    scale_rows = [j for j in cov_rows if j not in quat_rows]
+    opac_rows = [j for j in range(P) if moved[j]["opac"] and not moved[j]["conic"] and not moved[j]["mean"]]
+    sh_rows = [j for j in range(P) if moved[j]["colour"] and not (moved[j]["conic"] or moved[j]["opac"])
+               and not moved[j]["mean"]]
+    assert np.all(base[5] > 0)
+    return dict(mean=mean_rows, scale=scale_rows, quat=quat_rows, opacity=opac_rows, sh=sh_rows)
+
+
+def test_feature_groups_follow_the_parameters_they_name():
+    """Features 0-4 average the Jacobi diagonal over the mean, log-scale,
+    quaternion, opacity and SH rows, identified here by their effect on the
+    projection; computed per Gaussian with explicit loops over those rows."""
+    groups = _parameter_groups_from_the_projection(deg=1)
+    P = 11 + 3 * 4
+    assert sorted(sum(groups.values(), [])) == list(range(P))
+    assert [len(groups[k]) for k in ("mean", "scale", "quat", "opacity", "sh")] == [3, 3, 4, 1, 12]
+    for i, k in enumerate(("mean", "scale", "quat", "opacity", "sh")):
+        a, b = precond.GROUPS[i]
+        assert list(range(P)[a:b]) == groups[k], k
+    rng = np.random.default_rng(7)
+    N = 9
+    M = np.exp(rng.normal(0.0, 2.0, size=(P, N)))
+    M[:, 4] = 0.0                                   # an unobserved Gaussian
+    cov = rng.integers(1, 50, size=N).astype(np.float64)
+    x = rng.normal(size=(P, N))
+    f = precond.features(M, cov, x)
+    obs = [k for k in range(N) if M[:, k].sum() > 0]
+    for i, name in enumerate(("mean", "scale", "quat", "opacity", "sh")):
+        raw = {}
+        for k in obs:
+            tot = 0.0
+            for j in groups[name]:
+                tot += M[j, k]
+            raw[k] = math.log(tot / len(groups[name]))
+        ref = sum(raw.values()) / len(obs)
+        for k in obs:
+            assert f[i, k] == pytest.approx(raw[k] - ref, abs=1e-12), (name, k)
+        assert f[i, 4] == 0.0
+    raw5 = {k: math.log(1.0 + cov[k]) for k in obs}
+    ref5 = sum(raw5.values()) / len(obs)
+    for k in obs:
+        assert f[5, k] == pytest.approx(raw5[k] - ref5, abs=1e-12)
+        assert f[6, k] == pytest.approx(1.0 / (1.0 + math.exp(-x[groups["opacity"][0], k])), rel=1e-14)
+        assert f[7, k] == pytest.approx(sum(x[j, k] for j in groups["scale"]) / 3.0, rel=1e-13)
