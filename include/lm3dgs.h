@@ -7,7 +7,7 @@
  * with matrix-free Jacobi-preconditioned conjugate gradients (Algorithm 1),
  * where J is the Jacobian of the rendered pixel colours with respect to all
  * Gaussian parameters and F the per-pixel, per-channel residuals
- * F = rendered - target (least-squares colour residuals; supplement A.5 notes
+ * F = rendered - target (least-squares colour residuals; supplement A.4 notes
  * dr/dc = 1 for L2).  J p and J^T u are evaluated from a per-pixel,
  * per-splat gradient cache filled once per LM iteration (section 3.3,
  * "Cache-driven parallelization").
@@ -18,13 +18,15 @@
  *     No C++ exception crosses this boundary.
  *   - "dev" pointers are device (HBM) pointers owned by the caller; "host"
  *     pointers are ordinary host memory.  The library never frees caller
- *     memory.  Cache memory is allocated by the library (hipMalloc) and
- *     released by lm_cache_destroy().
+ *     memory.  The device memory a cache or workspace holds comes from the
+ *     allocator of the context it was built with (lm_ctx_create; hipMalloc
+ *     when the context has none) and goes back to that allocator in
+ *     lm_cache_destroy().
  *   - `stream` is a hipStream_t passed as void*; NULL means the default
  *     stream.  Work is enqueued on it and returns asynchronously unless a
  *     call says it synchronises.
  *   - Parameter vectors (x, p, g, b, M, delta) use the per-attribute
- *     structure-of-arrays layout x[P][N] (paper supplement A.4, vector "q"),
+ *     structure-of-arrays layout x[P][N] (paper supplement A.3, vector "q"),
  *     float32, with P = 11 + 3 (deg+1)^2 parameters per Gaussian in the order
  *     mean(3), log-scale(3), quaternion w,x,y,z (4), opacity logit (1),
  *     SH coefficients (index 11 + 3k + channel).
@@ -49,7 +51,9 @@ enum {
     LM_ERR_CAPACITY = -3,      /* a size exceeds an index range of the layout */
     LM_ERR_NOT_BUILT = -4,     /* the cache handle is empty                   */
     LM_ERR_UNSUPPORTED = -5,   /* option combination not implemented          */
-    LM_WARN_BREAKDOWN = 1      /* PCG stopped early on p^T A p <= 0 / NaN     */
+    LM_WARN_BREAKDOWN = 1,     /* PCG stopped early on p^T A p <= 0 / NaN     */
+    LM_WARN_FALLBACK_JACOBI = 2 /* a learned or block preconditioner fell back
+                                   to the Jacobi scaling for some parameters  */
 };
 
 enum { LM_CACHE_F32 = 0, LM_CACHE_BF16 = 1, LM_CACHE_F16 = 2 };
@@ -77,6 +81,8 @@ typedef struct lm_scene {
     const float* x;       /* dev */
 } lm_scene;
 
+typedef struct lm_ctx lm_ctx;       /* opaque, library-owned (lm_ctx_create) */
+
 typedef struct lm_options {
     int32_t tile_w, tile_h;  /* tile shape in pixels: tile_w a power of two, tile_w*tile_h
                                 <= 256 (0 selects 16)                                     */
@@ -86,6 +92,8 @@ typedef struct lm_options {
                                   that keeps the build-only buffers between compact builds
                                   (created on first use when *scratch is NULL; release it
                                   with lm_cache_destroy)                                 */
+    lm_ctx* ctx;             /* context of the call and of the handles it builds; NULL:
+                                the process-wide default context                      */
 } lm_options;
 
 /* lm_options.flags: after a successful lm_build_cache, synchronise the stream
@@ -106,23 +114,35 @@ typedef struct lm_options {
 
 typedef struct lm_cache lm_cache;   /* opaque, library-owned */
 
-/* Device memory of caches and workspaces.  By default the library calls
- * hipMalloc / hipFree.  With an allocator installed, every device buffer
- * the library needs comes from alloc(user, bytes, stream) - stream being
- * the hipStream_t of the call that needs it, on which the buffer's work is
- * ordered - and goes back through free(user, ptr, stream) of the same
- * allocator on the same stream, at the latest in lm_cache_destroy (after a
- * device synchronisation).  alloc returns NULL on failure (the call then
- * fails with LM_ERR_HIP).  The allocator is library-wide; a buffer is always
- * returned to the allocator that supplied it, so it may be changed between
- * calls.  (lm_autotune_tile's two scratch vectors use hipMalloc.) */
+/* Device memory allocator: alloc(user, bytes, stream) returns a device
+ * buffer for work ordered on `stream` (the hipStream_t of the call that
+ * needs it) or NULL on failure (the call then fails with LM_ERR_HIP);
+ * free(user, ptr, stream) takes it back on the same stream.  A buffer always
+ * goes back to the allocator that supplied it. */
 typedef struct lm_allocator {
     void* user;
     void* (*alloc)(void* user, size_t bytes, void* stream);
     void (*free)(void* user, void* ptr, void* stream);
 } lm_allocator;
 
-/* Installs a (copy of the) allocator; NULL restores hipMalloc / hipFree. */
+/* A library context holds the allocator of every device buffer allocated on
+ * its behalf (caches, workspaces, the autotuner's vectors, lm_vec_dot's
+ * partial sums), the PCG launch mode (lm_pcg_use_graph) and the profiling
+ * records (lm_profile_*).  A cache or workspace handle belongs to the context
+ * of the call that last built it (lm_options.ctx), and every later call on
+ * it runs in that context.  Contexts are independent: two contexts in one
+ * process give the same results.
+ *   lm_ctx_create: allocator (host, copied) may be NULL for hipMalloc /
+ *     hipFree; *out receives the context.
+ *   lm_ctx_destroy: fails with LM_ERR_INVALID_ARG while handles of the
+ *     context are alive (destroy them first) or for the default context;
+ *     NULL is a no-op. */
+lm_status lm_ctx_create(const lm_allocator* allocator, lm_ctx** out);
+lm_status lm_ctx_destroy(lm_ctx* ctx);
+
+/* Installs a (copy of the) allocator in the process-wide default context
+ * (lm_options.ctx == NULL); NULL restores hipMalloc / hipFree.  Buffers
+ * already allocated keep their allocator. */
 lm_status lm_set_allocator(const lm_allocator* allocator);
 
 typedef struct lm_cache_info {
@@ -131,8 +151,9 @@ typedef struct lm_cache_info {
                                 a tile of a splat's rectangle where it stays
                                 below its alpha threshold (alpha < 1/255, the
                                 alpha-blending equation's skip) is not a key */
-    int64_t n_pair_slots;    /* pair storage incl. the zero padding of each segment
-                                to a multiple of 8 pairs                        */
+    int64_t n_pair_slots;    /* pair storage incl. the zero padding of each piece (a
+                                splat's pairs in one 64-pixel block of a tile) to a
+                                multiple of 8 pairs                             */
     int64_t cache_bytes;     /* pair + segment arrays read by the products   */
     int64_t device_bytes;    /* all device memory held by the cache          */
     int32_t V, P, tile_w, tile_h, cache_dtype, sh_degree;
@@ -169,7 +190,7 @@ lm_status lm_cache_get_info(const lm_cache* cache, lm_cache_info* info);
 /* M = diag(J^T J) (paper eq. diag-jtj, kernel diagJTJ), dev float32 [P][N].
  * With residual weights set on the cache (lm_set_residual_weights,
  * lm_cache_objective) every product below uses J^T W J in place of J^T J
- * (supplement A.5, eq. apply-jtj-simplified-vec-vec): this diagonal, the
+ * (supplement A.4, eq. apply-jtj-simplified-vec-vec): this diagonal, the
  * J^T J half of lm_apply_JtJ and lm_pcg_solve, and the squared norms
  * (sum w (J p)^2).  lm_apply_J and lm_apply_JT stay the plain colour
  * Jacobian products. */
@@ -193,7 +214,7 @@ lm_status lm_jp_sqnorm(const lm_cache* cache, const float* p, double* out, void*
 lm_status lm_apply_JT(const lm_cache* cache, const float* u, float* g, void* stream);
 
 /* ---- the paper's objective (section 3.1 eq. sgd-loss, eq. gn-loss;
- * supplement A.5) ----
+ * supplement A.4) ----
  * Per pixel and colour channel, residuals r1 = sqrt(lambda1 |c - C|) and
  * r2 = sqrt(lambda2 (1 - SSIM(c, C))); E = sum r1^2 + r2^2.  SSIM per
  * channel: 11 x 11 Gaussian window of standard deviation 1.5 (weights sum to
@@ -278,8 +299,9 @@ lm_status lm_pcg_solve_block(lm_cache* const* caches, int32_t n_b, const float* 
 /* z = A^-1 r with the block-Jacobi factors for (lambda, diag_floor) (r, z
  * dev float32 [P][N]).  n_fallback (host, may be NULL): when given, the
  * factors are recomputed and it receives the number of Gaussians whose
- * damped block did not factor (those use their damped diagonal); the call
- * then synchronises the stream. */
+ * damped block did not factor (those use their damped diagonal, the Jacobi
+ * scaling); the call then synchronises the stream and returns
+ * LM_WARN_FALLBACK_JACOBI when the number is not 0. */
 lm_status lm_block_precond_apply(lm_cache* cache, float lambda, float diag_floor, const float* r, float* z,
                                  int32_t* n_fallback, void* stream);
 
@@ -289,22 +311,38 @@ lm_status lm_block_precond_apply(lm_cache* cache, float lambda, float diag_floor
  * products (along b) are timed; the shape with the smallest
  * build_ms + n_products * apply_ms is returned in tile_w/tile_h.  scores
  * (host, may be NULL) receives up to max_scores per-candidate timings and
- * n_scores their count.  Allocates and frees its own device memory and
- * synchronises the stream. */
+ * n_scores their count.  opts (may be NULL) gives the context, whose
+ * allocator supplies the candidates' caches and two parameter vectors
+ * (freed before returning), and the cache type; its tile fields are
+ * ignored.  Synchronises the stream. */
 typedef struct lm_tile_score {
     int32_t tile_w, tile_h;
     float build_ms, apply_ms;
 } lm_tile_score;
 lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
-                           int32_t cache_dtype, int32_t n_products, void* stream, int32_t* tile_w,
+                           const lm_options* opts, int32_t n_products, void* stream, int32_t* tile_w,
                            int32_t* tile_h, lm_tile_score* scores, int32_t max_scores, int32_t* n_scores);
 
-/* Launch mode of the PCG iterations (library-wide): 0 launches every
- * kernel of every iteration from the host; 1 captures one iteration into a
- * graph (on a library-owned stream) and replays it on the caller's stream;
- * 2 (default) uses the graph when a call solves more than one subset.
- * Results are the same in every mode. */
-lm_status lm_pcg_use_graph(int32_t mode);
+/* Launch mode of the PCG iterations of a context (NULL: the default
+ * context): 0 launches every kernel of every iteration from the host; 1
+ * captures one iteration into a graph (on a library-owned stream) and
+ * replays it on the caller's stream; 2 (default) uses the graph when a call
+ * solves more than one subset.  Results are the same in every mode. */
+lm_status lm_pcg_use_graph(lm_ctx* ctx, int32_t mode);
+
+/* Vector steps of the LM outer loop (section 3.2), so that no method
+ * arithmetic runs outside the library.
+ * lm_vec_dot: *out (dev double) = a^T b in float64 for float32 dev vectors
+ *   a, b of n elements; the trust-region ratio's model decrease (eq.
+ *   tr-update) is 2 gamma delta^T b - gamma^2 ||J delta||^2 with b = -J^T F.
+ *   Partial sums go to device memory of the context (NULL: default),
+ *   allocated through its allocator on first use and kept until
+ *   lm_ctx_destroy.  Fixed summation order (deterministic).
+ * lm_vec_axpy: out = x + gamma d element-wise in float32 (one rounding per
+ *   element), the parameter update x_{k+1} = x_k + gamma delta of section
+ *   3.2; out may alias x.  Allocates nothing. */
+lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream);
+lm_status lm_vec_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, void* stream);
 
 /* Weighted mean of subset directions (paper eq. combine-pcg):
  * out = sum_i M_i delta_i / sum_k M_k element-wise; 0 where sum_k M_k = 0.
@@ -367,7 +405,9 @@ lm_status lm_precond_features(const lm_cache* cache, const float* x, const float
  * of feat, dev [8][n]); 1 <= p_out <= 64.  s (dev [p_out][n]) and scale =
  * exp(clamp(s, -4, 4)) (dev [p_out][n]) may each be NULL.  A non-finite s
  * gives scale 1 (the Jacobi preconditioner) and is counted in n_fallback
- * (dev uint32, may be NULL; set to the count of this call). */
+ * (dev uint32, may be NULL; set to the count of this call).  With n_fallback
+ * given the call synchronises the stream and returns LM_WARN_FALLBACK_JACOBI
+ * when the count is not 0. */
 lm_status lm_mlp_forward(const float* w, const float* feat, int64_t n, int32_t p_out, float* s, float* scale,
                          uint32_t* n_fallback, void* stream);
 
@@ -420,27 +460,29 @@ enum {
     LM_EXPORT_PAIR_PIX = 7,      /* int32 [n_pairs]: global pixel index v*H*W + y*W + x       */
     LM_EXPORT_PAIR_GAUSS = 8,    /* int32 [n_pairs]: Gaussian id of the pair's splat          */
     LM_EXPORT_RESIDUAL = 9,      /* float [V][3][H][W]: F = rendered - target                 */
-    LM_EXPORT_PAIR_FLAGS = 10    /* int32 [n_pairs]: bit0 segment head, bit1 alpha clamped    */
+    LM_EXPORT_PAIR_FLAGS = 10    /* int32 [n_pairs]: bit0 first pair of a piece (a splat's
+                                    pairs in one pixel block of a tile), bit1 alpha clamped */
 };
 int64_t lm_cache_export_size(const lm_cache* cache, int32_t what);
 lm_status lm_cache_export(const lm_cache* cache, int32_t what, void* host_dst, int64_t bytes,
                           void* stream);
 
 /* Opt-in timing of the library's own kernels with HIP events recorded on
- * the stream each kernel is launched on.  lm_profile_enable(1) starts
- * recording (one start/stop event pair around every kernel group the
- * library launches), lm_profile_enable(0) stops.  lm_profile_read()
- * synchronises on the recorded events, returns per-group totals (at most
- * max_entries, sorted by name) and clears the record.  Not thread-safe:
- * meant for a single driver thread. */
+ * the stream each kernel is launched on, per context (NULL: the default
+ * context; a call records into the context it runs in).
+ * lm_profile_enable(ctx, 1) starts recording (one start/stop event pair
+ * around every kernel group the library launches), lm_profile_enable(ctx, 0)
+ * stops.  lm_profile_read() synchronises on the context's recorded events,
+ * returns per-group totals (at most max_entries, sorted by name) and clears
+ * the record.  Not thread-safe: meant for a single driver thread. */
 typedef struct lm_profile_entry {
     char name[40];
     int32_t launches;
     int32_t reserved;
     double total_ms;
 } lm_profile_entry;
-lm_status lm_profile_enable(int32_t on);
-int32_t lm_profile_read(lm_profile_entry* out, int32_t max_entries);
+lm_status lm_profile_enable(lm_ctx* ctx, int32_t on);
+int32_t lm_profile_read(lm_ctx* ctx, lm_profile_entry* out, int32_t max_entries);
 
 #ifdef __cplusplus
 }

@@ -17,7 +17,7 @@ Contents (each function cites the passage of the paper it follows):
                 solve, and the subset combination (eq. combine-pcg)
 * ``objective`` the paper's square-root L1 / SSIM residuals and their
                 per-pixel weights and colour gradients (eq. gn-loss,
-                supplement A.5)
+                supplement A.4)
 * ``precond``   per-Gaussian blocks of J^T J, targets and features of the
                 learned diagonal preconditioner, and its reference MLP
 

@@ -2,7 +2,7 @@
 Gaussian parameter, in float64, and the products the hot path computes.
 
 Paper eq. backward-pass (section 3.3): dr/dx = dr/dc * dc/ds * ds/dx.  With
-least-squares colour residuals r = c - C* (supplement A.5: dr/dc = 1 for L2),
+least-squares colour residuals r = c - C* (supplement A.4: dr/dc = 1 for L2),
 each contributing (pixel, splat) pair owns a dense 3 x P block
 
     J_pair = dC/dy (3 x 9)  @  dy/dx (9 x P)
@@ -182,7 +182,7 @@ class Jacobian:
 
     def apply_JtJ(self, p: np.ndarray, lam: float = 0.0, M: np.ndarray | None = None,
                   w: np.ndarray | None = None) -> np.ndarray:
-        """J^T J p (+ lam M p).  With per-residual weights w (supplement A.5,
+        """J^T J p (+ lam M p).  With per-residual weights w (supplement A.4,
         eq. apply-jtj-simplified-vec-vec: w = (dr/dc)^2 of each pixel and
         channel) the product is J^T (w . J p), J being the colour Jacobian."""
         p = np.asarray(p, np.float64).ravel()

@@ -8,7 +8,7 @@ term,
     f1 = lam1 |c - C|,   f2 = lam2 (1 - SSIM(c, C)),   r_t = sqrt(f_t),
 
 with lam1 = 0.8 and lam2 = 0.2, and E = sum over pixels and channels of
-r1^2 + r2^2 = f1 + f2.  Supplement A.5 (eq. res-sq-root-weights,
+r1^2 + r2^2 = f1 + f2.  Supplement A.4 (eq. res-sq-root-weights,
 res-sq-root-weights-sum, apply-jtj-simplified-vec-vec) factors every
 Jacobian row into dr/dc (a per-pixel scalar) times dc/dx (the colour
 Jacobian of the cache), so a Gauss-Newton step needs two per-pixel images:

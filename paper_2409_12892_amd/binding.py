@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(HERE, "liblm3dgs.so")
 
 LM_OK = 0
 LM_WARN_BREAKDOWN = 1
+LM_WARN_FALLBACK_JACOBI = 2
 CACHE_DTYPES = {"f32": 0, "bf16": 1, "f16": 2}
 TOL_NONE, TOL_PAPER_SQUARED, TOL_RELATIVE = 0, 1, 2
 PCG_MAX_HISTORY = 257
@@ -36,7 +37,8 @@ EXPORTED_SYMBOLS = (
     "lm_cache_view_sqnorm", "lm_pcg_use_graph", "lm_autotune_tile", "lm_pair_coverage", "lm_block_jacobi",
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
     "lm_jp_sqnorm", "lm_set_allocator", "lm_objective_terms", "lm_set_residual_weights", "lm_cache_objective",
-    "lm_objective_value", "lm_pcg_solve_block", "lm_block_precond_apply",
+    "lm_objective_value", "lm_pcg_solve_block", "lm_block_precond_apply", "lm_ctx_create", "lm_ctx_destroy",
+    "lm_vec_dot", "lm_vec_axpy",
 )
 
 # objective kinds (include/lm3dgs.h): plain least squares, and the paper's
@@ -71,7 +73,34 @@ class LmScene(ctypes.Structure):
 
 class LmOptions(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("cache_dtype", c_int32), ("flags", c_int32),
-                ("scratch", c_void_p)]
+                ("scratch", c_void_p), ("ctx", c_void_p)]
+
+
+class Ctx:
+    """Owner of one lm_ctx (its allocator, PCG launch mode and profiling
+    records); allocator is an LmAllocator kept alive with the context, or
+    None for hipMalloc."""
+
+    def __init__(self, allocator=None):
+        self.allocator = allocator
+        h = c_void_p(0)
+        _check(load().lm_ctx_create(byref(allocator) if allocator is not None else None, byref(h)), "lm_ctx_create")
+        self.handle = h
+
+    def destroy(self):
+        if self.handle and self.handle.value:
+            _check(load().lm_ctx_destroy(self.handle), "lm_ctx_destroy")
+            self.handle = c_void_p(0)
+
+
+def _ctx_ptr(ctx):
+    return None if ctx is None else ctx.handle.value
+
+
+def _opts(tile, cache_dtype=0, flags=0, ctx=None):
+    o = LmOptions(tile[0], tile[1], cache_dtype, flags)
+    o.ctx = _ctx_ptr(ctx)
+    return o
 
 
 class LmCacheInfo(ctypes.Structure):
@@ -195,7 +224,7 @@ BUILD_COMPACT = 1
 
 def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtype: str = "f32",
                    cache: Cache | None = None, want_b: bool = True, b=None, compact: bool = False,
-                   scratch: Cache | None = None):
+                   scratch: Cache | None = None, ctx: Ctx | None = None):
     """Build the gradient cache of one subset.  Returns (cache, b, F_sqnorm)
     with b = -J^T F as a [P, N] tensor (written into `b` when given) and
     ||F||^2 as a 1-element float64 tensor (both None when want_b is False).
@@ -207,7 +236,7 @@ def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtyp
     target = _dev_f32(target, "target")
     P, N = x.shape
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
-    opts = LmOptions(tile[0], tile[1], CACHE_DTYPES[cache_dtype], BUILD_COMPACT if compact else 0)
+    opts = _opts(tile, CACHE_DTYPES[cache_dtype], BUILD_COMPACT if compact else 0, ctx)
     sh = None
     if scratch is not None:
         if not compact:
@@ -367,7 +396,7 @@ def lm_combine_subsets(deltas, Ms, out=None):
 
 
 def lm_residual_sqnorm(x, sh_degree: int, cams, target, *, tile=(16, 16), workspace: Cache | None = None,
-                       out=None):
+                       out=None, ctx: Ctx | None = None):
     """||render(x) - target||^2 over the views of `cams` (forward pass only).
     Returns (value as a 1-element float64 device tensor, workspace)."""
     import torch
@@ -375,7 +404,7 @@ def lm_residual_sqnorm(x, sh_degree: int, cams, target, *, tile=(16, 16), worksp
     target = _dev_f32(target, "target")
     P, N = x.shape
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
-    opts = LmOptions(tile[0], tile[1], 0, 0)
+    opts = _opts(tile, ctx=ctx)
     carr = camera_array(cams)
     ws = Cache() if workspace is None else workspace
     out = torch.empty(1, device=x.device, dtype=torch.float64) if out is None else out
@@ -426,7 +455,7 @@ def lm_cache_objective(cache: Cache, target, obj: LmObjective, *, b=None, want_b
 
 
 def lm_objective_value(x, sh_degree: int, cams, target, obj: LmObjective, *, tile=(16, 16),
-                       workspace: Cache | None = None, out=None):
+                       workspace: Cache | None = None, out=None, ctx: Ctx | None = None):
     """Objective of a forward render over the views of `cams`.  Returns
     (value as a 1-element float64 device tensor, workspace)."""
     import torch
@@ -434,7 +463,7 @@ def lm_objective_value(x, sh_degree: int, cams, target, obj: LmObjective, *, til
     target = _dev_f32(target, "target")
     P, N = x.shape
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
-    opts = LmOptions(tile[0], tile[1], 0, 0)
+    opts = _opts(tile, ctx=ctx)
     carr = camera_array(cams)
     ws = Cache() if workspace is None else workspace
     out = torch.empty(1, device=x.device, dtype=torch.float64) if out is None else out
@@ -454,7 +483,8 @@ def lm_cache_view_sqnorm(cache: Cache, out=None):
     return out
 
 
-def lm_autotune_tile(x, sh_degree: int, cams, target, *, cache_dtype: str = "f32", n_products: int = 10):
+def lm_autotune_tile(x, sh_degree: int, cams, target, *, cache_dtype: str = "f32", n_products: int = 10,
+                     ctx: Ctx | None = None):
     """Measured tile shape for one subset: ((tile_w, tile_h), [per-candidate
     dicts with build_ms and apply_ms])."""
     x = _dev_f32(x, "x")
@@ -464,30 +494,57 @@ def lm_autotune_tile(x, sh_degree: int, cams, target, *, cache_dtype: str = "f32
     carr = camera_array(cams)
     tw, th, ns = c_int32(0), c_int32(0), c_int32(0)
     sc = (LmTileScore * 16)()
-    _check(load().lm_autotune_tile(byref(scene), carr, c_int32(len(carr)), _ptr(target),
-                                   c_int32(CACHE_DTYPES[cache_dtype]), c_int32(n_products), _stream(), byref(tw),
-                                   byref(th), sc, c_int32(16), byref(ns)), "lm_autotune_tile")
+    opts = _opts((0, 0), CACHE_DTYPES[cache_dtype], 0, ctx)
+    _check(load().lm_autotune_tile(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts),
+                                   c_int32(n_products), _stream(), byref(tw), byref(th), sc, c_int32(16), byref(ns)),
+           "lm_autotune_tile")
     return (tw.value, th.value), [dict(tile=(sc[i].tile_w, sc[i].tile_h), build_ms=sc[i].build_ms,
                                        apply_ms=sc[i].apply_ms) for i in range(ns.value)]
 
 
-def lm_pcg_use_graph(mode: int) -> None:
+def lm_pcg_use_graph(mode: int, ctx: Ctx | None = None) -> None:
     """0: eager iterations, 1: graph replay, 2: graph replay for batches (default)."""
-    _check(load().lm_pcg_use_graph(c_int32(mode)), "lm_pcg_use_graph")
+    _check(load().lm_pcg_use_graph(_ctx_ptr(ctx), c_int32(mode)), "lm_pcg_use_graph")
 
 
-def lm_profile_enable(on: bool = True) -> None:
-    _check(load().lm_profile_enable(c_int32(1 if on else 0)), "lm_profile_enable")
+def lm_profile_enable(on: bool = True, ctx: Ctx | None = None) -> None:
+    _check(load().lm_profile_enable(_ctx_ptr(ctx), c_int32(1 if on else 0)), "lm_profile_enable")
 
 
-def lm_profile_read() -> dict:
+def lm_profile_read(ctx: Ctx | None = None) -> dict:
     """{kernel group: (launches, total ms)} recorded since the last read."""
     arr = (LmProfileEntry * 64)()
-    n = load().lm_profile_read(arr, c_int32(64))
+    n = load().lm_profile_read(_ctx_ptr(ctx), arr, c_int32(64))
     return {arr[i].name.decode(): (arr[i].launches, arr[i].total_ms) for i in range(n)}
 
 
-def lm_render(x, sh_degree: int, cams, *, tile=(16, 16), out=None):
+def lm_vec_dot(a, b, out=None, ctx: Ctx | None = None):
+    """a . b in float64 (1-element device tensor) for float32 device vectors."""
+    import torch
+    a = _dev_f32(a, "a")
+    b = _dev_f32(b, "b")
+    if a.numel() != b.numel():
+        raise ValueError("lm_vec_dot: sizes differ")
+    out = torch.empty(1, device=a.device, dtype=torch.float64) if out is None else out
+    _check(load().lm_vec_dot(_ctx_ptr(ctx), _ptr(a), _ptr(b), c_int64(a.numel()), _ptr(out), _stream()),
+           "lm_vec_dot")
+    return out
+
+
+def lm_vec_axpy(x, d, gamma: float, out=None):
+    """x + gamma d (float32 device tensors of one shape); out may be x."""
+    import torch
+    x = _dev_f32(x, "x")
+    d = _dev_f32(d, "d")
+    if x.numel() != d.numel():
+        raise ValueError("lm_vec_axpy: sizes differ")
+    out = torch.empty_like(x) if out is None else _dev_f32(out, "out")
+    _check(load().lm_vec_axpy(_ptr(x), _ptr(d), c_float(gamma), c_int64(x.numel()), _ptr(out), _stream()),
+           "lm_vec_axpy")
+    return out
+
+
+def lm_render(x, sh_degree: int, cams, *, tile=(16, 16), out=None, ctx: Ctx | None = None):
     """Forward render of every view into a flat float32 [V][3][H][W] tensor."""
     import torch
     x = _dev_f32(x, "x")
@@ -496,7 +553,7 @@ def lm_render(x, sh_degree: int, cams, *, tile=(16, 16), out=None):
     n = sum(3 * int(cams.W[v]) * int(cams.H[v]) for v in range(len(carr)))
     out = torch.empty(n, device=x.device, dtype=torch.float32) if out is None else out
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
-    opts = LmOptions(tile[0], tile[1], 0, 0)
+    opts = _opts(tile, ctx=ctx)
     _check(load().lm_render(byref(scene), carr, c_int32(len(carr)), byref(opts), _ptr(out), _stream()),
            "lm_render")
     return out

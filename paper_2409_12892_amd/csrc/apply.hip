@@ -36,10 +36,7 @@
 namespace lm {
 namespace {
 
-constexpr int kThreads = 256;  // threads per tile workgroup (4 wave64)
-constexpr int kChunk = 256;    // segments staged per LDS chunk
-constexpr int kRun = 8;        // pairs per run (segments are padded to runs)
-constexpr int kJWin = 4;       // 64-pair windows a wave of the J half has in flight
+constexpr int kRun = 8;        // pairs per run (pieces are padded to runs)
 constexpr int MODE_J = 1, MODE_JT = 2, MODE_JTJ = 3;
 
 
@@ -82,45 +79,25 @@ __device__ __forceinline__ int segment_head(uint32_t key, int lane) {
     return kWave - 1 - __clzll(heads & upto);
 }
 
+// One aligned run of 8 pairs as loaded: the words kept packed as loaded
+// (two 16-bit words per register for the 16-bit caches, four pixel bytes
+// per register), unpacked where used.
 template <int DT>
 struct RunLoad {
     using S = Store<DT>;
     using W = typename S::word;
-    W t[kRun];
-    W d[3][kRun];
-    uint8_t pix[kRun];
+    static constexpr int NWD = kRun * (int)sizeof(W) / 4;   // 32-bit registers per plane
+    uint32_t tw[NWD];
+    uint32_t dw[3][NWD];
+    uint32_t pw[2];
     uint32_t seg;
-    __device__ __forceinline__ void load(const CacheView& c, int64_t run) {
-        const int64_t qr = run * kRun;
-        seg = c.run_seg[run];
-        if constexpr (sizeof(W) == 4) {
-            const uint4* pt = (const uint4*)((const uint32_t*)c.pT + qr);
-            uint4 a = pt[0], b = pt[1];
-            t[0] = a.x; t[1] = a.y; t[2] = a.z; t[3] = a.w; t[4] = b.x; t[5] = b.y; t[6] = b.z; t[7] = b.w;
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const uint4* pd = (const uint4*)((const uint32_t*)c.pD + ch * c.pair_stride + qr);
-                uint4 e = pd[0], f = pd[1];
-                d[ch][0] = e.x; d[ch][1] = e.y; d[ch][2] = e.z; d[ch][3] = e.w;
-                d[ch][4] = f.x; d[ch][5] = f.y; d[ch][6] = f.z; d[ch][7] = f.w;
-            }
-        } else {
-            const uint4 a = *(const uint4*)((const uint16_t*)c.pT + qr);
-            const uint32_t wa[4] = {a.x, a.y, a.z, a.w};
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { t[2 * i] = (W)(wa[i] & 0xFFFF); t[2 * i + 1] = (W)(wa[i] >> 16); }
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const uint4 e = *(const uint4*)((const uint16_t*)c.pD + ch * c.pair_stride + qr);
-                const uint32_t we[4] = {e.x, e.y, e.z, e.w};
-#pragma unroll
-                for (int i = 0; i < 4; ++i) { d[ch][2 * i] = (W)(we[i] & 0xFFFF); d[ch][2 * i + 1] = (W)(we[i] >> 16); }
-            }
-        }
-        const uint2 px = *(const uint2*)(c.ppix + qr);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { pix[i] = (px.x >> (8 * i)) & 0xFF; pix[4 + i] = (px.y >> (8 * i)) & 0xFF; }
+    __device__ __forceinline__ W word(const uint32_t* p, int k) const {
+        if constexpr (sizeof(W) == 4) return p[k];
+        else return (W)((p[k >> 1] >> (16 * (k & 1))) & 0xFFFFu);
     }
+    __device__ __forceinline__ W t(int k) const { return word(tw, k); }
+    __device__ __forceinline__ W d(int ch, int k) const { return word(dw[ch], k); }
+    __device__ __forceinline__ int pix(int k) const { return (int)((pw[k >> 2] >> (8 * (k & 3))) & 0xFFu); }
 };
 
 // ---- linearisation: the projection of every (Gaussian, view) at x ----------
@@ -202,14 +179,6 @@ __global__ void __launch_bounds__(kBlock) k_tangent(ApplyBatch Bt) {
 // The staged splat holds the mean shifted to pixel-centre coordinates and
 // the conic scaled by -log2(e)/2 (and -log2(e) for B), so exp(power) is one
 // exp2 of a quadratic form.
-template <int DT>
-struct PairLoad {
-    using W = typename Store<DT>::word;
-    W t, d0, d1, d2;
-    uint8_t pix;
-    uint32_t seg;
-};
-
 constexpr float kLog2e = 1.4426950408889634f;
 
 // Buffer resources over one tile's slots: every plane is addressed by a
@@ -241,71 +210,67 @@ struct TilePlanes {
         if constexpr (sizeof(W) == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, q * 4, 0, 0);
         else return __builtin_amdgcn_raw_buffer_load_b16(r, q * 2, 0, 0);
     }
-    // slot q of the tile (the J half: one pair per lane)
-    __device__ __forceinline__ void pair(int q, PairLoad<DT>& L) const {
-        L.t = word(t, q);
-        L.d0 = word(d0, q);
-        L.d1 = word(d1, q);
-        L.d2 = word(d2, q);
-        L.pix = __builtin_amdgcn_raw_buffer_load_b8(pix, q, 0, 0);
-        L.seg = __builtin_amdgcn_raw_buffer_load_b32(seg, (q / kRun) * 4, 0, 0);
-    }
-    // aligned run r of the tile (the J^T half: eight pairs per lane)
+    // aligned run r of the tile (eight pairs per lane)
     __device__ __forceinline__ void run(int r, RunLoad<DT>& L) const {
         L.seg = __builtin_amdgcn_raw_buffer_load_b32(seg, r * 4, 0, 0);
-        if constexpr (sizeof(W) == 4) {
-            const int o = r * kRun * 4;
-            const auto a = __builtin_amdgcn_raw_buffer_load_b128(t, o, 0, 0);
-            const auto b = __builtin_amdgcn_raw_buffer_load_b128(t, o + 16, 0, 0);
+        constexpr int NWD = RunLoad<DT>::NWD;
+        const int o = r * NWD * 4;
+        const __amdgpu_buffer_rsrc_t pr[4] = {t, d0, d1, d2};
 #pragma unroll
-            for (int i = 0; i < 4; ++i) { L.t[i] = a[i]; L.t[4 + i] = b[i]; }
-            const __amdgpu_buffer_rsrc_t dr[3] = {d0, d1, d2};
+        for (int pl = 0; pl < 4; ++pl) {
+            uint32_t* dst = pl == 0 ? L.tw : L.dw[pl - 1];
 #pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const auto e = __builtin_amdgcn_raw_buffer_load_b128(dr[ch], o, 0, 0);
-                const auto f = __builtin_amdgcn_raw_buffer_load_b128(dr[ch], o + 16, 0, 0);
+            for (int h = 0; h < NWD / 4; ++h) {
+                const auto v = __builtin_amdgcn_raw_buffer_load_b128(pr[pl], o + 16 * h, 0, 0);
 #pragma unroll
-                for (int i = 0; i < 4; ++i) { L.d[ch][i] = e[i]; L.d[ch][4 + i] = f[i]; }
-            }
-        } else {
-            const int o = r * kRun * 2;
-            const auto a = __builtin_amdgcn_raw_buffer_load_b128(t, o, 0, 0);
-#pragma unroll
-            for (int i = 0; i < 4; ++i) { L.t[2 * i] = (W)(a[i] & 0xFFFF); L.t[2 * i + 1] = (W)(a[i] >> 16); }
-            const __amdgpu_buffer_rsrc_t dr[3] = {d0, d1, d2};
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) {
-                const auto e = __builtin_amdgcn_raw_buffer_load_b128(dr[ch], o, 0, 0);
-#pragma unroll
-                for (int i = 0; i < 4; ++i) { L.d[ch][2 * i] = (W)(e[i] & 0xFFFF); L.d[ch][2 * i + 1] = (W)(e[i] >> 16); }
+                for (int i = 0; i < 4; ++i) dst[4 * h + i] = v[i];
             }
         }
         const auto px = __builtin_amdgcn_raw_buffer_load_b64(pix, r * kRun, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) { L.pix[i] = (px[0] >> (8 * i)) & 0xFF; L.pix[4 + i] = (px[1] >> (8 * i)) & 0xFF; }
+        L.pw[0] = px[0];
+        L.pw[1] = px[1];
     }
 };
 
+// Tile pass.  One workgroup of 512 threads per tile.  The tile's pairs are
+// stored block after block (a block is the 64 pixels of one raster wave),
+// so after a block's pairs every one of its pixels has its complete
+// u = J p.  In the fused J^T J pass each lane loads up to kHeld<DT> runs of
+// the block into registers, adds their J rows into per-wave LDS
+// accumulators (ds_add; a run's eight pixels are distinct), the waves'
+// accumulators are summed into u, and the J^T half takes its moments from
+// the same registers: each pair is read from HBM once.  Runs past the
+// register capacity are streamed in each half.  Segment moments gather in
+// LDS across the tile's blocks and are written once per segment.
+//   A tile with more segments than LDS stages at once (kSegCap) runs
+// segment chunk after chunk: J over every chunk's runs (each block's runs
+// of a chunk are found by binary search: a block lists its pieces in depth
+// order) completes u for the tile, then J^T streams the runs again.
+constexpr int kTileThreads = 512;
+constexpr int kTileWaves = kTileThreads / kWave;
+constexpr int kSegCap = 640;
+template <int DT>
+struct Held {
+    static constexpr int R = sizeof(typename Store<DT>::word) == 4 ? 2 : 3;   // runs held per lane
+};
+
 template <int MODE, int DT>
-__global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
+__global__ void __launch_bounds__(kTileThreads, 4) k_apply_tile(ApplyBatch Bt) {
     int bi = 0;
     while (bi + 1 < Bt.n && (int64_t)blockIdx.x >= Bt.tile_off[bi + 1]) ++bi;
     const ApplyArgs& a = Bt.a[bi];
     if (a.stop && *a.stop) return;
     using S = Store<DT>;
-    constexpr int NW = kThreads / kWave;
-    constexpr int kZero = kMaxTilePix;           // pixel slot that stays 0 (read by padding)
+    constexpr int NW = kTileWaves;
+    constexpr int R = MODE == MODE_JTJ ? Held<DT>::R : 0;
+    constexpr int kZero = kMaxTilePix;           // u slot that stays 0 (read by padding)
+    constexpr int kNoSeg = kSegCap;              // segment key of a lane without a run
     const CacheView& c = a.c;
-    // s_u[w]: wave w's private accumulators (u0, u1, u2, -) per pixel in the
-    // J half; afterwards s_u[0] holds u, read by the J^T half, whose segment
-    // moments reuse the other accumulators' storage (LDS stays below a
-    // quarter of the CU's 160 KB: four tile workgroups per CU)
-    __shared__ float4 s_u[NW][kMaxTilePix + 1];
-    __shared__ float4 s_sg[kChunk][4];   // mx', my', A', B' | C', o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
-    __shared__ uint32_t s_loc[kChunk + 1];
+    __shared__ float4 s_sg[kSegCap][4];   // mx', my', A', B' | C', o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
+    __shared__ float s_mom[9][kSegCap];
+    __shared__ float4 s_uw[NW][kBlockPix];      // per-wave J accumulators of one block
+    __shared__ float4 s_ut[kMaxTilePix + 1];   // u of the tile (weighted once complete)
     __shared__ double s_red[NW];
-    static_assert(sizeof(float) * 9 * kChunk <= sizeof(float4) * (NW - 1) * (kMaxTilePix + 1), "moments");
-    float (*s_mom)[kChunk] = reinterpret_cast<float (*)[kChunk]>(&s_u[1][0]);
 
     const int64_t t = blockIdx.x - Bt.tile_off[bi];
     const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
@@ -314,24 +279,52 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
     const int64_t lt = t - cam.tile_base;
     const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
     const int tw_mask = c.TW - 1, tw_shift = c.tw_shift;
-    const int lx = tid & tw_mask, ly = tid >> tw_shift;
-    const int px = tx * c.TW + lx, py = ty * c.TH + ly;
-    const bool valid = tid < c.TW * c.TH && px < cam.W && py < cam.H;
+    const int npix = c.TW * c.TH;
+    const bool blk8 = c.TW >= 8 && c.TH >= 8;
+    const int bpr = c.TW >> 3;
+    const int nblk = (npix + kBlockPix - 1) / kBlockPix;
     const int64_t HW = (int64_t)cam.W * cam.H;
-    const int64_t ib = 3 * cam.pix_base + (int64_t)py * cam.W + px;
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
     const TilePlanes<DT> P(c, pb, pe);
-    for (int i = tid; i < NW * (kMaxTilePix + 1); i += kThreads) (&s_u[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    __syncthreads();
-    if (MODE == MODE_JT && tid < kMaxTilePix && valid)
-        s_u[0][tid] = make_float4(a.uin[ib], a.uin[ib + HW], a.uin[ib + 2 * HW], 0.0f);
+    int brun[kTileBlocks + 1];                   // tile-relative runs of each block
+    brun[0] = 0;
+#pragma unroll
+    for (int b = 0; b < kTileBlocks; ++b) brun[b + 1] = brun[b] + (int)(c.tile_blk[t * kTileBlocks + b] / kRun);
+    const uint32_t* rseg = c.run_seg + pb / kRun;
 
-    // segments [c0, c0 + cn) of the tile: splat data (and tangents) and pair
-    // ranges into LDS
+    // tile pixel of pixel i of block b, and a tile pixel's index in its block
+    auto blk_pixel = [&](int b, int i) -> int {
+        return blk8 ? (((b / bpr) << 3) + (i >> 3)) * c.TW + ((b % bpr) << 3) + (i & 7) : b * kBlockPix + i;
+    };
+    auto local_of = [&](int pl) -> int { return blk8 ? (((pl >> tw_shift) & 7) << 3) | (pl & 7) : pl & (kBlockPix - 1); };
+    auto pix_valid = [&](int pl) -> bool {
+        return pl < npix && tx * c.TW + (pl & tw_mask) < cam.W && ty * c.TH + (pl >> tw_shift) < cam.H;
+    };
+    auto img_index = [&](int pl) -> int64_t {
+        return 3 * cam.pix_base + (int64_t)(ty * c.TH + (pl >> tw_shift)) * cam.W + tx * c.TW + (pl & tw_mask);
+    };
+    // first run in [r0, r1) whose segment is >= key (runs ascend by segment within a block)
+    auto lower = [&](int r0, int r1, uint32_t key) -> int {
+        while (r0 < r1) {
+            const int m = (r0 + r1) >> 1;
+            if (rseg[m] < key) r0 = m + 1; else r1 = m;
+        }
+        return r0;
+    };
+
+    for (int i = tid; i <= kMaxTilePix; i += kTileThreads) s_ut[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i < NW * kBlockPix; i += kTileThreads) (&s_uw[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    __syncthreads();
+    if (MODE == MODE_JT && tid < npix && pix_valid(tid)) {
+        const int64_t ib = img_index(tid);
+        s_ut[tid] = make_float4(a.uin[ib], a.uin[ib + HW], a.uin[ib + 2 * HW], 0.0f);
+    }
+
+    // segments [c0, c0 + cn): splat data (and tangents) into LDS
     auto stage = [&](int c0, int cn, bool tangents) {
-        for (int i = tid; i < cn; i += kThreads) {
+        for (int i = tid; i < cn; i += kTileThreads) {
             const int64_t s = sb + c0 + i;
             const int64_t ss = c.seg_stride;
             s_sg[i][0] = make_float4(c.seg_f[s] - 0.5f, c.seg_f[ss + s] - 0.5f, -0.5f * kLog2e * c.seg_f[2 * ss + s],
@@ -345,108 +338,239 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
                 s_sg[i][3] = make_float4(dy[6], dy[7], dy[8], 0.0f);
             }
             s_sg[i][1] = w1;
-            s_loc[i] = c.seg_loc[s];
         }
-        if (tid == 0) s_loc[cn] = c0 + cn < nseg ? c.seg_loc[sb + c0 + cn] : (uint32_t)(pe - pb);
+    };
+    auto zero_mom = [&](int cn) {
+        for (int i = tid; i < cn; i += kTileThreads)
+#pragma unroll
+            for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
+    };
+    // staged index of a run's segment (kNoSeg: no run, or not in the chunk)
+    auto staged = [&](const RunLoad<DT>& L, bool has, int64_t s0, int cn) -> int {
+        const int64_t sl = (int64_t)L.seg - s0;
+        return (has && sl >= 0 && sl < cn) ? (int)sl : kNoSeg;
     };
 
-    // ---------------- J p ----------------
-    // Wave w takes the 64-pair windows w, w + NW, ... of each chunk's pairs,
-    // one pair per lane, kJWin windows per round (the next kJWin loading),
-    // and adds into its private accumulators.  Pixels are
-    // distinct within a segment, so the window's segment pieces (contiguous
-    // lane ranges) update the accumulators one after another and need no
-    // atomics.
-    if (MODE & MODE_J) {
-        float4* up = s_u[wid];
-        for (int c0 = 0; c0 < nseg; c0 += kChunk) {
-            const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
-            __syncthreads();
-            stage(c0, cn, true);
-            __syncthreads();
-            const int q0 = (int)s_loc[0], q1 = (int)s_loc[cn];
-            const int nwin = (q1 - q0 + kWave - 1) / kWave;
-            const int64_t sbase = sb + c0;
-            // window w; slots past the chunk belong to later segments (not
-            // live) or lie past the tile (read as 0)
-            auto ld = [&](PairLoad<DT>& L, int w) { P.pair(q0 + w * kWave + lane, L); };
-            PairLoad<DT> nx[kJWin];
+    // J rows of one run into this wave's accumulators
+    auto j_run = [&](const RunLoad<DT>& L, int s) {
+        if (s == kNoSeg) return;
+        const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
+        float4* up = s_uw[wid];
 #pragma unroll
-            for (int h = 0; h < kJWin; ++h) ld(nx[h], wid + h * NW);
-            for (int win = wid; win < nwin; win += kJWin * NW) {
-                PairLoad<DT> Ls[kJWin];
+        for (int k = 0; k < kRun; ++k) {
+            if (L.t(k) == 0) continue;                  // padding
+            const float T = S::dec_T(L.t(k));
+            const bool clamped = S::clamp(L.t(k));
+            const int pl = L.pix(k);
+            const float dx = (float)(pl & tw_mask) - g0.x;
+            const float dy = (float)(pl >> tw_shift) - g0.y;
+            const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
+            const float alpha = clamped ? 0.99f : g1.y * G;
+            const float aT = alpha * T;
+            const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
+            const float dal = clamped ? 0.0f : dal_f;
+            const int li = local_of(pl);
+            atomicAdd(&up[li].x, S::dec(L.d(0, k)) * dal + aT * g3.x);
+            atomicAdd(&up[li].y, S::dec(L.d(1, k)) * dal + aT * g3.y);
+            atomicAdd(&up[li].z, S::dec(L.d(2, k)) * dal + aT * g3.z);
+        }
+    };
+    // J^T moments of one run per lane, reduced over the wave's lanes by
+    // segment (runs ascend with the lane) and added into the segment sums
+    auto jt_round = [&](const RunLoad<DT>& L, int s) {
+        float m[9];
 #pragma unroll
-                for (int h = 0; h < kJWin; ++h) {
-                    Ls[h] = nx[h];
-                    ld(nx[h], win + (kJWin + h) * NW);
-                }
+        for (int k = 0; k < 9; ++k) m[k] = 0.0f;
+        if (s != kNoSeg) {
+            const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
 #pragma unroll
-                for (int h = 0; h < kJWin; ++h) {
-                    const PairLoad<DT>& L = Ls[h];
-                    const uint32_t sl = L.seg - (uint32_t)sbase;      // segment ids fit 32 bits
-                    const bool live = L.t != 0 && sl < (uint32_t)cn;
-                    const int s = live ? (int)sl : 0;
-                    const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
-                    const float T = S::dec_T(L.t);
-                    const bool clamped = S::clamp(L.t);
-                    const int pl = L.pix;
-                    const float dx = (float)(pl & tw_mask) - g0.x;
-                    const float dy = (float)(pl >> tw_shift) - g0.y;
-                    const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
-                    const float alpha = clamped ? 0.99f : g1.y * G;
-                    const float aT = alpha * T;
-                    const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
-                    const float dal = clamped ? 0.0f : dal_f;
-                    const float v0 = S::dec(L.d0) * dal + aT * g3.x;
-                    const float v1 = S::dec(L.d1) * dal + aT * g3.y;
-                    const float v2 = S::dec(L.d2) * dal + aT * g3.z;
-                    uint64_t todo = __ballot(live);
-                    while (todo) {
-                        const int first = __ffsll((unsigned long long)todo) - 1;
-                        const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)L.seg, first);
-                        const bool mine = live && L.seg == sk;
-                        todo &= ~__ballot(mine);
-                        if (mine) {
-                            float4 u = up[pl];
-                            u.x += v0;
-                            u.y += v1;
-                            u.z += v2;
-                            up[pl] = u;
-                        }
-                    }
-                }
+            for (int k = 0; k < kRun; ++k) {
+                const float T = S::dec_T(L.t(k));
+                const bool clamped = S::clamp(L.t(k));
+                const int pl = L.pix(k);
+                const float dx = (float)(pl & tw_mask) - g0.x;
+                const float dy = (float)(pl >> tw_shift) - g0.y;
+                const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
+                const float alpha = clamped ? 0.99f : g1.y * G;
+                const float aT = alpha * T;                               // 0 for padding
+                const float4 u = s_ut[L.t(k) != 0 ? pl : kZero];         // padding reads u = 0
+                const float w = S::dec(L.d(0, k)) * u.x + S::dec(L.d(1, k)) * u.y + S::dec(L.d(2, k)) * u.z;
+                const float aw = clamped ? 0.0f : alpha * w;
+                const float awx = aw * dx, awy = aw * dy;
+                m[0] += awx;
+                m[1] += awy;
+                m[2] += awx * dx;
+                m[3] += awx * dy;
+                m[4] += awy * dy;
+                m[5] += clamped ? 0.0f : G * w;
+                m[6] += aT * u.x;
+                m[7] += aT * u.y;
+                m[8] += aT * u.z;
             }
         }
-        __syncthreads();
-        // u = sum of the waves' accumulators; ||J p||^2 of the tile
-        double sq = 0.0;
-        if (tid < kMaxTilePix) {
-            float4 u = s_u[0][tid];
+        const int next = __shfl_down(s, 1, kWave);
+        wave_segmented_scan<9>(m, lane, segment_head((uint32_t)s, lane));
+        if (s != kNoSeg && (lane == kWave - 1 || next != s)) {
+#pragma unroll
+            for (int k = 0; k < 9; ++k) atomicAdd(&s_mom[k][s], m[k]);
+        }
+    };
+    // runs [r0, r1) streamed, 512 per round, the next round loading
+    auto stream_j = [&](int r0, int r1, int64_t s0, int cn) {
+        if (r0 >= r1) return;
+        RunLoad<DT> nxt;
+        P.run(r0 + tid, nxt);
+        for (int base = r0; base < r1; base += kTileThreads) {
+            const RunLoad<DT> L = nxt;
+            const bool has = base + tid < r1;
+            if (base + kTileThreads < r1) P.run(base + kTileThreads + tid, nxt);
+            j_run(L, staged(L, has, s0, cn));
+        }
+    };
+    auto stream_jt = [&](int r0, int r1, int64_t s0, int cn) {
+        if (r0 >= r1) return;
+        RunLoad<DT> nxt;
+        P.run(r0 + tid, nxt);
+        for (int base = r0; base < r1; base += kTileThreads) {
+            const RunLoad<DT> L = nxt;
+            const bool has = base + tid < r1;
+            if (base + kTileThreads < r1) P.run(base + kTileThreads + tid, nxt);
+            jt_round(L, staged(L, has, s0, cn));
+        }
+    };
+    // the waves' accumulators of block b added into u (and cleared)
+    auto gather_u = [&](int b) {
+        if (tid < kBlockPix) {
+            float4 u = s_uw[0][tid];
+            s_uw[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
 #pragma unroll
             for (int w = 1; w < NW; ++w) {
-                const float4 o = s_u[w][tid];
+                const float4 o = s_uw[w][tid];
+                s_uw[w][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
                 u.x += o.x;
                 u.y += o.y;
                 u.z += o.z;
             }
-            // residual weights (w . u between the halves; ||J p||^2 becomes
-            // sum w u^2)
-            float4 wu = u;
-            if (valid && c.wres) {
-                wu.x = u.x * c.wres[ib];
-                wu.y = u.y * c.wres[ib + HW];
-                wu.z = u.z * c.wres[ib + 2 * HW];
-            }
-            s_u[0][tid] = wu;
-            if (valid) {
-                sq = (double)u.x * (double)wu.x + (double)u.y * (double)wu.y + (double)u.z * (double)wu.z;
-                if (MODE == MODE_J && a.uout) {
-                    a.uout[ib] = u.x;
-                    a.uout[ib + HW] = u.y;
-                    a.uout[ib + 2 * HW] = u.z;
-                }
+            const int pl = blk_pixel(b, tid);
+            if (pl < npix) {
+                float4 acc = s_ut[pl];
+                acc.x += u.x;
+                acc.y += u.y;
+                acc.z += u.z;
+                s_ut[pl] = acc;
             }
         }
+    };
+    // u of block b complete: ||J p||^2 (sum w u^2 with residual weights),
+    // the J output, and w . u for the J^T half
+    double sq = 0.0;
+    auto finish_u = [&](int b) {
+        if (tid < kBlockPix) {
+            const int pl = blk_pixel(b, tid);
+            if (pl < npix) {
+                const float4 u = s_ut[pl];
+                float4 wu = u;
+                if (pix_valid(pl)) {
+                    const int64_t ib = img_index(pl);
+                    if (c.wres) {
+                        wu.x = u.x * c.wres[ib];
+                        wu.y = u.y * c.wres[ib + HW];
+                        wu.z = u.z * c.wres[ib + 2 * HW];
+                    }
+                    sq += (double)u.x * (double)wu.x + (double)u.y * (double)wu.y + (double)u.z * (double)wu.z;
+                    if (MODE == MODE_J && a.uout) {
+                        a.uout[ib] = u.x;
+                        a.uout[ib + HW] = u.y;
+                        a.uout[ib + 2 * HW] = u.z;
+                    }
+                }
+                s_ut[pl] = wu;
+            }
+        }
+    };
+    auto write_mom = [&](int c0, int cn) {
+        for (int i = tid; i < cn * 9; i += kTileThreads) {
+            const int si = i / 9, k = i - si * 9;
+            a.gmom[(int64_t)c.seg_pos[sb + c0 + si] * 9 + k] = s_mom[k][si];
+        }
+    };
+
+    if (nseg <= kSegCap) {
+        stage(0, nseg, (MODE & MODE_J) != 0);
+        if (MODE & MODE_JT) zero_mom(nseg);
+        __syncthreads();
+        for (int b = 0; b < nblk; ++b) {
+            const int r0 = brun[b], r1 = brun[b + 1];
+            if (r0 == r1) continue;
+            const int rh = R > 0 ? min(r1, r0 + R * kTileThreads) : r0;   // runs held in registers
+            RunLoad<DT> held[R > 0 ? R : 1];
+            int hs[R > 0 ? R : 1];
+            if (MODE & MODE_J) {
+                // runs past the register capacity first (streamed), so that
+                // the held runs and the stream's buffers are never live together
+                stream_j(rh, r1, sb, nseg);
+#pragma unroll
+                for (int k = 0; k < R; ++k) {
+                    const int run = r0 + k * kTileThreads + tid;
+                    P.run(run, held[k]);
+                    hs[k] = staged(held[k], run < rh, sb, nseg);
+                }
+#pragma unroll
+                for (int k = 0; k < R; ++k) j_run(held[k], hs[k]);
+                __syncthreads();
+                gather_u(b);
+                __syncthreads();
+                finish_u(b);
+                __syncthreads();
+            }
+            if (MODE & MODE_JT) {
+#pragma unroll
+                for (int k = 0; k < R; ++k) jt_round(held[k], hs[k]);
+                stream_jt(rh, r1, sb, nseg);
+            }
+        }
+        if (MODE & MODE_JT) {
+            __syncthreads();
+            write_mom(0, nseg);
+        }
+    } else {
+        if (MODE & MODE_J) {
+            for (int c0 = 0; c0 < nseg; c0 += kSegCap) {
+                const int cn = min(nseg - c0, kSegCap);
+                __syncthreads();
+                stage(c0, cn, true);
+                __syncthreads();
+                for (int b = 0; b < nblk; ++b) {
+                    const int lo = lower(brun[b], brun[b + 1], (uint32_t)(sb + c0));
+                    const int hi = lower(lo, brun[b + 1], (uint32_t)(sb + c0 + cn));
+                    if (lo == hi) continue;
+                    stream_j(lo, hi, sb + c0, cn);
+                    __syncthreads();
+                    gather_u(b);
+                    __syncthreads();
+                }
+            }
+            for (int b = 0; b < nblk; ++b) finish_u(b);
+        }
+        if (MODE & MODE_JT) {
+            for (int c0 = 0; c0 < nseg; c0 += kSegCap) {
+                const int cn = min(nseg - c0, kSegCap);
+                __syncthreads();
+                stage(c0, cn, false);
+                zero_mom(cn);
+                __syncthreads();
+                for (int b = 0; b < nblk; ++b) {
+                    const int lo = lower(brun[b], brun[b + 1], (uint32_t)(sb + c0));
+                    const int hi = lower(lo, brun[b + 1], (uint32_t)(sb + c0 + cn));
+                    stream_jt(lo, hi, sb + c0, cn);
+                }
+                __syncthreads();
+                write_mom(c0, cn);
+            }
+        }
+    }
+    if (MODE & MODE_J) {
+        // ||J p||^2 of the tile, summed in a fixed order
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) sq += __shfl_xor(sq, off, kWave);
         if (lane == 0) s_red[wid] = sq;
@@ -455,78 +579,6 @@ __global__ void __launch_bounds__(kThreads) k_apply_tile(ApplyBatch Bt) {
             double tot = 0.0;
             for (int w = 0; w < NW; ++w) tot += s_red[w];
             a.jp_part[t] = tot;
-        }
-        if (MODE == MODE_J) return;
-    }
-
-    // ---------------- J^T u ----------------
-    for (int c0 = 0; c0 < nseg; c0 += kChunk) {
-        const int cn = nseg - c0 < kChunk ? nseg - c0 : kChunk;
-        __syncthreads();
-        stage(c0, cn, false);
-        for (int i = tid; i < cn; i += kThreads)
-#pragma unroll
-            for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
-        __syncthreads();
-        const int r0 = (int)s_loc[0] / kRun, r1 = (int)s_loc[cn] / kRun;   // tile-local runs
-        // rounds of kThreads runs, last first: the J half ended on the
-        // chunk's last pairs, which are the likeliest to be still cached
-        const int nround = (r1 - r0 + kThreads - 1) / kThreads;
-        RunLoad<DT> nxt;
-        P.run(r0 + (nround > 0 ? nround - 1 : 0) * kThreads + tid, nxt);
-        // every lane runs every round (converged for the wave scan); lanes
-        // without a run carry zeros under a key of their own
-        for (int k = nround - 1; k >= 0; --k) {
-            const int base = r0 + k * kThreads;
-            const int run = base + tid;
-            const bool has = run < r1;
-            const RunLoad<DT> L = nxt;
-            if (k > 0) P.run(base - kThreads + tid, nxt);
-            const int64_t sl = (int64_t)L.seg - (sb + c0);
-            const int s = (has && sl >= 0 && sl < cn) ? (int)sl : kChunk;   // kChunk: no run (or an inconsistent cache)
-            float m[9];
-#pragma unroll
-            for (int k = 0; k < 9; ++k) m[k] = 0.0f;
-            if (s < kChunk) {
-                const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
-#pragma unroll
-                for (int k = 0; k < kRun; ++k) {
-                    const float T = S::dec_T(L.t[k]);
-                    const bool clamped = S::clamp(L.t[k]);
-                    const int pl = L.pix[k];
-                    const float dx = (float)(pl & tw_mask) - g0.x;
-                    const float dy = (float)(pl >> tw_shift) - g0.y;
-                    const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
-                    const float alpha = clamped ? 0.99f : g1.y * G;
-                    const float aT = alpha * T;                               // 0 for padding
-                    const float4 u = s_u[0][L.t[k] != 0 ? pl : kZero];       // padding reads u = 0
-                    const float w = S::dec(L.d[0][k]) * u.x + S::dec(L.d[1][k]) * u.y + S::dec(L.d[2][k]) * u.z;
-                    const float aw = clamped ? 0.0f : alpha * w;
-                    const float awx = aw * dx, awy = aw * dy;
-                    m[0] += awx;
-                    m[1] += awy;
-                    m[2] += awx * dx;
-                    m[3] += awx * dy;
-                    m[4] += awy * dy;
-                    m[5] += clamped ? 0.0f : G * w;
-                    m[6] += aT * u.x;
-                    m[7] += aT * u.y;
-                    m[8] += aT * u.z;
-                }
-            }
-            // segmented scan over the wave: runs ascend with the lane, so each
-            // segment is a contiguous lane range; its last lane adds the sum
-            const int next = __shfl_down(s, 1, kWave);
-            wave_segmented_scan<9>(m, lane, segment_head((uint32_t)s, lane));
-            if (s < kChunk && (lane == kWave - 1 || next != s)) {
-#pragma unroll
-                for (int k = 0; k < 9; ++k) atomicAdd(&s_mom[k][s], m[k]);
-            }
-        }
-        __syncthreads();
-        for (int i = tid; i < cn * 9; i += kThreads) {
-            const int si = i / 9, k = i - si * 9;
-            a.gmom[(int64_t)c.seg_pos[sb + c0 + si] * 9 + k] = s_mom[k][si];
         }
     }
 }
@@ -750,155 +802,133 @@ constexpr int kGram = kGramValues;
 
 __device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i * (i - 1)) / 2 + (k - i); }
 
-// One lane per aligned 8-pair run of the whole cache.  A segment's runs
-// are adjacent, so after a segmented scan across the wave the last lane of
-// each segment piece holds the piece's sums: a piece that is a whole segment
-// is stored; a wave's piece that continues into the next wave (slot 1) or
-// comes from the previous one (slot 0) goes to the wave's edge slots, and
-// k_gram_join adds the pieces in wave order.
+// One workgroup per tile.  The tile's segments are taken in chunks of
+// kGramChunk with their Gram sums in LDS; for every block the chunk's runs
+// (found by binary search: a block lists its pieces in depth order) are
+// taken one per lane, each lane sums its run's 8 pairs, a segmented scan
+// over the wave (runs ascend with the lane) leaves one LDS add per segment
+// piece and wave, and the chunk's sums are written at the segments' list
+// positions.
+constexpr int kGramChunk = 256;
+
 template <int DT>
-__global__ void __launch_bounds__(kBlock) k_gram_runs(CacheView c, int64_t n_runs, float* __restrict__ gram,
-                                                     float* __restrict__ edge, uint32_t* __restrict__ ekey,
-                                                     uint32_t* __restrict__ eends) {
+__global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __restrict__ gram) {
     using S = Store<DT>;
-    const int64_t run = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    const int lane = __lane_id();
+    __shared__ float s_g[kGram][kGramChunk];
+    __shared__ float s_sp[6][kGramChunk];
+    const int64_t t = blockIdx.x;
+    const int tid = threadIdx.x, lane = __lane_id();
+    const int v = c.tile_view[t];
+    const CamDev& cam = c.cams[v];
+    const int64_t lt = t - cam.tile_base;
+    const int tx0 = (int)(lt % cam.TX) * c.TW, ty0 = (int)(lt / cam.TX) * c.TH;
     const int tw_mask = c.TW - 1, tw_shift = c.tw_shift;
-    const bool has = run < n_runs;
-    float acc[kGram];
+    const int64_t HW = (int64_t)cam.W * cam.H, ib0 = 3 * cam.pix_base;
+    const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
+    const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
+    const int nseg = (int)(se - sb);
+    const TilePlanes<DT> P(c, pb, pe);
+    const uint32_t* rseg = c.run_seg + pb / kRun;
+    int brun[kTileBlocks + 1];
+    brun[0] = 0;
 #pragma unroll
-    for (int k = 0; k < kGram; ++k) acc[k] = 0.0f;
-    uint32_t key = 0xFFFFFFFFu;
-    if (has) {
-        RunLoad<DT> L;
-        L.load(c, run);
-        key = L.seg;
-        const int64_t ss = c.seg_stride, sg = L.seg;
-        const float mlx = c.seg_f[sg], mly = c.seg_f[ss + sg];
-        const float A = c.seg_f[2 * ss + sg], B = c.seg_f[3 * ss + sg], C = c.seg_f[4 * ss + sg];
-        const float o = c.seg_f[5 * ss + sg];
-        // residual weights: the run's tile gives the view and the pixels'
-        // image positions.  The wave's first active lane finds its tile by a
-        // binary search over the tiles' segment ranges; segments ascend with
-        // the lane, so the others step forward from there (a wave's 512
-        // pairs rarely span two tiles).
-        int64_t wb = 0, whw = 0;
-        int wtx = 0, wty = 0, wW = 0, wH = 0;
-        if (c.wres) {
-            const int64_t s0 = (int64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)L.seg);
-            int64_t lo = 0, hi = c.n_tiles - 1;
-            while (lo < hi) {
-                const int64_t mid = (lo + hi + 1) >> 1;
-                if (c.tile_seg_off[mid] <= s0) lo = mid; else hi = mid - 1;
-            }
-            while (lo + 1 < c.n_tiles && c.tile_seg_off[lo + 1] <= sg) ++lo;
-            const CamDev& cam = c.cams[c.tile_view[lo]];
-            const int64_t lt = lo - cam.tile_base;
-            wtx = (int)(lt % cam.TX) * c.TW;
-            wty = (int)(lt / cam.TX) * c.TH;
-            wW = cam.W;
-            wH = cam.H;
-            whw = (int64_t)cam.W * cam.H;
-            wb = 3 * cam.pix_base;
+    for (int b = 0; b < kTileBlocks; ++b) brun[b + 1] = brun[b] + (int)(c.tile_blk[t * kTileBlocks + b] / kRun);
+    auto lower = [&](int r0, int r1, uint32_t key) -> int {
+        while (r0 < r1) {
+            const int m = (r0 + r1) >> 1;
+            if (rseg[m] < key) r0 = m + 1; else r1 = m;
         }
+        return r0;
+    };
+    for (int c0 = 0; c0 < nseg; c0 += kGramChunk) {
+        const int cn = min(nseg - c0, kGramChunk);
+        __syncthreads();
+        for (int i = tid; i < cn; i += kBlock) {
+            const int64_t sg = sb + c0 + i, ss = c.seg_stride;
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            const bool live = L.t[k] != 0;                  // padding contributes nothing
-            const float T = S::dec_T(L.t[k]);
-            const bool clamped = S::clamp(L.t[k]);
-            const float D0 = S::dec(L.d[0][k]), D1 = S::dec(L.d[1][k]), D2 = S::dec(L.d[2][k]);
-            const int pl = L.pix[k];
-            const float dx = (float)(pl & tw_mask) + 0.5f - mlx, dy = (float)(pl >> tw_shift) + 0.5f - mly;
-            const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
-            const float G = __expf(power);
-            const float alpha = clamped ? 0.99f : o * G;
-            const float e = live ? alpha * T : 0.0f;
-            const float ag = (clamped || !live) ? 0.0f : alpha;
-            float bb[6];
-            bb[0] = ag * dx; bb[1] = ag * dy; bb[2] = ag * dx * dx;
-            bb[3] = ag * dx * dy; bb[4] = ag * dy * dy; bb[5] = (clamped || !live) ? 0.0f : G;
-            float w0 = 1.0f, w1 = 1.0f, w2 = 1.0f;
-            if (c.wres) {
-                const int gx = wtx + (pl & tw_mask), gy = wty + (pl >> tw_shift);
-                if (live && gx < wW && gy < wH) {
-                    const int64_t ib = wb + (int64_t)gy * wW + gx;
-                    w0 = c.wres[ib];
-                    w1 = c.wres[ib + whw];
-                    w2 = c.wres[ib + 2 * whw];
+            for (int k = 0; k < 6; ++k) s_sp[k][i] = c.seg_f[k * ss + sg];
+#pragma unroll
+            for (int k = 0; k < kGram; ++k) s_g[k][i] = 0.0f;
+        }
+        __syncthreads();
+        for (int b = 0; b < kTileBlocks; ++b) {
+            const int lo = lower(brun[b], brun[b + 1], (uint32_t)(sb + c0));
+            const int hi = lower(lo, brun[b + 1], (uint32_t)(sb + c0 + cn));
+            for (int base = lo; base < hi; base += kBlock) {
+                const int run = base + tid;
+                float acc[kGram];
+#pragma unroll
+                for (int k = 0; k < kGram; ++k) acc[k] = 0.0f;
+                int key = kGramChunk;                 // no run
+                if (run < hi) {
+                    RunLoad<DT> L;
+                    P.run(run, L);
+                    const int64_t sl = (int64_t)L.seg - (sb + c0);
+                    if (sl >= 0 && sl < cn) key = (int)sl;
+                    if (key < kGramChunk) {
+                        const float mlx = s_sp[0][key], mly = s_sp[1][key];
+                        const float A = s_sp[2][key], B = s_sp[3][key], C = s_sp[4][key], o = s_sp[5][key];
+#pragma unroll
+                        for (int k = 0; k < kRun; ++k) {
+                            const bool live = L.t(k) != 0;                  // padding contributes nothing
+                            const float T = S::dec_T(L.t(k));
+                            const bool clamped = S::clamp(L.t(k));
+                            const float D0 = S::dec(L.d(0, k)), D1 = S::dec(L.d(1, k)), D2 = S::dec(L.d(2, k));
+                            const int pl = L.pix(k);
+                            const float dx = (float)(pl & tw_mask) + 0.5f - mlx, dy = (float)(pl >> tw_shift) + 0.5f - mly;
+                            const float power = -0.5f * (A * dx * dx + C * dy * dy) - B * dx * dy;
+                            const float G = __expf(power);
+                            const float alpha = clamped ? 0.99f : o * G;
+                            const float e = live ? alpha * T : 0.0f;
+                            const float ag = (clamped || !live) ? 0.0f : alpha;
+                            float bb[6];
+                            bb[0] = ag * dx; bb[1] = ag * dy; bb[2] = ag * dx * dx;
+                            bb[3] = ag * dx * dy; bb[4] = ag * dy * dy; bb[5] = (clamped || !live) ? 0.0f : G;
+                            float w0 = 1.0f, w1 = 1.0f, w2 = 1.0f;
+                            if (c.wres) {
+                                const int gx = tx0 + (pl & tw_mask), gy = ty0 + (pl >> tw_shift);
+                                if (live && gx < cam.W && gy < cam.H) {
+                                    const int64_t ib = ib0 + (int64_t)gy * cam.W + gx;
+                                    w0 = c.wres[ib];
+                                    w1 = c.wres[ib + HW];
+                                    w2 = c.wres[ib + 2 * HW];
+                                }
+                            }
+                            const float WD0 = w0 * D0, WD1 = w1 * D1, WD2 = w2 * D2;
+                            const float DD = WD0 * D0 + WD1 * D1 + WD2 * D2;
+#pragma unroll
+                            for (int i = 0; i < 6; ++i)
+#pragma unroll
+                                for (int j = i; j < 6; ++j) acc[tri6(i, j)] += DD * bb[i] * bb[j];
+#pragma unroll
+                            for (int i = 0; i < 6; ++i) {
+                                const float eb = e * bb[i];
+                                acc[21 + 3 * i] += eb * WD0;
+                                acc[22 + 3 * i] += eb * WD1;
+                                acc[23 + 3 * i] += eb * WD2;
+                            }
+                            const float ee = e * e;
+                            acc[39] += w0 * ee;
+                            acc[40] += w1 * ee;
+                            acc[41] += w2 * ee;
+                            acc[42] += live ? 1.0f : 0.0f;
+                        }
+                    }
+                }
+                const int next = __shfl_down(key, 1, kWave);
+                wave_segmented_scan<kGram>(acc, lane, segment_head((uint32_t)key, lane));
+                if (key < kGramChunk && (lane == kWave - 1 || next != key)) {
+#pragma unroll
+                    for (int k = 0; k < kGram; ++k) atomicAdd(&s_g[k][key], acc[k]);
                 }
             }
-            const float WD0 = w0 * D0, WD1 = w1 * D1, WD2 = w2 * D2;
-            const float DD = WD0 * D0 + WD1 * D1 + WD2 * D2;
-#pragma unroll
-            for (int i = 0; i < 6; ++i)
-#pragma unroll
-                for (int j = i; j < 6; ++j) acc[tri6(i, j)] += DD * bb[i] * bb[j];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                const float eb = e * bb[i];
-                acc[21 + 3 * i] += eb * WD0;
-                acc[22 + 3 * i] += eb * WD1;
-                acc[23 + 3 * i] += eb * WD2;
-            }
-            const float ee = e * e;
-            acc[39] += w0 * ee;
-            acc[40] += w1 * ee;
-            acc[41] += w2 * ee;
-            acc[42] += live ? 1.0f : 0.0f;
+        }
+        __syncthreads();
+        for (int i = tid; i < cn * kGram; i += kBlock) {
+            const int si = i / kGram, k = i - si * kGram;
+            gram[(int64_t)c.seg_pos[sb + c0 + si] * kGram + k] = s_g[k][si];
         }
     }
-    const uint32_t next = __shfl_down(key, 1, kWave);
-    const int head = segment_head(key, lane);
-    wave_segmented_scan<kGram>(acc, lane, head);
-    if (lane == kWave - 1 || next != key) {
-        const int64_t wave = run / kWave;
-        bool starts = true, ends = true;
-        if (has) {
-            const int64_t first = run - (lane - head);
-            starts = head > 0 || first == 0 || c.run_seg[first - 1] != key;
-            ends = lane < kWave - 1 || run + 1 >= n_runs || c.run_seg[run + 1] != key;
-        }
-        float* out = nullptr;
-        if (has && starts && ends) {
-            out = gram + (int64_t)c.seg_pos[key] * kGram;   // at the segment's list position
-        } else if (has && starts) {              // continues into the next wave (lane 63)
-            out = edge + (wave * 2 + 1) * kGram;
-            ekey[wave * 2 + 1] = key;
-        } else if (has) {                        // comes from the previous wave (the first piece)
-            out = edge + wave * 2 * kGram;
-            ekey[wave * 2] = key;
-            eends[wave] = ends ? 1u : 0u;
-        }
-        if (out) {
-#pragma unroll
-            for (int k = 0; k < kGram; ++k) out[k] = acc[k];
-        }
-        if (lane == kWave - 1 && !(has && starts && !ends)) ekey[wave * 2 + 1] = kNoGv;
-        if (head == 0 && !(has && !starts)) ekey[wave * 2] = kNoGv;
-    }
-}
-
-// Segments whose runs span waves: the wave where the segment starts adds
-// the pieces of the following waves in order and stores the sums.
-__global__ void __launch_bounds__(kBlock) k_gram_join(int64_t n_waves, const float* __restrict__ edge,
-                                                     const uint32_t* __restrict__ ekey,
-                                                     const uint32_t* __restrict__ eends,
-                                                     const uint32_t* __restrict__ seg_pos, float* __restrict__ gram) {
-    const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= n_waves) return;
-    const uint32_t key = ekey[w * 2 + 1];
-    if (key == kNoGv) return;
-    float acc[kGram];
-#pragma unroll
-    for (int k = 0; k < kGram; ++k) acc[k] = edge[(w * 2 + 1) * kGram + k];
-    for (int64_t u = w + 1; u < n_waves && ekey[u * 2] == key; ++u) {
-#pragma unroll
-        for (int k = 0; k < kGram; ++k) acc[k] += edge[u * 2 * kGram + k];
-        if (eends[u]) break;
-    }
-    float* out = gram + (int64_t)seg_pos[key] * kGram;
-#pragma unroll
-    for (int k = 0; k < kGram; ++k) out[k] = acc[k];
 }
 
 __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
@@ -1346,7 +1376,7 @@ hipError_t launch_tangent(const ApplyBatch& B, hipStream_t s) {
 hipError_t launch_apply_tile(int mode, const ApplyBatch& B, hipStream_t s) {
     const int64_t nt = B.tile_off[B.n];
     if (nt == 0) return hipSuccess;
-    dim3 g((unsigned)nt), b(kThreads);
+    dim3 g((unsigned)nt), b(kTileThreads);
 #define LM_APPLY_CASE(MODE, DT) hipLaunchKernelGGL((k_apply_tile<MODE, DT>), g, b, 0, s, B)
     const int dtype = B.a[0].c.dtype;
     if (dtype == LM_CACHE_F32) {
@@ -1457,23 +1487,13 @@ hipError_t launch_precond_features(const float* M, const float* coverage, const 
     return hipGetLastError();
 }
 
-int64_t gram_run_waves(int64_t n_pairs) { return (int64_t)grid_for(n_pairs / kRun) * (kBlock / kWave); }
-
 hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
-                       float* run_edge, uint32_t* run_ekey, uint32_t* run_eends, hipStream_t s) {
-    dim3 b(kBlock);
-    const int64_t n_runs = c.n_pairs / kRun;
-    if (n_runs > 0) {
-        const dim3 g(grid_for(n_runs));
-        const int64_t nw = gram_run_waves(c.n_pairs);
-        if (c.dtype == LM_CACHE_F32)
-            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F32>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
-        else if (c.dtype == LM_CACHE_BF16)
-            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_BF16>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
-        else
-            hipLaunchKernelGGL((k_gram_runs<LM_CACHE_F16>), g, b, 0, s, c, n_runs, gram, run_edge, run_ekey, run_eends);
-        hipLaunchKernelGGL(k_gram_join, dim3(grid_for(nw)), b, 0, s, nw, run_edge, run_ekey, run_eends, c.seg_pos,
-                           gram);
+                       hipStream_t s) {
+    if (c.n_tiles > 0 && c.n_seg > 0) {
+        const dim3 g((unsigned)c.n_tiles), b(kBlock);
+        if (c.dtype == LM_CACHE_F32) hipLaunchKernelGGL((k_gram_tile<LM_CACHE_F32>), g, b, 0, s, c, gram);
+        else if (c.dtype == LM_CACHE_BF16) hipLaunchKernelGGL((k_gram_tile<LM_CACHE_BF16>), g, b, 0, s, c, gram);
+        else hipLaunchKernelGGL((k_gram_tile<LM_CACHE_F16>), g, b, 0, s, c, gram);
     }
     return gv_reduce<kGram>(c, gram, gvgram, edge, edge_key, s);
 }

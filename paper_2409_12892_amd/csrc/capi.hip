@@ -14,55 +14,85 @@ namespace lm {
 static thread_local std::string g_last_error;
 void set_error(const std::string& msg) { g_last_error = msg; }
 
-// Device memory: hipMalloc/hipFree unless the caller installed an
-// allocator (lm_set_allocator).  Allocations are stream-ordered on the
-// stream of the entry point that made them, which each entry point binds for
-// the duration of the call.
-static lm_allocator g_alloc{};
-static thread_local hipStream_t g_alloc_stream = nullptr;
-struct StreamScope {
-    hipStream_t prev;
-    explicit StreamScope(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
-    ~StreamScope() { g_alloc_stream = prev; }
-};
-
 namespace prof {
 // Event pairs recorded around kernel groups while profiling is enabled.
 struct Rec {
     const char* name;
     hipEvent_t a, b;
 };
-static bool g_enabled = false;
-static bool g_capturing = false;   // no event records while a stream is captured
-static std::vector<hipEvent_t> g_pool;
-static size_t g_used = 0;
-static std::vector<Rec> g_recs;
+struct State {
+    bool enabled = false;
+    bool capturing = false;   // no event records while a stream is captured
+    std::vector<hipEvent_t> pool;
+    size_t used = 0;
+    std::vector<Rec> recs;
+    hipEvent_t take() {
+        if (used < pool.size()) return pool[used++];
+        hipEvent_t e = nullptr;
+        if (hipEventCreate(&e) != hipSuccess) return nullptr;
+        pool.push_back(e);
+        ++used;
+        return e;
+    }
+};
+}  // namespace prof
+}  // namespace lm
 
-static hipEvent_t take() {
-    if (g_used < g_pool.size()) return g_pool[g_used++];
-    hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
-    g_pool.push_back(e);
-    ++g_used;
-    return e;
-}
+// A library context: the allocator of the device memory allocated on its
+// behalf, the launch mode of PCG and the profiling records.  Caches belong
+// to the context they were built with.
+struct lm_ctx {
+    lm_allocator al{};
+    int pcg_graph = 2;       // 0 eager, 1 graph replay, 2 graph replay for batches
+    lm::prof::State prof;
+    int64_t n_caches = 0;    // live caches (and workspaces) bound to the context
+    // partial sums of lm_vec_dot (grown on demand, kept until lm_ctx_destroy)
+    void* part = nullptr;
+    size_t part_cap = 0;
+    lm_allocator part_al{};
+    hipStream_t part_stream = nullptr;
+};
 
+namespace lm {
+
+// The process-wide default context (lm_options.ctx == NULL), and the
+// context and stream of the entry point running on this thread: device
+// memory is allocated through the context's allocator, stream-ordered on
+// the entry point's stream.
+static lm_ctx g_default_ctx;
+static thread_local lm_ctx* g_ctx = &g_default_ctx;
+static thread_local hipStream_t g_alloc_stream = nullptr;
+struct StreamScope {
+    hipStream_t prev;
+    lm_ctx* prevc;
+    explicit StreamScope(hipStream_t s, lm_ctx* c = nullptr) : prev(g_alloc_stream), prevc(g_ctx) {
+        g_alloc_stream = s;
+        if (c) g_ctx = c;
+    }
+    ~StreamScope() {
+        g_alloc_stream = prev;
+        g_ctx = prevc;
+    }
+};
+
+namespace prof {
 struct Scope {
     const char* name;
     hipStream_t s;
     hipEvent_t a = nullptr;
-    Scope(const char* n, hipStream_t st) : name(n), s(st) {
-        if (g_enabled && !g_capturing) {
-            a = take();
+    State& st;
+    Scope(const char* n, hipStream_t stream) : name(n), s(stream), st(g_ctx->prof) {
+        if (st.enabled && !st.capturing) {
+            a = st.take();
             if (a) (void)hipEventRecord(a, s);
         }
     }
     ~Scope() {
-        if (g_enabled && !g_capturing && a) {
-            hipEvent_t b = take();
+        if (st.enabled && !st.capturing && a) {
+            hipEvent_t b = st.take();
             if (b) {
                 (void)hipEventRecord(b, s);
-                g_recs.push_back({name, a, b});
+                st.recs.push_back({name, a, b});
             }
         }
     }
@@ -85,7 +115,7 @@ struct DevBuf {
         if (bytes <= cap && p) return hipSuccess;
         release();
         const size_t want = bytes + bytes / 16 + 256;
-        const lm_allocator g = lm::g_alloc;
+        const lm_allocator g = lm::g_ctx->al;
         const hipStream_t s = lm::g_alloc_stream;
         if (g.alloc) {
             p = g.alloc(g.user, want, (void*)s);
@@ -127,6 +157,7 @@ inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
 using lm::DevBuf;
 
 struct lm_cache {
+    lm_ctx* ctx = nullptr;       // the context of its last build (NULL before)
     int64_t N = 0;
     int P = 0, deg = 0, V = 0, TW = 16, TH = 16, dtype = LM_CACHE_F32;
     int64_t n_tiles = 0, n_pix = 0, n_keys = 0, n_pairs = 0, n_slots = 0, n_seg = 0, n_gv = 0;
@@ -142,10 +173,9 @@ struct lm_cache {
     DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
     DevBuf tile_real, tile_real_off, run_seg;
     DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs, seg_pos, list_gv;
-    DevBuf pT, pD, ppix, seg_gv, seg_loc, seg_f;
+    DevBuf pT, pD, ppix, seg_gv, tile_blk, seg_f;
     DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
-    DevBuf gram_redge, gram_rkey, gram_rends;
     DevBuf wres, obj_e, obj_part;
     DevBuf bj_L, bj_count;
     bool weighted = false;       // wres holds residual weights for the products
@@ -170,7 +200,7 @@ struct lm_cache {
         c.pT = pT.p; c.pD = pD.p; c.ppix = ppix.as<uint8_t>();
         c.n_pairs = n_slots; c.pair_stride = pair_stride;
         c.run_seg = run_seg.as<uint32_t>();
-        c.seg_gv = seg_gv.as<uint32_t>(); c.seg_loc = seg_loc.as<uint32_t>(); c.seg_f = seg_f.as<float>();
+        c.seg_gv = seg_gv.as<uint32_t>(); c.tile_blk = tile_blk.as<uint32_t>(); c.seg_f = seg_f.as<float>();
         c.seg_stride = seg_stride;
         c.gv_rec = gv_rec.as<uint32_t>(); c.gv_first = gv_first.as<uint32_t>();
         c.gv_seg_off = gv_seg_off.as<uint32_t>(); c.gv_segs = gv_segs.as<uint32_t>();
@@ -201,8 +231,8 @@ struct lm_cache {
                                &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
                                &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
-                               &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                               &ppix, &seg_gv, &tile_blk, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
+                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &wres, &obj_e, &obj_part, &bj_L, &bj_count,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
@@ -243,8 +273,8 @@ struct lm_cache {
                          &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
                                &run_seg, &gv_cnt, &gv_flag,
                          &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
-                         &ppix, &seg_gv, &seg_loc, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &gvchain, &gram_redge, &gram_rkey, &gram_rends, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
+                         &ppix, &seg_gv, &tile_blk, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
+                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &wres, &obj_e, &obj_part, &bj_L, &bj_count,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
@@ -412,6 +442,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->resid.ensure(sizeof(float) * 3 * c->n_pix));
     LM_HIP(c->fsq_part.ensure(sizeof(double) * c->n_tiles));
     LM_HIP(c->tile_pairs.ensure(sizeof(uint32_t) * c->n_tiles));
+    LM_HIP(c->tile_blk.ensure(sizeof(uint32_t) * lm::kTileBlocks * std::max<int64_t>(c->n_tiles, 1)));
     LM_HIP(c->tile_segs.ensure(sizeof(uint32_t) * c->n_tiles));
     LM_HIP(c->tile_real.ensure(sizeof(uint32_t) * c->n_tiles));
     LM_HIP(c->gv_cnt.ensure(sizeof(uint32_t) * (R + 1)));
@@ -430,6 +461,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     ra.resid = c->resid.as<float>();
     ra.fsq_part = c->fsq_part.as<double>();
     ra.tile_pairs = c->tile_pairs.as<uint32_t>();
+    ra.tile_blk = c->tile_blk.as<uint32_t>();
     ra.tile_segs = c->tile_segs.as<uint32_t>();
     ra.tile_real = c->tile_real.as<uint32_t>();
     ra.gv_cnt = c->gv_cnt.as<uint32_t>();
@@ -502,7 +534,6 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     }
     LM_HIP(c->run_seg.ensure(sizeof(uint32_t) * (c->pair_stride / 8)));
     LM_HIP(c->seg_gv.ensure(sizeof(uint32_t) * nseg_a));
-    LM_HIP(c->seg_loc.ensure(sizeof(uint32_t) * nseg_a));
     LM_HIP(c->seg_f.ensure(sizeof(float) * 6 * c->seg_stride));
     RasterArgs ra{};
     ra.cams = c->cams.as<CamDev>();
@@ -525,7 +556,7 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.pair_stride = c->pair_stride;
     ra.ppix = c->ppix.as<uint8_t>();
     ra.seg_gv = c->seg_gv.as<uint32_t>();
-    ra.seg_loc = c->seg_loc.as<uint32_t>();
+    ra.tile_blk = c->tile_blk.as<uint32_t>();
     ra.seg_f = c->seg_f.as<float>();
     ra.seg_stride = c->seg_stride;
     ra.run_seg = c->run_seg.as<uint32_t>();
@@ -598,10 +629,6 @@ lm_status apply_JtJ_internal(lm_cache* c, const float* p, float lambda, const fl
     return apply_JtJ_batch(B, s);
 }
 
-// 0: iterations launched one by one; 1: captured once and replayed as a
-// graph; 2 (default): graph replay when a call solves more than one subset
-int g_pcg_graph = 2;
-
 // Non-blocking stream (default priority) that the iteration is captured
 // into; the graph itself is launched on the caller's stream.
 hipError_t capture_stream(hipStream_t* out) {
@@ -668,15 +695,90 @@ lm_status run_objective(lm_cache* ws, const float* a, const float* t, bool add_t
     return LM_OK;
 }
 
+// Binds a handle to the context of the running entry point; the context
+// counts its handles so that it is not destroyed under them.
+void bind_ctx(lm_cache* c) {
+    lm_ctx* x = lm::g_ctx;
+    if (c->ctx == x) return;
+    if (c->ctx) --c->ctx->n_caches;
+    c->ctx = x;
+    ++x->n_caches;
+}
+
+void free_handle(lm_cache* c) {
+    if (c->ctx) --c->ctx->n_caches;
+    c->release_all();
+    delete c;
+}
+
 }  // namespace
 
 extern "C" {
 
 const char* lm_last_error(void) { return lm::g_last_error.c_str(); }
 
+lm_status lm_ctx_create(const lm_allocator* allocator, lm_ctx** out) {
+    LM_CHECK(out, LM_ERR_INVALID_ARG, "lm_ctx_create: out is NULL");
+    LM_CHECK(!allocator || (allocator->alloc && allocator->free), LM_ERR_INVALID_ARG,
+             "lm_ctx_create: alloc and free are both required");
+    lm_ctx* x = new (std::nothrow) lm_ctx();
+    LM_CHECK(x, LM_ERR_HIP, "out of host memory");
+    if (allocator) x->al = *allocator;
+    *out = x;
+    return LM_OK;
+}
+
+lm_status lm_ctx_destroy(lm_ctx* ctx) {
+    if (!ctx) return LM_OK;
+    LM_CHECK(ctx != &lm::g_default_ctx, LM_ERR_INVALID_ARG, "lm_ctx_destroy: the default context");
+    LM_CHECK(ctx->n_caches == 0, LM_ERR_INVALID_ARG, "lm_ctx_destroy: caches of the context are still alive");
+    for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    if (ctx->part) {
+        (void)hipDeviceSynchronize();
+        if (ctx->part_al.alloc) ctx->part_al.free(ctx->part_al.user, ctx->part, (void*)ctx->part_stream);
+        else (void)hipFree(ctx->part);
+    }
+    delete ctx;
+    return LM_OK;
+}
+
+lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream) {
+    lm_ctx* x = ctx ? ctx : &lm::g_default_ctx;
+    lm::StreamScope lm_stream_scope_(S(stream), x);
+    LM_CHECK(a && b && out && n >= 0, LM_ERR_INVALID_ARG, "lm_vec_dot: bad argument");
+    hipStream_t s = S(stream);
+    const size_t need = sizeof(double) * (size_t)lm::dot_partial_count(n);
+    if (x->part_cap < need) {
+        if (x->part) {
+            LM_HIP(hipStreamSynchronize(s));
+            if (x->part_al.alloc) x->part_al.free(x->part_al.user, x->part, (void*)x->part_stream);
+            else LM_HIP(hipFree(x->part));
+            x->part = nullptr;
+            x->part_cap = 0;
+        }
+        if (x->al.alloc) {
+            x->part = x->al.alloc(x->al.user, need, (void*)s);
+            LM_CHECK(x->part, LM_ERR_HIP, "lm_vec_dot: allocation failed");
+        } else {
+            LM_HIP(hipMalloc(&x->part, need));
+        }
+        x->part_cap = need;
+        x->part_al = x->al;
+        x->part_stream = s;
+    }
+    LM_HIP(lm::launch_dot(a, b, n, (double*)x->part, out, s));
+    return LM_OK;
+}
+
+lm_status lm_vec_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, void* stream) {
+    LM_CHECK(x && d && out && n >= 0, LM_ERR_INVALID_ARG, "lm_vec_axpy: bad argument");
+    LM_HIP(lm::launch_axpy(x, d, gamma, n, out, S(stream)));
+    return LM_OK;
+}
+
 lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
                          const lm_options* opts, void* stream, lm_cache** inout, float* b, double* F_sqnorm) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), opts ? opts->ctx : nullptr);
     LM_CHECK(inout, LM_ERR_INVALID_ARG, "lm_build_cache: inout is NULL");
     LM_CHECK(target, LM_ERR_INVALID_ARG, "lm_build_cache: target is NULL");
     lm::set_error("");
@@ -687,6 +789,7 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         LM_CHECK(c, LM_ERR_HIP, "out of host memory");
         created = true;
     }
+    bind_ctx(c);
     hipStream_t s = S(stream);
     // a compact build with a scratch handle borrows its build-only buffers
     lm_cache* scratch = nullptr;
@@ -694,11 +797,12 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         if (!*opts->scratch) {
             *opts->scratch = new (std::nothrow) lm_cache();
             if (!*opts->scratch) {
-                if (created) delete c;
+                if (created) free_handle(c);
                 LM_CHECK(false, LM_ERR_HIP, "out of host memory");
             }
         }
         scratch = *opts->scratch;
+        bind_ctx(scratch);
         LM_CHECK(scratch != c, LM_ERR_INVALID_ARG, "lm_build_cache: the scratch handle is the cache itself");
         c->swap_build_buffers(*scratch);
     }
@@ -727,10 +831,7 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         }
     }
     if (st != LM_OK) {
-        if (created) {
-            c->release_all();
-            delete c;
-        }
+        if (created) free_handle(c);
         return st;
     }
     *inout = c;
@@ -740,8 +841,7 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
 lm_status lm_cache_destroy(lm_cache* cache) {
     if (!cache) return LM_OK;
     (void)hipDeviceSynchronize();
-    cache->release_all();
-    delete cache;
+    free_handle(cache);
     return LM_OK;
 }
 
@@ -780,13 +880,8 @@ static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
     LM_HIP(cm->gvgram.ensure(sizeof(float) * kG * std::max<int64_t>(cm->n_gv, 1)));
     LM_HIP(cm->edge_g.ensure(sizeof(float) * 2 * kG * nwav));
     LM_HIP(cm->ekey_g.ensure(sizeof(uint32_t) * nwav));
-    const int64_t nrw = std::max<int64_t>(lm::gram_run_waves(cm->n_slots), 1);
-    LM_HIP(cm->gram_redge.ensure(sizeof(float) * 2 * kG * nrw));
-    LM_HIP(cm->gram_rkey.ensure(sizeof(uint32_t) * 2 * nrw));
-    LM_HIP(cm->gram_rends.ensure(sizeof(uint32_t) * nrw));
     LM_HIP(lm::launch_gram(cm->view(), cm->gram.as<float>(), cm->gvgram.as<float>(), cm->edge_g.as<float>(),
-                           cm->ekey_g.as<uint32_t>(), cm->gram_redge.as<float>(), cm->gram_rkey.as<uint32_t>(),
-                           cm->gram_rends.as<uint32_t>(), s));
+                           cm->ekey_g.as<uint32_t>(), s));
     cm->gram_valid = true;
     return LM_OK;
 }
@@ -825,7 +920,7 @@ static lm::BlockPrecond block_precond_of(const lm_cache* c) {
 }
 
 lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && M, LM_ERR_INVALID_ARG, "lm_jacobi_diag: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -837,7 +932,7 @@ lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
 }
 
 lm_status lm_pair_coverage(const lm_cache* c, float* coverage, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && coverage, LM_ERR_INVALID_ARG, "lm_pair_coverage: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -848,7 +943,7 @@ lm_status lm_pair_coverage(const lm_cache* c, float* coverage, void* stream) {
 }
 
 lm_status lm_block_jacobi(const lm_cache* c, const int64_t* gaussians, int64_t n, float* blocks, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && (n == 0 || (gaussians && blocks)) && n >= 0, LM_ERR_INVALID_ARG, "lm_block_jacobi: bad argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -862,7 +957,7 @@ lm_status lm_block_jacobi(const lm_cache* c, const int64_t* gaussians, int64_t n
 
 lm_status lm_precond_targets(const lm_cache* c, float lambda, float diag_floor, float shrink, float* t, float* mask,
                              void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && t && mask, LM_ERR_INVALID_ARG, "lm_precond_targets: NULL argument");
     LM_CHECK(lambda >= 0.0f && diag_floor >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
     LM_CHECK(shrink >= 0.0f && shrink <= 1.0f, LM_ERR_INVALID_ARG, "shrink must be in [0, 1]");
@@ -881,7 +976,7 @@ lm_status lm_precond_targets(const lm_cache* c, float lambda, float diag_floor, 
 }
 
 lm_status lm_precond_features(const lm_cache* c, const float* x, const float* M, float* feat, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && x && M && feat, LM_ERR_INVALID_ARG, "lm_precond_features: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -899,7 +994,7 @@ lm_status lm_precond_features(const lm_cache* c, const float* x, const float* M,
 
 lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const float* M, float* g,
                        double* Jp_sqnorm, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && p && g, LM_ERR_INVALID_ARG, "lm_apply_JtJ: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -910,7 +1005,7 @@ lm_status lm_apply_JtJ(const lm_cache* c, const float* p, float lambda, const fl
 }
 
 lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && p && u, LM_ERR_INVALID_ARG, "lm_apply_J: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -923,7 +1018,7 @@ lm_status lm_apply_J(const lm_cache* c, const float* p, float* u, void* stream) 
 }
 
 lm_status lm_jp_sqnorm(const lm_cache* c, const float* p, double* out, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && p && out, LM_ERR_INVALID_ARG, "lm_jp_sqnorm: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     lm_cache* cm = const_cast<lm_cache*>(c);
@@ -937,7 +1032,7 @@ lm_status lm_jp_sqnorm(const lm_cache* c, const float* p, double* out, void* str
 }
 
 lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && u && g, LM_ERR_INVALID_ARG, "lm_apply_JT: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     return apply_JT_internal(c, u, 1.0f, g, S(stream));
@@ -1020,7 +1115,8 @@ static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const floa
         }
         return LM_OK;
     };
-    const bool use_graph = n_iters >= 2 && (g_pcg_graph == 1 || (g_pcg_graph == 2 && n_b > 1));
+    const int mode = lm::g_ctx->pcg_graph;   // 0 eager, 1 graph replay, 2 graph replay for batches
+    const bool use_graph = n_iters >= 2 && (mode == 1 || (mode == 2 && n_b > 1));
     if (use_graph) {
         // the iteration is captured once (nothing runs while capturing) and
         // replayed on the caller's stream: no host launch work per iteration
@@ -1029,9 +1125,9 @@ static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const floa
         hipGraph_t graph = nullptr;
         hipGraphExec_t exec = nullptr;
         LM_HIP(hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal));
-        lm::prof::g_capturing = true;
+        lm::g_ctx->prof.capturing = true;
         lm_status st = body(cs);
-        lm::prof::g_capturing = false;
+        lm::g_ctx->prof.capturing = false;
         hipError_t ce = hipStreamEndCapture(cs, &graph);
         if (st != LM_OK) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -1074,7 +1170,7 @@ static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const floa
 lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
                        float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
                        const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), caches && n_b > 0 && caches[0] ? caches[0]->ctx : nullptr);
     return pcg_solve_impl(caches, n_b, b, M, lambda, diag_floor, n_iters, tol, tol_mode, precond_scale, delta, stats,
                           stream, false);
 }
@@ -1082,45 +1178,48 @@ lm_status lm_pcg_solve(lm_cache* const* caches, int32_t n_b, const float* const*
 lm_status lm_pcg_solve_block(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
                              float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
                              float* const* delta, lm_pcg_stats* stats, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), caches && n_b > 0 && caches[0] ? caches[0]->ctx : nullptr);
     return pcg_solve_impl(caches, n_b, b, M, lambda, diag_floor, n_iters, tol, tol_mode, nullptr, delta, stats,
                           stream, true);
 }
 
 lm_status lm_block_precond_apply(lm_cache* c, float lambda, float diag_floor, const float* r, float* z,
                                  int32_t* n_fallback, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && r && z, LM_ERR_INVALID_ARG, "lm_block_precond_apply: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     LM_CHECK(lambda >= 0.0f && diag_floor >= 0.0f, LM_ERR_INVALID_ARG, "lambda and diag_floor must be >= 0");
     lm_status st = ensure_block_precond(c, lambda, diag_floor, S(stream), n_fallback);
     if (st != LM_OK) return st;
     LM_HIP(lm::launch_bj_apply(block_precond_of(c), r, z, S(stream)));
-    return LM_OK;
+    return n_fallback && *n_fallback > 0 ? LM_WARN_FALLBACK_JACOBI : LM_OK;
 }
 
 lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
-                           int32_t cache_dtype, int32_t n_products, void* stream, int32_t* tile_w, int32_t* tile_h,
+                           const lm_options* opts, int32_t n_products, void* stream, int32_t* tile_w, int32_t* tile_h,
                            lm_tile_score* scores, int32_t max_scores, int32_t* n_scores) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), opts ? opts->ctx : nullptr);
+    const int32_t cache_dtype = opts ? opts->cache_dtype : LM_CACHE_F32;
     LM_CHECK(scene && cams && target && tile_w && tile_h, LM_ERR_INVALID_ARG, "lm_autotune_tile: NULL argument");
     LM_CHECK(n_products >= 0, LM_ERR_INVALID_ARG, "lm_autotune_tile: n_products must be >= 0");
     static const int32_t cand[][2] = {{16, 16}, {32, 8}, {8, 32}, {16, 8}, {8, 16}, {8, 8}};
     const int nc = (int)(sizeof(cand) / sizeof(cand[0]));
     hipStream_t s = S(stream);
     lm_cache* c = nullptr;
-    float* b = nullptr;
-    float* g = nullptr;
     hipEvent_t ev[4] = {};
     for (auto& e : ev) LM_HIP(hipEventCreate(&e));
     const int64_t n = scene->N * (int64_t)(11 + 3 * (scene->sh_degree + 1) * (scene->sh_degree + 1));
     lm_status st = LM_OK;
-    hipError_t he = hipMalloc(&b, sizeof(float) * std::max<int64_t>(n, 1));
-    if (he == hipSuccess) he = hipMalloc(&g, sizeof(float) * std::max<int64_t>(n, 1));
+    // two parameter vectors from the context's allocator
+    DevBuf bb, gb;
+    hipError_t he = bb.ensure(sizeof(float) * std::max<int64_t>(n, 1));
+    if (he == hipSuccess) he = gb.ensure(sizeof(float) * std::max<int64_t>(n, 1));
+    float* b = bb.as<float>();
+    float* g = gb.as<float>();
     double best = -1.0;
     int found = 0;
     for (int k = 0; k < nc && he == hipSuccess && st == LM_OK; ++k) {
-        lm_options o{cand[k][0], cand[k][1], cache_dtype, 0};
+        lm_options o{cand[k][0], cand[k][1], cache_dtype, 0, nullptr, lm::g_ctx};
         // an untimed build first: buffer growth (device allocation) is not
         // part of the shape's cost
         st = lm_build_cache(scene, cams, V, target, &o, stream, &c, b, nullptr);
@@ -1154,13 +1253,10 @@ lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t
         }
     }
     if (n_scores) *n_scores = std::min(found, max_scores);
-    if (c) {
-        (void)hipDeviceSynchronize();
-        c->release_all();
-        delete c;
-    }
-    if (b) (void)hipFree(b);
-    if (g) (void)hipFree(g);
+    (void)hipStreamSynchronize(s);
+    if (c) lm_cache_destroy(c);
+    bb.release();
+    gb.release();
     for (auto& e : ev)
         if (e) (void)hipEventDestroy(e);
     if (st != LM_OK) return st;
@@ -1171,30 +1267,30 @@ lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t
 
 lm_status lm_set_allocator(const lm_allocator* a) {
     LM_CHECK(!a || (a->alloc && a->free), LM_ERR_INVALID_ARG, "lm_set_allocator: alloc and free are both required");
-    lm::g_alloc = a ? *a : lm_allocator{};
+    lm::g_default_ctx.al = a ? *a : lm_allocator{};
     return LM_OK;
 }
 
-lm_status lm_pcg_use_graph(int32_t mode) {
+lm_status lm_pcg_use_graph(lm_ctx* ctx, int32_t mode) {
     LM_CHECK(mode >= 0 && mode <= 2, LM_ERR_INVALID_ARG, "lm_pcg_use_graph: mode must be 0, 1 or 2");
-    g_pcg_graph = mode;
+    (ctx ? ctx : &lm::g_default_ctx)->pcg_graph = mode;
     return LM_OK;
 }
 
-lm_status lm_profile_enable(int32_t on) {
-    lm::prof::g_enabled = on != 0;
+lm_status lm_profile_enable(lm_ctx* ctx, int32_t on) {
+    (ctx ? ctx : &lm::g_default_ctx)->prof.enabled = on != 0;
     return LM_OK;
 }
 
-int32_t lm_profile_read(lm_profile_entry* out, int32_t max_entries) {
-    using namespace lm::prof;
+int32_t lm_profile_read(lm_ctx* ctx, lm_profile_entry* out, int32_t max_entries) {
+    lm::prof::State& P = (ctx ? ctx : &lm::g_default_ctx)->prof;
     struct Agg {
         std::string name;
         int32_t n = 0;
         double ms = 0.0;
     };
     std::vector<Agg> agg;
-    for (const Rec& r : g_recs) {
+    for (const lm::prof::Rec& r : P.recs) {
         float ms = 0.0f;
         if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) ms = 0.0f;
         auto it = std::find_if(agg.begin(), agg.end(), [&](const Agg& x) { return x.name == r.name; });
@@ -1205,8 +1301,8 @@ int32_t lm_profile_read(lm_profile_entry* out, int32_t max_entries) {
         it->n += 1;
         it->ms += ms;
     }
-    g_recs.clear();
-    g_used = 0;
+    P.recs.clear();
+    P.used = 0;
     std::sort(agg.begin(), agg.end(), [](const Agg& a, const Agg& b) { return a.name < b.name; });
     int32_t k = 0;
     for (const Agg& a : agg) {
@@ -1238,8 +1334,17 @@ lm_status lm_mlp_forward(const float* w, const float* feat, int64_t n, int32_t p
     LM_CHECK(p_out >= 1 && p_out <= LM_MLP_MAX_OUT, LM_ERR_INVALID_ARG, "lm_mlp_forward: p_out must be 1..64");
     LM_CHECK(n < ((int64_t)1 << 40), LM_ERR_CAPACITY, "lm_mlp_forward: n too large");
     if (n_fallback) LM_HIP(hipMemsetAsync(n_fallback, 0, sizeof(uint32_t), S(stream)));
-    LM_PROF("mlp_forward", S(stream));
-    LM_HIP(lm::launch_mlp_forward(w, feat, n, p_out, s, scale, n_fallback, S(stream)));
+    {
+        LM_PROF("mlp_forward", S(stream));
+        LM_HIP(lm::launch_mlp_forward(w, feat, n, p_out, s, scale, n_fallback, S(stream)));
+    }
+    if (n_fallback) {
+        // the count decides the warning: read it back
+        uint32_t h = 0;
+        LM_HIP(hipMemcpyAsync(&h, n_fallback, sizeof(h), hipMemcpyDeviceToHost, S(stream)));
+        LM_HIP(hipStreamSynchronize(S(stream)));
+        if (h > 0) return LM_WARN_FALLBACK_JACOBI;
+    }
     return LM_OK;
 }
 
@@ -1272,7 +1377,7 @@ lm_status lm_mlp_train_step(float* w, float* adam_m, float* adam_v, int32_t step
 
 lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, const lm_options* opts, float* image,
                     void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), opts ? opts->ctx : nullptr);
     LM_CHECK(image, LM_ERR_INVALID_ARG, "lm_render: image is NULL");
     lm_cache* c = new (std::nothrow) lm_cache();
     LM_CHECK(c, LM_ERR_HIP, "out of host memory");
@@ -1294,7 +1399,7 @@ lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, con
 
 lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
                              const lm_options* opts, void* stream, lm_cache** workspace, double* F_sqnorm) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), opts ? opts->ctx : nullptr);
     LM_CHECK(workspace && target && F_sqnorm, LM_ERR_INVALID_ARG, "lm_residual_sqnorm: NULL argument");
     lm_cache* c = *workspace;
     bool created = false;
@@ -1303,6 +1408,7 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
         LM_CHECK(c, LM_ERR_HIP, "out of host memory");
         created = true;
     }
+    bind_ctx(c);
     hipStream_t s = S(stream);
     lm_status st = build_forward(c, scene, cams, V, target, opts, s);
     if (st == LM_OK) {
@@ -1314,8 +1420,7 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
     }
     c->built = false;
     if (st != LM_OK && created) {
-        c->release_all();
-        delete c;
+        free_handle(c);
         return st;
     }
     *workspace = c;
@@ -1323,7 +1428,7 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
 }
 
 lm_status lm_cache_view_sqnorm(const lm_cache* c, double* per_view, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && per_view, LM_ERR_INVALID_ARG, "lm_cache_view_sqnorm: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     LM_HIP(lm::view_sum_f64(c->cams.as<lm::CamDev>(), c->V, c->fsq_part.as<double>(), per_view, S(stream)));
@@ -1333,7 +1438,7 @@ lm_status lm_cache_view_sqnorm(const lm_cache* c, double* per_view, void* stream
 lm_status lm_objective_terms(const float* image, const float* target, const lm_camera* cams, int32_t V,
                              const lm_objective* obj, float* w, float* e, double* E, void* stream,
                              lm_cache** workspace) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), workspace && *workspace ? (*workspace)->ctx : nullptr);
     LM_CHECK(image && target && cams && E && workspace, LM_ERR_INVALID_ARG, "lm_objective_terms: NULL argument");
     LM_CHECK(V > 0 && V <= lm::kMaxViews, LM_ERR_INVALID_ARG, "lm_objective_terms: bad view count");
     lm_status st = objective_check(obj);
@@ -1351,10 +1456,10 @@ lm_status lm_objective_terms(const float* image, const float* target, const lm_c
         LM_CHECK(c, LM_ERR_HIP, "out of host memory");
         created = true;
     }
+    bind_ctx(c);
     st = run_objective(c, image, target, false, Ws, Hs, obj, w, e, E, nullptr, nullptr, S(stream));
     if (st != LM_OK && created) {
-        c->release_all();
-        delete c;
+        free_handle(c);
         return st;
     }
     *workspace = c;
@@ -1362,7 +1467,7 @@ lm_status lm_objective_terms(const float* image, const float* target, const lm_c
 }
 
 lm_status lm_set_residual_weights(lm_cache* c, const float* w, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c, LM_ERR_INVALID_ARG, "lm_set_residual_weights: NULL cache");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     c->gram_valid = false;
@@ -1379,7 +1484,7 @@ lm_status lm_set_residual_weights(lm_cache* c, const float* w, void* stream) {
 
 lm_status lm_cache_objective(lm_cache* c, const float* target, const lm_objective* obj, float* b, double* E,
                              void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && target, LM_ERR_INVALID_ARG, "lm_cache_objective: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     LM_CHECK(!c->compact, LM_ERR_NOT_BUILT,
@@ -1416,7 +1521,7 @@ lm_status lm_cache_objective(lm_cache* c, const float* target, const lm_objectiv
 lm_status lm_objective_value(const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
                              const lm_options* opts, const lm_objective* obj, void* stream, lm_cache** workspace,
                              double* E) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), opts ? opts->ctx : nullptr);
     LM_CHECK(workspace && target && E, LM_ERR_INVALID_ARG, "lm_objective_value: NULL argument");
     lm_status st = objective_check(obj);
     if (st != LM_OK) return st;
@@ -1427,6 +1532,7 @@ lm_status lm_objective_value(const lm_scene* scene, const lm_camera* cams, int32
         LM_CHECK(c, LM_ERR_HIP, "out of host memory");
         created = true;
     }
+    bind_ctx(c);
     hipStream_t s = S(stream);
     st = build_forward(c, scene, cams, V, target, opts, s);
     if (st == LM_OK) {
@@ -1448,8 +1554,7 @@ lm_status lm_objective_value(const lm_scene* scene, const lm_camera* cams, int32
     }
     c->built = false;
     if (st != LM_OK && created) {
-        c->release_all();
-        delete c;
+        free_handle(c);
         return st;
     }
     *workspace = c;
@@ -1538,7 +1643,7 @@ hipError_t live_slots(const lm_cache* c, std::vector<int64_t>& live, hipStream_t
 }  // namespace
 
 extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host_dst, int64_t bytes, void* stream) {
-    lm::StreamScope lm_stream_scope_(S(stream));
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
     LM_CHECK(c && host_dst, LM_ERR_INVALID_ARG, "lm_cache_export: NULL argument");
     LM_CHECK(c->built, LM_ERR_NOT_BUILT, "cache not built");
     const int64_t need = lm_cache_export_size(c, what);
@@ -1628,45 +1733,37 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
         }
         case LM_EXPORT_PAIR_PIX:
         case LM_EXPORT_PAIR_GAUSS: {
-            std::vector<uint64_t> tpo, tso;
-            std::vector<uint32_t> sloc, sgv, gvrec;
+            // every live slot in slot order: its tile from the tile offsets,
+            // its segment from the run table
+            std::vector<uint64_t> tpo;
+            std::vector<uint32_t> rseg, sgv, gvrec;
             std::vector<uint8_t> pix;
             LM_HIP(fetch(tpo, c->tile_pair_off.p, c->n_tiles + 1, s));
-            LM_HIP(fetch(tso, c->tile_seg_off.p, c->n_tiles + 1, s));
-            LM_HIP(fetch(sloc, c->seg_loc.p, c->n_seg, s));
+            LM_HIP(fetch(rseg, c->run_seg.p, c->n_slots / 8, s));
             LM_HIP(fetch(sgv, c->seg_gv.p, c->n_seg, s));
             LM_HIP(fetch(gvrec, c->gv_rec.p, c->n_gv, s));
             LM_HIP(fetch(pix, c->ppix.p, c->n_slots, s));
             std::vector<int64_t> live;
             LM_HIP(live_slots(c, live, s));
-            std::vector<uint8_t> is_live((size_t)c->n_slots, 0);
-            for (int64_t q : live) is_live[(size_t)q] = 1;
-            int32_t* o = (int32_t*)host_dst;
-            int64_t k = 0;
-            int64_t t = 0;
             std::vector<int32_t> tview;
             for (int v = 0; v < c->V; ++v) {
                 const lm::CamDev& cam = c->cams_h[v];
                 tview.insert(tview.end(), (size_t)cam.TX * cam.TY, v);
             }
-            for (t = 0; t < c->n_tiles; ++t) {
-                const lm::CamDev& cam = c->cams_h[tview[t]];
-                const int64_t lt = t - cam.tile_base;
-                const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
-                for (uint64_t sI = tso[t]; sI < tso[t + 1]; ++sI) {
-                    const uint64_t q0 = tpo[t] + sloc[sI];
-                    const uint64_t q1 = sI + 1 < tso[t + 1] ? tpo[t] + sloc[sI + 1] : tpo[t + 1];
-                    const int32_t gid = (int32_t)(gvrec[sgv[sI]] % (uint64_t)c->N);
-                    for (uint64_t q = q0; q < q1; ++q) {
-                        if (!is_live[q]) continue;
-                        if (what == LM_EXPORT_PAIR_GAUSS) {
-                            o[k++] = gid;
-                        } else {
-                            const int pl = pix[q];
-                            const int px = tx * c->TW + pl % c->TW, py = ty * c->TH + pl / c->TW;
-                            o[k++] = (int32_t)(cam.pix_base + (int64_t)py * cam.W + px);
-                        }
-                    }
+            int32_t* o = (int32_t*)host_dst;
+            int64_t t = 0;
+            for (size_t k = 0; k < live.size(); ++k) {
+                const int64_t q = live[k];
+                while (t + 1 < c->n_tiles && (int64_t)tpo[t + 1] <= q) ++t;
+                if (what == LM_EXPORT_PAIR_GAUSS) {
+                    o[k] = (int32_t)(gvrec[sgv[rseg[q / 8]]] % (uint64_t)c->N);
+                } else {
+                    const lm::CamDev& cam = c->cams_h[tview[t]];
+                    const int64_t lt = t - cam.tile_base;
+                    const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
+                    const int pl = pix[q];
+                    const int px = tx * c->TW + pl % c->TW, py = ty * c->TH + pl / c->TW;
+                    o[k] = (int32_t)(cam.pix_base + (int64_t)py * cam.W + px);
                 }
             }
             return LM_OK;

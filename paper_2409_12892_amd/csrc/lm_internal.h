@@ -13,6 +13,8 @@ namespace lm {
 constexpr int kBlock = 256;        // threads per workgroup (4 wave64)
 constexpr int kWave = 64;
 constexpr int kMaxTilePix = 256;   // pixels per tile (pixel-in-tile index is one byte)
+constexpr int kTileBlocks = 4;     // pixel blocks per tile (the pixels of one raster wave each)
+constexpr int kBlockPix = 64;      // pixels per block
 constexpr int kMaxViews = 4096;
 
 // Blending constants (paper section 3.1 defers them to the original 3DGS
@@ -57,7 +59,7 @@ struct CacheView {
     int64_t n_pairs;             // pair slots including the zero padding of each segment to 8
     int64_t pair_stride;         // plane stride of pT/pD/ppix (>= n_pairs + 8, multiple of 8)
     const uint32_t* seg_gv;      // dev [n_seg] active (Gaussian, view) index
-    const uint32_t* seg_loc;     // dev [n_seg] first pair, relative to the tile
+    const uint32_t* tile_blk;    // dev [n_tiles][4] padded pairs of each pixel block (blocks in order)
     const float* seg_f;          // dev [6][seg_stride]: mean-in-tile x, y, A, B, C, opacity
     int64_t seg_stride;
     const uint32_t* run_seg;     // dev [pair_stride / 8]: segment of each aligned 8-pair run
@@ -200,6 +202,7 @@ struct RasterArgs {
     float* resid;              // image layout
     double* fsq_part;          // [n_tiles]
     uint32_t* tile_pairs;      // [n_tiles] padded pair count
+    uint32_t* tile_blk;        // [n_tiles][4] padded pair count per pixel block (count: out, fill: in)
     uint32_t* tile_segs;       // [n_tiles]
     uint32_t* tile_real;       // [n_tiles] real pair count
     uint32_t* gv_cnt;          // [N*V] segments per (g, v), index g*V + v
@@ -216,7 +219,6 @@ struct RasterArgs {
     int64_t pair_stride;
     uint8_t* ppix;
     uint32_t* seg_gv;
-    uint32_t* seg_loc;
     float* seg_f;              // [6][seg_stride]
     int64_t seg_stride;
     uint32_t* run_seg;         // [pair_stride / 8] segment of each aligned 8-pair run
@@ -299,10 +301,8 @@ hipError_t launch_chain(const ApplyBatch& B, hipStream_t s);
 unsigned chain_blocks(int64_t N);
 // Per-segment Gram values (43 floats) reduced per (Gaussian, view) into gvgram.
 constexpr int kGramValues = 43;
-// run_edge: 2 * kGramValues floats, run_ekey: 2 u32, run_eends: 1 u32 per gram_run_waves(n_pairs)
-int64_t gram_run_waves(int64_t n_pairs);
 hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
-                       float* run_edge, uint32_t* run_ekey, uint32_t* run_eends, hipStream_t s);
+                       hipStream_t s);
 hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s);
 hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* coverage, hipStream_t s);
 // out 0: dense blocks [n][P][P] of the selected Gaussians, or without a
@@ -373,5 +373,10 @@ hipError_t launch_bj_factor(const CacheView& c, const float* gvgram, float lam, 
 hipError_t launch_bj_apply(const BlockPrecond& bj, const float* r, float* z, hipStream_t s);
 hipError_t launch_combine(int n_b, const float* const* d, const float* const* m, int64_t n, float* out,
                           hipStream_t s);
+// a . b in float64 into out (dev); part holds dot_partial_count(n) doubles
+int64_t dot_partial_count(int64_t n);
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* part, double* out, hipStream_t s);
+// out = x + gamma d (float32, one rounding)
+hipError_t launch_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, hipStream_t s);
 
 }  // namespace lm

@@ -3,7 +3,7 @@
 // Section 3.1 (eq. sgd-loss, eq. gn-loss): the objective has, per pixel and
 // channel, the residuals r1 = sqrt(f1), f1 = lam1 |c - C|, and
 // r2 = sqrt(f2), f2 = lam2 (1 - SSIM(c, C)); E = sum f1 + f2.  Supplement
-// A.5 (eq. res-sq-root-weights, res-sq-root-weights-sum) splits every
+// A.4 (eq. res-sq-root-weights, res-sq-root-weights-sum) splits every
 // Jacobian row into dr/dc times the colour Jacobian, so the products need
 // two images per view:
 //   e = sum_t r_t dr_t/dc = sum_t f_t' / 2          (b = -J^T e)

@@ -261,9 +261,45 @@ unsigned vec_grid(int64_t n) {
     return (unsigned)(g < 1 ? 1 : g);
 }
 
+// float64 dot product of two float32 vectors: per-block partial sums over a
+// fixed grid, then one block sums them (fixed order, deterministic)
+__global__ void k_dot_part(int64_t n, const float* __restrict__ a, const float* __restrict__ b,
+                           double* __restrict__ part) {
+    double v[1] = {0.0};
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v[0] += (double)a[i] * (double)b[i];
+    block_partials<1>(v, part, 0);
+}
+
+__global__ void k_dot_sum(const double* __restrict__ part, int64_t nb, double* __restrict__ out) {
+    const double r = block_sum(part, nb);
+    if (threadIdx.x == 0) *out = r;
+}
+
+__global__ void k_axpy(int64_t n, const float* __restrict__ x, const float* __restrict__ d, float gamma,
+                       float* __restrict__ out) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        out[i] = fmaf(gamma, d[i], x[i]);
+}
+
 }  // namespace
 
 int64_t pcg_partial_count(int64_t n) { return vec_grid(n); }
+
+int64_t dot_partial_count(int64_t n) { return vec_grid(n); }
+
+hipError_t launch_dot(const float* a, const float* b, int64_t n, double* part, double* out, hipStream_t s) {
+    const unsigned nb = vec_grid(n);
+    hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(kBlock), 0, s, n, a, b, part);
+    hipLaunchKernelGGL(k_dot_sum, dim3(1), dim3(kBlock), 0, s, part, (int64_t)nb, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, hipStream_t s) {
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_axpy, dim3(vec_grid(n)), dim3(kBlock), 0, s, n, x, d, gamma, out);
+    return hipGetLastError();
+}
 
 hipError_t launch_bj_apply(const BlockPrecond& bj, const float* r, float* z, hipStream_t s) {
     return bj_solve(bj, r, z, nullptr, nullptr, nullptr, vec_grid(bj.N * bj.P), s);

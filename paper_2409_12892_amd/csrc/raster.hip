@@ -14,14 +14,21 @@
 // Two passes walk identically:
 //   count: per entry, contributing pixels per wave (packed 4 x u8); per pixel
 //          the rendered colour (float64), residual and contributor count;
-//          per tile the number of pairs and of active splats (segments).
-//   fill:  writes the cache in its final layout - per tile, active splats in
-//          depth order (segments), each segment's pairs in pixel order:
-//          T (with head/clamp flag bits), dC/dalpha (3 planes), pixel byte -
-//          plus the per-segment splat data, the (Gaussian,view) links and
-//          the run -> segment table.  Every
-//          segment starts on a multiple of 8 pairs (zero padding), so each
-//          aligned run of 8 pairs belongs to one segment.
+//          per tile the number of pairs (per pixel block, padded) and of
+//          active splats (segments).
+//   fill:  writes the cache in its final layout.  A tile's pixels form up
+//          to four blocks of 64 (the pixels of one wave: an 8x8 square when
+//          the tile is at least 8 pixels each way, else 64 consecutive
+//          pixels).  Per tile, block after block; within a block, the active
+//          splats in depth order, each with its pairs in that block (a
+//          piece) in lane order: T (with head/clamp flag bits), dC/dalpha
+//          (3 planes), pixel byte.  Every piece starts on a multiple of 8
+//          pairs (zero padding), so each aligned run of 8 pairs belongs to
+//          one segment (the splat's pieces in the tile) and one block; the
+//          run -> segment table names it.  A block's pairs are complete
+//          for its 64 pixels, so the product pass can finish u = J p of a
+//          block and run J^T on the same pairs while they are on chip.
+//          Per segment: the splat data and the (Gaussian, view) links.
 // dC_ch/dalpha = T c_ch - S_ch/(1 - alpha) with S_ch the colour blended by
 // later splats, S_ch = C_ch(final) - (colour blended up to and including
 // this splat), all in float64.
@@ -35,6 +42,7 @@ constexpr int NW = kBlock / kWave;
 
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
+__device__ __forceinline__ uint32_t pad8(uint32_t n) { return (n + 7u) & ~7u; }
 
 template <bool FILL, int DT>
 __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
@@ -42,12 +50,11 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     __shared__ double s_rec[10][kBlock];
     __shared__ uint32_t s_g[kBlock];
     __shared__ uint8_t s_wc[kBlock][NW];       // count pass: contributing pixels per wave
-    __shared__ uint32_t s_eoff[kBlock];        // fill pass: entry pair offset in tile
-    __shared__ uint32_t s_wpre[kBlock];        // fill pass: packed per-wave prefixes
-    __shared__ uint32_t s_run[3];              // running padded pairs, segments, real pairs
+    __shared__ uint32_t s_eoff[kBlock][NW];    // fill pass: tile offset of each entry's piece per block
+    __shared__ uint32_t s_run[3];              // running -, segments, real pairs
+    __shared__ uint32_t s_blk[NW];             // running padded pairs per block (count); block starts (fill)
     __shared__ double s_red[kBlock / kWave];
-    __shared__ uint32_t s_scan[NW];
-    __shared__ uint32_t s_real[NW];
+    __shared__ uint32_t s_scan4[NW][4];
 
     const int64_t t = blockIdx.x;
     const int v = a.tile_view[t];
@@ -83,12 +90,23 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         Ch2 = a.pixC[2 * a.n_pix + pg];
     }
     if (tid < 3) s_run[tid] = 0;
+    if (tid < NW) s_blk[tid] = 0;
     int64_t pair_base = 0, seg_base = 0, pair_end = 0, seg_end = 0;
+    uint32_t blk_end = 0;       // end of this wave's block in the tile (fill)
     if (FILL) {
         pair_base = a.tile_pair_off[t];
         seg_base = a.tile_seg_off[t];
         pair_end = a.tile_pair_off[t + 1];
         seg_end = a.tile_seg_off[t + 1];
+        for (int w = 0; w <= wid; ++w) blk_end += a.tile_blk[t * kTileBlocks + w];
+    }
+    __shared__ uint32_t s_bbase[NW];           // fill: first slot of each block in the tile
+    if (FILL && tid == 0) {
+        uint32_t acc = 0;
+        for (int w = 0; w < NW; ++w) {
+            s_bbase[w] = acc;
+            acc += a.tile_blk[t * kTileBlocks + w];
+        }
     }
     const int64_t ks = a.tile_start[t], ke = a.tile_start[t + 1];
     const double lmargin = 1e-9;
@@ -104,43 +122,61 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
         }
         if (FILL) {
-            // per-entry totals, block-wide exclusive scan of (pairs, active) and
-            // segment records for the active entries
-            uint32_t c = tid < nb ? a.entry_cnt[b0 + tid] : 0u;
-            uint32_t tot = (c & 0xFF) + ((c >> 8) & 0xFF) + ((c >> 16) & 0xFF) + (c >> 24);
-            const uint32_t padded = (tot + 7u) & ~7u;
-            uint32_t packed = (padded << 10) | (tot > 0 ? 1u : 0u);
-            // wave inclusive scan
-            uint32_t inc = packed;
+            // per entry and block the padded piece length; block-wide
+            // exclusive scans give each piece its offset in its block and each
+            // active entry its segment index
+            const uint32_t c = tid < nb ? a.entry_cnt[b0 + tid] : 0u;
+            uint32_t cw[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) cw[w] = (c >> (8 * w)) & 0xFFu;
+            const uint32_t tot = cw[0] + cw[1] + cw[2] + cw[3];
+            const uint32_t v01 = pad8(cw[0]) | (pad8(cw[1]) << 16);   // batch sums stay below 2^16
+            const uint32_t v23 = pad8(cw[2]) | (pad8(cw[3]) << 16);
+            const uint32_t vac = tot > 0 ? 1u : 0u;
+            uint32_t i01 = v01, i23 = v23, iac = vac;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
-                uint32_t o = __shfl_up(inc, off, kWave);
-                if (lane >= off) inc += o;
+                const uint32_t o01 = __shfl_up(i01, off, kWave), o23 = __shfl_up(i23, off, kWave);
+                const uint32_t oac = __shfl_up(iac, off, kWave);
+                if (lane >= off) {
+                    i01 += o01;
+                    i23 += o23;
+                    iac += oac;
+                }
             }
-            if (lane == kWave - 1) s_scan[wid] = inc;
+            if (lane == kWave - 1) {
+                s_scan4[wid][0] = i01;
+                s_scan4[wid][1] = i23;
+                s_scan4[wid][2] = iac;
+            }
             __syncthreads();
-            uint32_t wbase = 0, btot = 0;
+            uint32_t b01 = 0, b23 = 0, bac = 0, t01 = 0, t23 = 0, tac = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                if (w < wid) wbase += s_scan[w];
-                btot += s_scan[w];
+                if (w < wid) {
+                    b01 += s_scan4[w][0];
+                    b23 += s_scan4[w][1];
+                    bac += s_scan4[w][2];
+                }
+                t01 += s_scan4[w][0];
+                t23 += s_scan4[w][1];
+                tac += s_scan4[w][2];
             }
-            const uint32_t ex = wbase + inc - packed;
-            const uint32_t run_p = s_run[0], run_s = s_run[1];
-            const uint32_t eoff = run_p + (ex >> 10);
-            const uint32_t eseg = run_s + (ex & 0x3FF);
+            const uint32_t e01 = b01 + i01 - v01, e23 = b23 + i23 - v23;
+            const uint32_t ex[NW] = {e01 & 0xFFFFu, e01 >> 16, e23 & 0xFFFFu, e23 >> 16};
+            const uint32_t eseg = s_run[1] + bac + iac - vac;
+            uint32_t eoff[NW];
+#pragma unroll
+            for (int w = 0; w < NW; ++w) eoff[w] = s_bbase[w] + s_blk[w] + ex[w];
             if (tid < nb) {
-                s_eoff[tid] = eoff;
-                s_wpre[tid] = ((c & 0xFF) << 8) | ((((c & 0xFF) + ((c >> 8) & 0xFF))) << 16) |
-                              ((((c & 0xFF) + ((c >> 8) & 0xFF) + ((c >> 16) & 0xFF))) << 24);
-                // note: prefix of wave 0 is 0; the packed bytes hold waves 1..3 (each <= 192 fits a byte)
+#pragma unroll
+                for (int w = 0; w < NW; ++w) s_eoff[tid][w] = eoff[w];
                 if (tot > 0 && seg_base + eseg < seg_end) {
                     const int64_t s = seg_base + eseg;
                     const uint32_t gi = s_g[tid];
                     const int64_t gvkey = (int64_t)gi * a.V + v;
                     const uint32_t gv = (uint32_t)a.gv_idx[gvkey];
                     a.seg_gv[s] = gv;
-                    a.seg_loc[s] = eoff;
                     a.seg_f[0 * a.seg_stride + s] = (float)(s_rec[0][tid] - (double)(tx * a.TW));
                     a.seg_f[1 * a.seg_stride + s] = (float)(s_rec[1][tid] - (double)(ty * a.TH));
                     a.seg_f[2 * a.seg_stride + s] = (float)s_rec[2][tid];
@@ -149,28 +185,33 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     a.seg_f[5 * a.seg_stride + s] = (float)s_rec[5][tid];
                     const uint32_t slot = atomicAdd(&a.gv_cursor[gv], 1u);
                     if (a.gv_segoff[gvkey] + slot < a.gv_segoff[gvkey + 1]) a.gv_segs[a.gv_segoff[gvkey] + slot] = (uint32_t)s;
-                    // aligned runs of this segment -> its index
-                    const int64_t r0 = (pair_base + eoff) >> 3;
-                    const int64_t r1 = min((int64_t)(pair_base + eoff + padded), pair_end) >> 3;
-                    for (int64_t r = r0; r < r1; ++r) a.run_seg[r] = (uint32_t)s;
-                    // the segment's padding slots: a zero T word marks no pair
                     typename S::word* zT = (typename S::word*)a.pT;
                     typename S::word* zD = (typename S::word*)a.pD;
-                    for (uint32_t q = tot; q < padded; ++q) {
-                        const int64_t slot = pair_base + eoff + q;
-                        if (slot >= pair_end) break;
-                        zT[slot] = 0;
-                        zD[slot] = 0;
-                        zD[a.pair_stride + slot] = 0;
-                        zD[2 * a.pair_stride + slot] = 0;
-                        a.ppix[slot] = 0;
+#pragma unroll
+                    for (int w = 0; w < NW; ++w) {
+                        if (cw[w] == 0) continue;
+                        // the piece's aligned runs -> this segment; its padding
+                        // slots get a zero T word (no pair)
+                        const int64_t q0 = pair_base + eoff[w];
+                        const int64_t q1 = min(q0 + (int64_t)pad8(cw[w]), pair_end);
+                        for (int64_t r = q0 >> 3; r < (q1 >> 3); ++r) a.run_seg[r] = (uint32_t)s;
+                        for (int64_t q = q0 + cw[w]; q < q1; ++q) {
+                            zT[q] = 0;
+                            zD[q] = 0;
+                            zD[a.pair_stride + q] = 0;
+                            zD[2 * a.pair_stride + q] = 0;
+                            a.ppix[q] = 0;
+                        }
                     }
                 }
             }
             __syncthreads();
             if (tid == 0) {
-                s_run[0] = run_p + (btot >> 10);
-                s_run[1] = run_s + (btot & 0x3FF);
+                s_blk[0] += t01 & 0xFFFFu;
+                s_blk[1] += t01 >> 16;
+                s_blk[2] += t23 & 0xFFFFu;
+                s_blk[3] += t23 >> 16;
+                s_run[1] += tac;
             }
         }
         __syncthreads();
@@ -204,17 +245,16 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 acc2 += c2 * w;
                 if (FILL) {
                     const uint32_t rank = (uint32_t)__popcll(bal & lanemask_lt());
-                    const uint32_t wp = wid == 0 ? 0u : ((s_wpre[j] >> (8 * wid)) & 0xFFu);
-                    const uint32_t within = wp + rank;
-                    const int64_t slot = pair_base + s_eoff[j] + within;
-                    if (slot < pair_end) {   // always true when both passes agree
+                    const uint32_t within = s_eoff[j][wid] + rank;        // slot in the tile
+                    const int64_t slot = pair_base + within;
+                    if (within < blk_end) {   // always true when both passes agree
                         const double inv = 1.0 / (1.0 - alpha);
                         const float D0 = (float)(T * c0 - (Ch0 - acc0) * inv);
                         const float D1 = (float)(T * c1 - (Ch1 - acc1) * inv);
                         const float D2 = (float)(T * c2 - (Ch2 - acc2) * inv);
                         typename S::word* pT = (typename S::word*)a.pT;
                         typename S::word* pD = (typename S::word*)a.pD;
-                        pT[slot] = S::enc_T((float)T, within == 0, a_raw > kAlphaMax);
+                        pT[slot] = S::enc_T((float)T, rank == 0, a_raw > kAlphaMax);
                         pD[slot] = S::enc(D0);
                         pD[a.pair_stride + slot] = S::enc(D1);
                         pD[2 * a.pair_stride + slot] = S::enc(D2);
@@ -227,37 +267,41 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         }
         __syncthreads();
         if (!FILL) {
-            // per-entry counts, tile totals and the (Gaussian, view) segment counts
-            uint32_t tot = 0, packed = 0;
+            // per-entry counts, per-block padded totals, active entries and
+            // real pairs of the batch, and the (Gaussian, view) segment counts
+            uint32_t tot = 0, p01 = 0, p23 = 0;
             if (tid < nb) {
                 uint32_t c0 = s_wc[tid][0], c1 = s_wc[tid][1], c2 = s_wc[tid][2], c3 = s_wc[tid][3];
-                packed = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
+                a.entry_cnt[b0 + tid] = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
                 tot = c0 + c1 + c2 + c3;
-                a.entry_cnt[b0 + tid] = packed;
                 if (tot > 0) atomicAdd(&a.gv_cnt[(int64_t)s_g[tid] * a.V + v], 1u);
+                p01 = pad8(c0) | (pad8(c1) << 16);     // per wave at most 64 x 64 per half
+                p23 = pad8(c2) | (pad8(c3) << 16);
             }
-            // block reduction of (padded pairs, active entries) and of real pairs
-            uint32_t val = (((tot + 7u) & ~7u) << 10) | (tot > 0 ? 1u : 0u);
-            uint32_t real = tot;
+            uint32_t act = tot > 0 ? 1u : 0u, real = tot;
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) {
-                val += __shfl_xor(val, off, kWave);
+                p01 += __shfl_xor(p01, off, kWave);
+                p23 += __shfl_xor(p23, off, kWave);
+                act += __shfl_xor(act, off, kWave);
                 real += __shfl_xor(real, off, kWave);
             }
             if (lane == 0) {
-                s_scan[wid] = val;
-                s_real[wid] = real;
+                s_scan4[wid][0] = p01;
+                s_scan4[wid][1] = p23;
+                s_scan4[wid][2] = act;
+                s_scan4[wid][3] = real;
             }
             __syncthreads();
             if (tid == 0) {
-                uint32_t sum = 0, rsum = 0;
                 for (int w = 0; w < NW; ++w) {
-                    sum += s_scan[w];
-                    rsum += s_real[w];
+                    s_blk[0] += s_scan4[w][0] & 0xFFFFu;
+                    s_blk[1] += s_scan4[w][0] >> 16;
+                    s_blk[2] += s_scan4[w][1] & 0xFFFFu;
+                    s_blk[3] += s_scan4[w][1] >> 16;
+                    s_run[1] += s_scan4[w][2];
+                    s_run[2] += s_scan4[w][3];
                 }
-                s_run[0] += sum >> 10;
-                s_run[1] += sum & 0x3FF;
-                s_run[2] += rsum;
             }
             __syncthreads();
         }
@@ -288,7 +332,8 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             double s = 0.0;
             for (int w = 0; w < NW; ++w) s += s_red[w];
             a.fsq_part[t] = s;
-            a.tile_pairs[t] = s_run[0];
+            a.tile_pairs[t] = s_blk[0] + s_blk[1] + s_blk[2] + s_blk[3];
+            for (int w = 0; w < NW; ++w) a.tile_blk[t * kTileBlocks + w] = s_blk[w];
             a.tile_segs[t] = s_run[1];
             a.tile_real[t] = s_run[2];
         }

@@ -30,9 +30,10 @@ cache's residual weights and b come from lm_cache_objective after every
 build, every product is J^T W J, and the errors E compared by the line
 search and the trust-region ratio are the objective's values.
 
-Every product, render and reduction runs in the library; this module only
-sequences calls and does scalar bookkeeping (and the vector update
-x += gamma delta).
+Every product, render, reduction and vector update (d^T b through
+lm_vec_dot, x + gamma delta through lm_vec_axpy) runs in the library; this
+module only sequences calls and does the scalar bookkeeping of the line
+search and the trust-region rule.
 """
 from __future__ import annotations
 
@@ -134,7 +135,7 @@ class LMSolver:
         d = self.comb
         jd = B.lm_jp_sqnorm(self.cache, d)
         E0 = float(fsq.item())
-        dTb = float(torch.dot(d.reshape(-1).double(), b.reshape(-1).double()).item())
+        dTb = float(B.lm_vec_dot(d, b).item())
         Jd2 = float(jd.item())
         per_view = B.lm_cache_view_sqnorm(self.cache) if self.E_views is None else self.E_views
         E_ref = float(per_view[torch.as_tensor(self.ls_idx, device=per_view.device)].sum().item())
@@ -144,7 +145,7 @@ class LMSolver:
 
         def E(k):
             if k not in evals:
-                torch.add(self.x, d, alpha=gammas[k], out=self.x_try)
+                B.lm_vec_axpy(self.x, d, gammas[k], out=self.x_try)
                 evals[k] = self._E(self.x_try, self.ls_cams, self.ls_target)
             return evals[k]
 
@@ -158,7 +159,7 @@ class LMSolver:
         k = min(evals, key=lambda kk: (evals[kk], kk))
         self.k_prev = k
         g = gammas[k]
-        torch.add(self.x, d, alpha=g, out=self.x_try)
+        B.lm_vec_axpy(self.x, d, g, out=self.x_try)
         # the cache at the trial point gives ||F(x + g d)||^2 and serves the
         # next iteration if the step is accepted
         self._build(self.x_try)
@@ -173,6 +174,8 @@ class LMSolver:
         else:
             self.lam = self.lam * 2.0
         self.built_at_x = accepted
+        # for rho >= 1 the factor 1 - (2 rho - 1)^3 is <= 0: the clamp to
+        # [lam_min, lam_max] (the paper's constrained range) keeps lambda positive
         self.lam = float(min(max(self.lam, cfg.lam_min), cfg.lam_max))
         rec = dict(E0=E0, E1=E1, gamma=g, rho=rho, accepted=accepted, lam=lam_old, lam_next=self.lam,
                    pcg_iters=stats[0]["iters"], pcg_rel_res_sq=float(stats[0]["history"][-1]),

@@ -6,7 +6,7 @@ arithmetic (no projection, blending, Jacobians or solves), so both the FP64
 CPU oracle and the HIP path can consume exactly the same arrays.
 
 Parameter layout (per Gaussian, structure-of-arrays ``x[P][N]`` float32, the
-paper's per-attribute vector layout, supplement A.4):
+paper's per-attribute vector layout, supplement A.3):
 
     0..2    mean (world)
     3..5    log-scale
@@ -15,7 +15,7 @@ paper's per-attribute vector layout, supplement A.4):
     11..    SH coefficients, index 11 + 3*k + ch (k = SH basis index, ch = RGB)
 
 P = 11 + 3*(deg+1)**2, i.e. 14 at SH degree 0 and 59 at degree 3 (paper
-section 3.1 and supplement A.4 count 59 parameters per Gaussian).
+section 3.1 and supplement A.3 count 59 parameters per Gaussian).
 
 Cameras follow the OpenCV convention: camera x right, y down, z forward;
 ``R`` maps world to camera (row-major), ``t`` is the translation, pixel

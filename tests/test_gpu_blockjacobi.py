@@ -126,7 +126,7 @@ def test_block_jacobi_reaches_tolerance_in_fewer_iterations(prob, gpu, report):
 
 def test_block_precond_with_residual_weights(prob, gpu, report):
     """With residual weights on the cache the blocks are those of J^T W J
-    (supplement A.5): z = A^-1 r against the oracle's blocks of the
+    (supplement A.4): z = A^-1 r against the oracle's blocks of the
     row-scaled Jacobian."""
     B, cache, J = gpu["B"], gpu["cache"], prob["J"]
     rng = np.random.default_rng(61)

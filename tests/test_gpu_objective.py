@@ -1,4 +1,4 @@
-"""Parity of the paper's objective on the GPU (eq. gn-loss; supplement A.5)
+"""Parity of the paper's objective on the GPU (eq. gn-loss; supplement A.4)
 with the FP64 oracle, through the C ABI.
 
 * lm_objective_terms: w, e and E of seeded image pairs (ragged views,

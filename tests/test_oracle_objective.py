@@ -1,5 +1,5 @@
 """Pins of the oracle's square-root L1 / SSIM objective (eq. gn-loss,
-supplement A.5) and of its weighted products, against closed forms, an
+supplement A.4) and of its weighted products, against closed forms, an
 independent library routine, finite differences and brute force."""
 from __future__ import annotations
 
