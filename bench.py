@@ -146,12 +146,79 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, t
     return res
 
 
-def cpu_baseline(scene, cams, n_pairs_per_apply: int, tile: int = 16, crop: int = 64, reps: int = 3) -> dict:
+def cpu_model() -> str:
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_cores() -> int:
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def _oracle_view_worker(task):
+    """One view of an oracle workload in a child process: the explicit float64
+    Jacobian's build and its J^T J p (SciPy CSR, one thread)."""
+    name, v, reps = task
+    from oracle import jacobian
+    from paper_2409_12892_amd import scenegen as sg
+    d = sg.config_scene(name)
+    sc = d["scene"]
+    cams = d["cams"][0].subset([v])
+    t0 = time.perf_counter()
+    J = jacobian.Jacobian(sc.x, cams, sc.sh_degree)
+    t_build = time.perf_counter() - t0
+    p = np.random.default_rng(0).normal(size=J.P * J.N)
+    J.apply_JtJ(p)
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        J.apply_JtJ(p)
+    return t_build, (time.perf_counter() - t1) / reps, J.n_pairs
+
+
+def oracle_config_timing(name: str, reps: int = 3) -> dict:
+    """The oracle on a whole small workload (every view), on one core (views
+    one after another in this process) and on all cores (one view per child
+    process, the views at once).  J^T J p of the subset is the sum over views,
+    so the parallel apply time is the slowest view's."""
+    import multiprocessing as mp
+    from paper_2409_12892_amd import scenegen as sg
+    V = sg.CONFIGS[name]["subsets"][0][0]
+    t0 = time.perf_counter()
+    one = [_oracle_view_worker((name, v, reps)) for v in range(V)]
+    t_one = time.perf_counter() - t0
+    procs = min(V, cpu_cores())
+    t0 = time.perf_counter()
+    with mp.get_context("spawn").Pool(procs) as pool:
+        par = pool.map(_oracle_view_worker, [(name, v, reps) for v in range(V)])
+    t_par = time.perf_counter() - t0
+    apply_one = sum(r[1] for r in one)
+    apply_par = max(r[1] for r in par)
+    pairs = sum(r[2] for r in one)
+    return {"pairs": pairs, "one_core": {"build_s": round(sum(r[0] for r in one), 3),
+                                         "apply_ms": round(apply_one * 1e3, 2),
+                                         "applies_per_s": round(1.0 / apply_one, 3), "wall_s": round(t_one, 2)},
+            "all_cores": {"processes": procs, "build_s": round(max(r[0] for r in par), 3),
+                          "apply_ms": round(apply_par * 1e3, 2), "applies_per_s": round(1.0 / apply_par, 3),
+                          "wall_s": round(t_par, 2)}}
+
+
+def cpu_baseline(scene, cams, n_pairs_per_apply: int, tile: int = 16, crop: int = 64, reps: int = 3,
+                 configs=("tiny", "precision")) -> dict:
     """The FP64 oracle, as it stands, on a bounded sample of the same
     workload: a crop x crop pixel window at the centre of view 0 (all
     Gaussians whose tile rectangle touches it).  Times the oracle's explicit
     Jacobian build and its J^T J p (SciPy CSR, float64, one thread), and
-    scales the pair rate to applies/s of the full workload."""
+    scales the pair rate to applies/s of the full workload.  Beside it, the
+    oracle on the whole tiny and precision workloads, on one core and on all
+    cores (one view per process)."""
     from oracle import forward, jacobian
     cam = dict(cams.view(0))
     x0 = (cam["W"] // 2 - crop // 2) // tile * tile
@@ -172,13 +239,19 @@ def cpu_baseline(scene, cams, n_pairs_per_apply: int, tile: int = 16, crop: int 
     t_apply = (time.perf_counter() - t1) / reps
     pairs = J.n_pairs
     rate = pairs / t_apply
-    return dict(value=rate / n_pairs_per_apply, unit="applies/s", cores=1, kind="oracle",
-                sample=(f"view 0, {crop}x{crop} centre crop ({(crop // tile) ** 2} tiles), {len(sel)} Gaussians, "
-                        f"{pairs} pairs; J^T J p with the explicit float64 J (SciPy CSR, single thread) "
-                        f"= {t_apply * 1e3:.1f} ms, i.e. {rate / 1e6:.2f} M pairs/s, scaled to the "
-                        f"{n_pairs_per_apply} pairs of one full apply; oracle build of the sample "
-                        f"{t_build:.1f} s"),
-                pairs_per_s=rate, sample_build_s=t_build, sample_apply_ms=t_apply * 1e3)
+    out = dict(value=rate / n_pairs_per_apply, unit="applies/s", cores=1, kind="oracle",
+               sample=(f"view 0, {crop}x{crop} centre crop ({(crop // tile) ** 2} tiles), {len(sel)} Gaussians, "
+                       f"{pairs} pairs; J^T J p with the explicit float64 J (SciPy CSR, single thread) "
+                       f"= {t_apply * 1e3:.1f} ms, i.e. {rate / 1e6:.2f} M pairs/s, scaled to the "
+                       f"{n_pairs_per_apply} pairs of one full apply; oracle build of the sample "
+                       f"{t_build:.1f} s"),
+               pairs_per_s=rate, sample_build_s=t_build, sample_apply_ms=t_apply * 1e3,
+               cpu_model=cpu_model(), cores_available=cpu_cores())
+    out["configs"] = {}
+    for name in configs:
+        log(f"cpu baseline: oracle on the whole {name} workload")
+        out["configs"][name] = oracle_config_timing(name)
+    return out
 
 
 def bench_batching(args, B, sg, torch) -> dict:
