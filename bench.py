@@ -35,7 +35,12 @@ if ROOT not in sys.path:
 
 METRIC = "J^TJ·p applies/s + HBM GB/s; LM-iter ms, bf16/batched/learned vs plain"
 HBM_PEAK_GBPS = 8000.0
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "apply_tile_JtJ_paper_traffic.txt")
+
+
+def traffic_file(dtype: str) -> str:
+    """Committed rocprofv3 counter summary of the fused pass for one cache type."""
+    return os.path.join(ROOT, "profiles", f"apply_tile_JtJ_paper_{dtype}_traffic.txt")
+
 APPLY_SRC = os.path.join(ROOT, "paper_2409_12892_amd", "csrc", "apply.hip")
 
 
@@ -66,19 +71,20 @@ def apply_tile_alg_bytes(info: dict, weighted: bool = False) -> int:
                + (12 * info["n_pixels"] if weighted else 0))
 
 
-def read_traffic(alg_bytes: int, tile: str):
-    """HBM traffic per launch from the committed rocprofv3 counter summary, or
-    None when it is absent or was taken on a different kernel source or tile
-    shape."""
-    if not os.path.exists(TRAFFIC_FILE):
+def read_traffic(alg_bytes: int, tile: str, dtype: str):
+    """HBM traffic per launch from the committed rocprofv3 counter summary of
+    this cache type, or None when it is absent or was taken on a different
+    kernel source or tile shape."""
+    path = traffic_file(dtype)
+    if not os.path.exists(path):
         return None
     kv = {}
-    for line in open(TRAFFIC_FILE):
+    for line in open(path):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
     src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
-    if kv.get("apply_src_sha256") != src or kv.get("tile", tile) != tile:
+    if kv.get("apply_src_sha256") != src or kv.get("tile") != tile or kv.get("cache_dtype") != dtype:
         return None
     try:
         return int(float(kv["traffic_bytes_per_launch"]))
@@ -86,17 +92,18 @@ def read_traffic(alg_bytes: int, tile: str):
         return None
 
 
-COPY_BYTES = 256 * 1024 * 1024
+COPY_BYTES = 4 * 1024 * 1024 * 1024   # well beyond the 256 MB Infinity Cache
 
 
-def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, tile: str = "",
-                  last: int = 9) -> dict:
+def summarize_pmc(fetch_dir: str, write_dir: str, command: str, tile: str, dtype: str, last: int = 9) -> dict:
     """HBM traffic of the fused J^T J tile pass from two rocprofv3 --pmc runs
     of `bench.py --copy-calibration` (one with FETCH_SIZE, one with
     WRITE_SIZE).  Each counter is summed over its instances per dispatch and
-    averaged over the dispatches of the kernel; the plain 256 MiB device copy
-    of the same run gives the scale of each counter (true bytes / counted
-    bytes).  Writes the summary read by read_traffic()."""
+    averaged over the dispatches of the kernel.  The 4 GiB device copies of
+    the same run (16 times the Infinity Cache) give the scale of each counter
+    (true bytes / counted bytes); the 4 GiB reductions (a streaming read of
+    known size) cross-check the FETCH_SIZE scale.  Writes the summary that
+    read_traffic() reads for this cache type."""
     import csv
     import glob
 
@@ -121,25 +128,30 @@ def summarize_pmc(fetch_dir: str, write_dir: str, out_path: str, command: str, t
         # the timed step's products: the kernel's last `last` dispatches (the
         # autotuner's candidate shapes come before them)
         a, na = mean([v for (_, name), v in disp if "k_apply_tile<3," in name][-last:])
-        # the calibration copies are the run's last three device copies
+        # the calibration copies and reductions are the run's last three of each
         cp, nc = mean([v for (_, name), v in disp if "copyBuffer" in name][-3:])
+        rd, nr = mean([v for (_, name), v in disp if "reduce_kernel" in name][-3:])
         if a is None or cp is None:
             raise SystemExit(f"{ctr}: apply dispatches {na}, copy dispatches {nc} in {d}")
         scale = COPY_BYTES / (cp * 1024.0)
         res[tag] = dict(kib_per_launch=a, launches=na, copy_kib=cp, copy_launches=nc, scale=scale,
-                        bytes_per_launch=a * 1024.0 * scale)
+                        read_kib=rd, read_launches=nr, bytes_per_launch=a * 1024.0 * scale)
     total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
     src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
-    with open(out_path, "w") as f:
-        f.write("# HBM traffic of k_apply_tile<J^T J fused, float32 cache> at the paper workload\n")
+    gib = COPY_BYTES / 2**30
+    with open(traffic_file(dtype), "w") as f:
+        f.write(f"# HBM traffic of k_apply_tile<J^T J fused, {dtype} cache> at the paper workload, {tile} tiles\n")
         f.write(f"# command: {command}\n")
         for tag in ("fetch", "write"):
             r = res[tag]
             f.write(f"# {tag}: {r['kib_per_launch']:.1f} KiB counted per launch over {r['launches']} launches; "
-                    f"256 MiB copy counted {r['copy_kib']:.1f} KiB -> scale {r['scale']:.3f}\n")
+                    f"{gib:g} GiB copy counted {r['copy_kib']:.1f} KiB -> scale {r['scale']:.3f}")
+            if r["read_kib"] is not None:
+                f.write(f"; {gib:g} GiB streaming read (reduction) counted {r['read_kib']:.1f} KiB")
+            f.write("\n")
         f.write(f"apply_src_sha256={src}\n")
-        if tile:
-            f.write(f"tile={tile}\n")
+        f.write(f"tile={tile}\n")
+        f.write(f"cache_dtype={dtype}\n")
         f.write(f"fetch_bytes_per_launch={res['fetch']['bytes_per_launch']:.0f}\n")
         f.write(f"write_bytes_per_launch={res['write']['bytes_per_launch']:.0f}\n")
         f.write(f"traffic_bytes_per_launch={total:.0f}\n")
@@ -702,17 +714,19 @@ def main() -> int:
     ap.add_argument("--objective", default="l2", choices=["l2", "l1_ssim"],
                     help="least-squares RGB residuals (the configured workload) or the paper's square-root "
                          "L1 / SSIM residuals")
+    ap.add_argument("--thin", type=int, default=0,
+                    help="thinned cache: blend state of every K-th contributor per pixel (0: full cache)")
     ap.add_argument("--copy-calibration", action="store_true",
-                    help="after the timed steps, copy 256 MiB device to device three times (the "
-                         "reference kernel for rocprofv3 byte counters)")
+                    help="after the timed steps, copy 4 GiB device to device and sum 4 GiB three times "
+                         "each (the reference kernels for rocprofv3 byte counters)")
     ap.add_argument("--summarize-pmc", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="write the traffic summary from two rocprofv3 --pmc output folders and exit")
     ap.add_argument("--pmc-command", default="", help="command line recorded in the traffic summary")
     ap.add_argument("--pmc-tile", default="", help="tile shape of the counted runs, recorded in the summary")
     args = ap.parse_args()
     if args.summarize_pmc:
-        res = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], TRAFFIC_FILE, args.pmc_command,
-                            args.pmc_tile)
+        res = summarize_pmc(args.summarize_pmc[0], args.summarize_pmc[1], args.pmc_command, args.pmc_tile,
+                            args.cache_dtype)
         print(json.dumps(res))
         return 0
 
@@ -762,7 +776,7 @@ def main() -> int:
     tile_scores = None
     if args.tile == "auto":
         (tw, th), sc_ = B.lm_autotune_tile(x, scene.sh_degree, cams, target, cache_dtype=args.cache_dtype,
-                                          n_products=n_iters + 2)
+                                          n_products=n_iters + 2, thin_window=args.thin)
         tile_scores = [dict(tile=f"{c['tile'][0]}x{c['tile'][1]}", build_ms=round(c["build_ms"], 2),
                             apply_ms=round(c["apply_ms"], 3)) for c in sc_]
         log(f"autotuned tile {tw}x{th}: " + ", ".join(f"{c['tile']} {c['build_ms']:.0f}/{c['apply_ms']:.1f} ms"
@@ -773,7 +787,7 @@ def main() -> int:
     from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
     solver = LMSolver(x, scene.sh_degree, cams, target,
                       LMConfig(lam=lam, n_iters=n_iters, tile=(tw, th), cache_dtype=args.cache_dtype,
-                               objective=args.objective, precond=args.precond))
+                               objective=args.objective, precond=args.precond, thin_window=args.thin))
 
     def show(tag, rec):
         log(f"{tag}: E {rec['E0']:.4g} -> {rec['E1']:.4g} gamma {rec['gamma']:g} rho {rec['rho']:.3g} "
@@ -795,8 +809,11 @@ def main() -> int:
     if args.copy_calibration:
         src_buf = torch.empty(COPY_BYTES // 4, device=dev)
         dst_buf = torch.empty_like(src_buf)
+        src_buf.fill_(1.0)
         for _ in range(3):
             dst_buf.copy_(src_buf)
+        for _ in range(3):
+            dst_buf.sum()
         torch.cuda.synchronize()
         del src_buf, dst_buf
     info = solver.cache.info()
@@ -809,7 +826,7 @@ def main() -> int:
     alg = apply_tile_alg_bytes(info, weighted=args.objective != "l2")
     achieved = alg / (apply_ms * 1e-3) / 1e9
     # the counter summary covers the least-squares (unweighted) pass
-    traffic = read_traffic(alg, f"{tw}x{th}") if args.objective == "l2" else None
+    traffic = read_traffic(alg, f"{tw}x{th}", args.cache_dtype) if args.objective == "l2" else None
     full_apply_ms = sum(prof.get(k, (0, 0.0))[1] for k in ("tangent", "apply_tile_JtJ", "chain", "pcg_vector")) \
         / max(launches, 1)
     log(f"steps done: {ms_per_step:.1f} ms/step, apply tile pass {apply_ms:.3f} ms, {achieved:.0f} GB/s")

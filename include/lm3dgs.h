@@ -94,7 +94,19 @@ typedef struct lm_options {
                                   with lm_cache_destroy)                                 */
     lm_ctx* ctx;             /* context of the call and of the handles it builds; NULL:
                                 the process-wide default context                      */
+    int32_t thin_window;     /* 0: the full cache (T and dC/dalpha of every pair).  K in
+                                1..LM_THIN_WINDOW_MAX: a thinned cache (section 4.4,
+                                limitations: gradients kept only for every K-th splat along
+                                a ray, the alpha blending redone inside those windows); it
+                                keeps per 64-pixel block and splat a mask of the pixels it
+                                contributes to, per pixel the blend state in front of its
+                                contributors 0, K, 2K, ..., and no per-pair value; the
+                                products re-blend every pair in float32.  Needs
+                                LM_CACHE_F32 (else LM_ERR_UNSUPPORTED); the pair exports
+                                return LM_ERR_UNSUPPORTED                              */
+    int32_t reserved;
 } lm_options;
+#define LM_THIN_WINDOW_MAX 4096
 
 /* lm_options.flags: after a successful lm_build_cache, synchronise the stream
  * and free the buffers only the build uses (projection records, binning keys
@@ -157,6 +169,10 @@ typedef struct lm_cache_info {
     int64_t cache_bytes;     /* pair + segment arrays read by the products   */
     int64_t device_bytes;    /* all device memory held by the cache          */
     int32_t V, P, tile_w, tile_h, cache_dtype, sh_degree;
+    int32_t thin_window;     /* lm_options.thin_window of the build (0: full cache)  */
+    int32_t reserved;
+    int64_t n_pieces;        /* thinned cache: (splat, 64-pixel block) pieces         */
+    int64_t n_checkpoints;   /* thinned cache: stored blend states                    */
 } lm_cache_info;
 
 #define LM_PCG_MAX_HISTORY 257
@@ -327,13 +343,23 @@ lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t
  * context): 0 launches every kernel of every iteration from the host; 1
  * captures one iteration into a graph (on a library-owned stream) and
  * replays it on the caller's stream; 2 (default) uses the graph when a call
- * solves more than one subset.  Results are the same in every mode. */
+ * solves more than one subset; 3 runs all iterations of all subsets of a
+ * call in one persistent cooperative kernel (one workgroup per resident
+ * slot, grid-wide barriers between the phases of an iteration, the float64
+ * scalars formed identically by every workgroup), its launch captured into
+ * a graph once per context and kernel variant and replayed (issued directly
+ * where the runtime cannot capture a cooperative launch); the call
+ * synchronises the stream, and a barrier that does not complete within 10 s
+ * ends the kernel and the call returns LM_ERR_HIP.  lm_pcg_solve_block
+ * uses mode 2 when 3 is set.  Results agree between modes to float32
+ * rounding (modes 0-2 are bit-identical; mode 3 sums the p.g, r.z and r.r
+ * partials over its own grid). */
 lm_status lm_pcg_use_graph(lm_ctx* ctx, int32_t mode);
 
 /* Vector steps of the LM outer loop (section 3.2), so that no method
  * arithmetic runs outside the library.
  * lm_vec_dot: *out (dev double) = a^T b in float64 for float32 dev vectors
- *   a, b of n elements; the trust-region ratio's model decrease (eq.
+ *   a, b of n elements (NULL allowed when n = 0; then *out = 0); the trust-region ratio's model decrease (eq.
  *   tr-update) is 2 gamma delta^T b - gamma^2 ||J delta||^2 with b = -J^T F.
  *   Partial sums go to device memory of the context (NULL: default),
  *   allocated through its allocator on first use and kept until
@@ -343,6 +369,7 @@ lm_status lm_pcg_use_graph(lm_ctx* ctx, int32_t mode);
  *   3.2; out may alias x.  Allocates nothing. */
 lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream);
 lm_status lm_vec_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, void* stream);
+
 
 /* Weighted mean of subset directions (paper eq. combine-pcg):
  * out = sum_i M_i delta_i / sum_k M_k element-wise; 0 where sum_k M_k = 0.

@@ -73,7 +73,7 @@ class LmScene(ctypes.Structure):
 
 class LmOptions(ctypes.Structure):
     _fields_ = [("tile_w", c_int32), ("tile_h", c_int32), ("cache_dtype", c_int32), ("flags", c_int32),
-                ("scratch", c_void_p), ("ctx", c_void_p)]
+                ("scratch", c_void_p), ("ctx", c_void_p), ("thin_window", c_int32), ("reserved", c_int32)]
 
 
 class Ctx:
@@ -94,12 +94,14 @@ class Ctx:
 
 
 def _ctx_ptr(ctx):
-    return None if ctx is None else ctx.handle.value
+    # a c_void_p, not a Python int: ctypes passes a bare int as a 32-bit C int
+    return None if ctx is None else c_void_p(ctx.handle.value)
 
 
-def _opts(tile, cache_dtype=0, flags=0, ctx=None):
+def _opts(tile, cache_dtype=0, flags=0, ctx=None, thin_window=0):
     o = LmOptions(tile[0], tile[1], cache_dtype, flags)
     o.ctx = _ctx_ptr(ctx)
+    o.thin_window = int(thin_window)
     return o
 
 
@@ -108,7 +110,9 @@ class LmCacheInfo(ctypes.Structure):
                 ("n_gv", c_int64), ("n_pixels", c_int64), ("n_tiles", c_int64), ("n_pair_slots", c_int64),
                 ("cache_bytes", c_int64),
                 ("device_bytes", c_int64), ("V", c_int32), ("P", c_int32), ("tile_w", c_int32),
-                ("tile_h", c_int32), ("cache_dtype", c_int32), ("sh_degree", c_int32)]
+                ("tile_h", c_int32), ("cache_dtype", c_int32), ("sh_degree", c_int32),
+                ("thin_window", c_int32), ("reserved", c_int32), ("n_pieces", c_int64),
+                ("n_checkpoints", c_int64)]
 
 
 class LmTileScore(ctypes.Structure):
@@ -224,19 +228,21 @@ BUILD_COMPACT = 1
 
 def lm_build_cache(x, sh_degree: int, cams, target, *, tile=(16, 16), cache_dtype: str = "f32",
                    cache: Cache | None = None, want_b: bool = True, b=None, compact: bool = False,
-                   scratch: Cache | None = None, ctx: Ctx | None = None):
+                   scratch: Cache | None = None, ctx: Ctx | None = None, thin_window: int = 0):
     """Build the gradient cache of one subset.  Returns (cache, b, F_sqnorm)
     with b = -J^T F as a [P, N] tensor (written into `b` when given) and
     ||F||^2 as a 1-element float64 tensor (both None when want_b is False).
     With compact=True and a `scratch` Cache (possibly empty), the build's
-    transient buffers are kept in `scratch` for the next compact build."""
+    transient buffers are kept in `scratch` for the next compact build.
+    thin_window=K > 0 builds the thinned cache (blend state of every K-th
+    contributor per pixel; the products re-blend the pairs)."""
     import torch
     lib = load()
     x = _dev_f32(x, "x")
     target = _dev_f32(target, "target")
     P, N = x.shape
     scene = LmScene(N, sh_degree, 0, x.data_ptr())
-    opts = _opts(tile, CACHE_DTYPES[cache_dtype], BUILD_COMPACT if compact else 0, ctx)
+    opts = _opts(tile, CACHE_DTYPES[cache_dtype], BUILD_COMPACT if compact else 0, ctx, thin_window)
     sh = None
     if scratch is not None:
         if not compact:
@@ -484,7 +490,7 @@ def lm_cache_view_sqnorm(cache: Cache, out=None):
 
 
 def lm_autotune_tile(x, sh_degree: int, cams, target, *, cache_dtype: str = "f32", n_products: int = 10,
-                     ctx: Ctx | None = None):
+                     ctx: Ctx | None = None, thin_window: int = 0):
     """Measured tile shape for one subset: ((tile_w, tile_h), [per-candidate
     dicts with build_ms and apply_ms])."""
     x = _dev_f32(x, "x")
@@ -494,7 +500,7 @@ def lm_autotune_tile(x, sh_degree: int, cams, target, *, cache_dtype: str = "f32
     carr = camera_array(cams)
     tw, th, ns = c_int32(0), c_int32(0), c_int32(0)
     sc = (LmTileScore * 16)()
-    opts = _opts((0, 0), CACHE_DTYPES[cache_dtype], 0, ctx)
+    opts = _opts((0, 0), CACHE_DTYPES[cache_dtype], 0, ctx, thin_window)
     _check(load().lm_autotune_tile(byref(scene), carr, c_int32(len(carr)), _ptr(target), byref(opts),
                                    c_int32(n_products), _stream(), byref(tw), byref(th), sc, c_int32(16), byref(ns)),
            "lm_autotune_tile")

@@ -12,7 +12,9 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "liblm3dgs.so")
-SOURCES = ["scan.hip", "project_bin.hip", "raster.hip", "apply.hip", "pcg.hip", "mlp.hip", "objective.hip", "capi.hip"]
+SOURCES = ["scan.hip", "project_bin.hip", "raster.hip", "apply.hip", "thin.hip", "persist.hip", "pcg.hip", "mlp.hip",
+           "objective.hip",
+           "capi.hip"]
 ARCH = os.environ.get("LM3DGS_ARCH", "gfx950")
 
 # -packed-fp32-ops: no packed FP32 VALU instructions are generated.

@@ -43,7 +43,16 @@ struct State {
 // to the context they were built with.
 struct lm_ctx {
     lm_allocator al{};
-    int pcg_graph = 2;       // 0 eager, 1 graph replay, 2 graph replay for batches
+    int pcg_graph = 2;       // 0 eager, 1 graph replay, 2 graph replay for batches, 3 persistent kernel
+    // persistent-kernel PCG: device arguments, counters and partials (grown
+    // on demand, kept until lm_ctx_destroy) and the captured launch
+    void* persist_dev = nullptr;      // PersistArgs, then counters, then partials
+    size_t persist_cap = 0;
+    lm_allocator persist_al{};
+    hipStream_t persist_stream = nullptr;
+    hipGraphExec_t persist_exec = nullptr;
+    int persist_key[3] = {-1, -1, -1}; // (SH degree, tile variant, grid) of persist_exec
+    int persist_graph = -1;           // -1 untried, 0 capture unsupported, 1 captured launches
     lm::prof::State prof;
     int64_t n_caches = 0;    // live caches (and workspaces) bound to the context
     // partial sums of lm_vec_dot (grown on demand, kept until lm_ctx_destroy)
@@ -162,6 +171,8 @@ struct lm_cache {
     int P = 0, deg = 0, V = 0, TW = 16, TH = 16, dtype = LM_CACHE_F32;
     int64_t n_tiles = 0, n_pix = 0, n_keys = 0, n_pairs = 0, n_slots = 0, n_seg = 0, n_gv = 0;
     int64_t pair_stride = 8, seg_stride = 8, lin_stride = 8;
+    int thin_k = 0;                  // > 0: thinned cache (checkpoint every thin_k contributors)
+    int64_t n_pieces = 0, n_ck = 0;  // thinned cache: pieces and checkpoints
     bool vals_in_alt = false;
     bool built = false;
     std::vector<lm::CamDev> cams_h;
@@ -178,6 +189,7 @@ struct lm_cache {
     DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
     DevBuf wres, obj_e, obj_part;
     DevBuf bj_L, bj_count;
+    DevBuf tile_ck, tile_ck_off, pix_ck, ck, piece_seg, piece_mask, piece_cmask;
     bool weighted = false;       // wres holds residual weights for the products
     bool bj_valid = false;       // bj_L holds the block-Jacobi factors for (bj_lambda, bj_floor)
     float bj_lambda = 0.0f, bj_floor = 0.0f;
@@ -207,6 +219,13 @@ struct lm_cache {
         c.seg_pos = seg_pos.as<uint32_t>(); c.list_gv = list_gv.as<uint32_t>();
         c.lin = lin.as<float>(); c.lin_stride = lin_stride;
         c.wres = weighted ? wres.as<float>() : nullptr;
+        c.thin_k = thin_k;
+        c.piece_seg = piece_seg.as<uint32_t>();
+        c.piece_mask = piece_mask.as<uint64_t>();
+        c.piece_cmask = piece_cmask.as<uint64_t>();
+        c.tile_ck_off = tile_ck_off.as<int64_t>();
+        c.pix_ck = pix_ck.as<uint32_t>();
+        c.ck = ck.as<float4>();
         return c;
     }
 
@@ -234,6 +253,7 @@ struct lm_cache {
                                &ppix, &seg_gv, &tile_blk, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &wres, &obj_e, &obj_part, &bj_L, &bj_count,
+                               &tile_ck, &tile_ck_off, &pix_ck, &ck, &piece_seg, &piece_mask, &piece_cmask,
                                &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
         for (auto* b : all) s += b->cap;
@@ -241,13 +261,14 @@ struct lm_cache {
     }
 
     // buffers read only while building (see LM_BUILD_COMPACT)
-    static constexpr int kBuildBufs = 34;
+    static constexpr int kBuildBufs = 35;
     void build_buffers(DevBuf* (&out)[kBuildBufs]) {
         DevBuf* build[kBuildBufs] = {&x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &vals_alt,
                                      &sort_tmp, &scan_tmp, &rkeys, &rvals, &rkeys_alt, &rvals_alt, &cnt_sorted,
                                      &kept_blk, &kept_off, &kept_mask,
                                      &tile_start, &entry_cnt, &pixC, &ncontrib, &resid, &tile_pairs, &tile_segs,
-                                     &tile_real, &tile_real_off, &gv_cnt, &gv_flag, &gv_idx, &gv_segoff, &gv_cursor};
+                                     &tile_real, &tile_real_off, &gv_cnt, &gv_flag, &gv_idx, &gv_segoff, &gv_cursor,
+                                     &tile_ck};
         for (int i = 0; i < kBuildBufs; ++i) out[i] = build[i];
     }
     void release_build_buffers() {
@@ -276,6 +297,7 @@ struct lm_cache {
                          &ppix, &seg_gv, &tile_blk, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
                                &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
                                &wres, &obj_e, &obj_part, &bj_L, &bj_count,
+                         &tile_ck, &tile_ck_off, &pix_ck, &ck, &piece_seg, &piece_mask, &piece_cmask,
                          &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         for (auto* b : all) b->release();
     }
@@ -301,12 +323,16 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_CHECK(scene && cams && V > 0 && V <= kMaxViews, LM_ERR_INVALID_ARG, "lm_build_cache: bad scene/cameras");
     LM_CHECK(scene->x && scene->N > 0, LM_ERR_INVALID_ARG, "lm_build_cache: empty scene");
     LM_CHECK(scene->sh_degree >= 0 && scene->sh_degree <= 3, LM_ERR_INVALID_ARG, "sh_degree must be 0..3");
-    int TW = 16, TH = 16, dtype = LM_CACHE_F32;
+    int TW = 16, TH = 16, dtype = LM_CACHE_F32, thin = 0;
     if (opts) {
         if (opts->tile_w > 0) TW = opts->tile_w;
         if (opts->tile_h > 0) TH = opts->tile_h;
         dtype = opts->cache_dtype;
+        thin = opts->thin_window;
     }
+    LM_CHECK(thin >= 0 && thin <= LM_THIN_WINDOW_MAX, LM_ERR_INVALID_ARG, "thin_window must be 0..4096");
+    LM_CHECK(thin == 0 || dtype == LM_CACHE_F32, LM_ERR_UNSUPPORTED,
+             "a thinned cache stores no pair values: cache_dtype must be LM_CACHE_F32");
     LM_CHECK(TW * TH <= kMaxTilePix && TW > 0 && TH > 0, LM_ERR_INVALID_ARG, "tile_w * tile_h must be 1..256");
     LM_CHECK((TW & (TW - 1)) == 0, LM_ERR_INVALID_ARG, "tile_w must be a power of two");
     LM_CHECK(dtype == LM_CACHE_F32 || dtype == LM_CACHE_BF16 || dtype == LM_CACHE_F16, LM_ERR_INVALID_ARG,
@@ -326,6 +352,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     c->TW = TW;
     c->TH = TH;
     c->dtype = dtype;
+    c->thin_k = thin;
     c->cams_h.resize(V);
     int64_t tile_base = 0, pix_base = 0;
     std::vector<int32_t> tv;
@@ -447,6 +474,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->tile_real.ensure(sizeof(uint32_t) * c->n_tiles));
     LM_HIP(c->gv_cnt.ensure(sizeof(uint32_t) * (R + 1)));
     LM_HIP(hipMemsetAsync(c->gv_cnt.p, 0, sizeof(uint32_t) * (R + 1), s));
+    if (thin) LM_HIP(c->tile_ck.ensure(sizeof(uint32_t) * std::max<int64_t>(c->n_tiles, 1)));
     RasterArgs ra{};
     ra.cams = c->cams.as<CamDev>();
     ra.tile_view = c->tile_view.as<int32_t>();
@@ -466,6 +494,8 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     ra.tile_real = c->tile_real.as<uint32_t>();
     ra.gv_cnt = c->gv_cnt.as<uint32_t>();
     ra.n_pix = c->n_pix;
+    ra.thin_k = thin;
+    ra.tile_ck = c->tile_ck.as<uint32_t>();
     { LM_PROF("raster_count", s); LM_HIP(launch_raster(false, dtype, c->n_tiles, ra, s)); }
     return LM_OK;
 }
@@ -497,7 +527,8 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(hipMemcpyAsync(&host3[2], c->gv_idx.as<uint64_t>() + NV, 8, hipMemcpyDeviceToHost, s));
     LM_HIP(hipMemcpyAsync(&host3[3], c->tile_real_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
     LM_HIP(hipStreamSynchronize(s));
-    c->n_slots = (int64_t)host3[0];
+    c->n_slots = c->thin_k ? 0 : (int64_t)host3[0];
+    c->n_pieces = c->thin_k ? (int64_t)host3[0] : 0;
     c->n_pairs = (int64_t)host3[3];
     c->n_seg = (int64_t)host3[1];
     c->n_gv = (int64_t)host3[2];
@@ -515,10 +546,33 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     LM_HIP(launch_gv_compact(c->gv_cnt.as<uint32_t>(), c->gv_idx.as<uint64_t>(), c->gv_segoff.as<uint64_t>(), N,
                              (int)V, c->gv_rec.as<uint32_t>(), c->gv_seg_off.as<uint32_t>(),
                              c->gv_first.as<uint32_t>(), s));
+    c->seg_stride = round_up(nseg_a, 8);
+    if (c->thin_k) {
+        // thinned cache: pieces and per-pixel checkpoints instead of pair planes
+        LM_HIP(c->tile_ck_off.ensure(sizeof(uint64_t) * (c->n_tiles + 1)));
+        LM_HIP(exclusive_scan_u32_to_u64(c->tile_ck.as<uint32_t>(), c->tile_ck_off.as<uint64_t>(), c->n_tiles,
+                                         c->scan_tmp.p, c->scan_tmp.cap, s));
+        uint64_t nck = 0;
+        LM_HIP(hipMemcpyAsync(&nck, c->tile_ck_off.as<uint64_t>() + c->n_tiles, 8, hipMemcpyDeviceToHost, s));
+        LM_HIP(hipStreamSynchronize(s));
+        c->n_ck = (int64_t)nck;
+        const int64_t np_a = std::max<int64_t>(c->n_pieces, 1);
+        LM_HIP(c->piece_seg.ensure(sizeof(uint32_t) * np_a));
+        LM_HIP(c->piece_mask.ensure(sizeof(uint64_t) * np_a));
+        LM_HIP(c->piece_cmask.ensure(sizeof(uint64_t) * np_a));
+        LM_HIP(c->pix_ck.ensure(sizeof(uint32_t) * std::max<int64_t>(c->n_pix, 1)));
+        // two spare entries: a walk may read one past a pixel's last checkpoint
+        LM_HIP(c->ck.ensure(sizeof(float) * 4 * (c->n_ck + 2)));
+        LM_HIP(hipMemsetAsync(c->ck.as<float>() + 4 * c->n_ck, 0, sizeof(float) * 8, s));
+        c->pT.release();
+        c->pD.release();
+        c->ppix.release();
+        c->run_seg.release();
+        c->pair_stride = 8;
+    } else {
     // pair and segment arrays (planes padded so 8-wide vector loads stay inside);
     // the zero fill doubles as the padding of every segment to a multiple of 8
     c->pair_stride = round_up(c->n_slots, 8) + 8;
-    c->seg_stride = round_up(nseg_a, 8);
     const size_t wb = dtype_bytes(c->dtype);
     LM_HIP(c->pT.ensure(wb * c->pair_stride));
     LM_HIP(c->pD.ensure(wb * 3 * c->pair_stride));
@@ -533,8 +587,9 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
         LM_HIP(hipMemsetAsync(c->ppix.as<uint8_t>() + c->n_slots, 0, tail, s));
     }
     LM_HIP(c->run_seg.ensure(sizeof(uint32_t) * (c->pair_stride / 8)));
+    }
     LM_HIP(c->seg_gv.ensure(sizeof(uint32_t) * nseg_a));
-    LM_HIP(c->seg_f.ensure(sizeof(float) * 6 * c->seg_stride));
+    LM_HIP(c->seg_f.ensure(sizeof(float) * (c->thin_k ? 9 : 6) * c->seg_stride));
     RasterArgs ra{};
     ra.cams = c->cams.as<CamDev>();
     ra.tile_view = c->tile_view.as<int32_t>();
@@ -560,6 +615,14 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.seg_f = c->seg_f.as<float>();
     ra.seg_stride = c->seg_stride;
     ra.run_seg = c->run_seg.as<uint32_t>();
+    ra.thin_k = c->thin_k;
+    ra.ncontrib = c->ncontrib.as<int32_t>();
+    ra.tile_ck_off = c->tile_ck_off.as<int64_t>();
+    ra.pix_ck = c->pix_ck.as<uint32_t>();
+    ra.ck = c->ck.as<float>();
+    ra.piece_seg = c->piece_seg.as<uint32_t>();
+    ra.piece_mask = c->piece_mask.as<uint64_t>();
+    ra.piece_cmask = c->piece_cmask.as<uint64_t>();
     { LM_PROF("raster_fill", s); LM_HIP(launch_raster(true, c->dtype, c->n_tiles, ra, s)); }
     { LM_PROF("gv_sort", s); LM_HIP(launch_gv_sort(c->gv_seg_off.as<uint32_t>(), c->n_gv, c->gv_segs.as<uint32_t>(), s));
       LM_HIP(launch_seg_pos(c->gv_segs.as<uint32_t>(), c->seg_gv.as<uint32_t>(), c->n_seg, c->seg_pos.as<uint32_t>(),
@@ -733,10 +796,15 @@ lm_status lm_ctx_destroy(lm_ctx* ctx) {
     LM_CHECK(ctx != &lm::g_default_ctx, LM_ERR_INVALID_ARG, "lm_ctx_destroy: the default context");
     LM_CHECK(ctx->n_caches == 0, LM_ERR_INVALID_ARG, "lm_ctx_destroy: caches of the context are still alive");
     for (hipEvent_t e : ctx->prof.pool) (void)hipEventDestroy(e);
+    if (ctx->part || ctx->persist_dev) (void)hipDeviceSynchronize();
     if (ctx->part) {
-        (void)hipDeviceSynchronize();
         if (ctx->part_al.alloc) ctx->part_al.free(ctx->part_al.user, ctx->part, (void*)ctx->part_stream);
         else (void)hipFree(ctx->part);
+    }
+    if (ctx->persist_exec) (void)hipGraphExecDestroy(ctx->persist_exec);
+    if (ctx->persist_dev) {
+        if (ctx->persist_al.alloc) ctx->persist_al.free(ctx->persist_al.user, ctx->persist_dev, (void*)ctx->persist_stream);
+        else (void)hipFree(ctx->persist_dev);
     }
     delete ctx;
     return LM_OK;
@@ -745,7 +813,7 @@ lm_status lm_ctx_destroy(lm_ctx* ctx) {
 lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream) {
     lm_ctx* x = ctx ? ctx : &lm::g_default_ctx;
     lm::StreamScope lm_stream_scope_(S(stream), x);
-    LM_CHECK(a && b && out && n >= 0, LM_ERR_INVALID_ARG, "lm_vec_dot: bad argument");
+    LM_CHECK(((a && b) || n == 0) && out && n >= 0, LM_ERR_INVALID_ARG, "lm_vec_dot: bad argument");
     hipStream_t s = S(stream);
     const size_t need = sizeof(double) * (size_t)lm::dot_partial_count(n);
     if (x->part_cap < need) {
@@ -771,7 +839,8 @@ lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, dou
 }
 
 lm_status lm_vec_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, void* stream) {
-    LM_CHECK(x && d && out && n >= 0, LM_ERR_INVALID_ARG, "lm_vec_axpy: bad argument");
+    LM_CHECK((x && d && out) || n == 0, LM_ERR_INVALID_ARG, "lm_vec_axpy: bad argument");
+    LM_CHECK(n >= 0, LM_ERR_INVALID_ARG, "lm_vec_axpy: bad argument");
     LM_HIP(lm::launch_axpy(x, d, gamma, n, out, S(stream)));
     return LM_OK;
 }
@@ -858,7 +927,13 @@ lm_status lm_cache_get_info(const lm_cache* c, lm_cache_info* info) {
     info->n_pixels = c->n_pix;
     info->n_tiles = c->n_tiles;
     const int64_t wb = (int64_t)lm::dtype_bytes(c->dtype);
-    info->cache_bytes = c->n_slots * (4 * wb + 1) + (c->n_slots / 8) * 4 + c->n_seg * (4 + 4 + 24);
+    info->cache_bytes = c->thin_k
+                            ? c->n_pieces * (4 + 8 + 8) + c->n_ck * 16 + c->n_pix * 4 + c->n_tiles * 8 +
+                                  c->n_seg * (4 + 4 + 36)
+                            : c->n_slots * (4 * wb + 1) + (c->n_slots / 8) * 4 + c->n_seg * (4 + 4 + 24);
+    info->thin_window = c->thin_k;
+    info->n_pieces = c->n_pieces;
+    info->n_checkpoints = c->n_ck;
     info->device_bytes = (int64_t)c->device_bytes();
     info->V = c->V;
     info->P = c->P;
@@ -1038,6 +1113,110 @@ lm_status lm_apply_JT(const lm_cache* c, const float* u, float* g, void* stream)
     return apply_JT_internal(c, u, 1.0f, g, S(stream));
 }
 
+// The n_iters iterations of Algorithm 1 for the batch in one cooperative
+// launch (persist.hip), after the first product and the initial scalars.
+// The launch (counter reset + kernel) is captured into a graph once per
+// context, kernel variant and grid, and replayed; where the runtime cannot
+// capture a cooperative launch it is issued directly.  Synchronises the
+// stream to read the barrier's error flag.
+static lm_status pcg_persistent(lm_cache* const* caches, int32_t n_b, const lm::ApplyBatch& B,
+                                const float* const* M, const float* const* precond_scale, float* const* delta,
+                                float diag_floor, int32_t n_iters, double tol, int32_t tol_mode, hipStream_t s) {
+    lm_ctx* cx = lm::g_ctx;
+    const int kind = lm::persistent_tile_kind(caches[0]->dtype, caches[0]->thin_k > 0);
+    int grid = 0, nt = 0;
+    LM_HIP(lm::persistent_grid(caches[0]->deg, kind, &grid, &nt));
+    const int n_counters = 2 + LM_PCG_MAX_HISTORY;
+    const size_t off_cnt = (sizeof(lm::PersistArgs) + 255) / 256 * 256;
+    const size_t off_part = off_cnt + (sizeof(uint32_t) * n_counters + 255) / 256 * 256;
+    const size_t need = off_part + sizeof(double) * 3 * lm::kMaxBatch * lm::kPersistMaxGrid;
+    if (cx->persist_cap < need) {
+        if (cx->persist_dev) {
+            LM_HIP(hipStreamSynchronize(s));
+            if (cx->persist_al.alloc) cx->persist_al.free(cx->persist_al.user, cx->persist_dev, (void*)cx->persist_stream);
+            else LM_HIP(hipFree(cx->persist_dev));
+            cx->persist_dev = nullptr;
+            cx->persist_cap = 0;
+        }
+        if (cx->persist_exec) {
+            (void)hipGraphExecDestroy(cx->persist_exec);
+            cx->persist_exec = nullptr;
+        }
+        if (cx->al.alloc) {
+            cx->persist_dev = cx->al.alloc(cx->al.user, need, (void*)s);
+            LM_CHECK(cx->persist_dev, LM_ERR_HIP, "lm_pcg_solve: allocation failed");
+        } else {
+            LM_HIP(hipMalloc(&cx->persist_dev, need));
+        }
+        cx->persist_cap = need;
+        cx->persist_al = cx->al;
+        cx->persist_stream = s;
+    }
+    char* base = (char*)cx->persist_dev;
+    lm::PersistArgs* dev_args = (lm::PersistArgs*)base;
+    uint32_t* counters = (uint32_t*)(base + off_cnt);
+    // host copy of the arguments, kept in the context until the copy has run
+    static thread_local lm::PersistArgs H;
+    H = lm::PersistArgs{};
+    H.B = B;
+    for (int i = 0; i < n_b; ++i) {
+        lm_cache* c = caches[i];
+        H.B.a[i].stop = nullptr;
+        H.B.a[i].pg_part = (double*)(base + off_part);   // non-null: the chain forms p . g
+        H.v[i] = lm::PersistSubset{delta[i], c->pcg_r.as<float>(), c->pcg_z.as<float>(), c->pcg_p.as<float>(), M[i],
+                                   precond_scale ? precond_scale[i] : nullptr, c->pcg_state.as<lm::PcgState>()};
+    }
+    H.n = caches[0]->N * (int64_t)caches[0]->P;
+    H.n_iters = n_iters;
+    H.tol_mode = tol_mode;
+    H.tol = tol;
+    H.floor_ = diag_floor;
+    H.bar = counters;
+    H.err = (int32_t*)(counters + 1);
+    H.tile_ctr = counters + 2;
+    H.part = (double*)(base + off_part);
+    LM_HIP(hipMemcpyAsync(dev_args, &H, sizeof(H), hipMemcpyHostToDevice, s));
+    {
+        LM_PROF("pcg_persistent", s);
+        const int key[3] = {caches[0]->deg, kind, grid};
+        bool direct = cx->persist_graph == 0;
+        if (!direct && (!cx->persist_exec || memcmp(key, cx->persist_key, sizeof(key)) != 0)) {
+            if (cx->persist_exec) {
+                (void)hipGraphExecDestroy(cx->persist_exec);
+                cx->persist_exec = nullptr;
+            }
+            hipStream_t cs = nullptr;
+            LM_HIP(capture_stream(&cs));
+            hipGraph_t graph = nullptr;
+            hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                const hipError_t le = lm::launch_pcg_persistent(dev_args, counters, n_counters, caches[0]->deg, kind,
+                                                                grid, cs);
+                e = hipStreamEndCapture(cs, &graph);
+                if (e == hipSuccess) e = le;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&cx->persist_exec, graph, nullptr, nullptr, 0);
+            if (graph) (void)hipGraphDestroy(graph);
+            if (e != hipSuccess) {
+                (void)hipGetLastError();
+                cx->persist_exec = nullptr;
+                cx->persist_graph = 0;    // this runtime does not capture cooperative launches
+                direct = true;
+            } else {
+                cx->persist_graph = 1;
+                memcpy(cx->persist_key, key, sizeof(key));
+            }
+        }
+        if (direct) LM_HIP(lm::launch_pcg_persistent(dev_args, counters, n_counters, caches[0]->deg, kind, grid, s));
+        else LM_HIP(hipGraphLaunch(cx->persist_exec, s));
+    }
+    int32_t err = 0;
+    LM_HIP(hipMemcpyAsync(&err, counters + 1, sizeof(err), hipMemcpyDeviceToHost, s));
+    LM_HIP(hipStreamSynchronize(s));
+    LM_CHECK(err == 0, LM_ERR_HIP, "lm_pcg_solve: a grid barrier of the persistent kernel timed out");
+    return LM_OK;
+}
+
 static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const float* const* b, const float* const* M,
                                 float lambda, float diag_floor, int32_t n_iters, double tol, int32_t tol_mode,
                                 const float* const* precond_scale, float* const* delta, lm_pcg_stats* stats,
@@ -1051,7 +1230,8 @@ static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const floa
     for (int i = 0; i < n_b; ++i) {
         const lm_cache* c = caches[i];
         LM_CHECK(c && c->built && b[i] && M[i] && delta[i], LM_ERR_INVALID_ARG, "lm_pcg_solve: bad subset entry");
-        LM_CHECK(c->N == caches[0]->N && c->deg == caches[0]->deg && c->dtype == caches[0]->dtype,
+        LM_CHECK(c->N == caches[0]->N && c->deg == caches[0]->deg && c->dtype == caches[0]->dtype &&
+                     (c->thin_k > 0) == (caches[0]->thin_k > 0),
                  LM_ERR_INVALID_ARG, "lm_pcg_solve: subsets must share N, SH degree and cache type");
     }
     const int64_t n = caches[0]->N * (int64_t)caches[0]->P;
@@ -1115,9 +1295,12 @@ static lm_status pcg_solve_impl(lm_cache* const* caches, int32_t n_b, const floa
         }
         return LM_OK;
     };
-    const int mode = lm::g_ctx->pcg_graph;   // 0 eager, 1 graph replay, 2 graph replay for batches
-    const bool use_graph = n_iters >= 2 && (mode == 1 || (mode == 2 && n_b > 1));
-    if (use_graph) {
+    const int mode = lm::g_ctx->pcg_graph;   // 0 eager, 1 graph replay, 2 graph replay for batches, 3 persistent
+    const bool use_graph = n_iters >= 2 && (mode == 1 || ((mode == 2 || mode == 3) && n_b > 1));
+    if (mode == 3 && !block && n_iters > 0) {
+        lm_status ps = pcg_persistent(caches, n_b, B, M, precond_scale, delta, diag_floor, n_iters, tol, tol_mode, s);
+        if (ps != LM_OK) return ps;
+    } else if (use_graph) {
         // the iteration is captured once (nothing runs while capturing) and
         // replayed on the caller's stream: no host launch work per iteration
         hipStream_t cs = nullptr;
@@ -1219,7 +1402,7 @@ lm_status lm_autotune_tile(const lm_scene* scene, const lm_camera* cams, int32_t
     double best = -1.0;
     int found = 0;
     for (int k = 0; k < nc && he == hipSuccess && st == LM_OK; ++k) {
-        lm_options o{cand[k][0], cand[k][1], cache_dtype, 0, nullptr, lm::g_ctx};
+        lm_options o{cand[k][0], cand[k][1], cache_dtype, 0, nullptr, lm::g_ctx, opts ? opts->thin_window : 0, 0};
         // an untimed build first: buffer growth (device allocation) is not
         // part of the shape's cost
         st = lm_build_cache(scene, cams, V, target, &o, stream, &c, b, nullptr);
@@ -1272,7 +1455,7 @@ lm_status lm_set_allocator(const lm_allocator* a) {
 }
 
 lm_status lm_pcg_use_graph(lm_ctx* ctx, int32_t mode) {
-    LM_CHECK(mode >= 0 && mode <= 2, LM_ERR_INVALID_ARG, "lm_pcg_use_graph: mode must be 0, 1 or 2");
+    LM_CHECK(mode >= 0 && mode <= 3, LM_ERR_INVALID_ARG, "lm_pcg_use_graph: mode must be 0, 1, 2 or 3");
     (ctx ? ctx : &lm::g_default_ctx)->pcg_graph = mode;
     return LM_OK;
 }
@@ -1656,6 +1839,10 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
                             what == LM_EXPORT_NCONTRIB || what == LM_EXPORT_RESIDUAL;
     LM_CHECK(!(c->compact && build_only), LM_ERR_INVALID_ARG,
              "lm_cache_export: the build buffers of this cache were released (LM_BUILD_COMPACT)");
+    const bool pair_array = what == LM_EXPORT_PAIR_T || what == LM_EXPORT_PAIR_D || what == LM_EXPORT_PAIR_PIX ||
+                            what == LM_EXPORT_PAIR_GAUSS || what == LM_EXPORT_PAIR_FLAGS;
+    LM_CHECK(!(c->thin_k && pair_array), LM_ERR_UNSUPPORTED,
+             "lm_cache_export: a thinned cache stores no per-pair values");
     switch (what) {
         case LM_EXPORT_RECORDS_F32: {
             std::vector<float> rf;

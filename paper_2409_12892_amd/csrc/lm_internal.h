@@ -15,6 +15,8 @@ constexpr int kWave = 64;
 constexpr int kMaxTilePix = 256;   // pixels per tile (pixel-in-tile index is one byte)
 constexpr int kTileBlocks = 4;     // pixel blocks per tile (the pixels of one raster wave each)
 constexpr int kBlockPix = 64;      // pixels per block
+constexpr int kWindow = 512;       // pairs (64 runs of 8) a wave takes at a time in the pair passes
+constexpr int MODE_J = 1, MODE_JT = 2, MODE_JTJ = 3;   // product pass: J p, J^T u, fused J^T J p
 constexpr int kMaxViews = 4096;
 
 // Blending constants (paper section 3.1 defers them to the original 3DGS
@@ -72,6 +74,16 @@ struct CacheView {
     const float* lin;            // dev [kLin][lin_stride]: linearised projection per gv
     int64_t lin_stride;
     const float* wres;           // dev [3 * n_pix] residual weights (image layout), or null: all 1
+    // thinned cache (thin_k = K > 0): tile_pair_off and tile_blk count
+    // pieces (a splat's pixels in one 64-pixel block), seg_f has 9 rows
+    // (+ colour), and there are no pair planes
+    int32_t thin_k;
+    const uint32_t* piece_seg;   // dev [n_pieces] segment of each piece
+    const uint64_t* piece_mask;  // dev [n_pieces] contributing pixels (lane bits of the block)
+    const uint64_t* piece_cmask; // dev [n_pieces] those whose alpha is clamped
+    const int64_t* tile_ck_off;  // dev [n_tiles + 1] first checkpoint of each tile
+    const uint32_t* pix_ck;      // dev [n_pix] first checkpoint of each pixel within its tile's range
+    const float4* ck;            // dev [n_ck + 2] T, S0, S1, S2 in front of every K-th contributor
 };
 
 // Linearisation of the projection of one (Gaussian, view) at the cache's x,
@@ -102,6 +114,14 @@ void set_error(const std::string& msg);
 inline unsigned grid_for(int64_t n, int block = kBlock) {
     int64_t g = (n + block - 1) / block;
     return (unsigned)(g < 1 ? 1 : g);
+}
+
+// M^-1 of Algorithm 1 with the optional minimum diagonal (0 where M = 0) and
+// an optional learned scale per parameter.
+__device__ __forceinline__ float jacobi_inv(float M, float floor_, const float* scale, int64_t i) {
+    if (!(M > 0.0f)) return 0.0f;
+    const float s = scale ? scale[i] : 1.0f;
+    return s / fmaxf(M, floor_);
 }
 
 // ---- cache element storage -------------------------------------------------
@@ -222,6 +242,15 @@ struct RasterArgs {
     float* seg_f;              // [6][seg_stride]
     int64_t seg_stride;
     uint32_t* run_seg;         // [pair_stride / 8] segment of each aligned 8-pair run
+    // thinned cache (thin_k = K > 0; tile_pair_off / tile_blk count pieces)
+    int32_t thin_k;
+    uint32_t* tile_ck;         // count: [n_tiles] checkpoints per tile
+    const int64_t* tile_ck_off;// fill: [n_tiles + 1]
+    uint32_t* pix_ck;          // fill: [n_pix] first checkpoint of each pixel in its tile's range
+    float* ck;                 // fill: float4 [n_ck]: T, S0, S1, S2 in front of every K-th contributor
+    uint32_t* piece_seg;       // fill: [n_pieces] segment of each piece
+    uint64_t* piece_mask;      // fill: [n_pieces] contributing pixels of the block (lane bits)
+    uint64_t* piece_cmask;     // fill: [n_pieces] those with a clamped alpha
 };
 
 // Arguments of the product kernels (apply.hip).
@@ -263,6 +292,38 @@ struct PcgState {
     int32_t stop, iters, status, pad;
     double hist[LM_PCG_MAX_HISTORY];
 };
+
+// persist.hip: the iterations of Algorithm 1 for a batch in one cooperative
+// launch (per-subset vectors; the products' arguments are B's)
+constexpr int kPersistMaxGrid = 2048;
+struct PersistSubset {
+    float* x;                // the solution (Algorithm 1's x, the direction delta)
+    float* r;
+    float* z;
+    float* p;                // the search direction (also B.a[b].p)
+    const float* M;
+    const float* scale;      // learned factors of M^-1, or null
+    PcgState* st;
+};
+struct PersistArgs {
+    ApplyBatch B;            // products p -> out (= g); stop flags unused
+    PersistSubset v[kMaxBatch];
+    int64_t n;               // parameters per subset (N * P)
+    int32_t n_iters, tol_mode;
+    double tol;
+    float floor_;
+    uint32_t* bar;           // grid barrier counter (zeroed by the launch)
+    int32_t* err;            // set when a grid barrier timed out (zeroed by the launch)
+    uint32_t* tile_ctr;      // tile counter of each iteration (zeroed by the launch)
+    double* part;            // [kMaxBatch][3][grid] workgroup partial sums
+};
+int persistent_tile_kind(int dtype, bool thin);
+// workgroups that fit on the device at once, and the workgroup size
+hipError_t persistent_grid(int deg, int tile, int* grid, int* nt);
+// zeroes counters[0 .. n_counters) (barrier, error flag, tile counters),
+// then launches the cooperative kernel on dev_args
+hipError_t launch_pcg_persistent(const PersistArgs* dev_args, uint32_t* counters, int n_counters, int deg, int tile,
+                                 int grid, hipStream_t s);
 
 // project_bin.hip
 hipError_t launch_project(const CamDev* cams, const float* x, int64_t N, int V, int deg, int TW, int TH,
@@ -326,6 +387,9 @@ hipError_t launch_mlp_grad_step(float* w, float* adam_m, float* adam_v, int step
                                 double* loss_out, float* gpart, double* lpart, hipStream_t s);
 int mlp_grad_parts();
 hipError_t launch_gv_reduce_moments(const ApplyBatch& B, hipStream_t s);
+// thin.hip: the pair passes of a thinned cache (mode as launch_apply_tile)
+hipError_t launch_thin_tile(int mode, const ApplyBatch& B, hipStream_t s);
+hipError_t launch_thin_gram(const CacheView& c, float* gram, hipStream_t s);
 int64_t gv_reduce_waves(int64_t n_seg);
 hipError_t launch_linearize(const CacheView& c, const float* x, float* lin, hipStream_t s);
 // objective.hip: residual terms of one view (w, e may be null); part[part0 ..

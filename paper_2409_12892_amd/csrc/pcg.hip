@@ -14,12 +14,6 @@ namespace {
 
 constexpr int kVecBlocks = 2048;   // fixed grid: partial sums in a fixed order
 
-// M^-1 of Algorithm 1 with the optional minimum diagonal (0 where M = 0).
-__device__ __forceinline__ float jacobi_inv(float M, float floor_, const float* scale, int64_t i) {
-    if (!(M > 0.0f)) return 0.0f;
-    const float s = scale ? scale[i] : 1.0f;
-    return s / fmaxf(M, floor_);
-}
 
 template <int NV>
 __device__ __forceinline__ void block_partials(double (&v)[NV], double* part, int64_t stride) {

@@ -25,10 +25,22 @@
 //          (3 planes), pixel byte.  Every piece starts on a multiple of 8
 //          pairs (zero padding), so each aligned run of 8 pairs belongs to
 //          one segment (the splat's pieces in the tile) and one block; the
-//          run -> segment table names it.  A block's pairs are complete
-//          for its 64 pixels, so the product pass can finish u = J p of a
-//          block and run J^T on the same pairs while they are on chip.
+//          run -> segment table names it.  No piece crosses a multiple of
+//          kWindow pairs from its block's start (it moves to the next one;
+//          the gap is zero-filled and its runs are named by the piece's
+//          segment): the product and Gram passes give each wave kWindow
+//          pairs at a time, so every piece is summed by one wave and each
+//          segment gets one addition per block, in block order
+//          (deterministic sums).  A block's pairs are complete for its 64
+//          pixels, so the product pass can finish u = J p of a block and
+//          run J^T on the same pairs while they are on chip.
 //          Per segment: the splat data and the (Gaussian, view) links.
+//   thin fill (a thinned cache, thin_k = K > 0): per block the active
+//          splats in depth order as pieces (segment, 64-bit mask of the
+//          block's pixels it contributes to, mask of those where its alpha
+//          is clamped); per pixel, for its contributors 0, K, 2K, ...: the
+//          transmittance in front of it and the colour still to be blended
+//          from it on (float32 x 4); per segment also the splat's colour.
 // dC_ch/dalpha = T c_ch - S_ch/(1 - alpha) with S_ch the colour blended by
 // later splats, S_ch = C_ch(final) - (colour blended up to and including
 // this splat), all in float64.
@@ -43,14 +55,22 @@ constexpr int NW = kBlock / kWave;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 __device__ __forceinline__ uint32_t pad8(uint32_t n) { return (n + 7u) & ~7u; }
+// Start of a piece of len padded pairs placed at block offset e: moved to
+// the next window when it would cross one (len <= 64 <= kWindow).
+__device__ __forceinline__ uint32_t place_piece(uint32_t e, uint32_t len) {
+    return (e & (kWindow - 1)) + len > kWindow ? (e + kWindow - 1) & ~(kWindow - 1) : e;
+}
 
-template <bool FILL, int DT>
+template <bool FILL, int DT, bool THIN>
 __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     using S = Store<DT>;
     __shared__ double s_rec[10][kBlock];
     __shared__ uint32_t s_g[kBlock];
     __shared__ uint8_t s_wc[kBlock][NW];       // count pass: contributing pixels per wave
     __shared__ uint32_t s_eoff[kBlock][NW];    // fill pass: tile offset of each entry's piece per block
+    __shared__ uint32_t s_egap[kBlock][NW];    // fill pass: tile offset of the gap before it (its start if none)
+    __shared__ uint32_t s_cnt[kBlock];         // fill pass: the batch's per-entry counts
+    __shared__ uint32_t s_eseg[kBlock];        // thin fill: segment of each active entry
     __shared__ uint32_t s_run[3];              // running -, segments, real pairs
     __shared__ uint32_t s_blk[NW];             // running padded pairs per block (count); block starts (fill)
     __shared__ double s_red[kBlock / kWave];
@@ -110,6 +130,27 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     }
     const int64_t ks = a.tile_start[t], ke = a.tile_start[t + 1];
     const double lmargin = 1e-9;
+    // thin fill: this pixel's checkpoints (one per K contributors) in the
+    // tile's checkpoint range, pixels in thread order
+    float4* ckp = nullptr;
+    int kc = 0;                 // contributors left before the next checkpoint
+    if (FILL && THIN) {
+        const uint32_t nck = valid ? ((uint32_t)a.ncontrib[pg] + (uint32_t)a.thin_k - 1u) / (uint32_t)a.thin_k : 0u;
+        uint32_t inc = nck;
+#pragma unroll
+        for (int off = 1; off < kWave; off <<= 1) {
+            const uint32_t o = __shfl_up(inc, off, kWave);
+            if (lane >= off) inc += o;
+        }
+        if (lane == kWave - 1) s_scan4[wid][0] = inc;
+        __syncthreads();
+        uint32_t base = 0;
+        for (int w = 0; w < wid; ++w) base += s_scan4[w][0];
+        const uint32_t off = base + inc - nck;
+        if (valid) a.pix_ck[pg] = off;
+        ckp = (float4*)a.ck + a.tile_ck_off[t] + off;
+        __syncthreads();
+    }
 
     for (int64_t b0 = ks; b0 < ke; b0 += kBlock) {
         if (__syncthreads_and(done ? 1 : 0)) break;
@@ -122,55 +163,52 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
         }
         if (FILL) {
-            // per entry and block the padded piece length; block-wide
-            // exclusive scans give each piece its offset in its block and each
+            // per entry and block the padded piece, placed in depth order
+            // (one thread per block); a block-wide exclusive scan gives each
             // active entry its segment index
             const uint32_t c = tid < nb ? a.entry_cnt[b0 + tid] : 0u;
+            s_cnt[tid] = c;
             uint32_t cw[NW];
 #pragma unroll
             for (int w = 0; w < NW; ++w) cw[w] = (c >> (8 * w)) & 0xFFu;
             const uint32_t tot = cw[0] + cw[1] + cw[2] + cw[3];
-            const uint32_t v01 = pad8(cw[0]) | (pad8(cw[1]) << 16);   // batch sums stay below 2^16
-            const uint32_t v23 = pad8(cw[2]) | (pad8(cw[3]) << 16);
             const uint32_t vac = tot > 0 ? 1u : 0u;
-            uint32_t i01 = v01, i23 = v23, iac = vac;
+            uint32_t iac = vac;
 #pragma unroll
             for (int off = 1; off < kWave; off <<= 1) {
-                const uint32_t o01 = __shfl_up(i01, off, kWave), o23 = __shfl_up(i23, off, kWave);
                 const uint32_t oac = __shfl_up(iac, off, kWave);
-                if (lane >= off) {
-                    i01 += o01;
-                    i23 += o23;
-                    iac += oac;
-                }
+                if (lane >= off) iac += oac;
             }
-            if (lane == kWave - 1) {
-                s_scan4[wid][0] = i01;
-                s_scan4[wid][1] = i23;
-                s_scan4[wid][2] = iac;
-            }
+            if (lane == kWave - 1) s_scan4[wid][2] = iac;
             __syncthreads();
-            uint32_t b01 = 0, b23 = 0, bac = 0, t01 = 0, t23 = 0, tac = 0;
+            if (tid < NW) {
+                uint32_t e = s_blk[tid];
+                for (int j = 0; j < nb; ++j) {
+                    const uint32_t cj = (s_cnt[j] >> (8 * tid)) & 0xFFu;
+                    const uint32_t len = THIN ? (cj ? 1u : 0u) : pad8(cj);
+                    const uint32_t st = (len && !THIN) ? place_piece(e, len) : e;
+                    s_egap[j][tid] = s_bbase[tid] + e;
+                    s_eoff[j][tid] = s_bbase[tid] + st;
+                    e = st + len;
+                }
+                s_blk[tid] = e;
+            }
+            uint32_t bac = 0, tac = 0;
 #pragma unroll
             for (int w = 0; w < NW; ++w) {
-                if (w < wid) {
-                    b01 += s_scan4[w][0];
-                    b23 += s_scan4[w][1];
-                    bac += s_scan4[w][2];
-                }
-                t01 += s_scan4[w][0];
-                t23 += s_scan4[w][1];
+                if (w < wid) bac += s_scan4[w][2];
                 tac += s_scan4[w][2];
             }
-            const uint32_t e01 = b01 + i01 - v01, e23 = b23 + i23 - v23;
-            const uint32_t ex[NW] = {e01 & 0xFFFFu, e01 >> 16, e23 & 0xFFFFu, e23 >> 16};
             const uint32_t eseg = s_run[1] + bac + iac - vac;
-            uint32_t eoff[NW];
+            __syncthreads();
+            uint32_t eoff[NW], egap[NW];
 #pragma unroll
-            for (int w = 0; w < NW; ++w) eoff[w] = s_bbase[w] + s_blk[w] + ex[w];
+            for (int w = 0; w < NW; ++w) {
+                eoff[w] = s_eoff[tid][w];
+                egap[w] = s_egap[tid][w];
+            }
+            if (THIN && tid < nb) s_eseg[tid] = (uint32_t)(seg_base + eseg);
             if (tid < nb) {
-#pragma unroll
-                for (int w = 0; w < NW; ++w) s_eoff[tid][w] = eoff[w];
                 if (tot > 0 && seg_base + eseg < seg_end) {
                     const int64_t s = seg_base + eseg;
                     const uint32_t gi = s_g[tid];
@@ -183,19 +221,26 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     a.seg_f[3 * a.seg_stride + s] = (float)s_rec[3][tid];
                     a.seg_f[4 * a.seg_stride + s] = (float)s_rec[4][tid];
                     a.seg_f[5 * a.seg_stride + s] = (float)s_rec[5][tid];
+                    if (THIN) {
+#pragma unroll
+                        for (int ch = 0; ch < 3; ++ch) a.seg_f[(6 + ch) * a.seg_stride + s] = (float)s_rec[7 + ch][tid];
+                    }
                     const uint32_t slot = atomicAdd(&a.gv_cursor[gv], 1u);
                     if (a.gv_segoff[gvkey] + slot < a.gv_segoff[gvkey + 1]) a.gv_segs[a.gv_segoff[gvkey] + slot] = (uint32_t)s;
                     typename S::word* zT = (typename S::word*)a.pT;
                     typename S::word* zD = (typename S::word*)a.pD;
 #pragma unroll
                     for (int w = 0; w < NW; ++w) {
-                        if (cw[w] == 0) continue;
-                        // the piece's aligned runs -> this segment; its padding
-                        // slots get a zero T word (no pair)
+                        if (THIN || cw[w] == 0) continue;
+                        // the piece's aligned runs (and those of the gap before
+                        // it) -> this segment; padding and gap slots get a zero
+                        // T word (no pair)
+                        const int64_t qg = pair_base + egap[w];
                         const int64_t q0 = pair_base + eoff[w];
                         const int64_t q1 = min(q0 + (int64_t)pad8(cw[w]), pair_end);
-                        for (int64_t r = q0 >> 3; r < (q1 >> 3); ++r) a.run_seg[r] = (uint32_t)s;
-                        for (int64_t q = q0 + cw[w]; q < q1; ++q) {
+                        for (int64_t r = qg >> 3; r < (q1 >> 3); ++r) a.run_seg[r] = (uint32_t)s;
+                        for (int64_t q = qg; q < q1; ++q) {
+                            if (q >= q0 && q < q0 + (int64_t)cw[w]) continue;
                             zT[q] = 0;
                             zD[q] = 0;
                             zD[a.pair_stride + q] = 0;
@@ -206,13 +251,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 }
             }
             __syncthreads();
-            if (tid == 0) {
-                s_blk[0] += t01 & 0xFFFFu;
-                s_blk[1] += t01 >> 16;
-                s_blk[2] += t23 & 0xFFFFu;
-                s_blk[3] += t23 >> 16;
-                s_run[1] += tac;
-            }
+            if (tid == 0) s_run[1] += tac;
         }
         __syncthreads();
 
@@ -237,13 +276,32 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             if (!FILL) {
                 if (lane == 0) s_wc[j][wid] = (uint8_t)__popcll(bal);
             }
+            if (FILL && THIN) {
+                const uint64_t cbal = __ballot(contrib && a_raw > kAlphaMax);
+                if (lane == 0 && bal != 0ull) {
+                    const int64_t q = pair_base + s_eoff[j][wid];
+                    if (q < pair_end) {
+                        a.piece_seg[q] = s_eseg[j];
+                        a.piece_mask[q] = bal;
+                        a.piece_cmask[q] = cbal;
+                    }
+                }
+                if (contrib) {
+                    if (kc == 0) {   // blend state in front of contributors 0, K, 2K, ...
+                        ckp[cnt / a.thin_k] = make_float4((float)T, (float)(Ch0 - acc0), (float)(Ch1 - acc1),
+                                                          (float)(Ch2 - acc2));
+                        kc = a.thin_k;
+                    }
+                    --kc;
+                }
+            }
             if (contrib) {
                 const double w = alpha * T;
                 const double c0 = s_rec[7][j], c1 = s_rec[8][j], c2 = s_rec[9][j];
                 acc0 += c0 * w;
                 acc1 += c1 * w;
                 acc2 += c2 * w;
-                if (FILL) {
+                if (FILL && !THIN) {
                     const uint32_t rank = (uint32_t)__popcll(bal & lanemask_lt());
                     const uint32_t within = s_eoff[j][wid] + rank;        // slot in the tile
                     const int64_t slot = pair_base + within;
@@ -267,38 +325,37 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         }
         __syncthreads();
         if (!FILL) {
-            // per-entry counts, per-block padded totals, active entries and
+            // per-entry counts, per-block padded totals (pieces placed in
+            // depth order as the fill pass places them), active entries and
             // real pairs of the batch, and the (Gaussian, view) segment counts
-            uint32_t tot = 0, p01 = 0, p23 = 0;
+            uint32_t tot = 0;
             if (tid < nb) {
                 uint32_t c0 = s_wc[tid][0], c1 = s_wc[tid][1], c2 = s_wc[tid][2], c3 = s_wc[tid][3];
                 a.entry_cnt[b0 + tid] = c0 | (c1 << 8) | (c2 << 16) | (c3 << 24);
                 tot = c0 + c1 + c2 + c3;
                 if (tot > 0) atomicAdd(&a.gv_cnt[(int64_t)s_g[tid] * a.V + v], 1u);
-                p01 = pad8(c0) | (pad8(c1) << 16);     // per wave at most 64 x 64 per half
-                p23 = pad8(c2) | (pad8(c3) << 16);
             }
             uint32_t act = tot > 0 ? 1u : 0u, real = tot;
 #pragma unroll
             for (int off = kWave / 2; off > 0; off >>= 1) {
-                p01 += __shfl_xor(p01, off, kWave);
-                p23 += __shfl_xor(p23, off, kWave);
                 act += __shfl_xor(act, off, kWave);
                 real += __shfl_xor(real, off, kWave);
             }
             if (lane == 0) {
-                s_scan4[wid][0] = p01;
-                s_scan4[wid][1] = p23;
                 s_scan4[wid][2] = act;
                 s_scan4[wid][3] = real;
+            }
+            if (tid < NW) {
+                uint32_t e = s_blk[tid];
+                for (int j = 0; j < nb; ++j) {
+                    const uint32_t len = pad8(s_wc[j][tid]);
+                    if (len) e = THIN ? e + 1 : place_piece(e, len) + len;
+                }
+                s_blk[tid] = e;
             }
             __syncthreads();
             if (tid == 0) {
                 for (int w = 0; w < NW; ++w) {
-                    s_blk[0] += s_scan4[w][0] & 0xFFFFu;
-                    s_blk[1] += s_scan4[w][0] >> 16;
-                    s_blk[2] += s_scan4[w][1] & 0xFFFFu;
-                    s_blk[3] += s_scan4[w][1] >> 16;
                     s_run[1] += s_scan4[w][2];
                     s_run[2] += s_scan4[w][3];
                 }
@@ -327,6 +384,12 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
 #pragma unroll
         for (int off = kWave / 2; off > 0; off >>= 1) fsq += __shfl_xor(fsq, off, kWave);
         if (lane == 0) s_red[wid] = fsq;
+        if (THIN) {
+            uint32_t nck = valid ? ((uint32_t)cnt + (uint32_t)a.thin_k - 1u) / (uint32_t)a.thin_k : 0u;
+#pragma unroll
+            for (int off = kWave / 2; off > 0; off >>= 1) nck += __shfl_xor(nck, off, kWave);
+            if (lane == 0) s_scan4[wid][0] = nck;
+        }
         __syncthreads();
         if (tid == 0) {
             double s = 0.0;
@@ -336,6 +399,11 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             for (int w = 0; w < NW; ++w) a.tile_blk[t * kTileBlocks + w] = s_blk[w];
             a.tile_segs[t] = s_run[1];
             a.tile_real[t] = s_run[2];
+            if (THIN) {
+                uint32_t nck = 0;
+                for (int w = 0; w < NW; ++w) nck += s_scan4[w][0];
+                a.tile_ck[t] = nck;
+            }
         }
     }
 }
@@ -401,14 +469,18 @@ __global__ void k_gv_sort(const uint32_t* __restrict__ gv_seg_off, int64_t n_gv,
 
 hipError_t launch_raster(bool fill, int dtype, int64_t n_tiles, const RasterArgs& a, hipStream_t s) {
     dim3 g((unsigned)n_tiles), b(kBlock);
+    const bool thin = a.thin_k > 0;
     if (!fill) {
-        hipLaunchKernelGGL((k_raster<false, LM_CACHE_F32>), g, b, 0, s, a);
+        if (thin) hipLaunchKernelGGL((k_raster<false, LM_CACHE_F32, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_raster<false, LM_CACHE_F32, false>), g, b, 0, s, a);
+    } else if (thin) {
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F32, true>), g, b, 0, s, a);
     } else if (dtype == LM_CACHE_F32) {
-        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F32>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F32, false>), g, b, 0, s, a);
     } else if (dtype == LM_CACHE_BF16) {
-        hipLaunchKernelGGL((k_raster<true, LM_CACHE_BF16>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_BF16, false>), g, b, 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F16>), g, b, 0, s, a);
+        hipLaunchKernelGGL((k_raster<true, LM_CACHE_F16, false>), g, b, 0, s, a);
     }
     return hipGetLastError();
 }

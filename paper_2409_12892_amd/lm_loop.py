@@ -62,6 +62,7 @@ class LMConfig:
     objective: str = "l2"           # "l2" or "l1_ssim"
     precond: str = "jacobi"         # "jacobi" (Algorithm 1) or "block" (per-Gaussian block-Jacobi)
     obj_eps: float = B.OBJ_EPS
+    thin_window: int = 0            # 0: full cache; K > 0: thinned cache (re-blend windows of K)
 
 
 class LMSolver:
@@ -112,11 +113,13 @@ class LMSolver:
         self.E_views = None
         if self.obj is None:
             self.cache, self.b, self.fsq = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
-                                                            cache_dtype=cfg.cache_dtype, cache=self.cache, b=self.b)
+                                                            cache_dtype=cfg.cache_dtype, cache=self.cache, b=self.b,
+                                                            thin_window=cfg.thin_window)
         else:
             # the build's own b = -J^T F belongs to the least-squares objective
             self.cache, _, _ = B.lm_build_cache(x, self.deg, self.cams, self.target, tile=cfg.tile,
-                                                cache_dtype=cfg.cache_dtype, cache=self.cache, want_b=False)
+                                                cache_dtype=cfg.cache_dtype, cache=self.cache, want_b=False,
+                                                thin_window=cfg.thin_window)
             self.b, self.E_views = B.lm_cache_objective(self.cache, self.target, self.obj, b=self.b)
             self.fsq = self.E_views.sum().reshape(1)
 

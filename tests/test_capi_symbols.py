@@ -56,3 +56,20 @@ def test_binding_structs_match_header_layout():
                      ctypes.sizeof(binding.LmOptions), ctypes.sizeof(binding.LmCacheInfo),
                      ctypes.sizeof(binding.LmPcgStats), binding.PCG_MAX_HISTORY,
                      ctypes.sizeof(binding.LmTileScore), ctypes.sizeof(binding.LmProfileEntry)]
+
+
+def test_context_handles_cross_the_binding_as_pointers():
+    """Context calls that need no GPU: a context's handle reaches the library
+    as a full 64-bit pointer (a bare Python int would be passed as a 32-bit
+    C int and truncated)."""
+    from paper_2409_12892_amd import binding
+    if not os.path.exists(binding.LIB_PATH):
+        pytest.skip("liblm3dgs.so not built (run __graft_entry__.build())")
+    c = binding.Ctx()
+    try:
+        binding.lm_pcg_use_graph(1, ctx=c)
+        binding.lm_profile_enable(True, ctx=c)
+        assert binding.lm_profile_read(ctx=c) == {}
+        binding.lm_profile_enable(False, ctx=c)
+    finally:
+        c.destroy()

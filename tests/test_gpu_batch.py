@@ -73,6 +73,38 @@ def test_graph_replay_matches_eager_and_repeats(batch):
             assert rel(d_g, d_e) < 1e-5, rep
 
 
+def test_persistent_kernel_matches_graph_and_oracle(batch, report):
+    """Mode 3 (all iterations of all subsets in one cooperative kernel,
+    captured in a graph once and replayed): each subset's direction equals
+    the graph-replayed solve to float32 rounding and the oracle within its
+    bar; the residual history and stopping agree; a second call (graph
+    replay) repeats the first; the paper's stopping rule ends subsets at
+    their own iteration."""
+    graph, st_g = _solve(batch, 1)
+    for rep in range(2):
+        pers, st_p = _solve(batch, 3)
+        for i, (s_, d_p, d_g) in enumerate(zip(batch["subs"], pers, graph)):
+            report[("persistent_vs_graph", i, rep)] = rel(d_p, d_g)
+            assert rel(d_p, d_g) < 1e-5, (i, rep)
+            assert rel(d_p, s_["out"]["x"]) < s_["bar"], (i, rep)
+            assert st_p[i]["iters"] == st_g[i]["iters"] == 8
+            np.testing.assert_allclose(st_p[i]["history"], st_g[i]["history"], rtol=1e-5)
+    B = batch["B"]
+    subs = batch["subs"]
+    res = {}
+    for mode in (1, 3):
+        B.lm_pcg_use_graph(mode)
+        res[mode] = B.lm_pcg_solve([s_["cache"] for s_ in subs], [s_["b"] for s_ in subs],
+                                   [s_["M"] for s_ in subs], 1e-2, 40, tol=0.05, tol_mode=B.TOL_PAPER_SQUARED,
+                                   diag_floor=1e-2)
+    B.lm_pcg_use_graph(2)
+    for i in range(len(subs)):
+        assert res[3][1][i]["iters"] == res[1][1][i]["iters"], i
+        if res[3][1][i]["iters"] < 40:
+            assert res[3][1][i]["history"][-1] < 0.05
+        assert rel(res[3][0][i].cpu().numpy(), res[1][0][i].cpu().numpy()) < 1e-5, i
+
+
 def test_batched_block_jacobi_graph_matches_single_solves_and_oracle(batch, report):
     """Block-Jacobi through the batched, graph-replayed solve: every subset's
     direction equals its own single-subset solve, and subset 0 matches the

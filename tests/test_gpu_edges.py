@@ -50,9 +50,19 @@ def test_view_facing_away_has_no_splats():
     ref_b = J.b(list(target)).reshape(sc.P, -1)
     assert rel(b.cpu().numpy(), ref_b) < 1e-5
     p = random_direction(sc.P, sc.N, seed=3)
-    u = B.lm_apply_J(cache, torch.from_numpy(p).cuda()).cpu().numpy()
+    # every residual is written, also those of pixels (and 8x8 blocks)
+    # without pairs: the output starts as NaN
+    out = torch.full((3 * 3 * 48 * 48,), float("nan"), device="cuda")
+    u = B.lm_apply_J(cache, torch.from_numpy(p).cuda(), out=out).cpu().numpy()
+    assert np.isfinite(u).all()
     assert rel(u, J.apply_J(p.astype(np.float64))) < 1e-5
     assert np.all(u.reshape(3, 3, 48, 48)[1] == 0)
+    cache_t, _, _ = B.lm_build_cache(x, sc.sh_degree, cams, torch.from_numpy(target.ravel()).cuda(), thin_window=8)
+    out.fill_(float("nan"))
+    ut = B.lm_apply_J(cache_t, torch.from_numpy(p).cuda(), out=out).cpu().numpy()
+    assert np.isfinite(ut).all() and np.all(ut.reshape(3, 3, 48, 48)[1] == 0)
+    assert rel(ut, J.apply_J(p.astype(np.float64))) < 1e-5
+    cache_t.destroy()
 
 
 def test_no_visible_gaussian():
