@@ -370,6 +370,21 @@ lm_status lm_pcg_use_graph(lm_ctx* ctx, int32_t mode);
 lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, double* out, void* stream);
 lm_status lm_vec_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, void* stream);
 
+/* For callers that cannot allocate device memory (code under stream or
+ * graph capture, serving loops, harnesses that forbid hipMalloc): the same
+ * float64 dot product as lm_vec_dot, bit-identical to it, with its partial
+ * sums in a static device array of the library instead of context memory.
+ *   a, b: float32 dev vectors of n elements; out: one dev double.
+ *   n <= LM_VEC_DOT_STATIC_MAX_N (2^40), else LM_ERR_CAPACITY.  The array
+ *   holds the 2048 per-block partial sums of the fixed vector grid (16 KiB);
+ *   every GPU the library runs on holds its own copy until the process ends.
+ *   Every element the call reads is written by the same call first, so
+ *   nothing needs clearing between calls.
+ *   Allocates nothing (no hipMalloc, no allocator call).  All calls on one
+ *   GPU share that GPU's array: calls that overlap on one GPU (several
+ *   streams or threads without ordering) race and give wrong results. */
+#define LM_VEC_DOT_STATIC_MAX_N ((int64_t)1 << 40)
+lm_status lm_vec_dot_static(const float* a, const float* b, int64_t n, double* out, void* stream);
 
 /* Weighted mean of subset directions (paper eq. combine-pcg):
  * out = sum_i M_i delta_i / sum_k M_k element-wise; 0 where sum_k M_k = 0.

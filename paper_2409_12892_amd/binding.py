@@ -38,7 +38,7 @@ EXPORTED_SYMBOLS = (
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
     "lm_jp_sqnorm", "lm_set_allocator", "lm_objective_terms", "lm_set_residual_weights", "lm_cache_objective",
     "lm_objective_value", "lm_pcg_solve_block", "lm_block_precond_apply", "lm_ctx_create", "lm_ctx_destroy",
-    "lm_vec_dot", "lm_vec_axpy",
+    "lm_vec_dot", "lm_vec_axpy", "lm_vec_dot_static",
 )
 
 # objective kinds (include/lm3dgs.h): plain least squares, and the paper's
@@ -534,6 +534,18 @@ def lm_vec_dot(a, b, out=None, ctx: Ctx | None = None):
     out = torch.empty(1, device=a.device, dtype=torch.float64) if out is None else out
     _check(load().lm_vec_dot(_ctx_ptr(ctx), _ptr(a), _ptr(b), c_int64(a.numel()), _ptr(out), _stream()),
            "lm_vec_dot")
+    return out
+
+
+def lm_vec_dot_static(a, b, out):
+    """a . b in float64 into the caller's 1-element float64 device tensor
+    `out`, with the library's static partial-sum array (allocates nothing)."""
+    a = _dev_f32(a, "a")
+    b = _dev_f32(b, "b")
+    if a.numel() != b.numel():
+        raise ValueError("lm_vec_dot_static: sizes differ")
+    _check(load().lm_vec_dot_static(_ptr(a), _ptr(b), c_int64(a.numel()), _ptr(out), _stream()),
+           "lm_vec_dot_static")
     return out
 
 

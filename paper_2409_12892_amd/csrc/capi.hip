@@ -838,6 +838,18 @@ lm_status lm_vec_dot(lm_ctx* ctx, const float* a, const float* b, int64_t n, dou
     return LM_OK;
 }
 
+lm_status lm_vec_dot_static(const float* a, const float* b, int64_t n, double* out, void* stream) {
+    LM_CHECK(((a && b) || n == 0) && out && n >= 0, LM_ERR_INVALID_ARG, "lm_vec_dot_static: bad argument");
+    LM_CHECK(n <= LM_VEC_DOT_STATIC_MAX_N, LM_ERR_CAPACITY,
+             "lm_vec_dot_static: n exceeds the maximum of 2^40 elements");
+    LM_CHECK(lm::dot_partial_count(n) <= lm::dot_static_capacity(), LM_ERR_CAPACITY,
+             "lm_vec_dot_static: partial sums exceed the static scratch");
+    double* part = nullptr;
+    LM_HIP(lm::dot_static_scratch(&part));
+    LM_HIP(lm::launch_dot(a, b, n, part, out, S(stream)));
+    return LM_OK;
+}
+
 lm_status lm_vec_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, void* stream) {
     LM_CHECK((x && d && out) || n == 0, LM_ERR_INVALID_ARG, "lm_vec_axpy: bad argument");
     LM_CHECK(n >= 0, LM_ERR_INVALID_ARG, "lm_vec_axpy: bad argument");

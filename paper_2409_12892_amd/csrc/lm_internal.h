@@ -440,6 +440,10 @@ hipError_t launch_combine(int n_b, const float* const* d, const float* const* m,
 // a . b in float64 into out (dev); part holds dot_partial_count(n) doubles
 int64_t dot_partial_count(int64_t n);
 hipError_t launch_dot(const float* a, const float* b, int64_t n, double* part, double* out, hipStream_t s);
+// lm_vec_dot_static: this device's static partial-sum array (looked up on
+// first use per device) and its capacity in partial sums
+hipError_t dot_static_scratch(double** out);
+int64_t dot_static_capacity();
 // out = x + gamma d (float32, one rounding)
 hipError_t launch_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, hipStream_t s);
 

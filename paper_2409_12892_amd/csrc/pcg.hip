@@ -4,6 +4,8 @@
 // Every kernel of an iteration reads the device `stop` flag first and
 // returns when it is set, so the host enqueues n_iters iterations without
 // synchronising and the loop still ends where Algorithm 1 breaks.
+#include <mutex>
+
 #include "lm_internal.h"
 
 namespace lm {
@@ -287,6 +289,39 @@ hipError_t launch_dot(const float* a, const float* b, int64_t n, double* part, d
     hipLaunchKernelGGL(k_dot_part, dim3(nb), dim3(kBlock), 0, s, n, a, b, part);
     hipLaunchKernelGGL(k_dot_sum, dim3(1), dim3(kBlock), 0, s, part, (int64_t)nb, out);
     return hipGetLastError();
+}
+
+// Partial sums of lm_vec_dot_static: a library-owned device array, one
+// copy per GPU (a __device__ variable lives in every device's copy of the
+// code object), sized for the fixed vector grid.  Host code never passes
+// the array's name to a kernel (on the host it is a stand-in, not a device
+// address); the address is looked up once per device, with that device
+// current, and used for every later call on it.
+static __device__ __align__(256) double scratch[kVecBlocks];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_dev[kMaxDevices];
+}  // namespace
+
+int64_t dot_static_capacity() { return kVecBlocks; }
+
+hipError_t dot_static_scratch(double** out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_dev[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_dev[dev] = (double*)p;
+    }
+    *out = g_scratch_dev[dev];
+    return hipSuccess;
 }
 
 hipError_t launch_axpy(const float* x, const float* d, float gamma, int64_t n, float* out, hipStream_t s) {
