@@ -41,7 +41,7 @@ def traffic_file(dtype: str) -> str:
     """Committed rocprofv3 counter summary of the fused pass for one cache type."""
     return os.path.join(ROOT, "profiles", f"apply_tile_JtJ_paper_{dtype}_traffic.txt")
 
-APPLY_SRC = os.path.join(ROOT, "paper_2409_12892_amd", "csrc", "apply.hip")
+APPLY_SRC = os.path.join(ROOT, "paper_2409_12892_amd", "csrc", "products.h")   # the tile pass
 
 
 def log(msg: str) -> None:
@@ -379,31 +379,58 @@ def bench_batching(args, B, sg, torch) -> dict:
     return out
 
 
-def train_learned_mlp(args, B, torch, subset, cfg, lam, floor):
-    """The perceptron of the learned preconditioner, trained on the GPU on a
-    separate scene of the same generator (other seed, 300k Gaussians, 8 views
-    1280x720) with the shrunk row-sum targets: 300 Adam steps."""
-    log("training scene: 300000 Gaussians, 8 views 1280x720")
-    tr = subset(300_000, (8, 1280, 720), int(cfg["seed"]) + 100)
-    feat = B.lm_precond_features(tr["cache"], tr["x"], tr["M"])
-    t, mask = B.lm_precond_targets(tr["cache"], lam, floor)
+TRAIN_RUNS = 20          # seeded runs of the training scene
+TRAIN_STEPS = 600        # Adam steps
+
+
+def train_learned_mlp(args, B, sg, torch, lam, floor):
+    """The perceptron of the learned preconditioner, trained on the GPU on
+    20 seeded runs shaped like the tiny plain-method scene but with SH degree
+    3 (2,048 Gaussians, 4 views 64x64, targets rendered from perturbed
+    parameters plus pixel noise; seeds 1000..1019): per run the cache, the
+    Jacobi diagonal, the features and the exact targets (each Gaussian's
+    block rows summed over the views in float64, shrunk towards the run's
+    per-parameter means), then 600 Adam steps on all runs' samples."""
+    dev = torch.device("cuda:0")
+    feats, ts, masks = [], [], []
+    for r in range(TRAIN_RUNS):
+        d = sg.config_scene("tiny", deg=3, seed=1000 + r)
+        sc, cams = d["scene"], d["cams"][0]
+        x = torch.from_numpy(sc.x).to(dev)
+        target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
+        target.add_(torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev))
+        cache, _, _ = B.lm_build_cache(x, sc.sh_degree, cams, target)
+        M = B.lm_jacobi_diag(cache)
+        feats.append(B.lm_precond_features(cache, x, M))
+        t, m = B.lm_precond_targets(cache, lam, floor)
+        ts.append(t)
+        masks.append(m)
+        cache.destroy()
+    feat, t, mask = torch.cat(feats, 1), torch.cat(ts, 1), torch.cat(masks, 1)
+    n_samples = int(feat.shape[1])
+    log(f"training data: {TRAIN_RUNS} runs, {n_samples} Gaussians")
     P = t.shape[0]
     trainer = B.MlpTrainer(B.mlp_init(P, seed=3), lr=3e-3)
     loss0, _ = trainer.step(feat, t, mask, lr=0.0)
-    n_steps = 300
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(n_steps):
+    for _ in range(TRAIN_STEPS):
         trainer.step(feat, t, mask)
     torch.cuda.synchronize()
-    train_ms = (time.perf_counter() - t0) * 1e3 / n_steps
+    train_ms = (time.perf_counter() - t0) * 1e3 / TRAIN_STEPS
     loss1, _ = trainer.step(feat, t, mask, lr=0.0)
     log(f"training: loss {loss0.item():.4f} -> {loss1.item():.4f}, {train_ms:.3f} ms per Adam step "
-        f"({feat.shape[1]} samples)")
-    tr["cache"].destroy()
-    del tr, feat, t, mask
+        f"({n_samples} samples)")
+    del feat, t, mask, feats, ts, masks
     torch.cuda.empty_cache()
-    return trainer, n_steps, train_ms, loss0, loss1
+    return trainer, dict(runs=TRAIN_RUNS, samples=n_samples, steps=TRAIN_STEPS, ms_per_step=round(train_ms, 3),
+                         loss_first=round(loss0.item(), 5), loss_last=round(loss1.item(), 5))
+
+
+# parameter groups (rows of x): mean, log-scale, quaternion, opacity, SH
+# degree-0 colour, SH degrees 1-3
+PARAM_GROUPS = (("mean", 0, 3), ("log_scale", 3, 6), ("quaternion", 6, 10), ("opacity", 10, 11),
+                ("sh_dc", 11, 14), ("sh_rest", 14, 59))
 
 
 def bench_learned(args, B, sg, torch) -> dict:
@@ -411,10 +438,11 @@ def bench_learned(args, B, sg, torch) -> dict:
     workload, one subset at full size (3M Gaussians, SH 3, 40 views
     1280x720, bfloat16 cache; the workload's four subsets would not leave
     room for the build transients).  The perceptron is trained on the GPU on
-    a separate scene of the same generator (other seed, 300k Gaussians, 8
-    views 1280x720); then, on the workload subset, Algorithm 1 runs to a
-    relative residual of 1e-2 with the Jacobi, the learned and the exact-target
-    scaling."""
+    20 seeded tiny SH-3 runs (train_learned_mlp); then, on the workload
+    subset, Algorithm 1 runs to a relative residual of 1e-2 with the Jacobi,
+    the learned and the exact-target scalings (shrink 1/2, unshrunk, and the
+    per-parameter means alone), with constant rescalings of each parameter
+    group, and with the block-Jacobi preconditioner."""
     cfg = dict(sg.CONFIGS["learned"])
     lam, floor, tol, max_it = float(cfg["lam"]), 1e-2, 1e-2, 200
     dev = torch.device("cuda:0")
@@ -436,7 +464,7 @@ def bench_learned(args, B, sg, torch) -> dict:
         del target
         return dict(scene=sc, x=x, cache=cache, b=b, M=M, build_ms=(t1 - t0) * 1e3)
 
-    trainer, n_steps, train_ms, loss0, loss1 = train_learned_mlp(args, B, torch, subset, cfg, lam, floor)
+    trainer, training = train_learned_mlp(args, B, sg, torch, lam, floor)
     P = sg.n_params(int(cfg["deg"]))
 
     V, W, H = cfg["subsets"][0]
@@ -451,22 +479,40 @@ def bench_learned(args, B, sg, torch) -> dict:
         _, scale, nf = B.lm_mlp_forward(trainer.w, f, P, want_s=False)
     torch.cuda.synchronize()
     pre_ms = (time.perf_counter() - t0) * 1e3 / args.steps
-    tt, mm = B.lm_precond_targets(ws["cache"], lam, floor)
-    exact = torch.where(mm > 0, torch.exp(tt), torch.ones_like(tt))
-    del tt, mm
-    res = {}
-    for name, sc_ in (("jacobi", None), ("learned", scale), ("exact_target", exact)):
-        B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE,
-                       scales=None if sc_ is None else [sc_], diag_floor=floor)
+    def exact_scale(shrink):
+        tt, mm = B.lm_precond_targets(ws["cache"], lam, floor, shrink=shrink)
+        out = torch.where(mm > 0, torch.exp(tt), torch.ones_like(tt))
+        del tt, mm
+        return out
+
+    def solve(sc_, timed=True):
+        kw = dict(scales=None if sc_ is None else [sc_], diag_floor=floor)
+        if timed:
+            B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE, **kw)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, st = B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE,
-                               scales=None if sc_ is None else [sc_], diag_floor=floor)
+        _, st = B.lm_pcg_solve([ws["cache"]], [ws["b"]], [ws["M"]], lam, max_it, tol, B.TOL_RELATIVE, **kw)
         torch.cuda.synchronize()
         ms = (time.perf_counter() - t0) * 1e3
-        res[name] = dict(iters=int(st[0]["iters"]), ms=round(ms, 2),
-                         rel_res=float(np.sqrt(st[0]["history"][-1])))
-        log(f"{name}: {res[name]['iters']} iterations, {ms:.1f} ms")
+        return dict(iters=int(st[0]["iters"]), ms=round(ms, 2), rel_res=float(np.sqrt(st[0]["history"][-1])))
+
+    res = {}
+    for name, mk in (("jacobi", lambda: None), ("learned", lambda: scale),
+                     ("exact_target", lambda: exact_scale(0.5)), ("exact_target_unshrunk", lambda: exact_scale(1.0)),
+                     ("exact_target_means_only", lambda: exact_scale(0.0))):
+        res[name] = solve(mk())
+        log(f"{name}: {res[name]['iters']} iterations, {res[name]['ms']:.1f} ms")
+    # constant rescalings of whole parameter groups against Jacobi (how far
+    # any per-parameter-type diagonal can move the iteration count)
+    groups = {}
+    for gname, g0, g1 in PARAM_GROUPS:
+        for f in (0.5, 2.0):
+            sc_ = torch.ones(P, int(cfg["N"]), device=dev)
+            sc_[g0:g1] = f
+            r = solve(sc_, timed=False)
+            groups[f"{gname}_x{f:g}"] = r["iters"]
+            del sc_
+    log(f"group rescalings (iterations; Jacobi {res['jacobi']['iters']}): {groups}")
     # block-Jacobi (exact per-Gaussian damped blocks): factorisation timed on
     # its own (a call that recomputes the factors and synchronises), then the
     # solve with the factors kept
@@ -504,11 +550,13 @@ def bench_learned(args, B, sg, torch) -> dict:
                                 f"{W}x{H} (of the workload's four), {args.cache_dtype} cache"),
                    "N": int(cfg["N"]), "views": V, "width": W, "height": H, "lambda": lam, "diag_floor": floor,
                    "tol_relative": tol},
-        "jacobi": j, "learned": l_, "exact_target": res["exact_target"], "block_jacobi": res["block_jacobi"],
+        "jacobi": j, "learned": l_, "exact_target": res["exact_target"],
+        "exact_target_unshrunk": res["exact_target_unshrunk"],
+        "exact_target_means_only": res["exact_target_means_only"], "group_rescalings_iters": groups,
+        "block_jacobi": res["block_jacobi"],
         "features_and_forward_ms": round(pre_ms, 3),
         "speedup_vs_jacobi": round(j["ms"] / (l_["ms"] + pre_ms), 3),
-        "training": {"samples": 300_000, "steps": n_steps, "ms_per_step": round(train_ms, 3),
-                     "loss_first": round(loss0.item(), 5), "loss_last": round(loss1.item(), 5)},
+        "training": training,
         "n_pairs": info["n_pairs"], "build_and_diag_ms": round(ws["build_ms"], 1),
         "n_fallback": int(nf.item()),
     }
@@ -536,19 +584,7 @@ def bench_deploy(args, B, sg, torch) -> dict:
     cfg = dict(sg.CONFIGS["learned"])
     lam, floor, tol, max_it = float(cfg["lam"]), 1e-2, 1e-2, 80
     dev = torch.device("cuda:0")
-
-    def subset(N, views, seed):
-        d = sg.config_scene("learned", N=N, subsets=[views], seed=seed)
-        sc, cams = d["scene"], d["cams"][0]
-        x = torch.from_numpy(sc.x).to(dev)
-        noise = torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev)
-        target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
-        target.add_(noise)
-        cache, b, _ = B.lm_build_cache(x, sc.sh_degree, cams, target, cache_dtype="bf16", compact=True)
-        M = B.lm_jacobi_diag(cache)
-        return dict(scene=sc, x=x, cache=cache, b=b, M=M)
-
-    trainer, n_steps, train_ms, loss0, loss1 = train_learned_mlp(args, B, torch, subset, cfg, lam, floor)
+    trainer, training = train_learned_mlp(args, B, sg, torch, lam, floor)
     if args.deploy_alloc == "torch":
         B.use_torch_allocator()
     log("workload: 3000000 Gaussians, 4 subsets of 40 views 1280x720")
@@ -605,44 +641,57 @@ def bench_deploy(args, B, sg, torch) -> dict:
         out = B.lm_combine_subsets(deltas, Ms)
         torch.cuda.synchronize()
         plain_h[0] = cache
+        mem_tables[tag] = dict(subset=cache.memory())
         return out, its, cache.info()["device_bytes"]
 
-    def full():
+    def full_form(dtype, grp, thin, handles, tag, mode):
+        """Compact caches held grp at a time (sharing the last handle as the
+        scratch of their build transients), the learned scaling, one batched
+        Algorithm 1 per group in PCG launch mode `mode`, then eq. combine-pcg."""
         deltas, Ms_all, its, mem = [], [], [], 0
-        handles = full_h
-        for g0 in range(0, 4, group):
+        B.lm_pcg_use_graph(mode)
+        for g0 in range(0, 4, grp):
             caches, bs, Ms, scales = [], [], [], []
             t0 = time.perf_counter()
-            for k, i in enumerate(range(g0, min(4, g0 + group))):
+            for k, i in enumerate(range(g0, min(4, g0 + grp))):
                 cache, b, _ = B.lm_build_cache(x, sc.sh_degree, d["cams"][i], targets[i], tile=tile,
-                                               cache_dtype="bf16", compact=True, cache=handles[k],
-                                               scratch=handles[group])
+                                               cache_dtype=dtype, compact=True, cache=handles[k],
+                                               scratch=handles[grp], thin_window=thin)
                 handles[k] = cache
                 M = B.lm_jacobi_diag(cache)
                 f = B.lm_precond_features(cache, x, M)
                 _, scale, _ = B.lm_mlp_forward(trainer.w, f, P, want_s=False)
+                cache.trim()                     # the Gram values: not read by PCG
                 caches.append(cache)
                 bs.append(b)
                 Ms.append(M)
                 scales.append(scale)
                 del f
-            t0 = mark("full_build_diag_scale", t0)
+            t0 = mark(f"{tag}_build_diag_scale", t0)
             dl, st = B.lm_pcg_solve(caches, bs, Ms, lam, max_it, tol, B.TOL_RELATIVE, scales=scales,
                                     diag_floor=floor)
-            mark("full_pcg", t0)
+            mark(f"{tag}_pcg", t0)
             deltas += dl
             Ms_all += Ms
             its += [int(s_["iters"]) for s_ in st]
             mem = max(mem, sum(c.info()["device_bytes"] for c in caches))
+            mem_tables[tag] = dict(subset=caches[0].memory(), scratch=handles[grp].memory())
             del bs, scales
+        B.lm_pcg_use_graph(2)
         out = B.lm_combine_subsets(deltas, Ms_all)
         torch.cuda.synchronize()
         return out, its, mem
 
+    thin_k = int(args.deploy_thin)
+    thin_h = [None] * 4 + [B.Cache()]
+    mem_tables = {}            # device bytes per buffer: one subset's cache (and the scratch handle)
+
     res = {}
-    forms = (("plain", lambda: sequential("f32", False, "plain")),
+    forms = [("plain", lambda: sequential("f32", False, "plain")),
              ("bf16_learned_sequential", lambda: sequential("bf16", True, "seq")),
-             ("full", full))
+             ("full", lambda: full_form("bf16", group, 0, full_h, "full", 2))]
+    if thin_k > 0:
+        forms.append(("full_thin", lambda: full_form("f32", 4, thin_k, thin_h, "thin", 3)))
     for name, fn in forms:
         fn()                                    # warm-up: allocations and code objects
         torch.cuda.empty_cache()
@@ -655,7 +704,7 @@ def bench_deploy(args, B, sg, torch) -> dict:
                          phases_ms={k: round(v, 1) for k, v in phases.items()})
         res[name]["delta"] = r[0]
         log(f"{name}: {ms:.1f} ms, PCG iterations {r[1]}, phases {res[name]['phases_ms']}")
-        hl = full_h if name == "full" else plain_h
+        hl = full_h if name == "full" else (thin_h if name == "full_thin" else plain_h)
         for k, h in enumerate(hl):
             if h is not None:
                 h.destroy()
@@ -663,9 +712,11 @@ def bench_deploy(args, B, sg, torch) -> dict:
         torch.cuda.empty_cache()
     dp, df = res["plain"].pop("delta"), res["full"].pop("delta")
     res["bf16_learned_sequential"].pop("delta")
+    dt = res["full_thin"].pop("delta") if "full_thin" in res else None
     if args.deploy_alloc == "torch":
         B.use_torch_allocator(False)
     diff = float(torch.linalg.vector_norm(df - dp) / torch.linalg.vector_norm(dp))
+    diff_thin = None if dt is None else float(torch.linalg.vector_norm(dt - dp) / torch.linalg.vector_norm(dp))
     return {
         "metric": "LM solve phase to relative residual 1e-2 in every subset: ms, full form vs plain",
         "value": res["full"]["ms"],
@@ -686,10 +737,14 @@ def bench_deploy(args, B, sg, torch) -> dict:
                    "diag_floor": floor, "tol_relative": tol, "tile": f"{tile[0]}x{tile[1]}", "group": group,
                    "allocator": args.deploy_alloc},
         "plain": res["plain"], "full": res["full"], "bf16_learned_sequential": res["bf16_learned_sequential"],
+        "full_thin": res.get("full_thin"),
         "speedup_full_vs_plain": round(res["plain"]["ms"] / res["full"]["ms"], 3),
+        "speedup_full_thin_vs_plain": (round(res["plain"]["ms"] / res["full_thin"]["ms"], 3)
+                                       if "full_thin" in res else None),
+        "device_memory_per_buffer": mem_tables,
         "combined_direction_rel_diff": diff,
-        "training": {"samples": 300_000, "steps": n_steps, "ms_per_step": round(train_ms, 3),
-                     "loss_first": round(loss0.item(), 5), "loss_last": round(loss1.item(), 5)},
+        "combined_direction_rel_diff_thin": diff_thin,
+        "training": training,
     }
 
 
@@ -707,6 +762,9 @@ def main() -> int:
     ap.add_argument("--cpu-baseline", type=int, default=1)
     ap.add_argument("--deploy-alloc", default="torch", choices=["hip", "torch"],
                     help="device memory of --config deploy: hipMalloc, or PyTorch's caching allocator")
+    ap.add_argument("--deploy-thin", type=int, default=32,
+                    help="--config deploy: also run the full form with thinned caches (this window; 0: not), "
+                         "all four subsets resident, persistent-kernel PCG")
     ap.add_argument("--deploy-group", type=int, default=2,
                     help="subsets held and solved together by the full form of --config deploy")
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "block"],

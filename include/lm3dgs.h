@@ -203,6 +203,26 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
 lm_status lm_cache_destroy(lm_cache* cache);
 lm_status lm_cache_get_info(const lm_cache* cache, lm_cache_info* info);
 
+/* Device memory held by each buffer of the cache, for sizing a set of
+ * resident caches: entry i gets the buffer's name (NUL-terminated) and the
+ * bytes it holds (0 for a buffer never allocated or released).  out (host,
+ * capacity entries, may be NULL when capacity is 0) receives the first
+ * min(capacity, *n) entries; *n (host) is set to the number of buffers. */
+typedef struct lm_buffer_bytes {
+    char name[24];
+    uint64_t bytes;
+} lm_buffer_bytes;
+lm_status lm_cache_memory(const lm_cache* cache, lm_buffer_bytes* out, int32_t capacity, int32_t* n);
+
+/* Synchronises the stream and frees what the products and lm_pcg_solve do
+ * not read: the per-(Gaussian, view) Gram values behind the diagonal, the
+ * learned-preconditioner inputs and the block-Jacobi factors, with their
+ * scratch.  A later call that needs them computes them again.  For caches
+ * held resident together (with LM_BUILD_COMPACT).  On a compact cache the
+ * per-(splat, tile) Gram values, reduced per (Gaussian, view) right after
+ * they are formed, are never kept. */
+lm_status lm_cache_trim(lm_cache* cache, void* stream);
+
 /* M = diag(J^T J) (paper eq. diag-jtj, kernel diagJTJ), dev float32 [P][N].
  * With residual weights set on the cache (lm_set_residual_weights,
  * lm_cache_objective) every product below uses J^T W J in place of J^T J
@@ -415,7 +435,9 @@ lm_status lm_block_jacobi(const lm_cache* cache, const int64_t* gaussians, int64
 
 /* Training targets of the learned preconditioner, dev float32 [P][N] each.
  * For parameter j of Gaussian k with d = (B_k)_jj > 0 and D = max(d,
- * diag_floor): r = log(D / (sum_i |(B_k)_ji| + lambda D)), the diagonal
+ * diag_floor), row j of B_k summed over the views in float64 (from the
+ * float32 per-(Gaussian, view) Gram values) and the target computed in
+ * float64: r = log(D / (sum_i |(B_k)_ji| + lambda D)), the diagonal
  * scaling that bounds the Gershgorin discs of the damped block
  * B_k + lambda diag(D), relative to Jacobi; then t = mu_j + shrink
  * (r - mu_j) with mu_j the mean of r over the observed Gaussians of

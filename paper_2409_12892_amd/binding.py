@@ -38,7 +38,8 @@ EXPORTED_SYMBOLS = (
     "lm_precond_targets", "lm_precond_features", "lm_mlp_forward", "lm_mlp_workspace_bytes", "lm_mlp_train_step",
     "lm_jp_sqnorm", "lm_set_allocator", "lm_objective_terms", "lm_set_residual_weights", "lm_cache_objective",
     "lm_objective_value", "lm_pcg_solve_block", "lm_block_precond_apply", "lm_ctx_create", "lm_ctx_destroy",
-    "lm_vec_dot", "lm_vec_axpy", "lm_vec_dot_static",
+    "lm_vec_dot", "lm_vec_axpy", "lm_vec_dot_static", "lm_cache_memory",
+    "lm_cache_trim",
 )
 
 # objective kinds (include/lm3dgs.h): plain least squares, and the paper's
@@ -50,6 +51,10 @@ MLP_FEATURES, MLP_HIDDEN, MLP_MAX_OUT, MLP_PARAMS = 8, 64, 64, 8896
 # offsets of the weight layout: W1 [8][64], b1, W2 [64][64], b2, W3 [64][64], b3
 MLP_OFFSETS = dict(W1=(0, (8, 64)), b1=(512, (64,)), W2=(576, (64, 64)), b2=(4672, (64,)),
                    W3=(4736, (64, 64)), b3=(8832, (64,)))
+
+
+class LmBufferBytes(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("bytes", ctypes.c_uint64)]
 
 
 class LmObjective(ctypes.Structure):
@@ -199,6 +204,19 @@ class Cache:
         inf = LmCacheInfo()
         _check(load().lm_cache_get_info(self.handle, byref(inf)), "lm_cache_get_info")
         return {f: getattr(inf, f) for f, _ in LmCacheInfo._fields_}
+
+    def memory(self) -> dict:
+        """Device bytes held per buffer (name -> bytes, nonzero entries)."""
+        lib = load()
+        n = c_int32(0)
+        _check(lib.lm_cache_memory(self.handle, None, 0, byref(n)), "lm_cache_memory")
+        out = (LmBufferBytes * n.value)()
+        _check(lib.lm_cache_memory(self.handle, out, n, byref(n)), "lm_cache_memory")
+        return {e.name.decode(): int(e.bytes) for e in out if e.bytes}
+
+    def trim(self):
+        """Free what the products and PCG do not read (recomputed on demand)."""
+        _check(load().lm_cache_trim(self.handle, _stream()), "lm_cache_trim")
 
     def export(self, what: str) -> np.ndarray:
         lib = load()

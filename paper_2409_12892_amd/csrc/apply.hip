@@ -225,10 +225,11 @@ __global__ void __launch_bounds__(kBlock) k_coverage(CacheView c, const float* _
 }
 
 
-// Row j of the block B_g = J_g^T J_g of Gaussian g into r (see k_block_rows).
-template <int DEG>
+// Row j of the block B_g = J_g^T J_g of Gaussian g into r (see k_block_rows),
+// the views' terms summed in the precision of R.
+template <int DEG, class R>
 __device__ __forceinline__ void block_row(const CacheView& c, const float* __restrict__ gvgram, int64_t g, int j,
-                                          float (&r)[11 + 3 * (DEG + 1) * (DEG + 1)]) {
+                                          R (&r)[11 + 3 * (DEG + 1) * (DEG + 1)]) {
     constexpr int K = (DEG + 1) * (DEG + 1);
     constexpr int P = 11 + 3 * K;
     const int64_t ls = c.lin_stride;
@@ -236,7 +237,7 @@ __device__ __forceinline__ void block_row(const CacheView& c, const float* __res
     const int jg = jgeo ? j : 0;                      // in-range index for the geometric loads
     const int jk = jgeo ? 0 : (j - 11) / 3, jch = jgeo ? -1 : (j - 11) % 3;
 #pragma unroll
-    for (int i = 0; i < P; ++i) r[i] = 0.0f;
+    for (int i = 0; i < P; ++i) r[i] = R(0);
     const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
     for (uint32_t gv = b; gv < e; ++gv) {
         const float* H = gvgram + (int64_t)gv * kGram;
@@ -274,13 +275,13 @@ __device__ __forceinline__ void block_row(const CacheView& c, const float* __res
 #pragma unroll
                 for (int ch = 0; ch < 3; ++ch) a += c.lin[(int64_t)(kLinJdir + 3 * ch + i) * ls + gv] * w[6 + ch];
             }
-            r[i] += a;
+            r[i] += R(a);
         }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const float wc = w[6 + ch] * c.lin[(int64_t)(kLinMask + ch) * ls + gv];
 #pragma unroll
-            for (int k = 0; k < K; ++k) r[11 + 3 * k + ch] += wc * c.lin[(int64_t)(kLinY + k) * ls + gv];
+            for (int k = 0; k < K; ++k) r[11 + 3 * k + ch] += R(wc * c.lin[(int64_t)(kLinY + k) * ls + gv]);
         }
     }
 }
@@ -293,9 +294,11 @@ __device__ __forceinline__ void block_row(const CacheView& c, const float* __res
 // rows of a Gaussian adjacent, so the view data is read once per wave.
 // OUT = 0 writes the dense rows of the selected Gaussians ([n_sel][P][P];
 // without a selection, of the Gaussians g0, g0 + 1, ...);
-// OUT = 1 writes the preconditioner target of the row: with d = B_jj,
-// D = max(d, floor) and the damped block B + lambda diag(D), the row-sum
-// scaling t = log(D / (sum_i |B_ji| + lambda D)) and the observed flag d > 0.
+// OUT = 1 writes the preconditioner target of the row (relative to the
+// Jacobi inverse 1/D), the row summed over views in float64: with d = B_jj,
+// D = max(d, floor) and the damped block A = B + lambda diag(D), the row-sum
+// scaling that bounds the Gershgorin disc of the row,
+// t = log(D / sum_i |A_ji|), and the observed flag d > 0.
 template <int DEG, int OUT>
 __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float* __restrict__ gvgram,
                                                       const int64_t* __restrict__ sel, int64_t g0, int64_t n_rows,
@@ -308,22 +311,25 @@ __global__ void __launch_bounds__(kBlock) k_block_rows(CacheView c, const float*
     const int64_t s = t / P;
     const int j = (int)(t - s * P);
     const int64_t g = sel ? sel[s] : g0 + s;
-    float r[P];
-    block_row<DEG>(c, gvgram, g, j, r);
-    if (OUT == 0) {
+    if constexpr (OUT == 0) {
+        float r[P];
+        block_row<DEG>(c, gvgram, g, j, r);
         float* row = o0 + (s * P + j) * P;
 #pragma unroll
         for (int i = 0; i < P; ++i) row[i] = r[i];
     } else {
-        float d = 0.0f, sum = 0.0f;
+        double r[P];
+        block_row<DEG>(c, gvgram, g, j, r);
+        double d = 0.0;
 #pragma unroll
-        for (int i = 0; i < P; ++i) {
-            d = i == j ? r[i] : d;
-            sum += fabsf(r[i]);
-        }
-        const bool obs = d > 0.0f;
-        const float D = fmaxf(d, floor_);
-        o0[(int64_t)j * c.N + g] = obs ? logf(D / (sum + lam * D)) : 0.0f;
+        for (int i = 0; i < P; ++i) d = i == j ? r[i] : d;
+        const bool obs = d > 0.0;
+        const double D = fmax(d, (double)floor_);
+        const double ajj = d + (double)lam * D;
+        double sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < P; ++i) sum += fabs(i == j ? ajj : r[i]);
+        o0[(int64_t)j * c.N + g] = obs ? (float)log(D / sum) : 0.0f;
         o1[(int64_t)j * c.N + g] = obs ? 1.0f : 0.0f;
     }
 }

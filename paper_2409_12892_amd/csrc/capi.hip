@@ -165,6 +165,25 @@ inline int64_t round_up(int64_t n, int64_t m) { return (n + m - 1) / m * m; }
 
 using lm::DevBuf;
 
+// Every device buffer of a cache (one list for declaration, size report and
+// release).
+#define LM_CACHE_BUFFERS(X) \
+    X(cams) X(tile_view) X(x) X(rec64) X(recf) X(rad) \
+    X(keycnt) X(keyoff) X(keys) X(vals) X(keys_alt) X(vals_alt) \
+    X(sort_tmp) X(scan_tmp) X(rkeys) X(rvals) X(rkeys_alt) X(rvals_alt) \
+    X(cnt_sorted) X(kept_blk) X(kept_off) X(kept_mask) X(tile_start) X(entry_cnt) \
+    X(pixC) X(ncontrib) X(resid) X(fsq_part) X(tile_pairs) X(tile_segs) \
+    X(tile_pair_off) X(tile_seg_off) X(tile_real) X(tile_real_off) X(run_seg) X(gv_cnt) \
+    X(gv_flag) X(gv_idx) X(gv_segoff) X(gv_rec) X(gv_seg_off) X(gv_first) \
+    X(gv_cursor) X(gv_segs) X(seg_pos) X(list_gv) X(pT) X(pD) \
+    X(ppix) X(seg_gv) X(tile_blk) X(seg_f) X(dyc) X(gmom) \
+    X(jp_part) X(gram) X(pg_part) X(scalar) X(lin) X(gvsum) \
+    X(gvchain) X(edge_m) X(ekey_m) X(gvgram) X(edge_g) X(ekey_g) \
+    X(coverage) X(feat_red) X(tgt_red) X(wres) X(obj_e) X(obj_part) \
+    X(bj_L) X(bj_count) X(tile_ck) X(tile_ck_off) X(pix_ck) X(ck) \
+    X(piece_seg) X(piece_mask) X(piece_cmask) X(pcg_r) X(pcg_z) X(pcg_p) \
+    X(pcg_g) X(pcg_part) X(pcg_state)
+
 struct lm_cache {
     lm_ctx* ctx = nullptr;       // the context of its last build (NULL before)
     int64_t N = 0;
@@ -177,25 +196,14 @@ struct lm_cache {
     bool built = false;
     std::vector<lm::CamDev> cams_h;
     std::vector<int> viewW, viewH;
-    DevBuf cams, tile_view, x;
-    DevBuf rec64, recf, rad, keycnt, keyoff;
-    DevBuf keys, vals, keys_alt, vals_alt, sort_tmp, scan_tmp;
-    DevBuf rkeys, rvals, rkeys_alt, rvals_alt, cnt_sorted, kept_blk, kept_off, kept_mask;
-    DevBuf tile_start, entry_cnt, pixC, ncontrib, resid, fsq_part, tile_pairs, tile_segs, tile_pair_off, tile_seg_off;
-    DevBuf tile_real, tile_real_off, run_seg;
-    DevBuf gv_cnt, gv_flag, gv_idx, gv_segoff, gv_rec, gv_seg_off, gv_first, gv_cursor, gv_segs, seg_pos, list_gv;
-    DevBuf pT, pD, ppix, seg_gv, tile_blk, seg_f;
-    DevBuf dyc, gmom, jp_part, gram, pg_part, scalar, lin;
-    DevBuf gvsum, gvchain, edge_m, ekey_m, gvgram, edge_g, ekey_g, coverage, feat_red, tgt_red;
-    DevBuf wres, obj_e, obj_part;
-    DevBuf bj_L, bj_count;
-    DevBuf tile_ck, tile_ck_off, pix_ck, ck, piece_seg, piece_mask, piece_cmask;
+#define LM_DECLARE_BUF(n) DevBuf n;
+    LM_CACHE_BUFFERS(LM_DECLARE_BUF)
+#undef LM_DECLARE_BUF
     bool weighted = false;       // wres holds residual weights for the products
     bool bj_valid = false;       // bj_L holds the block-Jacobi factors for (bj_lambda, bj_floor)
     float bj_lambda = 0.0f, bj_floor = 0.0f;
     bool gram_valid = false;     // gvgram holds the Gram values of the current build
     bool compact = false;        // the build-only buffers were released (LM_BUILD_COMPACT)
-    DevBuf pcg_r, pcg_z, pcg_p, pcg_g, pcg_part, pcg_state;
 
     const uint32_t* sorted_vals() const { return vals_in_alt ? vals_alt.as<uint32_t>() : vals.as<uint32_t>(); }
 
@@ -244,20 +252,18 @@ struct lm_cache {
     }
 
     size_t device_bytes() const {
-        const DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
-                               &rkeys_alt, &rvals_alt, &cnt_sorted, &kept_blk, &kept_off, &kept_mask,
-                               &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
-                               &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
-                               &run_seg, &gv_cnt, &gv_flag,
-                               &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
-                               &ppix, &seg_gv, &tile_blk, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
-                               &wres, &obj_e, &obj_part, &bj_L, &bj_count,
-                               &tile_ck, &tile_ck_off, &pix_ck, &ck, &piece_seg, &piece_mask, &piece_cmask,
-                               &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
         size_t s = 0;
-        for (auto* b : all) s += b->cap;
+#define LM_ADD_BUF(n) s += n.cap;
+        LM_CACHE_BUFFERS(LM_ADD_BUF)
+#undef LM_ADD_BUF
         return s;
+    }
+    // name and bytes held of each buffer, in declaration order
+    template <class F>
+    void each_buffer(F&& f) const {
+#define LM_EACH_BUF(n) f(#n, n.cap);
+        LM_CACHE_BUFFERS(LM_EACH_BUF)
+#undef LM_EACH_BUF
     }
 
     // buffers read only while building (see LM_BUILD_COMPACT)
@@ -288,18 +294,9 @@ struct lm_cache {
     }
 
     void release_all() {
-        DevBuf* all[] = {&cams, &tile_view, &x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &rkeys, &rvals,
-                               &rkeys_alt, &rvals_alt, &cnt_sorted, &kept_blk, &kept_off, &kept_mask,
-                         &vals_alt, &sort_tmp, &scan_tmp, &tile_start, &entry_cnt, &pixC, &ncontrib, &resid,
-                         &fsq_part, &tile_pairs, &tile_segs, &tile_pair_off, &tile_seg_off, &tile_real, &tile_real_off,
-                               &run_seg, &gv_cnt, &gv_flag,
-                         &gv_idx, &gv_segoff, &gv_rec, &gv_seg_off, &gv_first, &gv_cursor, &gv_segs, &seg_pos, &list_gv, &pT, &pD,
-                         &ppix, &seg_gv, &tile_blk, &seg_f, &dyc, &gmom, &jp_part, &gram, &pg_part, &scalar, &lin,
-                               &gvsum, &gvchain, &edge_m, &ekey_m, &gvgram, &edge_g, &ekey_g, &coverage, &feat_red, &tgt_red,
-                               &wres, &obj_e, &obj_part, &bj_L, &bj_count,
-                         &tile_ck, &tile_ck_off, &pix_ck, &ck, &piece_seg, &piece_mask, &piece_cmask,
-                         &pcg_r, &pcg_z, &pcg_p, &pcg_g, &pcg_part, &pcg_state};
-        for (auto* b : all) b->release();
+#define LM_RELEASE_BUF(n) n.release();
+        LM_CACHE_BUFFERS(LM_RELEASE_BUF)
+#undef LM_RELEASE_BUF
     }
 };
 
@@ -956,6 +953,21 @@ lm_status lm_cache_get_info(const lm_cache* c, lm_cache_info* info) {
     return LM_OK;
 }
 
+lm_status lm_cache_memory(const lm_cache* c, lm_buffer_bytes* out, int32_t capacity, int32_t* n) {
+    LM_CHECK(c && n && capacity >= 0 && (out || capacity == 0), LM_ERR_INVALID_ARG, "lm_cache_memory: bad argument");
+    int32_t i = 0;
+    c->each_buffer([&](const char* name, size_t bytes) {
+        if (i < capacity) {
+            memset(out[i].name, 0, sizeof(out[i].name));
+            strncpy(out[i].name, name, sizeof(out[i].name) - 1);
+            out[i].bytes = bytes;
+        }
+        ++i;
+    });
+    *n = i;
+    return LM_OK;
+}
+
 // The per-(Gaussian, view) Gram values of the current build, computed on
 // first use; every quantity derived from J^T J per Gaussian reads them.
 static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
@@ -970,6 +982,25 @@ static lm_status ensure_gram(lm_cache* cm, hipStream_t s) {
     LM_HIP(lm::launch_gram(cm->view(), cm->gram.as<float>(), cm->gvgram.as<float>(), cm->edge_g.as<float>(),
                            cm->ekey_g.as<uint32_t>(), s));
     cm->gram_valid = true;
+    if (cm->compact) {
+        // per-(splat, tile) values: transients of the reduction
+        LM_HIP(hipStreamSynchronize(s));
+        cm->gram.release();
+        cm->edge_g.release();
+        cm->ekey_g.release();
+    }
+    return LM_OK;
+}
+
+lm_status lm_cache_trim(lm_cache* c, void* stream) {
+    lm::StreamScope lm_stream_scope_(S(stream), c ? c->ctx : nullptr);
+    LM_CHECK(c, LM_ERR_INVALID_ARG, "lm_cache_trim: NULL argument");
+    LM_HIP(hipStreamSynchronize(S(stream)));
+    DevBuf* derived[] = {&c->gram, &c->gvgram, &c->edge_g, &c->ekey_g, &c->coverage, &c->feat_red, &c->tgt_red,
+                         &c->bj_L, &c->bj_count};
+    for (DevBuf* b : derived) b->release();
+    c->gram_valid = false;
+    c->bj_valid = false;
     return LM_OK;
 }
 

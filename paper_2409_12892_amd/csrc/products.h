@@ -180,6 +180,14 @@ struct TilePlanes {
         if constexpr (sizeof(W) == 4) return __builtin_amdgcn_raw_buffer_load_b32(r, q * 4, 0, 0);
         else return __builtin_amdgcn_raw_buffer_load_b16(r, q * 2, 0, 0);
     }
+    // aligned run r of the tile when `want`; otherwise a run index past
+    // every tile (the buffer range check returns zeros without a memory
+    // access) and a segment word no chunk holds.  Straight-line, so the
+    // run stays in registers.
+    __device__ __forceinline__ void run_if(int r, RunLoad<DT>& L, bool want) const {
+        run(want ? r : (1 << 24), L);
+        L.seg = want ? L.seg : 0xFFFFFFFFu;
+    }
     // aligned run r of the tile (eight pairs per lane)
     __device__ __forceinline__ void run(int r, RunLoad<DT>& L) const {
         L.seg = __builtin_amdgcn_raw_buffer_load_b32(seg, r * 4, 0, 0);
@@ -202,27 +210,86 @@ struct TilePlanes {
     }
 };
 
-// Tile pass.  One workgroup of 512 threads per tile.  The tile's pairs are
-// stored block after block (a block is the 64 pixels of one raster wave),
-// so after a block's pairs every one of its pixels has its complete
-// u = J p.  In the fused J^T J pass each lane loads up to kHeld<DT> runs of
-// the block into registers, adds their J rows into per-wave LDS
-// accumulators (ds_add; a run's eight pixels are distinct), the waves'
-// accumulators are summed into u, and the J^T half takes its moments from
-// the same registers: each pair is read from HBM once.  Runs past the
-// register capacity are streamed in each half.  Segment moments gather in
-// LDS across the tile's blocks and are written once per segment.
-//   A tile with more segments than LDS stages at once (kSegCap) runs
-// segment chunk after chunk: J over every chunk's runs (each block's runs
-// of a chunk are found by binary search: a block lists its pieces in depth
-// order) completes u for the tile, then J^T streams the runs again.
+// Tile pass.  One workgroup of 512 threads (8 waves) per tile.  The tile's
+// pairs are stored block after block (a block is the 64 pixels of one
+// raster wave), so after a block's pairs every one of its pixels has its
+// complete u = J p.  A block's pairs are taken in chunks of 512 pairs (a
+// window of the fill's placement rule: no piece crosses one), chunk c by
+// wave c mod 8, so every piece of a chunk lies in one wave:
+//   J  : the wave holds the chunk as 8 windows of 64 consecutive pairs, one
+//        pair per lane (coalesced loads); per window the J rows of the
+//        lanes' pairs, and the window's pieces (a contiguous lane range
+//        each, distinct pixels within a piece) add into the wave's
+//        per-pixel accumulators one after another with plain LDS
+//        read-modify-writes; the waves' accumulators are added in wave
+//        order into u;
+//   J^T: the wave reads the chunk again as 64 runs of 8 pairs, one per lane
+//        (a run belongs to one piece); each lane sums the 9 moments of its
+//        run, one segmented scan over the wave (keyed by segment) leaves
+//        each piece's sum in its last lane, which adds it into the
+//        segment's moments (a segment has one piece per block, in one
+//        chunk; blocks in order).
+// No LDS atomics, and every sum runs in a fixed order.  The J^T read of a
+// block follows its J read within microseconds (an L2 hit); each wave
+// issues its first chunk of the next block before the current block's
+// barriers and J^T half, so the loads overlap the other work.  A tile with
+// more segments than LDS stages at once (kSegCap) runs segment chunk after
+// segment chunk (J over all, then J^T).
 constexpr int kTileThreads = 512;
 constexpr int kTileWaves = kTileThreads / kWave;
-constexpr int kSegCap = 640;
+constexpr int kSegCap = 512;
+constexpr int kChunkRuns = kWave;                 // runs of a chunk (one per lane in J^T)
+static_assert(kChunkRuns * kRun == kWindow, "a chunk is one placement window");
+constexpr int kChunkWins = kWindow / kWave;       // 64-pair windows of a chunk (J)
+
+// One chunk in pair order: window j's word of lane l is pair 64 j + l;
+// 16-bit words two per register, pixel bytes four per register, and the
+// segments of the chunk's 64 runs one per lane (run l in lane l).
 template <int DT>
-struct Held {
-    static constexpr int R = sizeof(typename Store<DT>::word) == 4 ? 2 : 3;   // runs held per lane
+struct PairChunk {
+    using S = Store<DT>;
+    using W = typename S::word;
+    static constexpr int NR = sizeof(W) == 4 ? kChunkWins : kChunkWins / 2;   // registers per plane
+    uint32_t tw[NR];
+    uint32_t dw[3][NR];
+    uint32_t pw[kChunkWins / 4];
+    uint32_t rseg;
+    __device__ __forceinline__ W word(const uint32_t* p, int j) const {
+        if constexpr (sizeof(W) == 4) return p[j];
+        else return (W)((p[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
+    }
+    __device__ __forceinline__ W t(int j) const { return word(tw, j); }
+    __device__ __forceinline__ W d(int ch, int j) const { return word(dw[ch], j); }
+    __device__ __forceinline__ int pix(int j) const { return (int)((pw[j >> 2] >> (8 * (j & 3))) & 0xFFu); }
 };
+
+// chunk of tile-relative first pair q0 in pair order (q0 = 1 << 28 reads
+// past every tile: zeros, no memory access)
+template <int DT>
+__device__ __forceinline__ void load_pair_chunk(const TilePlanes<DT>& P, int q0, int lane, PairChunk<DT>& L) {
+    using W = typename Store<DT>::word;
+    const __amdgpu_buffer_rsrc_t pr[4] = {P.t, P.d0, P.d1, P.d2};
+#pragma unroll
+    for (int pl = 0; pl < 4; ++pl) {
+        uint32_t* dst = pl == 0 ? L.tw : L.dw[pl - 1];
+#pragma unroll
+        for (int j = 0; j < kChunkWins; ++j) {
+            const int q = q0 + kWave * j + lane;
+            if constexpr (sizeof(W) == 4) {
+                dst[j] = __builtin_amdgcn_raw_buffer_load_b32(pr[pl], q * 4, 0, 0);
+            } else {
+                const uint32_t h = __builtin_amdgcn_raw_buffer_load_b16(pr[pl], q * 2, 0, 0);
+                dst[j >> 1] = (j & 1) ? (dst[j >> 1] | (h << 16)) : h;
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < kChunkWins; ++j) {
+        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(P.pix, q0 + kWave * j + lane, 0, 0);
+        L.pw[j >> 2] = (j & 3) ? (L.pw[j >> 2] | (b << (8 * (j & 3)))) : b;
+    }
+    L.rseg = __builtin_amdgcn_raw_buffer_load_b32(P.seg, ((q0 / kRun) + lane) * 4, 0, 0);
+}
 
 // gt: the tile's index over the batch (the subsets' tiles one after another)
 template <int MODE, int DT>
@@ -233,18 +300,19 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
     if (a.stop && *a.stop) return;
     using S = Store<DT>;
     constexpr int NW = kTileWaves;
-    constexpr int R = MODE == MODE_JTJ ? Held<DT>::R : 0;
-    constexpr int kZero = kMaxTilePix;           // u slot that stays 0 (read by padding)
     constexpr int kNoSeg = kSegCap;              // segment key of a lane without a run
+    constexpr int kFar = 1 << 28;                // pair offset past every tile
     const CacheView& c = a.c;
     __shared__ float4 s_sg[kSegCap][4];   // mx', my', A', B' | C', o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
     __shared__ float s_mom[9][kSegCap];
-    __shared__ float4 s_uw[NW][kBlockPix];      // per-wave J accumulators of one block
-    __shared__ float4 s_ut[kMaxTilePix + 1];   // u of the tile (weighted once complete)
+    __shared__ float s_uw[3][NW][kBlockPix];    // per-wave J accumulators of one block, per channel
+    __shared__ float4 s_ut[kMaxTilePix];        // u of the tile (weighted once complete)
     __shared__ double s_red[NW];
+    __shared__ int br[kTileBlocks + 1];         // tile-relative first run of each block
 
     const int64_t t = gt - Bt.tile_off[bi];
-    const int tid = threadIdx.x, lane = __lane_id(), wid = tid / kWave;
+    const int tid = threadIdx.x, lane = __lane_id();
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
     const int v = c.tile_view[t];
     const CamDev& cam = c.cams[v];
     const int64_t lt = t - cam.tile_base;
@@ -259,11 +327,11 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
     const TilePlanes<DT> P(c, pb, pe);
-    int brun[kTileBlocks + 1];                   // tile-relative runs of each block
-    brun[0] = 0;
+    if (tid == 0) {
+        br[0] = 0;
 #pragma unroll
-    for (int b = 0; b < kTileBlocks; ++b) brun[b + 1] = brun[b] + (int)(c.tile_blk[t * kTileBlocks + b] / kRun);
-    const uint32_t* rseg = c.run_seg + pb / kRun;
+        for (int b = 0; b < kTileBlocks; ++b) br[b + 1] = br[b] + (int)c.tile_blk[t * kTileBlocks + b] / kRun;
+    }
 
     // tile pixel of pixel i of block b, and a tile pixel's index in its block
     auto blk_pixel = [&](int b, int i) -> int {
@@ -276,17 +344,9 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
     auto img_index = [&](int pl) -> int64_t {
         return 3 * cam.pix_base + (int64_t)(ty * c.TH + (pl >> tw_shift)) * cam.W + tx * c.TW + (pl & tw_mask);
     };
-    // first run in [r0, r1) whose segment is >= key (runs ascend by segment within a block)
-    auto lower = [&](int r0, int r1, uint32_t key) -> int {
-        while (r0 < r1) {
-            const int m = (r0 + r1) >> 1;
-            if (rseg[m] < key) r0 = m + 1; else r1 = m;
-        }
-        return r0;
-    };
 
-    for (int i = tid; i <= kMaxTilePix; i += kTileThreads) s_ut[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int i = tid; i < NW * kBlockPix; i += kTileThreads) (&s_uw[0][0])[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i < kMaxTilePix; i += kTileThreads) s_ut[i] = make_float4(0.f, 0.f, 0.f, 0.f);
+    for (int i = tid; i < 3 * NW * kBlockPix; i += kTileThreads) (&s_uw[0][0][0])[i] = 0.0f;
     __syncthreads();
     if (MODE == MODE_JT && tid < npix && pix_valid(tid)) {
         const int64_t ib = img_index(tid);
@@ -316,46 +376,77 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
 #pragma unroll
             for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
     };
-    // staged index of a run's segment (kNoSeg: no run, or not in the chunk)
-    auto staged = [&](const RunLoad<DT>& L, bool has, int64_t s0, int cn) -> int {
-        const int64_t sl = (int64_t)L.seg - s0;
-        return (has && sl >= 0 && sl < cn) ? (int)sl : kNoSeg;
+    // first pair of chunk ch of block b (kFar when the wave has no such chunk)
+    auto chunk_q0 = [&](int b, int ch) -> int {
+        const int r = br[b] + ch * kChunkRuns;
+        return r < br[b + 1] ? r * kRun : kFar;
     };
 
-    // J rows of one run into this wave's accumulators
-    auto j_run = [&](const RunLoad<DT>& L, int s) {
-        if (s == kNoSeg) return;
-        const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
-        float4* up = s_uw[wid];
+    // J rows of one chunk (first pair q0, the block's pairs end at qe;
+    // segments [s0, s0 + cn) staged) into this wave's accumulators
+    auto j_chunk = [&](const PairChunk<DT>& L, int q0, int qe, int64_t s0, int cn) {
+        float* u0 = s_uw[0][wid];
+        float* u1 = s_uw[1][wid];
+        float* u2 = s_uw[2][wid];
 #pragma unroll
-        for (int k = 0; k < kRun; ++k) {
-            if (L.t(k) == 0) continue;                  // padding
-            const float T = S::dec_T(L.t(k));
-            const bool clamped = S::clamp(L.t(k));
-            const int pl = L.pix(k);
-            const float dx = (float)(pl & tw_mask) - g0.x;
-            const float dy = (float)(pl >> tw_shift) - g0.y;
-            const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
-            const float alpha = clamped ? 0.99f : g1.y * G;
-            const float aT = alpha * T;
-            const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
-            const float dal = clamped ? 0.0f : dal_f;
-            const int li = local_of(pl);
-            atomicAdd(&up[li].x, S::dec(L.d(0, k)) * dal + aT * g3.x);
-            atomicAdd(&up[li].y, S::dec(L.d(1, k)) * dal + aT * g3.y);
-            atomicAdd(&up[li].z, S::dec(L.d(2, k)) * dal + aT * g3.z);
+        for (int j = 0; j < kChunkWins; ++j) {
+            const uint32_t sg = (uint32_t)__shfl((int)L.rseg, (kWave / kRun) * j + (lane >> 3), kWave);
+            const int64_t sl = (int64_t)sg - s0;
+            const bool live = q0 + kWave * j + lane < qe && L.t(j) != 0 && sl >= 0 && sl < cn;
+            float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
+            const int pl = L.pix(j);
+            if (live) {
+                const int s = (int)sl;
+                const float4 g0 = s_sg[s][0], g1 = s_sg[s][1], g2 = s_sg[s][2], g3 = s_sg[s][3];
+                const float T = S::dec_T(L.t(j));
+                const bool clamped = S::clamp(L.t(j));
+                const float dx = (float)(pl & tw_mask) - g0.x;
+                const float dy = (float)(pl >> tw_shift) - g0.y;
+                const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
+                const float alpha = clamped ? 0.99f : g1.y * G;
+                const float aT = alpha * T;
+                const float dal_f = alpha * (dx * (g1.z + g2.x * dx + g2.y * dy) + dy * (g1.w + g2.z * dy)) + G * g2.w;
+                const float dal = clamped ? 0.0f : dal_f;
+                v0 = S::dec(L.d(0, j)) * dal + aT * g3.x;
+                v1 = S::dec(L.d(1, j)) * dal + aT * g3.y;
+                v2 = S::dec(L.d(2, j)) * dal + aT * g3.z;
+            }
+            // the window's pieces one after another (pixels are distinct
+            // within a piece)
+            uint64_t todo = __ballot(live);
+            while (todo) {
+                const int first = __ffsll((unsigned long long)todo) - 1;
+                const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)sg, first);
+                const bool mine = live && sg == sk;
+                todo &= ~__ballot(mine);
+                if (mine) {
+                    const int li = local_of(pl);
+                    u0[li] += v0;
+                    u1[li] += v1;
+                    u2[li] += v2;
+                }
+            }
         }
     };
-    // J^T moments of one run per lane, reduced over the wave's lanes by
-    // segment (runs ascend with the lane) and added into the segment sums
-    auto jt_round = [&](const RunLoad<DT>& L, int s) {
+    // J^T moments of one chunk (lane: one run, segments [s0, s0 + cn)
+    // staged): per lane the sums over its run, a segmented scan over the
+    // wave, one plain addition per piece with pairs (a gap run carries the
+    // next piece's segment and no pair: a group of gap runs adds nothing)
+    auto jt_chunk = [&](const RunLoad<DT>& L, int64_t s0, int cn) {
+        const int64_t sl = (int64_t)L.seg - s0;
+        const bool in = sl >= 0 && sl < cn;
+        const int key = in ? (int)sl : kNoSeg;
         float m[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) m[k] = 0.0f;
-        if (s != kNoSeg) {
+        bool any = false;
+        {
+            const int s = in ? key : 0;
             const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
 #pragma unroll
             for (int k = 0; k < kRun; ++k) {
+                const bool live = in && L.t(k) != 0;
+                any = any || live;
                 const float T = S::dec_T(L.t(k));
                 const bool clamped = S::clamp(L.t(k));
                 const int pl = L.pix(k);
@@ -363,64 +454,50 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 const float dy = (float)(pl >> tw_shift) - g0.y;
                 const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
                 const float alpha = clamped ? 0.99f : g1.y * G;
-                const float aT = alpha * T;                               // 0 for padding
-                const float4 u = s_ut[L.t(k) != 0 ? pl : kZero];         // padding reads u = 0
+                const float aT = live ? alpha * T : 0.0f;
+                const float4 u = s_ut[pl];
                 const float w = S::dec(L.d(0, k)) * u.x + S::dec(L.d(1, k)) * u.y + S::dec(L.d(2, k)) * u.z;
-                const float aw = clamped ? 0.0f : alpha * w;
+                const bool off = clamped || !live;
+                const float aw = off ? 0.0f : alpha * w;
                 const float awx = aw * dx, awy = aw * dy;
                 m[0] += awx;
                 m[1] += awy;
                 m[2] += awx * dx;
                 m[3] += awx * dy;
                 m[4] += awy * dy;
-                m[5] += clamped ? 0.0f : G * w;
+                m[5] += off ? 0.0f : G * w;
                 m[6] += aT * u.x;
                 m[7] += aT * u.y;
                 m[8] += aT * u.z;
             }
         }
-        const int next = __shfl_down(s, 1, kWave);
-        wave_segmented_scan<9>(m, lane, segment_head((uint32_t)s, lane));
-        if (s != kNoSeg && (lane == kWave - 1 || next != s)) {
+        const uint64_t lives = __ballot(any);
+        const int next = __shfl_down(key, 1, kWave);
+        const int head = segment_head((uint32_t)key, lane);
+        wave_segmented_scan<9>(m, lane, head);
+        const uint64_t grp = ((2ull << lane) - 1ull) & ~((1ull << head) - 1ull);
+        if (key != kNoSeg && (lane == kWave - 1 || next != key) && (lives & grp) != 0ull) {
 #pragma unroll
-            for (int k = 0; k < 9; ++k) atomicAdd(&s_mom[k][s], m[k]);
+            for (int k = 0; k < 9; ++k) s_mom[k][key] += m[k];
         }
     };
-    // runs [r0, r1) streamed, 512 per round, the next round loading
-    auto stream_j = [&](int r0, int r1, int64_t s0, int cn) {
-        if (r0 >= r1) return;
-        RunLoad<DT> nxt;
-        P.run(r0 + tid, nxt);
-        for (int base = r0; base < r1; base += kTileThreads) {
-            const RunLoad<DT> L = nxt;
-            const bool has = base + tid < r1;
-            if (base + kTileThreads < r1) P.run(base + kTileThreads + tid, nxt);
-            j_run(L, staged(L, has, s0, cn));
-        }
+    // the block's runs in a lane: run r when it lies in block b
+    auto load_run_chunk = [&](int b, int ch, RunLoad<DT>& L) {
+        const int r = br[b] + ch * kChunkRuns + lane;
+        P.run_if(r, L, r < br[b + 1]);
     };
-    auto stream_jt = [&](int r0, int r1, int64_t s0, int cn) {
-        if (r0 >= r1) return;
-        RunLoad<DT> nxt;
-        P.run(r0 + tid, nxt);
-        for (int base = r0; base < r1; base += kTileThreads) {
-            const RunLoad<DT> L = nxt;
-            const bool has = base + tid < r1;
-            if (base + kTileThreads < r1) P.run(base + kTileThreads + tid, nxt);
-            jt_round(L, staged(L, has, s0, cn));
-        }
-    };
+    auto nchunks = [&](int b) { return (br[b + 1] - br[b] + kChunkRuns - 1) / kChunkRuns; };
     // the waves' accumulators of block b added into u (and cleared)
     auto gather_u = [&](int b) {
         if (tid < kBlockPix) {
-            float4 u = s_uw[0][tid];
-            s_uw[0][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
+            float4 u = make_float4(s_uw[0][0][tid], s_uw[1][0][tid], s_uw[2][0][tid], 0.0f);
+            s_uw[0][0][tid] = s_uw[1][0][tid] = s_uw[2][0][tid] = 0.0f;
 #pragma unroll
             for (int w = 1; w < NW; ++w) {
-                const float4 o = s_uw[w][tid];
-                s_uw[w][tid] = make_float4(0.f, 0.f, 0.f, 0.f);
-                u.x += o.x;
-                u.y += o.y;
-                u.z += o.z;
+                u.x += s_uw[0][w][tid];
+                u.y += s_uw[1][w][tid];
+                u.z += s_uw[2][w][tid];
+                s_uw[0][w][tid] = s_uw[1][w][tid] = s_uw[2][w][tid] = 0.0f;
             }
             const int pl = blk_pixel(b, tid);
             if (pl < npix) {
@@ -470,27 +547,26 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         stage(0, nseg, (MODE & MODE_J) != 0);
         if (MODE & MODE_JT) zero_mom(nseg);
         __syncthreads();
+        // first chunk of this wave in block 0 (J: pair order; J^T only: runs)
+        PairChunk<DT> pj;
+        RunLoad<DT> rj;
+        if (MODE & MODE_J) load_pair_chunk(P, chunk_q0(0, wid), lane, pj);
+        else load_run_chunk(0, wid, rj);
         for (int b = 0; b < nblk; ++b) {
-            const int r0 = brun[b], r1 = brun[b + 1];
-            if (r0 == r1) {              // no pair: u = 0 (written out by the J product)
-                if (MODE == MODE_J) finish_u(b);
-                continue;
-            }
-            const int rh = R > 0 ? min(r1, r0 + R * kTileThreads) : r0;   // runs held in registers
-            RunLoad<DT> held[R > 0 ? R : 1];
-            int hs[R > 0 ? R : 1];
+            const int nch = nchunks(b);
+            const int qe = br[b + 1] * kRun;
             if (MODE & MODE_J) {
-                // runs past the register capacity first (streamed), so that
-                // the held runs and the stream's buffers are never live together
-                stream_j(rh, r1, sb, nseg);
-#pragma unroll
-                for (int k = 0; k < R; ++k) {
-                    const int run = r0 + k * kTileThreads + tid;
-                    P.run(run, held[k]);
-                    hs[k] = staged(held[k], run < rh, sb, nseg);
+                j_chunk(pj, chunk_q0(b, wid), qe, sb, nseg);
+                for (int ch = wid + NW; ch < nch; ch += NW) {
+                    PairChunk<DT> L;
+                    const int q0 = chunk_q0(b, ch);
+                    load_pair_chunk(P, q0, lane, L);
+                    j_chunk(L, q0, qe, sb, nseg);
                 }
-#pragma unroll
-                for (int k = 0; k < R; ++k) j_run(held[k], hs[k]);
+                // J^T of this block reads the runs again (in cache); the
+                // next block's first J chunk loads meanwhile
+                if (MODE & MODE_JT) load_run_chunk(b, wid, rj);
+                if (b + 1 < nblk) load_pair_chunk(P, chunk_q0(b + 1, wid), lane, pj);
                 __syncthreads();
                 gather_u(b);
                 __syncthreads();
@@ -498,9 +574,14 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 __syncthreads();
             }
             if (MODE & MODE_JT) {
-#pragma unroll
-                for (int k = 0; k < R; ++k) jt_round(held[k], hs[k]);
-                stream_jt(rh, r1, sb, nseg);
+                RunLoad<DT> cur = rj;
+                if (!(MODE & MODE_J) && b + 1 < nblk) load_run_chunk(b + 1, wid, rj);
+                jt_chunk(cur, sb, nseg);
+                for (int ch = wid + NW; ch < nch; ch += NW) {
+                    RunLoad<DT> L;
+                    load_run_chunk(b, ch, L);
+                    jt_chunk(L, sb, nseg);
+                }
                 // one addition per segment and block, blocks in order (the
                 // fused pass orders them with the next block's J barriers)
                 if (!(MODE & MODE_J)) __syncthreads();
@@ -518,10 +599,13 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 stage(c0, cn, true);
                 __syncthreads();
                 for (int b = 0; b < nblk; ++b) {
-                    const int lo = lower(brun[b], brun[b + 1], (uint32_t)(sb + c0));
-                    const int hi = lower(lo, brun[b + 1], (uint32_t)(sb + c0 + cn));
-                    if (lo == hi) continue;
-                    stream_j(lo, hi, sb + c0, cn);
+                    const int qe = br[b + 1] * kRun;
+                    for (int ch = wid; ch < nchunks(b); ch += NW) {
+                        PairChunk<DT> L;
+                        const int q0 = chunk_q0(b, ch);
+                        load_pair_chunk(P, q0, lane, L);
+                        j_chunk(L, q0, qe, sb + c0, cn);
+                    }
                     __syncthreads();
                     gather_u(b);
                     __syncthreads();
@@ -537,14 +621,13 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 zero_mom(cn);
                 __syncthreads();
                 for (int b = 0; b < nblk; ++b) {
-                    const int lo = lower(brun[b], brun[b + 1], (uint32_t)(sb + c0));
-                    const int hi = lower(lo, brun[b + 1], (uint32_t)(sb + c0 + cn));
-                    // rounds start on a window of the block, so that no piece
-                    // is split between waves (runs before lo are not staged)
-                    stream_jt(brun[b] + ((lo - brun[b]) & ~(kWinRuns - 1)), hi, sb + c0, cn);
+                    for (int ch = wid; ch < nchunks(b); ch += NW) {
+                        RunLoad<DT> L;
+                        load_run_chunk(b, ch, L);
+                        jt_chunk(L, sb + c0, cn);
+                    }
                     __syncthreads();
                 }
-                __syncthreads();
                 write_mom(c0, cn);
             }
         }

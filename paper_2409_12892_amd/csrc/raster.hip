@@ -21,8 +21,9 @@
 //          the tile is at least 8 pixels each way, else 64 consecutive
 //          pixels).  Per tile, block after block; within a block, the active
 //          splats in depth order, each with its pairs in that block (a
-//          piece) in lane order: T (with head/clamp flag bits), dC/dalpha
-//          (3 planes), pixel byte.  Every piece starts on a multiple of 8
+//          piece) in lane order, rotated within each run of 8 by the
+//          segment index: T (with head/clamp flag bits), dC/dalpha (3
+//          planes), pixel byte.  Every piece starts on a multiple of 8
 //          pairs (zero padding), so each aligned run of 8 pairs belongs to
 //          one segment (the splat's pieces in the tile) and one block; the
 //          run -> segment table names it.  No piece crosses a multiple of
@@ -70,7 +71,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     __shared__ uint32_t s_eoff[kBlock][NW];    // fill pass: tile offset of each entry's piece per block
     __shared__ uint32_t s_egap[kBlock][NW];    // fill pass: tile offset of the gap before it (its start if none)
     __shared__ uint32_t s_cnt[kBlock];         // fill pass: the batch's per-entry counts
-    __shared__ uint32_t s_eseg[kBlock];        // thin fill: segment of each active entry
+    __shared__ uint32_t s_eseg[kBlock];        // fill pass: segment of each active entry
     __shared__ uint32_t s_run[3];              // running -, segments, real pairs
     __shared__ uint32_t s_blk[NW];             // running padded pairs per block (count); block starts (fill)
     __shared__ double s_red[kBlock / kWave];
@@ -207,7 +208,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 eoff[w] = s_eoff[tid][w];
                 egap[w] = s_egap[tid][w];
             }
-            if (THIN && tid < nb) s_eseg[tid] = (uint32_t)(seg_base + eseg);
+            if (tid < nb) s_eseg[tid] = (uint32_t)(seg_base + eseg);
             if (tid < nb) {
                 if (tot > 0 && seg_base + eseg < seg_end) {
                     const int64_t s = seg_base + eseg;
@@ -233,14 +234,17 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     for (int w = 0; w < NW; ++w) {
                         if (THIN || cw[w] == 0) continue;
                         // the piece's aligned runs (and those of the gap before
-                        // it) -> this segment; padding and gap slots get a zero
-                        // T word (no pair)
+                        // it) -> this segment; the gap and the piece's last,
+                        // partial run get zero T words (no pair) here, and the
+                        // pairs of that run are written over them after the
+                        // barrier below
                         const int64_t qg = pair_base + egap[w];
                         const int64_t q0 = pair_base + eoff[w];
                         const int64_t q1 = min(q0 + (int64_t)pad8(cw[w]), pair_end);
+                        const int64_t qz = q0 + (int64_t)(cw[w] & ~7u);
                         for (int64_t r = qg >> 3; r < (q1 >> 3); ++r) a.run_seg[r] = (uint32_t)s;
                         for (int64_t q = qg; q < q1; ++q) {
-                            if (q >= q0 && q < q0 + (int64_t)cw[w]) continue;
+                            if (q >= q0 && q < qz) continue;
                             zT[q] = 0;
                             zD[q] = 0;
                             zD[a.pair_stride + q] = 0;
@@ -302,8 +306,13 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 acc1 += c1 * w;
                 acc2 += c2 * w;
                 if (FILL && !THIN) {
+                    // the pair's place in its piece, rotated within its run of
+                    // 8 by the segment: lanes of the product passes that take
+                    // runs of different splats at once then hit different
+                    // pixels at each step
                     const uint32_t rank = (uint32_t)__popcll(bal & lanemask_lt());
-                    const uint32_t within = s_eoff[j][wid] + rank;        // slot in the tile
+                    const uint32_t pos = (rank & ~7u) | ((rank + s_eseg[j]) & 7u);
+                    const uint32_t within = s_eoff[j][wid] + pos;         // slot in the tile
                     const int64_t slot = pair_base + within;
                     if (within < blk_end) {   // always true when both passes agree
                         const double inv = 1.0 / (1.0 - alpha);

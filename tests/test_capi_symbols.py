@@ -44,10 +44,10 @@ def test_binding_structs_match_header_layout():
     with tempfile.TemporaryDirectory() as d:
         src = os.path.join(d, "s.c")
         with open(src, "w") as f:
-            f.write('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu\\n",'
+            f.write('#include <stdio.h>\n#include "%s"\nint main(){printf("%%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu %%zu\\n",'
                     'sizeof(lm_camera),sizeof(lm_scene),sizeof(lm_options),sizeof(lm_cache_info),'
                     'sizeof(lm_pcg_stats),(size_t)LM_PCG_MAX_HISTORY,sizeof(lm_tile_score),'
-                    'sizeof(lm_profile_entry));}\n' % HEADER)
+                    'sizeof(lm_profile_entry),sizeof(lm_buffer_bytes));}\n' % HEADER)
         exe = os.path.join(d, "s")
         subprocess.run(["gcc", src, "-o", exe], check=True)
         out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout.split()
@@ -55,7 +55,8 @@ def test_binding_structs_match_header_layout():
     assert sizes == [ctypes.sizeof(binding.LmCamera), ctypes.sizeof(binding.LmScene),
                      ctypes.sizeof(binding.LmOptions), ctypes.sizeof(binding.LmCacheInfo),
                      ctypes.sizeof(binding.LmPcgStats), binding.PCG_MAX_HISTORY,
-                     ctypes.sizeof(binding.LmTileScore), ctypes.sizeof(binding.LmProfileEntry)]
+                     ctypes.sizeof(binding.LmTileScore), ctypes.sizeof(binding.LmProfileEntry),
+                     ctypes.sizeof(binding.LmBufferBytes)]
 
 
 def test_context_handles_cross_the_binding_as_pointers():

@@ -166,6 +166,38 @@ def test_compact_build_keeps_the_products_and_refuses_build_exports():
     comp2.destroy()
 
 
+def test_compact_cache_drops_the_gram_transients_and_trims():
+    """A compact cache keeps no per-(splat, tile) Gram values after the
+    diagonal; lm_cache_trim frees the per-(Gaussian, view) Gram values too,
+    PCG on the trimmed cache is bit-identical, and the diagonal and the
+    learned-preconditioner inputs computed again are bit-identical."""
+    from paper_2409_12892_amd import binding as B
+    d = sg.config_scene("tiny", N=700, subsets=[(3, 64, 48)], seed=25, deg=1)
+    sc, cams = d["scene"], d["cams"][0]
+    x = torch.from_numpy(sc.x).cuda()
+    tgt = B.lm_render(torch.from_numpy(d["x_star"]).cuda(), sc.sh_degree, cams)
+    full, b1, _ = B.lm_build_cache(x, sc.sh_degree, cams, tgt)
+    comp, b2, _ = B.lm_build_cache(x, sc.sh_degree, cams, tgt, compact=True)
+    M1, M2 = B.lm_jacobi_diag(full), B.lm_jacobi_diag(comp)
+    assert torch.equal(M1, M2)
+    mf, mc = full.memory(), comp.memory()
+    assert mf.get("gram", 0) > 0 and mc.get("gram", 0) == 0
+    assert mc.get("gvgram", 0) > 0
+    assert sum(mc.values()) == comp.info()["device_bytes"]
+    f1 = B.lm_precond_features(comp, x, M2)
+    d1, st1 = B.lm_pcg_solve([comp], [b2], [M2], 1e-2, 6)
+    comp.trim()
+    mt = comp.memory()
+    assert mt.get("gvgram", 0) == 0 and mt.get("gram", 0) == 0
+    assert comp.info()["device_bytes"] < sum(mc.values())
+    d2, st2 = B.lm_pcg_solve([comp], [b2], [M2], 1e-2, 6)
+    assert torch.equal(d1[0], d2[0])
+    assert torch.equal(B.lm_jacobi_diag(comp), M1)
+    assert torch.equal(B.lm_precond_features(comp, x, M2), f1)
+    full.destroy()
+    comp.destroy()
+
+
 def test_compact_builds_share_a_scratch_handle():
     """Compact builds of two subsets through one scratch handle: products,
     diagonal and b are bit-identical to those of full builds; the compacted
