@@ -441,7 +441,7 @@ lm_status lm_block_jacobi(const lm_cache* cache, const int64_t* gaussians, int64
  * scaling that bounds the Gershgorin discs of the damped block
  * B_k + lambda diag(D), relative to Jacobi; then t = mu_j + shrink
  * (r - mu_j) with mu_j the mean of r over the observed Gaussians of
- * parameter j (shrink in [0, 1]; 1 keeps r, 0.5 is the training target);
+ * parameter j (shrink in [0, 1]; 1 keeps r);
  * mask = 1.  Where d = 0: t = 0, mask = 0.  The means are summed in a fixed
  * order (deterministic). */
 lm_status lm_precond_targets(const lm_cache* cache, float lambda, float diag_floor, float shrink, float* t,
@@ -524,8 +524,10 @@ enum {
     LM_EXPORT_PAIR_PIX = 7,      /* int32 [n_pairs]: global pixel index v*H*W + y*W + x       */
     LM_EXPORT_PAIR_GAUSS = 8,    /* int32 [n_pairs]: Gaussian id of the pair's splat          */
     LM_EXPORT_RESIDUAL = 9,      /* float [V][3][H][W]: F = rendered - target                 */
-    LM_EXPORT_PAIR_FLAGS = 10    /* int32 [n_pairs]: bit0 first pair of a piece (a splat's
+    LM_EXPORT_PAIR_FLAGS = 10,   /* int32 [n_pairs]: bit0 first pair of a piece (a splat's
                                     pairs in one pixel block of a tile), bit1 alpha clamped */
+    LM_EXPORT_TILE_SEGMENTS = 11 /* int64 [n_tiles+1]: first segment (a splat with pairs in
+                                    the tile) of each tile                               */
 };
 int64_t lm_cache_export_size(const lm_cache* cache, int32_t what);
 lm_status lm_cache_export(const lm_cache* cache, int32_t what, void* host_dst, int64_t bytes,

@@ -25,10 +25,10 @@ TOL_NONE, TOL_PAPER_SQUARED, TOL_RELATIVE = 0, 1, 2
 PCG_MAX_HISTORY = 257
 
 EXPORT = dict(records=0, sorted_values=1, tile_ranges=2, image=3, ncontrib=4, pair_T=5, pair_D=6,
-              pair_pix=7, pair_gauss=8, residual=9, pair_flags=10)
+              pair_pix=7, pair_gauss=8, residual=9, pair_flags=10, tile_segments=11)
 _EXPORT_DTYPE = dict(records=np.float32, sorted_values=np.uint32, tile_ranges=np.int64, image=np.float32,
                      ncontrib=np.int32, pair_T=np.float32, pair_D=np.float32, pair_pix=np.int32,
-                     pair_gauss=np.int32, residual=np.float32, pair_flags=np.int32)
+                     pair_gauss=np.int32, residual=np.float32, pair_flags=np.int32, tile_segments=np.int64)
 
 EXPORTED_SYMBOLS = (
     "lm_last_error", "lm_build_cache", "lm_cache_destroy", "lm_cache_get_info", "lm_jacobi_diag",

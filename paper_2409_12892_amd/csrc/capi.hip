@@ -1801,6 +1801,7 @@ int64_t lm_cache_export_size(const lm_cache* c, int32_t what) {
         case LM_EXPORT_PAIR_GAUSS: return 4 * c->n_pairs;
         case LM_EXPORT_RESIDUAL: return 4 * 3 * c->n_pix;
         case LM_EXPORT_PAIR_FLAGS: return 4 * c->n_pairs;
+        case LM_EXPORT_TILE_SEGMENTS: return 8 * (c->n_tiles + 1);
         default: return -1;
     }
 }
@@ -1909,6 +1910,10 @@ extern "C" lm_status lm_cache_export(const lm_cache* c, int32_t what, void* host
             return LM_OK;
         case LM_EXPORT_TILE_RANGES:
             LM_HIP(hipMemcpyAsync(host_dst, c->tile_start.p, bytes, hipMemcpyDeviceToHost, s));
+            LM_HIP(hipStreamSynchronize(s));
+            return LM_OK;
+        case LM_EXPORT_TILE_SEGMENTS:
+            LM_HIP(hipMemcpyAsync(host_dst, c->tile_seg_off.p, bytes, hipMemcpyDeviceToHost, s));
             LM_HIP(hipStreamSynchronize(s));
             return LM_OK;
         case LM_EXPORT_IMAGE: {

@@ -212,48 +212,48 @@ struct TilePlanes {
 
 // Tile pass.  One workgroup of 512 threads (8 waves) per tile.  The tile's
 // pairs are stored block after block (a block is the 64 pixels of one
-// raster wave), so after a block's pairs every one of its pixels has its
-// complete u = J p.  A block's pairs are taken in chunks of 512 pairs (a
-// window of the fill's placement rule: no piece crosses one), chunk c by
-// wave c mod 8, so every piece of a chunk lies in one wave:
-//   J  : the wave holds the chunk as 8 windows of 64 consecutive pairs, one
-//        pair per lane (coalesced loads); per window the J rows of the
-//        lanes' pairs, and the window's pieces (a contiguous lane range
-//        each, distinct pixels within a piece) add into the wave's
-//        per-pixel accumulators one after another with plain LDS
-//        read-modify-writes; the waves' accumulators are added in wave
-//        order into u;
-//   J^T: the wave reads the chunk again as 64 runs of 8 pairs, one per lane
-//        (a run belongs to one piece); each lane sums the 9 moments of its
-//        run, one segmented scan over the wave (keyed by segment) leaves
-//        each piece's sum in its last lane, which adds it into the
-//        segment's moments (a segment has one piece per block, in one
-//        chunk; blocks in order).
-// No LDS atomics, and every sum runs in a fixed order.  The J^T read of a
-// block follows its J read within microseconds (an L2 hit); each wave
-// issues its first chunk of the next block before the current block's
-// barriers and J^T half, so the loads overlap the other work.  A tile with
-// more segments than LDS stages at once (kSegCap) runs segment chunk after
-// segment chunk (J over all, then J^T).
+// raster wave); within a block the splats' pieces in segment order, each
+// padded to whole runs of 8 pairs, and no piece crosses a window of 512
+// pairs from its block's start.
+//   J  : the tile's pairs in windows of 64, one pair per lane (coalesced
+//        loads), window k by wave k mod 8 (balanced to one window), two
+//        groups of kJGroup windows in flight per wave.  Per window the J
+//        rows of the lanes' pairs; the window's pieces (contiguous lane
+//        ranges with distinct pixels; a segment's pieces of two adjacent
+//        blocks have distinct pixels too) add into the wave's per-pixel
+//        accumulators one after another with plain LDS read-modify-writes.
+//        The waves' accumulators are added in wave order into u.
+//   J^T: block by block, the block's 512-pair windows in run order (64 runs
+//        of 8 pairs, one per lane; a run belongs to one piece), window c by
+//        wave c mod 8.  Each lane sums the 9 moments of its run, one
+//        segmented scan over the wave (keyed by segment) leaves each
+//        piece's sum in its last lane, which adds it into the segment's
+//        moments: a segment has one piece per block, in one window, so one
+//        wave adds per block, and a barrier between blocks orders the
+//        additions.
+// No LDS atomics, and every sum runs in a fixed order.  A tile with more
+// segments than LDS stages at once (kSegCap) runs segment chunk after
+// segment chunk.
 constexpr int kTileThreads = 512;
 constexpr int kTileWaves = kTileThreads / kWave;
-constexpr int kSegCap = 512;
-constexpr int kChunkRuns = kWave;                 // runs of a chunk (one per lane in J^T)
-static_assert(kChunkRuns * kRun == kWindow, "a chunk is one placement window");
-constexpr int kChunkWins = kWindow / kWave;       // 64-pair windows of a chunk (J)
+constexpr int kSegCap = 640;
+constexpr int kChunkRuns = kWave;                 // runs of a J^T window (one per lane)
+static_assert(kChunkRuns * kRun == kWindow, "a J^T window is one placement window");
+constexpr int kJGroup = 4;                        // 64-pair J windows a wave loads together
 
-// One chunk in pair order: window j's word of lane l is pair 64 j + l;
-// 16-bit words two per register, pixel bytes four per register, and the
-// segments of the chunk's 64 runs one per lane (run l in lane l).
+// A group of J windows in pair order: window j's word of lane l is pair
+// 64 j + l of the group; 16-bit words two per register, pixel bytes four
+// per register, segment words one per window.
 template <int DT>
-struct PairChunk {
+struct PairGroup {
     using S = Store<DT>;
     using W = typename S::word;
-    static constexpr int NR = sizeof(W) == 4 ? kChunkWins : kChunkWins / 2;   // registers per plane
+    static constexpr int NR = sizeof(W) == 4 ? kJGroup : kJGroup / 2;   // registers per plane
     uint32_t tw[NR];
     uint32_t dw[3][NR];
-    uint32_t pw[kChunkWins / 4];
-    uint32_t rseg;
+    uint32_t pw[(kJGroup + 3) / 4];
+    uint32_t sg[kJGroup];
+    int lim[kJGroup];                 // pairs of window j in its range (wave-uniform)
     __device__ __forceinline__ W word(const uint32_t* p, int j) const {
         if constexpr (sizeof(W) == 4) return p[j];
         else return (W)((p[j >> 1] >> (16 * (j & 1))) & 0xFFFFu);
@@ -263,18 +263,20 @@ struct PairChunk {
     __device__ __forceinline__ int pix(int j) const { return (int)((pw[j >> 2] >> (8 * (j & 3))) & 0xFFu); }
 };
 
-// chunk of tile-relative first pair q0 in pair order (q0 = 1 << 28 reads
-// past every tile: zeros, no memory access)
+// J windows: window j of the group starts at tile-relative pair q0[j] and
+// holds lim[j] pairs of its range (a window past the tile reads zeros
+// without a memory access)
 template <int DT>
-__device__ __forceinline__ void load_pair_chunk(const TilePlanes<DT>& P, int q0, int lane, PairChunk<DT>& L) {
+__device__ __forceinline__ void load_pair_group(const TilePlanes<DT>& P, const int (&q0)[kJGroup], int lane,
+                                                PairGroup<DT>& L) {
     using W = typename Store<DT>::word;
     const __amdgpu_buffer_rsrc_t pr[4] = {P.t, P.d0, P.d1, P.d2};
 #pragma unroll
     for (int pl = 0; pl < 4; ++pl) {
         uint32_t* dst = pl == 0 ? L.tw : L.dw[pl - 1];
 #pragma unroll
-        for (int j = 0; j < kChunkWins; ++j) {
-            const int q = q0 + kWave * j + lane;
+        for (int j = 0; j < kJGroup; ++j) {
+            const int q = q0[j] + lane;
             if constexpr (sizeof(W) == 4) {
                 dst[j] = __builtin_amdgcn_raw_buffer_load_b32(pr[pl], q * 4, 0, 0);
             } else {
@@ -284,11 +286,12 @@ __device__ __forceinline__ void load_pair_chunk(const TilePlanes<DT>& P, int q0,
         }
     }
 #pragma unroll
-    for (int j = 0; j < kChunkWins; ++j) {
-        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(P.pix, q0 + kWave * j + lane, 0, 0);
+    for (int j = 0; j < kJGroup; ++j) {
+        const uint32_t q = (uint32_t)(q0[j] + lane);
+        const uint32_t b = __builtin_amdgcn_raw_buffer_load_b8(P.pix, (int)q, 0, 0);
         L.pw[j >> 2] = (j & 3) ? (L.pw[j >> 2] | (b << (8 * (j & 3)))) : b;
+        L.sg[j] = __builtin_amdgcn_raw_buffer_load_b32(P.seg, (int)((q >> 3) << 2), 0, 0);
     }
-    L.rseg = __builtin_amdgcn_raw_buffer_load_b32(P.seg, ((q0 / kRun) + lane) * 4, 0, 0);
 }
 
 // gt: the tile's index over the batch (the subsets' tiles one after another)
@@ -301,14 +304,20 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
     using S = Store<DT>;
     constexpr int NW = kTileWaves;
     constexpr int kNoSeg = kSegCap;              // segment key of a lane without a run
-    constexpr int kFar = 1 << 28;                // pair offset past every tile
     const CacheView& c = a.c;
     __shared__ float4 s_sg[kSegCap][4];   // mx', my', A', B' | C', o, P1, P2 | Q1, Q2, Q3, do | dc0, dc1, dc2, -
-    __shared__ float s_mom[9][kSegCap];
-    __shared__ float s_uw[3][NW][kBlockPix];    // per-wave J accumulators of one block, per channel
+    // the J half's per-wave accumulators (u of each pixel, w unused) and the
+    // J^T half's segment moments share their LDS (the halves run one after
+    // the other)
+    constexpr int kAcc = 4 * NW * kMaxTilePix > 9 * kSegCap ? 4 * NW * kMaxTilePix : 9 * kSegCap;
+    __shared__ __align__(16) float s_acc[kAcc];
+    float4 (*s_uw)[kMaxTilePix] = reinterpret_cast<float4 (*)[kMaxTilePix]>(s_acc);
+    float (*s_mom)[kSegCap] = reinterpret_cast<float (*)[kSegCap]>(s_acc);
     __shared__ float4 s_ut[kMaxTilePix];        // u of the tile (weighted once complete)
     __shared__ double s_red[NW];
     __shared__ int br[kTileBlocks + 1];         // tile-relative first run of each block
+    __shared__ int rng[kTileBlocks][2];         // runs of the staged segments in each block
+    __shared__ int wpre[kTileBlocks + 1];       // J windows of the blocks' ranges before each block
 
     const int64_t t = gt - Bt.tile_off[bi];
     const int tid = threadIdx.x, lane = __lane_id();
@@ -319,8 +328,6 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
     const int tx = (int)(lt % cam.TX), ty = (int)(lt / cam.TX);
     const int tw_mask = c.TW - 1, tw_shift = c.tw_shift;
     const int npix = c.TW * c.TH;
-    const bool blk8 = c.TW >= 8 && c.TH >= 8;
-    const int bpr = c.TW >> 3;
     const int nblk = (npix + kBlockPix - 1) / kBlockPix;
     const int64_t HW = (int64_t)cam.W * cam.H;
     const int64_t pb = c.tile_pair_off[t], pe = c.tile_pair_off[t + 1];
@@ -333,11 +340,6 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         for (int b = 0; b < kTileBlocks; ++b) br[b + 1] = br[b] + (int)c.tile_blk[t * kTileBlocks + b] / kRun;
     }
 
-    // tile pixel of pixel i of block b, and a tile pixel's index in its block
-    auto blk_pixel = [&](int b, int i) -> int {
-        return blk8 ? (((b / bpr) << 3) + (i >> 3)) * c.TW + ((b % bpr) << 3) + (i & 7) : b * kBlockPix + i;
-    };
-    auto local_of = [&](int pl) -> int { return blk8 ? (((pl >> tw_shift) & 7) << 3) | (pl & 7) : pl & (kBlockPix - 1); };
     auto pix_valid = [&](int pl) -> bool {
         return pl < npix && tx * c.TW + (pl & tw_mask) < cam.W && ty * c.TH + (pl >> tw_shift) < cam.H;
     };
@@ -346,7 +348,8 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
     };
 
     for (int i = tid; i < kMaxTilePix; i += kTileThreads) s_ut[i] = make_float4(0.f, 0.f, 0.f, 0.f);
-    for (int i = tid; i < 3 * NW * kBlockPix; i += kTileThreads) (&s_uw[0][0][0])[i] = 0.0f;
+    if (MODE & MODE_J)
+        for (int i = tid; i < 4 * NW * kMaxTilePix; i += kTileThreads) s_acc[i] = 0.0f;
     __syncthreads();
     if (MODE == MODE_JT && tid < npix && pix_valid(tid)) {
         const int64_t ib = img_index(tid);
@@ -376,23 +379,16 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
 #pragma unroll
             for (int k = 0; k < 9; ++k) s_mom[k][i] = 0.0f;
     };
-    // first pair of chunk ch of block b (kFar when the wave has no such chunk)
-    auto chunk_q0 = [&](int b, int ch) -> int {
-        const int r = br[b] + ch * kChunkRuns;
-        return r < br[b + 1] ? r * kRun : kFar;
-    };
 
-    // J rows of one chunk (first pair q0, the block's pairs end at qe;
-    // segments [s0, s0 + cn) staged) into this wave's accumulators
-    auto j_chunk = [&](const PairChunk<DT>& L, int q0, int qe, int64_t s0, int cn) {
-        float* u0 = s_uw[0][wid];
-        float* u1 = s_uw[1][wid];
-        float* u2 = s_uw[2][wid];
+    // J rows of one group of windows (segments [s0, s0 + cn) staged) into
+    // this wave's accumulators
+    auto j_group = [&](const PairGroup<DT>& L, int64_t s0, int cn) {
+        float4* uw = s_uw[wid];
 #pragma unroll
-        for (int j = 0; j < kChunkWins; ++j) {
-            const uint32_t sg = (uint32_t)__shfl((int)L.rseg, (kWave / kRun) * j + (lane >> 3), kWave);
-            const int64_t sl = (int64_t)sg - s0;
-            const bool live = q0 + kWave * j + lane < qe && L.t(j) != 0 && sl >= 0 && sl < cn;
+        for (int j = 0; j < kJGroup; ++j) {
+            const uint32_t sg = L.sg[j];
+            const uint32_t sl = sg - (uint32_t)s0;        // segment ids fit 32 bits
+            const bool live = lane < L.lim[j] && L.t(j) != 0 && sl < (uint32_t)cn;
             float v0 = 0.0f, v1 = 0.0f, v2 = 0.0f;
             const int pl = L.pix(j);
             if (live) {
@@ -412,7 +408,7 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 v2 = S::dec(L.d(2, j)) * dal + aT * g3.z;
             }
             // the window's pieces one after another (pixels are distinct
-            // within a piece)
+            // within a segment's pieces)
             uint64_t todo = __ballot(live);
             while (todo) {
                 const int first = __ffsll((unsigned long long)todo) - 1;
@@ -420,21 +416,126 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 const bool mine = live && sg == sk;
                 todo &= ~__ballot(mine);
                 if (mine) {
-                    const int li = local_of(pl);
-                    u0[li] += v0;
-                    u1[li] += v1;
-                    u2[li] += v2;
+                    float4 u = uw[pl];
+                    u.x += v0;
+                    u.y += v1;
+                    u.z += v2;
+                    uw[pl] = u;
                 }
             }
         }
     };
-    // J^T moments of one chunk (lane: one run, segments [s0, s0 + cn)
+    // the runs of segments [s_lo, s_hi) (global ids) in each block into
+    // rng, and the J windows of those ranges into wpre: a block's runs ascend
+    // in segment (a gap run carries the next piece's segment), so each bound
+    // is a lower bound over the block's run segments, found by wave 2 b + e
+    // probing 64 runs at a time
+    auto find_ranges = [&](int64_t s_lo, int64_t s_hi, bool whole) {
+        if (whole) {
+            if (tid < kTileBlocks) {
+                rng[tid][0] = br[tid];
+                rng[tid][1] = br[tid + 1];
+            }
+        } else if (wid < 2 * kTileBlocks) {
+            const int b = wid >> 1;
+            const uint32_t key = (uint32_t)((wid & 1) ? s_hi : s_lo);
+            int lo = br[b], hi = br[b + 1];          // answer in [lo, hi]
+            while (hi > lo) {
+                const int step = (hi - lo + kWave - 1) / kWave;
+                const int r = lo + lane * step;
+                const bool ge = r >= hi || __builtin_amdgcn_raw_buffer_load_b32(P.seg, r * 4, 0, 0) >= key;
+                const uint64_t m = __ballot(ge);
+                // runs before the first probe at or above the key are below it
+                const int f = m ? __ffsll((unsigned long long)m) - 1 : kWave;
+                const int nlo = f == 0 ? lo : lo + (f - 1) * step + 1;
+                const int nhi = min(hi, lo + f * step);
+                if (step == 1) {
+                    lo = hi = min(hi, lo + f);
+                } else {
+                    lo = nlo;
+                    hi = nhi;
+                }
+            }
+            if (lane == 0) rng[b][wid & 1] = lo;
+        }
+        __syncthreads();
+        if (tid == 0) {
+            wpre[0] = 0;
+#pragma unroll
+            for (int b = 0; b < kTileBlocks; ++b) wpre[b + 1] = wpre[b] + (rng[b][1] - rng[b][0] + 7) / 8;
+        }
+        __syncthreads();
+    };
+    // start pair and pair count of J window i (past the last: none)
+    auto window = [&](int i, int& q0, int& lim) {
+        int b = 0;
+#pragma unroll
+        for (int k = 1; k < kTileBlocks; ++k) b = i >= wpre[k] ? k : b;
+        if (i >= wpre[kTileBlocks]) {
+            q0 = 1 << 28;
+            lim = 0;
+        } else {
+            q0 = rng[b][0] * kRun + (i - wpre[b]) * kWave;
+            lim = min(kWave, rng[b][1] * kRun - q0);
+        }
+    };
+    auto load_windows = [&](int i0, PairGroup<DT>& L) {
+        int q0[kJGroup];
+#pragma unroll
+        for (int j = 0; j < kJGroup; ++j) window(i0 + j * NW, q0[j], L.lim[j]);
+        load_pair_group(P, q0, lane, L);
+    };
+    // this wave's J windows of the ranges, segments [s0, s0 + cn) staged;
+    // two groups in flight
+    auto j_tile = [&](int64_t s0, int cn) {
+        const int nw = wpre[kTileBlocks];
+        PairGroup<DT> cur, nxt;
+        load_windows(wid, cur);
+        for (int i0 = wid; i0 < nw; i0 += kJGroup * NW) {
+            load_windows(i0 + kJGroup * NW, nxt);
+            j_group(cur, s0, cn);
+            cur = nxt;
+        }
+    };
+    // u of the tile: the waves' accumulators in wave order; ||J p||^2 (sum
+    // w u^2 with residual weights), the J output, and w . u for J^T
+    double sq = 0.0;
+    auto finish_u = [&] {
+        for (int pl = tid; pl < npix; pl += kTileThreads) {
+            float4 u = s_uw[0][pl];
+#pragma unroll
+            for (int w = 1; w < NW; ++w) {
+                const float4 o = s_uw[w][pl];
+                u.x += o.x;
+                u.y += o.y;
+                u.z += o.z;
+            }
+            float4 wu = u;
+            if (pix_valid(pl)) {
+                const int64_t ib = img_index(pl);
+                if (c.wres) {
+                    wu.x = u.x * c.wres[ib];
+                    wu.y = u.y * c.wres[ib + HW];
+                    wu.z = u.z * c.wres[ib + 2 * HW];
+                }
+                sq += (double)u.x * (double)wu.x + (double)u.y * (double)wu.y + (double)u.z * (double)wu.z;
+                if (MODE == MODE_J && a.uout) {
+                    a.uout[ib] = u.x;
+                    a.uout[ib + HW] = u.y;
+                    a.uout[ib + 2 * HW] = u.z;
+                }
+            }
+            s_ut[pl] = wu;
+        }
+    };
+
+    // J^T moments of one window (lane: one run, segments [s0, s0 + cn)
     // staged): per lane the sums over its run, a segmented scan over the
     // wave, one plain addition per piece with pairs (a gap run carries the
     // next piece's segment and no pair: a group of gap runs adds nothing)
     auto jt_chunk = [&](const RunLoad<DT>& L, int64_t s0, int cn) {
-        const int64_t sl = (int64_t)L.seg - s0;
-        const bool in = sl >= 0 && sl < cn;
+        const uint32_t sl = L.seg - (uint32_t)s0;     // segment ids fit 32 bits
+        const bool in = sl < (uint32_t)cn;
         const int key = in ? (int)sl : kNoSeg;
         float m[9];
 #pragma unroll
@@ -443,9 +544,12 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         {
             const int s = in ? key : 0;
             const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
+            // a padding pair has T, D and pixel 0: with its u taken as 0
+            // every term is 0 (G and alpha are finite: the power is <= 0);
+            // lanes outside [s0, s0 + cn) sum under a key no piece has
 #pragma unroll
             for (int k = 0; k < kRun; ++k) {
-                const bool live = in && L.t(k) != 0;
+                const bool live = L.t(k) != 0;
                 any = any || live;
                 const float T = S::dec_T(L.t(k));
                 const bool clamped = S::clamp(L.t(k));
@@ -454,22 +558,25 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 const float dy = (float)(pl >> tw_shift) - g0.y;
                 const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
                 const float alpha = clamped ? 0.99f : g1.y * G;
-                const float aT = live ? alpha * T : 0.0f;
-                const float4 u = s_ut[pl];
+                const float aT = alpha * T;
+                float4 u = s_ut[pl];
+                u.x = live ? u.x : 0.0f;
+                u.y = live ? u.y : 0.0f;
+                u.z = live ? u.z : 0.0f;
                 const float w = S::dec(L.d(0, k)) * u.x + S::dec(L.d(1, k)) * u.y + S::dec(L.d(2, k)) * u.z;
-                const bool off = clamped || !live;
-                const float aw = off ? 0.0f : alpha * w;
+                const float aw = clamped ? 0.0f : alpha * w;
                 const float awx = aw * dx, awy = aw * dy;
                 m[0] += awx;
                 m[1] += awy;
                 m[2] += awx * dx;
                 m[3] += awx * dy;
                 m[4] += awy * dy;
-                m[5] += off ? 0.0f : G * w;
+                m[5] += clamped ? 0.0f : G * w;
                 m[6] += aT * u.x;
                 m[7] += aT * u.y;
                 m[8] += aT * u.z;
             }
+            any = any && in;
         }
         const uint64_t lives = __ballot(any);
         const int next = __shfl_down(key, 1, kWave);
@@ -481,59 +588,31 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
             for (int k = 0; k < 9; ++k) s_mom[k][key] += m[k];
         }
     };
-    // the block's runs in a lane: run r when it lies in block b
+    // the block's runs in a lane: run r of the 512-pair window ch of block b
+    // when it lies in the block's range
     auto load_run_chunk = [&](int b, int ch, RunLoad<DT>& L) {
         const int r = br[b] + ch * kChunkRuns + lane;
-        P.run_if(r, L, r < br[b + 1]);
+        P.run_if(r, L, r >= rng[b][0] && r < rng[b][1]);
     };
-    auto nchunks = [&](int b) { return (br[b + 1] - br[b] + kChunkRuns - 1) / kChunkRuns; };
-    // the waves' accumulators of block b added into u (and cleared)
-    auto gather_u = [&](int b) {
-        if (tid < kBlockPix) {
-            float4 u = make_float4(s_uw[0][0][tid], s_uw[1][0][tid], s_uw[2][0][tid], 0.0f);
-            s_uw[0][0][tid] = s_uw[1][0][tid] = s_uw[2][0][tid] = 0.0f;
-#pragma unroll
-            for (int w = 1; w < NW; ++w) {
-                u.x += s_uw[0][w][tid];
-                u.y += s_uw[1][w][tid];
-                u.z += s_uw[2][w][tid];
-                s_uw[0][w][tid] = s_uw[1][w][tid] = s_uw[2][w][tid] = 0.0f;
+    // the block's 512-pair windows that meet its range: [first, end)
+    auto first_chunk = [&](int b) { return (rng[b][0] - br[b]) / kChunkRuns; };
+    auto end_chunk = [&](int b) { return (rng[b][1] - br[b] + kChunkRuns - 1) / kChunkRuns; };
+    // every block's J^T windows, blocks in order with a barrier after each
+    // (the next block's first window of this wave loads meanwhile)
+    auto jt_tile = [&](int64_t s0, int cn) {
+        RunLoad<DT> nx;
+        load_run_chunk(0, first_chunk(0) + wid, nx);
+        for (int b = 0; b < nblk; ++b) {
+            const int c_lo = first_chunk(b), c_hi = end_chunk(b);
+            RunLoad<DT> cur = nx;
+            if (b + 1 < nblk) load_run_chunk(b + 1, first_chunk(b + 1) + wid, nx);
+            if (c_lo + wid < c_hi) jt_chunk(cur, s0, cn);
+            for (int ch = c_lo + wid + NW; ch < c_hi; ch += NW) {
+                RunLoad<DT> L;
+                load_run_chunk(b, ch, L);
+                jt_chunk(L, s0, cn);
             }
-            const int pl = blk_pixel(b, tid);
-            if (pl < npix) {
-                float4 acc = s_ut[pl];
-                acc.x += u.x;
-                acc.y += u.y;
-                acc.z += u.z;
-                s_ut[pl] = acc;
-            }
-        }
-    };
-    // u of block b complete: ||J p||^2 (sum w u^2 with residual weights),
-    // the J output, and w . u for the J^T half
-    double sq = 0.0;
-    auto finish_u = [&](int b) {
-        if (tid < kBlockPix) {
-            const int pl = blk_pixel(b, tid);
-            if (pl < npix) {
-                const float4 u = s_ut[pl];
-                float4 wu = u;
-                if (pix_valid(pl)) {
-                    const int64_t ib = img_index(pl);
-                    if (c.wres) {
-                        wu.x = u.x * c.wres[ib];
-                        wu.y = u.y * c.wres[ib + HW];
-                        wu.z = u.z * c.wres[ib + 2 * HW];
-                    }
-                    sq += (double)u.x * (double)wu.x + (double)u.y * (double)wu.y + (double)u.z * (double)wu.z;
-                    if (MODE == MODE_J && a.uout) {
-                        a.uout[ib] = u.x;
-                        a.uout[ib + HW] = u.y;
-                        a.uout[ib + 2 * HW] = u.z;
-                    }
-                }
-                s_ut[pl] = wu;
-            }
+            __syncthreads();
         }
     };
     auto write_mom = [&](int c0, int cn) {
@@ -543,93 +622,36 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         }
     };
 
-    if (nseg <= kSegCap) {
-        stage(0, nseg, (MODE & MODE_J) != 0);
-        if (MODE & MODE_JT) zero_mom(nseg);
+    // segments staged kSegCap at a time; each chunk's pairs are the ranges
+    // of its segments in the blocks (the whole blocks when all fit)
+    const bool whole = nseg <= kSegCap;
+    __syncthreads();                             // br
+    if (MODE & MODE_J) {
+        for (int c0 = 0; c0 < max(nseg, 1); c0 += kSegCap) {
+            const int cn = min(nseg - c0, kSegCap);
+            if (c0 > 0) __syncthreads();
+            stage(c0, cn, true);
+            find_ranges(sb + c0, sb + c0 + cn, whole);
+            j_tile(sb + c0, cn);
+        }
         __syncthreads();
-        // first chunk of this wave in block 0 (J: pair order; J^T only: runs)
-        PairChunk<DT> pj;
-        RunLoad<DT> rj;
-        if (MODE & MODE_J) load_pair_chunk(P, chunk_q0(0, wid), lane, pj);
-        else load_run_chunk(0, wid, rj);
-        for (int b = 0; b < nblk; ++b) {
-            const int nch = nchunks(b);
-            const int qe = br[b + 1] * kRun;
-            if (MODE & MODE_J) {
-                j_chunk(pj, chunk_q0(b, wid), qe, sb, nseg);
-                for (int ch = wid + NW; ch < nch; ch += NW) {
-                    PairChunk<DT> L;
-                    const int q0 = chunk_q0(b, ch);
-                    load_pair_chunk(P, q0, lane, L);
-                    j_chunk(L, q0, qe, sb, nseg);
-                }
-                // J^T of this block reads the runs again (in cache); the
-                // next block's first J chunk loads meanwhile
-                if (MODE & MODE_JT) load_run_chunk(b, wid, rj);
-                if (b + 1 < nblk) load_pair_chunk(P, chunk_q0(b + 1, wid), lane, pj);
-                __syncthreads();
-                gather_u(b);
-                __syncthreads();
-                finish_u(b);
-                __syncthreads();
-            }
-            if (MODE & MODE_JT) {
-                RunLoad<DT> cur = rj;
-                if (!(MODE & MODE_J) && b + 1 < nblk) load_run_chunk(b + 1, wid, rj);
-                jt_chunk(cur, sb, nseg);
-                for (int ch = wid + NW; ch < nch; ch += NW) {
-                    RunLoad<DT> L;
-                    load_run_chunk(b, ch, L);
-                    jt_chunk(L, sb, nseg);
-                }
-                // one addition per segment and block, blocks in order (the
-                // fused pass orders them with the next block's J barriers)
-                if (!(MODE & MODE_J)) __syncthreads();
-            }
-        }
-        if (MODE & MODE_JT) {
-            __syncthreads();
-            write_mom(0, nseg);
-        }
-    } else {
-        if (MODE & MODE_J) {
-            for (int c0 = 0; c0 < nseg; c0 += kSegCap) {
-                const int cn = min(nseg - c0, kSegCap);
-                __syncthreads();
-                stage(c0, cn, true);
-                __syncthreads();
-                for (int b = 0; b < nblk; ++b) {
-                    const int qe = br[b + 1] * kRun;
-                    for (int ch = wid; ch < nchunks(b); ch += NW) {
-                        PairChunk<DT> L;
-                        const int q0 = chunk_q0(b, ch);
-                        load_pair_chunk(P, q0, lane, L);
-                        j_chunk(L, q0, qe, sb + c0, cn);
-                    }
-                    __syncthreads();
-                    gather_u(b);
-                    __syncthreads();
-                }
-            }
-            for (int b = 0; b < nblk; ++b) finish_u(b);
-        }
-        if (MODE & MODE_JT) {
-            for (int c0 = 0; c0 < nseg; c0 += kSegCap) {
-                const int cn = min(nseg - c0, kSegCap);
+        finish_u();
+        __syncthreads();
+    }
+    if (MODE & MODE_JT) {
+        for (int c0 = 0; c0 < nseg; c0 += kSegCap) {
+            const int cn = min(nseg - c0, kSegCap);
+            // (MODE_J staged the last chunk and its ranges; the fused pass of
+            // a tile that fits reuses them)
+            if (!((MODE & MODE_J) && whole)) {
                 __syncthreads();
                 stage(c0, cn, false);
-                zero_mom(cn);
-                __syncthreads();
-                for (int b = 0; b < nblk; ++b) {
-                    for (int ch = wid; ch < nchunks(b); ch += NW) {
-                        RunLoad<DT> L;
-                        load_run_chunk(b, ch, L);
-                        jt_chunk(L, sb + c0, cn);
-                    }
-                    __syncthreads();
-                }
-                write_mom(c0, cn);
+                find_ranges(sb + c0, sb + c0 + cn, whole);
             }
+            zero_mom(cn);
+            __syncthreads();
+            jt_tile(sb + c0, cn);
+            write_mom(c0, cn);
         }
     }
     if (MODE & MODE_J) {

@@ -9,6 +9,9 @@ cache, on several seeded scenes:
   tall      1,500 Gaussians, SH 3, 3 views 60x100, 8x32 tiles (the shape the
             autotuner picks at the paper workload; partial tiles in x and y)
   tall16    1,200 Gaussians, SH 3, 3 views 64x96, 8x16 tiles
+  dense     6,000 Gaussians, SH 1, 2 views 32x32, 16x16 tiles (850-990 splats
+            with pairs per tile: more than the tile pass stages at once)
+  dense_tall  the same at 8x32 tiles (up to 1,670 splats per tile)
 
 Bars: tile binning and depth order bit-exact (each GPU tile list an
 order-preserving subsequence of the oracle's 3-sigma-rectangle list, every
@@ -36,7 +39,13 @@ PROBLEMS = {
     "wide": dict(name="tiny", N=1200, deg=3, subsets=[(2, 96, 24)], seed=13, tile=(32, 8)),
     "tall": dict(name="tiny", N=1500, deg=3, subsets=[(3, 60, 100)], seed=14, tile=(8, 32)),
     "tall16": dict(name="tiny", N=1200, deg=3, subsets=[(3, 64, 96)], seed=15, tile=(8, 16)),
+    # 6,000 small Gaussians over 2 views 32x32: 850-1700 splats with pairs
+    # per tile, more than the tile pass stages at once (chunked segments)
+    "dense": dict(name="tiny", N=6000, deg=1, subsets=[(2, 32, 32)], seed=16, tile=(16, 16)),
+    "dense_tall": dict(name="tiny", N=6000, deg=1, subsets=[(2, 32, 32)], seed=16, tile=(8, 32)),
 }
+# segments the tile pass stages in LDS at once (a tile with more runs chunk by chunk)
+TILE_SEG_CAP = 640
 
 
 @pytest.fixture(scope="module", params=list(PROBLEMS))
@@ -172,6 +181,29 @@ def test_cache_pairs_match_oracle(prob, gpu):
     np.testing.assert_allclose(D[:, ig].T, o_D[io], rtol=0, atol=1e-6)
 
 
+def test_tile_segments_count_the_splats_with_pairs(prob, gpu):
+    """Per tile, the segments (splats with at least one pair in the tile)
+    equal the oracle's distinct Gaussians among the tile's pairs."""
+    seg = np.diff(gpu["cache"].export("tile_segments"))
+    V, H, W = _img_shape(prob)
+    TW, TH = prob["tile"]
+    TX, TY = -(-W // TW), -(-H // TH)
+    N = prob["scene"].N
+    counts = np.zeros(V * TX * TY, np.int64)
+    for v, vw in enumerate(prob["J"].views):
+        p = vw["raster"]["pairs"]
+        y, x = p["pixel"] // W, p["pixel"] % W
+        t = v * TX * TY + (y // TH) * TX + x // TW
+        u = np.unique(t.astype(np.int64) * (N + 1) + p["g"])
+        np.add.at(counts, u // (N + 1), 1)
+    np.testing.assert_array_equal(seg, counts)
+    assert seg.sum() == gpu["cache"].info()["n_segments"]
+    if prob["id"] == "dense":
+        assert seg.min() > TILE_SEG_CAP             # every tile in two segment chunks
+    if prob["id"] == "dense_tall":
+        assert seg.max() > 2 * TILE_SEG_CAP         # three chunks in the middle tiles
+
+
 @pytest.mark.parametrize("block", [None, *BLOCKS.keys()])
 def test_apply_J(prob, gpu, block, report):
     sc = prob["scene"]
@@ -227,7 +259,17 @@ def test_apply_JtJ_fused_with_damping(prob, gpu, report):
     assert float(jp2.item()) == float(jp.item())
 
 
+# sub-pixel splats behind others have Jacobi diagonals near 1e-29: Algorithm
+# 1 without a minimum diagonal then steps by b / M with b itself a float32
+# rounding residue (the oracle's direction is 2.6e11 on one such parameter);
+# the dense problems check PCG with the minimum diagonal instead
+# (test_pcg_with_diag_floor)
+UNFLOORED_PCG_SKIP = {"dense", "dense_tall"}
+
+
 def test_pcg_direction(prob, gpu, report):
+    if prob["id"] in UNFLOORED_PCG_SKIP:
+        pytest.skip("Jacobi diagonals near 1e-29 (sub-pixel occluded splats): checked with a minimum diagonal")
     cfg = prob["cfg"]
     J = prob["J"]
     b_ref, M_ref, out = oracle_pcg(J, prob["target"], cfg["lam"], cfg["n_iters"])
@@ -244,6 +286,8 @@ def test_pcg_direction(prob, gpu, report):
 
 def test_pcg_paper_stopping_rule(prob, gpu, report):
     """Algorithm 1's break: ||r||^2 < 0.01 ||b||^2 ends the loop on the device."""
+    if prob["id"] in UNFLOORED_PCG_SKIP:
+        pytest.skip("Jacobi diagonals near 1e-29 (sub-pixel occluded splats): checked with a minimum diagonal")
     J = prob["J"]
     _, _, out = oracle_pcg(J, prob["target"], 1e-2, 50, tol=0.01, tol_mode=solve.TOL_PAPER_SQUARED)
     B = gpu["B"]
