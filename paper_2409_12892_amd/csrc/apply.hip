@@ -22,7 +22,8 @@ __device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i 
 
 // One workgroup per tile.  The tile's segments are taken in chunks of
 // kGramChunk with their Gram sums in LDS; for every block the chunk's runs
-// (found by binary search: a block lists its pieces in depth order) are
+// (a lower-bound search by one wave per block: a block lists its pieces in
+// depth order) are
 // taken one per lane, each lane sums its run's 8 pairs, a segmented scan
 // over the wave (runs ascend with the lane) leaves one LDS add per segment
 // piece and wave, and the chunk's sums are written at the segments' list
@@ -46,18 +47,12 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
     const int64_t sb = c.tile_seg_off[t], se = c.tile_seg_off[t + 1];
     const int nseg = (int)(se - sb);
     const TilePlanes<DT> P(c, pb, pe);
-    const uint32_t* rseg = c.run_seg + pb / kRun;
+    __shared__ int s_lohi[kTileBlocks][2];
     int brun[kTileBlocks + 1];
     brun[0] = 0;
 #pragma unroll
     for (int b = 0; b < kTileBlocks; ++b) brun[b + 1] = brun[b] + (int)(c.tile_blk[t * kTileBlocks + b] / kRun);
-    auto lower = [&](int r0, int r1, uint32_t key) -> int {
-        while (r0 < r1) {
-            const int m = (r0 + r1) >> 1;
-            if (rseg[m] < key) r0 = m + 1; else r1 = m;
-        }
-        return r0;
-    };
+    const int wid = __builtin_amdgcn_readfirstlane(tid / kWave);
     for (int c0 = 0; c0 < nseg; c0 += kGramChunk) {
         const int cn = min(nseg - c0, kGramChunk);
         __syncthreads();
@@ -68,10 +63,31 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
 #pragma unroll
             for (int k = 0; k < kGram; ++k) s_g[k][i] = 0.0f;
         }
+        // the chunk's runs in each block (wave b searches block b; kBlock
+        // holds one wave per block)
+        static_assert(kBlock / kWave == kTileBlocks, "one wave per block");
+        {
+            int bb = 0;
+#pragma unroll
+            for (int k = 1; k < kTileBlocks; ++k) bb = wid == k ? k : bb;
+            int lo = brun[0], hi = brun[1];
+#pragma unroll
+            for (int k = 1; k < kTileBlocks; ++k)
+                if (bb == k) {
+                    lo = brun[k];
+                    hi = brun[k + 1];
+                }
+            const int rl = run_lower_bound(P.seg, lo, hi, (uint32_t)(sb + c0), lane);
+            const int rh = run_lower_bound(P.seg, rl, hi, (uint32_t)(sb + c0 + cn), lane);
+            if (lane == 0) {
+                s_lohi[bb][0] = rl;
+                s_lohi[bb][1] = rh;
+            }
+        }
         __syncthreads();
         for (int b = 0; b < kTileBlocks; ++b) {
-            const int lo = lower(brun[b], brun[b + 1], (uint32_t)(sb + c0));
-            const int hi = lower(lo, brun[b + 1], (uint32_t)(sb + c0 + cn));
+            const int lo = s_lohi[b][0];
+            const int hi = s_lohi[b][1];
             // rounds start on a window of the block (no piece is split
             // between waves; runs before lo belong to earlier chunks), and a
             // barrier ends each block: one addition per segment and block

@@ -210,6 +210,30 @@ struct TilePlanes {
     }
 };
 
+// First run in [lo, hi) of a tile whose segment word is >= key (hi if
+// none), for runs whose segments ascend (a block's runs: pieces in segment
+// order, a gap run carrying the next piece's segment).  The wave probes 64
+// runs at a time, so a block of up to 2^18 runs takes three rounds of
+// dependent loads.  Wave-uniform arguments; every lane returns the result.
+__device__ __forceinline__ int run_lower_bound(__amdgpu_buffer_rsrc_t seg, int lo, int hi, uint32_t key, int lane) {
+    while (hi > lo) {
+        const int step = (hi - lo + kWave - 1) / kWave;
+        const int r = lo + lane * step;
+        const bool ge = r >= hi || __builtin_amdgcn_raw_buffer_load_b32(seg, r * 4, 0, 0) >= key;
+        const uint64_t m = __ballot(ge);
+        // runs before the first probe at or above the key are below it
+        const int f = m ? __ffsll((unsigned long long)m) - 1 : kWave;
+        if (step == 1) {
+            lo = hi = min(hi, lo + f);
+        } else {
+            const int nlo = f == 0 ? lo : lo + (f - 1) * step + 1;
+            hi = min(hi, lo + f * step);
+            lo = nlo;
+        }
+    }
+    return lo;
+}
+
 // Tile pass.  One workgroup of 512 threads (8 waves) per tile.  The tile's
 // pairs are stored block after block (a block is the 64 pixels of one
 // raster wave); within a block the splats' pieces in segment order, each
@@ -426,10 +450,8 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         }
     };
     // the runs of segments [s_lo, s_hi) (global ids) in each block into
-    // rng, and the J windows of those ranges into wpre: a block's runs ascend
-    // in segment (a gap run carries the next piece's segment), so each bound
-    // is a lower bound over the block's run segments, found by wave 2 b + e
-    // probing 64 runs at a time
+    // rng (each bound a lower bound over the block's run segments, by wave
+    // 2 b + e), and the J windows of those ranges into wpre
     auto find_ranges = [&](int64_t s_lo, int64_t s_hi, bool whole) {
         if (whole) {
             if (tid < kTileBlocks) {
@@ -439,24 +461,8 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         } else if (wid < 2 * kTileBlocks) {
             const int b = wid >> 1;
             const uint32_t key = (uint32_t)((wid & 1) ? s_hi : s_lo);
-            int lo = br[b], hi = br[b + 1];          // answer in [lo, hi]
-            while (hi > lo) {
-                const int step = (hi - lo + kWave - 1) / kWave;
-                const int r = lo + lane * step;
-                const bool ge = r >= hi || __builtin_amdgcn_raw_buffer_load_b32(P.seg, r * 4, 0, 0) >= key;
-                const uint64_t m = __ballot(ge);
-                // runs before the first probe at or above the key are below it
-                const int f = m ? __ffsll((unsigned long long)m) - 1 : kWave;
-                const int nlo = f == 0 ? lo : lo + (f - 1) * step + 1;
-                const int nhi = min(hi, lo + f * step);
-                if (step == 1) {
-                    lo = hi = min(hi, lo + f);
-                } else {
-                    lo = nlo;
-                    hi = nhi;
-                }
-            }
-            if (lane == 0) rng[b][wid & 1] = lo;
+            const int r = run_lower_bound(P.seg, br[b], br[b + 1], key, lane);
+            if (lane == 0) rng[b][wid & 1] = r;
         }
         __syncthreads();
         if (tid == 0) {
