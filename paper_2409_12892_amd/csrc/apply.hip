@@ -31,7 +31,7 @@ __device__ __forceinline__ constexpr int tri6(int i, int k) { return i * 6 - (i 
 constexpr int kGramChunk = 256;
 
 template <int DT>
-__global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __restrict__ gram) {
+__global__ void __launch_bounds__(kBlock, 3) k_gram_tile(CacheView c, float* __restrict__ gram) {
     using S = Store<DT>;
     __shared__ float s_g[kGram][kGramChunk];
     __shared__ float s_sp[6][kGramChunk];
@@ -92,15 +92,18 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
             // between waves; runs before lo belong to earlier chunks), and a
             // barrier ends each block: one addition per segment and block
             if (b > 0) __syncthreads();
-            for (int base = brun[b] + ((lo - brun[b]) & ~(kWinRuns - 1)); base < hi; base += kBlock) {
-                const int run = base + tid;
+            // the next round's run loads while this round's is summed
+            const int start = brun[b] + ((lo - brun[b]) & ~(kWinRuns - 1));
+            RunLoad<DT> nx;
+            if (start < hi) P.run_if(start + tid, nx, start + tid < hi);
+            for (int base = start; base < hi; base += kBlock) {
+                const RunLoad<DT> L = nx;
+                if (base + kBlock < hi) P.run_if(base + kBlock + tid, nx, base + kBlock + tid < hi);
                 float acc[kGram];
 #pragma unroll
                 for (int k = 0; k < kGram; ++k) acc[k] = 0.0f;
                 int key = kGramChunk;                 // no run
-                if (run < hi) {
-                    RunLoad<DT> L;
-                    P.run(run, L);
+                {
                     const int64_t sl = (int64_t)L.seg - (sb + c0);
                     if (sl >= 0 && sl < cn) key = (int)sl;
                     if (key < kGramChunk) {
@@ -155,9 +158,13 @@ __global__ void __launch_bounds__(kBlock) k_gram_tile(CacheView c, float* __rest
                 }
                 const int next = __shfl_down(key, 1, kWave);
                 wave_segmented_scan<kGram>(acc, lane, segment_head((uint32_t)key, lane));
-                if (key < kGramChunk && (lane == kWave - 1 || next != key)) {
+                // one piece per segment and block, summed by one wave: a
+                // plain addition by the piece's last lane (a group of gap runs
+                // carries the next window's piece's segment and no pair: it
+                // adds nothing, so no two lanes add to a segment at once)
+                if (key < kGramChunk && (lane == kWave - 1 || next != key) && acc[kGram - 1] != 0.0f) {
 #pragma unroll
-                    for (int k = 0; k < kGram; ++k) atomicAdd(&s_g[k][key], acc[k]);
+                    for (int k = 0; k < kGram; ++k) s_g[k][key] += acc[k];
                 }
             }
         }
