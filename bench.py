@@ -576,7 +576,7 @@ def bench_learned(args, B, sg, torch) -> dict:
     }
 
 
-def bench_deploy(args, B, sg, torch) -> dict:
+def bench_deploy(args, B, sg, torch, brief: bool = False) -> dict:
     """One LM step's solve phase at the learned-preconditioner workload
     (3M Gaussians, SH 3, four subsets of 40 views 1280x720), to a relative
     residual of 1e-2 in each subset, in two forms:
@@ -593,6 +593,8 @@ def bench_deploy(args, B, sg, torch) -> dict:
              the persistent PCG kernel;
       bf16_learned_sequential: bfloat16 and the learned scaling, one subset
              at a time in one reused cache.
+    brief: the plain and full forms only (the comparison that the default
+    bench line carries).
     The cache handles persist from the warm-up run into the timed run (as in
     an LM loop), and the library's memory comes from PyTorch's caching
     allocator (--deploy-alloc torch, the default), so the transients that a
@@ -711,10 +713,11 @@ def bench_deploy(args, B, sg, torch) -> dict:
     mem_tables = {}            # device bytes per buffer: one subset's cache (and the scratch handle)
 
     res = {}
-    forms = [("plain", lambda: sequential("f32", False, "plain")),
-             ("bf16_learned_sequential", lambda: sequential("bf16", True, "seq")),
-             ("full", lambda: full_form("bf16", group, 0, full_h, "full", 2))]
-    if thin_k > 0:
+    forms = [("plain", lambda: sequential("f32", False, "plain"))]
+    if not brief:
+        forms.append(("bf16_learned_sequential", lambda: sequential("bf16", True, "seq")))
+    forms.append(("full", lambda: full_form("bf16", group, 0, full_h, "full", 2)))
+    if thin_k > 0 and not brief:
         forms.append(("full_thin", lambda: full_form("f32", 4, thin_k, thin_h, "thin", 3)))
     for name, fn in forms:
         fn()                                    # warm-up: allocations and code objects
@@ -735,7 +738,8 @@ def bench_deploy(args, B, sg, torch) -> dict:
             hl[k] = None
         torch.cuda.empty_cache()
     dp, df = res["plain"].pop("delta"), res["full"].pop("delta")
-    res["bf16_learned_sequential"].pop("delta")
+    if "bf16_learned_sequential" in res:
+        res["bf16_learned_sequential"].pop("delta")
     dt = res["full_thin"].pop("delta") if "full_thin" in res else None
     if args.deploy_alloc == "torch":
         B.use_torch_allocator(False)
@@ -760,7 +764,7 @@ def bench_deploy(args, B, sg, torch) -> dict:
                    "N": N, "subsets": 4, "views": 40, "width": 1280, "height": 720, "lambda": lam,
                    "diag_floor": floor, "tol_relative": tol, "tile": f"{tile[0]}x{tile[1]}", "group": group,
                    "allocator": args.deploy_alloc},
-        "plain": res["plain"], "full": res["full"], "bf16_learned_sequential": res["bf16_learned_sequential"],
+        "plain": res["plain"], "full": res["full"], "bf16_learned_sequential": res.get("bf16_learned_sequential"),
         "full_thin": res.get("full_thin"),
         "speedup_full_vs_plain": round(res["plain"]["ms"] / res["full"]["ms"], 3),
         "speedup_full_thin_vs_plain": (round(res["plain"]["ms"] / res["full_thin"]["ms"], 3)
@@ -789,6 +793,9 @@ def main() -> int:
     ap.add_argument("--deploy-thin", type=int, default=32,
                     help="--config deploy: also run the full form with thinned caches (this window; 0: not), "
                          "all four subsets resident, persistent-kernel PCG")
+    ap.add_argument("--deploy-sub", type=int, default=1,
+                    help="paper workload: after the timed steps, also run the plain-vs-full solve-phase "
+                         "comparison of --config deploy (plain and full forms) and attach it as `deploy`")
     ap.add_argument("--deploy-group", type=int, default=4,
                     help="subsets held and solved together by the full form of --config deploy")
     ap.add_argument("--precond", default="jacobi", choices=["jacobi", "block"],
@@ -964,8 +971,22 @@ def main() -> int:
         except Exception as e:  # the GPU result stands even if the CPU sample fails
             out["cpu_baseline"] = {"value": None, "error": repr(e)}
         log("cpu baseline done")
-    print(json.dumps(out), flush=True)
     solver.close()
+    if args.deploy_sub and args.config == "paper":
+        # the second comparison: BF16 + batched + learned solve phase against
+        # the plain float32 Jacobi form at the learned-preconditioner workload
+        del solver, x, target
+        torch.cuda.empty_cache()
+        log("deploy comparison: plain and full forms at the learned-preconditioner workload")
+        try:
+            dep = bench_deploy(args, B, sg, torch, brief=True)
+            out["deploy"] = {k: dep[k] for k in ("metric", "value", "unit", "config", "plain", "full",
+                                                "speedup_full_vs_plain", "combined_direction_rel_diff",
+                                                "training")}
+        except Exception as e:  # the headline line stands even if the comparison fails
+            out["deploy"] = {"value": None, "error": repr(e)}
+        log("deploy comparison done")
+    print(json.dumps(out), flush=True)
     return 0
 
 
