@@ -185,43 +185,58 @@ __global__ void k_fill_f32(float* __restrict__ p, int64_t n, float v) {
 // parameter j has power coefficients co = (L[.][j], Jdir[.][j]) and its
 // squared Jacobian column norm is the quadratic form of the (Gaussian,
 // view)'s Gram values; an SH coefficient (k, ch) has co = Y_k e_ch on the
-// colour slots.  One thread per Gaussian.
+// colour slots.  The geometric forms (float64) are evaluated with one thread
+// per (Gaussian, view) into geo[j][gv]; one thread per Gaussian then sums
+// them over its views, in view order, and forms the SH entries.
+template <int DEG>
+__global__ void __launch_bounds__(kBlock) k_diag_geo_gv(CacheView c, const float* __restrict__ gvgram,
+                                                       double* __restrict__ geo) {
+    const int64_t gv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (gv >= c.n_gv) return;
+    const int64_t ls = c.lin_stride;
+    const float* H = gvgram + gv * kGram;
+    double h[kGram - 1];
+#pragma unroll
+    for (int k = 0; k < kGram - 1; ++k) h[k] = (double)H[k];
+#pragma unroll
+    for (int j = 0; j < 11; ++j) {
+        double co[9];
+#pragma unroll
+        for (int i = 0; i < 6; ++i) co[i] = (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv];
+#pragma unroll
+        for (int ch = 0; ch < 3; ++ch) co[6 + ch] = j < 3 ? (double)c.lin[(int64_t)(kLinJdir + 3 * ch + j) * ls + gv] : 0.0;
+        double q = 0.0;
+#pragma unroll
+        for (int i = 0; i < 6; ++i) {
+            q += co[i] * co[i] * h[tri6(i, i)];
+#pragma unroll
+            for (int k = i + 1; k < 6; ++k) q += 2.0 * co[i] * co[k] * h[tri6(i, k)];
+            q += 2.0 * co[i] * (h[21 + 3 * i] * co[6] + h[22 + 3 * i] * co[7] + h[23 + 3 * i] * co[8]);
+        }
+        q += h[39] * co[6] * co[6] + h[40] * co[7] * co[7] + h[41] * co[8] * co[8];
+        geo[(int64_t)j * ls + gv] = q;
+    }
+}
+
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float* __restrict__ gvgram,
-                                                      float* __restrict__ M) {
+                                                      const double* __restrict__ geo, float* __restrict__ M) {
     constexpr int K = (DEG + 1) * (DEG + 1);
-    constexpr int P = 11 + 3 * K;
     const int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (g >= c.N) return;
     const int64_t ls = c.lin_stride;
-    double dgeo_acc[11];
+    const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
 #pragma unroll
-    for (int j = 0; j < 11; ++j) dgeo_acc[j] = 0.0;
+    for (int j = 0; j < 11; ++j) {
+        double acc = 0.0;
+        for (uint32_t gv = b; gv < e; ++gv) acc += geo[(int64_t)j * ls + gv];
+        M[(int64_t)j * c.N + g] = (float)acc;
+    }
     float dsh[3 * K];
 #pragma unroll
     for (int j = 0; j < 3 * K; ++j) dsh[j] = 0.0f;
-    const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
     for (uint32_t gv = b; gv < e; ++gv) {
         const float* H = gvgram + (int64_t)gv * kGram;
-#pragma unroll
-        for (int j = 0; j < 11; ++j) {
-            double co[9];
-#pragma unroll
-            for (int i = 0; i < 6; ++i) co[i] = (double)c.lin[(int64_t)(kLinL + 11 * i + j) * ls + gv];
-#pragma unroll
-            for (int ch = 0; ch < 3; ++ch) co[6 + ch] = j < 3 ? (double)c.lin[(int64_t)(kLinJdir + 3 * ch + j) * ls + gv] : 0.0;
-            double q = 0.0;
-#pragma unroll
-            for (int i = 0; i < 6; ++i) {
-                q += co[i] * co[i] * (double)H[tri6(i, i)];
-#pragma unroll
-                for (int k = i + 1; k < 6; ++k) q += 2.0 * co[i] * co[k] * (double)H[tri6(i, k)];
-                q += 2.0 * co[i] * ((double)H[21 + 3 * i] * co[6] + (double)H[22 + 3 * i] * co[7] +
-                                    (double)H[23 + 3 * i] * co[8]);
-            }
-            q += (double)H[39] * co[6] * co[6] + (double)H[40] * co[7] * co[7] + (double)H[41] * co[8] * co[8];
-            dgeo_acc[j] += q;
-        }
 #pragma unroll
         for (int ch = 0; ch < 3; ++ch) {
             const float w = c.lin[(int64_t)(kLinMask + ch) * ls + gv] * H[39 + ch];
@@ -233,8 +248,7 @@ __global__ void __launch_bounds__(kBlock) k_diag_gauss(CacheView c, const float*
         }
     }
 #pragma unroll
-    for (int j = 0; j < P; ++j)
-        M[(int64_t)j * c.N + g] = j < 11 ? (float)dgeo_acc[j < 11 ? j : 0] : dsh[j >= 11 ? j - 11 : 0];
+    for (int j = 0; j < 3 * K; ++j) M[(int64_t)(11 + j) * c.N + g] = dsh[j];
 }
 
 // Number of (pixel, splat) pairs of each Gaussian over all views.
@@ -758,9 +772,11 @@ hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* cover
     return hipGetLastError();
 }
 
-hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s) {
+hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, double* geo, float* M, hipStream_t s) {
     dim3 b(kBlock);
-#define LM_D(D) hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, gvgram, M)
+#define LM_D(D)                                                                                          \
+    if (c.n_gv > 0) hipLaunchKernelGGL(k_diag_geo_gv<D>, dim3(grid_for(c.n_gv)), b, 0, s, c, gvgram, geo); \
+    hipLaunchKernelGGL(k_diag_gauss<D>, dim3(grid_for(c.N)), b, 0, s, c, gvgram, (const double*)geo, M)
     LM_DEG_SWITCH(c.deg, LM_D)
 #undef LM_D
     return hipGetLastError();

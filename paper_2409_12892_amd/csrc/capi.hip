@@ -1045,7 +1045,9 @@ lm_status lm_jacobi_diag(const lm_cache* c, float* M, void* stream) {
     LM_PROF("jacobi_diag", S(stream));
     lm_status st = ensure_gram(cm, S(stream));
     if (st != LM_OK) return st;
-    LM_HIP(lm::launch_jacobi_diag(c->view(), cm->gvgram.as<float>(), M, S(stream)));
+    // the chain's per-(Gaussian, view) workspace (11 doubles per record
+    // first) serves as the diagonal's scratch: no product runs meanwhile
+    LM_HIP(lm::launch_jacobi_diag(c->view(), cm->gvgram.as<float>(), cm->gvchain.as<double>(), M, S(stream)));
     return LM_OK;
 }
 

@@ -364,7 +364,8 @@ unsigned chain_blocks(int64_t N);
 constexpr int kGramValues = 43;
 hipError_t launch_gram(const CacheView& c, float* gram, float* gvgram, float* edge, uint32_t* edge_key,
                        hipStream_t s);
-hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, float* M, hipStream_t s);
+// geo: scratch of 11 doubles per (Gaussian, view) record ([11][lin_stride])
+hipError_t launch_jacobi_diag(const CacheView& c, const float* gvgram, double* geo, float* M, hipStream_t s);
 hipError_t launch_coverage(const CacheView& c, const float* gvgram, float* coverage, hipStream_t s);
 // out 0: dense blocks [n][P][P] of the selected Gaussians, or without a
 // selection of the n_sel Gaussians from g0 on; out 1: targets and mask [P][N]
