@@ -389,7 +389,8 @@ def bench_batching(args, B, sg, torch) -> dict:
     return out
 
 
-TRAIN_RUNS = 20          # seeded runs of the training scene
+TRAIN_RUNS = 20          # seeded runs of the paper-scale plain-method workload
+TRAIN_SAMPLES = 65536    # observed Gaussians drawn per run
 TRAIN_STEPS = 600        # Adam steps
 # target: the row-sum scaling unshrunk (at the learned-preconditioner workload
 # the exact targets take 22 PCG iterations unshrunk, 26 shrunk by 1/2 and 33
@@ -399,30 +400,49 @@ TRAIN_SHRINK = 1.0
 
 def train_learned_mlp(args, B, sg, torch, lam, floor):
     """The perceptron of the learned preconditioner, trained on the GPU on
-    20 seeded runs shaped like the tiny plain-method scene but with SH degree
-    3 (2,048 Gaussians, 4 views 64x64, targets rendered from perturbed
-    parameters plus pixel noise; seeds 1000..1019): per run the cache, the
-    Jacobi diagonal, the features and the exact targets (each Gaussian's
-    block rows summed over the views in float64; the unshrunk row-sum
-    scaling, TRAIN_SHRINK), then 600 Adam steps on all runs' samples."""
+    20 seeded runs of the paper-scale plain-method workload (1,000,000
+    Gaussians, SH degree 3, 32 views 1024x640; seeds 1000..1019; targets
+    rendered from the perturbed parameters plus pixel noise; the scenes are
+    drawn on host threads while the GPU processes the previous run): per
+    run the bfloat16 cache (the deployed cache type), the Jacobi diagonal,
+    the features and the exact targets (each Gaussian's block rows summed
+    over the views in float64; the unshrunk row-sum scaling, TRAIN_SHRINK)
+    of TRAIN_SAMPLES observed Gaussians drawn per run (seeded), then
+    TRAIN_STEPS Adam steps on all runs' samples."""
+    import concurrent.futures as cf
     dev = torch.device("cuda:0")
     feats, ts, masks = [], [], []
-    for r in range(TRAIN_RUNS):
-        d = sg.config_scene("tiny", deg=3, seed=1000 + r)
-        sc, cams = d["scene"], d["cams"][0]
-        x = torch.from_numpy(sc.x).to(dev)
-        target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
-        target.add_(torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev))
-        cache, _, _ = B.lm_build_cache(x, sc.sh_degree, cams, target)
-        M = B.lm_jacobi_diag(cache)
-        feats.append(B.lm_precond_features(cache, x, M))
-        t, m = B.lm_precond_targets(cache, lam, floor, shrink=TRAIN_SHRINK)
-        ts.append(t)
-        masks.append(m)
-        cache.destroy()
-    feat, t, mask = torch.cat(feats, 1), torch.cat(ts, 1), torch.cat(masks, 1)
+    gen = torch.Generator(device="cpu")
+    gen.manual_seed(2024)
+    n_obs = []
+    t_data = time.perf_counter()
+    with cf.ThreadPoolExecutor(max_workers=min(8, max(1, (os.cpu_count() or 2) // 2))) as ex:
+        futs = [ex.submit(sg.config_scene, "paper", seed=1000 + r) for r in range(TRAIN_RUNS)]
+        for r in range(TRAIN_RUNS):
+            d = futs[r].result()
+            futs[r] = None
+            sc, cams = d["scene"], d["cams"][0]
+            x = torch.from_numpy(sc.x).to(dev)
+            target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
+            target.add_(torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev))
+            del d
+            cache, _, _ = B.lm_build_cache(x, sc.sh_degree, cams, target, tile=(8, 32), cache_dtype="bf16",
+                                           want_b=False)
+            M = B.lm_jacobi_diag(cache)
+            f = B.lm_precond_features(cache, x, M)
+            t, m = B.lm_precond_targets(cache, lam, floor, shrink=TRAIN_SHRINK)
+            cache.destroy()
+            obs = torch.nonzero(m[0] > 0).flatten().cpu()
+            n_obs.append(int(obs.numel()))
+            pick = obs[torch.randperm(obs.numel(), generator=gen)[:TRAIN_SAMPLES]].to(dev)
+            feats.append(f[:, pick])
+            ts.append(t[:, pick])
+            masks.append(m[:, pick])
+            del x, target, M, f, t, m
+    data_s = time.perf_counter() - t_data
+    feat, t, mask = torch.cat(feats, 1).contiguous(), torch.cat(ts, 1).contiguous(), torch.cat(masks, 1).contiguous()
     n_samples = int(feat.shape[1])
-    log(f"training data: {TRAIN_RUNS} runs, {n_samples} Gaussians")
+    log(f"training data: {TRAIN_RUNS} runs, {n_samples} Gaussians ({data_s:.1f} s)")
     P = t.shape[0]
     trainer = B.MlpTrainer(B.mlp_init(P, seed=3), lr=3e-3)
     loss0, _ = trainer.step(feat, t, mask, lr=0.0)
@@ -437,8 +457,10 @@ def train_learned_mlp(args, B, sg, torch, lam, floor):
         f"({n_samples} samples)")
     del feat, t, mask, feats, ts, masks
     torch.cuda.empty_cache()
-    return trainer, dict(runs=TRAIN_RUNS, samples=n_samples, steps=TRAIN_STEPS, ms_per_step=round(train_ms, 3),
-                         loss_first=round(loss0.item(), 5), loss_last=round(loss1.item(), 5))
+    return trainer, dict(runs=TRAIN_RUNS, workload="1000000 Gaussians SH3, 32 views 1024x640, bf16 cache",
+                         observed_per_run=n_obs, samples=n_samples, data_s=round(data_s, 1), steps=TRAIN_STEPS,
+                         ms_per_step=round(train_ms, 3), loss_first=round(loss0.item(), 5),
+                         loss_last=round(loss1.item(), 5))
 
 
 # parameter groups (rows of x): mean, log-scale, quaternion, opacity, SH
@@ -574,6 +596,60 @@ def bench_learned(args, B, sg, torch) -> dict:
         "n_pairs": info["n_pairs"], "build_and_diag_ms": round(ws["build_ms"], 1),
         "n_fallback": int(nf.item()),
     }
+
+
+def bench_thin(args, B, sg, torch) -> dict:
+    """The thinned cache (paper section 4.4): bytes and fused J^T J tile-pass
+    time at the paper workload (float32: full cache and windows of 8 and 32)
+    and at one subset of the learned-preconditioner workload (3M Gaussians,
+    40 views 1280x720: the full bfloat16 cache against float32 thinned caches
+    with windows of 8 and 32), 8x32 tiles; each tile pass timed over
+    `--steps` products after one untimed product."""
+    dev = torch.device("cuda:0")
+    out = []
+    for name, subsets, variants in (("paper", None, (("f32", 0), ("f32", 8), ("f32", 32))),
+                                    ("learned", [(40, 1280, 720)], (("bf16", 0), ("f32", 8), ("f32", 32)))):
+        d = sg.config_scene(name, subsets=subsets)
+        sc, cams = d["scene"], d["cams"][0]
+        x = torch.from_numpy(sc.x).to(dev)
+        target = B.lm_render(torch.from_numpy(d["x_star"]).to(dev), sc.sh_degree, cams)
+        target.add_(torch.from_numpy(np.concatenate([n.ravel() for n in d["noise"][0]])).to(dev))
+        del d
+        p = torch.full_like(x, 0.01)
+        for dt, K in variants:
+            cache, b, _ = B.lm_build_cache(x, sc.sh_degree, cams, target, tile=(8, 32), cache_dtype=dt, thin_window=K)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            cache, b, _ = B.lm_build_cache(x, sc.sh_degree, cams, target, tile=(8, 32), cache_dtype=dt, thin_window=K,
+                                           cache=cache, b=b)
+            torch.cuda.synchronize()
+            build_ms = (time.perf_counter() - t0) * 1e3
+            B.lm_apply_JtJ(cache, p)
+            torch.cuda.synchronize()
+            B.lm_profile_read()
+            B.lm_profile_enable(True)
+            for _ in range(args.steps):
+                B.lm_apply_JtJ(cache, p)
+            torch.cuda.synchronize()
+            prof = B.lm_profile_read()
+            B.lm_profile_enable(False)
+            n, tms = prof.get("apply_tile_JtJ", (0, 0.0))
+            info = cache.info()
+            r = dict(workload=name, cache_dtype=dt, thin_window=K, n_pairs=info["n_pairs"],
+                     cache_bytes=info["cache_bytes"], device_bytes=info["device_bytes"],
+                     cache_bytes_per_pair=round(info["cache_bytes"] / max(info["n_pairs"], 1), 3),
+                     build_ms=round(build_ms, 1), tile_pass_ms=round(tms / max(n, 1), 3),
+                     product_ms=round(sum(v[1] for v in prof.values()) / max(args.steps, 1), 3))
+            log(f"{name} {dt} K={K}: {r['cache_bytes'] / 1e9:.2f} GB cache ({r['cache_bytes_per_pair']} B/pair), "
+                f"tile pass {r['tile_pass_ms']} ms, build {r['build_ms']} ms")
+            out.append(r)
+            cache.destroy()
+            del b
+            torch.cuda.empty_cache()
+        del x, target, p
+        torch.cuda.empty_cache()
+    return {"metric": "thinned cache: bytes and J^T J tile-pass ms against the full cache", "value": None,
+            "unit": "ms", "n_gpus": 1, "steps": args.steps, "data": "synthetic", "results": out}
 
 
 def bench_deploy(args, B, sg, torch, brief: bool = False) -> dict:
@@ -720,8 +796,9 @@ def bench_deploy(args, B, sg, torch, brief: bool = False) -> dict:
     if thin_k > 0 and not brief:
         forms.append(("full_thin", lambda: full_form("f32", 4, thin_k, thin_h, "thin", 3)))
     for name, fn in forms:
-        fn()                                    # warm-up: allocations and code objects
-        torch.cuda.empty_cache()
+        # warm-up: allocations and code objects; the memory it freed stays in
+        # the caching allocator's pool for the timed run, as in an LM loop
+        fn()
         torch.cuda.synchronize()
         phases.clear()
         t0 = time.perf_counter()
@@ -843,6 +920,9 @@ def main() -> int:
         return 0
     if args.config == "deploy":
         print(json.dumps(bench_deploy(args, B, sg, torch)), flush=True)
+        return 0
+    if args.config == "thin":
+        print(json.dumps(bench_thin(args, B, sg, torch)), flush=True)
         return 0
     cfg = dict(sg.CONFIGS[args.config])
     subsets = cfg["subsets"][:1]
