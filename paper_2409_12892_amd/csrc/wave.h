@@ -11,28 +11,36 @@ template <int CTRL, int ROWMASK>
 __device__ __forceinline__ float dpp_mov(float v) {
     return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, ROWMASK, 0xF, false));
 }
+// Row shift across all rows: lanes whose source is outside the row read 0.
+template <int CTRL>
+__device__ __forceinline__ float dpp_shr(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, true));
+}
 
 // Segmented inclusive sum across the wave: segments are contiguous lane
 // ranges and head is the first lane of this lane's segment; afterwards lane
 // l holds the sum over lanes [head, l].  Row shifts 1, 2, 4, 8 scan the rows
 // of 16; broadcasts of lane 15 (to rows 1, 3) and lane 31 (to rows 2, 3)
-// join the rows.
+// join the rows.  Each step adds the moved value times a 0/1 factor (the
+// lane's segment reaches that far back): an exact add or no change, in one
+// multiply-add that takes the lane move as its operand.
 template <int NV>
 __device__ __forceinline__ void wave_segmented_scan(float (&m)[NV], int lane, int head) {
-    const bool c1 = lane - 1 >= head, c2 = lane - 2 >= head, c4 = lane - 4 >= head, c8 = lane - 8 >= head;
-    const bool c16 = (lane & ~15) - 1 >= head, c32 = 31 >= head;
+    const float c1 = lane - 1 >= head ? 1.0f : 0.0f, c2 = lane - 2 >= head ? 1.0f : 0.0f;
+    const float c4 = lane - 4 >= head ? 1.0f : 0.0f, c8 = lane - 8 >= head ? 1.0f : 0.0f;
+    const float c16 = (lane & ~15) - 1 >= head ? 1.0f : 0.0f, c32 = 31 >= head ? 1.0f : 0.0f;
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x111, 0xF>(m[k]); m[k] += c1 ? o : 0.0f; }
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x111>(m[k]), c1, m[k]);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x112, 0xF>(m[k]); m[k] += c2 ? o : 0.0f; }
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x112>(m[k]), c2, m[k]);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x114, 0xF>(m[k]); m[k] += c4 ? o : 0.0f; }
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x114>(m[k]), c4, m[k]);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x118, 0xF>(m[k]); m[k] += c8 ? o : 0.0f; }
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x118>(m[k]), c8, m[k]);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x142, 0xA>(m[k]); m[k] += c16 ? o : 0.0f; }
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_mov<0x142, 0xA>(m[k]), c16, m[k]);
 #pragma unroll
-    for (int k = 0; k < NV; ++k) { const float o = dpp_mov<0x143, 0xC>(m[k]); m[k] += c32 ? o : 0.0f; }
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_mov<0x143, 0xC>(m[k]), c32, m[k]);
 }
 
 // First lane of this lane's segment, given per-lane segment keys that are
