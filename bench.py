@@ -41,7 +41,15 @@ def traffic_file(dtype: str) -> str:
     """Committed rocprofv3 counter summary of the fused pass for one cache type."""
     return os.path.join(ROOT, "profiles", f"apply_tile_JtJ_paper_{dtype}_traffic.txt")
 
-APPLY_SRC = os.path.join(ROOT, "paper_2409_12892_amd", "csrc", "products.h")   # the tile pass
+# the tile pass and the wave sums it uses
+APPLY_SRC = [os.path.join(ROOT, "paper_2409_12892_amd", "csrc", f) for f in ("products.h", "wave.h")]
+
+
+def apply_src_sha() -> str:
+    h = hashlib.sha256()
+    for f in APPLY_SRC:
+        h.update(open(f, "rb").read())
+    return h.hexdigest()
 
 
 def log(msg: str) -> None:
@@ -83,7 +91,7 @@ def read_traffic(alg_bytes: int, tile: str, dtype: str):
         if "=" in line and not line.lstrip().startswith("#"):
             k, v = line.split("=", 1)
             kv[k.strip()] = v.strip()
-    src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
+    src = apply_src_sha()
     if kv.get("apply_src_sha256") != src or kv.get("tile") != tile or kv.get("cache_dtype") != dtype:
         return None
     try:
@@ -137,7 +145,7 @@ def summarize_pmc(fetch_dir: str, write_dir: str, command: str, tile: str, dtype
         res[tag] = dict(kib_per_launch=a, launches=na, copy_kib=cp, copy_launches=nc, scale=scale,
                         read_kib=rd, read_launches=nr, bytes_per_launch=a * 1024.0 * scale)
     total = res["fetch"]["bytes_per_launch"] + res["write"]["bytes_per_launch"]
-    src = hashlib.sha256(open(APPLY_SRC, "rb").read()).hexdigest()
+    src = apply_src_sha()
     gib = COPY_BYTES / 2**30
     with open(traffic_file(dtype), "w") as f:
         f.write(f"# HBM traffic of k_apply_tile<J^T J fused, {dtype} cache> at the paper workload, {tile} tiles\n")
@@ -474,7 +482,7 @@ def bench_learned(args, B, sg, torch) -> dict:
     workload, one subset at full size (3M Gaussians, SH 3, 40 views
     1280x720, bfloat16 cache; the workload's four subsets would not leave
     room for the build transients).  The perceptron is trained on the GPU on
-    20 seeded tiny SH-3 runs (train_learned_mlp); then, on the workload
+    20 seeded runs of the paper-scale workload (train_learned_mlp); then, on the workload
     subset, Algorithm 1 runs to a relative residual of 1e-2 with the Jacobi,
     the learned and the exact-target scalings (shrink 1/2, unshrunk, and the
     per-parameter means alone), with constant rescalings of each parameter

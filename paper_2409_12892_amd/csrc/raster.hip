@@ -56,10 +56,44 @@ constexpr int NW = kBlock / kWave;
 
 __device__ __forceinline__ uint64_t lanemask_lt() { return (1ull << __lane_id()) - 1ull; }
 __device__ __forceinline__ uint32_t pad8(uint32_t n) { return (n + 7u) & ~7u; }
-// Start of a piece of len padded pairs placed at block offset e: moved to
-// the next window when it would cross one (len <= 64 <= kWindow).
-__device__ __forceinline__ uint32_t place_piece(uint32_t e, uint32_t len) {
-    return (e & (kWindow - 1)) + len > kWindow ? (e + kWindow - 1) & ~(kWindow - 1) : e;
+// Placement of a block's pieces in depth order: a piece of len padded pairs
+// (len <= 64 <= kWindow) starts where the previous one ends, moved to the
+// next window when it would cross one.  64 consecutive pieces at once (one
+// wave; lane j holds piece j's padded length, 0 for none): an exclusive scan
+// of the lengths puts each piece at the end of the one before; then, lane
+// by lane in order, the first piece that would cross a window moves to the
+// next one and every later piece moves with it.  gap: the end of the
+// previous piece; off: this piece's start; returns the block's new end (in
+// every lane).  With windows false no piece moves.
+__device__ __forceinline__ uint32_t place_wave(uint32_t e, uint32_t len, bool windows, uint32_t& gap,
+                                               uint32_t& off) {
+    const int lane = __lane_id();
+    uint32_t inc = len;
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        const uint32_t o = __shfl_up(inc, d, kWave);
+        if (lane >= d) inc += o;
+    }
+    const uint32_t ex = inc - len;
+    uint32_t prev = 0, own = 0;       // moves of the earlier pieces, of this one
+    if (windows) {
+        int fixed = -1;               // lanes up to here are placed
+        for (;;) {
+            const uint32_t st = e + ex + prev;
+            const bool cross = lane > fixed && len > 0 && (st & (kWindow - 1)) + len > kWindow;
+            const uint64_t m = __ballot(cross);
+            if (m == 0ull) break;
+            const int f = __ffsll((unsigned long long)m) - 1;
+            const uint32_t sf = (uint32_t)__builtin_amdgcn_readlane((int)st, f);
+            const uint32_t add = kWindow - (sf & (kWindow - 1));
+            if (lane == f) own = add;
+            if (lane > f) prev += add;
+            fixed = f;
+        }
+    }
+    gap = e + ex + prev;
+    off = gap + own;
+    return (uint32_t)__builtin_amdgcn_readlane((int)(off + len), kWave - 1);
 }
 
 template <bool FILL, int DT, bool THIN>
@@ -182,17 +216,21 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             }
             if (lane == kWave - 1) s_scan4[wid][2] = iac;
             __syncthreads();
-            if (tid < NW) {
-                uint32_t e = s_blk[tid];
-                for (int j = 0; j < nb; ++j) {
-                    const uint32_t cj = (s_cnt[j] >> (8 * tid)) & 0xFFu;
+            {
+                // wave w places block w's pieces of the batch, 64 at a time
+                uint32_t e = s_blk[wid];
+                for (int j0 = 0; j0 < nb; j0 += kWave) {
+                    const int j = j0 + lane;
+                    const uint32_t cj = j < nb ? (s_cnt[j] >> (8 * wid)) & 0xFFu : 0u;
                     const uint32_t len = THIN ? (cj ? 1u : 0u) : pad8(cj);
-                    const uint32_t st = (len && !THIN) ? place_piece(e, len) : e;
-                    s_egap[j][tid] = s_bbase[tid] + e;
-                    s_eoff[j][tid] = s_bbase[tid] + st;
-                    e = st + len;
+                    uint32_t gap, off;
+                    e = place_wave(e, len, !THIN, gap, off);
+                    if (j < nb) {
+                        s_egap[j][wid] = s_bbase[wid] + gap;
+                        s_eoff[j][wid] = s_bbase[wid] + off;
+                    }
                 }
-                s_blk[tid] = e;
+                if (lane == 0) s_blk[wid] = e;
             }
             uint32_t bac = 0, tac = 0;
 #pragma unroll
@@ -354,13 +392,18 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 s_scan4[wid][2] = act;
                 s_scan4[wid][3] = real;
             }
-            if (tid < NW) {
-                uint32_t e = s_blk[tid];
-                for (int j = 0; j < nb; ++j) {
-                    const uint32_t len = pad8(s_wc[j][tid]);
-                    if (len) e = THIN ? e + 1 : place_piece(e, len) + len;
+            {
+                // wave w: block w's padded total, pieces placed as the fill
+                // pass places them
+                uint32_t e = s_blk[wid];
+                for (int j0 = 0; j0 < nb; j0 += kWave) {
+                    const int j = j0 + lane;
+                    const uint32_t c = j < nb ? (uint32_t)s_wc[j][wid] : 0u;
+                    const uint32_t len = THIN ? (c ? 1u : 0u) : pad8(c);
+                    uint32_t gap, off;
+                    e = place_wave(e, len, !THIN, gap, off);
                 }
-                s_blk[tid] = e;
+                if (lane == 0) s_blk[wid] = e;
             }
             __syncthreads();
             if (tid == 0) {
