@@ -313,9 +313,11 @@ namespace {
 inline hipStream_t S(void* s) { return (hipStream_t)s; }
 
 // Build the cache up to and including the count pass (projection, binning,
-// sort, forward render, residuals).  render_only stops there.
+// sort, forward render, residuals).  layout: also the per-entry and
+// (Gaussian, view) counts and the block layout that the fill pass of a build
+// reads (renders and residual norms pass false).
 lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cams, int32_t V, const float* target,
-                        const lm_options* opts, hipStream_t s) {
+                        const lm_options* opts, hipStream_t s, bool layout) {
     using namespace lm;
     LM_CHECK(scene && cams && V > 0 && V <= kMaxViews, LM_ERR_INVALID_ARG, "lm_build_cache: bad scene/cameras");
     LM_CHECK(scene->x && scene->N > 0, LM_ERR_INVALID_ARG, "lm_build_cache: empty scene");
@@ -479,6 +481,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     ra.vals = c->sorted_vals();
     ra.rec64 = c->rec64.as<double>();
     ra.N = N; ra.V = V; ra.TW = TW; ra.TH = TH;
+    ra.layout = layout ? 1 : 0;
     ra.target = target;
     ra.entry_cnt = c->entry_cnt.as<uint32_t>();
     ra.pixC = c->pixC.as<double>();
@@ -884,7 +887,7 @@ lm_status lm_build_cache(const lm_scene* scene, const lm_camera* cams, int32_t V
         LM_CHECK(scratch != c, LM_ERR_INVALID_ARG, "lm_build_cache: the scratch handle is the cache itself");
         c->swap_build_buffers(*scratch);
     }
-    lm_status st = build_forward(c, scene, cams, V, target, opts, s);
+    lm_status st = build_forward(c, scene, cams, V, target, opts, s, true);
     if (st == LM_OK) st = build_fill(c, s);
     if (st == LM_OK && F_sqnorm) {
         hipError_t e = lm::reduce_f64(c->fsq_part.as<double>(), c->n_tiles, F_sqnorm, s);
@@ -1610,7 +1613,7 @@ lm_status lm_render(const lm_scene* scene, const lm_camera* cams, int32_t V, con
     lm_cache* c = new (std::nothrow) lm_cache();
     LM_CHECK(c, LM_ERR_HIP, "out of host memory");
     hipStream_t s = S(stream);
-    lm_status st = build_forward(c, scene, cams, V, nullptr, opts, s);
+    lm_status st = build_forward(c, scene, cams, V, nullptr, opts, s, false);
     if (st == LM_OK) {
         hipError_t e = hipMemcpyAsync(image, c->resid.p, sizeof(float) * 3 * c->n_pix, hipMemcpyDeviceToDevice, s);
         if (e == hipSuccess) e = hipStreamSynchronize(s);
@@ -1638,7 +1641,7 @@ lm_status lm_residual_sqnorm(const lm_scene* scene, const lm_camera* cams, int32
     }
     bind_ctx(c);
     hipStream_t s = S(stream);
-    lm_status st = build_forward(c, scene, cams, V, target, opts, s);
+    lm_status st = build_forward(c, scene, cams, V, target, opts, s, false);
     if (st == LM_OK) {
         hipError_t e = lm::reduce_f64(c->fsq_part.as<double>(), c->n_tiles, F_sqnorm, s);
         if (e != hipSuccess) {
@@ -1762,7 +1765,7 @@ lm_status lm_objective_value(const lm_scene* scene, const lm_camera* cams, int32
     }
     bind_ctx(c);
     hipStream_t s = S(stream);
-    st = build_forward(c, scene, cams, V, target, opts, s);
+    st = build_forward(c, scene, cams, V, target, opts, s, false);
     if (st == LM_OK) {
         if (obj->kind == LM_OBJ_L2) {
             hipError_t e = lm::reduce_f64(c->fsq_part.as<double>(), c->n_tiles, E, s);

@@ -215,6 +215,7 @@ struct RasterArgs {
     int64_t N;
     int32_t V, TW, TH;
     // count pass
+    int32_t layout;            // 1: a build (per-entry counts, (g, v) counts, block layout); 0: render only
     const float* target;       // [V][3][H][W] or nullptr (render only)
     uint32_t* entry_cnt;       // [K]
     double* pixC;              // [3][n_pix]

@@ -371,7 +371,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             }
         }
         __syncthreads();
-        if (!FILL) {
+        if (!FILL && a.layout) {
             // per-entry counts, per-block padded totals (pieces placed in
             // depth order as the fill pass places them), active entries and
             // real pairs of the batch, and the (Gaussian, view) segment counts
@@ -447,11 +447,13 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             double s = 0.0;
             for (int w = 0; w < NW; ++w) s += s_red[w];
             a.fsq_part[t] = s;
-            a.tile_pairs[t] = s_blk[0] + s_blk[1] + s_blk[2] + s_blk[3];
-            for (int w = 0; w < NW; ++w) a.tile_blk[t * kTileBlocks + w] = s_blk[w];
-            a.tile_segs[t] = s_run[1];
-            a.tile_real[t] = s_run[2];
-            if (THIN) {
+            if (a.layout) {
+                a.tile_pairs[t] = s_blk[0] + s_blk[1] + s_blk[2] + s_blk[3];
+                for (int w = 0; w < NW; ++w) a.tile_blk[t * kTileBlocks + w] = s_blk[w];
+                a.tile_segs[t] = s_run[1];
+                a.tile_real[t] = s_run[2];
+            }
+            if (THIN && a.layout) {
                 uint32_t nck = 0;
                 for (int w = 0; w < NW; ++w) nck += s_scan4[w][0];
                 a.tile_ck[t] = nck;
