@@ -172,7 +172,7 @@ using lm::DevBuf;
     X(keycnt) X(keyoff) X(keys) X(vals) X(keys_alt) X(vals_alt) \
     X(sort_tmp) X(scan_tmp) X(rkeys) X(rvals) X(rkeys_alt) X(rvals_alt) \
     X(cnt_sorted) X(kept_blk) X(kept_off) X(kept_mask) X(tile_start) X(entry_cnt) \
-    X(pixC) X(ncontrib) X(resid) X(fsq_part) X(tile_pairs) X(tile_segs) \
+    X(pixC) X(ncontrib) X(pix_stop) X(resid) X(fsq_part) X(tile_pairs) X(tile_segs) \
     X(tile_pair_off) X(tile_seg_off) X(tile_real) X(tile_real_off) X(run_seg) X(gv_cnt) \
     X(gv_flag) X(gv_idx) X(gv_segoff) X(gv_rec) X(gv_seg_off) X(gv_first) \
     X(gv_cursor) X(gv_segs) X(seg_pos) X(list_gv) X(pT) X(pD) \
@@ -267,14 +267,14 @@ struct lm_cache {
     }
 
     // buffers read only while building (see LM_BUILD_COMPACT)
-    static constexpr int kBuildBufs = 35;
+    static constexpr int kBuildBufs = 36;
     void build_buffers(DevBuf* (&out)[kBuildBufs]) {
         DevBuf* build[kBuildBufs] = {&x, &rec64, &recf, &rad, &keycnt, &keyoff, &keys, &vals, &keys_alt, &vals_alt,
                                      &sort_tmp, &scan_tmp, &rkeys, &rvals, &rkeys_alt, &rvals_alt, &cnt_sorted,
                                      &kept_blk, &kept_off, &kept_mask,
                                      &tile_start, &entry_cnt, &pixC, &ncontrib, &resid, &tile_pairs, &tile_segs,
                                      &tile_real, &tile_real_off, &gv_cnt, &gv_flag, &gv_idx, &gv_segoff, &gv_cursor,
-                                     &tile_ck};
+                                     &tile_ck, &pix_stop};
         for (int i = 0; i < kBuildBufs; ++i) out[i] = build[i];
     }
     void release_build_buffers() {
@@ -465,6 +465,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     LM_HIP(c->entry_cnt.ensure(sizeof(uint32_t) * Ka));
     LM_HIP(c->pixC.ensure(sizeof(double) * 3 * c->n_pix));
     LM_HIP(c->ncontrib.ensure(sizeof(int32_t) * c->n_pix));
+    if (layout) LM_HIP(c->pix_stop.ensure(sizeof(uint32_t) * c->n_pix));
     LM_HIP(c->resid.ensure(sizeof(float) * 3 * c->n_pix));
     LM_HIP(c->fsq_part.ensure(sizeof(double) * c->n_tiles));
     LM_HIP(c->tile_pairs.ensure(sizeof(uint32_t) * c->n_tiles));
@@ -486,6 +487,7 @@ lm_status build_forward(lm_cache* c, const lm_scene* scene, const lm_camera* cam
     ra.entry_cnt = c->entry_cnt.as<uint32_t>();
     ra.pixC = c->pixC.as<double>();
     ra.ncontrib = c->ncontrib.as<int32_t>();
+    ra.pix_stop = layout ? c->pix_stop.as<uint32_t>() : nullptr;
     ra.resid = c->resid.as<float>();
     ra.fsq_part = c->fsq_part.as<double>();
     ra.tile_pairs = c->tile_pairs.as<uint32_t>();
@@ -617,6 +619,7 @@ lm_status build_fill(lm_cache* c, hipStream_t s) {
     ra.run_seg = c->run_seg.as<uint32_t>();
     ra.thin_k = c->thin_k;
     ra.ncontrib = c->ncontrib.as<int32_t>();
+    ra.pix_stop = c->pix_stop.as<uint32_t>();
     ra.tile_ck_off = c->tile_ck_off.as<int64_t>();
     ra.pix_ck = c->pix_ck.as<uint32_t>();
     ra.ck = c->ck.as<float>();

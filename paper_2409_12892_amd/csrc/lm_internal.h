@@ -220,6 +220,7 @@ struct RasterArgs {
     uint32_t* entry_cnt;       // [K]
     double* pixC;              // [3][n_pix]
     int32_t* ncontrib;         // [n_pix]
+    uint32_t* pix_stop;        // [n_pix] build: tile-relative key at which the pixel saturated (~0u: never)
     float* resid;              // image layout
     double* fsq_part;          // [n_tiles]
     uint32_t* tile_pairs;      // [n_tiles] padded pair count

@@ -106,6 +106,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     __shared__ uint32_t s_egap[kBlock][NW];    // fill pass: tile offset of the gap before it (its start if none)
     __shared__ uint32_t s_cnt[kBlock];         // fill pass: the batch's per-entry counts
     __shared__ uint32_t s_eseg[kBlock];        // fill pass: segment of each active entry
+    __shared__ uint16_t s_act[kBlock];         // fill pass: the batch's active entries in depth order
     __shared__ uint32_t s_run[3];              // running -, segments, real pairs
     __shared__ uint32_t s_blk[NW];             // running padded pairs per block (count); block starts (fill)
     __shared__ double s_red[kBlock / kWave];
@@ -139,6 +140,9 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     double Ch0 = 0.0, Ch1 = 0.0, Ch2 = 0.0;
     int cnt = 0;
     bool done = !valid;
+    // tile-relative key at which the pixel saturates (the count pass finds it
+    // and a build stores it; the fill pass reads it): no later key reaches it
+    uint32_t stop = (FILL && valid) ? a.pix_stop[pg] : 0xFFFFFFFFu;
     if (FILL && valid) {
         Ch0 = a.pixC[pg];
         Ch1 = a.pixC[a.n_pix + pg];
@@ -188,20 +192,28 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
     }
 
     for (int64_t b0 = ks; b0 < ke; b0 += kBlock) {
+        if (FILL && (uint32_t)(b0 - ks) >= stop) done = true;
         if (__syncthreads_and(done ? 1 : 0)) break;
         const int nb = (int)(ke - b0 < kBlock ? ke - b0 : kBlock);
+        // fill: only the entries with pairs (the count pass's per-block
+        // counts) need their records
+        uint32_t ecnt = 0;
         if (tid < nb) {
             const uint32_t gi = a.vals[b0 + tid];
             const int64_t r = (int64_t)v * a.N + gi;
             s_g[tid] = gi;
+            if (FILL) ecnt = a.entry_cnt[b0 + tid];
+            if (!FILL || ecnt != 0u) {
 #pragma unroll
-            for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
+                for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
+            }
         }
+        int nact = 0;
         if (FILL) {
             // per entry and block the padded piece, placed in depth order
             // (one thread per block); a block-wide exclusive scan gives each
             // active entry its segment index
-            const uint32_t c = tid < nb ? a.entry_cnt[b0 + tid] : 0u;
+            const uint32_t c = ecnt;
             s_cnt[tid] = c;
             uint32_t cw[NW];
 #pragma unroll
@@ -239,6 +251,8 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                 tac += s_scan4[w][2];
             }
             const uint32_t eseg = s_run[1] + bac + iac - vac;
+            if (tid < nb && vac) s_act[bac + iac - vac] = (uint16_t)tid;
+            nact = (int)tac;
             __syncthreads();
             uint32_t eoff[NW], egap[NW];
 #pragma unroll
@@ -297,7 +311,16 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         }
         __syncthreads();
 
-        for (int j = 0; j < nb; ++j) {
+        // the count pass takes every entry; the fill pass only the entries
+        // with pairs in this wave's block (a key without pairs changes no
+        // pixel's blend; where it saturates a pixel, the stored stop does)
+        const int n_it = FILL ? nact : nb;
+        for (int k = 0; k < n_it; ++k) {
+            const int j = FILL ? (int)s_act[k] : k;
+            if (FILL) {
+                if (((s_cnt[j] >> (8 * wid)) & 0xFFu) == 0u) continue;
+                if ((uint32_t)(b0 - ks) + (uint32_t)j >= stop) done = true;
+            }
             bool contrib = false;
             double alpha = 0.0, a_raw = 0.0, Tn = T;
             if (!done) {
@@ -309,8 +332,12 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     alpha = a_raw < kAlphaMax ? a_raw : kAlphaMax;
                     if (alpha >= kAlphaMin) {
                         Tn = T * (1.0 - alpha);
-                        if (Tn < kTMin) done = true;
-                        else contrib = true;
+                        if (Tn < kTMin) {
+                            done = true;
+                            if (!FILL) stop = (uint32_t)(b0 - ks) + (uint32_t)j;
+                        } else {
+                            contrib = true;
+                        }
                     }
                 }
             }
@@ -423,6 +450,7 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             a.pixC[a.n_pix + pg] = acc1;
             a.pixC[2 * a.n_pix + pg] = acc2;
             a.ncontrib[pg] = cnt;
+            if (a.layout) a.pix_stop[pg] = stop;
             const int64_t ib = 3 * cam.pix_base + (int64_t)py * cam.W + px;
             const double accs[3] = {acc0, acc1, acc2};
 #pragma unroll
