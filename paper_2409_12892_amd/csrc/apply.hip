@@ -157,7 +157,7 @@ __global__ void __launch_bounds__(kBlock, 3) k_gram_tile(CacheView c, float* __r
                     }
                 }
                 const int next = __shfl_down(key, 1, kWave);
-                wave_segmented_scan<kGram>(acc, lane, segment_head((uint32_t)key, lane));
+                wave_piece_scan<kGram>(acc, lane, segment_head((uint32_t)key, lane));
                 // one piece per segment and block, summed by one wave: a
                 // plain addition by the piece's last lane (a group of gap runs
                 // carries the next window's piece's segment and no pair: it

@@ -546,17 +546,20 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
         float m[9];
 #pragma unroll
         for (int k = 0; k < 9; ++k) m[k] = 0.0f;
-        bool any = false;
+        // a run with pairs has a nonzero T word (a stored T is at least 1e-4)
+        uint32_t tor = 0u;
+#pragma unroll
+        for (int i = 0; i < RunLoad<DT>::NWD; ++i) tor |= L.tw[i];
+        const bool any = tor != 0u && in;
         {
             const int s = in ? key : 0;
             const float4 g0 = s_sg[s][0], g1 = s_sg[s][1];
-            // a padding pair has T, D and pixel 0: with its u taken as 0
-            // every term is 0 (G and alpha are finite: the power is <= 0);
-            // lanes outside [s0, s0 + cn) sum under a key no piece has
+            // a padding pair has T, D and pixel 0: w = D . u and alpha T are
+            // 0, so every term is 0 (G and alpha are finite: the power is
+            // <= 0; u is pixel 0's, finite); lanes outside [s0, s0 + cn) sum
+            // under a key no piece has
 #pragma unroll
             for (int k = 0; k < kRun; ++k) {
-                const bool live = L.t(k) != 0;
-                any = any || live;
                 const float T = S::dec_T(L.t(k));
                 const bool clamped = S::clamp(L.t(k));
                 const int pl = L.pix(k);
@@ -565,10 +568,7 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 const float G = __builtin_amdgcn_exp2f(dx * (g0.z * dx + g0.w * dy) + g1.x * dy * dy);
                 const float alpha = clamped ? 0.99f : g1.y * G;
                 const float aT = alpha * T;
-                float4 u = s_ut[pl];
-                u.x = live ? u.x : 0.0f;
-                u.y = live ? u.y : 0.0f;
-                u.z = live ? u.z : 0.0f;
+                const float4 u = s_ut[pl];
                 const float w = S::dec(L.d(0, k)) * u.x + S::dec(L.d(1, k)) * u.y + S::dec(L.d(2, k)) * u.z;
                 const float aw = clamped ? 0.0f : alpha * w;
                 const float awx = aw * dx, awy = aw * dy;
@@ -582,12 +582,11 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
                 m[7] += aT * u.y;
                 m[8] += aT * u.z;
             }
-            any = any && in;
         }
         const uint64_t lives = __ballot(any);
         const int next = __shfl_down(key, 1, kWave);
         const int head = segment_head((uint32_t)key, lane);
-        wave_segmented_scan<9>(m, lane, head);
+        wave_piece_scan<9>(m, lane, head);
         const uint64_t grp = ((2ull << lane) - 1ull) & ~((1ull << head) - 1ull);
         if (key != kNoSeg && (lane == kWave - 1 || next != key) && (lives & grp) != 0ull) {
 #pragma unroll

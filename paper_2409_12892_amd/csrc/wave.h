@@ -43,6 +43,25 @@ __device__ __forceinline__ void wave_segmented_scan(float (&m)[NV], int lane, in
     for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_mov<0x143, 0xC>(m[k]), c32, m[k]);
 }
 
+// The same sum for segments of at most 8 lanes (a piece: one splat's pairs
+// in one 64-pixel block, at most 8 runs of 8): row shifts 1, 2, 4 scan
+// within the rows of 16, then a segment that starts in the previous row
+// takes that row's last lane (lanes 15, 31, 47 to rows 1, 2, 3).  Lanes of
+// a longer segment hold partial sums.
+template <int NV>
+__device__ __forceinline__ void wave_piece_scan(float (&m)[NV], int lane, int head) {
+    const float c1 = lane - 1 >= head ? 1.0f : 0.0f, c2 = lane - 2 >= head ? 1.0f : 0.0f;
+    const float c4 = lane - 4 >= head ? 1.0f : 0.0f, c16 = (lane & ~15) - 1 >= head ? 1.0f : 0.0f;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x111>(m[k]), c1, m[k]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x112>(m[k]), c2, m[k]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_shr<0x114>(m[k]), c4, m[k]);
+#pragma unroll
+    for (int k = 0; k < NV; ++k) m[k] = __builtin_fmaf(dpp_mov<0x142, 0xE>(m[k]), c16, m[k]);
+}
+
 // First lane of this lane's segment, given per-lane segment keys that are
 // ascending across the wave.
 __device__ __forceinline__ int segment_head(uint32_t key, int lane) {

@@ -186,6 +186,15 @@ class LMSolver:
         self.history.append(rec)
         return rec
 
+    def restart(self, x0, lam: float | None = None):
+        """Start a new LM run from x0 (a device copy of the starting
+        parameters) with the configured damping; the caches stay as
+        workspaces and the first iteration builds at x0."""
+        self.x.copy_(x0)
+        self.lam = self.cfg.lam if lam is None else float(lam)
+        self.built_at_x = False
+        self.k_prev = 0
+
     def close(self):
         for h in (self.cache, self.ws):
             if h is not None:

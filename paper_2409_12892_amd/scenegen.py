@@ -171,7 +171,7 @@ CONFIGS = {
     # tiny plain-method scene: 2,048 Gaussians, SH 0, 4 views 64x64, one subset
     "tiny": dict(N=2048, deg=0, seed=1, subsets=[(4, 64, 64)], n_iters=10, lam=1e-2),
     # paper-scale plain method: 1M Gaussians, SH 3, 32 views 1024x640, one subset
-    "paper": dict(N=1_000_000, deg=3, seed=2, subsets=[(32, 1024, 640)], n_iters=8, lam=1e-2),
+    "paper": dict(N=1_000_000, deg=3, seed=2, subsets=[(32, 1024, 640)], n_iters=8, lam=1e-2, lm_steps=5),
     # precision study: 20k Gaussians, SH 0, 4 views 128x128
     "precision": dict(N=20_000, deg=0, seed=3, subsets=[(4, 128, 128)], n_iters=10, lam=1e-2),
     # uneven batched subsets: 1.5M Gaussians, SH 3
