@@ -433,13 +433,14 @@ __device__ __forceinline__ void apply_tile_body(const ApplyBatch& Bt, int64_t gt
             }
             // the window's pieces one after another (pixels are distinct
             // within a segment's pieces)
-            uint64_t todo = __ballot(live);
+            const uint64_t livem = __ballot(live);
+            uint64_t todo = livem;
             while (todo) {
                 const int first = __ffsll((unsigned long long)todo) - 1;
                 const uint32_t sk = (uint32_t)__builtin_amdgcn_readlane((int)sg, first);
-                const bool mine = live && sg == sk;
-                todo &= ~__ballot(mine);
-                if (mine) {
+                const bool same = sg == sk;
+                todo &= ~(__ballot(same) & livem);
+                if (same && live) {
                     float4 u = uw[pl];
                     u.x += v0;
                     u.y += v1;
