@@ -341,8 +341,10 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
                     }
                 }
             }
-            const uint64_t bal = __ballot(contrib);
-            if (!FILL) {
+            // per-block contributor counts: a build's count pass and the fill
+            // pass (renders need none)
+            const uint64_t bal = (FILL || a.layout) ? __ballot(contrib) : 0ull;
+            if (!FILL && a.layout) {
                 if (lane == 0) s_wc[j][wid] = (uint8_t)__popcll(bal);
             }
             if (FILL && THIN) {
