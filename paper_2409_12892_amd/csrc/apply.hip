@@ -677,7 +677,7 @@ hipError_t launch_chain(const ApplyBatch& B, hipStream_t s) {
     return hipGetLastError();
 }
 
-unsigned chain_blocks(int64_t N) { return kChainSplit * grid_for(N); }
+unsigned chain_blocks(int64_t N) { return grid_for(N); }
 
 int64_t gv_reduce_waves(int64_t n_seg) { return (n_seg + kWave - 1) / kWave; }
 

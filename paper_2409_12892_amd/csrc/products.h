@@ -820,12 +820,10 @@ __global__ void __launch_bounds__(kBlock) k_chain_gv(ApplyBatch Bt) {
     chain_gv_body<DEG>(a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
 }
 
-// Gaussian g: out = scale J^T u (+ lambda M p) over its parameters j0, j0 +
-// dj, ... (all P by default); returns its share of p . out (0 past the last
-// Gaussian)
+// Gaussian g: out = scale J^T u (+ lambda M p) over its P parameters; returns
+// its share of p . out (0 past the last Gaussian)
 template <int DEG>
-__device__ __forceinline__ double chain_body(const ApplyBatch& Bt, const ApplyArgs& a, int64_t g, int j0 = 0,
-                                             int dj = 1) {
+__device__ __forceinline__ double chain_body(const ApplyBatch& Bt, const ApplyArgs& a, int64_t g) {
     const float scale = Bt.scale, lambda = Bt.lambda, diag_floor = Bt.diag_floor;
     const float* __restrict__ M = a.M;
     float* __restrict__ out = a.out;
@@ -840,7 +838,7 @@ __device__ __forceinline__ double chain_body(const ApplyBatch& Bt, const ApplyAr
     if (g < c.N) {
         const uint32_t b = c.gv_first[g], e = c.gv_first[g + 1];
         const uint32_t n = e - b;
-        for (int j = j0; j < P; j += dj) {
+        for (int j = 0; j < P; ++j) {
             // the first four records' loads are issued together (most
             // Gaussians have at most four); the sums keep record order
             double v = 0.0;
@@ -877,20 +875,12 @@ __device__ __forceinline__ double chain_body(const ApplyBatch& Bt, const ApplyAr
     return pg;
 }
 
-// kChainSplit groups of workgroups, group q taking the parameters q, q +
-// kChainSplit, ... of every Gaussian (more waves in flight; each workgroup
-// writes its own p . out partial)
-constexpr int kChainSplit = 4;
-
 template <int DEG>
 __global__ void __launch_bounds__(kBlock) k_chain(ApplyBatch Bt) {
     const ApplyArgs& a = Bt.a[blockIdx.y];
     if (a.stop && *a.stop) return;
     __shared__ double s_red[kBlock / kWave];
-    const unsigned nbg = gridDim.x / kChainSplit;
-    const int part = (int)(blockIdx.x / nbg);
-    const int64_t g = (int64_t)(blockIdx.x - part * nbg) * blockDim.x + threadIdx.x;
-    double pg = chain_body<DEG>(Bt, a, g, part, kChainSplit);
+    double pg = chain_body<DEG>(Bt, a, (int64_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (a.pg_part) {
         const int lane = __lane_id(), wid = threadIdx.x / kWave;
 #pragma unroll
