@@ -35,6 +35,28 @@ def test_lm_iterations_decrease_error():
     solver.close()
 
 
+def test_restart_repeats_the_run():
+    """LMSolver.restart (the bench's repeated LM runs) returns to the start
+    point with the configured damping: the restarted run repeats the first
+    run's iterations (the products are deterministic)."""
+    from paper_2409_12892_amd.lm_loop import LMConfig, LMSolver
+    pr = make_problem("tiny", with_J=False)
+    sc = pr["scene"]
+    x = torch.from_numpy(sc.x).cuda()
+    x0 = x.clone()
+    tgt = torch.from_numpy(pr["target"].ravel()).cuda()
+    solver = LMSolver(x, sc.sh_degree, pr["cams"], tgt, LMConfig(lam=1e-2, n_iters=8, line_search_fraction=0.5))
+    first = [solver.iteration() for _ in range(2)]
+    assert not torch.equal(x, x0) or not any(r["accepted"] for r in first)
+    solver.restart(x0)
+    assert torch.equal(x, x0) and solver.lam == pytest.approx(1e-2)
+    again = [solver.iteration() for _ in range(2)]
+    for a, b in zip(first, again):
+        for k in ("E0", "E1", "gamma", "rho", "lam", "lam_next", "accepted"):
+            assert a[k] == b[k], (k, a[k], b[k])
+    solver.close()
+
+
 def test_per_view_residuals_match_oracle():
     from paper_2409_12892_amd import binding as B
     from oracle import forward
