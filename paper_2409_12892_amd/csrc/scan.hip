@@ -205,11 +205,22 @@ __global__ void __launch_bounds__(kBlock) k_radix_scatter(const KeyT* __restrict
         }
         __syncthreads();
     }
+    // every round's item is loaded up front (the loads overlap instead of
+    // waiting behind each round's barriers)
+    KeyT kr[radix_items<KeyT>()];
+    uint32_t vr[radix_items<KeyT>()];
+#pragma unroll
+    for (int r = 0; r < radix_items<KeyT>(); ++r) {
+        const int li = r * kBlock + tid;
+        kr[r] = li < nloc ? keys[base + li] : (KeyT)0;
+        vr[r] = li < nloc ? vals[base + li] : 0u;
+    }
+#pragma unroll
     for (int r = 0; r < radix_items<KeyT>(); ++r) {
         const int li = r * kBlock + tid;
         const bool live = li < nloc;
-        KeyT k = live ? keys[base + li] : (KeyT)0;
-        uint32_t v = live ? vals[base + li] : 0u;
+        const KeyT k = kr[r];
+        const uint32_t v = vr[r];
         const uint32_t d = (uint32_t)((k >> shift) & (NDIG - 1));
         uint64_t peers = __ballot(live);
 #pragma unroll
