@@ -191,22 +191,45 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         __syncthreads();
     }
 
+    // this thread's entry of a batch (Gaussian and record): the count pass
+    // loads it one batch ahead, so that the loads overlap the blending of the
+    // batch before; the fill pass (short of registers) loads each batch's at
+    // its start, and only the records of entries with pairs (the count
+    // pass's per-block counts)
+    uint32_t nx_g = 0u;
+    double nx_rec[10];
+    auto fetch = [&](int64_t bb) {
+        if (bb + tid < ke) {
+            nx_g = a.vals[bb + tid];
+            const int64_t r = (int64_t)v * a.N + nx_g;
+#pragma unroll
+            for (int i = 0; i < 10; ++i) nx_rec[i] = a.rec64[r * kRecStride + i];
+        }
+    };
+    if (!FILL) fetch(ks);
     for (int64_t b0 = ks; b0 < ke; b0 += kBlock) {
         if (FILL && (uint32_t)(b0 - ks) >= stop) done = true;
         if (__syncthreads_and(done ? 1 : 0)) break;
         const int nb = (int)(ke - b0 < kBlock ? ke - b0 : kBlock);
-        // fill: only the entries with pairs (the count pass's per-block
-        // counts) need their records
         uint32_t ecnt = 0;
-        if (tid < nb) {
-            const uint32_t gi = a.vals[b0 + tid];
-            const int64_t r = (int64_t)v * a.N + gi;
-            s_g[tid] = gi;
-            if (FILL) ecnt = a.entry_cnt[b0 + tid];
-            if (!FILL || ecnt != 0u) {
+        if (FILL) {
+            if (tid < nb) {
+                const uint32_t gi = a.vals[b0 + tid];
+                const int64_t r = (int64_t)v * a.N + gi;
+                s_g[tid] = gi;
+                ecnt = a.entry_cnt[b0 + tid];
+                if (ecnt != 0u) {
 #pragma unroll
-                for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
+                    for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
+                }
             }
+        } else {
+            if (tid < nb) {
+                s_g[tid] = nx_g;
+#pragma unroll
+                for (int i = 0; i < 10; ++i) s_rec[i][tid] = nx_rec[i];
+            }
+            fetch(b0 + kBlock);
         }
         int nact = 0;
         if (FILL) {
