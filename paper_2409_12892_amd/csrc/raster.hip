@@ -193,9 +193,9 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
 
     // this thread's entry of a batch (Gaussian and record): the count pass
     // loads it one batch ahead, so that the loads overlap the blending of the
-    // batch before; the fill pass (short of registers) loads each batch's at
-    // its start, and only the records of entries with pairs (the count
-    // pass's per-block counts)
+    // batch before; the fill pass (short of registers) loads the Gaussians
+    // and per-block counts one batch ahead and, at the batch's start, only
+    // the records of entries with pairs
     uint32_t nx_g = 0u;
     double nx_rec[10];
     auto fetch = [&](int64_t bb) {
@@ -206,6 +206,16 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
             for (int i = 0; i < 10; ++i) nx_rec[i] = a.rec64[r * kRecStride + i];
         }
     };
+    // fill: the batch's Gaussians and per-block counts one batch ahead
+    uint32_t nf_g = 0u, nf_cnt = 0u;
+    auto fetch_fill = [&](int64_t bb) {
+        nf_cnt = 0u;
+        if (bb + tid < ke) {
+            nf_g = a.vals[bb + tid];
+            nf_cnt = a.entry_cnt[bb + tid];
+        }
+    };
+    if (FILL) fetch_fill(ks);
     if (!FILL) fetch(ks);
     for (int64_t b0 = ks; b0 < ke; b0 += kBlock) {
         if (FILL && (uint32_t)(b0 - ks) >= stop) done = true;
@@ -214,15 +224,16 @@ __global__ void __launch_bounds__(kBlock) k_raster(RasterArgs a) {
         uint32_t ecnt = 0;
         if (FILL) {
             if (tid < nb) {
-                const uint32_t gi = a.vals[b0 + tid];
+                const uint32_t gi = nf_g;
                 const int64_t r = (int64_t)v * a.N + gi;
                 s_g[tid] = gi;
-                ecnt = a.entry_cnt[b0 + tid];
+                ecnt = nf_cnt;
                 if (ecnt != 0u) {
 #pragma unroll
                     for (int i = 0; i < 10; ++i) s_rec[i][tid] = a.rec64[r * kRecStride + i];
                 }
             }
+            fetch_fill(b0 + kBlock);
         } else {
             if (tid < nb) {
                 s_g[tid] = nx_g;
